@@ -1,0 +1,173 @@
+"""Seeded synthetic inputs: grids, marker sets and initial fields.
+
+This module is shared by the HIP path and the oracle and therefore holds none of
+the method's arithmetic: it only states the workloads (box, resolution, flow
+parameters, marker sampling of the body surface) and draws the initial fields.
+
+Workloads take the shapes of the paper's test cases (a heated circular cylinder,
+Sec. 3; a heated sphere, Sec. 4; an oscillating cylinder, Sec. 5) on uniform
+Cartesian grids; they stand in for the paper's refined meshes and literature
+comparison data, which are not used.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
+CONV_VANLEER, CONV_LINEAR = 0, 1
+MU_SUTHERLAND, MU_CONSTANT = 0, 1
+
+SUTHERLAND_AIR = 110.4 / 288.15  # Sutherland temperature of air over T_inf = 288.15 K
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(counter: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function (Steele, Lea, Flood 2014) applied to a counter:
+    z = (c + 1) * golden; then the two xor-shift-multiply rounds."""
+    with np.errstate(over="ignore"):
+        z = (counter.astype(np.uint64) + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform_pm1(seed: int, component: int, n: int) -> np.ndarray:
+    """Counter-based uniform draws in [-1, 1): counter = seed*2^32 + component*2^28 + i,
+    53 random bits per double."""
+    i = np.arange(n, dtype=np.uint64)
+    ctr = np.uint64(seed) * np.uint64(1 << 32) + np.uint64(component) * np.uint64(1 << 28) + i
+    bits = splitmix64(ctr) >> np.uint64(11)
+    u = bits.astype(np.float64) * (1.0 / 9007199254740992.0)
+    return 2.0 * u - 1.0
+
+
+def normal(seed: int, n: int) -> np.ndarray:
+    """Seeded standard normal draws (Box-Muller on the counter-based uniforms)."""
+    u1 = 0.5 * (uniform_pm1(seed, 0, n) + 1.0)
+    u2 = 0.5 * (uniform_pm1(seed, 1, n) + 1.0)
+    u1 = np.maximum(u1, 1e-300)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+# ----------------------------------------------------------------- marker sets
+def ring(ns: int, diameter: float = 1.0, center=(0.0, 0.0)):
+    """Equispaced markers on a circle at angles 2 pi (k + 1/2) / ns: none lies on the
+    line y = center_y, and for even ns the set is exactly mirror-symmetric in y
+    (marker ns-1-k is the mirror image of marker k).
+    Returns X [ns,2] and the surface element dA [ns] (per unit span)."""
+    k = np.arange(ns)
+    ang = 2.0 * math.pi * (k + 0.5) / ns
+    x = 0.5 * diameter * np.cos(ang)
+    y = 0.5 * diameter * np.sin(ang)
+    if ns % 2 == 0:
+        for j in range(ns // 2):
+            x[ns - 1 - j] = x[j]
+            y[ns - 1 - j] = -y[j]
+    X = np.stack([x + center[0], y + center[1]], axis=1)
+    dA = np.full(ns, math.pi * diameter / ns)
+    return np.ascontiguousarray(X), dA
+
+
+def fibonacci_sphere(ns: int, diameter: float = 1.0):
+    """Fibonacci-lattice markers on a sphere: z_k = 1-(2k+1)/ns, azimuth k*pi*(3-sqrt 5)."""
+    k = np.arange(ns)
+    z = 1.0 - (2.0 * k + 1.0) / ns
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    rxy = np.sqrt(1.0 - z * z)
+    X = 0.5 * diameter * np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1)
+    dA = np.full(ns, math.pi * diameter * diameter / ns)
+    return np.ascontiguousarray(X), dA
+
+
+# ----------------------------------------------------------------- workloads
+def _bc_channel(dim):
+    bc = [[INFLOW, OUTFLOW], [SLIP, SLIP]]
+    if dim == 3:
+        bc.append([SLIP, SLIP])
+    return bc
+
+
+def case(name: str, **over):
+    """Problem description of a named workload (dict; keys follow the C ABI).
+
+    cfg1  2D heated cylinder, 128^2 over [-2,6]x[-4,4], 100 markers, Re 40, Ma 0.1, Tw 1.1
+    cfg2  2D heated cylinder, 1024^2 over [-4,12]x[-8,8], 400 markers, Re 100, Ma 0.2,
+          Tw 0.8 (cfg2a) or 1.5 (cfg2b)
+    cfg3  3D heated sphere, 256^3 over [-2.5,7.5]x[-4,4]^2, 3200 markers, Re 300,
+          Ma 0.3 or 0.8, Tw 0.5 or 1.5
+    cfg4  2D cylinder oscillating transversely, y = 0.2 sin(2 pi 0.2 t), 512^2 over
+          [-4,12]x[-8,8], 200 markers, Re 100, Ma 0.2, Tw 1.2
+    cfg5  2D heated cylinder for gradients, 512^2 as cfg4, 200 markers, Tw 1.3
+    """
+    base = dict(Pr=0.71, gamma=1.4, sutherland_S=SUTHERLAND_AIR, U_inf=(1.0, 0.0, 0.0),
+                convection=CONV_VANLEER, viscosity_law=MU_SUTHERLAND, cfl=0.5, dt=0.0,
+                cg_rtol=1e-13, cg_maxit=2000, dt_u_max=0.0, motion=None, dedupe=True)
+    if name == "cfg1":
+        c = dict(dim=2, n=(128, 128), lo=(-2.0, -4.0), hi=(6.0, 4.0), Re=40.0, Ma=0.1,
+                 Tw=1.1, ns=100, seed=1, steps=200)
+    elif name in ("cfg2", "cfg2a", "cfg2b"):
+        c = dict(dim=2, n=(1024, 1024), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=100.0, Ma=0.2,
+                 Tw=1.5 if name == "cfg2b" else 0.8, ns=400, seed=2, steps=2000)
+    elif name == "cfg3":
+        c = dict(dim=3, n=(256, 256, 256), lo=(-2.5, -4.0, -4.0), hi=(7.5, 4.0, 4.0),
+                 Re=300.0, Ma=0.3, Tw=1.5, ns=3200, seed=3, steps=500)
+    elif name == "cfg4":
+        amp, freq = 0.2, 0.2
+        c = dict(dim=2, n=(512, 512), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=100.0, Ma=0.2,
+                 Tw=1.2, ns=200, seed=4, steps=4000,
+                 motion=dict(axis=1, amp=amp, freq=freq),
+                 dt_u_max=2.0 * math.pi * freq * amp)
+    elif name == "cfg5":
+        c = dict(dim=2, n=(512, 512), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=100.0, Ma=0.2,
+                 Tw=1.3, ns=200, seed=5, steps=500, checkpoint=50)
+    else:
+        raise KeyError(name)
+    base.update(c)
+    base["bc"] = _bc_channel(base["dim"])
+    base.update(over)
+    base["dt_theta_max"] = max(1.0, float(base["Tw"]))
+    if "dt_theta_max_override" in over:
+        base["dt_theta_max"] = over["dt_theta_max_override"]
+    return base
+
+
+def scaled(name: str, n, ns=None, **over):
+    """A named workload on another grid (same box and physics), for small tests."""
+    c = case(name, **over)
+    c["n"] = tuple(n)
+    if ns is not None:
+        c["ns"] = int(ns)
+    return c
+
+
+def markers(c):
+    """Marker set of a workload: X [ns,dim], U_d [ns,dim] (body at rest), Tw [ns], dA."""
+    ns = int(c["ns"])
+    if c["dim"] == 2:
+        X, dA = ring(ns)
+    else:
+        X, dA = fibonacci_sphere(ns)
+    Ud = np.zeros_like(X)
+    Tw = np.full(ns, float(c["Tw"]))
+    return X, Ud, Tw, dA
+
+
+def initial_fields(c, amplitude: float = 1e-3, seed=None):
+    """Uniform stream rho = 1, theta = 1, u = e_x plus i.i.d. uniform perturbations
+    amplitude*xi, xi in [-1, 1), per cell and velocity component (inside the body too).
+    Arrays are x-fastest: rho [N], u [dim, N], theta [N]."""
+    seed = int(c["seed"] if seed is None else seed)
+    dim = int(c["dim"])
+    N = int(np.prod(c["n"][:dim]))
+    rho = np.ones(N)
+    theta = np.ones(N)
+    U = list(c.get("U_inf", (1.0, 0.0, 0.0)))
+    u = np.zeros((dim, N))
+    for q in range(dim):
+        u[q] = U[q] + (amplitude * uniform_pm1(seed, q, N) if amplitude else 0.0)
+    return rho, u, theta

@@ -1,0 +1,207 @@
+/*
+ * ibm.h -- C ABI of the MI355X (gfx950) library for one pressure-based time step
+ * of the discrete-forcing immersed boundary method for compressible flow with
+ * heat exchange (Riahi, Goncalves da Silva, Meldi: "A Discrete Immersed Boundary
+ * Method for the numerical simulation of heat transfer in compressible flows").
+ *
+ * Problem statement followed by the arguments:
+ *   - a body given by Lagrangian markers (Sec. 2.2), with a desired velocity
+ *     (Eq. (10)) and an imposed wall temperature (Dirichlet, Sec. 2.2 and
+ *     Eqs. (16)-(17)),
+ *   - in a perfect gas with Sutherland viscosity (Sec. 2.1, Eqs. (1)-(4)),
+ *   - at a given Reynolds, Mach and Prandtl number,
+ *   - advanced by the IBM-HT-sonicFoam step of Appendix A on a uniform
+ *     Cartesian finite-volume grid,
+ *   - returning the flow, the marker forces (Sec. 3.1, Eq. (18)) and the heat
+ *     exchanged with the body.
+ *
+ * Units are non-dimensional: rho_inf = |U_inf| = D = theta_inf = 1,
+ * R = 1/(gamma Ma^2), c_v = R/(gamma-1), mu_inf = 1/Re.
+ *
+ * Conventions for every entry point:
+ *   - Return ibm_status; IBM_OK is 0. No C++ exception crosses the ABI.
+ *   - On an argument error (IBM_E_ARG, IBM_E_SIZE) nothing is modified and
+ *     ibm_last_error() describes the problem.
+ *   - All device work is enqueued on the stream given at creation, in order.
+ *     Calls that fill host memory (ibm_step_info, totals) synchronise it.
+ *   - Device pointers are HIP device addresses owned by the caller; the library
+ *     reads them during the call (stream-ordered) and keeps no reference unless
+ *     stated. The library never allocates device memory: all of its buffers are
+ *     carved from the caller's workspace.
+ *   - Cell arrays are structure-of-arrays, x fastest: index i + n0*(j + n1*k).
+ *     Vector fields are stored component after component ([dim][N]).
+ *     The face array of direction d has n_d+1 faces along d and n_e cells along
+ *     the other directions e (face i_d lies between cells i_d-1 and i_d); the dim
+ *     face arrays are concatenated, direction 0 first. In a periodic direction
+ *     face n_d is the same face as face 0 and holds the same value.
+ *   - Field arrays are double (IBM_FP64) or float (IBM_FP32) as the context's
+ *     precision says; marker arrays, forces and heat are always double.
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibm_ctx ibm_ctx;
+
+typedef enum {
+  IBM_OK = 0,
+  IBM_E_ARG = 1,           /* invalid argument                                   */
+  IBM_E_SIZE = 2,          /* workspace or marker capacity too small             */
+  IBM_E_HIP = 3,           /* a HIP runtime call failed                           */
+  IBM_E_NOT_CONVERGED = 4, /* a CG solve exceeded its iteration limit             */
+  IBM_E_NONFINITE = 5,     /* a step produced NaN/Inf or non-positive rho, theta */
+  IBM_E_STATE = 6          /* call out of order (e.g. markers never set)         */
+} ibm_status;
+
+/* boundary condition of one side of the box (ghost rules per variable):
+ *   PERIODIC  wrap (both sides of a direction must be periodic)
+ *   INFLOW    u = U_inf and theta = 1 on the face; rho, p zero gradient;
+ *             face mass flux rho_P U_inf (rho at the start of the step)
+ *   OUTFLOW   zero gradient; p = p_inf on the face
+ *   SLIP      no normal velocity, no normal gradient of anything else          */
+enum { IBM_PERIODIC = 0, IBM_INFLOW = 1, IBM_OUTFLOW = 2, IBM_SLIP = 3 };
+enum { IBM_FP64 = 0, IBM_FP32 = 1 };
+/* convected face values: van Leer limited (Sec. 2.2.2) or linear */
+enum { IBM_CONV_VANLEER = 0, IBM_CONV_LINEAR = 1 };
+enum { IBM_MU_SUTHERLAND = 0, IBM_MU_CONSTANT = 1 };
+/* ibm_set_markers flags: apply the marker check routine of Sec. 3.1 (of the
+ * markers that fall in one cell only the one nearest to its centre is used,
+ * ties to the lower id), at set-up and after every motion update. */
+#define IBM_DEDUPE 1u
+/* ibm_step flags: record each step of the call on the tape for the adjoint */
+#define IBM_RECORD 1u
+
+typedef struct {
+  int32_t dim;              /* 2 or 3                                          */
+  int32_t n[3];             /* cells per direction; n[2] = 1 in 2D, each >= 3  */
+  double lo[3], hi[3];      /* box; h_d = (hi_d - lo_d)/n_d                    */
+  int32_t bc[3][2];         /* IBM_PERIODIC/INFLOW/OUTFLOW/SLIP, [dir][lo,hi]  */
+  int32_t precision;        /* IBM_FP64 or IBM_FP32                            */
+  int32_t convection;       /* IBM_CONV_VANLEER or IBM_CONV_LINEAR             */
+  int32_t viscosity_law;    /* IBM_MU_SUTHERLAND or IBM_MU_CONSTANT            */
+  int32_t reserved;         /* must be 0                                       */
+  double Re, Ma, Pr, gamma; /* flow parameters                                 */
+  double sutherland_S;      /* Sutherland temperature over T_inf               */
+  double U_inf[3];          /* inflow velocity                                 */
+  double dt;                /* > 0: time step; <= 0: computed from cfl         */
+  double cfl;               /* fraction of the explicit convection+conduction  */
+                            /* limit used when dt <= 0                         */
+  double dt_theta_max;      /* largest temperature expected (for the limit)    */
+  double dt_u_max;          /* largest body speed expected (for the limit)     */
+  double cg_rtol;           /* pressure CG stops at |r| <= cg_rtol |b|         */
+  int32_t cg_maxit;         /* pressure CG iteration limit                     */
+  int32_t max_markers;      /* capacity for candidate markers                  */
+} ibm_grid_desc;
+
+typedef struct {
+  int64_t steps_done;     /* steps completed by the call                      */
+  int64_t step;           /* step counter of the state after the call         */
+  int32_t cg_iters_last;  /* CG iterations of the last step                   */
+  int32_t cg_iters_total; /* CG iterations summed over the call               */
+  double cg_residual;     /* |r|/|b| at the end of the last solve              */
+  double dt;              /* time step                                        */
+  double time;            /* step * dt                                        */
+  double mass;            /* sum of rho dV after the call (FP64 reduction)     */
+} ibm_step_info;
+
+/* Bytes of device workspace needed for a grid, a marker capacity and a tape
+ * of `tape_steps` recorded steps (0: no adjoint). Returns 0 for an invalid
+ * descriptor. */
+size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32_t tape_steps);
+
+/* Creates a context on the current HIP device. `dev_workspace` (device memory,
+ * at least ibm_workspace_bytes(desc, desc->max_markers, tape_steps) bytes,
+ * 256-byte aligned) must stay valid until ibm_destroy; `tape_steps` is the
+ * capacity used in that size computation. `hip_stream` (hipStream_t, may be
+ * NULL for the null stream) orders all work. The state starts as the uniform
+ * stream rho = 1, theta = 1, u = U_inf. */
+ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
+                           int32_t tape_steps, void *hip_stream, ibm_ctx **out);
+
+/* Releases the host-side context (the workspace stays with the caller). */
+void ibm_destroy(ibm_ctx *ctx);
+
+/* Message of the last error of this context ("" if none). */
+const char *ibm_last_error(const ibm_ctx *ctx);
+
+/* Time step in use (given, or computed at creation from cfl). */
+double ibm_dt(const ibm_ctx *ctx);
+
+/* Sets the state from primitive fields (device, context precision): rho [N],
+ * u [dim][N], theta [N]. Conserved state m = rho u, E = rho c_v theta; face
+ * mass flux from the momentum (linear interpolation; boundary faces by their
+ * rule). Resets the step counter to 0. */
+ibm_status ibm_init_primitive(ibm_ctx *ctx, const void *rho, const void *u, const void *theta);
+
+/* Sets the conserved state (device, context precision): rho [N], mom [dim][N],
+ * eint = rho e [N], face_flux [sum_d NF_d] or NULL to derive it from mom.
+ * `step` sets the step counter (time = step * dt, which drives marker motion). */
+ibm_status ibm_set_state(ibm_ctx *ctx, const void *rho, const void *mom, const void *eint,
+                         const void *face_flux, int64_t step);
+
+/* Copies the conserved state out (device, context precision). NULL skips. */
+ibm_status ibm_get_state(const ibm_ctx *ctx, void *rho, void *mom, void *eint, void *face_flux);
+
+/* Sets the body (Sec. 2.2): n candidate markers with positions X [n][dim],
+ * desired velocities U_d [n][dim] (NULL: at rest), wall temperatures T_w [n]
+ * (theta_wall / theta_inf) and surface elements dA [n] (NULL: zero); all device
+ * double arrays, copied. With IBM_DEDUPE the check routine of Sec. 3.1 selects
+ * the markers in use. Builds the supports (the 3 nearest cells per direction),
+ * sorts the (cell, marker) pairs, and solves A eps = 1 (Eqs. (8)-(9)) in FP64.
+ * IBM_E_ARG if a support leaves a non-periodic box; IBM_E_SIZE if n exceeds the
+ * capacity; IBM_E_NOT_CONVERGED if the eps solve fails. */
+ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const double *U_d,
+                           const double *T_w, const double *dA, uint32_t flags);
+
+/* Prescribed motion (Sec. 5, Eq. (19)): at time t every candidate marker sits at
+ * X(0) + amplitude sin(2 pi frequency t) e_axis and moves with the derivative of
+ * that law added to its U_d. Step n -> n+1 uses t = (n+1) dt; the markers are
+ * re-selected, re-sorted and eps re-solved on the device every step.
+ * axis < 0 switches motion off. */
+ibm_status ibm_set_motion(ibm_ctx *ctx, int32_t axis, double amplitude, double frequency);
+
+/* Replaces the wall temperatures (device double [n], candidate order). */
+ibm_status ibm_set_wall_temperature(ibm_ctx *ctx, const double *T_w);
+
+/* Advances n_steps steps of Appendix A: predictor with f = q = 0; interpolation
+ * (Eq. (5)), forcing (Eqs. (10), (17)) and spreading (Eq. (7)); the pressure
+ * equation solved by matrix-free CG; correction of the face mass flux, density,
+ * momentum and energy. `hist` (device double [n_steps][4] or NULL) receives per
+ * step the force of the fluid on the body (Fx, Fy, Fz) and the heat given to
+ * the fluid H. `info` (host, may be NULL) is filled after a synchronisation.
+ * IBM_E_NOT_CONVERGED: the CG hit cg_maxit (the state is advanced, the call
+ * stops after that step). IBM_E_NONFINITE: the step produced NaN/Inf or a
+ * non-positive density or temperature; the state is the one before that step.
+ * With IBM_RECORD each step is stored on the tape (IBM_E_SIZE when full). */
+ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
+                    ibm_step_info *info);
+
+/* Wall fluxes of the last step (Sec. 3.1): per marker in use the force on the
+ * body -dV eps_k F_k (device [n_used][dim], may be NULL) and the heat given to
+ * the fluid dV eps_k Q_k (device [n_used], may be NULL); totals (host [4]:
+ * Fx, Fy, Fz, H, may be NULL; synchronises). */
+ibm_status ibm_wall_fluxes(const ibm_ctx *ctx, double *force, double *heat, double *totals);
+
+/* Markers in use: their number (host), candidate ids (device int32 [n_used]) and
+ * Lagrangian quadrature eps (device double [n_used]); NULL pointers skip. */
+ibm_status ibm_markers_in_use(const ibm_ctx *ctx, int32_t *n_used, int32_t *ids, double *eps);
+
+/* Intermediate fields of the last step, for inspection (device, context
+ * precision unless noted): 0 rho* (predictor), 1 mom** [dim][N] and 2 E** (the
+ * predictor values with the spread forcing added; equal to the predictor values
+ * away from the markers), 3 psi, 4 pressure right-hand side (double), 5 pressure
+ * solution (double), 6 per-marker rho_L, M (dim), E_L, F (dim), Q
+ * (double [n_used][2 dim + 3]). Synchronises. */
+ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBM_H */

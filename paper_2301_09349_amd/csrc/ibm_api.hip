@@ -1,0 +1,681 @@
+// ibm_api.hip -- host side of the C ABI declared in include/ibm.h: descriptor
+// validation, workspace carving (the library never allocates device memory),
+// marker set-up and the step loop with the pressure-CG convergence probe.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ibm.h"
+#include "ibm_launch.h"
+
+using ibmk::Bufs;
+using ibmk::CgScal;
+using ibmk::GridK;
+using ibmk::Launch;
+
+struct ibm_ctx {
+  ibm_grid_desc desc;
+  Launch L;
+  Bufs B;
+  int cur = 0;
+  int64_t step = 0;
+  int nc = 0;  // candidate markers (0: no body)
+  int dedupe = 0;
+  int motion_axis = -1;
+  double motion_amp = 0.0, motion_freq = 0.0;
+  int cg_hint = 8;
+  int tape_cap = 0;
+  std::string err;
+  CgScal cgh;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+ibm_status fail(ibm_ctx *ctx, ibm_status s, const char *msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+#define HIPCHECK(ctx, expr)                                              \
+  do {                                                                   \
+    hipError_t e_ = (expr);                                              \
+    if (e_ != hipSuccess) {                                              \
+      if (ctx) (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_); \
+      return IBM_E_HIP;                                                  \
+    }                                                                    \
+  } while (0)
+
+const char *check_desc(const ibm_grid_desc *d) {
+  if (!d) return "descriptor is NULL";
+  if (d->dim != 2 && d->dim != 3) return "dim must be 2 or 3";
+  for (int a = 0; a < d->dim; ++a) {
+    if (d->n[a] < 3) return "each n[d] must be >= 3";
+    if (!(d->hi[a] > d->lo[a])) return "hi must exceed lo";
+    for (int s = 0; s < 2; ++s)
+      if (d->bc[a][s] < IBM_PERIODIC || d->bc[a][s] > IBM_SLIP) return "unknown boundary type";
+    if ((d->bc[a][0] == IBM_PERIODIC) != (d->bc[a][1] == IBM_PERIODIC))
+      return "periodic must be set on both sides";
+  }
+  if (d->dim == 2 && d->n[2] != 1) return "n[2] must be 1 in 2D";
+  if (d->precision != IBM_FP64 && d->precision != IBM_FP32) return "unknown precision";
+  if (d->convection != IBM_CONV_VANLEER && d->convection != IBM_CONV_LINEAR)
+    return "unknown convection scheme";
+  if (d->viscosity_law != IBM_MU_SUTHERLAND && d->viscosity_law != IBM_MU_CONSTANT)
+    return "unknown viscosity law";
+  if (d->reserved != 0) return "reserved must be 0";
+  if (!(d->Re > 0) || !(d->Ma > 0) || !(d->Pr > 0) || !(d->gamma > 1.0))
+    return "Re, Ma, Pr must be > 0 and gamma > 1";
+  if (!(d->sutherland_S >= 0)) return "sutherland_S must be >= 0";
+  if (!(d->dt > 0) && !(d->cfl > 0)) return "need dt > 0 or cfl > 0";
+  if (!(d->cg_rtol > 0) || d->cg_maxit < 1) return "cg_rtol > 0 and cg_maxit >= 1 required";
+  if (d->max_markers < 0) return "max_markers must be >= 0";
+  int64_t N = 1;
+  for (int a = 0; a < d->dim; ++a) N *= d->n[a];
+  if (N > (int64_t)1 << 31) return "grid too large";
+  return nullptr;
+}
+
+double mu_law(const ibm_grid_desc &d, double th) {
+  double mu_inf = 1.0 / d.Re;
+  if (d.viscosity_law == IBM_MU_CONSTANT) return mu_inf;
+  return mu_inf * th * std::sqrt(th) * (1.0 + d.sutherland_S) / (th + d.sutherland_S);
+}
+
+GridK make_grid(const ibm_grid_desc &d) {
+  GridK g;
+  std::memset(&g, 0, sizeof(g));
+  g.dim = d.dim;
+  g.N = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = (a < d.dim) ? d.n[a] : 1;
+    g.lo[a] = (a < d.dim) ? d.lo[a] : 0.0;
+    g.h[a] = (a < d.dim) ? (d.hi[a] - d.lo[a]) / double(g.n[a]) : 1.0;
+    g.ih[a] = 1.0 / g.h[a];
+    g.N *= g.n[a];
+    for (int s = 0; s < 2; ++s) g.bc[a][s] = (a < d.dim) ? d.bc[a][s] : IBM_PERIODIC;
+    g.U_inf[a] = d.U_inf[a];
+  }
+  for (int a = 0; a < 3; ++a) {
+    g.NF[a] = 1;
+    for (int b = 0; b < 3; ++b) {
+      g.fn[a][b] = g.n[b] + (a == b ? 1 : 0);
+      g.NF[a] *= g.fn[a][b];
+    }
+    if (a >= d.dim) g.NF[a] = 0;
+  }
+  g.conv = d.convection;
+  g.visc = d.viscosity_law;
+  g.R = 1.0 / (d.gamma * d.Ma * d.Ma);
+  g.cv = g.R / (d.gamma - 1.0);
+  g.inv_cv = 1.0 / g.cv;
+  g.cp = d.gamma * g.cv;
+  g.gm1 = d.gamma - 1.0;
+  g.mu_inf = 1.0 / d.Re;
+  g.S = d.sutherland_S;
+  g.Pr = d.Pr;
+  g.p_inf = g.R;
+  g.dV = g.h[0] * g.h[1] * (d.dim == 3 ? g.h[2] : 1.0);
+  if (d.dt > 0.0) {
+    g.dt = d.dt;
+  } else {
+    // half of the combined explicit limit of convection and conduction, with the
+    // thermal diffusivity gamma mu / (Pr rho) at theta_max and rho = 1/theta_max
+    double thm = std::max(1.0, d.dt_theta_max);
+    double uref = std::sqrt(d.U_inf[0] * d.U_inf[0] + d.U_inf[1] * d.U_inf[1] +
+                            d.U_inf[2] * d.U_inf[2]) + d.dt_u_max;
+    double alpha = d.gamma * mu_law(d, thm) * thm / d.Pr;
+    double sc = 0.0, sd = 0.0;
+    for (int a = 0; a < d.dim; ++a) {
+      sc += uref / g.h[a];
+      sd += 1.0 / (g.h[a] * g.h[a]);
+    }
+    g.dt = d.cfl / (sc + 2.0 * alpha * sd);
+  }
+  if (d.dim == 2) {
+    g.tiles[0] = (g.n[0] + 63) / 64;
+    g.tiles[1] = (g.n[1] + 3) / 4;
+    g.tiles[2] = 1;
+  } else {
+    g.tiles[0] = (g.n[0] + 63) / 64;
+    g.tiles[1] = (g.n[1] + 1) / 2;
+    g.tiles[2] = (g.n[2] + 1) / 2;
+  }
+  g.ntiles = (int64_t)g.tiles[0] * g.tiles[1] * g.tiles[2];
+  g.nblocks = ((g.ntiles + 7) / 8) * 8;
+  return g;
+}
+
+int next_pow2(int64_t v) {
+  int64_t p = 2;
+  while (p < v) p <<= 1;
+  return (int)p;
+}
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Lays the buffers out in the workspace (or only measures when base == NULL).
+size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_steps, char *base,
+            Bufs &B, int &npairs_pad) {
+  (void)tape_steps;
+  Carver C{base};
+  const size_t w = (d.precision == IBM_FP32) ? 4 : 8;
+  const int dim = d.dim;
+  const size_t N = (size_t)g.N;
+  auto field = [&](size_t n) { return (void *)C.take<char>(n * w); };
+  for (int s = 0; s < 2; ++s) {
+    B.rho[s] = field(N);
+    B.E[s] = field(N);
+    for (int q = 0; q < 3; ++q) {
+      B.mom[s][q] = q < dim ? field(N) : nullptr;
+      B.F[s][q] = q < dim ? field((size_t)g.NF[q]) : nullptr;
+    }
+  }
+  B.rho_s = field(N);
+  B.E_s = field(N);
+  B.psi = field(N);
+  for (int q = 0; q < 3; ++q) {
+    B.mom_s[q] = q < dim ? field(N) : nullptr;
+    B.mhat[q] = q < dim ? field(N) : nullptr;
+    B.Fhat[q] = q < dim ? field((size_t)g.NF[q]) : nullptr;
+  }
+  B.b = C.take<double>(N);
+  B.x = C.take<double>(N);
+  B.r = C.take<double>(N);
+  B.p[0] = C.take<double>(N);
+  B.p[1] = C.take<double>(N);
+  B.q = C.take<double>(N);
+  B.partials = C.take<double>(4 * (size_t)g.nblocks + 64);
+  B.cg = C.take<CgScal>(1);
+  B.scal = C.take<double>(8);
+  B.flags = C.take<int>(8);
+  const size_t nc = std::max(max_markers, 1);
+  const int nslot = dim == 3 ? 27 : 9;
+  npairs_pad = next_pow2((int64_t)nc * nslot);
+  B.cX0 = C.take<double>(3 * nc);
+  B.cUd0 = C.take<double>(3 * nc);
+  B.cXc = C.take<double>(3 * nc);
+  B.cUdc = C.take<double>(3 * nc);
+  B.cTw = C.take<double>(nc);
+  B.cdA = C.take<double>(nc);
+  B.ceps = C.take<double>(nc);
+  B.ckey = C.take<int64_t>(nc);
+  B.cd2 = C.take<double>(nc);
+  B.ckeep = C.take<int>(nc);
+  B.mcount = C.take<int>(8);
+  B.ids = C.take<int>(nc);
+  B.X = C.take<double>(3 * nc);
+  B.Ud = C.take<double>(3 * nc);
+  B.Tw = C.take<double>(nc);
+  B.dA = C.take<double>(nc);
+  B.eps = C.take<double>(nc);
+  B.sidx = C.take<int>(9 * nc);
+  B.sw1 = C.take<double>(9 * nc);
+  B.pcell = C.take<int64_t>(27 * nc);
+  B.pw = C.take<double>(27 * nc);
+  B.keys = C.take<uint64_t>((size_t)npairs_pad);
+  B.seg = C.take<int>(27 * nc + 1);
+  B.ell_col = C.take<int>((size_t)ibmk::kMaxNbr * nc);
+  B.ell_val = C.take<double>((size_t)ibmk::kMaxNbr * nc);
+  B.ell_cnt = C.take<int>(nc);
+  for (int v = 0; v < 4; ++v) B.ev[v] = C.take<double>(nc);
+  B.mk = C.take<double>(9 * nc);
+  B.mforce = C.take<double>(3 * nc);
+  B.mheat = C.take<double>(nc);
+  B.totals = C.take<double>(8);
+  return (C.off + 255) & ~size_t(255);
+}
+
+ibm_status sync_read(ibm_ctx *ctx, void *dst, const void *src, size_t bytes) {
+  HIPCHECK(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->L.st));
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->L.st));
+  return IBM_OK;
+}
+
+// marker positions of the current step counter, supports, sort, eps
+ibm_status rebuild_markers(ibm_ctx *ctx, double t) {
+  double off = 0.0, vel = 0.0;
+  int axis = -1;
+  if (ctx->motion_axis >= 0) {
+    axis = ctx->motion_axis;
+    off = ctx->motion_amp * std::sin(2.0 * kPi * ctx->motion_freq * t);
+    vel = ctx->motion_amp * 2.0 * kPi * ctx->motion_freq * std::cos(2.0 * kPi * ctx->motion_freq * t);
+  }
+  ibmk::run_place_markers(ctx->L, ctx->B, ctx->nc, off, vel, axis, ctx->dedupe);
+  ibmk::run_build_markers(ctx->L, ctx->B, ctx->nc);
+  HIPCHECK(ctx, hipGetLastError());
+  return IBM_OK;
+}
+
+ibm_status marker_flags(ibm_ctx *ctx, const int *f) {
+  if (f[1]) return fail(ctx, IBM_E_ARG, "a marker support leaves the (non-periodic) box");
+  if (f[3]) return fail(ctx, IBM_E_SIZE, "too many overlapping markers for one Gram row");
+  if (f[2]) return fail(ctx, IBM_E_NOT_CONVERGED, "the quadrature solve A eps = 1 did not converge");
+  return IBM_OK;
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+extern "C" {
+
+size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32_t tape_steps) {
+  if (check_desc(desc) || max_markers < 0 || tape_steps < 0) return 0;
+  GridK g = make_grid(*desc);
+  Bufs B;
+  int np;
+  return plan(*desc, g, max_markers, tape_steps, nullptr, B, np);
+}
+
+ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
+                           int32_t tape_steps, void *hip_stream, ibm_ctx **out) {
+  if (!out) return IBM_E_ARG;
+  *out = nullptr;
+  if (check_desc(desc)) return IBM_E_ARG;
+  if (tape_steps < 0) return IBM_E_ARG;
+  if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) return IBM_E_ARG;
+  const int nslot = desc->dim == 3 ? 27 : 9;
+  if ((int64_t)desc->max_markers * nslot >= ((int64_t)1 << ibmk::kPairBits)) return IBM_E_SIZE;
+  ibm_ctx *ctx = new (std::nothrow) ibm_ctx();
+  if (!ctx) return IBM_E_HIP;
+  ctx->desc = *desc;
+  ctx->L.g = make_grid(*desc);
+  ctx->L.prec = desc->precision;
+  ctx->L.nc_cap = std::max(desc->max_markers, 1);
+  ctx->L.st = (hipStream_t)hip_stream;
+  ctx->tape_cap = tape_steps;
+  size_t need = plan(*desc, ctx->L.g, desc->max_markers, tape_steps, (char *)dev_workspace, ctx->B,
+                     ctx->L.npairs_pad);
+  if (bytes < need) {
+    delete ctx;
+    return IBM_E_SIZE;
+  }
+  CgScal c0;
+  std::memset(&c0, 0, sizeof(c0));
+  c0.tol2 = desc->cg_rtol * desc->cg_rtol;
+  c0.maxit = desc->cg_maxit;
+  hipError_t e = hipMemcpyAsync(ctx->B.cg, &c0, sizeof(c0), hipMemcpyHostToDevice, ctx->L.st);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->B.flags, 0, 8 * sizeof(int), ctx->L.st);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->B.mcount, 0, 8 * sizeof(int), ctx->L.st);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->B.totals, 0, 8 * sizeof(double), ctx->L.st);
+  if (e == hipSuccess) {
+    ibmk::run_uniform_state(ctx->L, ctx->B, 0);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->L.st);
+  if (e != hipSuccess) {
+    delete ctx;
+    return IBM_E_HIP;
+  }
+  *out = ctx;
+  return IBM_OK;
+}
+
+void ibm_destroy(ibm_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->L.st);
+  delete ctx;
+}
+
+const char *ibm_last_error(const ibm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+double ibm_dt(const ibm_ctx *ctx) { return ctx ? ctx->L.g.dt : 0.0; }
+
+ibm_status ibm_init_primitive(ibm_ctx *ctx, const void *rho, const void *u, const void *theta) {
+  if (!ctx) return IBM_E_ARG;
+  if (!rho || !u || !theta) return fail(ctx, IBM_E_ARG, "init_primitive: NULL field");
+  ibmk::run_init_primitive(ctx->L, ctx->B, ctx->cur, rho, u, theta);
+  HIPCHECK(ctx, hipGetLastError());
+  ctx->step = 0;
+  if (ctx->nc > 0 && ctx->motion_axis >= 0) {
+    ibm_status s = rebuild_markers(ctx, 0.0);
+    if (s) return s;
+  }
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->L.st));
+  return IBM_OK;
+}
+
+ibm_status ibm_set_state(ibm_ctx *ctx, const void *rho, const void *mom, const void *eint,
+                         const void *face_flux, int64_t step) {
+  if (!ctx) return IBM_E_ARG;
+  if (!rho || !mom || !eint) return fail(ctx, IBM_E_ARG, "set_state: NULL field");
+  if (step < 0) return fail(ctx, IBM_E_ARG, "set_state: negative step");
+  const GridK &g = ctx->L.g;
+  const size_t w = ctx->L.prec ? 4 : 8;
+  const int c = ctx->cur;
+  hipStream_t st = ctx->L.st;
+  HIPCHECK(ctx, hipMemcpyAsync(ctx->B.rho[c], rho, g.N * w, hipMemcpyDeviceToDevice, st));
+  HIPCHECK(ctx, hipMemcpyAsync(ctx->B.E[c], eint, g.N * w, hipMemcpyDeviceToDevice, st));
+  for (int q = 0; q < g.dim; ++q)
+    HIPCHECK(ctx, hipMemcpyAsync(ctx->B.mom[c][q], (const char *)mom + q * g.N * w, g.N * w,
+                                 hipMemcpyDeviceToDevice, st));
+  if (face_flux) {
+    size_t off = 0;
+    for (int q = 0; q < g.dim; ++q) {
+      HIPCHECK(ctx, hipMemcpyAsync(ctx->B.F[c][q], (const char *)face_flux + off * w, g.NF[q] * w,
+                                   hipMemcpyDeviceToDevice, st));
+      off += g.NF[q];
+    }
+  } else {
+    ibmk::run_flux_from_momentum(ctx->L, ctx->B, c);
+    HIPCHECK(ctx, hipGetLastError());
+  }
+  ctx->step = step;
+  if (ctx->nc > 0 && ctx->motion_axis >= 0) {
+    ibm_status s = rebuild_markers(ctx, double(step) * g.dt);
+    if (s) return s;
+  }
+  HIPCHECK(ctx, hipStreamSynchronize(st));
+  return IBM_OK;
+}
+
+ibm_status ibm_get_state(const ibm_ctx *cctx, void *rho, void *mom, void *eint, void *face_flux) {
+  ibm_ctx *ctx = const_cast<ibm_ctx *>(cctx);
+  if (!ctx) return IBM_E_ARG;
+  const GridK &g = ctx->L.g;
+  const size_t w = ctx->L.prec ? 4 : 8;
+  const int c = ctx->cur;
+  hipStream_t st = ctx->L.st;
+  if (rho) HIPCHECK(ctx, hipMemcpyAsync(rho, ctx->B.rho[c], g.N * w, hipMemcpyDeviceToDevice, st));
+  if (eint) HIPCHECK(ctx, hipMemcpyAsync(eint, ctx->B.E[c], g.N * w, hipMemcpyDeviceToDevice, st));
+  if (mom)
+    for (int q = 0; q < g.dim; ++q)
+      HIPCHECK(ctx, hipMemcpyAsync((char *)mom + q * g.N * w, ctx->B.mom[c][q], g.N * w,
+                                   hipMemcpyDeviceToDevice, st));
+  if (face_flux) {
+    size_t off = 0;
+    for (int q = 0; q < g.dim; ++q) {
+      HIPCHECK(ctx, hipMemcpyAsync((char *)face_flux + off * w, ctx->B.F[c][q], g.NF[q] * w,
+                                   hipMemcpyDeviceToDevice, st));
+      off += g.NF[q];
+    }
+  }
+  return IBM_OK;
+}
+
+ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const double *U_d,
+                           const double *T_w, const double *dA, uint32_t flags) {
+  if (!ctx) return IBM_E_ARG;
+  if (n < 0) return fail(ctx, IBM_E_ARG, "set_markers: n < 0");
+  if (n > ctx->desc.max_markers) return fail(ctx, IBM_E_SIZE, "set_markers: n exceeds max_markers");
+  if (flags & ~IBM_DEDUPE) return fail(ctx, IBM_E_ARG, "set_markers: unknown flag");
+  if (n > 0 && !X) return fail(ctx, IBM_E_ARG, "set_markers: X is NULL");
+  const int dim = ctx->desc.dim;
+  hipStream_t st = ctx->L.st;
+  Bufs &B = ctx->B;
+  ctx->nc = 0;
+  if (n == 0) {
+    HIPCHECK(ctx, hipMemsetAsync(B.mcount, 0, 8 * sizeof(int), st));
+    HIPCHECK(ctx, hipStreamSynchronize(st));
+    return IBM_OK;
+  }
+  const size_t pitch_dst = 3 * sizeof(double), pitch_src = dim * sizeof(double);
+  HIPCHECK(ctx, hipMemsetAsync(B.cX0, 0, 3 * n * sizeof(double), st));
+  HIPCHECK(ctx, hipMemsetAsync(B.cUd0, 0, 3 * n * sizeof(double), st));
+  HIPCHECK(ctx, hipMemcpy2DAsync(B.cX0, pitch_dst, X, pitch_src, pitch_src, n,
+                                 hipMemcpyDeviceToDevice, st));
+  if (U_d)
+    HIPCHECK(ctx, hipMemcpy2DAsync(B.cUd0, pitch_dst, U_d, pitch_src, pitch_src, n,
+                                   hipMemcpyDeviceToDevice, st));
+  if (T_w)
+    HIPCHECK(ctx, hipMemcpyAsync(B.cTw, T_w, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    ibmk::run_fill(ctx->L, B.cTw, n, 1.0);
+  if (dA)
+    HIPCHECK(ctx, hipMemcpyAsync(B.cdA, dA, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  else
+    HIPCHECK(ctx, hipMemsetAsync(B.cdA, 0, n * sizeof(double), st));
+  ibmk::run_fill(ctx->L, B.ceps, n, dim == 3 ? 8.0 : 4.0);
+  HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
+  ctx->nc = n;
+  ctx->dedupe = (flags & IBM_DEDUPE) ? 1 : 0;
+  ibm_status s = rebuild_markers(ctx, double(ctx->step) * ctx->L.g.dt);
+  if (s) {
+    ctx->nc = 0;
+    return s;
+  }
+  int f[8];
+  s = sync_read(ctx, f, B.flags, sizeof(f));
+  if (s) return s;
+  s = marker_flags(ctx, f);
+  if (s) ctx->nc = 0;
+  return s;
+}
+
+ibm_status ibm_set_motion(ibm_ctx *ctx, int32_t axis, double amplitude, double frequency) {
+  if (!ctx) return IBM_E_ARG;
+  if (axis >= ctx->desc.dim) return fail(ctx, IBM_E_ARG, "set_motion: axis >= dim");
+  if (!std::isfinite(amplitude) || !std::isfinite(frequency))
+    return fail(ctx, IBM_E_ARG, "set_motion: non-finite parameter");
+  ctx->motion_axis = axis < 0 ? -1 : axis;
+  ctx->motion_amp = amplitude;
+  ctx->motion_freq = frequency;
+  if (ctx->nc > 0) {
+    hipStream_t st = ctx->L.st;
+    HIPCHECK(ctx, hipMemsetAsync(ctx->B.flags, 0, 8 * sizeof(int), st));
+    ibm_status s = rebuild_markers(ctx, double(ctx->step) * ctx->L.g.dt);
+    if (s) return s;
+    int f[8];
+    s = sync_read(ctx, f, ctx->B.flags, sizeof(f));
+    if (s) return s;
+    return marker_flags(ctx, f);
+  }
+  return IBM_OK;
+}
+
+ibm_status ibm_set_wall_temperature(ibm_ctx *ctx, const double *T_w) {
+  if (!ctx) return IBM_E_ARG;
+  if (ctx->nc == 0) return fail(ctx, IBM_E_STATE, "set_wall_temperature: no markers");
+  if (!T_w) return fail(ctx, IBM_E_ARG, "set_wall_temperature: NULL");
+  hipStream_t st = ctx->L.st;
+  HIPCHECK(ctx, hipMemcpyAsync(ctx->B.cTw, T_w, ctx->nc * sizeof(double), hipMemcpyDeviceToDevice,
+                               st));
+  // re-gather the markers in use (same time, same selection; eps unchanged)
+  double off = 0.0, vel = 0.0;
+  const double t = double(ctx->step) * ctx->L.g.dt;
+  if (ctx->motion_axis >= 0) {
+    off = ctx->motion_amp * std::sin(2.0 * kPi * ctx->motion_freq * t);
+    vel = ctx->motion_amp * 2.0 * kPi * ctx->motion_freq * std::cos(2.0 * kPi * ctx->motion_freq * t);
+  }
+  ibmk::run_place_markers(ctx->L, ctx->B, ctx->nc, off, vel, ctx->motion_axis, ctx->dedupe);
+  HIPCHECK(ctx, hipGetLastError());
+  HIPCHECK(ctx, hipStreamSynchronize(st));
+  return IBM_OK;
+}
+
+ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
+                    ibm_step_info *info) {
+  if (!ctx) return IBM_E_ARG;
+  if (n_steps < 0) return fail(ctx, IBM_E_ARG, "step: n_steps < 0");
+  if (flags & ~IBM_RECORD) return fail(ctx, IBM_E_ARG, "step: unknown flag");
+  if ((flags & IBM_RECORD) && ctx->tape_cap == 0)
+    return fail(ctx, IBM_E_SIZE, "step: no tape capacity for IBM_RECORD");
+  const Launch &L = ctx->L;
+  Bufs &B = ctx->B;
+  hipStream_t st = L.st;
+  ibm_status rc = IBM_OK;
+  int64_t done = 0;
+  int total_it = 0, last_it = 0;
+  double res = 0.0;
+  for (int s = 0; s < n_steps; ++s) {
+    HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
+    if (ctx->nc > 0 && ctx->motion_axis >= 0) {
+      ibm_status ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt);
+      if (ms) return ms;
+    }
+    ibmk::run_predictor(L, B, ctx->cur);
+    double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
+    if (ctx->nc > 0) {
+      ibmk::run_interp_force(L, B, hrow);
+      ibmk::run_spread(L, B);
+    } else if (hrow) {
+      HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
+    }
+    ibmk::run_setup(L, B, ctx->cur, ctx->desc.cg_rtol, ctx->desc.cg_maxit);
+    HIPCHECK(ctx, hipGetLastError());
+    int launched = 0, parity = 0, chunk = std::max(1, ctx->cg_hint);
+    for (;;) {
+      for (int c = 0; c < chunk; ++c) {
+        ibmk::run_cg_iteration(L, B, parity);
+        parity ^= 1;
+        ++launched;
+      }
+      HIPCHECK(ctx, hipGetLastError());
+      ibm_status r = sync_read(ctx, &ctx->cgh, B.cg, sizeof(CgScal));
+      if (r) return r;
+      if (ctx->cgh.done) break;
+      if (launched > ctx->desc.cg_maxit + 4) break;
+      chunk = 2;
+    }
+    ibmk::run_correct(L, B, ctx->cur);
+    HIPCHECK(ctx, hipGetLastError());
+    int f[8];
+    ibm_status r = sync_read(ctx, f, B.flags, sizeof(f));
+    if (r) return r;
+    if (f[1] || f[2] || f[3]) {
+      rc = marker_flags(ctx, f);
+      break;
+    }
+    if (f[0]) {
+      rc = fail(ctx, IBM_E_NONFINITE, "step produced a non-finite or non-positive value");
+      break;
+    }
+    ctx->cur ^= 1;
+    ctx->step += 1;
+    ++done;
+    last_it = ctx->cgh.iters;
+    total_it += last_it;
+    res = ctx->cgh.res;
+    ctx->cg_hint = std::max(1, last_it);
+    if (ctx->cgh.done != 1) {
+      rc = fail(ctx, IBM_E_NOT_CONVERGED, "pressure CG reached cg_maxit");
+      break;
+    }
+  }
+  if (info) {
+    info->steps_done = done;
+    info->step = ctx->step;
+    info->cg_iters_last = last_it;
+    info->cg_iters_total = total_it;
+    info->cg_residual = res;
+    info->dt = L.g.dt;
+    info->time = double(ctx->step) * L.g.dt;
+    double m = 0.0;
+    if (done > 0) {
+      ibm_status r = sync_read(ctx, &m, B.scal, sizeof(double));
+      if (r) return r;
+    }
+    info->mass = m;
+  }
+  return rc;
+}
+
+ibm_status ibm_wall_fluxes(const ibm_ctx *cctx, double *force, double *heat, double *totals) {
+  ibm_ctx *ctx = const_cast<ibm_ctx *>(cctx);
+  if (!ctx) return IBM_E_ARG;
+  hipStream_t st = ctx->L.st;
+  int nu = 0;
+  if (ctx->nc > 0) {
+    ibm_status r = sync_read(ctx, &nu, ctx->B.mcount, sizeof(int));
+    if (r) return r;
+  }
+  const int dim = ctx->desc.dim;
+  if (force && nu > 0)
+    HIPCHECK(ctx, hipMemcpy2DAsync(force, dim * sizeof(double), ctx->B.mforce, 3 * sizeof(double),
+                                   dim * sizeof(double), nu, hipMemcpyDeviceToDevice, st));
+  if (heat && nu > 0)
+    HIPCHECK(ctx, hipMemcpyAsync(heat, ctx->B.mheat, nu * sizeof(double), hipMemcpyDeviceToDevice,
+                                 st));
+  if (totals) {
+    if (ctx->nc > 0) {
+      ibm_status r = sync_read(ctx, totals, ctx->B.totals, 4 * sizeof(double));
+      if (r) return r;
+    } else {
+      for (int q = 0; q < 4; ++q) totals[q] = 0.0;
+    }
+  }
+  return IBM_OK;
+}
+
+ibm_status ibm_markers_in_use(const ibm_ctx *cctx, int32_t *n_used, int32_t *ids, double *eps) {
+  ibm_ctx *ctx = const_cast<ibm_ctx *>(cctx);
+  if (!ctx) return IBM_E_ARG;
+  int nu = 0;
+  if (ctx->nc > 0) {
+    ibm_status r = sync_read(ctx, &nu, ctx->B.mcount, sizeof(int));
+    if (r) return r;
+  }
+  if (n_used) *n_used = nu;
+  hipStream_t st = ctx->L.st;
+  if (ids && nu > 0)
+    HIPCHECK(ctx, hipMemcpyAsync(ids, ctx->B.ids, nu * sizeof(int), hipMemcpyDeviceToDevice, st));
+  if (eps && nu > 0)
+    HIPCHECK(ctx, hipMemcpyAsync(eps, ctx->B.eps, nu * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHECK(ctx, hipStreamSynchronize(st));
+  return IBM_OK;
+}
+
+ibm_status ibm_get_field(const ibm_ctx *cctx, int32_t which, void *dst) {
+  ibm_ctx *ctx = const_cast<ibm_ctx *>(cctx);
+  if (!ctx) return IBM_E_ARG;
+  if (!dst) return fail(ctx, IBM_E_ARG, "get_field: NULL destination");
+  const GridK &g = ctx->L.g;
+  const size_t w = ctx->L.prec ? 4 : 8;
+  hipStream_t st = ctx->L.st;
+  const Bufs &B = ctx->B;
+  switch (which) {
+    case 0:
+      HIPCHECK(ctx, hipMemcpyAsync(dst, B.rho_s, g.N * w, hipMemcpyDeviceToDevice, st));
+      break;
+    case 1:
+      for (int q = 0; q < g.dim; ++q)
+        HIPCHECK(ctx, hipMemcpyAsync((char *)dst + q * g.N * w, B.mom_s[q], g.N * w,
+                                     hipMemcpyDeviceToDevice, st));
+      break;
+    case 2:
+      HIPCHECK(ctx, hipMemcpyAsync(dst, B.E_s, g.N * w, hipMemcpyDeviceToDevice, st));
+      break;
+    case 3:
+      HIPCHECK(ctx, hipMemcpyAsync(dst, B.psi, g.N * w, hipMemcpyDeviceToDevice, st));
+      break;
+    case 4:
+      HIPCHECK(ctx, hipMemcpyAsync(dst, B.b, g.N * 8, hipMemcpyDeviceToDevice, st));
+      break;
+    case 5:
+      HIPCHECK(ctx, hipMemcpyAsync(dst, B.x, g.N * 8, hipMemcpyDeviceToDevice, st));
+      break;
+    case 6: {
+      int nu = 0;
+      if (ctx->nc > 0) {
+        ibm_status r = sync_read(ctx, &nu, B.mcount, sizeof(int));
+        if (r) return r;
+      }
+      if (nu > 0)
+        HIPCHECK(ctx, hipMemcpyAsync(dst, B.mk, (size_t)nu * (2 * g.dim + 3) * sizeof(double),
+                                     hipMemcpyDeviceToDevice, st));
+      break;
+    }
+    default:
+      return fail(ctx, IBM_E_ARG, "get_field: unknown field");
+  }
+  HIPCHECK(ctx, hipStreamSynchronize(st));
+  return IBM_OK;
+}
+
+}  // extern "C"

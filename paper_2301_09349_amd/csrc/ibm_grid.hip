@@ -1,0 +1,649 @@
+// ibm_grid.hip -- grid kernels of one IBM-HT time step on gfx950: the predictor
+// flux stencil, the pressure-equation set-up, the matrix-free CG and the
+// correction (Appendix A of Riahi, Goncalves da Silva, Meldi), plus state
+// initialisation. Templated on the dimension and on the storage/stencil type
+// (double, or float for the reduced-precision form).
+#include "ibm_launch.h"
+
+namespace ibmk {
+
+// ------------------------------------------------------------------ physics
+// Sutherland's law (Sec. 2.1), theta^{3/2} as theta*sqrt(theta).
+template <typename S>
+__device__ __forceinline__ S mu_of(const GridK &g, S th) {
+  if (g.visc == MU_CONSTANT) return S(g.mu_inf);
+  S sut = S(g.S);
+  return S(g.mu_inf) * th * sqrt(th) * (S(1) + sut) / (th + sut);
+}
+// lambda = c_p mu / Pr
+template <typename S>
+__device__ __forceinline__ S lam_of(const GridK &g, S th) {
+  return S(g.cp) * mu_of(g, th) / S(g.Pr);
+}
+// van Leer limited face value from the upwind (C), downwind (D) and far-upwind
+// (U) cell values: phi_C + (1/2) psi(r) (phi_D - phi_C), written without r.
+template <typename S>
+__device__ __forceinline__ S vanleer(S phC, S phD, S phU) {
+  S a = phC - phU, b = phD - phC;
+  S ab = a * b;
+  return (ab > S(0)) ? phC + ab / (a + b) : phC;
+}
+
+// Primitive variables at a (possibly ghost) cell.
+template <int DIM, typename S>
+__device__ __forceinline__ void load_prim(const GridK &g, const StateV<S> &st, int i, int j, int k,
+                                          S &rho, S *u, S &th, S &p) {
+  Resolved r = resolve<DIM>(g, i, j, k);
+  rho = st.rho[r.c];
+  S inv = S(1) / rho;
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) u[q] = st.mom[q][r.c] * inv;
+  S E = st.E[r.c];
+  th = E * inv * S(g.inv_cv);
+  p = S(g.gm1) * E;
+  if (any_side<DIM, S>(r)) {
+    rho = ghosted<DIM>(g, r, V_RHO, rho);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) u[q] = ghosted<DIM>(g, r, V_U0 + q, u[q]);
+    th = ghosted<DIM>(g, r, V_TH, th);
+    p = ghosted<DIM>(g, r, V_P, p);
+  }
+}
+
+template <int DIM, typename S>
+__device__ __forceinline__ void load_u(const GridK &g, const StateV<S> &st, int i, int j, int k,
+                                       S *u) {
+  Resolved r = resolve<DIM>(g, i, j, k);
+  S inv = S(1) / st.rho[r.c];
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) u[q] = st.mom[q][r.c] * inv;
+  if (any_side<DIM, S>(r)) {
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) u[q] = ghosted<DIM>(g, r, V_U0 + q, u[q]);
+  }
+}
+
+template <int DIM, typename S>
+__device__ __forceinline__ void load_u_th(const GridK &g, const StateV<S> &st, int i, int j, int k,
+                                          S *u, S &th) {
+  Resolved r = resolve<DIM>(g, i, j, k);
+  S inv = S(1) / st.rho[r.c];
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) u[q] = st.mom[q][r.c] * inv;
+  th = st.E[r.c] * inv * S(g.inv_cv);
+  if (any_side<DIM, S>(r)) {
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) u[q] = ghosted<DIM>(g, r, V_U0 + q, u[q]);
+    th = ghosted<DIM>(g, r, V_TH, th);
+  }
+}
+
+// Fluxes through the face of direction d with face index (fi, fj, fk), between
+// cells P = (.., f_d - 1, ..) and Q = (.., f_d, ..), in the +e_d direction:
+// face-normal velocity uf = F / lin_f(rho), momentum fluxes F u_f - tau_{d,q},
+// energy flux F e_f - lambda_f d theta / d n. Normal velocity derivatives are
+// compact, tangential ones the face average of the two centred cell gradients.
+template <int DIM, typename S>
+__device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, int d, int fi,
+                                          int fj, int fk, S &uf, S *fm, S &fe) {
+  int P[3] = {fi, fj, fk}, Q[3] = {fi, fj, fk};
+  P[d] -= 1;
+  const S F = st.F[d][fidx(g, d, fi, fj, fk)];
+  S rP, uP[3], thP, pP, rQ, uQ[3], thQ, pQ;
+  load_prim<DIM>(g, st, P[0], P[1], P[2], rP, uP, thP, pP);
+  load_prim<DIM>(g, st, Q[0], Q[1], Q[2], rQ, uQ, thQ, pQ);
+  uf = F / (S(0.5) * (rP + rQ));
+  const S muf = S(0.5) * (mu_of(g, thP) + mu_of(g, thQ));
+  const S lamf = S(0.5) * (lam_of(g, thP) + lam_of(g, thQ));
+  const S ih = S(g.ih[d]);
+  S dn[3], tg[3] = {S(0), S(0), S(0)};
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) dn[q] = (uQ[q] - uP[q]) * ih;
+  S divf = dn[d];
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    if (t == d) continue;
+    const S hh = S(0.5 * g.ih[t]);
+    S up[3], um[3];
+    int a[3] = {P[0], P[1], P[2]}, b[3] = {P[0], P[1], P[2]};
+    a[t] += 1;
+    b[t] -= 1;
+    load_u<DIM>(g, st, a[0], a[1], a[2], up);
+    load_u<DIM>(g, st, b[0], b[1], b[2], um);
+    S gdP = (up[d] - um[d]) * hh, gtP = (up[t] - um[t]) * hh;
+    int c2[3] = {Q[0], Q[1], Q[2]}, e2[3] = {Q[0], Q[1], Q[2]};
+    c2[t] += 1;
+    e2[t] -= 1;
+    load_u<DIM>(g, st, c2[0], c2[1], c2[2], up);
+    load_u<DIM>(g, st, e2[0], e2[1], e2[2], um);
+    S gdQ = (up[d] - um[d]) * hh, gtQ = (up[t] - um[t]) * hh;
+    tg[t] = S(0.5) * (gdP + gdQ);
+    divf += S(0.5) * (gtP + gtQ);
+  }
+  S cu[3], ce;
+  const S cv = S(g.cv);
+  if (g.conv == CONV_LINEAR) {
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) cu[q] = S(0.5) * (uP[q] + uQ[q]);
+    ce = S(0.5) * (cv * thP + cv * thQ);
+  } else {
+    const bool pos = F >= S(0);
+    int U[3] = {pos ? P[0] : Q[0], pos ? P[1] : Q[1], pos ? P[2] : Q[2]};
+    U[d] += pos ? -1 : 1;
+    S uU[3], thU;
+    load_u_th<DIM>(g, st, U[0], U[1], U[2], uU, thU);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q)
+      cu[q] = pos ? vanleer(uP[q], uQ[q], uU[q]) : vanleer(uQ[q], uP[q], uU[q]);
+    ce = pos ? vanleer(cv * thP, cv * thQ, cv * thU) : vanleer(cv * thQ, cv * thP, cv * thU);
+  }
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    S tau = (q == d) ? muf * (S(2) * dn[d] - S(2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+    fm[q] = F * cu[q] - tau;
+  }
+  fe = F * ce - lamf * (thQ - thP) * ih;
+}
+
+// ----------------------------------------------------- Appendix A, step 1
+// Predictor (f = q = 0): explicit update of mass, momentum and internal energy.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S *rho_s, S *ms0,
+                                                        S *ms1, S *ms2, S *E_s) {
+  int i, j, k;
+  if (!cell_of_thread<DIM>(g, i, j, k)) return;
+  const int64_t c = cidx(g, i, j, k);
+  S divF = S(0), divU = S(0), divE = S(0), divM[3] = {S(0), S(0), S(0)};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+    hi[d] += 1;
+    S ufL, fmL[3], feL, ufH, fmH[3], feH;
+    face_flux<DIM>(g, st, d, lo[0], lo[1], lo[2], ufL, fmL, feL);
+    face_flux<DIM>(g, st, d, hi[0], hi[1], hi[2], ufH, fmH, feH);
+    const S FL = st.F[d][fidx(g, d, lo[0], lo[1], lo[2])];
+    const S FH = st.F[d][fidx(g, d, hi[0], hi[1], hi[2])];
+    const S ih = S(g.ih[d]);
+    divF += (FH - FL) * ih;
+    divU += (ufH - ufL) * ih;
+    divE += (feH - feL) * ih;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) divM[q] += (fmH[q] - fmL[q]) * ih;
+  }
+  // cell-centred velocity gradients gr[a][b] = d u_a / d x_b and pressure gradient
+  S gr[3][3], gp[3];
+#pragma unroll
+  for (int b = 0; b < DIM; ++b) {
+    int a1[3] = {i, j, k}, a0[3] = {i, j, k};
+    a1[b] += 1;
+    a0[b] -= 1;
+    S r1, u1[3], t1, p1, r0, u0[3], t0, p0;
+    load_prim<DIM>(g, st, a1[0], a1[1], a1[2], r1, u1, t1, p1);
+    load_prim<DIM>(g, st, a0[0], a0[1], a0[2], r0, u0, t0, p0);
+    const S hh = S(0.5 * g.ih[b]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) gr[a][b] = (u1[a] - u0[a]) * hh;
+    gp[b] = (p1 - p0) * hh;
+  }
+  S divu = S(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) divu += gr[a][a];
+  S phi = S(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) phi += (gr[a][b] + gr[b][a]) * gr[a][b];
+  const S rho = st.rho[c], E = st.E[c];
+  const S th = E * (S(1) / rho) * S(g.inv_cv);
+  phi = mu_of(g, th) * (phi - S(2.0 / 3.0) * divu * divu);
+  const S dt = S(g.dt);
+  const S pc = S(g.gm1) * E;
+  rho_s[c] = rho - dt * divF;
+  S *ms[3] = {ms0, ms1, ms2};
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) ms[q][c] = st.mom[q][c] - dt * divM[q] - dt * gp[q];
+  E_s[c] = E - dt * divE - dt * pc * divU + dt * phi;
+}
+
+// ------------------------------------------------------- initialisation
+__global__ void k_fill(double *p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// uniform stream rho = 1, u = U_inf, theta = 1
+template <int DIM, typename S>
+__global__ void k_uniform(GridK g, StateV<S> st) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  st.rho[c] = S(1);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) st.mom[q][c] = S(g.U_inf[q]);
+  st.E[c] = S(g.cv);
+}
+
+template <int DIM, typename S>
+__global__ void k_init_primitive(GridK g, StateV<S> st, const S *rho, const S *u, const S *th) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  S r = rho[c];
+  st.rho[c] = r;
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) st.mom[q][c] = r * u[(int64_t)q * g.N + c];
+  st.E[c] = r * S(g.cv) * th[c];
+}
+
+// Face mass flux from cell momentum: linear interpolation inside; boundary faces
+// by their rule (inflow rho_P U_inf, slip 0, outflow m_P).
+template <int DIM, typename S, typename M>
+__device__ __forceinline__ S face_from_cells(const GridK &g, M *const *m, const S *rho0, int d,
+                                             int fi, int fj, int fk) {
+  int ix[3] = {fi, fj, fk};
+  int id = ix[d], n = g.n[d];
+  if (g.bc[d][0] == BC_PERIODIC || (id > 0 && id < n)) {
+    int P[3] = {fi, fj, fk}, Q[3] = {fi, fj, fk};
+    P[d] = (id - 1 + n) % n;
+    Q[d] = id % n;
+    return S(0.5) * (S(m[d][cidx(g, P[0], P[1], P[2])]) + S(m[d][cidx(g, Q[0], Q[1], Q[2])]));
+  }
+  int side = (id == 0) ? 0 : 1;
+  int A[3] = {fi, fj, fk};
+  A[d] = side == 0 ? 0 : n - 1;
+  int64_t ca = cidx(g, A[0], A[1], A[2]);
+  int b = g.bc[d][side];
+  if (b == BC_INFLOW) return rho0[ca] * S(g.U_inf[d]);
+  if (b == BC_SLIP) return S(0);
+  return S(m[d][ca]);
+}
+
+template <int DIM, typename S>
+__global__ void k_flux_from_mom(GridK g, StateV<S> st, int d) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.NF[d]) return;
+  int fi = (int)(f % g.fn[d][0]);
+  int64_t r = f / g.fn[d][0];
+  int fj = (int)(r % g.fn[d][1]);
+  int fk = (int)(r / g.fn[d][1]);
+  st.F[d][f] = face_from_cells<DIM, S>(g, st.mom, st.rho, d, fi, fj, fk);
+}
+
+// --------------------------------------------------- Appendix A, step 3
+// Pressure set-up, part 1: p^n = (gamma-1) E^n; m^ = mom** + dt G_c p^n;
+// theta** = E**/(rho* c_v); psi = 1/(R theta**); CG start x = p^n.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_setup1(GridK g, StateV<S> st, const S *rho_s,
+                                                     const S *ms0, const S *ms1, const S *ms2,
+                                                     const S *E_s, S *mh0, S *mh1, S *mh2, S *psi,
+                                                     double *x) {
+  int i, j, k;
+  if (!cell_of_thread<DIM>(g, i, j, k)) return;
+  const int64_t c = cidx(g, i, j, k);
+  const S *ms[3] = {ms0, ms1, ms2};
+  S *mh[3] = {mh0, mh1, mh2};
+  const S gm1 = S(g.gm1);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    int a1[3] = {i, j, k}, a0[3] = {i, j, k};
+    a1[q] += 1;
+    a0[q] -= 1;
+    Resolved r1 = resolve<DIM>(g, a1[0], a1[1], a1[2]);
+    Resolved r0 = resolve<DIM>(g, a0[0], a0[1], a0[2]);
+    S p1 = ghosted<DIM>(g, r1, V_P, gm1 * st.E[r1.c]);
+    S p0 = ghosted<DIM>(g, r0, V_P, gm1 * st.E[r0.c]);
+    mh[q][c] = ms[q][c] + S(g.dt) * ((p1 - p0) * S(0.5 * g.ih[q]));
+  }
+  const S theta = E_s[c] / (rho_s[c] * S(g.cv));
+  psi[c] = S(1) / (S(g.R) * theta);
+  x[c] = double(gm1 * st.E[c]);
+}
+
+// Homogeneous pressure operator at one cell: psi v - dt^2 div(grad_f v), zero
+// normal gradient at inflow and slip faces, v = 0 beyond outflow faces.
+template <int DIM, typename S, typename VF>
+__device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, int i, int j, int k,
+                                          int64_t c, double vc) {
+  double lap = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double ih = g.ih[d];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int ix[3] = {i, j, k};
+      ix[d] += side ? 1 : -1;
+      const int n = g.n[d];
+      double gf;
+      if (ix[d] >= 0 && ix[d] < n) {
+        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+      } else if (g.bc[d][0] == BC_PERIODIC) {
+        ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
+        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+      } else {
+        gf = (g.bc[d][side] == BC_OUTFLOW) ? (-2.0 * vc) * ih : 0.0;
+      }
+      lap += gf * ih;
+    }
+  }
+  return double(psi[c]) * vc - g.dt * g.dt * lap;
+}
+
+// Pressure set-up, part 2, fused with the CG start: predicted face flux
+// F^ = lin_f(m^) (boundary rules), b = rho^n - dt D(F^) + outflow terms,
+// r = b - A x, p = r; FP64 partial sums of b.b and r.r.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, const S *mh0,
+                                                     const S *mh1, const S *mh2, S *Fh0, S *Fh1,
+                                                     S *Fh2, const S *psi, const double *x,
+                                                     double *b, double *r, double *p,
+                                                     double *partials, CgScal *cs) {
+  __shared__ double lds[32];
+  int i, j, k;
+  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  double sums[2] = {0.0, 0.0};
+  if (valid) {
+    const int64_t c = cidx(g, i, j, k);
+    const S *mh[3] = {mh0, mh1, mh2};
+    S *Fh[3] = {Fh0, Fh1, Fh2};
+    const int ix[3] = {i, j, k};
+    double div = 0.0, aff = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int hi[3] = {i, j, k};
+      hi[d] += 1;
+      S fl = face_from_cells<DIM, S>(g, mh, rho_n, d, i, j, k);
+      S fh = face_from_cells<DIM, S>(g, mh, rho_n, d, hi[0], hi[1], hi[2]);
+      Fh[d][fidx(g, d, i, j, k)] = fl;
+      if (ix[d] == g.n[d] - 1) Fh[d][fidx(g, d, hi[0], hi[1], hi[2])] = fh;
+      div += (double(fh) - double(fl)) * g.ih[d];
+      if (g.bc[d][0] != BC_PERIODIC) {
+        if (ix[d] == 0 && g.bc[d][0] == BC_OUTFLOW) aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
+        if (ix[d] == g.n[d] - 1 && g.bc[d][1] == BC_OUTFLOW)
+          aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
+      }
+    }
+    const double bc_ = double(rho_n[c]) - g.dt * div + g.dt * g.dt * aff;
+    const double xc = x[c];
+    const double ax = helm_at<DIM>(g, psi, [&](int64_t q) { return x[q]; }, i, j, k, c, xc);
+    const double rc = bc_ - ax;
+    b[c] = bc_;
+    r[c] = rc;
+    p[c] = rc;
+    sums[0] = bc_ * bc_;
+    sums[1] = rc * rc;
+  }
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = sums[0];
+    partials[2 * blockIdx.x + 1] = sums[1];
+  }
+  if (arrive_last(&cs->counter_c, gridDim.x)) {
+    double v[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+      v[0] += load_coherent(partials + 2 * q);
+      v[1] += load_coherent(partials + 2 * q + 1);
+    }
+    block_sum_n<2>(v, lds);
+    if (threadIdx.x == 0) {
+      cs->bb = v[0];
+      cs->rr = v[1];
+      cs->res = v[0] > 0.0 ? sqrt(v[1] / v[0]) : 0.0;
+      cs->done = (v[1] <= cs->tol2 * v[0]) ? 1 : 0;
+      cs->iters = 0;
+      cs->beta = 0.0;
+      cs->counter_c = 0;
+    }
+  }
+}
+
+// CG part a: p = r + beta p_old (on the fly at the neighbours), q = A p,
+// partial p.q; the last block forms alpha = r.r / p.q.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_cg_a(GridK g, const S *psi, const double *r,
+                                                   const double *pold, double *pnew, double *q,
+                                                   double *partials, CgScal *cs) {
+  __shared__ double lds[32];
+  if (cs->done) return;
+  const double beta = cs->beta;
+  int i, j, k;
+  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  double pq = 0.0;
+  if (valid) {
+    const int64_t c = cidx(g, i, j, k);
+    auto pv = [&](int64_t m) { return r[m] + beta * pold[m]; };
+    const double pc = pv(c);
+    const double qc = helm_at<DIM>(g, psi, pv, i, j, k, c, pc);
+    pnew[c] = pc;
+    q[c] = qc;
+    pq = pc * qc;
+  }
+  double s = block_sum(pq, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (arrive_last(&cs->counter_a, gridDim.x)) {
+    double tot = sum_partials(partials, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+      cs->alpha = cs->rr / tot;
+      cs->counter_a = 0;
+    }
+  }
+}
+
+// CG part b: x += alpha p, r -= alpha q, partial r.r; the last block tests
+// convergence (|r| <= rtol |b|) and forms beta.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_cg_b(GridK g, double *x, double *r, const double *p,
+                                                   const double *q, double *partials, CgScal *cs) {
+  __shared__ double lds[32];
+  if (cs->done) return;
+  const double alpha = cs->alpha;
+  int i, j, k;
+  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  double rr = 0.0;
+  if (valid) {
+    const int64_t c = cidx(g, i, j, k);
+    x[c] += alpha * p[c];
+    const double rc = r[c] - alpha * q[c];
+    r[c] = rc;
+    rr = rc * rc;
+  }
+  double s = block_sum(rr, lds);
+  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s;
+  if (arrive_last(&cs->counter_b, gridDim.x)) {
+    double rn = sum_partials(partials + gridDim.x, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+      cs->iters += 1;
+      cs->res = cs->bb > 0.0 ? sqrt(rn / cs->bb) : 0.0;
+      if (rn <= cs->tol2 * cs->bb) {
+        cs->done = 1;
+      } else {
+        cs->beta = rn / cs->rr;
+        cs->rr = rn;
+        if (cs->iters >= cs->maxit) cs->done = 2;
+      }
+      cs->counter_b = 0;
+    }
+  }
+}
+
+// Pressure with its ghost rule (zero gradient at inflow and slip, p_inf on
+// outflow faces).
+template <int DIM>
+__device__ __forceinline__ double pres_at(const GridK &g, const double *x, int i, int j, int k) {
+  Resolved r = resolve<DIM>(g, i, j, k);
+  return ghosted<DIM>(g, r, V_P, x[r.c]);
+}
+
+// Correction: F^{n+1} = F^ - dt grad_f p; rho^{n+1} = rho^n - dt D(F^{n+1});
+// m^{n+1} = m^ - dt G_c p; E^{n+1} = rho^{n+1} c_v theta**. Writes the other
+// state copy; flags non-finite results; FP64 partial sums of the mass.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, StateV<S> nxt,
+                                                      const S *rho_s, const S *E_s, const S *mh0,
+                                                      const S *mh1, const S *mh2, const S *Fh0,
+                                                      const S *Fh1, const S *Fh2, const double *x,
+                                                      double *partials, CgScal *cs, double *mass,
+                                                      int *flags) {
+  __shared__ double lds[32];
+  int i, j, k;
+  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  double m = 0.0;
+  if (valid) {
+    const int64_t c = cidx(g, i, j, k);
+    const S *mh[3] = {mh0, mh1, mh2};
+    const S *Fh[3] = {Fh0, Fh1, Fh2};
+    const int ix[3] = {i, j, k};
+    const double dt = g.dt;
+    const double xc = pres_at<DIM>(g, x, i, j, k);
+    double div = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+      lo[d] -= 1;
+      hi[d] += 1;
+      const double xl = pres_at<DIM>(g, x, lo[0], lo[1], lo[2]);
+      const double xh = pres_at<DIM>(g, x, hi[0], hi[1], hi[2]);
+      const int64_t fl = fidx(g, d, i, j, k), fh = fidx(g, d, hi[0], hi[1], hi[2]);
+      const double Fl = double(Fh[d][fl]) - dt * ((xc - xl) * g.ih[d]);
+      const double Fu = double(Fh[d][fh]) - dt * ((xh - xc) * g.ih[d]);
+      nxt.F[d][fl] = S(Fl);
+      if (ix[d] == g.n[d] - 1) nxt.F[d][fh] = S(Fu);
+      div += (Fu - Fl) * g.ih[d];
+      const double mn = double(mh[d][c]) - dt * ((xh - xl) * (0.5 * g.ih[d]));
+      nxt.mom[d][c] = S(mn);
+      bad = bad || !isfinite(mn);
+    }
+    const double rn = double(cur.rho[c]) - dt * div;
+    const double theta = double(E_s[c] / (rho_s[c] * S(g.cv)));
+    const double En = rn * g.cv * theta;
+    nxt.rho[c] = S(rn);
+    nxt.E[c] = S(En);
+    bad = bad || !(rn > 0.0) || !(theta > 0.0) || !isfinite(rn) || !isfinite(En);
+    if (bad) atomicOr(flags, 1);
+    m = rn * g.dV;
+  }
+  double s = block_sum(m, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (arrive_last(&cs->counter_a, gridDim.x)) {
+    double tot = sum_partials(partials, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+      *mass = tot;
+      cs->counter_a = 0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+int64_t cell_blocks(const GridK &g) { return g.nblocks; }
+
+template <typename S>
+static StateV<S> state_of(const Bufs &B, int cur) {
+  StateV<S> s;
+  s.rho = (S *)B.rho[cur];
+  s.E = (S *)B.E[cur];
+  for (int q = 0; q < 3; ++q) {
+    s.mom[q] = (S *)B.mom[cur][q];
+    s.F[q] = (S *)B.F[cur][q];
+  }
+  return s;
+}
+
+#define IBM_DISPATCH(L, ...)                         \
+  do {                                               \
+    if ((L).g.dim == 2 && (L).prec == 0) {           \
+      constexpr int DIM = 2;                         \
+      using S = double;                              \
+      __VA_ARGS__;                                   \
+    } else if ((L).g.dim == 2) {                     \
+      constexpr int DIM = 2;                         \
+      using S = float;                               \
+      __VA_ARGS__;                                   \
+    } else if ((L).prec == 0) {                      \
+      constexpr int DIM = 3;                         \
+      using S = double;                              \
+      __VA_ARGS__;                                   \
+    } else {                                         \
+      constexpr int DIM = 3;                         \
+      using S = float;                               \
+      __VA_ARGS__;                                   \
+    }                                                \
+  } while (0)
+
+void run_fill(const Launch &L, double *p, int64_t n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, L.st, p, n, v);
+}
+
+void run_uniform_state(const Launch &L, const Bufs &B, int cur) {
+  IBM_DISPATCH(L, {
+    int64_t nb = (L.g.N + 255) / 256;
+    hipLaunchKernelGGL((k_uniform<DIM, S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g,
+                       state_of<S>(B, cur));
+  });
+  run_flux_from_momentum(L, B, cur);
+}
+
+void run_init_primitive(const Launch &L, const Bufs &B, int cur, const void *rho, const void *u,
+                        const void *theta) {
+  IBM_DISPATCH(L, {
+    int64_t nb = (L.g.N + 255) / 256;
+    hipLaunchKernelGGL((k_init_primitive<DIM, S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g,
+                       state_of<S>(B, cur), (const S *)rho, (const S *)u, (const S *)theta);
+  });
+  run_flux_from_momentum(L, B, cur);
+}
+
+void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur) {
+  IBM_DISPATCH(L, {
+    for (int d = 0; d < DIM; ++d) {
+      int64_t nb = (L.g.NF[d] + 255) / 256;
+      hipLaunchKernelGGL((k_flux_from_mom<DIM, S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g,
+                         state_of<S>(B, cur), d);
+    }
+  });
+}
+
+void run_predictor(const Launch &L, const Bufs &B, int cur) {
+  IBM_DISPATCH(L, {
+    hipLaunchKernelGGL((k_predictor<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                       L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0], (S *)B.mom_s[1],
+                       (S *)B.mom_s[2], (S *)B.E_s);
+  });
+}
+
+void run_setup(const Launch &L, const Bufs &B, int cur, double rtol, int maxit) {
+  (void)rtol;
+  (void)maxit;
+  IBM_DISPATCH(L, {
+    hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                       L.g, state_of<S>(B, cur), (const S *)B.rho_s, (const S *)B.mom_s[0],
+                       (const S *)B.mom_s[1], (const S *)B.mom_s[2], (const S *)B.E_s,
+                       (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], (S *)B.psi, B.x);
+    hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                       L.g, (const S *)B.rho[cur], (const S *)B.mhat[0], (const S *)B.mhat[1],
+                       (const S *)B.mhat[2], (S *)B.Fhat[0], (S *)B.Fhat[1], (S *)B.Fhat[2],
+                       (const S *)B.psi, (const double *)B.x, B.b, B.r, B.p[0], B.partials, B.cg);
+  });
+}
+
+void run_cg_iteration(const Launch &L, const Bufs &B, int parity) {
+  IBM_DISPATCH(L, {
+    double *pold = B.p[parity], *pnew = B.p[parity ^ 1];
+    hipLaunchKernelGGL((k_cg_a<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+                       (const S *)B.psi, (const double *)B.r, (const double *)pold, pnew, B.q,
+                       B.partials, B.cg);
+    hipLaunchKernelGGL((k_cg_b<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+                       B.x, B.r, (const double *)pnew, (const double *)B.q, B.partials, B.cg);
+  });
+}
+
+void run_correct(const Launch &L, const Bufs &B, int cur) {
+  IBM_DISPATCH(L, {
+    hipLaunchKernelGGL((k_correct<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                       L.g, state_of<S>(B, cur), state_of<S>(B, cur ^ 1), (const S *)B.rho_s,
+                       (const S *)B.E_s, (const S *)B.mhat[0], (const S *)B.mhat[1],
+                       (const S *)B.mhat[2], (const S *)B.Fhat[0], (const S *)B.Fhat[1],
+                       (const S *)B.Fhat[2], (const double *)B.x, B.partials, B.cg, B.scal,
+                       B.flags);
+  });
+}
+
+}  // namespace ibmk

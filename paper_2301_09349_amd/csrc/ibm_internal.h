@@ -1,0 +1,231 @@
+// ibm_internal.h -- device-side types and helpers shared by the HIP kernels of the
+// IBM-HT library (grid stencils, pressure CG, marker operations) and its host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace ibmk {
+
+constexpr int BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_SLIP = 3;
+constexpr int CONV_VANLEER = 0, CONV_LINEAR = 1;
+constexpr int MU_SUTHERLAND = 0, MU_CONSTANT = 1;
+// kinds of cell variables, selecting the ghost rule of a boundary side
+constexpr int V_RHO = 0, V_U0 = 1, V_TH = 4, V_P = 5, V_PHOM = 7;
+
+constexpr int kThreads = 256;      // threads per block of the grid kernels
+constexpr int kRedThreads = 1024;  // threads of the single-block marker kernels
+constexpr int kPairBits = 20;      // (cell << 20) | pair id in the sorted pair keys
+constexpr int kMaxNbr = 192;       // neighbours per marker row of the Gram matrix
+
+// Grid, physics and time-step constants, passed by value to every grid kernel.
+struct GridK {
+  int dim;
+  int n[3];
+  int fn[3][3];       // dims of the face array of each direction
+  int64_t N;
+  int64_t NF[3];
+  double lo[3], h[3], ih[3];
+  int bc[3][2];
+  int conv, visc;
+  double dt, R, cv, inv_cv, cp, gm1, mu_inf, S, Pr, p_inf, dV;
+  double U_inf[3];
+  int tiles[3];       // tiles per direction of the cell kernels
+  int64_t ntiles;     // tiles in all
+  int64_t nblocks;    // blocks launched: ntiles rounded up to a multiple of 8
+};
+
+template <typename S>
+struct StateV {
+  S *rho;
+  S *mom[3];
+  S *E;
+  S *F[3];
+};
+
+// Scalars of one pressure solve, in device memory.
+struct CgScal {
+  double bb, rr, tol2, alpha, beta, res;
+  int iters, done, maxit, nonfinite;
+  unsigned counter_a, counter_b, counter_c, pad;
+};
+
+__device__ __forceinline__ int64_t cidx(const GridK &g, int i, int j, int k) {
+  return i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k);
+}
+__device__ __forceinline__ int64_t fidx(const GridK &g, int d, int i, int j, int k) {
+  return i + (int64_t)g.fn[d][0] * (j + (int64_t)g.fn[d][1] * k);
+}
+
+// Cell coordinates of a thread of a cell kernel. Tiles of kThreads cells
+// (64 x 4 in 2D, 64 x 2 x 2 in 3D); consecutive tiles are handed to one XCD so
+// that neighbouring tiles share an L2 (blocks are dealt round-robin to the 8 XCDs).
+// The grid is launched with 8 * ceil(ntiles / 8) blocks; block b runs on XCD b % 8
+// and takes tile (b % 8) * (gridDim / 8) + b / 8; tiles past ntiles are idle.
+template <int DIM>
+__device__ __forceinline__ bool cell_of_thread(const GridK &g, int &i, int &j, int &k) {
+  int64_t b = blockIdx.x;
+  int64_t per = gridDim.x >> 3;
+  int64_t t = (b & 7) * per + (b >> 3);
+  if (t >= g.ntiles) return false;
+  int tx = (int)(t % g.tiles[0]);
+  int64_t r = t / g.tiles[0];
+  int ty = (int)(r % g.tiles[1]);
+  int tz = (int)(r / g.tiles[1]);
+  int lx = threadIdx.x & 63, ly, lz;
+  if (DIM == 2) {
+    ly = threadIdx.x >> 6;
+    lz = 0;
+    i = tx * 64 + lx;
+    j = ty * 4 + ly;
+    k = 0;
+  } else {
+    ly = (threadIdx.x >> 6) & 1;
+    lz = threadIdx.x >> 7;
+    i = tx * 64 + lx;
+    j = ty * 2 + ly;
+    k = tz * 2 + lz;
+  }
+  return i < g.n[0] && j < g.n[1] && k < g.n[2];
+}
+
+// An index up to two layers outside the box, resolved to an interior cell and the
+// boundary sides crossed (-1: none, 0: low side, 1: high side) per direction.
+struct Resolved {
+  int64_t c;
+  int side[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ Resolved resolve(const GridK &g, int i, int j, int k) {
+  int ix[3] = {i, j, k};
+  Resolved r;
+  r.side[0] = r.side[1] = r.side[2] = -1;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    int v = ix[d], n = g.n[d];
+    if (v < 0 || v >= n) {
+      if (g.bc[d][0] == BC_PERIODIC) {
+        v = v < 0 ? v + n : v - n;
+      } else {
+        r.side[d] = v < 0 ? 0 : 1;
+        v = v < 0 ? -v - 1 : 2 * n - 1 - v;
+      }
+      ix[d] = v;
+    }
+  }
+  r.c = ix[0] + (int64_t)g.n[0] * (ix[1] + (int64_t)g.n[1] * ix[2]);
+  return r;
+}
+
+// Ghost value of one boundary side: sigma * (mirror value) + c.
+template <typename T>
+__device__ __forceinline__ T side_rule(const GridK &g, int bc, int var, int d, T v) {
+  if (bc == BC_INFLOW) {
+    if (var >= V_U0 && var < V_U0 + 3) return T(2.0 * g.U_inf[var - V_U0]) - v;
+    if (var == V_TH) return T(2.0) - v;
+    return v;
+  }
+  if (bc == BC_OUTFLOW) {
+    if (var == V_P) return T(2.0 * g.p_inf) - v;
+    if (var == V_PHOM) return -v;
+    return v;
+  }
+  if (bc == BC_SLIP) {
+    if (var == V_U0 + d) return -v;
+    return v;
+  }
+  return v;
+}
+
+// Applies the rules of all sides crossed, the last direction first (x outermost).
+template <int DIM, typename T>
+__device__ __forceinline__ T ghosted(const GridK &g, const Resolved &r, int var, T v) {
+#pragma unroll
+  for (int d = DIM - 1; d >= 0; --d)
+    if (r.side[d] >= 0) v = side_rule(g, g.bc[d][r.side[d]], var, d, v);
+  return v;
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ bool any_side(const Resolved &r) {
+  bool a = false;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) a = a || (r.side[d] >= 0);
+  return a;
+}
+
+// -------------------------------------------------------------- reductions
+// Block sum of a double over a block of blockDim.x threads (multiple of 64);
+// fixed shuffle/LDS order, so the result is deterministic. Valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds /* >= 16 */) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; ++q) s += lds[q];
+  }
+  return s;
+}
+
+// Block sums of NV doubles at once.
+template <int NV>
+__device__ __forceinline__ void block_sum_n(double *v, double *lds /* >= 16*NV */) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_down(v[q], o, 64);
+  }
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[q * 16 + w] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int p = 0; p < nw; ++p) s += lds[q * 16 + p];
+      v[q] = s;
+    }
+  }
+}
+
+// True in every thread of the last block of the grid to arrive; the partials
+// written by all blocks before the call are then visible to it. The counter is
+// reset by the caller's last block when done.
+__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblocks) {
+  __shared__ int am_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    am_last = (prev == nblocks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (am_last) __threadfence();
+  return am_last != 0;
+}
+
+__device__ __forceinline__ double load_coherent(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of partials[0..n) in a fixed order by one block (all threads call).
+__device__ __forceinline__ double sum_partials(const double *partials, int n, double *lds) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += load_coherent(partials + i);
+  return block_sum(v, lds);
+}
+
+}  // namespace ibmk

@@ -1,0 +1,78 @@
+// ibm_launch.h -- device buffers of a context and the host-side launchers of the
+// grid and marker kernels (defined in ibm_grid.hip and ibm_markers.hip).
+#pragma once
+
+#include "ibm_internal.h"
+
+namespace ibmk {
+
+// Device buffers carved from the caller's workspace.
+struct Bufs {
+  // conserved state, two copies (ping-pong): rho, mom[3], E, F[3]
+  void *rho[2], *mom[2][3], *E[2], *F[2][3];
+  // predictor output; mom_s and E_s become mom** and E** after spreading
+  void *rho_s, *mom_s[3], *E_s;
+  // pressure equation: m^ = mom** + dt G p^n, its face flux, psi
+  void *mhat[3], *Fhat[3], *psi;
+  // pressure CG (FP64)
+  double *b, *x, *r, *p[2], *q;
+  double *partials;  // per-block partial sums, 4 per block
+  CgScal *cg;
+  double *scal;      // [0] mass
+  int *flags;        // [0] non-finite, [1] support out of box, [2] eps solve failed,
+                     // [3] Gram row overflow
+
+  // candidate markers
+  double *cX0, *cUd0, *cTw, *cdA, *ceps;  // ceps: last eps per candidate (warm start)
+  double *cXc, *cUdc;                     // candidate positions, velocities at time t
+  int64_t *ckey;
+  double *cd2;
+  int *ckeep;
+  // markers in use (indexed 0..n_used-1)
+  int *mcount;  // [0] n_used, [1] n_segments, [2] eps CG iterations
+  int *ids;
+  double *X, *Ud, *Tw, *dA, *eps;
+  int *sidx;      // [ns][3][3] cell index per direction and slot
+  double *sw1;    // [ns][3][3] 1D kernel weights
+  int64_t *pcell; // [ns][27] support cell of each slot
+  double *pw;     // [ns][27] support weight of each slot
+  uint64_t *keys; // sorted (cell << 20 | pair id), padded to a power of two
+  int *seg;       // segment starts, [n_segments + 1]
+  int *ell_col;   // [ns][kMaxNbr]
+  double *ell_val;
+  int *ell_cnt;
+  double *ev[4];  // eps CG vectors
+  double *mk;     // [ns][2 dim + 3]: rho_L, M, E_L, F, Q
+  double *mforce; // [ns][3]
+  double *mheat;  // [ns]
+  double *totals; // [4]
+};
+
+struct Launch {
+  GridK g;
+  int prec;  // 0: FP64, 1: FP32
+  int nc_cap;     // candidate capacity
+  int npairs_pad; // power of two >= nc_cap * nslot
+  hipStream_t st;
+};
+
+// grid kernels (ibm_grid.hip)
+void run_fill(const Launch &L, double *p, int64_t n, double v);
+void run_uniform_state(const Launch &L, const Bufs &B, int cur);
+void run_init_primitive(const Launch &L, const Bufs &B, int cur, const void *rho, const void *u,
+                        const void *theta);
+void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
+void run_predictor(const Launch &L, const Bufs &B, int cur);
+void run_setup(const Launch &L, const Bufs &B, int cur, double rtol, int maxit);
+void run_cg_iteration(const Launch &L, const Bufs &B, int parity);
+void run_correct(const Launch &L, const Bufs &B, int cur);
+int64_t cell_blocks(const GridK &g);
+
+// marker kernels (ibm_markers.hip)
+void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,
+                       int dedupe);
+void run_build_markers(const Launch &L, const Bufs &B, int nc);
+void run_interp_force(const Launch &L, const Bufs &B, double *hist_row);
+void run_spread(const Launch &L, const Bufs &B);
+
+}  // namespace ibmk

@@ -1,0 +1,516 @@
+// ibm_markers.hip -- Lagrangian-marker kernels of the IBM-HT step on gfx950, all in
+// FP64: marker placement and the check routine (Sec. 3.1, Sec. 5), supports and
+// kernel weights (Sec. 2.2, Eq. (6)), a deterministic sort of the (cell, marker)
+// pairs, the Lagrangian quadrature A eps = 1 (Eqs. (8)-(9)) by CG, interpolation
+// and forcing (Eqs. (5), (10), (17)) and the spread (Eq. (7)) as a segmented
+// reduction in marker order (no floating-point atomics).
+//
+// Marker counts are read on the device (mcount), so a motion update needs no
+// host round trip: the kernels are launched for the candidate capacity and
+// threads past the live count return.
+#include "ibm_launch.h"
+
+namespace ibmk {
+
+// Pinelli et al. 3-point kernel (Sec. 2.2, Eq. (6)); r in mesh widths.
+__device__ __forceinline__ double kernel_phi(double r) {
+#pragma clang fp contract(off)
+  r = fabs(r);
+  if (r <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+  if (r <= 1.5) return (5.0 - 3.0 * r - sqrt(1.0 - 3.0 * (1.0 - r) * (1.0 - r))) / 6.0;
+  return 0.0;
+}
+
+// Exclusive block scan of ints (blockDim.x a multiple of 64, <= 1024).
+__device__ __forceinline__ int block_scan_excl(int v, int *lds, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    int t = (lane < nw) ? lds[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(t, o, 64);
+      if (lane >= o) t += y;
+    }
+    if (lane < nw) lds[lane] = t;
+  }
+  __syncthreads();
+  int off = (w > 0 ? lds[w - 1] : 0) + x - v;
+  *total = lds[nw - 1];
+  __syncthreads();
+  return off;
+}
+
+// ------------------------------------------------ placement, check routine
+// Candidate positions at the current time (Sec. 5, Eq. (19): a common offset
+// along `axis`); the containing cell and the squared distance to its centre.
+__global__ void k_place(GridK g, int nc, const double *X0, const double *U0, double *X, double *U,
+                        double off, double vel, int axis, int64_t *key, double *d2) {
+#pragma clang fp contract(off)
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  int64_t b[3] = {0, 0, 0};
+  double dd = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    double x = X0[3 * k + a], u = U0[3 * k + a];
+    if (a == axis) {
+      x += off;
+      u += vel;
+    }
+    X[3 * k + a] = x;
+    U[3 * k + a] = u;
+    if (a < g.dim) {
+      double xi = (x - g.lo[a]) / g.h[a];
+      int64_t bb = (int64_t)floor(xi);
+      double dx = x - (g.lo[a] + (double(bb) + 0.5) * g.h[a]);
+      dd += dx * dx;
+      if (g.bc[a][0] == BC_PERIODIC) bb = ((bb % g.n[a]) + g.n[a]) % g.n[a];
+      b[a] = bb;
+    }
+  }
+  key[k] = b[0] + (int64_t)g.n[0] * (b[1] + (int64_t)g.n[1] * b[2]);
+  d2[k] = dd;
+}
+
+// Sec. 3.1 check routine: a candidate is kept when no other candidate in its
+// cell is nearer to the centre (ties: the lower id wins).
+__global__ void k_dedupe(int nc, const int64_t *key, const double *d2, int *keep) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  const int64_t kk = key[k];
+  const double dk = d2[k];
+  int ok = 1;
+  for (int j = 0; j < nc; ++j) {
+    if (key[j] == kk && (d2[j] < dk || (d2[j] == dk && j < k))) {
+      ok = 0;
+      break;
+    }
+  }
+  keep[k] = ok;
+}
+
+__global__ void k_keep_all(int nc, int *keep) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nc) keep[k] = 1;
+}
+
+// Gathers the kept candidates, in increasing id, into the markers in use; eps
+// starts from the candidate's last value (warm start of the quadrature solve).
+__global__ void k_compact(int nc, const int *keep, const double *cX, const double *cU,
+                          const double *cTw, const double *cdA, const double *ceps, int *ids,
+                          double *X, double *U, double *Tw, double *dA, double *eps, int *mcount) {
+  __shared__ int lds[32];
+  int base = 0;
+  for (int start = 0; start < nc; start += blockDim.x) {
+    int k = start + threadIdx.x;
+    int v = (k < nc) ? keep[k] : 0;
+    int tot;
+    int off = block_scan_excl(v, lds, &tot);
+    if (v) {
+      int m = base + off;
+      ids[m] = k;
+      for (int a = 0; a < 3; ++a) {
+        X[3 * m + a] = cX[3 * k + a];
+        U[3 * m + a] = cU[3 * k + a];
+      }
+      Tw[m] = cTw[k];
+      dA[m] = cdA[k];
+      eps[m] = ceps[k];
+    }
+    base += tot;
+  }
+  if (threadIdx.x == 0) mcount[0] = base;
+}
+
+// ------------------------------------------------------------ supports
+// Support of marker k: the 3 cells per direction around the cell containing it,
+// weight the product of 1D kernel values at r = (x_c - X)/h; pair keys
+// (cell << 20 | k * nslot + slot) for the sort.
+__global__ void k_support(GridK g, const int *mcount, const double *X, int nslot, int *sidx,
+                          double *sw1, int64_t *pcell, double *pw, uint64_t *keys, int *flags) {
+#pragma clang fp contract(off)
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mcount[0]) return;
+  int idx[3][3];
+  double w1[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 3; ++s) {
+      idx[a][s] = 0;
+      w1[a][s] = (s == 0) ? 1.0 : 0.0;
+    }
+  for (int a = 0; a < g.dim; ++a) {
+    double xi = (X[3 * k + a] - g.lo[a]) / g.h[a];
+    int64_t b = (int64_t)floor(xi);
+    for (int s = 0; s < 3; ++s) {
+      int64_t ii = b - 1 + s;
+      w1[a][s] = kernel_phi((double(ii) + 0.5) - xi);
+      if (g.bc[a][0] == BC_PERIODIC) {
+        ii = ((ii % g.n[a]) + g.n[a]) % g.n[a];
+      } else if (ii < 0 || ii >= g.n[a]) {
+        atomicOr(flags + 1, 1);
+        ii = ii < 0 ? 0 : g.n[a] - 1;
+      }
+      idx[a][s] = (int)ii;
+    }
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 3; ++s) {
+      sidx[9 * k + 3 * a + s] = idx[a][s];
+      sw1[9 * k + 3 * a + s] = w1[a][s];
+    }
+  const int s2n = (g.dim == 3) ? 3 : 1;
+  for (int s2 = 0; s2 < s2n; ++s2)
+    for (int s1 = 0; s1 < 3; ++s1)
+      for (int s0 = 0; s0 < 3; ++s0) {
+        int s = s0 + 3 * (s1 + 3 * s2);
+        int64_t cell = idx[0][s0] + (int64_t)g.n[0] * (idx[1][s1] + (int64_t)g.n[1] * idx[2][s2]);
+        pcell[27 * k + s] = cell;
+        pw[27 * k + s] = w1[0][s0] * w1[1][s1] * w1[2][s2];
+        keys[(int64_t)nslot * k + s] = ((uint64_t)cell << kPairBits) | (uint64_t)(nslot * k + s);
+      }
+}
+
+// Bitonic sort of the pair keys in one block (npad a power of two); the keys
+// are unique, so the order is fully determined. Up to 4096 keys are sorted in LDS.
+__global__ void k_sort(uint64_t *keys, int npad, const int *mcount, int nslot) {
+  extern __shared__ uint64_t sk[];
+  const int np = mcount[0] * nslot;
+  const bool in_lds = npad <= 4096;
+  for (int i = threadIdx.x; i < npad; i += blockDim.x) {
+    uint64_t v = (i < np) ? keys[i] : ~0ull;
+    if (in_lds)
+      sk[i] = v;
+    else
+      keys[i] = v;
+  }
+  __syncthreads();
+  uint64_t *K = in_lds ? sk : keys;
+  for (unsigned size = 2; size <= (unsigned)npad; size <<= 1) {
+    for (unsigned stride = size >> 1; stride > 0; stride >>= 1) {
+      for (unsigned t = threadIdx.x; t < (unsigned)npad / 2; t += blockDim.x) {
+        unsigned i = 2 * t - (t & (stride - 1));
+        unsigned j = i + stride;
+        bool asc = (i & size) == 0;
+        uint64_t a = K[i], b = K[j];
+        if ((a > b) == asc) {
+          K[i] = b;
+          K[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (in_lds)
+    for (int i = threadIdx.x; i < npad; i += blockDim.x) keys[i] = sk[i];
+}
+
+// Segments of equal cell in the sorted pairs: seg[s] = first pair of segment s.
+__global__ void k_segments(const uint64_t *keys, int nslot, int *mcount, int *seg) {
+  __shared__ int lds[32];
+  const int np = mcount[0] * nslot;
+  int base = 0;
+  for (int start = 0; start < np; start += blockDim.x) {
+    int i = start + threadIdx.x;
+    int head = 0;
+    if (i < np) head = (i == 0) || ((keys[i] >> kPairBits) != (keys[i - 1] >> kPairBits));
+    int tot;
+    int off = block_scan_excl(head, lds, &tot);
+    if (head) seg[base + off] = i;
+    base += tot;
+  }
+  if (threadIdx.x == 0) {
+    seg[base] = np;
+    mcount[1] = base;
+  }
+}
+
+// Rows of the Gram matrix A_kl = sum_c w_ck w_cl (Eq. (9)) in ELL form, from the
+// tensor-product structure: A_kl = prod_d sum_{s,t: same cell index} phi_ks phi_lt.
+__global__ void k_gram(GridK g, const int *mcount, const int *sidx, const double *sw1, int *col,
+                       double *val, int *cnt, int *flags) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = mcount[0];
+  if (k >= n) return;
+  int c = 0;
+  for (int l = 0; l < n; ++l) {
+    double a = 1.0;
+    bool nz = true;
+    for (int d = 0; d < g.dim && nz; ++d) {
+      double s = 0.0;
+      bool any = false;
+      for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q)
+          if (sidx[9 * k + 3 * d + p] == sidx[9 * l + 3 * d + q]) {
+            s += sw1[9 * k + 3 * d + p] * sw1[9 * l + 3 * d + q];
+            any = true;
+          }
+      if (!any) nz = false;
+      a *= s;
+    }
+    if (nz) {
+      if (c < kMaxNbr) {
+        col[(int64_t)kMaxNbr * k + c] = l;
+        val[(int64_t)kMaxNbr * k + c] = a;
+      }
+      ++c;
+    }
+  }
+  if (c > kMaxNbr) atomicOr(flags + 3, 1);
+  cnt[k] = c < kMaxNbr ? c : kMaxNbr;
+}
+
+__device__ __forceinline__ double block_dot_all(double v, double *lds) {
+  double s = block_sum(v, lds);
+  __shared__ double bc;
+  if (threadIdx.x == 0) bc = s;
+  __syncthreads();
+  double r = bc;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void ell_matvec(int n, const int *col, const double *val,
+                                           const int *cnt, const double *v, double *out) {
+  for (int row = threadIdx.x; row < n; row += blockDim.x) {
+    double s = 0.0;
+    const int m = cnt[row];
+    for (int e = 0; e < m; ++e)
+      s += val[(int64_t)kMaxNbr * row + e] * v[col[(int64_t)kMaxNbr * row + e]];
+    out[row] = s;
+  }
+}
+
+// A eps = 1 by conjugate gradients in one block, warm started, restarted from the
+// true residual until |1 - A eps| <= 1e-13 |1| (a backward-stable FP64 solve).
+__global__ void k_eps_cg(int *mcount, const int *col, const double *val, const int *cnt,
+                         double *x, double *r, double *p, double *q, int *flags) {
+  __shared__ double lds[32];
+  const int n = mcount[0];
+  if (n == 0) return;
+  const double tol_true2 = 1e-26 * n, tol_in2 = 1e-30 * n;
+  int total_it = 0;
+  bool ok = false;
+  for (int restart = 0; restart < 7 && !ok; ++restart) {
+    ell_matvec(n, col, val, cnt, x, q);
+    __syncthreads();
+    double rr = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double ri = 1.0 - q[i];
+      r[i] = ri;
+      p[i] = ri;
+      rr += ri * ri;
+    }
+    rr = block_dot_all(rr, lds);
+    if (rr <= tol_true2) {
+      ok = true;
+      break;
+    }
+    if (restart == 6) break;
+    const int maxit = 4 * n + 50;
+    for (int it = 0; it < maxit; ++it) {
+      ell_matvec(n, col, val, cnt, p, q);
+      __syncthreads();
+      double pq = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) pq += p[i] * q[i];
+      pq = block_dot_all(pq, lds);
+      const double alpha = rr / pq;
+      double rn = 0.0;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        x[i] += alpha * p[i];
+        double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        rn += ri * ri;
+      }
+      rn = block_dot_all(rn, lds);
+      ++total_it;
+      if (rn <= tol_in2) break;
+      const double beta = rn / rr;
+      for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = r[i] + beta * p[i];
+      rr = rn;
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    mcount[2] = total_it;
+    if (!ok) atomicOr(flags + 2, 1);
+  }
+}
+
+__global__ void k_eps_save(const int *mcount, const int *ids, const double *eps, double *ceps) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < mcount[0]) ceps[ids[k]] = eps[k];
+}
+
+// ------------------------------------------------ interpolation and forcing
+// Eq. (5) at each marker from the predictor fields, then Eq. (10) with a_s = 1/dt
+// and Eq. (17) with a_e = 1/dt: F = (rho_L U^d - M)/dt, Q = (c_v rho_L Theta^d - E_L)/dt.
+// Per-marker force on the body -dV eps F and heat given to the fluid dV eps Q.
+template <typename S>
+__global__ void k_interp_force(GridK g, const int *mcount, const int64_t *pcell, const double *pw,
+                               int nslot, const S *rho_s, const S *ms0, const S *ms1,
+                               const S *ms2, const S *E_s, const double *Ud, const double *Tw,
+                               const double *eps, double *mk, double *mforce, double *mheat) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mcount[0]) return;
+  const S *ms[3] = {ms0, ms1, ms2};
+  const int dim = g.dim, W = 2 * dim + 3;
+  double rl = 0.0, el = 0.0, M[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < nslot; ++s) {
+    const int64_t c = pcell[27 * k + s];
+    const double w = pw[27 * k + s];
+    rl += w * double(rho_s[c]);
+    for (int q = 0; q < dim; ++q) M[q] += w * double(ms[q][c]);
+    el += w * double(E_s[c]);
+  }
+  double *o = mk + (int64_t)W * k;
+  o[0] = rl;
+  for (int q = 0; q < dim; ++q) o[1 + q] = M[q];
+  o[1 + dim] = el;
+  const double e = eps[k];
+  for (int q = 0; q < 3; ++q) {
+    double F = 0.0;
+    if (q < dim) {
+      F = (rl * Ud[3 * k + q] - M[q]) / g.dt;
+      o[2 + dim + q] = F;
+    }
+    mforce[3 * k + q] = -(g.dV * (e * F));
+  }
+  const double Q = (g.cv * rl * Tw[k] - el) / g.dt;
+  o[2 + 2 * dim] = Q;
+  mheat[k] = g.dV * (e * Q);
+}
+
+// Totals over the markers in use (fixed order); one history row if given.
+__global__ void k_totals(const int *mcount, const double *mforce, const double *mheat,
+                         double *totals, double *hist_row) {
+  __shared__ double lds[64];
+  const int n = mcount[0];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    v[0] += mforce[3 * k];
+    v[1] += mforce[3 * k + 1];
+    v[2] += mforce[3 * k + 2];
+    v[3] += mheat[k];
+  }
+  block_sum_n<4>(v, lds);
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 4; ++q) totals[q] = v[q];
+    if (hist_row)
+      for (int q = 0; q < 4; ++q) hist_row[q] = v[q];
+  }
+}
+
+// Eq. (7) as a segmented reduction: one thread per cell touched by a support,
+// summing w eps F and w eps Q over its pairs in increasing marker id, then
+// mom** = mom* + dt f and E** = E* + dt q in place.
+template <typename S>
+__global__ void k_spread(GridK g, const int *mcount, const int *seg, const uint64_t *keys,
+                         const double *pw, int nslot, const double *eps, const double *mk, S *ms0,
+                         S *ms1, S *ms2, S *E_s) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= mcount[1]) return;
+  const int dim = g.dim, W = 2 * dim + 3;
+  const int a = seg[s], b = seg[s + 1];
+  const int64_t cell = (int64_t)(keys[a] >> kPairBits);
+  const uint64_t mask = (1ull << kPairBits) - 1;
+  double acc[3] = {0.0, 0.0, 0.0}, aq = 0.0;
+  for (int i = a; i < b; ++i) {
+    const int pid = (int)(keys[i] & mask);
+    const int k = pid / nslot, slot = pid - k * nslot;
+    const double coef = pw[27 * k + slot] * eps[k];
+    const double *o = mk + (int64_t)W * k;
+    for (int q = 0; q < dim; ++q) acc[q] += coef * o[2 + dim + q];
+    aq += coef * o[2 + 2 * dim];
+  }
+  S *ms[3] = {ms0, ms1, ms2};
+  for (int q = 0; q < dim; ++q) ms[q][cell] = S(double(ms[q][cell]) + g.dt * acc[q]);
+  E_s[cell] = S(double(E_s[cell]) + g.dt * aq);
+}
+
+// ------------------------------------------------------------------ launchers
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,
+                       int dedupe) {
+  hipLaunchKernelGGL(k_place, dim3(nblk(nc, 256)), dim3(256), 0, L.st, L.g, nc,
+                     (const double *)B.cX0, (const double *)B.cUd0, B.cXc, B.cUdc, off, vel, axis,
+                     B.ckey, B.cd2);
+  if (dedupe)
+    hipLaunchKernelGGL(k_dedupe, dim3(nblk(nc, 256)), dim3(256), 0, L.st, nc,
+                       (const int64_t *)B.ckey, (const double *)B.cd2, B.ckeep);
+  else
+    hipLaunchKernelGGL(k_keep_all, dim3(nblk(nc, 256)), dim3(256), 0, L.st, nc, B.ckeep);
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(kRedThreads), 0, L.st, nc, (const int *)B.ckeep,
+                     (const double *)B.cXc, (const double *)B.cUdc, (const double *)B.cTw,
+                     (const double *)B.cdA, (const double *)B.ceps, B.ids, B.X, B.Ud, B.Tw, B.dA,
+                     B.eps, B.mcount);
+}
+
+void run_build_markers(const Launch &L, const Bufs &B, int nc) {
+  const int nslot = (L.g.dim == 3) ? 27 : 9;
+  hipLaunchKernelGGL(k_support, dim3(nblk(nc, 256)), dim3(256), 0, L.st, L.g,
+                     (const int *)B.mcount, (const double *)B.X, nslot, B.sidx, B.sw1, B.pcell,
+                     B.pw, B.keys, B.flags);
+  size_t shm = (L.npairs_pad <= 4096) ? (size_t)L.npairs_pad * sizeof(uint64_t) : 0;
+  hipLaunchKernelGGL(k_sort, dim3(1), dim3(kRedThreads), shm, L.st, B.keys, L.npairs_pad,
+                     (const int *)B.mcount, nslot);
+  hipLaunchKernelGGL(k_segments, dim3(1), dim3(kRedThreads), 0, L.st, (const uint64_t *)B.keys,
+                     nslot, B.mcount, B.seg);
+  hipLaunchKernelGGL(k_gram, dim3(nblk(nc, 64)), dim3(64), 0, L.st, L.g, (const int *)B.mcount,
+                     (const int *)B.sidx, (const double *)B.sw1, B.ell_col, B.ell_val, B.ell_cnt,
+                     B.flags);
+  hipLaunchKernelGGL(k_eps_cg, dim3(1), dim3(kRedThreads), 0, L.st, B.mcount,
+                     (const int *)B.ell_col, (const double *)B.ell_val, (const int *)B.ell_cnt,
+                     B.eps, B.ev[0], B.ev[1], B.ev[2], B.flags);
+  hipLaunchKernelGGL(k_eps_save, dim3(nblk(nc, 256)), dim3(256), 0, L.st, (const int *)B.mcount,
+                     (const int *)B.ids, (const double *)B.eps, B.ceps);
+}
+
+void run_interp_force(const Launch &L, const Bufs &B, double *hist_row) {
+  const int nslot = (L.g.dim == 3) ? 27 : 9;
+  if (L.prec == 0) {
+    hipLaunchKernelGGL(k_interp_force<double>, dim3(nblk(L.nc_cap, 128)), dim3(128), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
+                       nslot, (const double *)B.rho_s, (const double *)B.mom_s[0],
+                       (const double *)B.mom_s[1], (const double *)B.mom_s[2],
+                       (const double *)B.E_s, (const double *)B.Ud, (const double *)B.Tw,
+                       (const double *)B.eps, B.mk, B.mforce, B.mheat);
+  } else {
+    hipLaunchKernelGGL(k_interp_force<float>, dim3(nblk(L.nc_cap, 128)), dim3(128), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
+                       nslot, (const float *)B.rho_s, (const float *)B.mom_s[0],
+                       (const float *)B.mom_s[1], (const float *)B.mom_s[2],
+                       (const float *)B.E_s, (const double *)B.Ud, (const double *)B.Tw,
+                       (const double *)B.eps, B.mk, B.mforce, B.mheat);
+  }
+  hipLaunchKernelGGL(k_totals, dim3(1), dim3(kRedThreads), 0, L.st, (const int *)B.mcount,
+                     (const double *)B.mforce, (const double *)B.mheat, B.totals, hist_row);
+}
+
+void run_spread(const Launch &L, const Bufs &B) {
+  const int nslot = (L.g.dim == 3) ? 27 : 9;
+  const int64_t cap = (int64_t)L.nc_cap * nslot;
+  if (L.prec == 0) {
+    hipLaunchKernelGGL(k_spread<double>, dim3(nblk(cap, 256)), dim3(256), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int *)B.seg, (const uint64_t *)B.keys,
+                       (const double *)B.pw, nslot, (const double *)B.eps, (const double *)B.mk,
+                       (double *)B.mom_s[0], (double *)B.mom_s[1], (double *)B.mom_s[2],
+                       (double *)B.E_s);
+  } else {
+    hipLaunchKernelGGL(k_spread<float>, dim3(nblk(cap, 256)), dim3(256), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int *)B.seg, (const uint64_t *)B.keys,
+                       (const double *)B.pw, nslot, (const double *)B.eps, (const double *)B.mk,
+                       (float *)B.mom_s[0], (float *)B.mom_s[1], (float *)B.mom_s[2],
+                       (float *)B.E_s);
+  }
+}
+
+}  // namespace ibmk

@@ -200,6 +200,21 @@ ibm_status ibm_markers_in_use(const ibm_ctx *ctx, int32_t *n_used, int32_t *ids,
  * (double [n_used][2 dim + 3]). Synchronises. */
 ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
 
+/* Kernel timing for measurement. While enabled, ibm_step records HIP events on
+ * the context's stream around the launches of each kernel class and, after each
+ * step, adds their durations to per-class totals (CG launches after convergence
+ * are not counted). Classes (IBM_PROF_*): 0 predictor, 1 marker work (motion
+ * update, interpolation/forcing, spread), 2 pressure set-up, 3 CG part a
+ * (p update + matvec + p.q), 4 CG part b (x, r updates + r.r), 5 correction.
+ * enable != 0 clears the totals and starts timing; 0 stops it. */
+enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG_A = 3,
+       IBM_PROF_CG_B = 4, IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };
+ibm_status ibm_profile(ibm_ctx *ctx, int32_t enable);
+
+/* Per-class totals since timing was enabled: ms [IBM_PROF_CLASSES] (host) summed
+ * durations in milliseconds, launches [IBM_PROF_CLASSES] (host) launch counts. */
+ibm_status ibm_profile_read(const ibm_ctx *ctx, double *ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

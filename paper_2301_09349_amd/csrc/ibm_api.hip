@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ibm.h"
 #include "ibm_launch.h"
@@ -17,6 +18,54 @@ using ibmk::Bufs;
 using ibmk::CgScal;
 using ibmk::GridK;
 using ibmk::Launch;
+
+// Event-pair timing of kernel classes (measurement only).
+struct Prof {
+  bool on = false;
+  double ms[IBM_PROF_CLASSES] = {};
+  int64_t n[IBM_PROF_CLASSES] = {};
+  struct Pair {
+    int cls, it;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool, used;
+  std::vector<Pair> pending;
+  hipEvent_t get() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      return nullptr;
+    }
+    used.push_back(e);
+    return e;
+  }
+  hipEvent_t mark(hipStream_t st) {
+    hipEvent_t e = get();
+    if (e) (void)hipEventRecord(e, st);
+    return e;
+  }
+  // after a synchronisation: accumulate, dropping CG launches past `cg_iters`
+  void settle(int cg_iters) {
+    for (const Pair &p : pending) {
+      if (!p.a || !p.b) continue;
+      if ((p.cls == IBM_PROF_CG_A || p.cls == IBM_PROF_CG_B) && p.it >= cg_iters) continue;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+        ms[p.cls] += t;
+        n[p.cls] += 1;
+      }
+    }
+    pending.clear();
+    pool.insert(pool.end(), used.begin(), used.end());
+    used.clear();
+  }
+  ~Prof() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : used) (void)hipEventDestroy(e);
+  }
+};
 
 struct ibm_ctx {
   ibm_grid_desc desc;
@@ -32,6 +81,7 @@ struct ibm_ctx {
   int tape_cap = 0;
   std::string err;
   CgScal cgh;
+  Prof prof;
 };
 
 namespace {
@@ -148,7 +198,7 @@ GridK make_grid(const ibm_grid_desc &d) {
     g.tiles[2] = (g.n[2] + 1) / 2;
   }
   g.ntiles = (int64_t)g.tiles[0] * g.tiles[1] * g.tiles[2];
-  g.nblocks = ((g.ntiles + 7) / 8) * 8;
+  g.nblocks = std::min<int64_t>(((g.ntiles + 7) / 8) * 8, ibmk::kMaxBlocks);
   return g;
 }
 
@@ -201,7 +251,7 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   B.p[0] = C.take<double>(N);
   B.p[1] = C.take<double>(N);
   B.q = C.take<double>(N);
-  B.partials = C.take<double>(4 * (size_t)g.nblocks + 64);
+  B.partials = C.take<double>((size_t)ibmk::PART_REGIONS * ibmk::kMaxBlocks);
   B.cg = C.take<CgScal>(1);
   B.scal = C.take<double>(8);
   B.flags = C.take<int>(8);
@@ -513,27 +563,54 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   int64_t done = 0;
   int total_it = 0, last_it = 0;
   double res = 0.0;
+  Prof &P = ctx->prof;
+  auto timed = [&](int cls, int it, auto &&launch) {
+    if (!P.on) {
+      launch();
+      return;
+    }
+    hipEvent_t a = P.mark(st);
+    launch();
+    hipEvent_t b = P.mark(st);
+    P.pending.push_back({cls, it, a, b});
+  };
   for (int s = 0; s < n_steps; ++s) {
     HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
     if (ctx->nc > 0 && ctx->motion_axis >= 0) {
-      ibm_status ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt);
+      ibm_status ms = IBM_OK;
+      timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
       if (ms) return ms;
     }
-    ibmk::run_predictor(L, B, ctx->cur);
+    timed(IBM_PROF_PREDICTOR, 0, [&] { ibmk::run_predictor(L, B, ctx->cur); });
     double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
     if (ctx->nc > 0) {
-      ibmk::run_interp_force(L, B, hrow);
-      ibmk::run_spread(L, B);
+      timed(IBM_PROF_MARKERS, 0, [&] {
+        ibmk::run_interp_force(L, B, hrow);
+        ibmk::run_spread(L, B);
+      });
     } else if (hrow) {
       HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
     }
-    ibmk::run_setup(L, B, ctx->cur, ctx->desc.cg_rtol, ctx->desc.cg_maxit);
+    timed(IBM_PROF_SETUP, 0,
+          [&] { ibmk::run_setup(L, B, ctx->cur, ctx->desc.cg_rtol, ctx->desc.cg_maxit); });
     HIPCHECK(ctx, hipGetLastError());
-    int launched = 0, parity = 0, chunk = std::max(1, ctx->cg_hint);
+    // Iteration `it` tests convergence after `it` updates at its start, so a solve
+    // of n iterations needs n + 1 launches of part a; launches past convergence
+    // return at once. The chunk follows the last step's count.
+    int launched = 0, chunk = std::max(1, ctx->cg_hint + 1);
     for (;;) {
       for (int c = 0; c < chunk; ++c) {
-        ibmk::run_cg_iteration(L, B, parity);
-        parity ^= 1;
+        if (P.on) {
+          hipEvent_t e0 = P.mark(st);
+          ibmk::run_cg_half(L, B, launched, 0);
+          hipEvent_t e1 = P.mark(st);
+          ibmk::run_cg_half(L, B, launched, 1);
+          hipEvent_t e2 = P.mark(st);
+          P.pending.push_back({IBM_PROF_CG_A, launched, e0, e1});
+          P.pending.push_back({IBM_PROF_CG_B, launched, e1, e2});
+        } else {
+          ibmk::run_cg_iteration(L, B, launched);
+        }
         ++launched;
       }
       HIPCHECK(ctx, hipGetLastError());
@@ -543,11 +620,12 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       if (launched > ctx->desc.cg_maxit + 4) break;
       chunk = 2;
     }
-    ibmk::run_correct(L, B, ctx->cur);
+    timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur); });
     HIPCHECK(ctx, hipGetLastError());
     int f[8];
     ibm_status r = sync_read(ctx, f, B.flags, sizeof(f));
     if (r) return r;
+    if (P.on) P.settle(ctx->cgh.iters);
     if (f[1] || f[2] || f[3]) {
       rc = marker_flags(ctx, f);
       break;
@@ -675,6 +753,29 @@ ibm_status ibm_get_field(const ibm_ctx *cctx, int32_t which, void *dst) {
       return fail(ctx, IBM_E_ARG, "get_field: unknown field");
   }
   HIPCHECK(ctx, hipStreamSynchronize(st));
+  return IBM_OK;
+}
+
+ibm_status ibm_profile(ibm_ctx *ctx, int32_t enable) {
+  if (!ctx) return IBM_E_ARG;
+  HIPCHECK(ctx, hipStreamSynchronize(ctx->L.st));
+  ctx->prof.settle(0);
+  ctx->prof.on = enable != 0;
+  if (enable) {
+    for (int c = 0; c < IBM_PROF_CLASSES; ++c) {
+      ctx->prof.ms[c] = 0.0;
+      ctx->prof.n[c] = 0;
+    }
+  }
+  return IBM_OK;
+}
+
+ibm_status ibm_profile_read(const ibm_ctx *ctx, double *ms, int64_t *launches) {
+  if (!ctx) return IBM_E_ARG;
+  for (int c = 0; c < IBM_PROF_CLASSES; ++c) {
+    if (ms) ms[c] = ctx->prof.ms[c];
+    if (launches) launches[c] = ctx->prof.n[c];
+  }
   return IBM_OK;
 }
 

@@ -145,13 +145,12 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
   fe = F * ce - lamf * (thQ - thP) * ih;
 }
 
+
 // ----------------------------------------------------- Appendix A, step 1
 // Predictor (f = q = 0): explicit update of mass, momentum and internal energy.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S *rho_s, S *ms0,
-                                                        S *ms1, S *ms2, S *E_s) {
-  int i, j, k;
-  if (!cell_of_thread<DIM>(g, i, j, k)) return;
+__device__ __forceinline__ void predictor_cell(const GridK &g, const StateV<S> &st, int i, int j,
+                                               int k, S *rho_s, S *const *ms, S *E_s) {
   const int64_t c = cidx(g, i, j, k);
   S divF = S(0), divU = S(0), divE = S(0), divM[3] = {S(0), S(0), S(0)};
 #pragma unroll
@@ -199,10 +198,21 @@ __global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S
   const S dt = S(g.dt);
   const S pc = S(g.gm1) * E;
   rho_s[c] = rho - dt * divF;
-  S *ms[3] = {ms0, ms1, ms2};
 #pragma unroll
   for (int q = 0; q < DIM; ++q) ms[q][c] = st.mom[q][c] - dt * divM[q] - dt * gp[q];
   E_s[c] = E - dt * divE - dt * pc * divU + dt * phi;
+}
+
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S *rho_s, S *ms0,
+                                                        S *ms1, S *ms2, S *E_s) {
+  S *ms[3] = {ms0, ms1, ms2};
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (cell_in_tile<DIM>(g, t, i, j, k)) predictor_cell<DIM>(g, st, i, j, k, rho_s, ms, E_s);
+  }
 }
 
 // ------------------------------------------------------- initialisation
@@ -275,26 +285,30 @@ __global__ __launch_bounds__(kThreads) void k_setup1(GridK g, StateV<S> st, cons
                                                      const S *ms0, const S *ms1, const S *ms2,
                                                      const S *E_s, S *mh0, S *mh1, S *mh2, S *psi,
                                                      double *x) {
-  int i, j, k;
-  if (!cell_of_thread<DIM>(g, i, j, k)) return;
-  const int64_t c = cidx(g, i, j, k);
   const S *ms[3] = {ms0, ms1, ms2};
   S *mh[3] = {mh0, mh1, mh2};
   const S gm1 = S(g.gm1);
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
 #pragma unroll
-  for (int q = 0; q < DIM; ++q) {
-    int a1[3] = {i, j, k}, a0[3] = {i, j, k};
-    a1[q] += 1;
-    a0[q] -= 1;
-    Resolved r1 = resolve<DIM>(g, a1[0], a1[1], a1[2]);
-    Resolved r0 = resolve<DIM>(g, a0[0], a0[1], a0[2]);
-    S p1 = ghosted<DIM>(g, r1, V_P, gm1 * st.E[r1.c]);
-    S p0 = ghosted<DIM>(g, r0, V_P, gm1 * st.E[r0.c]);
-    mh[q][c] = ms[q][c] + S(g.dt) * ((p1 - p0) * S(0.5 * g.ih[q]));
+    for (int q = 0; q < DIM; ++q) {
+      int a1[3] = {i, j, k}, a0[3] = {i, j, k};
+      a1[q] += 1;
+      a0[q] -= 1;
+      Resolved r1 = resolve<DIM>(g, a1[0], a1[1], a1[2]);
+      Resolved r0 = resolve<DIM>(g, a0[0], a0[1], a0[2]);
+      S p1 = ghosted<DIM>(g, r1, V_P, gm1 * st.E[r1.c]);
+      S p0 = ghosted<DIM>(g, r0, V_P, gm1 * st.E[r0.c]);
+      mh[q][c] = ms[q][c] + S(g.dt) * ((p1 - p0) * S(0.5 * g.ih[q]));
+    }
+    const S theta = E_s[c] / (rho_s[c] * S(g.cv));
+    psi[c] = S(1) / (S(g.R) * theta);
+    x[c] = double(gm1 * st.E[c]);
   }
-  const S theta = E_s[c] / (rho_s[c] * S(g.cv));
-  psi[c] = S(1) / (S(g.R) * theta);
-  x[c] = double(gm1 * st.E[c]);
 }
 
 // Homogeneous pressure operator at one cell: psi v - dt^2 div(grad_f v), zero
@@ -328,7 +342,7 @@ __device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, in
 
 // Pressure set-up, part 2, fused with the CG start: predicted face flux
 // F^ = lin_f(m^) (boundary rules), b = rho^n - dt D(F^) + outflow terms,
-// r = b - A x, p = r; FP64 partial sums of b.b and r.r.
+// r = b - A x, p = r; per-block FP64 partial sums of b.b and r.r.
 template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, const S *mh0,
                                                      const S *mh1, const S *mh2, S *Fh0, S *Fh1,
@@ -336,13 +350,15 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
                                                      double *b, double *r, double *p,
                                                      double *partials, CgScal *cs) {
   __shared__ double lds[32];
-  int i, j, k;
-  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  const S *mh[3] = {mh0, mh1, mh2};
+  S *Fh[3] = {Fh0, Fh1, Fh2};
   double sums[2] = {0.0, 0.0};
-  if (valid) {
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
-    const S *mh[3] = {mh0, mh1, mh2};
-    S *Fh[3] = {Fh0, Fh1, Fh2};
     const int ix[3] = {i, j, k};
     double div = 0.0, aff = 0.0;
 #pragma unroll
@@ -367,100 +383,90 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
     b[c] = bc_;
     r[c] = rc;
     p[c] = rc;
-    sums[0] = bc_ * bc_;
-    sums[1] = rc * rc;
+    sums[0] += bc_ * bc_;
+    sums[1] += rc * rc;
   }
   block_sum_n<2>(sums, lds);
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = sums[0];
-    partials[2 * blockIdx.x + 1] = sums[1];
-  }
-  if (arrive_last(&cs->counter_c, gridDim.x)) {
-    double v[2] = {0.0, 0.0};
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
-      v[0] += load_coherent(partials + 2 * q);
-      v[1] += load_coherent(partials + 2 * q + 1);
-    }
-    block_sum_n<2>(v, lds);
-    if (threadIdx.x == 0) {
-      cs->bb = v[0];
-      cs->rr = v[1];
-      cs->res = v[0] > 0.0 ? sqrt(v[1] / v[0]) : 0.0;
-      cs->done = (v[1] <= cs->tol2 * v[0]) ? 1 : 0;
+    partials[PART_BB * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[PART_RR * kMaxBlocks + blockIdx.x] = sums[1];
+    if (blockIdx.x == 0) {
+      cs->done = 0;
       cs->iters = 0;
-      cs->beta = 0.0;
-      cs->counter_c = 0;
     }
   }
 }
 
-// CG part a: p = r + beta p_old (on the fly at the neighbours), q = A p,
-// partial p.q; the last block forms alpha = r.r / p.q.
+// CG iteration `it`, part a. Every block forms r.r (after `it` updates) from the
+// partials of the previous kernel; converged (|r| <= rtol |b|) or out of
+// iterations -> all blocks stop and block 0 records it. Otherwise
+// beta = rr_it / rr_{it-1} (0 at it = 0), p = r + beta p_old (also at the
+// neighbours, on the fly), q = A p, partial p.q.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_cg_a(GridK g, const S *psi, const double *r,
+__global__ __launch_bounds__(kThreads) void k_cg_a(GridK g, int it, const S *psi, const double *r,
                                                    const double *pold, double *pnew, double *q,
                                                    double *partials, CgScal *cs) {
   __shared__ double lds[32];
   if (cs->done) return;
-  const double beta = cs->beta;
-  int i, j, k;
-  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  const int nb = gridDim.x;
+  const double rr = sum_partials(partials + PART_RR * kMaxBlocks, nb, lds);
+  const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
+  const double tol2 = cs->tol2;
+  const bool conv = rr <= tol2 * bb;
+  const bool out = !conv && it >= cs->maxit;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (it == 0) cs->bb = bb;
+    cs->rr[it & 1] = rr;
+    cs->res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    if (conv || out) {
+      cs->done = conv ? 1 : 2;
+      cs->iters = it;
+    }
+  }
+  if (conv || out) return;
+  const double beta = (it == 0) ? 0.0 : rr / cs->rr[(it - 1) & 1];
+  auto pv = [&](int64_t m) { return r[m] + beta * pold[m]; };
   double pq = 0.0;
-  if (valid) {
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
-    auto pv = [&](int64_t m) { return r[m] + beta * pold[m]; };
     const double pc = pv(c);
     const double qc = helm_at<DIM>(g, psi, pv, i, j, k, c, pc);
     pnew[c] = pc;
     q[c] = qc;
-    pq = pc * qc;
+    pq += pc * qc;
   }
   double s = block_sum(pq, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (arrive_last(&cs->counter_a, gridDim.x)) {
-    double tot = sum_partials(partials, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-      cs->alpha = cs->rr / tot;
-      cs->counter_a = 0;
-    }
-  }
+  if (threadIdx.x == 0) partials[PART_PQ * kMaxBlocks + blockIdx.x] = s;
 }
 
-// CG part b: x += alpha p, r -= alpha q, partial r.r; the last block tests
-// convergence (|r| <= rtol |b|) and forms beta.
+// CG iteration `it`, part b: alpha = rr_it / p.q; x += alpha p, r -= alpha q,
+// partial r.r.
 template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_cg_b(GridK g, double *x, double *r, const double *p,
-                                                   const double *q, double *partials, CgScal *cs) {
+__global__ __launch_bounds__(kThreads) void k_cg_b(GridK g, int it, double *x, double *r,
+                                                   const double *p, const double *q,
+                                                   double *partials, CgScal *cs) {
   __shared__ double lds[32];
   if (cs->done) return;
-  const double alpha = cs->alpha;
-  int i, j, k;
-  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  const double pq = sum_partials(partials + PART_PQ * kMaxBlocks, gridDim.x, lds);
+  const double alpha = cs->rr[it & 1] / pq;
   double rr = 0.0;
-  if (valid) {
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
     x[c] += alpha * p[c];
     const double rc = r[c] - alpha * q[c];
     r[c] = rc;
-    rr = rc * rc;
+    rr += rc * rc;
   }
   double s = block_sum(rr, lds);
-  if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = s;
-  if (arrive_last(&cs->counter_b, gridDim.x)) {
-    double rn = sum_partials(partials + gridDim.x, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-      cs->iters += 1;
-      cs->res = cs->bb > 0.0 ? sqrt(rn / cs->bb) : 0.0;
-      if (rn <= cs->tol2 * cs->bb) {
-        cs->done = 1;
-      } else {
-        cs->beta = rn / cs->rr;
-        cs->rr = rn;
-        if (cs->iters >= cs->maxit) cs->done = 2;
-      }
-      cs->counter_b = 0;
-    }
-  }
+  if (threadIdx.x == 0) partials[PART_RR * kMaxBlocks + blockIdx.x] = s;
 }
 
 // Pressure with its ghost rule (zero gradient at inflow and slip, p_inf on
@@ -473,27 +479,28 @@ __device__ __forceinline__ double pres_at(const GridK &g, const double *x, int i
 
 // Correction: F^{n+1} = F^ - dt grad_f p; rho^{n+1} = rho^n - dt D(F^{n+1});
 // m^{n+1} = m^ - dt G_c p; E^{n+1} = rho^{n+1} c_v theta**. Writes the other
-// state copy; flags non-finite results; FP64 partial sums of the mass.
+// state copy; flags non-finite results; per-block partial sums of the mass.
 template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, StateV<S> nxt,
                                                       const S *rho_s, const S *E_s, const S *mh0,
                                                       const S *mh1, const S *mh2, const S *Fh0,
                                                       const S *Fh1, const S *Fh2, const double *x,
-                                                      double *partials, CgScal *cs, double *mass,
-                                                      int *flags) {
+                                                      double *partials, int *flags) {
   __shared__ double lds[32];
-  int i, j, k;
-  const bool valid = cell_of_thread<DIM>(g, i, j, k);
+  const S *mh[3] = {mh0, mh1, mh2};
+  const S *Fh[3] = {Fh0, Fh1, Fh2};
+  const double dt = g.dt;
   double m = 0.0;
-  if (valid) {
+  bool bad = false;
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
-    const S *mh[3] = {mh0, mh1, mh2};
-    const S *Fh[3] = {Fh0, Fh1, Fh2};
     const int ix[3] = {i, j, k};
-    const double dt = g.dt;
     const double xc = pres_at<DIM>(g, x, i, j, k);
     double div = 0.0;
-    bool bad = false;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       int lo[3] = {i, j, k}, hi[3] = {i, j, k};
@@ -517,18 +524,18 @@ __global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, St
     nxt.rho[c] = S(rn);
     nxt.E[c] = S(En);
     bad = bad || !(rn > 0.0) || !(theta > 0.0) || !isfinite(rn) || !isfinite(En);
-    if (bad) atomicOr(flags, 1);
-    m = rn * g.dV;
+    m += rn * g.dV;
   }
+  if (bad) atomicOr(flags, 1);
   double s = block_sum(m, lds);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-  if (arrive_last(&cs->counter_a, gridDim.x)) {
-    double tot = sum_partials(partials, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-      *mass = tot;
-      cs->counter_a = 0;
-    }
-  }
+  if (threadIdx.x == 0) partials[PART_MASS * kMaxBlocks + blockIdx.x] = s;
+}
+
+// One block: the sum of per-block partials into a scalar.
+__global__ void k_reduce(const double *partials, int n, double *out) {
+  __shared__ double lds[32];
+  double s = sum_partials(partials, n, lds);
+  if (threadIdx.x == 0) *out = s;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -603,9 +610,9 @@ void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur) {
 
 void run_predictor(const Launch &L, const Bufs &B, int cur) {
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_predictor<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
-                       L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0], (S *)B.mom_s[1],
-                       (S *)B.mom_s[2], (S *)B.E_s);
+    hipLaunchKernelGGL((k_predictor<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
+                       L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
+                       (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
   });
 }
 
@@ -624,26 +631,38 @@ void run_setup(const Launch &L, const Bufs &B, int cur, double rtol, int maxit) 
   });
 }
 
-void run_cg_iteration(const Launch &L, const Bufs &B, int parity) {
+void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
   IBM_DISPATCH(L, {
+    const int parity = it & 1;
     double *pold = B.p[parity], *pnew = B.p[parity ^ 1];
-    hipLaunchKernelGGL((k_cg_a<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
-                       (const S *)B.psi, (const double *)B.r, (const double *)pold, pnew, B.q,
-                       B.partials, B.cg);
-    hipLaunchKernelGGL((k_cg_b<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
-                       B.x, B.r, (const double *)pnew, (const double *)B.q, B.partials, B.cg);
+    if (part == 0)
+      hipLaunchKernelGGL((k_cg_a<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                         L.g, it, (const S *)B.psi, (const double *)B.r, (const double *)pold,
+                         pnew, B.q, B.partials, B.cg);
+    else
+      hipLaunchKernelGGL((k_cg_b<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                         L.g, it, B.x, B.r, (const double *)pnew, (const double *)B.q, B.partials,
+                         B.cg);
   });
+}
+
+void run_cg_iteration(const Launch &L, const Bufs &B, int it) {
+  run_cg_half(L, B, it, 0);
+  run_cg_half(L, B, it, 1);
 }
 
 void run_correct(const Launch &L, const Bufs &B, int cur) {
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_correct<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
-                       L.g, state_of<S>(B, cur), state_of<S>(B, cur ^ 1), (const S *)B.rho_s,
-                       (const S *)B.E_s, (const S *)B.mhat[0], (const S *)B.mhat[1],
-                       (const S *)B.mhat[2], (const S *)B.Fhat[0], (const S *)B.Fhat[1],
-                       (const S *)B.Fhat[2], (const double *)B.x, B.partials, B.cg, B.scal,
-                       B.flags);
+    hipLaunchKernelGGL((k_correct<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
+                       L.st, L.g, state_of<S>(B, cur), state_of<S>(B, cur ^ 1),
+                       (const S *)B.rho_s, (const S *)B.E_s, (const S *)B.mhat[0],
+                       (const S *)B.mhat[1], (const S *)B.mhat[2], (const S *)B.Fhat[0],
+                       (const S *)B.Fhat[1], (const S *)B.Fhat[2], (const double *)B.x,
+                       B.partials, B.flags);
   });
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, L.st,
+                     (const double *)B.partials + PART_MASS * kMaxBlocks, (int)L.g.nblocks,
+                     B.scal);
 }
 
 }  // namespace ibmk

@@ -16,6 +16,7 @@ constexpr int MU_SUTHERLAND = 0, MU_CONSTANT = 1;
 constexpr int V_RHO = 0, V_U0 = 1, V_TH = 4, V_P = 5, V_PHOM = 7;
 
 constexpr int kThreads = 256;      // threads per block of the grid kernels
+constexpr int kMaxBlocks = 1024;   // blocks of a grid kernel (4 per CU on 256 CUs)
 constexpr int kRedThreads = 1024;  // threads of the single-block marker kernels
 constexpr int kPairBits = 20;      // (cell << 20) | pair id in the sorted pair keys
 constexpr int kMaxNbr = 192;       // neighbours per marker row of the Gram matrix
@@ -34,7 +35,7 @@ struct GridK {
   double U_inf[3];
   int tiles[3];       // tiles per direction of the cell kernels
   int64_t ntiles;     // tiles in all
-  int64_t nblocks;    // blocks launched: ntiles rounded up to a multiple of 8
+  int64_t nblocks;    // blocks of a cell kernel: a multiple of 8, at most kMaxBlocks
 };
 
 template <typename S>
@@ -45,12 +46,16 @@ struct StateV {
   S *F[3];
 };
 
-// Scalars of one pressure solve, in device memory.
+// Scalars of one pressure solve, in device memory. rr[i & 1] holds r.r after
+// i CG updates (two slots, so that the kernel of iteration i reads the value of
+// iteration i-1 while writing its own).
 struct CgScal {
-  double bb, rr, tol2, alpha, beta, res;
-  int iters, done, maxit, nonfinite;
-  unsigned counter_a, counter_b, counter_c, pad;
+  double bb, tol2, rr[2], res;
+  int iters, done, maxit, pad;
 };
+
+// Per-block partial sums of the cell kernels, each region kMaxBlocks long.
+enum { PART_PQ = 0, PART_RR = 1, PART_BB = 2, PART_MASS = 3, PART_REGIONS = 4 };
 
 __device__ __forceinline__ int64_t cidx(const GridK &g, int i, int j, int k) {
   return i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k);
@@ -59,17 +64,23 @@ __device__ __forceinline__ int64_t fidx(const GridK &g, int d, int i, int j, int
   return i + (int64_t)g.fn[d][0] * (j + (int64_t)g.fn[d][1] * k);
 }
 
-// Cell coordinates of a thread of a cell kernel. Tiles of kThreads cells
-// (64 x 4 in 2D, 64 x 2 x 2 in 3D); consecutive tiles are handed to one XCD so
-// that neighbouring tiles share an L2 (blocks are dealt round-robin to the 8 XCDs).
-// The grid is launched with 8 * ceil(ntiles / 8) blocks; block b runs on XCD b % 8
-// and takes tile (b % 8) * (gridDim / 8) + b / 8; tiles past ntiles are idle.
+// Tiles of kThreads cells (64 x 4 in 2D, 64 x 2 x 2 in 3D), x fastest. A cell
+// kernel runs gridDim.x (a multiple of 8) blocks; block b runs on XCD b % 8 (blocks
+// are dealt round-robin to the 8 XCDs), so it is given the logical rank
+// (b % 8) * (gridDim / 8) + b / 8 and a contiguous range of tiles: the blocks of
+// one XCD sweep one contiguous slab of the grid and share their halos in its L2.
+__device__ __forceinline__ void block_tiles(const GridK &g, int64_t &t0, int64_t &t1) {
+  const int64_t nb = gridDim.x;
+  const int64_t b = blockIdx.x;
+  const int64_t rank = (b & 7) * (nb >> 3) + (b >> 3);
+  const int64_t per = (g.ntiles + nb - 1) / nb;
+  t0 = rank * per;
+  t1 = t0 + per < g.ntiles ? t0 + per : g.ntiles;
+}
+
+// Cell coordinates of this thread in tile t; false outside the grid.
 template <int DIM>
-__device__ __forceinline__ bool cell_of_thread(const GridK &g, int &i, int &j, int &k) {
-  int64_t b = blockIdx.x;
-  int64_t per = gridDim.x >> 3;
-  int64_t t = (b & 7) * per + (b >> 3);
-  if (t >= g.ntiles) return false;
+__device__ __forceinline__ bool cell_in_tile(const GridK &g, int64_t t, int &i, int &j, int &k) {
   int tx = (int)(t % g.tiles[0]);
   int64_t r = t / g.tiles[0];
   int ty = (int)(r % g.tiles[1]);
@@ -201,31 +212,19 @@ __device__ __forceinline__ void block_sum_n(double *v, double *lds /* >= 16*NV *
   }
 }
 
-// True in every thread of the last block of the grid to arrive; the partials
-// written by all blocks before the call are then visible to it. The counter is
-// reset by the caller's last block when done.
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblocks) {
-  __shared__ int am_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (prev == nblocks - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (am_last) __threadfence();
-  return am_last != 0;
-}
-
-__device__ __forceinline__ double load_coherent(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum of partials[0..n) in a fixed order by one block (all threads call).
+// Sum of partials[0..n), written by an earlier kernel, in a fixed order; every
+// thread of the block gets the result. Blocks of a consumer kernel each form the
+// same sum, so no block of a kernel ever waits for another.
 __device__ __forceinline__ double sum_partials(const double *partials, int n, double *lds) {
+  __shared__ double bcast;
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += load_coherent(partials + i);
-  return block_sum(v, lds);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += partials[i];
+  double s = block_sum(v, lds);
+  if (threadIdx.x == 0) bcast = s;
+  __syncthreads();
+  s = bcast;
+  __syncthreads();
+  return s;
 }
 
 }  // namespace ibmk

@@ -65,6 +65,7 @@ void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
 void run_predictor(const Launch &L, const Bufs &B, int cur);
 void run_setup(const Launch &L, const Bufs &B, int cur, double rtol, int maxit);
 void run_cg_iteration(const Launch &L, const Bufs &B, int parity);
+void run_cg_half(const Launch &L, const Bufs &B, int parity, int part);  // part 0: a, 1: b
 void run_correct(const Launch &L, const Bufs &B, int cur);
 int64_t cell_blocks(const GridK &g);
 

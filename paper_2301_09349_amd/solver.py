@@ -203,6 +203,16 @@ class IBMSolver:
         self.stream.synchronize()
         return force[:nu], heat[:nu], np.array(tot[:])
 
+    def profile(self, enable: bool):
+        L.check(self.lib.ibm_profile(self.ctx, 1 if enable else 0), self.ctx, "ibm_profile")
+
+    def profile_read(self):
+        """{class: (total ms, launches)} of the kernel classes timed since enabling."""
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_int64 * 8)()
+        L.check(self.lib.ibm_profile_read(self.ctx, ms, n), self.ctx, "ibm_profile_read")
+        return {name: (ms[i], n[i]) for i, name in enumerate(L.PROF_CLASSES)}
+
     def field(self, name: str):
         idx = {"rho_s": 0, "mom_ss": 1, "E_ss": 2, "psi": 3, "rhs": 4, "pres": 5, "markers": 6}[name]
         if name == "markers":

@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -27,9 +29,11 @@ struct Prof {
   struct Pair {
     int cls, it;
     hipEvent_t a, b;
+    bool drop = false;
   };
   std::vector<hipEvent_t> pool, used;
   std::vector<Pair> pending;
+  size_t step_first = 0;  // first pending pair of the current step
   hipEvent_t get() {
     hipEvent_t e = nullptr;
     if (!pool.empty()) {
@@ -46,11 +50,18 @@ struct Prof {
     if (e) (void)hipEventRecord(e, st);
     return e;
   }
-  // after a synchronisation: accumulate, dropping CG launches past `cg_iters`
-  void settle(int cg_iters) {
+  // CG launches of the current step past its solve (they return at once) are not
+  // counted
+  void drop_cg_after(int cg_iters) {
+    for (size_t i = step_first; i < pending.size(); ++i) {
+      Pair &p = pending[i];
+      if ((p.cls == IBM_PROF_CG_A || p.cls == IBM_PROF_CG_B) && p.it >= cg_iters) p.drop = true;
+    }
+  }
+  // after a synchronisation: accumulate the recorded durations
+  void settle() {
     for (const Pair &p : pending) {
-      if (!p.a || !p.b) continue;
-      if ((p.cls == IBM_PROF_CG_A || p.cls == IBM_PROF_CG_B) && p.it >= cg_iters) continue;
+      if (!p.a || !p.b || p.drop) continue;
       float t = 0.f;
       if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
         ms[p.cls] += t;
@@ -79,9 +90,13 @@ struct ibm_ctx {
   double motion_amp = 0.0, motion_freq = 0.0;
   int cg_hint = 8;
   int tape_cap = 0;
+  int tag = 0;  // step tag, one per step launched
   std::string err;
   CgScal cgh;
   Prof prof;
+  ~ibm_ctx() {
+    if (B.progress) (void)hipHostFree(B.progress);
+  }
 };
 
 namespace {
@@ -313,6 +328,50 @@ ibm_status rebuild_markers(ibm_ctx *ctx, double t) {
   return IBM_OK;
 }
 
+// Waits until the CG of step `tag` has posted a finished solve or its test at
+// iteration `target` (see pack_progress). The host spins on the progress word in
+// pinned memory; if the stream drains without it, or after a long stall, it
+// stops with an error instead of waiting for ever. Without pinned memory the
+// stream is synchronised and the scalars are read back.
+ibm_status wait_progress(ibm_ctx *ctx, int tag, int target, uint64_t *out) {
+  hipStream_t st = ctx->L.st;
+  if (!ctx->B.progress) {
+    HIPCHECK(ctx, hipStreamSynchronize(st));
+    CgScal c;
+    HIPCHECK(ctx, hipMemcpy(&c, ctx->B.cg, sizeof(c), hipMemcpyDeviceToHost));
+    int f[8];
+    HIPCHECK(ctx, hipMemcpy(f, ctx->B.flags, sizeof(f), hipMemcpyDeviceToHost));
+    const int err = (f[0] ? 1 : 0) | (f[1] ? 2 : 0) | (f[2] ? 4 : 0) | (f[3] ? 8 : 0);
+    *out = ibmk::pack_progress(c.step_tag, c.iters, err, c.done);
+    return IBM_OK;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t spin = 1;; ++spin) {
+    const uint64_t w = __atomic_load_n(ctx->B.progress, __ATOMIC_ACQUIRE);
+    if ((int)(uint32_t)(w >> 32) == tag) {
+      const int it = (int)((w >> 8) & 0xFFFFFF);
+      if ((w & 0xF) != 0 || it >= target) {
+        *out = w;
+        return IBM_OK;
+      }
+    }
+    if ((spin & 4095) == 0) {
+      hipError_t q = hipStreamQuery(st);
+      if (q == hipSuccess) {
+        const uint64_t w2 = __atomic_load_n(ctx->B.progress, __ATOMIC_ACQUIRE);
+        if (w2 != w) continue;
+        return fail(ctx, IBM_E_HIP, "pressure CG finished without reporting its progress");
+      }
+      if (q != hipErrorNotReady) {
+        ctx->err = std::string("stream error while waiting for the CG: ") + hipGetErrorString(q);
+        return IBM_E_HIP;
+      }
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120))
+        return fail(ctx, IBM_E_HIP, "no CG progress for 120 s");
+    }
+  }
+}
+
 ibm_status marker_flags(ibm_ctx *ctx, const int *f) {
   if (f[1]) return fail(ctx, IBM_E_ARG, "a marker support leaves the (non-periodic) box");
   if (f[3]) return fail(ctx, IBM_E_SIZE, "too many overlapping markers for one Gram row");
@@ -349,12 +408,35 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   ctx->L.prec = desc->precision;
   ctx->L.nc_cap = std::max(desc->max_markers, 1);
   ctx->L.st = (hipStream_t)hip_stream;
+  {
+    // LDS-tiled predictor when its tile fits the device's LDS per workgroup;
+    // IBM_PREDICTOR=plain selects the per-cell variant (for comparisons).
+    int dev = 0, maxsh = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t need = ibmk::predictor_lds_bytes(desc->dim, desc->precision);
+    const char *env = std::getenv("IBM_PREDICTOR");
+    ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
+    if (ctx->L.pred_lds && need > 65536) ibmk::enable_predictor_lds(desc->dim, desc->precision);
+  }
   ctx->tape_cap = tape_steps;
   size_t need = plan(*desc, ctx->L.g, desc->max_markers, tape_steps, (char *)dev_workspace, ctx->B,
                      ctx->L.npairs_pad);
   if (bytes < need) {
     delete ctx;
     return IBM_E_SIZE;
+  }
+  // one word of pinned, coherent host memory through which the CG reports its
+  // progress (without it the step loop synchronises instead)
+  {
+    void *hp = nullptr;
+    if (hipHostMalloc(&hp, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess && hp) {
+      ctx->B.progress = static_cast<uint64_t *>(hp);
+      *ctx->B.progress = 0;
+    } else {
+      (void)hipGetLastError();
+      ctx->B.progress = nullptr;
+    }
   }
   CgScal c0;
   std::memset(&c0, 0, sizeof(c0));
@@ -562,7 +644,6 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   ibm_status rc = IBM_OK;
   int64_t done = 0;
   int total_it = 0, last_it = 0;
-  double res = 0.0;
   Prof &P = ctx->prof;
   auto timed = [&](int cls, int it, auto &&launch) {
     if (!P.on) {
@@ -574,8 +655,28 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     hipEvent_t b = P.mark(st);
     P.pending.push_back({cls, it, a, b});
   };
+  auto cg_iteration = [&](int it) {
+    if (P.on) {
+      hipEvent_t e0 = P.mark(st);
+      ibmk::run_cg_half(L, B, it, 0);
+      hipEvent_t e1 = P.mark(st);
+      ibmk::run_cg_half(L, B, it, 1);
+      hipEvent_t e2 = P.mark(st);
+      P.pending.push_back({IBM_PROF_CG_A, it, e0, e1});
+      P.pending.push_back({IBM_PROF_CG_B, it, e1, e2});
+    } else {
+      ibmk::run_cg_iteration(L, B, it);
+    }
+  };
+  // Flags are sticky for the whole call: a step that fails keeps every later step
+  // from writing the state, so the state it started from survives.
+  HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
+  const int cur0 = ctx->cur;
+  const int64_t step0 = ctx->step;
+  const int first_tag = ctx->tag + 1;
   for (int s = 0; s < n_steps; ++s) {
-    HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
+    const int tag = ++ctx->tag;
+    P.step_first = P.pending.size();
     if (ctx->nc > 0 && ctx->motion_axis >= 0) {
       ibm_status ms = IBM_OK;
       timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
@@ -591,67 +692,74 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     } else if (hrow) {
       HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
     }
-    timed(IBM_PROF_SETUP, 0,
-          [&] { ibmk::run_setup(L, B, ctx->cur, ctx->desc.cg_rtol, ctx->desc.cg_maxit); });
+    timed(IBM_PROF_SETUP, 0, [&] { ibmk::run_setup(L, B, ctx->cur, tag); });
+    // Iteration `it` tests convergence after `it` updates at its start, so a solve of
+    // n iterations takes n + 1 launches of part a; launches past convergence return
+    // at once. The first batch follows the last step's count, and the correction is
+    // queued behind it (it runs only once the solve has finished), so the device
+    // does not wait for the host unless the batch falls short.
+    int launched = 0;
+    const int first = std::max(1, ctx->cg_hint + 1);
+    for (int c = 0; c < first; ++c) cg_iteration(launched++);
+    timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
     HIPCHECK(ctx, hipGetLastError());
-    // Iteration `it` tests convergence after `it` updates at its start, so a solve
-    // of n iterations needs n + 1 launches of part a; launches past convergence
-    // return at once. The chunk follows the last step's count.
-    int launched = 0, chunk = std::max(1, ctx->cg_hint + 1);
+    uint64_t w = 0;
     for (;;) {
-      for (int c = 0; c < chunk; ++c) {
-        if (P.on) {
-          hipEvent_t e0 = P.mark(st);
-          ibmk::run_cg_half(L, B, launched, 0);
-          hipEvent_t e1 = P.mark(st);
-          ibmk::run_cg_half(L, B, launched, 1);
-          hipEvent_t e2 = P.mark(st);
-          P.pending.push_back({IBM_PROF_CG_A, launched, e0, e1});
-          P.pending.push_back({IBM_PROF_CG_B, launched, e1, e2});
-        } else {
-          ibmk::run_cg_iteration(L, B, launched);
-        }
-        ++launched;
-      }
-      HIPCHECK(ctx, hipGetLastError());
-      ibm_status r = sync_read(ctx, &ctx->cgh, B.cg, sizeof(CgScal));
+      ibm_status r = wait_progress(ctx, tag, launched - 1, &w);
       if (r) return r;
-      if (ctx->cgh.done) break;
-      if (launched > ctx->desc.cg_maxit + 4) break;
-      chunk = 2;
+      if (w & 0xF) break;
+      for (int c = 0; c < 2; ++c) cg_iteration(launched++);
+      timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
+      HIPCHECK(ctx, hipGetLastError());
     }
-    timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur); });
-    HIPCHECK(ctx, hipGetLastError());
-    int f[8];
-    ibm_status r = sync_read(ctx, f, B.flags, sizeof(f));
-    if (r) return r;
-    if (P.on) P.settle(ctx->cgh.iters);
-    if (f[1] || f[2] || f[3]) {
-      rc = marker_flags(ctx, f);
-      break;
-    }
-    if (f[0]) {
-      rc = fail(ctx, IBM_E_NONFINITE, "step produced a non-finite or non-positive value");
+    const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
+    const int iters = (int)((w >> 8) & 0xFFFFFF);
+    if (P.on) P.drop_cg_after(iters);
+    if (err) {
+      // this step's correction did not run; an earlier failure is sorted out below
+      rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE
+                                                                         : IBM_E_NOT_CONVERGED;
       break;
     }
     ctx->cur ^= 1;
     ctx->step += 1;
     ++done;
-    last_it = ctx->cgh.iters;
-    total_it += last_it;
-    res = ctx->cgh.res;
-    ctx->cg_hint = std::max(1, last_it);
-    if (ctx->cgh.done != 1) {
+    last_it = iters;
+    total_it += iters;
+    ctx->cg_hint = std::max(1, iters);
+    if (dstate != 1) {
       rc = fail(ctx, IBM_E_NOT_CONVERGED, "pressure CG reached cg_maxit");
       break;
     }
+  }
+  if (done > 0) ibmk::run_mass(L, B);
+  HIPCHECK(ctx, hipStreamSynchronize(st));
+  int f[8];
+  {
+    ibm_status r = sync_read(ctx, f, B.flags, sizeof(f));
+    if (r) return r;
+    r = sync_read(ctx, &ctx->cgh, B.cg, sizeof(CgScal));
+    if (r) return r;
+  }
+  if (P.on) P.settle();
+  if (f[ibmk::FLAG_NONFINITE]) {
+    // the first failing step and every later one left their input in place
+    const int s_bad = (f[ibmk::FLAG_BAD_STEP] - 1) - first_tag;
+    if (s_bad >= 0 && s_bad <= n_steps) {
+      ctx->cur = cur0 ^ (s_bad & 1);
+      ctx->step = step0 + s_bad;
+      done = s_bad;
+    }
+    rc = fail(ctx, IBM_E_NONFINITE, "step produced a non-finite or non-positive value");
+  } else if (f[ibmk::FLAG_SUPPORT] || f[ibmk::FLAG_EPS] || f[ibmk::FLAG_GRAM]) {
+    rc = marker_flags(ctx, f);
   }
   if (info) {
     info->steps_done = done;
     info->step = ctx->step;
     info->cg_iters_last = last_it;
     info->cg_iters_total = total_it;
-    info->cg_residual = res;
+    info->cg_residual = ctx->cgh.res;
     info->dt = L.g.dt;
     info->time = double(ctx->step) * L.g.dt;
     double m = 0.0;
@@ -759,7 +867,7 @@ ibm_status ibm_get_field(const ibm_ctx *cctx, int32_t which, void *dst) {
 ibm_status ibm_profile(ibm_ctx *ctx, int32_t enable) {
   if (!ctx) return IBM_E_ARG;
   HIPCHECK(ctx, hipStreamSynchronize(ctx->L.st));
-  ctx->prof.settle(0);
+  ctx->prof.settle();
   ctx->prof.on = enable != 0;
   if (enable) {
     for (int c = 0; c < IBM_PROF_CLASSES; ++c) {

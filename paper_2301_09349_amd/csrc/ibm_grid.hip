@@ -3,6 +3,8 @@
 // correction (Appendix A of Riahi, Goncalves da Silva, Meldi), plus state
 // initialisation. Templated on the dimension and on the storage/stencil type
 // (double, or float for the reduced-precision form).
+#include <algorithm>
+
 #include "ibm_launch.h"
 
 namespace ibmk {
@@ -215,6 +217,252 @@ __global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S
   }
 }
 
+// ------------------------------------------------------ LDS-tiled predictor
+// The same update with its work shared through LDS: a block owns a tile of
+// TX x TY (x TZ) cells; the primitive variables (rho, u, theta, mu) of the tile
+// and a two-cell halo are computed once into LDS with the ghost rules applied;
+// the fluxes of each face direction are then computed once per face into an LDS
+// buffer, from which every cell sums its divergence.
+template <int DIM>
+struct PTile;
+template <>
+struct PTile<2> {
+  static constexpr int TX = 64, TY = 8, TZ = 1;
+};
+template <>
+struct PTile<3> {
+  static constexpr int TX = 16, TY = 8, TZ = 4;
+};
+
+template <int DIM, typename S>
+struct PredLds {
+  static constexpr int TX = PTile<DIM>::TX, TY = PTile<DIM>::TY, TZ = PTile<DIM>::TZ;
+  static constexpr int SX = TX + 4, SY = TY + 4, SZ = (DIM == 3) ? TZ + 4 : 1;
+  static constexpr int NP = SX * SY * SZ;
+  static constexpr int NV = DIM + 3;  // rho, u[DIM], theta, mu
+  static constexpr int F0 = (TX + 1) * TY * TZ, F1 = TX * (TY + 1) * TZ,
+                       F2 = (DIM == 3) ? TX * TY * (TZ + 1) : 0;
+  static constexpr int NFMAX = F0 > F1 ? (F0 > F2 ? F0 : F2) : (F1 > F2 ? F1 : F2);
+  static constexpr int NFV = DIM + 3;  // F, uf, fm[DIM], fe
+  static constexpr int CPT = TX * TY * TZ / kThreads;  // cells per thread
+  static constexpr size_t bytes = sizeof(S) * (size_t)(NP * NV + NFMAX * NFV);
+  __device__ static constexpr int pt(int a, int b, int c) {
+    return (a + 2) + SX * ((b + 2) + SY * (DIM == 3 ? c + 2 : 0));
+  }
+};
+
+// Face fluxes from the LDS primitives; Q is the cell at local (qa, qb, qc), P the
+// cell below it along d. Same arithmetic as face_flux.
+template <int DIM, typename S>
+__device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int d, int qa, int qb,
+                                              int qc, S F, S &uf, S *fm, S &fe) {
+  using T = PredLds<DIM, S>;
+  constexpr int NP = T::NP;
+  int Q[3] = {qa, qb, qc}, P[3] = {qa, qb, qc};
+  P[d] -= 1;
+  const int iP = T::pt(P[0], P[1], P[2]), iQ = T::pt(Q[0], Q[1], Q[2]);
+  const S rP = lv[iP], rQ = lv[iQ];
+  S uP[3], uQ[3];
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    uP[q] = lv[(1 + q) * NP + iP];
+    uQ[q] = lv[(1 + q) * NP + iQ];
+  }
+  const S thP = lv[(DIM + 1) * NP + iP], thQ = lv[(DIM + 1) * NP + iQ];
+  const S muP = lv[(DIM + 2) * NP + iP], muQ = lv[(DIM + 2) * NP + iQ];
+  uf = F / (S(0.5) * (rP + rQ));
+  const S muf = S(0.5) * (muP + muQ);
+  const S lamf = S(0.5) * (S(g.cp) * muP / S(g.Pr) + S(g.cp) * muQ / S(g.Pr));
+  const S ih = S(g.ih[d]);
+  S dn[3], tg[3] = {S(0), S(0), S(0)};
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) dn[q] = (uQ[q] - uP[q]) * ih;
+  S divf = dn[d];
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    if (t == d) continue;
+    const S hh = S(0.5 * g.ih[t]);
+    int a[3] = {P[0], P[1], P[2]}, b[3] = {P[0], P[1], P[2]};
+    a[t] += 1;
+    b[t] -= 1;
+    const int ia = T::pt(a[0], a[1], a[2]), ib = T::pt(b[0], b[1], b[2]);
+    S gdP = (lv[(1 + d) * NP + ia] - lv[(1 + d) * NP + ib]) * hh;
+    S gtP = (lv[(1 + t) * NP + ia] - lv[(1 + t) * NP + ib]) * hh;
+    int c2[3] = {Q[0], Q[1], Q[2]}, e2[3] = {Q[0], Q[1], Q[2]};
+    c2[t] += 1;
+    e2[t] -= 1;
+    const int ic = T::pt(c2[0], c2[1], c2[2]), ie = T::pt(e2[0], e2[1], e2[2]);
+    S gdQ = (lv[(1 + d) * NP + ic] - lv[(1 + d) * NP + ie]) * hh;
+    S gtQ = (lv[(1 + t) * NP + ic] - lv[(1 + t) * NP + ie]) * hh;
+    tg[t] = S(0.5) * (gdP + gdQ);
+    divf += S(0.5) * (gtP + gtQ);
+  }
+  S cu[3], ce;
+  const S cv = S(g.cv);
+  if (g.conv == CONV_LINEAR) {
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) cu[q] = S(0.5) * (uP[q] + uQ[q]);
+    ce = S(0.5) * (cv * thP + cv * thQ);
+  } else {
+    const bool pos = F >= S(0);
+    int U[3] = {pos ? P[0] : Q[0], pos ? P[1] : Q[1], pos ? P[2] : Q[2]};
+    U[d] += pos ? -1 : 1;
+    const int iU = T::pt(U[0], U[1], U[2]);
+    const S thU = lv[(DIM + 1) * NP + iU];
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      const S uU = lv[(1 + q) * NP + iU];
+      cu[q] = pos ? vanleer(uP[q], uQ[q], uU) : vanleer(uQ[q], uP[q], uU);
+    }
+    ce = pos ? vanleer(cv * thP, cv * thQ, cv * thU) : vanleer(cv * thQ, cv * thP, cv * thU);
+  }
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    S tau = (q == d) ? muf * (S(2) * dn[d] - S(2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+    fm[q] = F * cu[q] - tau;
+  }
+  fe = F * ce - lamf * (thQ - thP) * ih;
+}
+
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> st, S *rho_s,
+                                                            S *ms0, S *ms1, S *ms2, S *E_s) {
+  using T = PredLds<DIM, S>;
+  constexpr int NP = T::NP, NFM = T::NFMAX, CPT = T::CPT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  S *lv = reinterpret_cast<S *>(smem);  // [NV][NP]
+  S *lf = lv + T::NV * NP;              // [NFV][NFMAX]
+  S *ms[3] = {ms0, ms1, ms2};
+  const int ptx = (g.n[0] + T::TX - 1) / T::TX, pty = (g.n[1] + T::TY - 1) / T::TY;
+  const int ptz = (DIM == 3) ? (g.n[2] + T::TZ - 1) / T::TZ : 1;
+  const int64_t ntile = (int64_t)ptx * pty * ptz;
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t rank = (b & 7) * (nb >> 3) + (b >> 3);
+  const int64_t per = (ntile + nb - 1) / nb;
+  const int64_t t0 = rank * per, t1 = (t0 + per < ntile) ? t0 + per : ntile;
+  const S dt = S(g.dt), gm1 = S(g.gm1);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int x0 = (int)(t % ptx) * T::TX;
+    const int y0 = (int)((t / ptx) % pty) * T::TY;
+    const int z0 = (DIM == 3) ? (int)(t / ((int64_t)ptx * pty)) * T::TZ : 0;
+    __syncthreads();  // the previous tile is done with LDS
+    // phase 1: primitives of the tile and its halo (points beyond two ghost
+    // layers are not needed and not loaded)
+    for (int p = threadIdx.x; p < NP; p += kThreads) {
+      const int li = p % T::SX, lj = (p / T::SX) % T::SY, lk = p / (T::SX * T::SY);
+      const int gi = x0 - 2 + li, gj = y0 - 2 + lj, gk = (DIM == 3) ? z0 - 2 + lk : 0;
+      bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
+      if (DIM == 3) ok = ok && gk >= -2 && gk <= g.n[2] + 1;
+      if (!ok) continue;
+      S r, u[3], th, pp;
+      load_prim<DIM>(g, st, gi, gj, gk, r, u, th, pp);
+      lv[p] = r;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + p] = u[q];
+      lv[(DIM + 1) * NP + p] = th;
+      lv[(DIM + 2) * NP + p] = mu_of(g, th);
+    }
+    __syncthreads();
+    // phase 2: cell-centred terms (-grad p, viscous dissipation) into registers
+    S acc[CPT][DIM + 3];  // rho, mom[DIM], E, div(uf)
+    int cl[CPT][3];
+    bool cv_ok[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      const int lc = threadIdx.x + kThreads * m;
+      const int ci = lc % T::TX, cj = (lc / T::TX) % T::TY, ck = lc / (T::TX * T::TY);
+      cl[m][0] = ci;
+      cl[m][1] = cj;
+      cl[m][2] = ck;
+      const int i = x0 + ci, j = y0 + cj, k = z0 + ck;
+      cv_ok[m] = i < g.n[0] && j < g.n[1] && (DIM == 2 || k < g.n[2]);
+#pragma unroll
+      for (int v = 0; v < DIM + 3; ++v) acc[m][v] = S(0);
+      if (!cv_ok[m]) continue;
+      S gr[3][3], gp[3];
+#pragma unroll
+      for (int bd = 0; bd < DIM; ++bd) {
+        int a1[3] = {ci, cj, ck}, a0[3] = {ci, cj, ck};
+        a1[bd] += 1;
+        a0[bd] -= 1;
+        const int i1 = T::pt(a1[0], a1[1], a1[2]), i0 = T::pt(a0[0], a0[1], a0[2]);
+        const S hh = S(0.5 * g.ih[bd]);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) gr[a][bd] = (lv[(1 + a) * NP + i1] - lv[(1 + a) * NP + i0]) * hh;
+        int g1[3] = {i, j, k}, g0[3] = {i, j, k};
+        g1[bd] += 1;
+        g0[bd] -= 1;
+        Resolved r1 = resolve<DIM>(g, g1[0], g1[1], g1[2]);
+        Resolved r0 = resolve<DIM>(g, g0[0], g0[1], g0[2]);
+        S p1 = ghosted<DIM>(g, r1, V_P, gm1 * st.E[r1.c]);
+        S p0 = ghosted<DIM>(g, r0, V_P, gm1 * st.E[r0.c]);
+        gp[bd] = (p1 - p0) * hh;
+      }
+      S divu = S(0);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) divu += gr[a][a];
+      S phi = S(0);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int bd = 0; bd < DIM; ++bd) phi += (gr[a][bd] + gr[bd][a]) * gr[a][bd];
+      phi = lv[(DIM + 2) * NP + T::pt(ci, cj, ck)] * (phi - S(2.0 / 3.0) * divu * divu);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) acc[m][1 + q] = -dt * gp[q];
+      acc[m][DIM + 1] = dt * phi;
+    }
+    // phase 3: faces, one direction at a time
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2 ? 1 : 0);
+      const int nfd = FX * FY * FZ;
+      for (int f = threadIdx.x; f < nfd; f += kThreads) {
+        const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
+        const int gi = x0 + fi, gj = y0 + fj, gk = z0 + fk;
+        const int gc[3] = {gi, gj, gk};
+        bool ok = true;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) ok = ok && (gc[e] < g.n[e] + (e == d ? 1 : 0));
+        if (!ok) continue;
+        const S F = st.F[d][fidx(g, d, gi, gj, gk)];
+        S uf, fm[3], fe;
+        face_flux_lds<DIM, S>(g, lv, d, fi, fj, fk, F, uf, fm, fe);
+        lf[f] = F;
+        lf[NFM + f] = uf;
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) lf[(2 + q) * NFM + f] = fm[q];
+        lf[(2 + DIM) * NFM + f] = fe;
+      }
+      __syncthreads();
+      const int step = (d == 0) ? 1 : (d == 1) ? FX : FX * FY;
+      const S ih = S(g.ih[d]);
+#pragma unroll
+      for (int m = 0; m < CPT; ++m) {
+        if (!cv_ok[m]) continue;
+        const int fl = cl[m][0] + FX * (cl[m][1] + FY * cl[m][2]), fh = fl + step;
+        acc[m][0] += (lf[fh] - lf[fl]) * ih;
+        acc[m][DIM + 2] += (lf[NFM + fh] - lf[NFM + fl]) * ih;
+#pragma unroll
+        for (int q = 0; q < DIM; ++q)
+          acc[m][1 + q] -= dt * ((lf[(2 + q) * NFM + fh] - lf[(2 + q) * NFM + fl]) * ih);
+        acc[m][DIM + 1] -= dt * ((lf[(2 + DIM) * NFM + fh] - lf[(2 + DIM) * NFM + fl]) * ih);
+      }
+      __syncthreads();
+    }
+    // phase 4: outputs
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      if (!cv_ok[m]) continue;
+      const int64_t c = cidx(g, x0 + cl[m][0], y0 + cl[m][1], z0 + cl[m][2]);
+      const S E = st.E[c];
+      rho_s[c] = st.rho[c] - dt * acc[m][0];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) ms[q][c] = st.mom[q][c] + acc[m][1 + q];
+      E_s[c] = E + acc[m][DIM + 1] - dt * (gm1 * E) * acc[m][DIM + 2];
+    }
+  }
+}
+
 // ------------------------------------------------------- initialisation
 __global__ void k_fill(double *p, int64_t n, double v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -348,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
                                                      const S *mh1, const S *mh2, S *Fh0, S *Fh1,
                                                      S *Fh2, const S *psi, const double *x,
                                                      double *b, double *r, double *p,
-                                                     double *partials, CgScal *cs) {
+                                                     double *partials, CgScal *cs, int tag) {
   __shared__ double lds[32];
   const S *mh[3] = {mh0, mh1, mh2};
   S *Fh[3] = {Fh0, Fh1, Fh2};
@@ -393,6 +641,7 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
     if (blockIdx.x == 0) {
       cs->done = 0;
       cs->iters = 0;
+      cs->step_tag = tag;
     }
   }
 }
@@ -402,26 +651,37 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
 // iterations -> all blocks stop and block 0 records it. Otherwise
 // beta = rr_it / rr_{it-1} (0 at it = 0), p = r + beta p_old (also at the
 // neighbours, on the fly), q = A p, partial p.q.
+// Block 0 posts (step tag, it, error flags, done) to `progress` (host memory, may
+// be NULL) so that the host can follow the solve without synchronising; a step
+// whose flags show an error stops its solve.
 template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_cg_a(GridK g, int it, const S *psi, const double *r,
                                                    const double *pold, double *pnew, double *q,
-                                                   double *partials, CgScal *cs) {
+                                                   double *partials, CgScal *cs, const int *flags,
+                                                   uint64_t *progress) {
   __shared__ double lds[32];
-  if (cs->done) return;
+  // block 0 of this kernel may set `done` while other blocks start: one read per block
+  __shared__ int done0;
+  if (threadIdx.x == 0) done0 = cs->done;
+  __syncthreads();
+  if (done0) return;
   const int nb = gridDim.x;
   const double rr = sum_partials(partials + PART_RR * kMaxBlocks, nb, lds);
   const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
   const double tol2 = cs->tol2;
+  const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
+                  (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
   const bool conv = rr <= tol2 * bb;
-  const bool out = !conv && it >= cs->maxit;
+  const bool out = !conv && (it >= cs->maxit || err != 0 || !(rr == rr));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (it == 0) cs->bb = bb;
     cs->rr[it & 1] = rr;
     cs->res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    if (conv || out) {
-      cs->done = conv ? 1 : 2;
-      cs->iters = it;
-    }
+    cs->iters = it;
+    if (conv || out) cs->done = conv ? 1 : 2;
+    if (progress)
+      __hip_atomic_store(progress, pack_progress(cs->step_tag, it, err, conv ? 1 : out ? 2 : 0),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   if (conv || out) return;
   const double beta = (it == 0) ? 0.0 : rr / cs->rr[(it - 1) & 1];
@@ -485,8 +745,18 @@ __global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, St
                                                       const S *rho_s, const S *E_s, const S *mh0,
                                                       const S *mh1, const S *mh2, const S *Fh0,
                                                       const S *Fh1, const S *Fh2, const double *x,
-                                                      double *partials, int *flags) {
+                                                      double *partials, int *flags,
+                                                      const CgScal *cs, int tag) {
   __shared__ double lds[32];
+  // Runs only after a finished solve of this step and while no earlier step has
+  // failed: a failed step leaves the state it started from untouched. (Decided by
+  // one thread: other blocks may raise a flag while this one starts.)
+  __shared__ int skip;
+  if (threadIdx.x == 0)
+    skip = cs->step_tag != tag || cs->done == 0 || flags[FLAG_NONFINITE] ||
+           flags[FLAG_SUPPORT] || flags[FLAG_EPS] || flags[FLAG_GRAM];
+  __syncthreads();
+  if (skip) return;
   const S *mh[3] = {mh0, mh1, mh2};
   const S *Fh[3] = {Fh0, Fh1, Fh2};
   const double dt = g.dt;
@@ -526,7 +796,10 @@ __global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, St
     bad = bad || !(rn > 0.0) || !(theta > 0.0) || !isfinite(rn) || !isfinite(En);
     m += rn * g.dV;
   }
-  if (bad) atomicOr(flags, 1);
+  if (bad) {
+    atomicOr(flags + FLAG_NONFINITE, 1);
+    atomicCAS(flags + FLAG_BAD_STEP, 0, tag + 1);
+  }
   double s = block_sum(m, lds);
   if (threadIdx.x == 0) partials[PART_MASS * kMaxBlocks + blockIdx.x] = s;
 }
@@ -608,17 +881,47 @@ void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur) {
   });
 }
 
+size_t predictor_lds_bytes(int dim, int prec) {
+  if (dim == 2) return prec ? PredLds<2, float>::bytes : PredLds<2, double>::bytes;
+  return prec ? PredLds<3, float>::bytes : PredLds<3, double>::bytes;
+}
+
+void enable_predictor_lds(int dim, int prec) {
+  const int bytes = (int)predictor_lds_bytes(dim, prec);
+  if (dim == 2 && prec == 0)
+    (void)hipFuncSetAttribute((const void *)k_predictor_lds<2, double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  else if (dim == 2)
+    (void)hipFuncSetAttribute((const void *)k_predictor_lds<2, float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  else if (prec == 0)
+    (void)hipFuncSetAttribute((const void *)k_predictor_lds<3, double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  else
+    (void)hipFuncSetAttribute((const void *)k_predictor_lds<3, float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 void run_predictor(const Launch &L, const Bufs &B, int cur) {
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_predictor<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
-                       L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
-                       (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
+    if (L.pred_lds) {
+      using T = PredLds<DIM, S>;
+      const int64_t nt = (int64_t)((L.g.n[0] + T::TX - 1) / T::TX) *
+                         ((L.g.n[1] + T::TY - 1) / T::TY) *
+                         (DIM == 3 ? (L.g.n[2] + T::TZ - 1) / T::TZ : 1);
+      const int64_t nb = std::min<int64_t>(((nt + 7) / 8) * 8, kMaxBlocks);
+      hipLaunchKernelGGL((k_predictor_lds<DIM, S>), dim3((unsigned)nb), dim3(kThreads), T::bytes,
+                         L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
+                         (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
+    } else {
+      hipLaunchKernelGGL((k_predictor<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
+                         L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
+                         (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
+    }
   });
 }
 
-void run_setup(const Launch &L, const Bufs &B, int cur, double rtol, int maxit) {
-  (void)rtol;
-  (void)maxit;
+void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
   IBM_DISPATCH(L, {
     hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                        L.g, state_of<S>(B, cur), (const S *)B.rho_s, (const S *)B.mom_s[0],
@@ -627,7 +930,8 @@ void run_setup(const Launch &L, const Bufs &B, int cur, double rtol, int maxit) 
     hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                        L.g, (const S *)B.rho[cur], (const S *)B.mhat[0], (const S *)B.mhat[1],
                        (const S *)B.mhat[2], (S *)B.Fhat[0], (S *)B.Fhat[1], (S *)B.Fhat[2],
-                       (const S *)B.psi, (const double *)B.x, B.b, B.r, B.p[0], B.partials, B.cg);
+                       (const S *)B.psi, (const double *)B.x, B.b, B.r, B.p[0], B.partials, B.cg,
+                       tag);
   });
 }
 
@@ -638,7 +942,7 @@ void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
     if (part == 0)
       hipLaunchKernelGGL((k_cg_a<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                          L.g, it, (const S *)B.psi, (const double *)B.r, (const double *)pold,
-                         pnew, B.q, B.partials, B.cg);
+                         pnew, B.q, B.partials, B.cg, (const int *)B.flags, B.progress);
     else
       hipLaunchKernelGGL((k_cg_b<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                          L.g, it, B.x, B.r, (const double *)pnew, (const double *)B.q, B.partials,
@@ -651,15 +955,18 @@ void run_cg_iteration(const Launch &L, const Bufs &B, int it) {
   run_cg_half(L, B, it, 1);
 }
 
-void run_correct(const Launch &L, const Bufs &B, int cur) {
+void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {
   IBM_DISPATCH(L, {
     hipLaunchKernelGGL((k_correct<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
                        L.st, L.g, state_of<S>(B, cur), state_of<S>(B, cur ^ 1),
                        (const S *)B.rho_s, (const S *)B.E_s, (const S *)B.mhat[0],
                        (const S *)B.mhat[1], (const S *)B.mhat[2], (const S *)B.Fhat[0],
                        (const S *)B.Fhat[1], (const S *)B.Fhat[2], (const double *)B.x,
-                       B.partials, B.flags);
+                       B.partials, B.flags, (const CgScal *)B.cg, tag);
   });
+}
+
+void run_mass(const Launch &L, const Bufs &B) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, L.st,
                      (const double *)B.partials + PART_MASS * kMaxBlocks, (int)L.g.nblocks,
                      B.scal);

@@ -51,8 +51,20 @@ struct StateV {
 // iteration i-1 while writing its own).
 struct CgScal {
   double bb, tol2, rr[2], res;
-  int iters, done, maxit, pad;
+  int iters, done, maxit, step_tag;
 };
+
+// Progress word the CG posts to host memory after each convergence test:
+// bits 32..63 step tag, 8..31 iteration, 4..7 error flags seen, 0..3 done state.
+__host__ __device__ inline uint64_t pack_progress(int tag, int it, int err, int done) {
+  return ((uint64_t)(uint32_t)tag << 32) | ((uint64_t)(it & 0xFFFFFF) << 8) |
+         ((uint64_t)(err & 0xF) << 4) | (uint64_t)(done & 0xF);
+}
+
+// Device flags (int): [0] non-finite result, [1] marker support out of the box,
+// [2] quadrature solve failed, [3] Gram row overflow, [4] 1 + tag of the first
+// step whose correction failed.
+enum { FLAG_NONFINITE = 0, FLAG_SUPPORT = 1, FLAG_EPS = 2, FLAG_GRAM = 3, FLAG_BAD_STEP = 4 };
 
 // Per-block partial sums of the cell kernels, each region kMaxBlocks long.
 enum { PART_PQ = 0, PART_RR = 1, PART_BB = 2, PART_MASS = 3, PART_REGIONS = 4 };

@@ -19,8 +19,8 @@ struct Bufs {
   double *partials;  // per-block partial sums, 4 per block
   CgScal *cg;
   double *scal;      // [0] mass
-  int *flags;        // [0] non-finite, [1] support out of box, [2] eps solve failed,
-                     // [3] Gram row overflow
+  int *flags;        // FLAG_* (ibm_internal.h)
+  uint64_t *progress;  // host memory (pinned, coherent): CG progress word
 
   // candidate markers
   double *cX0, *cUd0, *cTw, *cdA, *ceps;  // ceps: last eps per candidate (warm start)
@@ -50,7 +50,8 @@ struct Bufs {
 
 struct Launch {
   GridK g;
-  int prec;  // 0: FP64, 1: FP32
+  int prec;      // 0: FP64, 1: FP32
+  int pred_lds;  // 1: LDS-tiled predictor, 0: per-cell predictor
   int nc_cap;     // candidate capacity
   int npairs_pad; // power of two >= nc_cap * nslot
   hipStream_t st;
@@ -63,10 +64,13 @@ void run_init_primitive(const Launch &L, const Bufs &B, int cur, const void *rho
                         const void *theta);
 void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
 void run_predictor(const Launch &L, const Bufs &B, int cur);
-void run_setup(const Launch &L, const Bufs &B, int cur, double rtol, int maxit);
-void run_cg_iteration(const Launch &L, const Bufs &B, int parity);
-void run_cg_half(const Launch &L, const Bufs &B, int parity, int part);  // part 0: a, 1: b
-void run_correct(const Launch &L, const Bufs &B, int cur);
+size_t predictor_lds_bytes(int dim, int prec);
+void enable_predictor_lds(int dim, int prec);
+void run_setup(const Launch &L, const Bufs &B, int cur, int tag);
+void run_cg_iteration(const Launch &L, const Bufs &B, int it);
+void run_cg_half(const Launch &L, const Bufs &B, int it, int part);  // part 0: a, 1: b
+void run_correct(const Launch &L, const Bufs &B, int cur, int tag);
+void run_mass(const Launch &L, const Bufs &B);
 int64_t cell_blocks(const GridK &g);
 
 // marker kernels (ibm_markers.hip)

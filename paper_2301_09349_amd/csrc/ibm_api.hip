@@ -262,10 +262,23 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   }
   B.b = C.take<double>(N);
   B.x = C.take<double>(N);
-  B.r = C.take<double>(N);
-  B.p[0] = C.take<double>(N);
-  B.p[1] = C.take<double>(N);
-  B.q = C.take<double>(N);
+  if (d.precision == IBM_FP32) {
+    // FP32 form: x ping-pong for the refinement; inner CG vectors in FP32
+    B.x2 = C.take<double>(N);
+    B.r32 = C.take<float>(N);
+    B.p32[0] = C.take<float>(N);
+    B.p32[1] = C.take<float>(N);
+    B.q32 = C.take<float>(N);
+    B.d32 = C.take<float>(N);
+    B.r = B.p[0] = B.p[1] = B.q = nullptr;
+  } else {
+    B.r = C.take<double>(N);
+    B.p[0] = C.take<double>(N);
+    B.p[1] = C.take<double>(N);
+    B.q = C.take<double>(N);
+    B.x2 = nullptr;
+    B.r32 = B.p32[0] = B.p32[1] = B.q32 = B.d32 = nullptr;
+  }
   B.partials = C.take<double>((size_t)ibmk::PART_REGIONS * ibmk::kMaxBlocks);
   B.cg = C.take<CgScal>(1);
   B.scal = C.take<double>(8);
@@ -843,9 +856,13 @@ ibm_status ibm_get_field(const ibm_ctx *cctx, int32_t which, void *dst) {
     case 4:
       HIPCHECK(ctx, hipMemcpyAsync(dst, B.b, g.N * 8, hipMemcpyDeviceToDevice, st));
       break;
-    case 5:
-      HIPCHECK(ctx, hipMemcpyAsync(dst, B.x, g.N * 8, hipMemcpyDeviceToDevice, st));
+    case 5: {
+      ibm_status r = sync_read(ctx, &ctx->cgh, B.cg, sizeof(CgScal));
+      if (r) return r;
+      const double *xs = (ctx->cgh.xfinal && B.x2) ? B.x2 : B.x;
+      HIPCHECK(ctx, hipMemcpyAsync(dst, xs, g.N * 8, hipMemcpyDeviceToDevice, st));
       break;
+    }
     case 6: {
       int nu = 0;
       if (ctx->nc > 0) {

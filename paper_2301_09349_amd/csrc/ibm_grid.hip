@@ -642,6 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
       cs->done = 0;
       cs->iters = 0;
       cs->step_tag = tag;
+      cs->xfinal = 0;
     }
   }
 }
@@ -729,6 +730,248 @@ __global__ __launch_bounds__(kThreads) void k_cg_b(GridK g, int it, double *x, d
   if (threadIdx.x == 0) partials[PART_RR * kMaxBlocks + blockIdx.x] = s;
 }
 
+// ------------------------------------- FP32 form: pressure by iterative refinement
+// x and the outer residual r = b - A x are FP64; each inner solve A d = r runs CG
+// on FP32 vectors with FP64 dot products to a relative 1e-4 (or kInnerMax
+// iterations), then x += d and the FP64 residual is formed again. The solve ends
+// when the FP64 residual meets |r| <= rtol |b|.
+constexpr double kInnerTol2 = 1e-8;
+constexpr int kInnerMax = 60;
+
+// Set-up part 2 of the FP32 form: as k_setup2, with the FP64 start residual
+// handed to the inner solve as FP32 (r32) and d = 0.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_setup2m(GridK g, const float *rho_n, const float *mh0,
+                                                      const float *mh1, const float *mh2,
+                                                      float *Fh0, float *Fh1, float *Fh2,
+                                                      const float *psi, const double *x,
+                                                      double *b, float *r32, float *d32,
+                                                      double *partials, CgScal *cs, int tag) {
+  using S = float;
+  __shared__ double lds[32];
+  const S *mh[3] = {mh0, mh1, mh2};
+  S *Fh[3] = {Fh0, Fh1, Fh2};
+  double sums[2] = {0.0, 0.0};
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const int ix[3] = {i, j, k};
+    double div = 0.0, aff = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int hi[3] = {i, j, k};
+      hi[d] += 1;
+      S fl = face_from_cells<DIM, S>(g, mh, rho_n, d, i, j, k);
+      S fh = face_from_cells<DIM, S>(g, mh, rho_n, d, hi[0], hi[1], hi[2]);
+      Fh[d][fidx(g, d, i, j, k)] = fl;
+      if (ix[d] == g.n[d] - 1) Fh[d][fidx(g, d, hi[0], hi[1], hi[2])] = fh;
+      div += (double(fh) - double(fl)) * g.ih[d];
+      if (g.bc[d][0] != BC_PERIODIC) {
+        if (ix[d] == 0 && g.bc[d][0] == BC_OUTFLOW) aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
+        if (ix[d] == g.n[d] - 1 && g.bc[d][1] == BC_OUTFLOW)
+          aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
+      }
+    }
+    const double bc_ = double(rho_n[c]) - g.dt * div + g.dt * g.dt * aff;
+    const double xc = x[c];
+    const double ax = helm_at<DIM>(g, psi, [&](int64_t q) { return x[q]; }, i, j, k, c, xc);
+    const double rc = bc_ - ax;
+    b[c] = bc_;
+    r32[c] = float(rc);
+    d32[c] = 0.0f;
+    sums[0] += bc_ * bc_;
+    sums[1] += rc * rc;
+  }
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[PART_BB * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[PART_RR * kMaxBlocks + blockIdx.x] = sums[1];
+    if (blockIdx.x == 0) {
+      cs->done = 0;
+      cs->iters = 0;
+      cs->step_tag = tag;
+      cs->xfinal = 0;
+      cs->outer[0] = 1;
+      cs->xpar[0] = 0;
+      cs->inner_it[0] = 0;
+      cs->rr_in0[0] = 0.0;
+      cs->skip_b = 0;
+    }
+  }
+}
+
+// FP32 pressure operator at one cell (single precision arithmetic).
+template <int DIM, typename VF>
+__device__ __forceinline__ float helm32_at(const GridK &g, const float *psi, VF v, int i, int j,
+                                           int k, int64_t c, float vc) {
+  float lap = 0.0f;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const float ih = float(g.ih[d]);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int ix[3] = {i, j, k};
+      ix[d] += side ? 1 : -1;
+      const int n = g.n[d];
+      float gf;
+      if (ix[d] >= 0 && ix[d] < n) {
+        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+      } else if (g.bc[d][0] == BC_PERIODIC) {
+        ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
+        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+      } else {
+        gf = (g.bc[d][side] == BC_OUTFLOW) ? (-2.0f * vc) * ih : 0.0f;
+      }
+      lap += gf * ih;
+    }
+  }
+  return psi[c] * vc - float(g.dt * g.dt) * lap;
+}
+
+// Iteration `it`, part a, of the FP32 form. Every block forms the same r.r from
+// the partials and takes the same decision:
+//  - after an outer residual: converged -> done; else start an inner solve
+//    (p = r), as CG part a;
+//  - inside an inner solve: converged to 1e-4 relative (or kInnerMax) -> refine:
+//    x_new = x + d (also at the neighbours, on the fly), r = b - A x_new in FP64,
+//    r32 = r, d = 0, partial r.r; otherwise CG part a with beta.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_mcg_a(GridK g, int it, const float *psi,
+                                                    const double *b, double *x0, double *x1,
+                                                    float *r32, const float *pold, float *pnew,
+                                                    float *q32, float *d32, double *partials,
+                                                    CgScal *cs, const int *flags,
+                                                    uint64_t *progress) {
+  __shared__ double lds[32];
+  __shared__ int done0;
+  if (threadIdx.x == 0) done0 = cs->done;
+  __syncthreads();
+  if (done0) return;
+  const int nb = gridDim.x, sl = it & 1, sn = (it + 1) & 1;
+  const double rr = sum_partials(partials + PART_RR * kMaxBlocks, nb, lds);
+  const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
+  const double tol2 = cs->tol2;
+  const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
+                  (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
+  const bool outer = cs->outer[sl] != 0;
+  const int xp = cs->xpar[sl];
+  const bool bad = err != 0 || !(rr == rr);
+  bool conv = false, out = false, refine = false;
+  double beta = 0.0;
+  if (outer) {
+    conv = rr <= tol2 * bb;
+    out = !conv && (it >= cs->maxit || bad);
+  } else {
+    const int ni = cs->inner_it[sl];
+    refine = rr <= kInnerTol2 * cs->rr_in0[sl] || ni >= kInnerMax || it >= cs->maxit || bad;
+    if (!refine) beta = rr / cs->rr[(it - 1) & 1];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (it == 0) cs->bb = bb;
+    cs->rr[sl] = rr;
+    cs->iters = it;
+    if (outer) {
+      cs->res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+      if (conv || out) {
+        cs->done = conv ? 1 : 2;
+        cs->xfinal = xp;
+      } else {
+        cs->rr_in0[sn] = rr;
+        cs->inner_it[sn] = 1;
+        cs->outer[sn] = 0;
+        cs->xpar[sn] = xp;
+        cs->skip_b = 0;
+      }
+    } else if (refine) {
+      cs->outer[sn] = 1;
+      cs->xpar[sn] = xp ^ 1;
+      cs->skip_b = 1;
+    } else {
+      cs->rr_in0[sn] = cs->rr_in0[sl];
+      cs->inner_it[sn] = cs->inner_it[sl] + 1;
+      cs->outer[sn] = 0;
+      cs->xpar[sn] = xp;
+      cs->skip_b = 0;
+    }
+    if (progress)
+      __hip_atomic_store(progress, pack_progress(cs->step_tag, it, err, conv ? 1 : out ? 2 : 0),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  if (conv || out) return;
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  double part = 0.0;
+  if (refine) {
+    const double *xo = xp ? x1 : x0;
+    double *xn = xp ? x0 : x1;
+    auto xv = [&](int64_t m) { return xo[m] + double(d32[m]); };
+    for (int64_t t = t0; t < t1; ++t) {
+      int i, j, k;
+      if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+      const int64_t c = cidx(g, i, j, k);
+      const double xc = xv(c);
+      const double rc = b[c] - helm_at<DIM>(g, psi, xv, i, j, k, c, xc);
+      xn[c] = xc;
+      r32[c] = float(rc);
+      part += rc * rc;
+    }
+    // d is cleared once every block has read it: done by part b of this iteration
+  } else {
+    // the first iteration of an inner solve takes p = r (the old p is not read)
+    const float bf = float(beta);
+    auto pv = [&](int64_t m) { return outer ? r32[m] : r32[m] + bf * pold[m]; };
+    for (int64_t t = t0; t < t1; ++t) {
+      int i, j, k;
+      if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+      const int64_t c = cidx(g, i, j, k);
+      const float pc = pv(c);
+      const float qc = helm32_at<DIM>(g, psi, pv, i, j, k, c, pc);
+      pnew[c] = pc;
+      q32[c] = qc;
+      part += double(pc) * double(qc);
+    }
+  }
+  double s = block_sum(part, lds);
+  if (threadIdx.x == 0)
+    partials[(refine ? PART_RR : PART_PQ) * kMaxBlocks + blockIdx.x] = s;
+}
+
+// Part b of the FP32 form: d += alpha p, r -= alpha q (FP32), partial r.r (FP64);
+// after a refinement it clears d instead.
+template <int DIM>
+__global__ __launch_bounds__(kThreads) void k_mcg_b(GridK g, int it, float *d32, float *r32,
+                                                    const float *p, const float *q32,
+                                                    double *partials, CgScal *cs) {
+  __shared__ double lds[32];
+  if (cs->done) return;
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  if (cs->skip_b) {
+    for (int64_t t = t0; t < t1; ++t) {
+      int i, j, k;
+      if (cell_in_tile<DIM>(g, t, i, j, k)) d32[cidx(g, i, j, k)] = 0.0f;
+    }
+    return;
+  }
+  const double pq = sum_partials(partials + PART_PQ * kMaxBlocks, gridDim.x, lds);
+  const float alpha = float(cs->rr[it & 1] / pq);
+  double rr = 0.0;
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    d32[c] += alpha * p[c];
+    const float rc = r32[c] - alpha * q32[c];
+    r32[c] = rc;
+    rr += double(rc) * double(rc);
+  }
+  double s = block_sum(rr, lds);
+  if (threadIdx.x == 0) partials[PART_RR * kMaxBlocks + blockIdx.x] = s;
+}
+
 // Pressure with its ghost rule (zero gradient at inflow and slip, p_inf on
 // outflow faces).
 template <int DIM>
@@ -744,7 +987,8 @@ template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, StateV<S> nxt,
                                                       const S *rho_s, const S *E_s, const S *mh0,
                                                       const S *mh1, const S *mh2, const S *Fh0,
-                                                      const S *Fh1, const S *Fh2, const double *x,
+                                                      const S *Fh1, const S *Fh2,
+                                                      const double *xa, const double *xb,
                                                       double *partials, int *flags,
                                                       const CgScal *cs, int tag) {
   __shared__ double lds[32];
@@ -757,6 +1001,7 @@ __global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, St
            flags[FLAG_SUPPORT] || flags[FLAG_EPS] || flags[FLAG_GRAM];
   __syncthreads();
   if (skip) return;
+  const double *x = cs->xfinal ? xb : xa;  // the solution buffer of the FP32 form's solve
   const S *mh[3] = {mh0, mh1, mh2};
   const S *Fh[3] = {Fh0, Fh1, Fh2};
   const double dt = g.dt;
@@ -922,6 +1167,28 @@ void run_predictor(const Launch &L, const Bufs &B, int cur) {
 }
 
 void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
+  if (L.prec == 1) {
+    IBM_DISPATCH(L, {
+      hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
+                         L.st, L.g, state_of<S>(B, cur), (const S *)B.rho_s,
+                         (const S *)B.mom_s[0], (const S *)B.mom_s[1], (const S *)B.mom_s[2],
+                         (const S *)B.E_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2],
+                         (S *)B.psi, B.x);
+    });
+    if (L.g.dim == 2)
+      hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+                         (const float *)B.rho[cur], (const float *)B.mhat[0],
+                         (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
+                         (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
+                         (const double *)B.x, B.b, B.r32, B.d32, B.partials, B.cg, tag);
+    else
+      hipLaunchKernelGGL((k_setup2m<3>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+                         (const float *)B.rho[cur], (const float *)B.mhat[0],
+                         (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
+                         (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
+                         (const double *)B.x, B.b, B.r32, B.d32, B.partials, B.cg, tag);
+    return;
+  }
   IBM_DISPATCH(L, {
     hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                        L.g, state_of<S>(B, cur), (const S *)B.rho_s, (const S *)B.mom_s[0],
@@ -935,7 +1202,28 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
   });
 }
 
+template <int DIM>
+static void run_mcg_half(const Launch &L, const Bufs &B, int it, int part) {
+  float *pold = B.p32[it & 1], *pnew = B.p32[(it & 1) ^ 1];
+  if (part == 0)
+    hipLaunchKernelGGL((k_mcg_a<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+                       it, (const float *)B.psi, (const double *)B.b, B.x, B.x2, B.r32,
+                       (const float *)pold, pnew, B.q32, B.d32, B.partials, B.cg,
+                       (const int *)B.flags, B.progress);
+  else
+    hipLaunchKernelGGL((k_mcg_b<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+                       it, B.d32, B.r32, (const float *)pnew, (const float *)B.q32, B.partials,
+                       B.cg);
+}
+
 void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
+  if (L.prec == 1) {
+    if (L.g.dim == 2)
+      run_mcg_half<2>(L, B, it, part);
+    else
+      run_mcg_half<3>(L, B, it, part);
+    return;
+  }
   IBM_DISPATCH(L, {
     const int parity = it & 1;
     double *pold = B.p[parity], *pnew = B.p[parity ^ 1];
@@ -962,7 +1250,8 @@ void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {
                        (const S *)B.rho_s, (const S *)B.E_s, (const S *)B.mhat[0],
                        (const S *)B.mhat[1], (const S *)B.mhat[2], (const S *)B.Fhat[0],
                        (const S *)B.Fhat[1], (const S *)B.Fhat[2], (const double *)B.x,
-                       B.partials, B.flags, (const CgScal *)B.cg, tag);
+                       (const double *)(B.x2 ? B.x2 : B.x), B.partials, B.flags,
+                       (const CgScal *)B.cg, tag);
   });
 }
 

@@ -52,6 +52,14 @@ struct StateV {
 struct CgScal {
   double bb, tol2, rr[2], res;
   int iters, done, maxit, step_tag;
+  // FP32 form (iterative refinement). Values the kernel of iteration `it` reads
+  // sit in slot it & 1; block 0 of that kernel writes slot (it + 1) & 1.
+  double rr_in0[2];  // r.r at the start of the current inner solve
+  int inner_it[2];   // inner iterations since the last refinement
+  int outer[2];      // 1: the partial sums come from an FP64 outer residual
+  int xpar[2];       // which x buffer holds the current solution
+  int xfinal;        // x buffer of the finished solve (read by the correction)
+  int skip_b;        // 1: part b of this iteration has nothing to do
 };
 
 // Progress word the CG posts to host memory after each convergence test:

@@ -16,6 +16,9 @@ struct Bufs {
   void *mhat[3], *Fhat[3], *psi;
   // pressure CG (FP64)
   double *b, *x, *r, *p[2], *q;
+  // FP32 form: second FP64 solution buffer and the FP32 inner-CG vectors
+  double *x2;
+  float *r32, *p32[2], *q32, *d32;
   double *partials;  // per-block partial sums, 4 per block
   CgScal *cg;
   double *scal;      // [0] mass

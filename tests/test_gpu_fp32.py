@@ -1,0 +1,53 @@
+"""The FP32 form: FP32 state, stencils and psi; FP64 markers, sums and pressure
+solution (iterative refinement around an FP32 inner CG). Its error against the
+FP64 oracle is measured per result and held to the stated bounds."""
+import numpy as np
+import pytest
+
+from paper_2301_09349_amd import inputs
+from helpers import make_gpu, make_oracle, rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _primitives(rho, mom, E, cv):
+    rho = to_np(rho)
+    u = to_np(mom) / rho
+    th = to_np(E) / (rho * cv)
+    return rho, u, th
+
+
+def test_fp32_form_against_fp64_oracle(cuda):
+    c = inputs.case("cfg1")
+    g32 = make_gpu(c, precision="fp32")
+    o = make_oracle(c)
+    h32, info = g32.step(100)
+    ho = o.step(100)
+    assert info["cg_residual"] <= c["cg_rtol"]  # the FP64 outer residual meets rtol
+    R = 1.0 / (1.4 * c["Ma"] ** 2)
+    cv = R / 0.4
+    r, m, E, _ = g32.get_state()
+    ro, mo, Eo, _ = o.get_state()
+    _, u32, t32 = _primitives(r, m, E, cv)
+    _, u64, t64 = _primitives(ro, mo, Eo, cv)
+    e_u = rel_l2(u32, u64)
+    e_t = rel_l2(t32 - 1.0, t64 - 1.0)  # temperature departure from the free stream
+    # force and heat histories (drag and Nusselt number are proportional to them)
+    h32 = to_np(h32)
+    e_fx = abs(h32[:, 0].mean() - ho[:, 0].mean()) / abs(ho[:, 0].mean())
+    e_h = abs(h32[:, 3].mean() - ho[:, 3].mean()) / abs(ho[:, 3].mean())
+    print(f"fp32 vs fp64 after 100 steps: u {e_u:.2e}, theta-1 {e_t:.2e}, "
+          f"mean Fx {e_fx:.2e}, mean H {e_h:.2e}")
+    assert e_u < 1e-4 and e_t < 1e-3
+    assert e_fx < 1e-4 and e_h < 1e-4
+
+
+def test_fp32_form_3d_runs_close_to_fp64(cuda):
+    c = inputs.scaled("cfg3", (48, 40, 40), ns=400)
+    g32, g64 = make_gpu(c, precision="fp32"), make_gpu(c, precision="fp64")
+    h32, _ = g32.step(10)
+    h64, _ = g64.step(10)
+    r32, m32, _, _ = g32.get_state()
+    r64, m64, _, _ = g64.get_state()
+    assert rel_l2(to_np(m32), to_np(m64)) < 1e-5
+    assert rel_l2(to_np(h32)[:, [0, 3]], to_np(h64)[:, [0, 3]]) < 1e-4

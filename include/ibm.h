@@ -200,6 +200,30 @@ ibm_status ibm_markers_in_use(const ibm_ctx *ctx, int32_t *n_used, int32_t *ids,
  * (double [n_used][2 dim + 3]). Synchronises. */
 ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
 
+/* Discrete adjoint of one step recorded by the last ibm_step(..., IBM_RECORD, ...)
+ * call (a hand-written reverse of the whole step: correction, pressure CG (the
+ * operator is symmetric, so its adjoint is one more CG solve), set-up, forcing and
+ * spreading (spreading transposes to interpolation and back), predictor). Not in
+ * the paper: it serves gradients of time-averaged Nusselt number and drag with
+ * respect to the wall temperatures. Requirements: FP64 context, linear
+ * convection, markers at rest (IBM_E_ARG otherwise); IBM_E_STATE if tape_index is
+ * not a recorded step.
+ *   tape_index     0 = first step of the recording call
+ *   state_bar_in   device double: cotangent of the state after the step, in the
+ *                  ibm_set_state layout (rho [N], mom [dim][N], E [N], F [sum NF])
+ *   state_bar_out  device double, same layout: cotangent of the state before the
+ *                  step (written; must not overlap state_bar_in)
+ *   out_bar        host double [4]: cotangents of the step's outputs Fx, Fy, Fz, H
+ *                  (the history row of ibm_step)
+ *   Tw_bar         device double [n candidate markers]: the step's contribution to
+ *                  the gradient with respect to T_w is added (+=)
+ * The context's current state is not changed; the step's own buffers are. */
+ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *state_bar_in,
+                            double *state_bar_out, const double *out_bar, double *Tw_bar);
+
+/* Number of steps on the tape (recorded by the last IBM_RECORD call). */
+int32_t ibm_tape_length(const ibm_ctx *ctx);
+
 /* Kernel timing for measurement. While enabled, ibm_step records HIP events on
  * the context's stream around the launches of each kernel class and, after each
  * step, adds their durations to per-class totals (CG launches after convergence

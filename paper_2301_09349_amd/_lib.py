@@ -83,6 +83,8 @@ SIGNATURES = {
     "ibm_wall_fluxes": (ctypes.c_int, [_P, _P, _P, _D]),
     "ibm_markers_in_use": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P, _P]),
     "ibm_get_field": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "ibm_adjoint_step": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _D, _P]),
+    "ibm_tape_length": (ctypes.c_int32, [_P]),
     "ibm_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ibm_profile_read": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
 }

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libibm_hip.so")
-SOURCES = ["ibm_grid.hip", "ibm_markers.hip", "ibm_api.hip"]
+SOURCES = ["ibm_grid.hip", "ibm_markers.hip", "ibm_adjoint.hip", "ibm_api.hip"]
 HEADERS = ["ibm_internal.h", "ibm_launch.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

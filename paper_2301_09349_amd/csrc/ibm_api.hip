@@ -90,6 +90,7 @@ struct ibm_ctx {
   double motion_amp = 0.0, motion_freq = 0.0;
   int cg_hint = 8;
   int tape_cap = 0;
+  int tape_len = 0;  // steps recorded by the last IBM_RECORD call
   int tag = 0;  // step tag, one per step launched
   std::string err;
   CgScal cgh;
@@ -238,7 +239,6 @@ struct Carver {
 // Lays the buffers out in the workspace (or only measures when base == NULL).
 size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_steps, char *base,
             Bufs &B, int &npairs_pad) {
-  (void)tape_steps;
   Carver C{base};
   const size_t w = (d.precision == IBM_FP32) ? 4 : 8;
   const int dim = d.dim;
@@ -317,6 +317,30 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   B.mforce = C.take<double>(3 * nc);
   B.mheat = C.take<double>(nc);
   B.totals = C.take<double>(8);
+  // tape and adjoint work buffers (FP64 contexts with a tape only)
+  B.tape = nullptr;
+  B.tape_stride = 0;
+  B.pprim = B.pbar = B.fo = B.co = B.rs_bar = B.Es_bar = B.fbar = B.tbar = B.lam = B.rhs = nullptr;
+  B.mkbar = nullptr;
+  for (int q = 0; q < 3; ++q) B.ms_bar[q] = nullptr;
+  if (tape_steps > 0) {
+    const size_t NFt = (size_t)(g.NF[0] + g.NF[1] + g.NF[2]);
+    const size_t Np = (size_t)ibmk::padded_cells(g);
+    B.tape_stride = ((size_t)(dim + 3) * N + NFt + 31) & ~size_t(31);
+    B.tape = C.take<double>(B.tape_stride * (size_t)tape_steps);
+    B.pprim = C.take<double>((size_t)(dim + 4) * Np);
+    B.pbar = C.take<double>((size_t)(dim + 3) * Np);
+    B.fo = C.take<double>((size_t)(4 * dim + 2) * NFt);
+    B.co = C.take<double>((size_t)(dim * dim + dim + 2) * N);
+    B.rs_bar = C.take<double>(N);
+    B.Es_bar = C.take<double>(N);
+    for (int q = 0; q < dim; ++q) B.ms_bar[q] = C.take<double>(N);
+    B.fbar = C.take<double>(NFt);
+    B.tbar = C.take<double>(N);
+    B.lam = C.take<double>(N);
+    B.rhs = C.take<double>(N);
+    B.mkbar = C.take<double>((size_t)(2 * dim + 3) * nc);
+  }
   return (C.off + 255) & ~size_t(255);
 }
 
@@ -392,6 +416,66 @@ ibm_status marker_flags(ibm_ctx *ctx, const int *f) {
   return IBM_OK;
 }
 
+// Offset of the pressure solution in a tape record (after rho, mom, E, F).
+size_t tape_x_offset(const GridK &g) {
+  return (size_t)(g.dim + 2) * (size_t)g.N + (size_t)(g.NF[0] + g.NF[1] + g.NF[2]);
+}
+
+// Copies state slot `slot` to tape record `rec` (to_tape) or back.
+ibm_status tape_copy(ibm_ctx *ctx, int rec, int slot, bool to_tape) {
+  const GridK &g = ctx->L.g;
+  Bufs &B = ctx->B;
+  hipStream_t st = ctx->L.st;
+  double *base = B.tape + B.tape_stride * (size_t)rec;
+  const size_t N = (size_t)g.N;
+  void *parts[9];
+  size_t sizes[9];
+  int np = 0;
+  parts[np] = B.rho[slot];
+  sizes[np++] = N;
+  for (int q = 0; q < g.dim; ++q) {
+    parts[np] = B.mom[slot][q];
+    sizes[np++] = N;
+  }
+  parts[np] = B.E[slot];
+  sizes[np++] = N;
+  for (int q = 0; q < g.dim; ++q) {
+    parts[np] = B.F[slot][q];
+    sizes[np++] = (size_t)g.NF[q];
+  }
+  size_t off = 0;
+  for (int i = 0; i < np; ++i) {
+    void *dst = to_tape ? (void *)(base + off) : parts[i];
+    const void *src = to_tape ? (const void *)parts[i] : (const void *)(base + off);
+    HIPCHECK(ctx, hipMemcpyAsync(dst, src, sizes[i] * sizeof(double), hipMemcpyDeviceToDevice, st));
+    off += sizes[i];
+  }
+  return IBM_OK;
+}
+
+// Runs a pressure-type CG whose set-up has been queued (tag posted by its
+// iterations) to completion with the buffers of `Bc`; returns its iterations.
+ibm_status run_cg_to_end(ibm_ctx *ctx, const Bufs &Bc, int tag, int *iters) {
+  const Launch &L = ctx->L;
+  int launched = 0;
+  const int first = std::max(1, ctx->cg_hint + 1);
+  for (int c = 0; c < first; ++c) ibmk::run_cg_iteration(L, Bc, launched++);
+  HIPCHECK(ctx, hipGetLastError());
+  uint64_t w = 0;
+  for (;;) {
+    ibm_status r = wait_progress(ctx, tag, launched - 1, &w);
+    if (r) return r;
+    if (w & 0xF) break;
+    for (int c = 0; c < 4; ++c) ibmk::run_cg_iteration(L, Bc, launched++);
+    HIPCHECK(ctx, hipGetLastError());
+  }
+  const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
+  *iters = (int)((w >> 8) & 0xFFFFFF);
+  if (err) return fail(ctx, IBM_E_NONFINITE, "adjoint pressure solve stopped on an error flag");
+  if (dstate != 1) return fail(ctx, IBM_E_NOT_CONVERGED, "adjoint pressure CG reached cg_maxit");
+  return IBM_OK;
+}
+
 }  // namespace
 
 // ======================================================================== ABI
@@ -399,6 +483,7 @@ extern "C" {
 
 size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32_t tape_steps) {
   if (check_desc(desc) || max_markers < 0 || tape_steps < 0) return 0;
+  if (tape_steps > 0 && desc->precision != IBM_FP64) return 0;
   GridK g = make_grid(*desc);
   Bufs B;
   int np;
@@ -411,6 +496,7 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   *out = nullptr;
   if (check_desc(desc)) return IBM_E_ARG;
   if (tape_steps < 0) return IBM_E_ARG;
+  if (tape_steps > 0 && desc->precision != IBM_FP64) return IBM_E_ARG;
   if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) return IBM_E_ARG;
   const int nslot = desc->dim == 3 ? 27 : 9;
   if ((int64_t)desc->max_markers * nslot >= ((int64_t)1 << ibmk::kPairBits)) return IBM_E_SIZE;
@@ -565,6 +651,7 @@ ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const doubl
   hipStream_t st = ctx->L.st;
   Bufs &B = ctx->B;
   ctx->nc = 0;
+  ctx->tape_len = 0;
   if (n == 0) {
     HIPCHECK(ctx, hipMemsetAsync(B.mcount, 0, 8 * sizeof(int), st));
     HIPCHECK(ctx, hipStreamSynchronize(st));
@@ -609,6 +696,7 @@ ibm_status ibm_set_motion(ibm_ctx *ctx, int32_t axis, double amplitude, double f
   if (!std::isfinite(amplitude) || !std::isfinite(frequency))
     return fail(ctx, IBM_E_ARG, "set_motion: non-finite parameter");
   ctx->motion_axis = axis < 0 ? -1 : axis;
+  ctx->tape_len = 0;
   ctx->motion_amp = amplitude;
   ctx->motion_freq = frequency;
   if (ctx->nc > 0) {
@@ -628,6 +716,7 @@ ibm_status ibm_set_wall_temperature(ibm_ctx *ctx, const double *T_w) {
   if (!ctx) return IBM_E_ARG;
   if (ctx->nc == 0) return fail(ctx, IBM_E_STATE, "set_wall_temperature: no markers");
   if (!T_w) return fail(ctx, IBM_E_ARG, "set_wall_temperature: NULL");
+  ctx->tape_len = 0;
   hipStream_t st = ctx->L.st;
   HIPCHECK(ctx, hipMemcpyAsync(ctx->B.cTw, T_w, ctx->nc * sizeof(double), hipMemcpyDeviceToDevice,
                                st));
@@ -649,8 +738,10 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   if (!ctx) return IBM_E_ARG;
   if (n_steps < 0) return fail(ctx, IBM_E_ARG, "step: n_steps < 0");
   if (flags & ~IBM_RECORD) return fail(ctx, IBM_E_ARG, "step: unknown flag");
-  if ((flags & IBM_RECORD) && ctx->tape_cap == 0)
-    return fail(ctx, IBM_E_SIZE, "step: no tape capacity for IBM_RECORD");
+  const bool record = (flags & IBM_RECORD) != 0;
+  if (record && n_steps > ctx->tape_cap)
+    return fail(ctx, IBM_E_SIZE, "step: IBM_RECORD of more steps than the tape holds");
+  if (record) ctx->tape_len = 0;
   const Launch &L = ctx->L;
   Bufs &B = ctx->B;
   hipStream_t st = L.st;
@@ -695,6 +786,10 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
       if (ms) return ms;
     }
+    if (record) {
+      ibm_status ts = tape_copy(ctx, s, ctx->cur, true);
+      if (ts) return ts;
+    }
     timed(IBM_PROF_PREDICTOR, 0, [&] { ibmk::run_predictor(L, B, ctx->cur); });
     double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
     if (ctx->nc > 0) {
@@ -733,6 +828,10 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE
                                                                          : IBM_E_NOT_CONVERGED;
       break;
+    }
+    if (record) {
+      HIPCHECK(ctx, hipMemcpyAsync(B.tape + B.tape_stride * (size_t)s + tape_x_offset(L.g), B.x,
+                                   (size_t)L.g.N * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
     ctx->cur ^= 1;
     ctx->step += 1;
@@ -782,6 +881,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     }
     info->mass = m;
   }
+  if (record) ctx->tape_len = (int)done;
   return rc;
 }
 
@@ -877,6 +977,63 @@ ibm_status ibm_get_field(const ibm_ctx *cctx, int32_t which, void *dst) {
     default:
       return fail(ctx, IBM_E_ARG, "get_field: unknown field");
   }
+  HIPCHECK(ctx, hipStreamSynchronize(st));
+  return IBM_OK;
+}
+
+int32_t ibm_tape_length(const ibm_ctx *ctx) { return ctx ? ctx->tape_len : 0; }
+
+ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *state_bar_in,
+                            double *state_bar_out, const double *out_bar, double *Tw_bar) {
+  if (!ctx) return IBM_E_ARG;
+  if (ctx->L.prec != 0) return fail(ctx, IBM_E_ARG, "adjoint_step: needs an FP64 context");
+  if (ctx->L.g.conv != ibmk::CONV_LINEAR)
+    return fail(ctx, IBM_E_ARG, "adjoint_step: needs linear convection");
+  if (ctx->motion_axis >= 0) return fail(ctx, IBM_E_ARG, "adjoint_step: markers must be at rest");
+  if (!state_bar_in || !state_bar_out) return fail(ctx, IBM_E_ARG, "adjoint_step: NULL cotangent");
+  if (state_bar_in == state_bar_out)
+    return fail(ctx, IBM_E_ARG, "adjoint_step: state_bar_in and state_bar_out must differ");
+  if (ctx->nc > 0 && (!out_bar || !Tw_bar))
+    return fail(ctx, IBM_E_ARG, "adjoint_step: out_bar and Tw_bar are needed with markers");
+  if (tape_index < 0 || tape_index >= ctx->tape_len)
+    return fail(ctx, IBM_E_STATE, "adjoint_step: tape_index is not a recorded step");
+  const Launch &L = ctx->L;
+  Bufs &B = ctx->B;
+  hipStream_t st = L.st;
+  const int slot = ctx->cur ^ 1;
+  const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
+  const double *ob = out_bar ? out_bar : zero4;
+  // forward pieces of the step, recomputed from its record
+  HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
+  {
+    ibm_status r = tape_copy(ctx, tape_index, slot, false);
+    if (r) return r;
+  }
+  ibmk::run_predictor(L, B, slot);
+  if (ctx->nc > 0) {
+    ibmk::run_interp_force(L, B, nullptr);
+    ibmk::run_spread(L, B);
+  }
+  ibmk::run_setup(L, B, slot, ++ctx->tag);
+  HIPCHECK(ctx, hipMemcpyAsync(B.x,
+                               B.tape + B.tape_stride * (size_t)tape_index + tape_x_offset(L.g),
+                               (size_t)L.g.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // reverse: correction, pressure solve, set-up, forcing and spreading, predictor
+  ibmk::run_adj_correction(L, B, slot, state_bar_in, state_bar_out);
+  const int tag = ++ctx->tag;
+  ibmk::run_adj_cg_init(L, B, tag);
+  HIPCHECK(ctx, hipGetLastError());
+  Bufs Ba = B;
+  Ba.x = B.lam;
+  int iters = 0;
+  {
+    ibm_status r = run_cg_to_end(ctx, Ba, tag, &iters);
+    if (r) return r;
+  }
+  ibmk::run_adj_setup(L, B, slot, state_bar_in, state_bar_out);
+  if (ctx->nc > 0) ibmk::run_adj_markers(L, B, ob, Tw_bar);
+  ibmk::run_adj_predictor(L, B, slot, state_bar_out);
+  HIPCHECK(ctx, hipGetLastError());
   HIPCHECK(ctx, hipStreamSynchronize(st));
   return IBM_OK;
 }

@@ -20,6 +20,7 @@ constexpr int kMaxBlocks = 1024;   // blocks of a grid kernel (4 per CU on 256 C
 constexpr int kRedThreads = 1024;  // threads of the single-block marker kernels
 constexpr int kPairBits = 20;      // (cell << 20) | pair id in the sorted pair keys
 constexpr int kMaxNbr = 192;       // neighbours per marker row of the Gram matrix
+constexpr int kFaceOut = 14;       // per-face values of the reverse predictor (4 dim + 2)
 
 // Grid, physics and time-step constants, passed by value to every grid kernel.
 struct GridK {

@@ -49,6 +49,21 @@ struct Bufs {
   double *mforce; // [ns][3]
   double *mheat;  // [ns]
   double *totals; // [4]
+
+  // tape (IBM_RECORD): per recorded step the state it started from and its
+  // pressure solution, FP64: rho, mom[dim], E [N]; F [sum NF]; x [N]
+  double *tape;
+  size_t tape_stride;  // doubles per recorded step
+  // adjoint work buffers (FP64)
+  double *pprim;        // padded primitives [(dim+4)][Npad]: rho, u[dim], theta, mu, p
+  double *pbar;         // padded primitive cotangents [(dim+3)][Npad]: rho, u[dim], theta, p
+  double *fo;           // per-face reverse outputs [kFaceOut][sum NF]
+  double *co;           // per-cell reverse outputs [(dim^2 + dim + 2)][N]
+  double *rs_bar, *ms_bar[3], *Es_bar;  // cotangents of rho*, m* (m**), E* (E**)
+  double *fbar;         // [sum NF] cotangent of the corrected face flux
+  double *tbar;         // [N] cotangent of theta**
+  double *lam, *rhs;    // [N] adjoint pressure and its right-hand side
+  double *mkbar;        // [nc][2 dim + 3] marker cotangents
 };
 
 struct Launch {
@@ -75,6 +90,19 @@ void run_cg_half(const Launch &L, const Bufs &B, int it, int part);  // part 0: 
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag);
 void run_mass(const Launch &L, const Bufs &B);
 int64_t cell_blocks(const GridK &g);
+
+// adjoint kernels (ibm_adjoint.hip); FP64 contexts only. `st` is the state the step
+// started from (tape copy loaded into a state slot), `sb_in`/`sb_out` the state
+// cotangents after/before the step (ibm_set_state layout).
+int64_t padded_cells(const GridK &g);
+void run_adj_correction(const Launch &L, const Bufs &B, int slot, const double *sb_in,
+                        double *sb_out);
+// the adjoint pressure solve then runs run_cg_iteration with x -> lam
+void run_adj_cg_init(const Launch &L, const Bufs &B, int tag);
+void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in, double *sb_out);
+// out_bar: host double[4], the cotangents of the step's Fx, Fy, Fz, H
+void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, double *Tw_bar);
+void run_adj_predictor(const Launch &L, const Bufs &B, int slot, double *sb_out);
 
 // marker kernels (ibm_markers.hip)
 void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,

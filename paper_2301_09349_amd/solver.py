@@ -203,6 +203,26 @@ class IBMSolver:
         self.stream.synchronize()
         return force[:nu], heat[:nu], np.array(tot[:])
 
+    # ---------------------------------------------------------------- adjoint
+    @property
+    def state_size(self) -> int:
+        """Entries of a state (or state cotangent) in the ibm_set_state layout."""
+        return (2 + self.dim) * self.N + sum(self.NF)
+
+    def tape_length(self) -> int:
+        return int(self.lib.ibm_tape_length(self.ctx))
+
+    def adjoint_step(self, tape_index: int, state_bar_in, state_bar_out, out_bar=None,
+                     Tw_bar=None):
+        """Reverse of recorded step ``tape_index``: writes the cotangent of the state
+        before the step into ``state_bar_out`` (device float64 [state_size]) from that
+        after it (``state_bar_in``) and the cotangents ``out_bar`` of the step's
+        (Fx, Fy, Fz, H); adds the step's part of dJ/dT_w to ``Tw_bar``."""
+        ob = (ctypes.c_double * 4)(*([0.0] * 4 if out_bar is None else [float(v) for v in out_bar]))
+        st = self.lib.ibm_adjoint_step(self.ctx, int(tape_index), _ptr(state_bar_in),
+                                       _ptr(state_bar_out), ob, _ptr(Tw_bar))
+        L.check(st, self.ctx, "ibm_adjoint_step")
+
     def profile(self, enable: bool):
         L.check(self.lib.ibm_profile(self.ctx, 1 if enable else 0), self.ctx, "ibm_profile")
 

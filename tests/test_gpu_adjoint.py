@@ -1,0 +1,189 @@
+"""GPU tests of the hand-written discrete adjoint (ibm_adjoint_step) through the C
+ABI: one step against central finite differences of the GPU's own forward step,
+per input block of the state (so that a wrong transpose names its block), and the
+checkpointed gradient with respect to the wall temperatures against the FP64
+oracle's tangent-linear (dual-number) run and against central finite differences.
+
+The adjoint needs linear convection; every case here sets it."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2301_09349_amd import inputs
+from paper_2301_09349_amd.adjoint import wall_temperature_gradient, _state_vector, \
+    _set_state_vector
+from helpers import make_gpu, make_oracle, to_np
+
+pytestmark = pytest.mark.gpu
+
+LIN = inputs.CONV_LINEAR
+
+
+def _blocks(s):
+    N, dim = s.N, s.dim
+    b = {"rho": (0, N)}
+    for q in range(dim):
+        b[f"mom{q}"] = ((1 + q) * N, (2 + q) * N)
+    b["E"] = ((1 + dim) * N, (2 + dim) * N)
+    off = (2 + dim) * N
+    for d in range(dim):
+        b[f"F{d}"] = (off, off + s.NF[d])
+        off += s.NF[d]
+    return b
+
+
+def _J(s, x, step0, w, ob):
+    _set_state_vector(s, x, step0)
+    h, _ = s.step(1)
+    y = _state_vector(s)
+    return float(torch.dot(w, y)) + float(np.dot(ob, to_np(h[0])))
+
+
+def _single_step_case(c, amplitude, warm, seed, h=1e-5, with_w=True):
+    s = make_gpu(c, amplitude=amplitude, tape_steps=1)
+    if warm:
+        s.step(warm)
+    x0 = _state_vector(s)
+    _, info = s.step(0)
+    step0 = int(info["step"])
+    gen = np.random.default_rng(seed)
+    n = s.state_size
+    w = torch.as_tensor(gen.standard_normal(n) if with_w else np.zeros(n), device=s.device)
+    ob = gen.standard_normal(4) * 1e-2
+    # adjoint of the step from x0
+    _set_state_vector(s, x0, step0)
+    s.step(1, hist=False, record=True)
+    sb = torch.empty_like(w)
+    Twb = torch.zeros(max(s.nc, 1), dtype=torch.float64, device=s.device)
+    s.adjoint_step(0, w, sb, ob, Twb)
+    out = {}
+    for name, (a, b) in _blocks(s).items():
+        v = torch.zeros(n, dtype=torch.float64, device=s.device)
+        v[a:b] = torch.as_tensor(gen.standard_normal(b - a), device=s.device)
+        ad = float(torch.dot(sb, v))
+        ident = float(torch.dot(w, v)) if (name == "rho" or name.startswith("mom")) else 0.0
+        fd = (_J(s, x0 + h * v, step0, w, ob) - _J(s, x0 - h * v, step0, w, ob)) / (2 * h)
+        out[name] = (fd, ad, ident)
+    return out
+
+
+def _check(out, tol):
+    bad = {}
+    for name, (fd, ad, ident) in out.items():
+        scale = max(abs(ad - ident), 1e-300)
+        rel = abs(fd - ad) / scale
+        if not rel < tol:
+            bad[name] = (fd, ad, ident, rel)
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("with_w", [True, False])
+def test_adjoint_step_channel_with_body(cuda, with_w):
+    # inflow / outflow / slip, ragged grid, markers
+    c = inputs.scaled("cfg1", (70, 52), ns=60, convection=LIN, Re=20.0)
+    _check(_single_step_case(c, 1e-2, 3, 11, with_w=with_w), 1e-6)
+
+
+def test_adjoint_step_periodic_no_body(cuda):
+    c = inputs.scaled("cfg1", (40, 30), ns=0, convection=LIN,
+                      bc=[[inputs.PERIODIC] * 2, [inputs.PERIODIC] * 2])
+    _check(_single_step_case(c, 5e-2, 2, 12), 1e-6)
+
+
+def test_adjoint_step_constant_viscosity(cuda):
+    c = inputs.scaled("cfg1", (48, 40), ns=40, convection=LIN,
+                      viscosity_law=inputs.MU_CONSTANT)
+    _check(_single_step_case(c, 1e-2, 2, 13), 1e-6)
+
+
+def test_adjoint_step_sphere_3d(cuda):
+    c = inputs.scaled("cfg3", (26, 20, 18), ns=120, convection=LIN, Re=50.0)
+    _check(_single_step_case(c, 1e-2, 2, 14), 1e-6)
+
+
+def _tw_case():
+    # the gradient workload's physics on a small grid
+    return inputs.scaled("cfg5", (96, 96), ns=60, convection=LIN)
+
+
+def test_tw_gradient_matches_oracle_tangent_linear(cuda):
+    c = _tw_case()
+    nsteps, ck = 12, 5
+    gen = np.random.default_rng(21)
+    ob = gen.standard_normal((nsteps, 4))
+    s = make_gpu(c, tape_steps=ck)
+    hist, Twb, _ = wall_temperature_gradient(s, nsteps, ob, checkpoint=ck)
+    Twb = to_np(Twb)
+    o = make_oracle(c)
+    for j in range(3):
+        d = inputs.normal(1000 + j, c["ns"])
+        d = d / np.linalg.norm(d)
+        hv, hd = o.tangent_linear(nsteps, d)
+        tl = float(np.sum(ob * hd))
+        ad = float(Twb @ d)
+        assert abs(ad - tl) <= 1e-10 * abs(tl), (j, ad, tl)
+        # the forward history agrees with the oracle's values as well
+        assert np.max(np.abs(to_np(hist) - hv)) <= 1e-10 * np.max(np.abs(hv))
+
+
+def test_tw_gradient_matches_central_differences(cuda):
+    c = _tw_case()
+    nsteps, ck = 10, 4
+    gen = np.random.default_rng(22)
+    ob = gen.standard_normal((nsteps, 4))
+    s = make_gpu(c, tape_steps=ck)
+    x0 = _state_vector(s)
+    _, Twb, _ = wall_temperature_gradient(s, nsteps, ob, checkpoint=ck)
+    Twb = to_np(Twb)
+    Tw0 = np.full(c["ns"], float(c["Tw"]))
+    h = 1e-6
+    for j in range(3):
+        d = inputs.normal(1000 + j, c["ns"])
+        d = d / np.linalg.norm(d)
+        Js = []
+        for sgn in (1.0, -1.0):
+            _set_state_vector(s, x0, 0)
+            s.set_wall_temperature(Tw0 + sgn * h * d)
+            hh, _ = s.step(nsteps)
+            Js.append(float(np.sum(ob * to_np(hh))))
+        s.set_wall_temperature(Tw0)
+        fd = (Js[0] - Js[1]) / (2 * h)
+        ad = float(Twb @ d)
+        assert abs(ad - fd) <= 1e-5 * abs(ad), (j, ad, fd)
+
+
+def test_gradient_rollout_leaves_the_forward_state(cuda):
+    c = _tw_case()
+    s1 = make_gpu(c, tape_steps=4)
+    s2 = make_gpu(c)
+    wall_temperature_gradient(s1, 9, np.ones(4), checkpoint=4)
+    s2.step(9)
+    a, b = _state_vector(s1), _state_vector(s2)
+    assert torch.equal(a, b)
+
+
+def test_adjoint_rejects_bad_calls(cuda):
+    from paper_2301_09349_amd._lib import IBMError
+
+    c = inputs.scaled("cfg1", (40, 32), ns=20, convection=LIN)
+    s = make_gpu(c, tape_steps=2)
+    sb = torch.zeros(s.state_size, dtype=torch.float64, device=s.device)
+    sb2 = torch.zeros_like(sb)
+    Twb = torch.zeros(s.nc, dtype=torch.float64, device=s.device)
+    with pytest.raises(IBMError):  # nothing recorded
+        s.adjoint_step(0, sb, sb2, np.zeros(4), Twb)
+    with pytest.raises(IBMError):  # more steps than the tape holds
+        s.step(3, record=True)
+    s.step(2, record=True)
+    assert s.tape_length() == 2
+    with pytest.raises(IBMError):
+        s.adjoint_step(2, sb, sb2, np.zeros(4), Twb)
+    with pytest.raises(IBMError):  # in place
+        s.adjoint_step(0, sb, sb, np.zeros(4), Twb)
+    s.adjoint_step(1, sb, sb2, np.zeros(4), Twb)
+    # VANLEER contexts have no adjoint
+    cv = inputs.scaled("cfg1", (40, 32), ns=20)
+    sv = make_gpu(cv, tape_steps=1)
+    sv.step(1, record=True)
+    with pytest.raises(IBMError):
+        sv.adjoint_step(0, sb, sb2, np.zeros(4), Twb)

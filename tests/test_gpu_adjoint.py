@@ -10,8 +10,8 @@ import pytest
 import torch
 
 from paper_2301_09349_amd import inputs
-from paper_2301_09349_amd.adjoint import wall_temperature_gradient, _state_vector, \
-    _set_state_vector
+from paper_2301_09349_amd.adjoint import IBMRollout, drag_scale, nusselt_scale, \
+    wall_temperature_gradient, _state_vector, _set_state_vector
 from helpers import make_gpu, make_oracle, to_np
 
 pytestmark = pytest.mark.gpu
@@ -160,6 +160,71 @@ def test_gradient_rollout_leaves_the_forward_state(cuda):
     s2.step(9)
     a, b = _state_vector(s1), _state_vector(s2)
     assert torch.equal(a, b)
+
+
+def test_autograd_function_matches_the_driver(cuda):
+    c = _tw_case()
+    n, ck = 9, 4
+    s = make_gpu(c, tape_steps=ck)
+    Tw = torch.full((c["ns"],), float(c["Tw"]), dtype=torch.float64, device=s.device,
+                    requires_grad=True)
+    Jn, Jc = IBMRollout.apply(Tw, s, n, ck)
+    (0.7 * Jn + 0.3 * Jc).backward()
+    s2 = make_gpu(c, tape_steps=ck)
+    ob = np.zeros((n, 4))
+    ob[:, 3] = 0.7 * nusselt_scale(c) / n
+    ob[:, 0] = 0.3 * drag_scale(c) / n
+    hist, Twb, _ = wall_temperature_gradient(s2, n, ob, checkpoint=ck)
+    assert float(Jn.detach()) == pytest.approx(nusselt_scale(c) * float(hist[:, 3].mean()),
+                                               rel=1e-14)
+    assert float(Jc.detach()) == pytest.approx(drag_scale(c) * float(hist[:, 0].mean()),
+                                               rel=1e-14)
+    assert torch.allclose(Tw.grad, Twb, rtol=1e-13, atol=0.0)
+    assert float(Jn.detach()) > 0.0  # the wall is hotter than the stream
+
+
+def test_cfg5_nusselt_gradient_full_size(cuda):
+    """The gradient workload at full size: 512^2, 200 markers, T_w = 1.3, time-averaged
+    Nusselt number over 500 steps, checkpoints every 50; central differences with step
+    1e-6 on 10 seeded unit directions, and the oracle's tangent-linear over the first
+    10 steps."""
+    c = inputs.case("cfg5", convection=LIN)
+    n, ck = int(c["steps"]), int(c["checkpoint"])
+    s = make_gpu(c, tape_steps=ck)
+    x0 = _state_vector(s)
+    Tw0 = torch.full((c["ns"],), float(c["Tw"]), dtype=torch.float64, device=s.device)
+    Tw = Tw0.clone().requires_grad_(True)
+    Jn, _ = IBMRollout.apply(Tw, s, n, ck)
+    Jn.backward()
+    g = to_np(Tw.grad)
+    ku = nusselt_scale(c)
+    h = 1e-6
+    for j in range(10):
+        d = inputs.normal(1000 + j, c["ns"])
+        d = d / np.linalg.norm(d)
+        Js = []
+        for sgn in (1.0, -1.0):
+            _set_state_vector(s, x0, 0)
+            s.set_wall_temperature(Tw0 + sgn * h * torch.as_tensor(d, device=s.device))
+            hh, _ = s.step(n)
+            Js.append(ku * float(hh[:, 3].mean()))
+        fd = (Js[0] - Js[1]) / (2 * h)
+        ad = float(g @ d)
+        assert abs(ad - fd) <= 1e-5 * abs(ad), (j, ad, fd)
+    # oracle tangent-linear over the first steps
+    m = 10
+    _set_state_vector(s, x0, 0)
+    s.set_wall_temperature(Tw0)
+    ob = np.zeros((m, 4))
+    ob[:, 3] = 1.0
+    _, Twb, _ = wall_temperature_gradient(s, m, ob, checkpoint=5)
+    o = make_oracle(c)
+    d = inputs.normal(1000, c["ns"])
+    d = d / np.linalg.norm(d)
+    _, hd = o.tangent_linear(m, d)
+    tl = float(np.sum(hd[:, 3]))
+    ad = float(to_np(Twb) @ d)
+    assert abs(ad - tl) <= 1e-10 * abs(tl), (ad, tl)
 
 
 def test_adjoint_rejects_bad_calls(cuda):

@@ -5,16 +5,24 @@ forcing / spreading, pressure set-up, pressure CG to convergence, correction -- 
 the 2D heated-cylinder workload (1024^2 cells over [-4,12]x[-8,8], 400 candidate
 markers, Re 100, Ma 0.2, Tw/Tinf 0.8), with all inputs resident in HBM.
 
-Prints ONE JSON line: Mcell-steps/s, per-kernel roofline of the dominant kernel
-(HIP events on the library's stream over the timed region), and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+Prints ONE JSON line: FP64 Mcell-steps/s (``value``), the FP32 form's throughput and
+its error against the FP64 run, the adjoint/forward time ratio on the gradient
+workload (512^2 cylinder, linear convection, 200 markers, checkpoints every 50),
+the roofline of the dominant kernel (HIP events on the library's stream over the
+timed region), and the FP64 CPU oracle timed on a bounded sample.
+
+``--summarize DIR`` (no GPU) turns rocprofv3 output of this script into the text
+summaries kept under profiles/.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+CALIB_ELEMS = 1 << 26  # float64 elements of the copy-kernel calibration (512 MiB)
 
 
 def log(*a):
@@ -41,6 +50,32 @@ def kernel_words(cls: str, dim: int) -> int:
     }[cls]
 
 
+# kernel symbol prefix -> kernel class of the library's event timing
+KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_mcg_a", "cg_a"),
+                ("k_mcg_b", "cg_b"), ("k_cg_a", "cg_a"), ("k_cg_b", "cg_b"),
+                ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
+                ("k_totals", "markers")]
+
+
+def kernel_class(name: str):
+    """Class of a kernel from its demangled name (``void ibmk::k_setup2<2, double>(...)``)."""
+    m = re.search(r"ibmk::(\w+)", name)
+    if not m:
+        return None
+    sym = m.group(1)
+    for key, cls in KERNEL_CLASS:
+        if sym.startswith(key):
+            return cls
+    return None
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("ibm_grid.hip", "ibm_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2301_09349_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_entry(kernel: str, precision: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, when it was
     taken on the current kernel source; None otherwise."""
@@ -51,10 +86,8 @@ def traffic_entry(kernel: str, precision: str):
         rec = json.load(open(path))
     except Exception:
         return None
-    src = os.path.join(ROOT, "paper_2301_09349_amd", "csrc", "ibm_grid.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     ent = rec.get(precision, {}).get(kernel)
-    if not ent or ent.get("source_sha") != h:
+    if not ent or rec.get("source_sha") != source_sha():
         return None
     return ent.get("bytes_per_launch")
 
@@ -78,36 +111,15 @@ def cpu_baseline(case, steps: int):
         ncell *= v
     return {"value": ncell * steps / dt / 1e6, "unit": "Mcell-steps/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{steps} steps of the same 1024^2 workload after 1 warm-up step "
+            "sample": f"{steps} steps of the same workload after 1 warm-up step "
                       f"({dt:.1f} s, single thread, -O2 FP64)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--workload", default="cfg2a")
-    ap.add_argument("--cpu-steps", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the step runs on one MI355X); "
-              "--gpus must be 1", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
+def make_solver(case, precision, tape_steps=0):
     from paper_2301_09349_amd import inputs
     from paper_2301_09349_amd.solver import IBMSolver
 
-    case = inputs.case(args.workload, cg_rtol=1e-10)
-    dim = case["dim"]
-    N = int(np.prod(case["n"][:dim]))
-    dev = torch.device("cuda:0")
-    s = IBMSolver(case, args.precision, max_markers=case["ns"])
+    s = IBMSolver(case, precision, max_markers=case["ns"], tape_steps=tape_steps)
     rho, u, th = inputs.initial_fields(case)
     s.init_primitive(rho, u, th)
     X, Ud, Tw, dA = inputs.markers(case)
@@ -115,70 +127,317 @@ def main():
     if case.get("motion"):
         m = case["motion"]
         s.set_motion(m["axis"], m["amp"], m["freq"])
-    hist = torch.zeros((max(args.steps, args.warmup, 1), 4), dtype=torch.float64, device=dev)
-    log(f"bench: {args.workload} {case['n']} {args.precision}, dt={s.dt:.4e}, "
-        f"warmup {args.warmup}, steps {args.steps}")
-    if args.warmup:
-        s.step(args.warmup, hist_out=hist)
+    return s
+
+
+def run_forward(case, precision, steps, warmup):
+    """Times `steps` steps after `warmup`; per-kernel-class times from the library's
+    HIP events on its stream over the same region."""
+    import numpy as np
+    import torch
+
+    dim = case["dim"]
+    N = int(np.prod(case["n"][:dim]))
+    s = make_solver(case, precision)
+    hist = torch.zeros((max(steps, warmup, 1), 4), dtype=torch.float64, device="cuda:0")
+    log(f"bench: {case['n']} {precision}, dt={s.dt:.4e}, warmup {warmup}, steps {steps}")
+    if warmup:
+        s.step(warmup, hist_out=hist)
     torch.cuda.synchronize()
     s.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, info = s.step(args.steps, hist_out=hist)
+    _, info = s.step(steps, hist_out=hist)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = s.profile_read()
     s.profile(False)
-    ids, _ = s.markers_in_use()
-    value = N * args.steps / elapsed / 1e6
-    ms_per_step = 1e3 * elapsed / args.steps
-    cg_per_step = info["cg_iters_total"] / max(args.steps, 1)
-    w = 4 if args.precision == "fp32" else 8
+    w = 4 if precision == "fp32" else 8
     per_kernel = {}
     for cls, (ms, n) in prof.items():
         if n == 0:
             continue
         ent = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n}
         if cls in ("predictor", "setup", "cg_a", "cg_b", "correct"):
-            # the CG vectors stay FP64 in both precision forms
-            ww = 8 if cls in ("cg_a", "cg_b") else w
-            b = kernel_words(cls, dim) * ww * N
+            b = kernel_words(cls, dim) * w * N
             ent["alg_bytes_per_launch"] = b
             ent["GBps"] = b / (ms / n * 1e-3) / 1e9
         per_kernel[cls] = ent
+    return {"solver": s, "N": N, "elapsed": elapsed, "info": info, "per_kernel": per_kernel,
+            "hist": hist[:steps].clone(), "value": N * steps / elapsed / 1e6,
+            "ms_per_step": 1e3 * elapsed / steps}
+
+
+def fp32_error(r64, r32):
+    """Error of the FP32 form against the FP64 run after the same steps: velocity and
+    temperature (relative L2; temperature as theta - 1), and the time-averaged drag
+    and heat (relative)."""
+    import torch
+
+    def prim(s):
+        r, m, e, _ = s.get_state()
+        r, m, e = r.double(), m.double(), e.double()
+        cv = 1.0 / (s.case["gamma"] * s.case["Ma"] ** 2) / (s.case["gamma"] - 1.0)
+        return m / r, e / (r * cv)
+
+    u64, t64 = prim(r64["solver"])
+    u32, t32 = prim(r32["solver"])
+    h64, h32 = r64["hist"], r32["hist"]
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    return {"u": rel(u32, u64), "theta_minus_1": rel(t32 - 1.0, t64 - 1.0),
+            "drag_mean": abs(float(h32[:, 0].mean() / h64[:, 0].mean()) - 1.0),
+            "heat_mean": abs(float(h32[:, 3].mean() / h64[:, 3].mean()) - 1.0)}
+
+
+def run_adjoint(steps: int, checkpoint: int, warmup: int):
+    """Adjoint/forward time ratio on the gradient workload: forward = `steps` plain
+    steps; backward = the checkpointed reverse pass over the same steps (segment
+    re-run with the tape on, then one adjoint step per step)."""
+    import numpy as np
+    import torch
+
+    from paper_2301_09349_amd import inputs
+    from paper_2301_09349_amd.adjoint import Rollout, nusselt_scale, _set_state_vector
+
+    case = inputs.case("cfg5", convection=inputs.CONV_LINEAR)
+    s = make_solver(case, "fp64", tape_steps=checkpoint)
+    if warmup:
+        s.step(warmup)
+    roll = Rollout(s, steps, checkpoint)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    roll.forward()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    ob = np.zeros((steps, 4))
+    ob[:, 3] = nusselt_scale(case) / steps
+    # the reverse pass of Rollout.reverse, with its two parts timed apart
+    sb = torch.zeros(s.state_size, dtype=torch.float64, device="cuda:0")
+    sb2 = torch.empty_like(sb)
+    Tw_bar = torch.zeros(s.nc, dtype=torch.float64, device="cuda:0")
+    t_rec = t_adj = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for start, k, ck, st_step in reversed(roll.segs):
+        ta = time.perf_counter()
+        _set_state_vector(s, ck, st_step)
+        s.step(k, hist=False, record=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for i in reversed(range(k)):
+            s.adjoint_step(i, sb, sb2, ob[start + i], Tw_bar)
+            sb, sb2 = sb2, sb
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        t_rec += tb - ta
+        t_adj += tc - tb
+    t_rev = time.perf_counter() - t0
+    gnorm = float(torch.linalg.norm(Tw_bar))
+    return {"workload": "2D heated cylinder, 512x512 over [-4,12]x[-8,8], 200 candidate "
+                        "markers, Re 100, Ma 0.2, Tw 1.3, linear convection, CG rtol 1e-13; "
+                        "gradient of the time-averaged Nusselt number w.r.t. T_w",
+            "steps": steps, "checkpoint": checkpoint,
+            "forward_ms_per_step": round(1e3 * t_fwd / steps, 4),
+            "backward_ms_per_step": round(1e3 * t_rev / steps, 4),
+            "recompute_ms_per_step": round(1e3 * t_rec / steps, 4),
+            "adjoint_step_ms": round(1e3 * t_adj / steps, 4),
+            "ratio": round(t_rev / t_fwd, 3),
+            "ratio_adjoint_step_only": round(t_adj / t_fwd, 3),
+            "grad_norm": gnorm}
+
+
+def calibrate_copy():
+    """A plain streaming kernel of known size for scaling the HBM counters: negation
+    of CALIB_ELEMS float64 values (8 B read + 8 B written each), three launches."""
+    import torch
+
+    a = torch.ones(CALIB_ELEMS, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
+# ------------------------------------------------------------ rocprofv3 summaries
+def _rows(pattern):
+    files = sorted(glob.glob(pattern, recursive=True))
+    if not files:
+        raise SystemExit(f"no file matches {pattern}")
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize(directory: str, label: str, command: str):
+    """Reads rocprofv3 output under `directory` (kernel_stats from a --kernel-trace
+    --stats run; counter_collection from --pmc FETCH_SIZE and --pmc WRITE_SIZE runs,
+    in subdirectories stats/, fetch/, write/) and writes profiles/kernels_<label>.md
+    and profiles/traffic_<label>.json."""
+    out_md = os.path.join(ROOT, "profiles", f"kernels_{label}.md")
+    lines = [f"# rocprofv3 summary: {label}", "", "Commands (from the repository root):", ""]
+    for c in command.split(";;"):
+        lines.append(f"    {c.strip()}")
+    lines += ["", "## Kernel trace (--kernel-trace --stats)", "",
+              "| kernel | class | calls | avg us | total ms | % |", "|---|---|---|---|---|---|"]
+    stats = _rows(os.path.join(directory, "stats", "**", "*kernel_stats.csv"))
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+        name = r["Name"]
+        short = name.split("(")[0][:70]
+        lines.append(f"| `{short}` | {kernel_class(name) or ''} | {r['Calls']} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.3f} "
+                     f"| {float(r['Percentage']):.1f} |")
+    traffic = {}
+    have_pmc = all(glob.glob(os.path.join(directory, d, "**", "*counter_collection.csv"),
+                             recursive=True) for d in ("fetch", "write"))
+    if have_pmc:
+        per = {}
+        for d, counter in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+            acc = {}
+            for r in _rows(os.path.join(directory, d, "**", "*counter_collection.csv")):
+                if r.get("Counter_Name") != counter:
+                    continue
+                key = r["Kernel_Name"]
+                disp = r.get("Dispatch_Id") or r.get("Correlation_Id")
+                acc.setdefault(key, {}).setdefault(disp, 0.0)
+                acc[key][disp] += float(r["Counter_Value"])
+            for k, v in acc.items():
+                per.setdefault(k, {})[counter] = sum(v.values()) / len(v)  # KiB per dispatch
+                per[k]["dispatches_" + d] = len(v)
+        calib = [k for k in per if "neg" in k.lower()]
+        if not calib:
+            raise SystemExit("the copy calibration kernel was not found in the counters")
+        c = per[calib[0]]
+        nominal_kib = CALIB_ELEMS * 8 / 1024.0
+        f_fetch = c.get("FETCH_SIZE", 0.0) / nominal_kib
+        f_write = c.get("WRITE_SIZE", 0.0) / nominal_kib
+        lines += ["", "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
+                  f"Copy calibration: negation of {CALIB_ELEMS} float64 values (512 MiB read, "
+                  f"512 MiB written) reads FETCH_SIZE x{f_fetch:.4f} and WRITE_SIZE "
+                  f"x{f_write:.4f} of the nominal bytes; the per-kernel figures below are "
+                  "divided by these factors.", "",
+                  "| kernel | class | dispatches | fetch MB/launch | write MB/launch | "
+                  "total MB/launch |", "|---|---|---|---|---|---|"]
+        for k, v in sorted(per.items(), key=lambda kv: -(kv[1].get("FETCH_SIZE", 0)
+                                                         + kv[1].get("WRITE_SIZE", 0))):
+            fb = v.get("FETCH_SIZE", 0.0) * 1024 / max(f_fetch, 1e-12)
+            wb = v.get("WRITE_SIZE", 0.0) * 1024 / max(f_write, 1e-12)
+            cls = kernel_class(k)
+            lines.append(f"| `{k.split('(')[0][:70]}` | {cls or ''} | "
+                         f"{v.get('dispatches_fetch', 0)} | {fb / 1e6:.2f} | {wb / 1e6:.2f} | "
+                         f"{(fb + wb) / 1e6:.2f} |")
+            if cls:
+                prev = traffic.get(cls)
+                # one class may hold several kernels (set-up parts): sum them per step
+                traffic[cls] = {"bytes_per_launch": (prev["bytes_per_launch"] if prev else 0.0)
+                                + fb + wb}
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    log(f"wrote {out_md}")
+    if traffic:
+        prec = "fp32" if "fp32" in label else "fp64"
+        path = os.path.join(ROOT, "profiles", "traffic_cylinder1024.json")
+        rec = json.load(open(path)) if os.path.exists(path) else {}
+        if rec.get("source_sha") != source_sha():
+            rec = {}
+        rec["source_sha"] = source_sha()
+        rec[prec] = traffic
+        json.dump(rec, open(path, "w"), indent=1, sort_keys=True)
+        log(f"wrote {path}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the headline value (the other form is run too)")
+    ap.add_argument("--workload", default="cfg2a")
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=100)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="launch the copy kernel used to scale HBM counters first")
+    ap.add_argument("--summarize", metavar="DIR", help="summarize rocprofv3 output (no GPU)")
+    ap.add_argument("--label", default="cylinder1024_fp64")
+    ap.add_argument("--command", default="")
+    args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, args.label, args.command)
+        return
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the step runs on one MI355X); "
+              "--gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2301_09349_amd import inputs
+
+    if args.calibrate_copy:
+        calibrate_copy()
+    case = inputs.case(args.workload, cg_rtol=1e-10)
+    main_p = args.precision
+    other = "fp32" if main_p == "fp64" else "fp64"
+    r = run_forward(case, main_p, args.steps, args.warmup)
+    ro = None if args.no_fp32 else run_forward(case, other, args.steps, args.warmup)
+    per_kernel = r["per_kernel"]
     dom = max((k for k in per_kernel if "GBps" in per_kernel[k]),
               key=lambda k: per_kernel[k]["total_ms"])
     d = per_kernel[dom]
-    traffic = traffic_entry(dom, args.precision)
+    traffic = traffic_entry(dom, main_p)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBps"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4),
             "traffic": traffic}
     log("bench: per-kernel " + json.dumps({k: {kk: (round(vv, 2) if isinstance(vv, float) else vv)
                                                  for kk, vv in v.items()}
                                              for k, v in per_kernel.items()}))
+    ids, _ = r["solver"].markers_in_use()
+    n = case["n"]
     out = {
         "metric": "Mcell-steps/s (fwd, FP32 vs FP64 at stated err) + adjoint/forward time ratio",
-        "value": round(value, 2),
+        "value": round(r["value"], 2),
         "unit": "Mcell-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(r["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": "f64" if main_p == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "2D heated cylinder, 1024x1024 cells over [-4,12]x[-8,8], "
-                               "400 candidate markers (check routine keeps %d), Re 100, Ma 0.2, "
-                               "Tw/Tinf 0.8, dt %.4e, CG rtol 1e-10" % (ids.shape[0], s.dt),
-                   "cells": N, "precision": args.precision,
-                   "cg_iters_per_step": round(cg_per_step, 2)},
+        "config": {"workload": "2D heated cylinder, %dx%d cells over [%g,%g]x[%g,%g], %d candidate "
+                               "markers (check routine keeps %d), Re %g, Ma %g, Tw/Tinf %g, dt %.4e, "
+                               "CG rtol 1e-10" % (n[0], n[1], case["lo"][0], case["hi"][0],
+                                                  case["lo"][1], case["hi"][1], case["ns"],
+                                                  ids.shape[0], case["Re"], case["Ma"],
+                                                  case["Tw"], r["solver"].dt),
+                   "cells": r["N"], "precision": main_p,
+                   "cg_iters_per_step": round(r["info"]["cg_iters_total"] / args.steps, 2)},
         "roofline": roof,
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
                         **({"GBps": round(v["GBps"], 1)} if "GBps" in v else {})}
                     for k, v in per_kernel.items()},
     }
+    if ro is not None:
+        r64, r32 = (r, ro) if main_p == "fp64" else (ro, r)
+        out[other] = {"value": round(ro["value"], 2), "ms_per_step": round(ro["ms_per_step"], 4),
+                      "cg_iters_per_step": round(ro["info"]["cg_iters_total"] / args.steps, 2),
+                      "kernels": {k: {"avg_us": round(v["avg_us"], 2),
+                                      **({"GBps": round(v["GBps"], 1)} if "GBps" in v else {})}
+                                  for k, v in ro["per_kernel"].items()}}
+        out["fp32_error_vs_fp64"] = {k: float("%.3g" % v) for k, v in fp32_error(r64, r32).items()}
+        del ro
+    del r
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        log(f"bench: adjoint leg, {args.adjoint_steps} steps ...")
+        out["adjoint"] = run_adjoint(args.adjoint_steps, 50, 10)
     if not args.no_cpu:
         log(f"bench: timing the oracle on {args.cpu_steps} steps ...")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -111,15 +111,17 @@ typedef struct {
 } ibm_step_info;
 
 /* Bytes of device workspace needed for a grid, a marker capacity and a tape
- * of `tape_steps` recorded steps (0: no adjoint). Returns 0 for an invalid
- * descriptor. */
+ * of `tape_steps` recorded steps (0: no adjoint; > 0 needs precision IBM_FP64).
+ * A tape step holds the FP64 state and pressure, (dim + 3) N + sum NF doubles;
+ * tape_steps > 0 also adds the adjoint's work buffers (about (9 dim + 12) N +
+ * (4 dim + 3) sum NF doubles). Returns 0 for an invalid descriptor. */
 size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32_t tape_steps);
 
 /* Creates a context on the current HIP device. `dev_workspace` (device memory,
  * at least ibm_workspace_bytes(desc, desc->max_markers, tape_steps) bytes,
  * 256-byte aligned) must stay valid until ibm_destroy; `tape_steps` is the
- * capacity used in that size computation. `hip_stream` (hipStream_t, may be
- * NULL for the null stream) orders all work. The state starts as the uniform
+ * capacity used in that size computation (IBM_E_ARG if > 0 with IBM_FP32).
+ * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all work. The state starts as the uniform
  * stream rho = 1, theta = 1, u = U_inf. */
 ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
                            int32_t tape_steps, void *hip_stream, ibm_ctx **out);
@@ -217,7 +219,10 @@ ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
  *                  (the history row of ibm_step)
  *   Tw_bar         device double [n candidate markers]: the step's contribution to
  *                  the gradient with respect to T_w is added (+=)
- * The context's current state is not changed; the step's own buffers are. */
+ * The context's current state is not changed; the step's own buffers are. The
+ * host waits for the adjoint pressure solve; the kernels after it are queued on
+ * the stream (state_bar_out and Tw_bar are ready when the stream is). Needs a
+ * workspace planned with tape_steps > 0 (FP64 descriptors only). */
 ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *state_bar_in,
                             double *state_bar_out, const double *out_bar, double *Tw_bar);
 

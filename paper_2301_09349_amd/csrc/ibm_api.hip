@@ -1034,7 +1034,6 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
   if (ctx->nc > 0) ibmk::run_adj_markers(L, B, ob, Tw_bar);
   ibmk::run_adj_predictor(L, B, slot, state_bar_out);
   HIPCHECK(ctx, hipGetLastError());
-  HIPCHECK(ctx, hipStreamSynchronize(st));
   return IBM_OK;
 }
 

@@ -37,21 +37,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_words(cls: str, dim: int) -> int:
+def kernel_words(cls: str, dim: int, precision: str = "fp64") -> int:
     """Algorithmic cell-array words each kernel class must move per cell (each
     distinct array element read or written once; face arrays counted as one word
     per cell and direction)."""
+    if precision == "fp64":
+        # single-reduction CG: r, w, s_old, p, x, psi -> r', w', s, p, x
+        cg = {"cg_a": 6 + 5}
+        start = 3  # CG start: r0, psi -> w0
+    else:
+        # FP32 form: part a r, p_old, psi -> p, q; part b d, p, r, q -> d, r
+        cg = {"cg_a": 3 + 2, "cg_b": 4 + 2}
+        start = 0
     return {
         "predictor": (2 * dim + 2) + (dim + 2),          # rho, m, E, F -> rho*, m*, E*
-        "setup": (dim + 3) + (dim + 2) + (dim + 3) + (dim + 3),
-        "cg_a": 3 + 2,                                    # r, p_old, psi -> p, q
-        "cg_b": 4 + 2,                                    # x, p, r, q -> x, r
+        "setup": (dim + 3) + (dim + 2) + (dim + 3) + (dim + 3) + start,
         "correct": (2 * dim + 4) + (2 * dim + 2),
+        **cg,
     }[cls]
 
 
 # kernel symbol prefix -> kernel class of the library's event timing
-KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_mcg_a", "cg_a"),
+KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start", "setup"),
+                ("k_cg_iter", "cg_a"), ("k_mcg_a", "cg_a"),
                 ("k_mcg_b", "cg_b"), ("k_cg_a", "cg_a"), ("k_cg_b", "cg_b"),
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
                 ("k_totals", "markers")]
@@ -159,7 +167,7 @@ def run_forward(case, precision, steps, warmup):
             continue
         ent = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n}
         if cls in ("predictor", "setup", "cg_a", "cg_b", "correct"):
-            b = kernel_words(cls, dim) * w * N
+            b = kernel_words(cls, dim, precision) * w * N
             ent["alg_bytes_per_launch"] = b
             ent["GBps"] = b / (ms / n * 1e-3) / 1e9
         per_kernel[cls] = ent

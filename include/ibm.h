@@ -233,8 +233,10 @@ int32_t ibm_tape_length(const ibm_ctx *ctx);
  * the context's stream around the launches of each kernel class and, after each
  * step, adds their durations to per-class totals (CG launches after convergence
  * are not counted). Classes (IBM_PROF_*): 0 predictor, 1 marker work (motion
- * update, interpolation/forcing, spread), 2 pressure set-up, 3 CG part a
- * (p update + matvec + p.q), 4 CG part b (x, r updates + r.r), 5 correction.
+ * update, interpolation/forcing, spread), 2 pressure set-up (with the CG's
+ * start), 3 CG iteration (FP64: the whole single-reduction iteration; FP32 form:
+ * p update + matvec + p.q), 4 FP32 form's second CG kernel (d, r updates + r.r),
+ * 5 correction.
  * enable != 0 clears the totals and starts timing; 0 stops it. */
 enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG_A = 3,
        IBM_PROF_CG_B = 4, IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };

@@ -200,12 +200,12 @@ __global__ void k_adj_corr_cell(GridK g, StateV<double> st, SBar sb, SBarW so, c
 }
 
 // ------------------------------------------------------ R2: adjoint pressure
-// Start of the solve A lambda = rhs from lambda = 0: r = rhs, p = r; partial r.r
-// (also the reference b.b).
+// Start of the solve A lambda = rhs from lambda = 0: r0 = rhs; partial b.b (the
+// CG's own start, w0 = A r0, follows).
 template <int DIM>
 __global__ __launch_bounds__(kThreads) void k_adj_cg_init(GridK g, const double *rhs, double *r,
-                                                          double *p, double *lam,
-                                                          double *partials, CgScal *cs, int tag) {
+                                                          double *lam, double *partials,
+                                                          CgScal *cs, int tag) {
   __shared__ double lds[32];
   double s = 0.0;
   int64_t t0, t1;
@@ -216,14 +216,12 @@ __global__ __launch_bounds__(kThreads) void k_adj_cg_init(GridK g, const double 
     const int64_t c = cidx(g, i, j, k);
     const double v = rhs[c];
     r[c] = v;
-    p[c] = v;
     lam[c] = 0.0;
     s += v * v;
   }
   s = block_sum(s, lds);
   if (threadIdx.x == 0) {
     partials[PART_BB * kMaxBlocks + blockIdx.x] = s;
-    partials[PART_RR * kMaxBlocks + blockIdx.x] = s;
     if (blockIdx.x == 0) {
       cs->done = 0;
       cs->iters = 0;
@@ -848,8 +846,9 @@ void run_adj_correction(const Launch &L, const Bufs &B, int slot, const double *
 void run_adj_cg_init(const Launch &L, const Bufs &B, int tag) {
   ADJ_DIM(L, {
     hipLaunchKernelGGL((k_adj_cg_init<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
-                       L.g, (const double *)B.rhs, B.r, B.p[0], B.lam, B.partials, B.cg, tag);
+                       L.g, (const double *)B.rhs, B.rv[0], B.lam, B.partials, B.cg, tag);
   });
+  run_cg_start(L, B);
 }
 
 void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in, double *sb_out) {

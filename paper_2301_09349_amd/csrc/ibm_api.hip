@@ -270,12 +270,15 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
     B.p32[1] = C.take<float>(N);
     B.q32 = C.take<float>(N);
     B.d32 = C.take<float>(N);
-    B.r = B.p[0] = B.p[1] = B.q = nullptr;
+    B.pv = nullptr;
+    for (int s = 0; s < 2; ++s) B.rv[s] = B.wv[s] = B.sv[s] = nullptr;
   } else {
-    B.r = C.take<double>(N);
-    B.p[0] = C.take<double>(N);
-    B.p[1] = C.take<double>(N);
-    B.q = C.take<double>(N);
+    B.pv = C.take<double>(N);
+    for (int s = 0; s < 2; ++s) {
+      B.rv[s] = C.take<double>(N);
+      B.wv[s] = C.take<double>(N);
+      B.sv[s] = C.take<double>(N);
+    }
     B.x2 = nullptr;
     B.r32 = B.p32[0] = B.p32[1] = B.q32 = B.d32 = nullptr;
   }
@@ -762,12 +765,12 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   auto cg_iteration = [&](int it) {
     if (P.on) {
       hipEvent_t e0 = P.mark(st);
-      ibmk::run_cg_half(L, B, it, 0);
-      hipEvent_t e1 = P.mark(st);
-      ibmk::run_cg_half(L, B, it, 1);
-      hipEvent_t e2 = P.mark(st);
-      P.pending.push_back({IBM_PROF_CG_A, it, e0, e1});
-      P.pending.push_back({IBM_PROF_CG_B, it, e1, e2});
+      for (int part = 0; part < ibmk::cg_parts(L); ++part) {
+        ibmk::run_cg_half(L, B, it, part);
+        hipEvent_t e1 = P.mark(st);
+        P.pending.push_back({part == 0 ? IBM_PROF_CG_A : IBM_PROF_CG_B, it, e0, e1});
+        e0 = e1;
+      }
     } else {
       ibmk::run_cg_iteration(L, B, it);
     }

@@ -595,12 +595,12 @@ template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, const S *mh0,
                                                      const S *mh1, const S *mh2, S *Fh0, S *Fh1,
                                                      S *Fh2, const S *psi, const double *x,
-                                                     double *b, double *r, double *p,
-                                                     double *partials, CgScal *cs, int tag) {
+                                                     double *b, double *r0, double *partials,
+                                                     CgScal *cs, int tag) {
   __shared__ double lds[32];
   const S *mh[3] = {mh0, mh1, mh2};
   S *Fh[3] = {Fh0, Fh1, Fh2};
-  double sums[2] = {0.0, 0.0};
+  double bb = 0.0;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
   for (int64_t t = t0; t < t1; ++t) {
@@ -627,17 +627,13 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
     const double bc_ = double(rho_n[c]) - g.dt * div + g.dt * g.dt * aff;
     const double xc = x[c];
     const double ax = helm_at<DIM>(g, psi, [&](int64_t q) { return x[q]; }, i, j, k, c, xc);
-    const double rc = bc_ - ax;
     b[c] = bc_;
-    r[c] = rc;
-    p[c] = rc;
-    sums[0] += bc_ * bc_;
-    sums[1] += rc * rc;
+    r0[c] = bc_ - ax;
+    bb += bc_ * bc_;
   }
-  block_sum_n<2>(sums, lds);
+  bb = block_sum(bb, lds);
   if (threadIdx.x == 0) {
-    partials[PART_BB * kMaxBlocks + blockIdx.x] = sums[0];
-    partials[PART_RR * kMaxBlocks + blockIdx.x] = sums[1];
+    partials[PART_BB * kMaxBlocks + blockIdx.x] = bb;
     if (blockIdx.x == 0) {
       cs->done = 0;
       cs->iters = 0;
@@ -647,19 +643,52 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
   }
 }
 
-// CG iteration `it`, part a. Every block forms r.r (after `it` updates) from the
-// partials of the previous kernel; converged (|r| <= rtol |b|) or out of
-// iterations -> all blocks stop and block 0 records it. Otherwise
-// beta = rr_it / rr_{it-1} (0 at it = 0), p = r + beta p_old (also at the
-// neighbours, on the fly), q = A p, partial p.q.
+// Start of the single-reduction CG (Chronopoulos and Gear's variant): w0 = A r0
+// and the per-block partials of gamma_0 = r0.r0 and delta_0 = w0.r0.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_cg_start(GridK g, const S *psi, const double *r0,
+                                                       double *w0, double *partials) {
+  __shared__ double lds[32];
+  double sums[2] = {0.0, 0.0};
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const double rc = r0[c];
+    const double wc = helm_at<DIM>(g, psi, [&](int64_t m) { return r0[m]; }, i, j, k, c, rc);
+    w0[c] = wc;
+    sums[0] += rc * rc;
+    sums[1] += wc * rc;
+  }
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[PART_G * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[PART_D * kMaxBlocks + blockIdx.x] = sums[1];
+  }
+}
+
+// CG iteration `it` with one global reduction (the recurrences of Chronopoulos and
+// Gear: s = A p is carried as s = w + beta s_old, so r.r and w.r of the new
+// residual are reduced together). Every block forms gamma_it = r.r and delta_it =
+// w.r from the partials of the previous kernel; converged (|r| <= rtol |b|) or out
+// of iterations -> all blocks stop and block 0 records it. Otherwise
+//   beta = gamma_it / gamma_{it-1} (0 at it = 0),
+//   alpha = gamma_it / (delta_it - beta gamma_it / alpha_{it-1}) (gamma/delta at 0),
+//   p = r + beta p, s = w + beta s, x += alpha p, r' = r - alpha s, w' = A r',
+// with r' of the neighbours formed on the fly from r, w, s; partials of r'.r' and
+// w'.r'. r, w, s are read from slot it & 1 and written to the other slot.
 // Block 0 posts (step tag, it, error flags, done) to `progress` (host memory, may
 // be NULL) so that the host can follow the solve without synchronising; a step
 // whose flags show an error stops its solve.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_cg_a(GridK g, int it, const S *psi, const double *r,
-                                                   const double *pold, double *pnew, double *q,
-                                                   double *partials, CgScal *cs, const int *flags,
-                                                   uint64_t *progress) {
+__global__ __launch_bounds__(kThreads) void k_cg_iter(GridK g, int it, const S *psi,
+                                                      const double *r, const double *w,
+                                                      const double *sold, double *rn, double *wn,
+                                                      double *snew, double *p, double *x,
+                                                      double *partials, CgScal *cs,
+                                                      const int *flags, uint64_t *progress) {
   __shared__ double lds[32];
   // block 0 of this kernel may set `done` while other blocks start: one read per block
   __shared__ int done0;
@@ -667,17 +696,27 @@ __global__ __launch_bounds__(kThreads) void k_cg_a(GridK g, int it, const S *psi
   __syncthreads();
   if (done0) return;
   const int nb = gridDim.x;
-  const double rr = sum_partials(partials + PART_RR * kMaxBlocks, nb, lds);
+  const int par = it & 1;
+  double gd[2];
+  sum_partials2(partials + (PART_G + par) * kMaxBlocks, partials + (PART_D + par) * kMaxBlocks,
+                nb, lds, gd);
+  const double gam = gd[0], del = gd[1];
   const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
   const double tol2 = cs->tol2;
   const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
                   (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
-  const bool conv = rr <= tol2 * bb;
-  const bool out = !conv && (it >= cs->maxit || err != 0 || !(rr == rr));
+  const bool conv = gam <= tol2 * bb;
+  const bool out = !conv && (it >= cs->maxit || err != 0 || !(gam == gam));
+  double beta = 0.0, alpha = gam / del;
+  if (it > 0) {
+    beta = gam / cs->rr[(it - 1) & 1];
+    alpha = gam / (del - beta * gam / cs->alpha[(it - 1) & 1]);
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (it == 0) cs->bb = bb;
-    cs->rr[it & 1] = rr;
-    cs->res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    cs->rr[par] = gam;
+    cs->alpha[par] = alpha;
+    cs->res = bb > 0.0 ? sqrt(gam / bb) : 0.0;
     cs->iters = it;
     if (conv || out) cs->done = conv ? 1 : 2;
     if (progress)
@@ -685,49 +724,51 @@ __global__ __launch_bounds__(kThreads) void k_cg_a(GridK g, int it, const S *psi
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   if (conv || out) return;
-  const double beta = (it == 0) ? 0.0 : rr / cs->rr[(it - 1) & 1];
-  auto pv = [&](int64_t m) { return r[m] + beta * pold[m]; };
-  double pq = 0.0;
+  double sums[2] = {0.0, 0.0};
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
-    int i, j, k;
-    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-    const int64_t c = cidx(g, i, j, k);
-    const double pc = pv(c);
-    const double qc = helm_at<DIM>(g, psi, pv, i, j, k, c, pc);
-    pnew[c] = pc;
-    q[c] = qc;
-    pq += pc * qc;
+  if (it == 0) {
+    // p = r, s = w: the old p and s are not read
+    auto rv = [&](int64_t m) { return r[m] - alpha * w[m]; };
+    for (int64_t t = t0; t < t1; ++t) {
+      int i, j, k;
+      if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+      const int64_t c = cidx(g, i, j, k);
+      const double pc = r[c], sc = w[c];
+      x[c] += alpha * pc;
+      const double rc = pc - alpha * sc;
+      const double wc = helm_at<DIM>(g, psi, rv, i, j, k, c, rc);
+      p[c] = pc;
+      snew[c] = sc;
+      rn[c] = rc;
+      wn[c] = wc;
+      sums[0] += rc * rc;
+      sums[1] += wc * rc;
+    }
+  } else {
+    auto rv = [&](int64_t m) { return r[m] - alpha * (w[m] + beta * sold[m]); };
+    for (int64_t t = t0; t < t1; ++t) {
+      int i, j, k;
+      if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+      const int64_t c = cidx(g, i, j, k);
+      const double pc = r[c] + beta * p[c];
+      const double sc = w[c] + beta * sold[c];
+      x[c] += alpha * pc;
+      const double rc = r[c] - alpha * sc;
+      const double wc = helm_at<DIM>(g, psi, rv, i, j, k, c, rc);
+      p[c] = pc;
+      snew[c] = sc;
+      rn[c] = rc;
+      wn[c] = wc;
+      sums[0] += rc * rc;
+      sums[1] += wc * rc;
+    }
   }
-  double s = block_sum(pq, lds);
-  if (threadIdx.x == 0) partials[PART_PQ * kMaxBlocks + blockIdx.x] = s;
-}
-
-// CG iteration `it`, part b: alpha = rr_it / p.q; x += alpha p, r -= alpha q,
-// partial r.r.
-template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_cg_b(GridK g, int it, double *x, double *r,
-                                                   const double *p, const double *q,
-                                                   double *partials, CgScal *cs) {
-  __shared__ double lds[32];
-  if (cs->done) return;
-  const double pq = sum_partials(partials + PART_PQ * kMaxBlocks, gridDim.x, lds);
-  const double alpha = cs->rr[it & 1] / pq;
-  double rr = 0.0;
-  int64_t t0, t1;
-  block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
-    int i, j, k;
-    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-    const int64_t c = cidx(g, i, j, k);
-    x[c] += alpha * p[c];
-    const double rc = r[c] - alpha * q[c];
-    r[c] = rc;
-    rr += rc * rc;
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[(PART_G + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[(PART_D + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[1];
   }
-  double s = block_sum(rr, lds);
-  if (threadIdx.x == 0) partials[PART_RR * kMaxBlocks + blockIdx.x] = s;
 }
 
 // ------------------------------------- FP32 form: pressure by iterative refinement
@@ -1197,10 +1238,20 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
     hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                        L.g, (const S *)B.rho[cur], (const S *)B.mhat[0], (const S *)B.mhat[1],
                        (const S *)B.mhat[2], (S *)B.Fhat[0], (S *)B.Fhat[1], (S *)B.Fhat[2],
-                       (const S *)B.psi, (const double *)B.x, B.b, B.r, B.p[0], B.partials, B.cg,
+                       (const S *)B.psi, (const double *)B.x, B.b, B.rv[0], B.partials, B.cg,
                        tag);
   });
+  run_cg_start(L, B);
 }
+
+void run_cg_start(const Launch &L, const Bufs &B) {
+  IBM_DISPATCH(L, {
+    hipLaunchKernelGGL((k_cg_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                       L.g, (const S *)B.psi, (const double *)B.rv[0], B.wv[0], B.partials);
+  });
+}
+
+int cg_parts(const Launch &L) { return L.prec == 1 ? 2 : 1; }
 
 template <int DIM>
 static void run_mcg_half(const Launch &L, const Bufs &B, int it, int part) {
@@ -1224,23 +1275,18 @@ void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
       run_mcg_half<3>(L, B, it, part);
     return;
   }
+  if (part != 0) return;
   IBM_DISPATCH(L, {
-    const int parity = it & 1;
-    double *pold = B.p[parity], *pnew = B.p[parity ^ 1];
-    if (part == 0)
-      hipLaunchKernelGGL((k_cg_a<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
-                         L.g, it, (const S *)B.psi, (const double *)B.r, (const double *)pold,
-                         pnew, B.q, B.partials, B.cg, (const int *)B.flags, B.progress);
-    else
-      hipLaunchKernelGGL((k_cg_b<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
-                         L.g, it, B.x, B.r, (const double *)pnew, (const double *)B.q, B.partials,
-                         B.cg);
+    const int a = it & 1, b = a ^ 1;
+    hipLaunchKernelGGL((k_cg_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+                       L.g, it, (const S *)B.psi, (const double *)B.rv[a], (const double *)B.wv[a],
+                       (const double *)B.sv[a], B.rv[b], B.wv[b], B.sv[b], B.pv, B.x, B.partials,
+                       B.cg, (const int *)B.flags, B.progress);
   });
 }
 
 void run_cg_iteration(const Launch &L, const Bufs &B, int it) {
-  run_cg_half(L, B, it, 0);
-  run_cg_half(L, B, it, 1);
+  for (int part = 0; part < cg_parts(L); ++part) run_cg_half(L, B, it, part);
 }
 
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {

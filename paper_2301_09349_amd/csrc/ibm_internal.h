@@ -48,10 +48,11 @@ struct StateV {
 };
 
 // Scalars of one pressure solve, in device memory. rr[i & 1] holds r.r after
-// i CG updates (two slots, so that the kernel of iteration i reads the value of
-// iteration i-1 while writing its own).
+// i CG updates and alpha[i & 1] the step length of update i (two slots, so that
+// the kernel of iteration i reads the values of iteration i-1 while writing its
+// own).
 struct CgScal {
-  double bb, tol2, rr[2], res;
+  double bb, tol2, rr[2], res, alpha[2];
   int iters, done, maxit, step_tag;
   // FP32 form (iterative refinement). Values the kernel of iteration `it` reads
   // sit in slot it & 1; block 0 of that kernel writes slot (it + 1) & 1.
@@ -75,8 +76,18 @@ __host__ __device__ inline uint64_t pack_progress(int tag, int it, int err, int 
 // step whose correction failed.
 enum { FLAG_NONFINITE = 0, FLAG_SUPPORT = 1, FLAG_EPS = 2, FLAG_GRAM = 3, FLAG_BAD_STEP = 4 };
 
-// Per-block partial sums of the cell kernels, each region kMaxBlocks long.
-enum { PART_PQ = 0, PART_RR = 1, PART_BB = 2, PART_MASS = 3, PART_REGIONS = 4 };
+// Per-block partial sums of the cell kernels, each region kMaxBlocks long. The
+// single-reduction CG of iteration i reads (r.r, w.r) from regions PART_G + (i & 1),
+// PART_D + (i & 1) and writes the other pair.
+enum {
+  PART_PQ = 0,
+  PART_RR = 1,
+  PART_BB = 2,
+  PART_MASS = 3,
+  PART_G = 4,
+  PART_D = 6,
+  PART_REGIONS = 8
+};
 
 __device__ __forceinline__ int64_t cidx(const GridK &g, int i, int j, int k) {
   return i + (int64_t)g.n[0] * (j + (int64_t)g.n[1] * k);
@@ -246,6 +257,27 @@ __device__ __forceinline__ double sum_partials(const double *partials, int n, do
   s = bcast;
   __syncthreads();
   return s;
+}
+
+// Sums of two partial arrays at once (same order as sum_partials); every thread of
+// the block gets both.
+__device__ __forceinline__ void sum_partials2(const double *pa, const double *pb, int n,
+                                              double *lds, double *out) {
+  __shared__ double bc[2];
+  double v[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    v[0] += pa[i];
+    v[1] += pb[i];
+  }
+  block_sum_n<2>(v, lds);
+  if (threadIdx.x == 0) {
+    bc[0] = v[0];
+    bc[1] = v[1];
+  }
+  __syncthreads();
+  out[0] = bc[0];
+  out[1] = bc[1];
+  __syncthreads();
 }
 
 }  // namespace ibmk

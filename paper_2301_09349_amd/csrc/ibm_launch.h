@@ -14,8 +14,9 @@ struct Bufs {
   void *rho_s, *mom_s[3], *E_s;
   // pressure equation: m^ = mom** + dt G p^n, its face flux, psi
   void *mhat[3], *Fhat[3], *psi;
-  // pressure CG (FP64)
-  double *b, *x, *r, *p[2], *q;
+  // pressure CG (FP64, single-reduction form): x and p in place; r, w = A r and
+  // s = A p ping-pong between iterations (their neighbour values are read)
+  double *b, *x, *pv, *rv[2], *wv[2], *sv[2];
   // FP32 form: second FP64 solution buffer and the FP32 inner-CG vectors
   double *x2;
   float *r32, *p32[2], *q32, *d32;
@@ -84,9 +85,14 @@ void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
 void run_predictor(const Launch &L, const Bufs &B, int cur);
 size_t predictor_lds_bytes(int dim, int prec);
 void enable_predictor_lds(int dim, int prec);
+// set-up of the pressure equation, ending with the start of its CG (r0, w0 = A r0)
 void run_setup(const Launch &L, const Bufs &B, int cur, int tag);
+// start of the FP64 CG from r0 = rv[0]: w0 = A r0 and the first dot products
+void run_cg_start(const Launch &L, const Bufs &B);
 void run_cg_iteration(const Launch &L, const Bufs &B, int it);
-void run_cg_half(const Launch &L, const Bufs &B, int it, int part);  // part 0: a, 1: b
+// kernels of one CG iteration: 1 in FP64, 2 in the FP32 form (part 0: a, 1: b)
+int cg_parts(const Launch &L);
+void run_cg_half(const Launch &L, const Bufs &B, int it, int part);
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag);
 void run_mass(const Launch &L, const Bufs &B);
 int64_t cell_blocks(const GridK &g);

@@ -42,25 +42,22 @@ def kernel_words(cls: str, dim: int, precision: str = "fp64") -> int:
     distinct array element read or written once; face arrays counted as one word
     per cell and direction)."""
     if precision == "fp64":
-        # single-reduction CG: r, w, s_old, p, x, psi -> r', w', s, p, x
-        cg = {"cg_a": 6 + 5}
-        start = 3  # CG start: r0, psi -> w0
+        cg = 6 + 5   # single-reduction CG: r, w, s_old, p, x, psi -> r', w', s, p, x
+        start = 3    # CG start: r0, psi -> w0
     else:
-        # FP32 form: part a r, p_old, psi -> p, q; part b d, p, r, q -> d, r
-        cg = {"cg_a": 3 + 2, "cg_b": 4 + 2}
+        cg = 5 + 6   # FP32 inner CG: r, p_old, psi -> p, q; then d, p, r, q -> d, r
         start = 0
     return {
         "predictor": (2 * dim + 2) + (dim + 2),          # rho, m, E, F -> rho*, m*, E*
         "setup": (dim + 3) + (dim + 2) + (dim + 3) + (dim + 3) + start,
         "correct": (2 * dim + 4) + (2 * dim + 2),
-        **cg,
+        "cg": cg,
     }[cls]
 
 
 # kernel symbol prefix -> kernel class of the library's event timing
 KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start", "setup"),
-                ("k_cg_iter", "cg_a"), ("k_mcg_a", "cg_a"),
-                ("k_mcg_b", "cg_b"), ("k_cg_a", "cg_a"), ("k_cg_b", "cg_b"),
+                ("k_cg_iter", "cg"), ("k_mcg_a", "cg"), ("k_mcg_b", "cg"),
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
                 ("k_totals", "markers")]
 
@@ -139,8 +136,9 @@ def make_solver(case, precision, tape_steps=0):
 
 
 def run_forward(case, precision, steps, warmup):
-    """Times `steps` steps after `warmup`; per-kernel-class times from the library's
-    HIP events on its stream over the same region."""
+    """Times `steps` steps after `warmup` with kernel timing off (the throughput),
+    then `steps` more with the library's per-class HIP events on its stream (the
+    kernel durations; the events slow the step a little)."""
     import numpy as np
     import torch
 
@@ -152,12 +150,17 @@ def run_forward(case, precision, steps, warmup):
     if warmup:
         s.step(warmup, hist_out=hist)
     torch.cuda.synchronize()
-    s.profile(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, info = s.step(steps, hist_out=hist)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    h_timed = hist[:steps].clone()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.step(steps, hist=False)
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t1
     prof = s.profile_read()
     s.profile(False)
     w = 4 if precision == "fp32" else 8
@@ -165,15 +168,17 @@ def run_forward(case, precision, steps, warmup):
     for cls, (ms, n) in prof.items():
         if n == 0:
             continue
-        ent = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n}
-        if cls in ("predictor", "setup", "cg_a", "cg_b", "correct"):
+        ent = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n,
+               "ms_per_step": ms / steps}
+        if cls in ("predictor", "setup", "cg", "correct"):
             b = kernel_words(cls, dim, precision) * w * N
             ent["alg_bytes_per_launch"] = b
             ent["GBps"] = b / (ms / n * 1e-3) / 1e9
         per_kernel[cls] = ent
     return {"solver": s, "N": N, "elapsed": elapsed, "info": info, "per_kernel": per_kernel,
-            "hist": hist[:steps].clone(), "value": N * steps / elapsed / 1e6,
-            "ms_per_step": 1e3 * elapsed / steps}
+            "hist": h_timed, "value": N * steps / elapsed / 1e6,
+            "ms_per_step": 1e3 * elapsed / steps,
+            "ms_per_step_profiled": 1e3 * elapsed_prof / steps}
 
 
 def fp32_error(r64, r32):
@@ -280,23 +285,48 @@ def _rows(pattern):
 
 
 def summarize(directory: str, label: str, command: str):
-    """Reads rocprofv3 output under `directory` (kernel_stats from a --kernel-trace
-    --stats run; counter_collection from --pmc FETCH_SIZE and --pmc WRITE_SIZE runs,
-    in subdirectories stats/, fetch/, write/) and writes profiles/kernels_<label>.md
-    and profiles/traffic_<label>.json."""
+    """Reads rocprofv3 output under `directory` -- kernel_stats from a --kernel-trace
+    --stats run (stats/), counter_collection from --pmc FETCH_SIZE (fetch/) and --pmc
+    WRITE_SIZE (write/) runs, and each run's JSON line (stats.json) -- and writes
+    profiles/kernels_<label>.md and, with counters, profiles/traffic_<label>.json."""
     out_md = os.path.join(ROOT, "profiles", f"kernels_{label}.md")
+    bj = json.loads(open(os.path.join(directory, "stats.json")).read().strip().splitlines()[-1])
+    total_steps = bj["warmup"] + 2 * bj["steps"]
+    iters = bj["config"]["cg_iters_per_step"]
+    prec = bj["config"]["precision"]
     lines = [f"# rocprofv3 summary: {label}", "", "Commands (from the repository root):", ""]
     for c in command.split(";;"):
         lines.append(f"    {c.strip()}")
-    lines += ["", "## Kernel trace (--kernel-trace --stats)", "",
+    lines += ["", f"The profiled program runs {bj['warmup']} warm-up steps, {bj['steps']} steps "
+              f"without and {bj['steps']} steps with the library's event timing "
+              f"({total_steps} steps, {iters} CG iterations per step); per-step figures divide "
+              "the kernel totals by the steps.", "",
+              "## Kernel trace (--kernel-trace --stats)", "",
               "| kernel | class | calls | avg us | total ms | % |", "|---|---|---|---|---|---|"]
     stats = _rows(os.path.join(directory, "stats", "**", "*kernel_stats.csv"))
+    cls_ns = {}
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"]
+        cls = kernel_class(name)
+        if cls:
+            cls_ns[cls] = cls_ns.get(cls, 0.0) + float(r["TotalDurationNs"])
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
         name = r["Name"]
-        short = name.split("(")[0][:70]
-        lines.append(f"| `{short}` | {kernel_class(name) or ''} | {r['Calls']} | "
+        lines.append(f"| `{name.split('(')[0][:70]}` | {kernel_class(name) or ''} | {r['Calls']} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.3f} "
                      f"| {float(r['Percentage']):.1f} |")
+    lines += ["", "## Kernel time per step: kernel trace against the HIP events of the same run",
+              "", "| class | trace us/step | events us/step | trace us per launch or CG iteration "
+              "| events us per launch or CG iteration |", "|---|---|---|---|---|"]
+    for cls, ns in sorted(cls_ns.items(), key=lambda kv: -kv[1]):
+        ev = bj["kernels"].get(cls)
+        tr_step = ns / 1e3 / total_steps
+        per = tr_step / iters if cls == "cg" else None
+        if ev:
+            ev_step = 1e3 * ev["ms_per_step"]
+            ev_per = ev["avg_us"]
+            lines.append(f"| {cls} | {tr_step:.2f} | {ev_step:.2f} | "
+                         f"{(per if per else tr_step):.2f} | {ev_per:.2f} |")
     traffic = {}
     have_pmc = all(glob.glob(os.path.join(directory, d, "**", "*counter_collection.csv"),
                              recursive=True) for d in ("fetch", "write"))
@@ -312,9 +342,10 @@ def summarize(directory: str, label: str, command: str):
                 acc.setdefault(key, {}).setdefault(disp, 0.0)
                 acc[key][disp] += float(r["Counter_Value"])
             for k, v in acc.items():
-                per.setdefault(k, {})[counter] = sum(v.values()) / len(v)  # KiB per dispatch
+                per.setdefault(k, {})[counter + "_total"] = sum(v.values())  # KiB
+                per[k][counter] = sum(v.values()) / len(v)                    # KiB per dispatch
                 per[k]["dispatches_" + d] = len(v)
-        calib = [k for k in per if "neg" in k.lower()]
+        calib = [k for k in per if "neg_kernel" in k]
         if not calib:
             raise SystemExit("the copy calibration kernel was not found in the counters")
         c = per[calib[0]]
@@ -324,10 +355,11 @@ def summarize(directory: str, label: str, command: str):
         lines += ["", "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
                   f"Copy calibration: negation of {CALIB_ELEMS} float64 values (512 MiB read, "
                   f"512 MiB written) reads FETCH_SIZE x{f_fetch:.4f} and WRITE_SIZE "
-                  f"x{f_write:.4f} of the nominal bytes; the per-kernel figures below are "
-                  "divided by these factors.", "",
-                  "| kernel | class | dispatches | fetch MB/launch | write MB/launch | "
-                  "total MB/launch |", "|---|---|---|---|---|---|"]
+                  f"x{f_write:.4f} of the nominal bytes; the figures below are divided by "
+                  "these factors.", "",
+                  "| kernel | class | dispatches | fetch MB/dispatch | write MB/dispatch | "
+                  "total MB/dispatch |", "|---|---|---|---|---|---|"]
+        cls_bytes = {}
         for k, v in sorted(per.items(), key=lambda kv: -(kv[1].get("FETCH_SIZE", 0)
                                                          + kv[1].get("WRITE_SIZE", 0))):
             fb = v.get("FETCH_SIZE", 0.0) * 1024 / max(f_fetch, 1e-12)
@@ -337,14 +369,18 @@ def summarize(directory: str, label: str, command: str):
                          f"{v.get('dispatches_fetch', 0)} | {fb / 1e6:.2f} | {wb / 1e6:.2f} | "
                          f"{(fb + wb) / 1e6:.2f} |")
             if cls:
-                prev = traffic.get(cls)
-                # one class may hold several kernels (set-up parts): sum them per step
-                traffic[cls] = {"bytes_per_launch": (prev["bytes_per_launch"] if prev else 0.0)
-                                + fb + wb}
+                tot = (v.get("FETCH_SIZE_total", 0.0) * 1024 / max(f_fetch, 1e-12)
+                       + v.get("WRITE_SIZE_total", 0.0) * 1024 / max(f_write, 1e-12))
+                cls_bytes[cls] = cls_bytes.get(cls, 0.0) + tot
+        lines += ["", "Per class, as the bench line uses them (bytes per step; per CG iteration "
+                  "for the CG):", "", "| class | MB |", "|---|---|"]
+        for cls, tot in sorted(cls_bytes.items()):
+            units = total_steps * (iters if cls == "cg" else 1)
+            traffic[cls] = {"bytes_per_launch": tot / units}
+            lines.append(f"| {cls} | {tot / units / 1e6:.2f} |")
     open(out_md, "w").write("\n".join(lines) + "\n")
     log(f"wrote {out_md}")
     if traffic:
-        prec = "fp32" if "fp32" in label else "fp64"
         path = os.path.join(ROOT, "profiles", "traffic_cylinder1024.json")
         rec = json.load(open(path)) if os.path.exists(path) else {}
         if rec.get("source_sha") != source_sha():
@@ -400,7 +436,11 @@ def main():
     traffic = traffic_entry(dom, main_p)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBps"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4),
-            "traffic": traffic}
+            "traffic": traffic,
+            "alg_bytes_per_launch": d["alg_bytes_per_launch"],
+            "avg_us": round(d["avg_us"], 3),
+            "timing": "HIP events on the library stream over a second run of the same "
+                      "steps (the throughput run is untimed per kernel)"}
     log("bench: per-kernel " + json.dumps({k: {kk: (round(vv, 2) if isinstance(vv, float) else vv)
                                                  for kk, vv in v.items()}
                                              for k, v in per_kernel.items()}))
@@ -429,8 +469,10 @@ def main():
                    "cg_iters_per_step": round(r["info"]["cg_iters_total"] / args.steps, 2)},
         "roofline": roof,
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
+                        "ms_per_step": round(v["ms_per_step"], 4),
                         **({"GBps": round(v["GBps"], 1)} if "GBps" in v else {})}
                     for k, v in per_kernel.items()},
+        "ms_per_step_profiled": round(r["ms_per_step_profiled"], 4),
     }
     if ro is not None:
         r64, r32 = (r, ro) if main_p == "fp64" else (ro, r)

@@ -231,12 +231,13 @@ int32_t ibm_tape_length(const ibm_ctx *ctx);
 
 /* Kernel timing for measurement. While enabled, ibm_step records HIP events on
  * the context's stream around the launches of each kernel class and, after each
- * step, adds their durations to per-class totals (CG launches after convergence
- * are not counted). Classes (IBM_PROF_*): 0 predictor, 1 marker work (motion
- * update, interpolation/forcing, spread), 2 pressure set-up (with the CG's
- * start), 3 CG iteration (FP64: the whole single-reduction iteration; FP32 form:
- * p update + matvec + p.q), 4 FP32 form's second CG kernel (d, r updates + r.r),
- * 5 correction.
+ * step, adds their durations to per-class totals. Classes (IBM_PROF_*): 0
+ * predictor, 1 marker work (motion update, interpolation/forcing, spread), 2
+ * pressure set-up (with the CG's start), 3 CG iterations (one event pair around
+ * each batch of back-to-back iterations; the launch count is the number of
+ * iterations that did work, so total / count is the time per iteration, with the
+ * launch that detects convergence included in the total), 4 unused, 5 correction.
+ * The events themselves slow a step down; time throughput with timing off.
  * enable != 0 clears the totals and starts timing; 0 stops it. */
 enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG_A = 3,
        IBM_PROF_CG_B = 4, IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };

@@ -7,7 +7,8 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libibm_hip.so")
+# the in-tree build; IBM_HIP_LIB names another build of the same sources
+LIB_PATH = os.environ.get("IBM_HIP_LIB") or os.path.join(PKG, "libibm_hip.so")
 
 IBM_OK, IBM_E_ARG, IBM_E_SIZE, IBM_E_HIP, IBM_E_NOT_CONVERGED, IBM_E_NONFINITE, IBM_E_STATE = range(7)
 STATUS_NAMES = {0: "IBM_OK", 1: "IBM_E_ARG", 2: "IBM_E_SIZE", 3: "IBM_E_HIP",
@@ -89,7 +90,7 @@ SIGNATURES = {
     "ibm_profile_read": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
 }
 
-PROF_CLASSES = ["predictor", "markers", "setup", "cg_a", "cg_b", "correct"]
+PROF_CLASSES = ["predictor", "markers", "setup", "cg", "unused", "correct"]
 
 _lib = None
 

@@ -21,15 +21,17 @@ using ibmk::CgScal;
 using ibmk::GridK;
 using ibmk::Launch;
 
-// Event-pair timing of kernel classes (measurement only).
+// Event-pair timing of kernel classes (measurement only). A pair brackets the
+// launches of one class in a step; the CG's pairs bracket a batch of back-to-back
+// iterations (it0 .. it0 + nl - 1) and count only the iterations that did work.
 struct Prof {
   bool on = false;
   double ms[IBM_PROF_CLASSES] = {};
   int64_t n[IBM_PROF_CLASSES] = {};
   struct Pair {
-    int cls, it;
+    int cls, it0, nl;
     hipEvent_t a, b;
-    bool drop = false;
+    int count = 1;
   };
   std::vector<hipEvent_t> pool, used;
   std::vector<Pair> pending;
@@ -50,22 +52,25 @@ struct Prof {
     if (e) (void)hipEventRecord(e, st);
     return e;
   }
-  // CG launches of the current step past its solve (they return at once) are not
-  // counted
-  void drop_cg_after(int cg_iters) {
+  // the CG batches of the current step: count the iterations that did work (a
+  // solve of n iterations also launches the test that ends it, and a batch may run
+  // past the end; that time stays in the total)
+  void count_cg(int cg_iters) {
     for (size_t i = step_first; i < pending.size(); ++i) {
       Pair &p = pending[i];
-      if ((p.cls == IBM_PROF_CG_A || p.cls == IBM_PROF_CG_B) && p.it >= cg_iters) p.drop = true;
+      if (p.cls != IBM_PROF_CG_A) continue;
+      const int hi = std::min(p.it0 + p.nl, cg_iters);
+      p.count = std::max(0, hi - p.it0);
     }
   }
   // after a synchronisation: accumulate the recorded durations
   void settle() {
     for (const Pair &p : pending) {
-      if (!p.a || !p.b || p.drop) continue;
+      if (!p.a || !p.b) continue;
       float t = 0.f;
       if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
         ms[p.cls] += t;
-        n[p.cls] += 1;
+        n[p.cls] += p.count;
       }
     }
     pending.clear();
@@ -760,19 +765,15 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     hipEvent_t a = P.mark(st);
     launch();
     hipEvent_t b = P.mark(st);
-    P.pending.push_back({cls, it, a, b});
+    P.pending.push_back({cls, it, 1, a, b});
   };
-  auto cg_iteration = [&](int it) {
+  // a batch of `count` CG iterations from `it0`, back to back
+  auto cg_batch = [&](int it0, int count) {
+    hipEvent_t a = P.on ? P.mark(st) : nullptr;
+    for (int it = it0; it < it0 + count; ++it) ibmk::run_cg_iteration(L, B, it);
     if (P.on) {
-      hipEvent_t e0 = P.mark(st);
-      for (int part = 0; part < ibmk::cg_parts(L); ++part) {
-        ibmk::run_cg_half(L, B, it, part);
-        hipEvent_t e1 = P.mark(st);
-        P.pending.push_back({part == 0 ? IBM_PROF_CG_A : IBM_PROF_CG_B, it, e0, e1});
-        e0 = e1;
-      }
-    } else {
-      ibmk::run_cg_iteration(L, B, it);
+      hipEvent_t b = P.mark(st);
+      P.pending.push_back({IBM_PROF_CG_A, it0, count, a, b});
     }
   };
   // Flags are sticky for the whole call: a step that fails keeps every later step
@@ -811,7 +812,8 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     // does not wait for the host unless the batch falls short.
     int launched = 0;
     const int first = std::max(1, ctx->cg_hint + 1);
-    for (int c = 0; c < first; ++c) cg_iteration(launched++);
+    cg_batch(launched, first);
+    launched += first;
     timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
     HIPCHECK(ctx, hipGetLastError());
     uint64_t w = 0;
@@ -819,13 +821,14 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       ibm_status r = wait_progress(ctx, tag, launched - 1, &w);
       if (r) return r;
       if (w & 0xF) break;
-      for (int c = 0; c < 2; ++c) cg_iteration(launched++);
+      cg_batch(launched, 2);
+      launched += 2;
       timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
       HIPCHECK(ctx, hipGetLastError());
     }
     const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
     const int iters = (int)((w >> 8) & 0xFFFFFF);
-    if (P.on) P.drop_cg_after(iters);
+    if (P.on) P.count_cg(iters);
     if (err) {
       // this step's correction did not run; an earlier failure is sorted out below
       rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE

@@ -225,13 +225,25 @@ __global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S
 // buffer, from which every cell sums its divergence.
 template <int DIM>
 struct PTile;
+#ifndef IBM_PRED_TX2
+#define IBM_PRED_TX2 64
+#define IBM_PRED_TY2 8
+#endif
+#ifndef IBM_PRED_TX3
+#define IBM_PRED_TX3 16
+#define IBM_PRED_TY3 8
+#define IBM_PRED_TZ3 4
+#endif
+#ifndef IBM_PRED_MAXB
+#define IBM_PRED_MAXB kMaxBlocks
+#endif
 template <>
 struct PTile<2> {
-  static constexpr int TX = 64, TY = 8, TZ = 1;
+  static constexpr int TX = IBM_PRED_TX2, TY = IBM_PRED_TY2, TZ = 1;
 };
 template <>
 struct PTile<3> {
-  static constexpr int TX = 16, TY = 8, TZ = 4;
+  static constexpr int TX = IBM_PRED_TX3, TY = IBM_PRED_TY3, TZ = IBM_PRED_TZ3;
 };
 
 template <int DIM, typename S>
@@ -1195,7 +1207,7 @@ void run_predictor(const Launch &L, const Bufs &B, int cur) {
       const int64_t nt = (int64_t)((L.g.n[0] + T::TX - 1) / T::TX) *
                          ((L.g.n[1] + T::TY - 1) / T::TY) *
                          (DIM == 3 ? (L.g.n[2] + T::TZ - 1) / T::TZ : 1);
-      const int64_t nb = std::min<int64_t>(((nt + 7) / 8) * 8, kMaxBlocks);
+      const int64_t nb = std::min<int64_t>(((nt + 7) / 8) * 8, IBM_PRED_MAXB);
       hipLaunchKernelGGL((k_predictor_lds<DIM, S>), dim3((unsigned)nb), dim3(kThreads), T::bytes,
                          L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
                          (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);

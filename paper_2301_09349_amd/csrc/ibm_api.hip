@@ -797,10 +797,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     timed(IBM_PROF_PREDICTOR, 0, [&] { ibmk::run_predictor(L, B, ctx->cur); });
     double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
     if (ctx->nc > 0) {
-      timed(IBM_PROF_MARKERS, 0, [&] {
-        ibmk::run_interp_force(L, B, hrow);
-        ibmk::run_spread(L, B);
-      });
+      timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
     } else if (hrow) {
       HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
     }
@@ -1016,10 +1013,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     if (r) return r;
   }
   ibmk::run_predictor(L, B, slot);
-  if (ctx->nc > 0) {
-    ibmk::run_interp_force(L, B, nullptr);
-    ibmk::run_spread(L, B);
-  }
+  if (ctx->nc > 0) ibmk::run_markers_step(L, B, nullptr);
   ibmk::run_setup(L, B, slot, ++ctx->tag);
   HIPCHECK(ctx, hipMemcpyAsync(B.x,
                                B.tape + B.tape_stride * (size_t)tape_index + tape_x_offset(L.g),

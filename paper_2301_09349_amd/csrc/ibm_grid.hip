@@ -223,32 +223,51 @@ __global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S
 // and a two-cell halo are computed once into LDS with the ghost rules applied;
 // the fluxes of each face direction are then computed once per face into an LDS
 // buffer, from which every cell sums its divergence.
-template <int DIM>
+template <int DIM, typename S>
 struct PTile;
-#ifndef IBM_PRED_TX2
-#define IBM_PRED_TX2 64
-#define IBM_PRED_TY2 8
+// Tile shapes (measured on gfx950): FP64 tiles are smaller so that more blocks fit
+// the LDS of a CU.
+#ifndef IBM_PRED_TX2D
+#define IBM_PRED_TX2D 32
+#define IBM_PRED_TY2D 8
 #endif
-#ifndef IBM_PRED_TX3
-#define IBM_PRED_TX3 16
-#define IBM_PRED_TY3 8
-#define IBM_PRED_TZ3 4
+#ifndef IBM_PRED_TX2F
+#define IBM_PRED_TX2F 64
+#define IBM_PRED_TY2F 8
+#endif
+#ifndef IBM_PRED_TX3D
+#define IBM_PRED_TX3D 16
+#define IBM_PRED_TY3D 8
+#define IBM_PRED_TZ3D 4
+#endif
+#ifndef IBM_PRED_TX3F
+#define IBM_PRED_TX3F 16
+#define IBM_PRED_TY3F 8
+#define IBM_PRED_TZ3F 4
 #endif
 #ifndef IBM_PRED_MAXB
 #define IBM_PRED_MAXB kMaxBlocks
 #endif
 template <>
-struct PTile<2> {
-  static constexpr int TX = IBM_PRED_TX2, TY = IBM_PRED_TY2, TZ = 1;
+struct PTile<2, double> {
+  static constexpr int TX = IBM_PRED_TX2D, TY = IBM_PRED_TY2D, TZ = 1;
 };
 template <>
-struct PTile<3> {
-  static constexpr int TX = IBM_PRED_TX3, TY = IBM_PRED_TY3, TZ = IBM_PRED_TZ3;
+struct PTile<2, float> {
+  static constexpr int TX = IBM_PRED_TX2F, TY = IBM_PRED_TY2F, TZ = 1;
+};
+template <>
+struct PTile<3, double> {
+  static constexpr int TX = IBM_PRED_TX3D, TY = IBM_PRED_TY3D, TZ = IBM_PRED_TZ3D;
+};
+template <>
+struct PTile<3, float> {
+  static constexpr int TX = IBM_PRED_TX3F, TY = IBM_PRED_TY3F, TZ = IBM_PRED_TZ3F;
 };
 
 template <int DIM, typename S>
 struct PredLds {
-  static constexpr int TX = PTile<DIM>::TX, TY = PTile<DIM>::TY, TZ = PTile<DIM>::TZ;
+  static constexpr int TX = PTile<DIM, S>::TX, TY = PTile<DIM, S>::TY, TZ = PTile<DIM, S>::TZ;
   static constexpr int SX = TX + 4, SY = TY + 4, SZ = (DIM == 3) ? TZ + 4 : 1;
   static constexpr int NP = SX * SY * SZ;
   static constexpr int NV = DIM + 3;  // rho, u[DIM], theta, mu
@@ -573,9 +592,9 @@ __global__ __launch_bounds__(kThreads) void k_setup1(GridK g, StateV<S> st, cons
 
 // Homogeneous pressure operator at one cell: psi v - dt^2 div(grad_f v), zero
 // normal gradient at inflow and slip faces, v = 0 beyond outflow faces.
-template <int DIM, typename S, typename VF>
-__device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, int i, int j, int k,
-                                          int64_t c, double vc) {
+// The homogeneous Laplacian of v at (i, j, k), vc = v there.
+template <int DIM, typename VF>
+__device__ __forceinline__ double helm_lap(const GridK &g, VF v, int i, int j, int k, double vc) {
   double lap = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -597,7 +616,13 @@ __device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, in
       lap += gf * ih;
     }
   }
-  return double(psi[c]) * vc - g.dt * g.dt * lap;
+  return lap;
+}
+
+template <int DIM, typename S, typename VF>
+__device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, int i, int j, int k,
+                                          int64_t c, double vc) {
+  return double(psi[c]) * vc - g.dt * g.dt * helm_lap<DIM>(g, v, i, j, k, vc);
 }
 
 // Pressure set-up, part 2, fused with the CG start: predicted face flux
@@ -655,6 +680,10 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
   }
 }
 
+#ifndef IBM_CG_UNROLL
+#define IBM_CG_UNROLL 1
+#endif
+
 // Start of the single-reduction CG (Chronopoulos and Gear's variant): w0 = A r0
 // and the per-block partials of gamma_0 = r0.r0 and delta_0 = w0.r0.
 template <int DIM, typename S>
@@ -681,6 +710,60 @@ __global__ __launch_bounds__(kThreads) void k_cg_start(GridK g, const S *psi, co
   }
 }
 
+constexpr int kCgPrefetch = 4;  // tiles per block whose cell values are loaded early
+
+// Update of one cell in a CG iteration (see k_cg_iter): rc, wc, sc0, pc0, xc, psc
+// are r, w, s_old, p_old, x, psi at the cell. FIRST: p = r, s = w (the old p, s are
+// not read).
+template <int DIM, bool FIRST, typename S>
+__device__ __forceinline__ void cg_cell(const GridK &g, double alpha, double beta, int i, int j,
+                                        int k, double rc, double wc, double sc0, double pc0,
+                                        double xc, S psc, const double *__restrict__ r,
+                                        const double *__restrict__ w,
+                                        const double *__restrict__ sold, double *__restrict__ rn,
+                                        double *__restrict__ wn, double *__restrict__ snew,
+                                        double *__restrict__ p, double *__restrict__ x,
+                                        double *sums) {
+  const int64_t c = cidx(g, i, j, k);
+  const double pc = FIRST ? rc : rc + beta * pc0;
+  const double sc = FIRST ? wc : wc + beta * sc0;
+  x[c] = xc + alpha * pc;
+  const double rnc = rc - alpha * sc;
+  auto rv = [&](int64_t m) {
+    return FIRST ? r[m] - alpha * w[m] : r[m] - alpha * (w[m] + beta * sold[m]);
+  };
+  const double wnc = double(psc) * rnc - g.dt * g.dt * helm_lap<DIM>(g, rv, i, j, k, rnc);
+  p[c] = pc;
+  snew[c] = sc;
+  rn[c] = rnc;
+  wn[c] = wnc;
+  sums[0] += rnc * rnc;
+  sums[1] += wnc * rnc;
+}
+
+// All tiles of the block: the first kCgPrefetch from the values loaded early.
+template <int DIM, bool FIRST, typename S>
+__device__ __forceinline__ void cg_sweep(
+    const GridK &g, double alpha, double beta, const double *qr, const double *qw,
+    const double *qs, const double *qp, const double *qx, const S *qpsi, int (*ci)[3],
+    const bool *ok, int64_t t0, int64_t t1, const S *__restrict__ psi, const double *__restrict__ r,
+    const double *__restrict__ w, const double *__restrict__ sold, double *__restrict__ rn,
+    double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
+    double *__restrict__ x, double *sums) {
+#pragma unroll
+  for (int q = 0; q < kCgPrefetch; ++q)
+    if (ok[q])
+      cg_cell<DIM, FIRST>(g, alpha, beta, ci[q][0], ci[q][1], ci[q][2], qr[q], qw[q], qs[q], qp[q],
+                          qx[q], qpsi[q], r, w, sold, rn, wn, snew, p, x, sums);
+  for (int64_t t = t0 + kCgPrefetch; t < t1; ++t) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    cg_cell<DIM, FIRST>(g, alpha, beta, i, j, k, r[c], w[c], FIRST ? 0.0 : sold[c],
+                        FIRST ? 0.0 : p[c], x[c], psi[c], r, w, sold, rn, wn, snew, p, x, sums);
+  }
+}
+
 // CG iteration `it` with one global reduction (the recurrences of Chronopoulos and
 // Gear: s = A p is carried as s = w + beta s_old, so r.r and w.r of the new
 // residual are reduced together). Every block forms gamma_it = r.r and delta_it =
@@ -695,18 +778,43 @@ __global__ __launch_bounds__(kThreads) void k_cg_start(GridK g, const S *psi, co
 // be NULL) so that the host can follow the solve without synchronising; a step
 // whose flags show an error stops its solve.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_cg_iter(GridK g, int it, const S *psi,
-                                                      const double *r, const double *w,
-                                                      const double *sold, double *rn, double *wn,
-                                                      double *snew, double *p, double *x,
-                                                      double *partials, CgScal *cs,
-                                                      const int *flags, uint64_t *progress) {
+__global__ __launch_bounds__(kThreads) void k_cg_iter(
+    GridK g, int it, const S *__restrict__ psi, const double *__restrict__ r,
+    const double *__restrict__ w, const double *__restrict__ sold, double *__restrict__ rn,
+    double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
+    double *__restrict__ x, double *partials, CgScal *cs, const int *flags, uint64_t *progress) {
   __shared__ double lds[32];
   // block 0 of this kernel may set `done` while other blocks start: one read per block
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = cs->done;
   __syncthreads();
   if (done0) return;
+  // the cell values of the block's first tiles, loaded before the reduction so that
+  // their latency overlaps it
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  double qr[kCgPrefetch], qw[kCgPrefetch], qs[kCgPrefetch], qp[kCgPrefetch], qx[kCgPrefetch];
+  S qpsi[kCgPrefetch];
+  int ci[kCgPrefetch][3];
+  bool ok[kCgPrefetch];
+#pragma unroll
+  for (int q = 0; q < kCgPrefetch; ++q) {
+    const int64_t t = t0 + q;
+    ok[q] = t < t1 && cell_in_tile<DIM>(g, t, ci[q][0], ci[q][1], ci[q][2]);
+    qr[q] = qw[q] = qs[q] = qp[q] = qx[q] = 0.0;
+    qpsi[q] = S(0);
+    if (ok[q]) {
+      const int64_t c = cidx(g, ci[q][0], ci[q][1], ci[q][2]);
+      qr[q] = r[c];
+      qw[q] = w[c];
+      qx[q] = x[c];
+      qpsi[q] = psi[c];
+      if (it > 0) {
+        qs[q] = sold[c];
+        qp[q] = p[c];
+      }
+    }
+  }
   const int nb = gridDim.x;
   const int par = it & 1;
   double gd[2];
@@ -737,45 +845,12 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(GridK g, int it, const S *
   }
   if (conv || out) return;
   double sums[2] = {0.0, 0.0};
-  int64_t t0, t1;
-  block_tiles(g, t0, t1);
-  if (it == 0) {
-    // p = r, s = w: the old p and s are not read
-    auto rv = [&](int64_t m) { return r[m] - alpha * w[m]; };
-    for (int64_t t = t0; t < t1; ++t) {
-      int i, j, k;
-      if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-      const int64_t c = cidx(g, i, j, k);
-      const double pc = r[c], sc = w[c];
-      x[c] += alpha * pc;
-      const double rc = pc - alpha * sc;
-      const double wc = helm_at<DIM>(g, psi, rv, i, j, k, c, rc);
-      p[c] = pc;
-      snew[c] = sc;
-      rn[c] = rc;
-      wn[c] = wc;
-      sums[0] += rc * rc;
-      sums[1] += wc * rc;
-    }
-  } else {
-    auto rv = [&](int64_t m) { return r[m] - alpha * (w[m] + beta * sold[m]); };
-    for (int64_t t = t0; t < t1; ++t) {
-      int i, j, k;
-      if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-      const int64_t c = cidx(g, i, j, k);
-      const double pc = r[c] + beta * p[c];
-      const double sc = w[c] + beta * sold[c];
-      x[c] += alpha * pc;
-      const double rc = r[c] - alpha * sc;
-      const double wc = helm_at<DIM>(g, psi, rv, i, j, k, c, rc);
-      p[c] = pc;
-      snew[c] = sc;
-      rn[c] = rc;
-      wn[c] = wc;
-      sums[0] += rc * rc;
-      sums[1] += wc * rc;
-    }
-  }
+  if (it == 0)
+    cg_sweep<DIM, true>(g, alpha, beta, qr, qw, qs, qp, qx, qpsi, ci, ok, t0, t1, psi, r, w, sold,
+                        rn, wn, snew, p, x, sums);
+  else
+    cg_sweep<DIM, false>(g, alpha, beta, qr, qw, qs, qp, qx, qpsi, ci, ok, t0, t1, psi, r, w, sold,
+                         rn, wn, snew, p, x, sums);
   block_sum_n<2>(sums, lds);
   if (threadIdx.x == 0) {
     partials[(PART_G + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[0];

@@ -16,10 +16,14 @@ constexpr int MU_SUTHERLAND = 0, MU_CONSTANT = 1;
 constexpr int V_RHO = 0, V_U0 = 1, V_TH = 4, V_P = 5, V_PHOM = 7;
 
 constexpr int kThreads = 256;      // threads per block of the grid kernels
-constexpr int kMaxBlocks = 1024;   // blocks of a grid kernel (4 per CU on 256 CUs)
+#ifndef IBM_MAX_BLOCKS
+#define IBM_MAX_BLOCKS 1024
+#endif
+constexpr int kMaxBlocks = IBM_MAX_BLOCKS;  // blocks of a grid kernel (4 per CU on 256 CUs)
 constexpr int kRedThreads = 1024;  // threads of the single-block marker kernels
 constexpr int kPairBits = 20;      // (cell << 20) | pair id in the sorted pair keys
 constexpr int kMaxNbr = 192;       // neighbours per marker row of the Gram matrix
+constexpr int kFusedMarkers = 1024; // marker capacity up to which one block does a step's marker work
 constexpr int kFaceOut = 14;       // per-face values of the reverse predictor (4 dim + 2)
 
 // Grid, physics and time-step constants, passed by value to every grid kernel.

@@ -116,5 +116,8 @@ void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, doubl
 void run_build_markers(const Launch &L, const Bufs &B, int nc);
 void run_interp_force(const Launch &L, const Bufs &B, double *hist_row);
 void run_spread(const Launch &L, const Bufs &B);
+// interpolation, forcing, totals and spread of one step: one single-block kernel
+// when the candidate capacity is at most kFusedMarkers, else the kernels above
+void run_markers_step(const Launch &L, const Bufs &B, double *hist_row);
 
 }  // namespace ibmk

@@ -353,28 +353,48 @@ __global__ void k_eps_save(const int *mcount, const int *ids, const double *eps,
 // Eq. (5) at each marker from the predictor fields, then Eq. (10) with a_s = 1/dt
 // and Eq. (17) with a_e = 1/dt: F = (rho_L U^d - M)/dt, Q = (c_v rho_L Theta^d - E_L)/dt.
 // Per-marker force on the body -dV eps F and heat given to the fluid dV eps Q.
-template <typename S>
-__global__ void k_interp_force(GridK g, const int *mcount, const int64_t *pcell, const double *pw,
-                               int nslot, const S *rho_s, const S *ms0, const S *ms1,
-                               const S *ms2, const S *E_s, const double *Ud, const double *Tw,
-                               const double *eps, double *mk, double *mforce, double *mheat) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= mcount[0]) return;
-  const S *ms[3] = {ms0, ms1, ms2};
-  const int dim = g.dim, W = 2 * dim + 3;
+template <int DIM, typename S>
+__device__ __forceinline__ void interp_force_one(const GridK &g, int k, const int64_t *pcell,
+                                                 const double *pw, const S *rho_s,
+                                                 const S *const *ms, const S *E_s,
+                                                 const double *Ud, const double *Tw,
+                                                 const double *eps, double *mk, double *mforce,
+                                                 double *mheat) {
+  constexpr int dim = DIM, W = 2 * DIM + 3, nslot = (DIM == 3) ? 27 : 9;
   double rl = 0.0, el = 0.0, M[3] = {0.0, 0.0, 0.0};
-  for (int s = 0; s < nslot; ++s) {
-    const int64_t c = pcell[27 * k + s];
-    const double w = pw[27 * k + s];
-    rl += w * double(rho_s[c]);
-    for (int q = 0; q < dim; ++q) M[q] += w * double(ms[q][c]);
-    el += w * double(E_s[c]);
+  // slots in groups of 9: the loads of a group are issued together (the sums keep
+  // the slot order)
+#pragma unroll
+  for (int s0 = 0; s0 < nslot; s0 += 9) {
+    int64_t cc[9];
+    double ww[9], vr[9], ve[9], vm[DIM][9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+      cc[u] = pcell[27 * k + s0 + u];
+      ww[u] = pw[27 * k + s0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+      vr[u] = double(rho_s[cc[u]]);
+      ve[u] = double(E_s[cc[u]]);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) vm[q][u] = double(ms[q][cc[u]]);
+    }
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+      rl += ww[u] * vr[u];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) M[q] += ww[u] * vm[q][u];
+      el += ww[u] * ve[u];
+    }
   }
   double *o = mk + (int64_t)W * k;
   o[0] = rl;
+#pragma unroll
   for (int q = 0; q < dim; ++q) o[1 + q] = M[q];
   o[1 + dim] = el;
   const double e = eps[k];
+#pragma unroll
   for (int q = 0; q < 3; ++q) {
     double F = 0.0;
     if (q < dim) {
@@ -388,10 +408,21 @@ __global__ void k_interp_force(GridK g, const int *mcount, const int64_t *pcell,
   mheat[k] = g.dV * (e * Q);
 }
 
+template <int DIM, typename S>
+__global__ void k_interp_force(GridK g, const int *mcount, const int64_t *pcell, const double *pw,
+                               const S *rho_s, const S *ms0, const S *ms1, const S *ms2,
+                               const S *E_s, const double *Ud, const double *Tw,
+                               const double *eps, double *mk, double *mforce, double *mheat) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mcount[0]) return;
+  const S *ms[3] = {ms0, ms1, ms2};
+  interp_force_one<DIM>(g, k, pcell, pw, rho_s, ms, E_s, Ud, Tw, eps, mk, mforce, mheat);
+}
+
 // Totals over the markers in use (fixed order); one history row if given.
-__global__ void k_totals(const int *mcount, const double *mforce, const double *mheat,
-                         double *totals, double *hist_row) {
-  __shared__ double lds[64];
+__device__ __forceinline__ void totals_block(const int *mcount, const double *mforce,
+                                             const double *mheat, double *totals,
+                                             double *hist_row, double *lds) {
   const int n = mcount[0];
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -408,31 +439,88 @@ __global__ void k_totals(const int *mcount, const double *mforce, const double *
   }
 }
 
+__global__ void k_totals(const int *mcount, const double *mforce, const double *mheat,
+                         double *totals, double *hist_row) {
+  __shared__ double lds[64];
+  totals_block(mcount, mforce, mheat, totals, hist_row, lds);
+}
+
 // Eq. (7) as a segmented reduction: one thread per cell touched by a support,
 // summing w eps F and w eps Q over its pairs in increasing marker id, then
 // mom** = mom* + dt f and E** = E* + dt q in place.
-template <typename S>
-__global__ void k_spread(GridK g, const int *mcount, const int *seg, const uint64_t *keys,
-                         const double *pw, int nslot, const double *eps, const double *mk, S *ms0,
-                         S *ms1, S *ms2, S *E_s) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= mcount[1]) return;
-  const int dim = g.dim, W = 2 * dim + 3;
+template <int DIM, typename S>
+__device__ __forceinline__ void spread_one(const GridK &g, int s, const int *seg,
+                                           const uint64_t *keys, const double *pw,
+                                           const double *eps, const double *mk, S *const *ms,
+                                           S *E_s) {
+  constexpr int dim = DIM, W = 2 * DIM + 3, nslot = (DIM == 3) ? 27 : 9;
   const int a = seg[s], b = seg[s + 1];
   const int64_t cell = (int64_t)(keys[a] >> kPairBits);
   const uint64_t mask = (1ull << kPairBits) - 1;
   double acc[3] = {0.0, 0.0, 0.0}, aq = 0.0;
-  for (int i = a; i < b; ++i) {
-    const int pid = (int)(keys[i] & mask);
-    const int k = pid / nslot, slot = pid - k * nslot;
-    const double coef = pw[27 * k + slot] * eps[k];
-    const double *o = mk + (int64_t)W * k;
-    for (int q = 0; q < dim; ++q) acc[q] += coef * o[2 + dim + q];
-    aq += coef * o[2 + 2 * dim];
+  // pairs in groups of 4, the loads of a group issued together (sums in pair order)
+  for (int i0 = a; i0 < b; i0 += 4) {
+    double coef[4], f[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      coef[u] = 0.0;
+      f[u][0] = f[u][1] = f[u][2] = f[u][3] = 0.0;
+      if (i0 + u < b) {
+        const int pid = (int)(keys[i0 + u] & mask);
+        const int k = pid / nslot, slot = pid - k * nslot;
+        coef[u] = pw[27 * k + slot] * eps[k];
+        const double *o = mk + (int64_t)W * k;
+#pragma unroll
+        for (int q = 0; q < dim; ++q) f[u][q] = o[2 + dim + q];
+        f[u][3] = o[2 + 2 * dim];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u < b) {
+#pragma unroll
+        for (int q = 0; q < dim; ++q) acc[q] += coef[u] * f[u][q];
+        aq += coef[u] * f[u][3];
+      }
+    }
   }
-  S *ms[3] = {ms0, ms1, ms2};
+#pragma unroll
   for (int q = 0; q < dim; ++q) ms[q][cell] = S(double(ms[q][cell]) + g.dt * acc[q]);
   E_s[cell] = S(double(E_s[cell]) + g.dt * aq);
+}
+
+template <int DIM, typename S>
+__global__ void k_spread(GridK g, const int *mcount, const int *seg, const uint64_t *keys,
+                         const double *pw, const double *eps, const double *mk, S *ms0, S *ms1,
+                         S *ms2, S *E_s) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= mcount[1]) return;
+  S *ms[3] = {ms0, ms1, ms2};
+  spread_one<DIM>(g, s, seg, keys, pw, eps, mk, ms, E_s);
+}
+
+// The three steps above in one block (for small marker sets, where launch latency
+// dominates): interpolation and forcing per marker, the totals, then the spread.
+// The block barrier between the phases also makes the marker values written in one
+// phase visible to the threads of the next.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kRedThreads) void k_markers_fused(
+    GridK g, const int *mcount, const int64_t *pcell, const double *pw, const int *seg,
+    const uint64_t *keys, S *rho_s, S *ms0, S *ms1, S *ms2, S *E_s, const double *Ud,
+    const double *Tw, const double *eps, double *mk, double *mforce, double *mheat,
+    double *totals, double *hist_row) {
+  __shared__ double lds[64];
+  const S *msc[3] = {ms0, ms1, ms2};
+  S *ms[3] = {ms0, ms1, ms2};
+  const int n = mcount[0];
+  for (int k = threadIdx.x; k < n; k += blockDim.x)
+    interp_force_one<DIM>(g, k, pcell, pw, (const S *)rho_s, msc, (const S *)E_s, Ud, Tw, eps,
+                          mk, mforce, mheat);
+  __syncthreads();
+  totals_block(mcount, mforce, mheat, totals, hist_row, lds);
+  const int nseg = mcount[1];
+  for (int s = threadIdx.x; s < nseg; s += blockDim.x)
+    spread_one<DIM>(g, s, seg, keys, pw, eps, mk, ms, E_s);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -474,43 +562,65 @@ void run_build_markers(const Launch &L, const Bufs &B, int nc) {
                      (const int *)B.ids, (const double *)B.eps, B.ceps);
 }
 
+// Launches kernel template K<DIM, S> for the context's dimension and precision.
+#define MK_DISPATCH(L, ...)                      \
+  do {                                           \
+    if ((L).g.dim == 2 && (L).prec == 0) {       \
+      constexpr int DIM = 2;                     \
+      using S = double;                          \
+      __VA_ARGS__;                               \
+    } else if ((L).g.dim == 2) {                 \
+      constexpr int DIM = 2;                     \
+      using S = float;                           \
+      __VA_ARGS__;                               \
+    } else if ((L).prec == 0) {                  \
+      constexpr int DIM = 3;                     \
+      using S = double;                          \
+      __VA_ARGS__;                               \
+    } else {                                     \
+      constexpr int DIM = 3;                     \
+      using S = float;                           \
+      __VA_ARGS__;                               \
+    }                                            \
+  } while (0)
+
 void run_interp_force(const Launch &L, const Bufs &B, double *hist_row) {
-  const int nslot = (L.g.dim == 3) ? 27 : 9;
-  if (L.prec == 0) {
-    hipLaunchKernelGGL(k_interp_force<double>, dim3(nblk(L.nc_cap, 128)), dim3(128), 0, L.st, L.g,
-                       (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
-                       nslot, (const double *)B.rho_s, (const double *)B.mom_s[0],
-                       (const double *)B.mom_s[1], (const double *)B.mom_s[2],
-                       (const double *)B.E_s, (const double *)B.Ud, (const double *)B.Tw,
-                       (const double *)B.eps, B.mk, B.mforce, B.mheat);
-  } else {
-    hipLaunchKernelGGL(k_interp_force<float>, dim3(nblk(L.nc_cap, 128)), dim3(128), 0, L.st, L.g,
-                       (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
-                       nslot, (const float *)B.rho_s, (const float *)B.mom_s[0],
-                       (const float *)B.mom_s[1], (const float *)B.mom_s[2],
-                       (const float *)B.E_s, (const double *)B.Ud, (const double *)B.Tw,
-                       (const double *)B.eps, B.mk, B.mforce, B.mheat);
-  }
+  MK_DISPATCH(L, {
+    hipLaunchKernelGGL((k_interp_force<DIM, S>), dim3(nblk(L.nc_cap, 128)), dim3(128), 0, L.st,
+                       L.g, (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
+                       (const S *)B.rho_s, (const S *)B.mom_s[0], (const S *)B.mom_s[1],
+                       (const S *)B.mom_s[2], (const S *)B.E_s, (const double *)B.Ud,
+                       (const double *)B.Tw, (const double *)B.eps, B.mk, B.mforce, B.mheat);
+  });
   hipLaunchKernelGGL(k_totals, dim3(1), dim3(kRedThreads), 0, L.st, (const int *)B.mcount,
                      (const double *)B.mforce, (const double *)B.mheat, B.totals, hist_row);
+}
+
+void run_markers_step(const Launch &L, const Bufs &B, double *hist_row) {
+  if (L.nc_cap > kFusedMarkers) {
+    run_interp_force(L, B, hist_row);
+    run_spread(L, B);
+    return;
+  }
+  MK_DISPATCH(L, {
+    hipLaunchKernelGGL((k_markers_fused<DIM, S>), dim3(1), dim3(kRedThreads), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
+                       (const int *)B.seg, (const uint64_t *)B.keys, (S *)B.rho_s,
+                       (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s,
+                       (const double *)B.Ud, (const double *)B.Tw, (const double *)B.eps, B.mk,
+                       B.mforce, B.mheat, B.totals, hist_row);
+  });
 }
 
 void run_spread(const Launch &L, const Bufs &B) {
   const int nslot = (L.g.dim == 3) ? 27 : 9;
   const int64_t cap = (int64_t)L.nc_cap * nslot;
-  if (L.prec == 0) {
-    hipLaunchKernelGGL(k_spread<double>, dim3(nblk(cap, 256)), dim3(256), 0, L.st, L.g,
+  MK_DISPATCH(L, {
+    hipLaunchKernelGGL((k_spread<DIM, S>), dim3(nblk(cap, 256)), dim3(256), 0, L.st, L.g,
                        (const int *)B.mcount, (const int *)B.seg, (const uint64_t *)B.keys,
-                       (const double *)B.pw, nslot, (const double *)B.eps, (const double *)B.mk,
-                       (double *)B.mom_s[0], (double *)B.mom_s[1], (double *)B.mom_s[2],
-                       (double *)B.E_s);
-  } else {
-    hipLaunchKernelGGL(k_spread<float>, dim3(nblk(cap, 256)), dim3(256), 0, L.st, L.g,
-                       (const int *)B.mcount, (const int *)B.seg, (const uint64_t *)B.keys,
-                       (const double *)B.pw, nslot, (const double *)B.eps, (const double *)B.mk,
-                       (float *)B.mom_s[0], (float *)B.mom_s[1], (float *)B.mom_s[2],
-                       (float *)B.E_s);
-  }
+                       (const double *)B.pw, (const double *)B.eps, (const double *)B.mk,
+                       (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
+  });
 }
 
 }  // namespace ibmk

@@ -83,6 +83,18 @@ def test_sphere_3d_parity(cuda):
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
 
 
+def test_large_marker_set_parity(cuda):
+    # a candidate capacity above the single-block marker kernel's: the multi-block
+    # interpolation / totals / spread kernels run instead
+    c = inputs.scaled("cfg3", (44, 36, 36), ns=1500)
+    g, o = make_gpu(c), make_oracle(c)
+    hg, _ = g.step(2)
+    ho = o.step(2)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-11, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
+
+
 @pytest.mark.parametrize("variant", ["plain", "lds"])
 @pytest.mark.parametrize("shape", [(133, 75), (36, 30, 26)])
 def test_predictor_variants_parity(cuda, monkeypatch, variant, shape):

@@ -81,17 +81,23 @@ def source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_entry(kernel: str, precision: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, when it was
-    taken on the current kernel source; None otherwise."""
-    path = os.path.join(ROOT, "profiles", "traffic_cylinder1024.json")
+WORKLOAD_LABEL = {"cfg1": "cylinder128", "cfg2a": "cylinder1024", "cfg2b": "cylinder1024",
+                  "cfg2": "cylinder1024", "cfg3": "sphere256", "cfg4": "moving512",
+                  "cfg5": "gradient512"}
+
+
+def traffic_entry(label: str, kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    workload and precision (profiles/traffic_<label>.json), when it was taken on the
+    current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{label}.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
     except Exception:
         return None
-    ent = rec.get(precision, {}).get(kernel)
+    ent = rec.get("classes", {}).get(kernel)
     if not ent or rec.get("source_sha") != source_sha():
         return None
     return ent.get("bytes_per_launch")
@@ -381,14 +387,22 @@ def summarize(directory: str, label: str, command: str):
     open(out_md, "w").write("\n".join(lines) + "\n")
     log(f"wrote {out_md}")
     if traffic:
-        path = os.path.join(ROOT, "profiles", "traffic_cylinder1024.json")
-        rec = json.load(open(path)) if os.path.exists(path) else {}
-        if rec.get("source_sha") != source_sha():
-            rec = {}
-        rec["source_sha"] = source_sha()
-        rec[prec] = traffic
+        path = os.path.join(ROOT, "profiles", f"traffic_{label}.json")
+        rec = {"source_sha": source_sha(), "precision": prec, "classes": traffic,
+               "note": "HBM bytes per launch (per CG iteration for the CG) from FETCH_SIZE + "
+                       "WRITE_SIZE scaled by the copy calibration; see kernels_%s.md" % label}
         json.dump(rec, open(path, "w"), indent=1, sort_keys=True)
         log(f"wrote {path}")
+
+
+def workload_text(case, kept: int, dt: float) -> str:
+    dim = case["dim"]
+    body = "2D heated cylinder" if dim == 2 else "3D heated sphere"
+    cells = "x".join(str(v) for v in case["n"][:dim])
+    box = "x".join("[%g,%g]" % (case["lo"][d], case["hi"][d]) for d in range(dim))
+    return ("%s, %s cells over %s, %d candidate markers (check routine keeps %d), Re %g, "
+            "Ma %g, Tw/Tinf %g, dt %.4e, CG rtol 1e-10"
+            % (body, cells, box, case["ns"], kept, case["Re"], case["Ma"], case["Tw"], dt))
 
 
 def main():
@@ -407,7 +421,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch the copy kernel used to scale HBM counters first")
     ap.add_argument("--summarize", metavar="DIR", help="summarize rocprofv3 output (no GPU)")
-    ap.add_argument("--label", default="cylinder1024_fp64")
+    ap.add_argument("--label", default="cylinder1024_fp64",
+                    help="summary name: <workload>_<precision>, e.g. sphere256_fp32")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
     if args.summarize:
@@ -433,7 +448,8 @@ def main():
     dom = max((k for k in per_kernel if "GBps" in per_kernel[k]),
               key=lambda k: per_kernel[k]["total_ms"])
     d = per_kernel[dom]
-    traffic = traffic_entry(dom, main_p)
+    label = "%s_%s" % (WORKLOAD_LABEL.get(args.workload, args.workload), main_p)
+    traffic = traffic_entry(label, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBps"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4),
             "traffic": traffic,
@@ -459,12 +475,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_p == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "2D heated cylinder, %dx%d cells over [%g,%g]x[%g,%g], %d candidate "
-                               "markers (check routine keeps %d), Re %g, Ma %g, Tw/Tinf %g, dt %.4e, "
-                               "CG rtol 1e-10" % (n[0], n[1], case["lo"][0], case["hi"][0],
-                                                  case["lo"][1], case["hi"][1], case["ns"],
-                                                  ids.shape[0], case["Re"], case["Ma"],
-                                                  case["Tw"], r["solver"].dt),
+        "config": {"workload": workload_text(case, ids.shape[0], r["solver"].dt),
                    "cells": r["N"], "precision": main_p,
                    "cg_iters_per_step": round(r["info"]["cg_iters_total"] / args.steps, 2)},
         "roofline": roof,

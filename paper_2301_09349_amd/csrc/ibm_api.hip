@@ -215,8 +215,8 @@ GridK make_grid(const ibm_grid_desc &d) {
     g.tiles[2] = 1;
   } else {
     g.tiles[0] = (g.n[0] + 63) / 64;
-    g.tiles[1] = (g.n[1] + 1) / 2;
-    g.tiles[2] = (g.n[2] + 1) / 2;
+    g.tiles[1] = (g.n[1] + 3) / 4;
+    g.tiles[2] = g.n[2];
   }
   g.ntiles = (int64_t)g.tiles[0] * g.tiles[1] * g.tiles[2];
   g.nblocks = std::min<int64_t>(((g.ntiles + 7) / 8) * 8, ibmk::kMaxBlocks);

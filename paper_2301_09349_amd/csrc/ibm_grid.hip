@@ -237,12 +237,12 @@ struct PTile;
 #endif
 #ifndef IBM_PRED_TX3D
 #define IBM_PRED_TX3D 16
-#define IBM_PRED_TY3D 8
+#define IBM_PRED_TY3D 4
 #define IBM_PRED_TZ3D 4
 #endif
 #ifndef IBM_PRED_TX3F
 #define IBM_PRED_TX3F 16
-#define IBM_PRED_TY3F 8
+#define IBM_PRED_TY3F 4
 #define IBM_PRED_TZ3F 4
 #endif
 #ifndef IBM_PRED_MAXB
@@ -373,9 +373,18 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
   const int64_t t0 = rank * per, t1 = (t0 + per < ntile) ? t0 + per : ntile;
   const S dt = S(g.dt), gm1 = S(g.gm1);
   for (int64_t t = t0; t < t1; ++t) {
-    const int x0 = (int)(t % ptx) * T::TX;
-    const int y0 = (int)((t / ptx) % pty) * T::TY;
-    const int z0 = (DIM == 3) ? (int)(t / ((int64_t)ptx * pty)) * T::TZ : 0;
+    // 2D: x fastest; 3D: z fastest (a block walks up a column of tiles, so the halo
+    // planes below a tile were loaded by its previous tile)
+    int x0, y0, z0;
+    if (DIM == 2) {
+      x0 = (int)(t % ptx) * T::TX;
+      y0 = (int)(t / ptx) * T::TY;
+      z0 = 0;
+    } else {
+      z0 = (int)(t % ptz) * T::TZ;
+      x0 = (int)((t / ptz) % ptx) * T::TX;
+      y0 = (int)(t / ((int64_t)ptz * ptx)) * T::TY;
+    }
     __syncthreads();  // the previous tile is done with LDS
     // phase 1: primitives of the tile and its halo (points beyond two ghost
     // layers are not needed and not loaded)

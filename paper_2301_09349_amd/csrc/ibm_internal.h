@@ -100,11 +100,13 @@ __device__ __forceinline__ int64_t fidx(const GridK &g, int d, int i, int j, int
   return i + (int64_t)g.fn[d][0] * (j + (int64_t)g.fn[d][1] * k);
 }
 
-// Tiles of kThreads cells (64 x 4 in 2D, 64 x 2 x 2 in 3D), x fastest. A cell
-// kernel runs gridDim.x (a multiple of 8) blocks; block b runs on XCD b % 8 (blocks
-// are dealt round-robin to the 8 XCDs), so it is given the logical rank
+// Tiles of kThreads cells: 64 x 4 (x fastest) in 2D; 64 x 4 x 1 in 3D, ordered z
+// fastest, so that a block's range of tiles walks up a column of planes and the
+// planes below and above a tile are still in L2 when it needs them. A cell kernel
+// runs gridDim.x (a multiple of 8) blocks; block b runs on XCD b % 8 (blocks are
+// dealt round-robin to the 8 XCDs), so it is given the logical rank
 // (b % 8) * (gridDim / 8) + b / 8 and a contiguous range of tiles: the blocks of
-// one XCD sweep one contiguous slab of the grid and share their halos in its L2.
+// one XCD sweep neighbouring tiles and share their halos in its L2.
 __device__ __forceinline__ void block_tiles(const GridK &g, int64_t &t0, int64_t &t1) {
   const int64_t nb = gridDim.x;
   const int64_t b = blockIdx.x;
@@ -117,23 +119,20 @@ __device__ __forceinline__ void block_tiles(const GridK &g, int64_t &t0, int64_t
 // Cell coordinates of this thread in tile t; false outside the grid.
 template <int DIM>
 __device__ __forceinline__ bool cell_in_tile(const GridK &g, int64_t t, int &i, int &j, int &k) {
-  int tx = (int)(t % g.tiles[0]);
-  int64_t r = t / g.tiles[0];
-  int ty = (int)(r % g.tiles[1]);
-  int tz = (int)(r / g.tiles[1]);
-  int lx = threadIdx.x & 63, ly, lz;
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
   if (DIM == 2) {
-    ly = threadIdx.x >> 6;
-    lz = 0;
+    const int tx = (int)(t % g.tiles[0]);
+    const int ty = (int)(t / g.tiles[0]);
     i = tx * 64 + lx;
     j = ty * 4 + ly;
     k = 0;
   } else {
-    ly = (threadIdx.x >> 6) & 1;
-    lz = threadIdx.x >> 7;
+    k = (int)(t % g.tiles[2]);
+    const int64_t r = t / g.tiles[2];
+    const int tx = (int)(r % g.tiles[0]);
+    const int ty = (int)(r / g.tiles[0]);
     i = tx * 64 + lx;
-    j = ty * 2 + ly;
-    k = tz * 2 + lz;
+    j = ty * 4 + ly;
   }
   return i < g.n[0] && j < g.n[1] && k < g.n[2];
 }

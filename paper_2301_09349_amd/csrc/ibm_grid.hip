@@ -572,7 +572,7 @@ template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_setup1(GridK g, StateV<S> st, const S *rho_s,
                                                      const S *ms0, const S *ms1, const S *ms2,
                                                      const S *E_s, S *mh0, S *mh1, S *mh2, S *psi,
-                                                     double *x) {
+                                                     double *x, const S *E_prev) {
   const S *ms[3] = {ms0, ms1, ms2};
   S *mh[3] = {mh0, mh1, mh2};
   const S gm1 = S(g.gm1);
@@ -595,7 +595,9 @@ __global__ __launch_bounds__(kThreads) void k_setup1(GridK g, StateV<S> st, cons
     }
     const S theta = E_s[c] / (rho_s[c] * S(g.cv));
     psi[c] = S(1) / (S(g.R) * theta);
-    x[c] = double(gm1 * st.E[c]);
+    // CG start: p^n, or with the previous step's energy p^n + (p^n - p^{n-1})
+    const double pn = double(gm1 * st.E[c]);
+    x[c] = E_prev ? 2.0 * pn - double(gm1 * E_prev[c]) : pn;
   }
 }
 
@@ -1303,14 +1305,15 @@ void run_predictor(const Launch &L, const Bufs &B, int cur) {
   });
 }
 
-void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
+void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolate) {
+  const void *eprev = extrapolate ? B.E[cur ^ 1] : nullptr;
   if (L.prec == 1) {
     IBM_DISPATCH(L, {
       hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
                          L.st, L.g, state_of<S>(B, cur), (const S *)B.rho_s,
                          (const S *)B.mom_s[0], (const S *)B.mom_s[1], (const S *)B.mom_s[2],
                          (const S *)B.E_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2],
-                         (S *)B.psi, B.x);
+                         (S *)B.psi, B.x, (const S *)eprev);
     });
     if (L.g.dim == 2)
       hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
@@ -1330,7 +1333,8 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
     hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                        L.g, state_of<S>(B, cur), (const S *)B.rho_s, (const S *)B.mom_s[0],
                        (const S *)B.mom_s[1], (const S *)B.mom_s[2], (const S *)B.E_s,
-                       (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], (S *)B.psi, B.x);
+                       (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], (S *)B.psi, B.x,
+                       (const S *)eprev);
     hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
                        L.g, (const S *)B.rho[cur], (const S *)B.mhat[0], (const S *)B.mhat[1],
                        (const S *)B.mhat[2], (S *)B.Fhat[0], (S *)B.Fhat[1], (S *)B.Fhat[2],

@@ -85,8 +85,10 @@ void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
 void run_predictor(const Launch &L, const Bufs &B, int cur);
 size_t predictor_lds_bytes(int dim, int prec);
 void enable_predictor_lds(int dim, int prec);
-// set-up of the pressure equation, ending with the start of its CG (r0, w0 = A r0)
-void run_setup(const Launch &L, const Bufs &B, int cur, int tag);
+// set-up of the pressure equation, ending with the start of its CG (r0, w0 = A r0);
+// extrapolate: the other state slot holds the previous step's state, and the CG
+// starts from p^n + (p^n - p^{n-1}) instead of p^n
+void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolate);
 // start of the FP64 CG from r0 = rv[0]: w0 = A r0 and the first dot products
 void run_cg_start(const Launch &L, const Bufs &B);
 void run_cg_iteration(const Launch &L, const Bufs &B, int it);

@@ -124,10 +124,9 @@ size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32
  * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all work.
  * The state starts as the uniform stream rho = 1, theta = 1, u = U_inf.
  * Environment, read here: IBM_PREDICTOR=plain selects the per-cell predictor
- * instead of the LDS-tiled one; IBM_CG_START=plain starts every FP64 pressure CG
+ * instead of the LDS-tiled one; IBM_CG_START=plain starts every pressure solve
  * from p^n instead of p^n + (p^n - p^{n-1}) (the latter is used after a step of
- * this context; either start converges to the same solution within cg_rtol; the
- * FP32 form always starts from p^n). */
+ * this context; either start converges to the same solution within cg_rtol). */
 ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
                            int32_t tape_steps, void *hip_stream, ibm_ctx **out);
 

@@ -203,14 +203,14 @@ __global__ void k_adj_corr_cell(GridK g, StateV<double> st, SBar sb, SBarW so, c
 // Start of the solve A lambda = rhs from lambda = 0: r0 = rhs; partial b.b (the
 // CG's own start, w0 = A r0, follows).
 template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_adj_cg_init(GridK g, const double *rhs, double *r,
+__global__ __launch_bounds__(kBlockThreads) void k_adj_cg_init(GridK g, const double *rhs, double *r,
                                                           double *lam, double *partials,
                                                           CgScal *cs, int tag) {
   __shared__ double lds[32];
   double s = 0.0;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -444,7 +444,7 @@ __global__ void k_adj_faces(GridK g, int d, StateV<double> st, const double *pp,
   const double lr = 0.5 * (rP + rQ);
   const double U = F / lr;
   const double muf = 0.5 * (muP + muQ);
-  const double lamf = 0.5 * (g.cp * muP / g.Pr + g.cp * muQ / g.Pr);
+  const double lamf = g.cp_Pr * muf;
   double dn[3], tg[3] = {0.0, 0.0, 0.0}, cu[3];
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
@@ -518,7 +518,7 @@ __global__ void k_adj_faces(GridK g, int d, StateV<double> st, const double *pp,
     uQb[q] += dnb[q] * ih;
     uPb[q] -= dnb[q] * ih;
   }
-  const double muh = 0.5 * (mufb + (g.cp / g.Pr) * lamfb);
+  const double muh = 0.5 * (mufb + g.cp_Pr * lamfb);
   const double rhoh = 0.5 * (-Ub * U / lr);
   double *o = fo + foff + f;
   int v = 0;
@@ -845,7 +845,7 @@ void run_adj_correction(const Launch &L, const Bufs &B, int slot, const double *
 
 void run_adj_cg_init(const Launch &L, const Bufs &B, int tag) {
   ADJ_DIM(L, {
-    hipLaunchKernelGGL((k_adj_cg_init<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+    hipLaunchKernelGGL((k_adj_cg_init<DIM>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
                        L.g, (const double *)B.rhs, B.rv[0], B.lam, B.partials, B.cg, tag);
   });
   run_cg_start(L, B);

@@ -99,7 +99,7 @@ struct ibm_ctx {
   // the other state slot holds the state of the step before the current one (the CG
   // start is then extrapolated); cleared whenever the state is set from outside
   bool prev_valid = false;
-  bool extrapolate = true;  // FP64 only; IBM_CG_START=plain turns it off
+  bool extrapolate = true;  // IBM_CG_START=plain turns it off
   int tag = 0;  // step tag, one per step launched
   std::string err;
   CgScal cgh;
@@ -195,6 +195,7 @@ GridK make_grid(const ibm_grid_desc &d) {
   g.mu_inf = 1.0 / d.Re;
   g.S = d.sutherland_S;
   g.Pr = d.Pr;
+  g.cp_Pr = g.cp / d.Pr;
   g.p_inf = g.R;
   g.dV = g.h[0] * g.h[1] * (d.dim == 3 ? g.h[2] : 1.0);
   if (d.dt > 0.0) {
@@ -223,7 +224,8 @@ GridK make_grid(const ibm_grid_desc &d) {
     g.tiles[2] = g.n[2];
   }
   g.ntiles = (int64_t)g.tiles[0] * g.tiles[1] * g.tiles[2];
-  g.nblocks = std::min<int64_t>(((g.ntiles + 7) / 8) * 8, ibmk::kMaxBlocks);
+  const int64_t groups = ibmk::kBlockThreads / ibmk::kTile;
+  g.nblocks = std::min<int64_t>(((g.ntiles + groups - 1) / groups + 7) / 8 * 8, ibmk::kMaxBlocks);
   return g;
 }
 
@@ -274,10 +276,12 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   if (d.precision == IBM_FP32) {
     // FP32 form: x ping-pong for the refinement; inner CG vectors in FP32
     B.x2 = C.take<double>(N);
-    B.r32 = C.take<float>(N);
-    B.p32[0] = C.take<float>(N);
-    B.p32[1] = C.take<float>(N);
-    B.q32 = C.take<float>(N);
+    for (int s = 0; s < 2; ++s) {
+      B.rv32[s] = C.take<float>(N);
+      B.wv32[s] = C.take<float>(N);
+      B.sv32[s] = C.take<float>(N);
+    }
+    B.pv32 = C.take<float>(N);
     B.d32 = C.take<float>(N);
     B.pv = nullptr;
     for (int s = 0; s < 2; ++s) B.rv[s] = B.wv[s] = B.sv[s] = nullptr;
@@ -289,7 +293,8 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
       B.sv[s] = C.take<double>(N);
     }
     B.x2 = nullptr;
-    B.r32 = B.p32[0] = B.p32[1] = B.q32 = B.d32 = nullptr;
+    for (int s = 0; s < 2; ++s) B.rv32[s] = B.wv32[s] = B.sv32[s] = nullptr;
+    B.pv32 = B.d32 = nullptr;
   }
   B.partials = C.take<double>((size_t)ibmk::PART_REGIONS * ibmk::kMaxBlocks);
   B.cg = C.take<CgScal>(1);
@@ -528,9 +533,8 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
     const size_t need = ibmk::predictor_lds_bytes(desc->dim, desc->precision);
     const char *env = std::getenv("IBM_PREDICTOR");
     ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
-    // (measured: fewer FP64 iterations; no gain for the FP32 form's inner solves)
     const char *cgs = std::getenv("IBM_CG_START");
-    ctx->extrapolate = desc->precision == IBM_FP64 && !(cgs && std::strcmp(cgs, "plain") == 0);
+    ctx->extrapolate = !(cgs && std::strcmp(cgs, "plain") == 0);
     if (ctx->L.pred_lds && need > 65536) ibmk::enable_predictor_lds(desc->dim, desc->precision);
   }
   ctx->tape_cap = tape_steps;

@@ -17,11 +17,6 @@ __device__ __forceinline__ S mu_of(const GridK &g, S th) {
   S sut = S(g.S);
   return S(g.mu_inf) * th * sqrt(th) * (S(1) + sut) / (th + sut);
 }
-// lambda = c_p mu / Pr
-template <typename S>
-__device__ __forceinline__ S lam_of(const GridK &g, S th) {
-  return S(g.cp) * mu_of(g, th) / S(g.Pr);
-}
 // van Leer limited face value from the upwind (C), downwind (D) and far-upwind
 // (U) cell values: phi_C + (1/2) psi(r) (phi_D - phi_C), written without r.
 template <typename S>
@@ -96,7 +91,7 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
   load_prim<DIM>(g, st, Q[0], Q[1], Q[2], rQ, uQ, thQ, pQ);
   uf = F / (S(0.5) * (rP + rQ));
   const S muf = S(0.5) * (mu_of(g, thP) + mu_of(g, thQ));
-  const S lamf = S(0.5) * (lam_of(g, thP) + lam_of(g, thQ));
+  const S lamf = S(g.cp_Pr) * muf;
   const S ih = S(g.ih[d]);
   S dn[3], tg[3] = {S(0), S(0), S(0)};
 #pragma unroll
@@ -246,7 +241,7 @@ struct PTile;
 #define IBM_PRED_TZ3F 4
 #endif
 #ifndef IBM_PRED_MAXB
-#define IBM_PRED_MAXB kMaxBlocks
+#define IBM_PRED_MAXB 1024
 #endif
 template <>
 struct PTile<2, double> {
@@ -303,7 +298,7 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int d
   const S muP = lv[(DIM + 2) * NP + iP], muQ = lv[(DIM + 2) * NP + iQ];
   uf = F / (S(0.5) * (rP + rQ));
   const S muf = S(0.5) * (muP + muQ);
-  const S lamf = S(0.5) * (S(g.cp) * muP / S(g.Pr) + S(g.cp) * muQ / S(g.Pr));
+  const S lamf = S(g.cp_Pr) * muf;
   const S ih = S(g.ih[d]);
   S dn[3], tg[3] = {S(0), S(0), S(0)};
 #pragma unroll
@@ -569,7 +564,7 @@ __global__ void k_flux_from_mom(GridK g, StateV<S> st, int d) {
 // Pressure set-up, part 1: p^n = (gamma-1) E^n; m^ = mom** + dt G_c p^n;
 // theta** = E**/(rho* c_v); psi = 1/(R theta**); CG start x = p^n.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_setup1(GridK g, StateV<S> st, const S *rho_s,
+__global__ __launch_bounds__(kBlockThreads) void k_setup1(GridK g, StateV<S> st, const S *rho_s,
                                                      const S *ms0, const S *ms1, const S *ms2,
                                                      const S *E_s, S *mh0, S *mh1, S *mh2, S *psi,
                                                      double *x, const S *E_prev) {
@@ -578,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_setup1(GridK g, StateV<S> st, cons
   const S gm1 = S(g.gm1);
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -640,7 +635,7 @@ __device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, in
 // F^ = lin_f(m^) (boundary rules), b = rho^n - dt D(F^) + outflow terms,
 // r = b - A x, p = r; per-block FP64 partial sums of b.b and r.r.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, const S *mh0,
+__global__ __launch_bounds__(kBlockThreads) void k_setup2(GridK g, const S *rho_n, const S *mh0,
                                                      const S *mh1, const S *mh2, S *Fh0, S *Fh1,
                                                      S *Fh2, const S *psi, const double *x,
                                                      double *b, double *r0, double *partials,
@@ -651,7 +646,7 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
   double bb = 0.0;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -698,13 +693,13 @@ __global__ __launch_bounds__(kThreads) void k_setup2(GridK g, const S *rho_n, co
 // Start of the single-reduction CG (Chronopoulos and Gear's variant): w0 = A r0
 // and the per-block partials of gamma_0 = r0.r0 and delta_0 = w0.r0.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_cg_start(GridK g, const S *psi, const double *r0,
+__global__ __launch_bounds__(kBlockThreads) void k_cg_start(GridK g, const S *psi, const double *r0,
                                                        double *w0, double *partials) {
   __shared__ double lds[32];
   double sums[2] = {0.0, 0.0};
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -766,7 +761,7 @@ __device__ __forceinline__ void cg_sweep(
     if (ok[q])
       cg_cell<DIM, FIRST>(g, alpha, beta, ci[q][0], ci[q][1], ci[q][2], qr[q], qw[q], qs[q], qp[q],
                           qx[q], qpsi[q], r, w, sold, rn, wn, snew, p, x, sums);
-  for (int64_t t = t0 + kCgPrefetch; t < t1; ++t) {
+  for (int64_t t = t0 + tile_group() + kCgPrefetch * tile_groups(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -789,7 +784,7 @@ __device__ __forceinline__ void cg_sweep(
 // be NULL) so that the host can follow the solve without synchronising; a step
 // whose flags show an error stops its solve.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_cg_iter(
+__global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
     GridK g, int it, const S *__restrict__ psi, const double *__restrict__ r,
     const double *__restrict__ w, const double *__restrict__ sold, double *__restrict__ rn,
     double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
@@ -810,7 +805,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(
   bool ok[kCgPrefetch];
 #pragma unroll
   for (int q = 0; q < kCgPrefetch; ++q) {
-    const int64_t t = t0 + q;
+    const int64_t t = t0 + tile_group() + q * tile_groups();
     ok[q] = t < t1 && cell_in_tile<DIM>(g, t, ci[q][0], ci[q][1], ci[q][2]);
     qr[q] = qw[q] = qs[q] = qp[q] = qx[q] = 0.0;
     qpsi[q] = S(0);
@@ -870,22 +865,24 @@ __global__ __launch_bounds__(kThreads) void k_cg_iter(
 }
 
 // ------------------------------------- FP32 form: pressure by iterative refinement
-// x and the outer residual r = b - A x are FP64; each inner solve A d = r runs CG
-// on FP32 vectors with FP64 dot products to a relative 1e-4 (or kInnerMax
-// iterations), then x += d and the FP64 residual is formed again. The solve ends
-// when the FP64 residual meets |r| <= rtol |b|.
+// x and the outer residual r = b - A x are FP64; each inner solve A d = r runs the
+// single-reduction CG on FP32 vectors with FP64 dot products to a relative 1e-4 (or
+// kInnerMax iterations), then x += d and the FP64 residual is formed again. The
+// solve ends when the FP64 residual meets |r| <= rtol |b|. One kernel per
+// iteration: an inner CG iteration, or a refinement that also starts the next
+// inner solve (w = A r of the new FP32 residual).
 constexpr double kInnerTol2 = 1e-8;
 constexpr int kInnerMax = 60;
 
 // Set-up part 2 of the FP32 form: as k_setup2, with the FP64 start residual
-// handed to the inner solve as FP32 (r32) and d = 0.
+// handed to the inner solve as FP32 (r32) and its FP64 r.r as the outer partial.
 template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_setup2m(GridK g, const float *rho_n, const float *mh0,
+__global__ __launch_bounds__(kBlockThreads) void k_setup2m(GridK g, const float *rho_n, const float *mh0,
                                                       const float *mh1, const float *mh2,
                                                       float *Fh0, float *Fh1, float *Fh2,
                                                       const float *psi, const double *x,
-                                                      double *b, float *r32, float *d32,
-                                                      double *partials, CgScal *cs, int tag) {
+                                                      double *b, float *r32, double *partials,
+                                                      CgScal *cs, int tag) {
   using S = float;
   __shared__ double lds[32];
   const S *mh[3] = {mh0, mh1, mh2};
@@ -893,7 +890,7 @@ __global__ __launch_bounds__(kThreads) void k_setup2m(GridK g, const float *rho_
   double sums[2] = {0.0, 0.0};
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -920,14 +917,13 @@ __global__ __launch_bounds__(kThreads) void k_setup2m(GridK g, const float *rho_
     const double rc = bc_ - ax;
     b[c] = bc_;
     r32[c] = float(rc);
-    d32[c] = 0.0f;
     sums[0] += bc_ * bc_;
     sums[1] += rc * rc;
   }
   block_sum_n<2>(sums, lds);
   if (threadIdx.x == 0) {
     partials[PART_BB * kMaxBlocks + blockIdx.x] = sums[0];
-    partials[PART_RR * kMaxBlocks + blockIdx.x] = sums[1];
+    partials[PART_O * kMaxBlocks + blockIdx.x] = sums[1];
     if (blockIdx.x == 0) {
       cs->done = 0;
       cs->iters = 0;
@@ -937,12 +933,12 @@ __global__ __launch_bounds__(kThreads) void k_setup2m(GridK g, const float *rho_
       cs->xpar[0] = 0;
       cs->inner_it[0] = 0;
       cs->rr_in0[0] = 0.0;
-      cs->skip_b = 0;
     }
   }
 }
 
-// FP32 pressure operator at one cell (single precision arithmetic).
+// FP32 pressure operator at one cell (single precision arithmetic); v(i, j, k, m)
+// gives the value of cell m at (i, j, k).
 template <int DIM, typename VF>
 __device__ __forceinline__ float helm32_at(const GridK &g, const float *psi, VF v, int i, int j,
                                            int k, int64_t c, float vc) {
@@ -957,10 +953,10 @@ __device__ __forceinline__ float helm32_at(const GridK &g, const float *psi, VF 
       const int n = g.n[d];
       float gf;
       if (ix[d] >= 0 && ix[d] < n) {
-        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+        gf = (v(ix[0], ix[1], ix[2], cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
       } else if (g.bc[d][0] == BC_PERIODIC) {
         ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
-        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+        gf = (v(ix[0], ix[1], ix[2], cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
       } else {
         gf = (g.bc[d][side] == BC_OUTFLOW) ? (-2.0f * vc) * ih : 0.0f;
       }
@@ -970,70 +966,111 @@ __device__ __forceinline__ float helm32_at(const GridK &g, const float *psi, VF 
   return psi[c] * vc - float(g.dt * g.dt) * lap;
 }
 
-// Iteration `it`, part a, of the FP32 form. Every block forms the same r.r from
-// the partials and takes the same decision:
-//  - after an outer residual: converged -> done; else start an inner solve
-//    (p = r), as CG part a;
-//  - inside an inner solve: converged to 1e-4 relative (or kInnerMax) -> refine:
-//    x_new = x + d (also at the neighbours, on the fly), r = b - A x_new in FP64,
-//    r32 = r, d = 0, partial r.r; otherwise CG part a with beta.
+// Start of an FP32 inner solve after the set-up: w = A r32 and the partials of
+// r32.r32 and w.r32 (FP64 sums).
 template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_mcg_a(GridK g, int it, const float *psi,
-                                                    const double *b, double *x0, double *x1,
-                                                    float *r32, const float *pold, float *pnew,
-                                                    float *q32, float *d32, double *partials,
-                                                    CgScal *cs, const int *flags,
-                                                    uint64_t *progress) {
+__global__ __launch_bounds__(kBlockThreads) void k_mcg_start(GridK g, const float *psi, const float *r32,
+                                                        float *w32, double *partials) {
   __shared__ double lds[32];
+  double sums[2] = {0.0, 0.0};
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const float rc = r32[c];
+    const float wc =
+        helm32_at<DIM>(g, psi, [&](int, int, int, int64_t m) { return r32[m]; }, i, j, k, c, rc);
+    w32[c] = wc;
+    sums[0] += double(rc) * double(rc);
+    sums[1] += double(wc) * double(rc);
+  }
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[PART_G * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[PART_D * kMaxBlocks + blockIdx.x] = sums[1];
+  }
+}
+
+// Iteration `it` of the FP32 form. Every block forms the same sums from the
+// partials of the previous kernel and takes the same decision:
+//  - after a refinement (or the set-up): outer |r| <= rtol |b| -> done; otherwise
+//    the first iteration of an inner solve (p = r, s = w, d = alpha p);
+//  - inside an inner solve: converged to 1e-4 relative (or kInnerMax) -> refine:
+//    x' = x + d, r = b - A x' in FP64, r32 = r, w = A r32 with r32 of the
+//    neighbours formed on the fly; otherwise an inner single-reduction iteration.
+// Scalars the kernel reads sit in slot it & 1 of CgScal, those it writes in the
+// other slot; r, w, s likewise ping-pong.
+template <int DIM>
+__global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
+    GridK g, int it, const float *__restrict__ psi, const double *__restrict__ b, double *x0,
+    double *x1, const float *__restrict__ r, const float *__restrict__ w,
+    const float *__restrict__ sold, float *__restrict__ rn, float *__restrict__ wn,
+    float *__restrict__ snew, float *__restrict__ p, float *__restrict__ d, double *partials,
+    CgScal *cs, const int *flags, uint64_t *progress) {
+  __shared__ double lds[48];
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = cs->done;
   __syncthreads();
   if (done0) return;
-  const int nb = gridDim.x, sl = it & 1, sn = (it + 1) & 1;
-  const double rr = sum_partials(partials + PART_RR * kMaxBlocks, nb, lds);
+  const int nb = gridDim.x, sl = it & 1, sn = sl ^ 1;
+  const bool outer = cs->outer[sl] != 0;
+  double gdo[3] = {0.0, 0.0, 0.0};
+  sum_partials2(partials + (PART_G + sl) * kMaxBlocks, partials + (PART_D + sl) * kMaxBlocks, nb,
+                lds, gdo);
+  if (outer) gdo[2] = sum_partials(partials + (PART_O + sl) * kMaxBlocks, nb, lds);
+  const double gam = gdo[0], del = gdo[1], rro = gdo[2];
   const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
   const double tol2 = cs->tol2;
   const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
                   (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
-  const bool outer = cs->outer[sl] != 0;
   const int xp = cs->xpar[sl];
-  const bool bad = err != 0 || !(rr == rr);
+  const bool bad = err != 0;
   bool conv = false, out = false, refine = false;
-  double beta = 0.0;
+  double alpha = 0.0, beta = 0.0;
+  int ni = 0;
   if (outer) {
-    conv = rr <= tol2 * bb;
-    out = !conv && (it >= cs->maxit || bad);
+    conv = rro <= tol2 * bb;
+    out = !conv && (it >= cs->maxit || bad || !(rro == rro));
+    alpha = gam / del;
   } else {
-    const int ni = cs->inner_it[sl];
-    refine = rr <= kInnerTol2 * cs->rr_in0[sl] || ni >= kInnerMax || it >= cs->maxit || bad;
-    if (!refine) beta = rr / cs->rr[(it - 1) & 1];
+    ni = cs->inner_it[sl];
+    // an inner solve ends at 1e-4 of its start, or once its residual already meets
+    // the outer tolerance (the refinement then checks that in FP64)
+    refine = gam <= kInnerTol2 * cs->rr_in0[sl] || gam <= tol2 * bb || ni >= kInnerMax ||
+             it >= cs->maxit || bad || !(gam == gam);
+    if (!refine) {
+      beta = gam / cs->rr[(it - 1) & 1];
+      alpha = gam / (del - beta * gam / cs->alpha[(it - 1) & 1]);
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (it == 0) cs->bb = bb;
-    cs->rr[sl] = rr;
     cs->iters = it;
     if (outer) {
-      cs->res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+      cs->res = bb > 0.0 ? sqrt(rro / bb) : 0.0;
       if (conv || out) {
         cs->done = conv ? 1 : 2;
         cs->xfinal = xp;
       } else {
-        cs->rr_in0[sn] = rr;
+        cs->rr[sl] = gam;
+        cs->alpha[sl] = alpha;
+        cs->rr_in0[sn] = gam;
         cs->inner_it[sn] = 1;
         cs->outer[sn] = 0;
         cs->xpar[sn] = xp;
-        cs->skip_b = 0;
       }
     } else if (refine) {
       cs->outer[sn] = 1;
       cs->xpar[sn] = xp ^ 1;
-      cs->skip_b = 1;
     } else {
+      cs->rr[sl] = gam;
+      cs->alpha[sl] = alpha;
       cs->rr_in0[sn] = cs->rr_in0[sl];
-      cs->inner_it[sn] = cs->inner_it[sl] + 1;
+      cs->inner_it[sn] = ni + 1;
       cs->outer[sn] = 0;
       cs->xpar[sn] = xp;
-      cs->skip_b = 0;
     }
     if (progress)
       __hip_atomic_store(progress, pack_progress(cs->step_tag, it, err, conv ? 1 : out ? 2 : 0),
@@ -1042,73 +1079,67 @@ __global__ __launch_bounds__(kThreads) void k_mcg_a(GridK g, int it, const float
   if (conv || out) return;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  double part = 0.0;
+  double sums[3] = {0.0, 0.0, 0.0};
   if (refine) {
     const double *xo = xp ? x1 : x0;
-    double *xn = xp ? x0 : x1;
-    auto xv = [&](int64_t m) { return xo[m] + double(d32[m]); };
-    for (int64_t t = t0; t < t1; ++t) {
+    double *xnew = xp ? x0 : x1;
+    auto xv = [&](int64_t m) { return xo[m] + double(d[m]); };
+    // the new FP32 residual of cell m at (ii, jj, kk), as that cell forms its own
+    auto r32v = [&](int ii, int jj, int kk, int64_t m) {
+      const double xm = xv(m);
+      return float(b[m] - helm_at<DIM>(g, psi, xv, ii, jj, kk, m, xm));
+    };
+    for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
       int i, j, k;
       if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
       const int64_t c = cidx(g, i, j, k);
       const double xc = xv(c);
       const double rc = b[c] - helm_at<DIM>(g, psi, xv, i, j, k, c, xc);
-      xn[c] = xc;
-      r32[c] = float(rc);
-      part += rc * rc;
+      const float r32c = float(rc);
+      const float wc = helm32_at<DIM>(g, psi, r32v, i, j, k, c, r32c);
+      xnew[c] = xc;
+      rn[c] = r32c;
+      wn[c] = wc;
+      sums[0] += double(r32c) * double(r32c);
+      sums[1] += double(wc) * double(r32c);
+      sums[2] += rc * rc;
     }
-    // d is cleared once every block has read it: done by part b of this iteration
   } else {
-    // the first iteration of an inner solve takes p = r (the old p is not read)
-    const float bf = float(beta);
-    auto pv = [&](int64_t m) { return outer ? r32[m] : r32[m] + bf * pold[m]; };
-    for (int64_t t = t0; t < t1; ++t) {
+    const float af = float(alpha), bf = float(beta);
+    for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
       int i, j, k;
       if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
       const int64_t c = cidx(g, i, j, k);
-      const float pc = pv(c);
-      const float qc = helm32_at<DIM>(g, psi, pv, i, j, k, c, pc);
-      pnew[c] = pc;
-      q32[c] = qc;
-      part += double(pc) * double(qc);
+      float pc, sc, rnc, wnc;
+      if (outer) {  // first iteration of an inner solve: the old p, s, d are not read
+        pc = r[c];
+        sc = w[c];
+        d[c] = af * pc;
+        rnc = pc - af * sc;
+        auto rv = [&](int, int, int, int64_t m) { return r[m] - af * w[m]; };
+        wnc = helm32_at<DIM>(g, psi, rv, i, j, k, c, rnc);
+      } else {
+        pc = r[c] + bf * p[c];
+        sc = w[c] + bf * sold[c];
+        d[c] += af * pc;
+        rnc = r[c] - af * sc;
+        auto rv = [&](int, int, int, int64_t m) { return r[m] - af * (w[m] + bf * sold[m]); };
+        wnc = helm32_at<DIM>(g, psi, rv, i, j, k, c, rnc);
+      }
+      p[c] = pc;
+      snew[c] = sc;
+      rn[c] = rnc;
+      wn[c] = wnc;
+      sums[0] += double(rnc) * double(rnc);
+      sums[1] += double(wnc) * double(rnc);
     }
   }
-  double s = block_sum(part, lds);
-  if (threadIdx.x == 0)
-    partials[(refine ? PART_RR : PART_PQ) * kMaxBlocks + blockIdx.x] = s;
-}
-
-// Part b of the FP32 form: d += alpha p, r -= alpha q (FP32), partial r.r (FP64);
-// after a refinement it clears d instead.
-template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_mcg_b(GridK g, int it, float *d32, float *r32,
-                                                    const float *p, const float *q32,
-                                                    double *partials, CgScal *cs) {
-  __shared__ double lds[32];
-  if (cs->done) return;
-  int64_t t0, t1;
-  block_tiles(g, t0, t1);
-  if (cs->skip_b) {
-    for (int64_t t = t0; t < t1; ++t) {
-      int i, j, k;
-      if (cell_in_tile<DIM>(g, t, i, j, k)) d32[cidx(g, i, j, k)] = 0.0f;
-    }
-    return;
+  block_sum_n<3>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[(PART_G + sn) * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[(PART_D + sn) * kMaxBlocks + blockIdx.x] = sums[1];
+    if (refine) partials[(PART_O + sn) * kMaxBlocks + blockIdx.x] = sums[2];
   }
-  const double pq = sum_partials(partials + PART_PQ * kMaxBlocks, gridDim.x, lds);
-  const float alpha = float(cs->rr[it & 1] / pq);
-  double rr = 0.0;
-  for (int64_t t = t0; t < t1; ++t) {
-    int i, j, k;
-    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-    const int64_t c = cidx(g, i, j, k);
-    d32[c] += alpha * p[c];
-    const float rc = r32[c] - alpha * q32[c];
-    r32[c] = rc;
-    rr += double(rc) * double(rc);
-  }
-  double s = block_sum(rr, lds);
-  if (threadIdx.x == 0) partials[PART_RR * kMaxBlocks + blockIdx.x] = s;
 }
 
 // Pressure with its ghost rule (zero gradient at inflow and slip, p_inf on
@@ -1123,7 +1154,7 @@ __device__ __forceinline__ double pres_at(const GridK &g, const double *x, int i
 // m^{n+1} = m^ - dt G_c p; E^{n+1} = rho^{n+1} c_v theta**. Writes the other
 // state copy; flags non-finite results; per-block partial sums of the mass.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, StateV<S> nxt,
+__global__ __launch_bounds__(kBlockThreads) void k_correct(GridK g, StateV<S> cur, StateV<S> nxt,
                                                       const S *rho_s, const S *E_s, const S *mh0,
                                                       const S *mh1, const S *mh2, const S *Fh0,
                                                       const S *Fh1, const S *Fh2,
@@ -1148,7 +1179,7 @@ __global__ __launch_bounds__(kThreads) void k_correct(GridK g, StateV<S> cur, St
   bool bad = false;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -1309,33 +1340,34 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolat
   const void *eprev = extrapolate ? B.E[cur ^ 1] : nullptr;
   if (L.prec == 1) {
     IBM_DISPATCH(L, {
-      hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
+      hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
                          L.st, L.g, state_of<S>(B, cur), (const S *)B.rho_s,
                          (const S *)B.mom_s[0], (const S *)B.mom_s[1], (const S *)B.mom_s[2],
                          (const S *)B.E_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2],
                          (S *)B.psi, B.x, (const S *)eprev);
     });
     if (L.g.dim == 2)
-      hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+      hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st, L.g,
                          (const float *)B.rho[cur], (const float *)B.mhat[0],
                          (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
                          (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
-                         (const double *)B.x, B.b, B.r32, B.d32, B.partials, B.cg, tag);
+                         (const double *)B.x, B.b, B.rv32[0], B.partials, B.cg, tag);
     else
-      hipLaunchKernelGGL((k_setup2m<3>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
+      hipLaunchKernelGGL((k_setup2m<3>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st, L.g,
                          (const float *)B.rho[cur], (const float *)B.mhat[0],
                          (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
                          (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
-                         (const double *)B.x, B.b, B.r32, B.d32, B.partials, B.cg, tag);
+                         (const double *)B.x, B.b, B.rv32[0], B.partials, B.cg, tag);
+    run_cg_start(L, B);
     return;
   }
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+    hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
                        L.g, state_of<S>(B, cur), (const S *)B.rho_s, (const S *)B.mom_s[0],
                        (const S *)B.mom_s[1], (const S *)B.mom_s[2], (const S *)B.E_s,
                        (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], (S *)B.psi, B.x,
                        (const S *)eprev);
-    hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+    hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
                        L.g, (const S *)B.rho[cur], (const S *)B.mhat[0], (const S *)B.mhat[1],
                        (const S *)B.mhat[2], (S *)B.Fhat[0], (S *)B.Fhat[1], (S *)B.Fhat[2],
                        (const S *)B.psi, (const double *)B.x, B.b, B.rv[0], B.partials, B.cg,
@@ -1345,40 +1377,47 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolat
 }
 
 void run_cg_start(const Launch &L, const Bufs &B) {
+  if (L.prec == 1) {
+    if (L.g.dim == 2)
+      hipLaunchKernelGGL((k_mcg_start<2>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
+                         L.g, (const float *)B.psi, (const float *)B.rv32[0], B.wv32[0],
+                         B.partials);
+    else
+      hipLaunchKernelGGL((k_mcg_start<3>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
+                         L.g, (const float *)B.psi, (const float *)B.rv32[0], B.wv32[0],
+                         B.partials);
+    return;
+  }
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_cg_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+    hipLaunchKernelGGL((k_cg_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
                        L.g, (const S *)B.psi, (const double *)B.rv[0], B.wv[0], B.partials);
   });
 }
 
-int cg_parts(const Launch &L) { return L.prec == 1 ? 2 : 1; }
+int cg_parts(const Launch &) { return 1; }
 
 template <int DIM>
-static void run_mcg_half(const Launch &L, const Bufs &B, int it, int part) {
-  float *pold = B.p32[it & 1], *pnew = B.p32[(it & 1) ^ 1];
-  if (part == 0)
-    hipLaunchKernelGGL((k_mcg_a<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
-                       it, (const float *)B.psi, (const double *)B.b, B.x, B.x2, B.r32,
-                       (const float *)pold, pnew, B.q32, B.d32, B.partials, B.cg,
-                       (const int *)B.flags, B.progress);
-  else
-    hipLaunchKernelGGL((k_mcg_b<DIM>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st, L.g,
-                       it, B.d32, B.r32, (const float *)pnew, (const float *)B.q32, B.partials,
-                       B.cg);
+static void run_mcg_iter(const Launch &L, const Bufs &B, int it) {
+  const int a = it & 1, b = a ^ 1;
+  hipLaunchKernelGGL((k_mcg_iter<DIM>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st, L.g,
+                     it, (const float *)B.psi, (const double *)B.b, B.x, B.x2,
+                     (const float *)B.rv32[a], (const float *)B.wv32[a], (const float *)B.sv32[a],
+                     B.rv32[b], B.wv32[b], B.sv32[b], B.pv32, B.d32, B.partials, B.cg,
+                     (const int *)B.flags, B.progress);
 }
 
 void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
+  if (part != 0) return;
   if (L.prec == 1) {
     if (L.g.dim == 2)
-      run_mcg_half<2>(L, B, it, part);
+      run_mcg_iter<2>(L, B, it);
     else
-      run_mcg_half<3>(L, B, it, part);
+      run_mcg_iter<3>(L, B, it);
     return;
   }
-  if (part != 0) return;
   IBM_DISPATCH(L, {
     const int a = it & 1, b = a ^ 1;
-    hipLaunchKernelGGL((k_cg_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0, L.st,
+    hipLaunchKernelGGL((k_cg_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
                        L.g, it, (const S *)B.psi, (const double *)B.rv[a], (const double *)B.wv[a],
                        (const double *)B.sv[a], B.rv[b], B.wv[b], B.sv[b], B.pv, B.x, B.partials,
                        B.cg, (const int *)B.flags, B.progress);
@@ -1391,7 +1430,7 @@ void run_cg_iteration(const Launch &L, const Bufs &B, int it) {
 
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_correct<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
+    hipLaunchKernelGGL((k_correct<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
                        L.st, L.g, state_of<S>(B, cur), state_of<S>(B, cur ^ 1),
                        (const S *)B.rho_s, (const S *)B.E_s, (const S *)B.mhat[0],
                        (const S *)B.mhat[1], (const S *)B.mhat[2], (const S *)B.Fhat[0],

@@ -15,11 +15,19 @@ constexpr int MU_SUTHERLAND = 0, MU_CONSTANT = 1;
 // kinds of cell variables, selecting the ghost rule of a boundary side
 constexpr int V_RHO = 0, V_U0 = 1, V_TH = 4, V_P = 5, V_PHOM = 7;
 
-constexpr int kThreads = 256;      // threads per block of the grid kernels
-#ifndef IBM_MAX_BLOCKS
-#define IBM_MAX_BLOCKS 1024
+constexpr int kTile = 256;         // cells per tile = threads per tile group
+#ifndef IBM_BLOCK_THREADS
+#define IBM_BLOCK_THREADS 1024
 #endif
-constexpr int kMaxBlocks = IBM_MAX_BLOCKS;  // blocks of a grid kernel (4 per CU on 256 CUs)
+#ifndef IBM_MAX_BLOCKS
+#define IBM_MAX_BLOCKS 256
+#endif
+// Cell kernels: blocks of kBlockThreads threads (kBlockThreads / kTile tile groups),
+// at most kMaxBlocks of them (one per CU on 256 CUs). Few large blocks keep the
+// per-block partial sums that every block of the next kernel adds up few.
+constexpr int kBlockThreads = IBM_BLOCK_THREADS;
+constexpr int kMaxBlocks = IBM_MAX_BLOCKS;
+constexpr int kThreads = 256;      // threads per block of the predictor kernels
 constexpr int kRedThreads = 1024;  // threads of the single-block marker kernels
 constexpr int kPairBits = 20;      // (cell << 20) | pair id in the sorted pair keys
 constexpr int kMaxNbr = 192;       // neighbours per marker row of the Gram matrix
@@ -37,6 +45,7 @@ struct GridK {
   int bc[3][2];
   int conv, visc;
   double dt, R, cv, inv_cv, cp, gm1, mu_inf, S, Pr, p_inf, dV;
+  double cp_Pr;       // c_p / Pr: lambda = cp_Pr mu
   double U_inf[3];
   int tiles[3];       // tiles per direction of the cell kernels
   int64_t ntiles;     // tiles in all
@@ -65,7 +74,6 @@ struct CgScal {
   int outer[2];      // 1: the partial sums come from an FP64 outer residual
   int xpar[2];       // which x buffer holds the current solution
   int xfinal;        // x buffer of the finished solve (read by the correction)
-  int skip_b;        // 1: part b of this iteration has nothing to do
 };
 
 // Progress word the CG posts to host memory after each convergence test:
@@ -90,7 +98,8 @@ enum {
   PART_MASS = 3,
   PART_G = 4,
   PART_D = 6,
-  PART_REGIONS = 8
+  PART_O = 8,  // FP32 form: FP64 r.r of the outer residual (two regions)
+  PART_REGIONS = 10
 };
 
 __device__ __forceinline__ int64_t cidx(const GridK &g, int i, int j, int k) {
@@ -100,7 +109,7 @@ __device__ __forceinline__ int64_t fidx(const GridK &g, int d, int i, int j, int
   return i + (int64_t)g.fn[d][0] * (j + (int64_t)g.fn[d][1] * k);
 }
 
-// Tiles of kThreads cells: 64 x 4 (x fastest) in 2D; 64 x 4 x 1 in 3D, ordered z
+// Tiles of kTile cells: 64 x 4 (x fastest) in 2D; 64 x 4 x 1 in 3D, ordered z
 // fastest, so that a block's range of tiles walks up a column of planes and the
 // planes below and above a tile are still in L2 when it needs them. A cell kernel
 // runs gridDim.x (a multiple of 8) blocks; block b runs on XCD b % 8 (blocks are
@@ -116,10 +125,15 @@ __device__ __forceinline__ void block_tiles(const GridK &g, int64_t &t0, int64_t
   t1 = t0 + per < g.ntiles ? t0 + per : g.ntiles;
 }
 
+// The tile group of this thread within its block, and the number of groups: a
+// block's range of tiles is shared out round-robin over its groups.
+__device__ __forceinline__ int64_t tile_group() { return threadIdx.x / kTile; }
+__device__ __forceinline__ int64_t tile_groups() { return blockDim.x / kTile; }
+
 // Cell coordinates of this thread in tile t; false outside the grid.
 template <int DIM>
 __device__ __forceinline__ bool cell_in_tile(const GridK &g, int64_t t, int &i, int &j, int &k) {
-  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const int lx = threadIdx.x & 63, ly = (threadIdx.x % kTile) >> 6;
   if (DIM == 2) {
     const int tx = (int)(t % g.tiles[0]);
     const int ty = (int)(t / g.tiles[0]);

@@ -17,9 +17,10 @@ struct Bufs {
   // pressure CG (FP64, single-reduction form): x and p in place; r, w = A r and
   // s = A p ping-pong between iterations (their neighbour values are read)
   double *b, *x, *pv, *rv[2], *wv[2], *sv[2];
-  // FP32 form: second FP64 solution buffer and the FP32 inner-CG vectors
+  // FP32 form: second FP64 solution buffer and the FP32 inner-CG vectors (r, w, s
+  // ping-pong; p and the correction d in place)
   double *x2;
-  float *r32, *p32[2], *q32, *d32;
+  float *rv32[2], *wv32[2], *sv32[2], *pv32, *d32;
   double *partials;  // per-block partial sums, 4 per block
   CgScal *cg;
   double *scal;      // [0] mass

@@ -152,18 +152,22 @@ def run_forward(case, precision, steps, warmup):
     s = make_solver(case, precision)
     hist = torch.zeros((max(steps, warmup, 1), 4), dtype=torch.float64, device="cuda:0")
     log(f"bench: {case['n']} {precision}, dt={s.dt:.4e}, warmup {warmup}, steps {steps}")
+    it_all = 0
     if warmup:
-        s.step(warmup, hist_out=hist)
+        _, wi = s.step(warmup, hist_out=hist)
+        it_all += wi["cg_iters_total"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, info = s.step(steps, hist_out=hist)
+    it_all += info["cg_iters_total"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     h_timed = hist[:steps].clone()
     s.profile(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    s.step(steps, hist=False)
+    _, pi = s.step(steps, hist=False)
+    it_all += pi["cg_iters_total"]
     torch.cuda.synchronize()
     elapsed_prof = time.perf_counter() - t1
     prof = s.profile_read()
@@ -183,7 +187,7 @@ def run_forward(case, precision, steps, warmup):
     return {"solver": s, "N": N, "elapsed": elapsed, "info": info, "per_kernel": per_kernel,
             "hist": h_timed, "value": N * steps / elapsed / 1e6,
             "ms_per_step": 1e3 * elapsed / steps,
-            "ms_per_step_profiled": 1e3 * elapsed_prof / steps}
+            "ms_per_step_profiled": 1e3 * elapsed_prof / steps, "cg_iters_all": it_all}
 
 
 def fp32_error(r64, r32):
@@ -297,14 +301,16 @@ def summarize(directory: str, label: str, command: str):
     out_md = os.path.join(ROOT, "profiles", f"kernels_{label}.md")
     bj = json.loads(open(os.path.join(directory, "stats.json")).read().strip().splitlines()[-1])
     total_steps = bj["warmup"] + 2 * bj["steps"]
-    iters = bj["config"]["cg_iters_per_step"]
+    # CG iterations per step over every step of the profiled run (warm-up included)
+    iters = bj.get("cg_iters_all_steps", bj["config"]["cg_iters_per_step"] * total_steps)
+    iters = iters / total_steps
     prec = bj["config"]["precision"]
     lines = [f"# rocprofv3 summary: {label}", "", "Commands (from the repository root):", ""]
     for c in command.split(";;"):
         lines.append(f"    {c.strip()}")
     lines += ["", f"The profiled program runs {bj['warmup']} warm-up steps, {bj['steps']} steps "
               f"without and {bj['steps']} steps with the library's event timing "
-              f"({total_steps} steps, {iters} CG iterations per step); per-step figures divide "
+              f"({total_steps} steps, {iters:.2f} CG iterations per step); per-step figures divide "
               "the kernel totals by the steps.", "",
               "## Kernel trace (--kernel-trace --stats)", "",
               "| kernel | class | calls | avg us | total ms | % |", "|---|---|---|---|---|---|"]
@@ -483,6 +489,7 @@ def main():
                         **({"GBps": round(v["GBps"], 1)} if "GBps" in v else {})}
                     for k, v in per_kernel.items()},
         "ms_per_step_profiled": round(r["ms_per_step_profiled"], 4),
+        "cg_iters_all_steps": r["cg_iters_all"],
     }
     if ro is not None:
         r64, r32 = (r, ro) if main_p == "fp64" else (ro, r)

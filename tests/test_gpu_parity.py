@@ -95,6 +95,24 @@ def test_large_marker_set_parity(cuda):
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-6)])
+def test_cg_start_does_not_change_the_solution(cuda, monkeypatch, precision, tol):
+    # the pressure solve starts from p^n + (p^n - p^{n-1}) after a step, or from p^n
+    # with IBM_CG_START=plain; both converge to the same solution within cg_rtol
+    c = _channel((90, 70), 60)
+    g1 = make_gpu(c, precision)
+    monkeypatch.setenv("IBM_CG_START", "plain")
+    g2 = make_gpu(c, precision)
+    monkeypatch.delenv("IBM_CG_START")
+    _, i1 = g1.step(30)
+    _, i2 = g2.step(30)
+    assert i1["cg_iters_total"] < i2["cg_iters_total"]
+    r1, m1, e1, _ = g1.get_state()
+    r2, m2, e2, _ = g2.get_state()
+    for a, b in ((r1, r2), (m1, m2), (e1, e2)):
+        assert rel_l2(to_np(a), to_np(b)) < tol
+
+
 @pytest.mark.parametrize("variant", ["plain", "lds"])
 @pytest.mark.parametrize("shape", [(133, 75), (36, 30, 26)])
 def test_predictor_variants_parity(cuda, monkeypatch, variant, shape):

@@ -716,8 +716,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_start(GridK g, const S *ps
   }
 }
 
-constexpr int kCgPrefetch = 4;  // tiles per block whose cell values are loaded early
-
 // Update of one cell in a CG iteration (see k_cg_iter): rc, wc, sc0, pc0, xc, psc
 // are r, w, s_old, p_old, x, psi at the cell. FIRST: p = r, s = w (the old p, s are
 // not read).
@@ -747,21 +745,17 @@ __device__ __forceinline__ void cg_cell(const GridK &g, double alpha, double bet
   sums[1] += wnc * rnc;
 }
 
-// All tiles of the block: the first kCgPrefetch from the values loaded early.
+// All tiles of this thread's tile group.
 template <int DIM, bool FIRST, typename S>
-__device__ __forceinline__ void cg_sweep(
-    const GridK &g, double alpha, double beta, const double *qr, const double *qw,
-    const double *qs, const double *qp, const double *qx, const S *qpsi, int (*ci)[3],
-    const bool *ok, int64_t t0, int64_t t1, const S *__restrict__ psi, const double *__restrict__ r,
-    const double *__restrict__ w, const double *__restrict__ sold, double *__restrict__ rn,
-    double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
-    double *__restrict__ x, double *sums) {
-#pragma unroll
-  for (int q = 0; q < kCgPrefetch; ++q)
-    if (ok[q])
-      cg_cell<DIM, FIRST>(g, alpha, beta, ci[q][0], ci[q][1], ci[q][2], qr[q], qw[q], qs[q], qp[q],
-                          qx[q], qpsi[q], r, w, sold, rn, wn, snew, p, x, sums);
-  for (int64_t t = t0 + tile_group() + kCgPrefetch * tile_groups(); t < t1; t += tile_groups()) {
+__device__ __forceinline__ void cg_sweep(const GridK &g, double alpha, double beta, int64_t t0,
+                                         int64_t t1, const S *__restrict__ psi,
+                                         const double *__restrict__ r,
+                                         const double *__restrict__ w,
+                                         const double *__restrict__ sold, double *__restrict__ rn,
+                                         double *__restrict__ wn, double *__restrict__ snew,
+                                         double *__restrict__ p, double *__restrict__ x,
+                                         double *sums) {
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
@@ -795,32 +789,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
   if (threadIdx.x == 0) done0 = cs->done;
   __syncthreads();
   if (done0) return;
-  // the cell values of the block's first tiles, loaded before the reduction so that
-  // their latency overlaps it
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  double qr[kCgPrefetch], qw[kCgPrefetch], qs[kCgPrefetch], qp[kCgPrefetch], qx[kCgPrefetch];
-  S qpsi[kCgPrefetch];
-  int ci[kCgPrefetch][3];
-  bool ok[kCgPrefetch];
-#pragma unroll
-  for (int q = 0; q < kCgPrefetch; ++q) {
-    const int64_t t = t0 + tile_group() + q * tile_groups();
-    ok[q] = t < t1 && cell_in_tile<DIM>(g, t, ci[q][0], ci[q][1], ci[q][2]);
-    qr[q] = qw[q] = qs[q] = qp[q] = qx[q] = 0.0;
-    qpsi[q] = S(0);
-    if (ok[q]) {
-      const int64_t c = cidx(g, ci[q][0], ci[q][1], ci[q][2]);
-      qr[q] = r[c];
-      qw[q] = w[c];
-      qx[q] = x[c];
-      qpsi[q] = psi[c];
-      if (it > 0) {
-        qs[q] = sold[c];
-        qp[q] = p[c];
-      }
-    }
-  }
   const int nb = gridDim.x;
   const int par = it & 1;
   double gd[2];
@@ -852,11 +822,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
   if (conv || out) return;
   double sums[2] = {0.0, 0.0};
   if (it == 0)
-    cg_sweep<DIM, true>(g, alpha, beta, qr, qw, qs, qp, qx, qpsi, ci, ok, t0, t1, psi, r, w, sold,
-                        rn, wn, snew, p, x, sums);
+    cg_sweep<DIM, true>(g, alpha, beta, t0, t1, psi, r, w, sold, rn, wn, snew, p, x, sums);
   else
-    cg_sweep<DIM, false>(g, alpha, beta, qr, qw, qs, qp, qx, qpsi, ci, ok, t0, t1, psi, r, w, sold,
-                         rn, wn, snew, p, x, sums);
+    cg_sweep<DIM, false>(g, alpha, beta, t0, t1, psi, r, w, sold, rn, wn, snew, p, x, sums);
   block_sum_n<2>(sums, lds);
   if (threadIdx.x == 0) {
     partials[(PART_G + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[0];

@@ -42,10 +42,10 @@ def kernel_words(cls: str, dim: int, precision: str = "fp64") -> int:
     distinct array element read or written once; face arrays counted as one word
     per cell and direction)."""
     # single-reduction CG: r, w, s_old, p, x (FP32 form: d), psi -> r', w', s, p, x (d);
-    # the FP32 form's refinement iterations (2-3 per solve) move more and are
-    # counted as inner iterations
+    # the FP32 form's refinement and restart launches (2-3 of each per solve) are
+    # counted as iterations
     cg = 6 + 5
-    start = 3    # CG start: r0, psi -> w0
+    start = 3 if precision == "fp64" else 0   # FP64 CG start: r0, psi -> w0
     return {
         "predictor": (2 * dim + 2) + (dim + 2),          # rho, m, E, F -> rho*, m*, E*
         "setup": (dim + 3) + (dim + 2) + (dim + 3) + (dim + 3) + start,
@@ -56,7 +56,7 @@ def kernel_words(cls: str, dim: int, precision: str = "fp64") -> int:
 
 # kernel symbol prefix -> kernel class of the library's event timing
 KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start", "setup"),
-                ("k_mcg_start", "setup"), ("k_cg_iter", "cg"), ("k_mcg_iter", "cg"),
+                ("k_cg_iter", "cg"), ("k_mcg_iter", "cg"),
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
                 ("k_totals", "markers")]
 

@@ -841,6 +841,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
 // inner solve (w = A r of the new FP32 residual).
 constexpr double kInnerTol2 = 1e-8;
 constexpr int kInnerMax = 60;
+enum { MS_INNER = 0, MS_START = 1, MS_FIRST = 2 };  // stages, see k_mcg_iter
 
 // Set-up part 2 of the FP32 form: as k_setup2, with the FP64 start residual
 // handed to the inner solve as FP32 (r32) and its FP64 r.r as the outer partial.
@@ -897,7 +898,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_setup2m(GridK g, const float 
       cs->iters = 0;
       cs->step_tag = tag;
       cs->xfinal = 0;
-      cs->outer[0] = 1;
+      cs->outer[0] = MS_START;
       cs->xpar[0] = 0;
       cs->inner_it[0] = 0;
       cs->rr_in0[0] = 0.0;
@@ -934,42 +935,15 @@ __device__ __forceinline__ float helm32_at(const GridK &g, const float *psi, VF 
   return psi[c] * vc - float(g.dt * g.dt) * lap;
 }
 
-// Start of an FP32 inner solve after the set-up: w = A r32 and the partials of
-// r32.r32 and w.r32 (FP64 sums).
-template <int DIM>
-__global__ __launch_bounds__(kBlockThreads) void k_mcg_start(GridK g, const float *psi, const float *r32,
-                                                        float *w32, double *partials) {
-  __shared__ double lds[32];
-  double sums[2] = {0.0, 0.0};
-  int64_t t0, t1;
-  block_tiles(g, t0, t1);
-  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
-    int i, j, k;
-    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-    const int64_t c = cidx(g, i, j, k);
-    const float rc = r32[c];
-    const float wc =
-        helm32_at<DIM>(g, psi, [&](int, int, int, int64_t m) { return r32[m]; }, i, j, k, c, rc);
-    w32[c] = wc;
-    sums[0] += double(rc) * double(rc);
-    sums[1] += double(wc) * double(rc);
-  }
-  block_sum_n<2>(sums, lds);
-  if (threadIdx.x == 0) {
-    partials[PART_G * kMaxBlocks + blockIdx.x] = sums[0];
-    partials[PART_D * kMaxBlocks + blockIdx.x] = sums[1];
-  }
-}
-
-// Iteration `it` of the FP32 form. Every block forms the same sums from the
-// partials of the previous kernel and takes the same decision:
-//  - after a refinement (or the set-up): outer |r| <= rtol |b| -> done; otherwise
-//    the first iteration of an inner solve (p = r, s = w, d = alpha p);
-//  - inside an inner solve: converged to 1e-4 relative (or kInnerMax) -> refine:
-//    x' = x + d, r = b - A x' in FP64, r32 = r, w = A r32 with r32 of the
-//    neighbours formed on the fly; otherwise an inner single-reduction iteration.
-// Scalars the kernel reads sit in slot it & 1 of CgScal, those it writes in the
-// other slot; r, w, s likewise ping-pong.
+// Stages of the FP32 form's solve, one kernel each (the stage a kernel runs is in
+// CgScal::outer of its slot):
+//  MS_START: the partials hold the FP64 r.r of the outer residual r (set-up or a
+//            refinement): |r| <= rtol |b| -> done; otherwise w = A r32 and the
+//            partials of r32.r32, w.r32 (r32 is copied to the next slot);
+//  MS_FIRST: first iteration of an inner solve: p = r, s = w, d = alpha p;
+//  MS_INNER: inner single-reduction iteration, or, once the inner residual is 1e-4
+//            of its start or meets the outer tolerance, a refinement: x' = x + d,
+//            r = b - A x' in FP64, r32 = r, partial of r.r (-> MS_START).
 template <int DIM>
 __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
     GridK g, int it, const float *__restrict__ psi, const double *__restrict__ b, double *x0,
@@ -977,18 +951,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
     const float *__restrict__ sold, float *__restrict__ rn, float *__restrict__ wn,
     float *__restrict__ snew, float *__restrict__ p, float *__restrict__ d, double *partials,
     CgScal *cs, const int *flags, uint64_t *progress) {
-  __shared__ double lds[48];
+  __shared__ double lds[32];
   __shared__ int done0;
   if (threadIdx.x == 0) done0 = cs->done;
   __syncthreads();
   if (done0) return;
   const int nb = gridDim.x, sl = it & 1, sn = sl ^ 1;
-  const bool outer = cs->outer[sl] != 0;
-  double gdo[3] = {0.0, 0.0, 0.0};
-  sum_partials2(partials + (PART_G + sl) * kMaxBlocks, partials + (PART_D + sl) * kMaxBlocks, nb,
-                lds, gdo);
-  if (outer) gdo[2] = sum_partials(partials + (PART_O + sl) * kMaxBlocks, nb, lds);
-  const double gam = gdo[0], del = gdo[1], rro = gdo[2];
+  const int stage = cs->outer[sl];
+  double gd[2] = {0.0, 0.0}, rro = 0.0;
+  if (stage == MS_START)
+    rro = sum_partials(partials + (PART_O + sl) * kMaxBlocks, nb, lds);
+  else
+    sum_partials2(partials + (PART_G + sl) * kMaxBlocks, partials + (PART_D + sl) * kMaxBlocks,
+                  nb, lds, gd);
+  const double gam = gd[0], del = gd[1];
   const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
   const double tol2 = cs->tol2;
   const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
@@ -998,9 +974,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
   bool conv = false, out = false, refine = false;
   double alpha = 0.0, beta = 0.0;
   int ni = 0;
-  if (outer) {
+  if (stage == MS_START) {
     conv = rro <= tol2 * bb;
     out = !conv && (it >= cs->maxit || bad || !(rro == rro));
+  } else if (stage == MS_FIRST) {
     alpha = gam / del;
   } else {
     ni = cs->inner_it[sl];
@@ -1016,28 +993,31 @@ __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (it == 0) cs->bb = bb;
     cs->iters = it;
-    if (outer) {
+    if (stage == MS_START) {
       cs->res = bb > 0.0 ? sqrt(rro / bb) : 0.0;
       if (conv || out) {
         cs->done = conv ? 1 : 2;
         cs->xfinal = xp;
       } else {
-        cs->rr[sl] = gam;
-        cs->alpha[sl] = alpha;
-        cs->rr_in0[sn] = gam;
-        cs->inner_it[sn] = 1;
-        cs->outer[sn] = 0;
+        cs->outer[sn] = MS_FIRST;
         cs->xpar[sn] = xp;
       }
+    } else if (stage == MS_FIRST) {
+      cs->rr[sl] = gam;
+      cs->alpha[sl] = alpha;
+      cs->rr_in0[sn] = gam;
+      cs->inner_it[sn] = 1;
+      cs->outer[sn] = MS_INNER;
+      cs->xpar[sn] = xp;
     } else if (refine) {
-      cs->outer[sn] = 1;
+      cs->outer[sn] = MS_START;
       cs->xpar[sn] = xp ^ 1;
     } else {
       cs->rr[sl] = gam;
       cs->alpha[sl] = alpha;
       cs->rr_in0[sn] = cs->rr_in0[sl];
       cs->inner_it[sn] = ni + 1;
-      cs->outer[sn] = 0;
+      cs->outer[sn] = MS_INNER;
       cs->xpar[sn] = xp;
     }
     if (progress)
@@ -1047,39 +1027,43 @@ __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
   if (conv || out) return;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  double sums[3] = {0.0, 0.0, 0.0};
-  if (refine) {
+  double sums[2] = {0.0, 0.0};
+  if (stage == MS_START) {
+    for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+      int i, j, k;
+      if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+      const int64_t c = cidx(g, i, j, k);
+      const float rc = r[c];
+      const float wc = helm32_at<DIM>(g, psi, [&](int, int, int, int64_t m) { return r[m]; }, i,
+                                      j, k, c, rc);
+      rn[c] = rc;
+      wn[c] = wc;
+      sums[0] += double(rc) * double(rc);
+      sums[1] += double(wc) * double(rc);
+    }
+  } else if (refine) {
     const double *xo = xp ? x1 : x0;
     double *xnew = xp ? x0 : x1;
     auto xv = [&](int64_t m) { return xo[m] + double(d[m]); };
-    // the new FP32 residual of cell m at (ii, jj, kk), as that cell forms its own
-    auto r32v = [&](int ii, int jj, int kk, int64_t m) {
-      const double xm = xv(m);
-      return float(b[m] - helm_at<DIM>(g, psi, xv, ii, jj, kk, m, xm));
-    };
     for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
       int i, j, k;
       if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
       const int64_t c = cidx(g, i, j, k);
       const double xc = xv(c);
       const double rc = b[c] - helm_at<DIM>(g, psi, xv, i, j, k, c, xc);
-      const float r32c = float(rc);
-      const float wc = helm32_at<DIM>(g, psi, r32v, i, j, k, c, r32c);
       xnew[c] = xc;
-      rn[c] = r32c;
-      wn[c] = wc;
-      sums[0] += double(r32c) * double(r32c);
-      sums[1] += double(wc) * double(r32c);
-      sums[2] += rc * rc;
+      rn[c] = float(rc);
+      sums[0] += rc * rc;
     }
   } else {
+    const bool first = stage == MS_FIRST;
     const float af = float(alpha), bf = float(beta);
     for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
       int i, j, k;
       if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
       const int64_t c = cidx(g, i, j, k);
       float pc, sc, rnc, wnc;
-      if (outer) {  // first iteration of an inner solve: the old p, s, d are not read
+      if (first) {  // the old p, s, d are not read
         pc = r[c];
         sc = w[c];
         d[c] = af * pc;
@@ -1102,11 +1086,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
       sums[1] += double(wnc) * double(rnc);
     }
   }
-  block_sum_n<3>(sums, lds);
+  block_sum_n<2>(sums, lds);
   if (threadIdx.x == 0) {
-    partials[(PART_G + sn) * kMaxBlocks + blockIdx.x] = sums[0];
-    partials[(PART_D + sn) * kMaxBlocks + blockIdx.x] = sums[1];
-    if (refine) partials[(PART_O + sn) * kMaxBlocks + blockIdx.x] = sums[2];
+    if (refine) {
+      partials[(PART_O + sn) * kMaxBlocks + blockIdx.x] = sums[0];
+    } else {
+      partials[(PART_G + sn) * kMaxBlocks + blockIdx.x] = sums[0];
+      partials[(PART_D + sn) * kMaxBlocks + blockIdx.x] = sums[1];
+    }
   }
 }
 
@@ -1345,20 +1332,10 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolat
 }
 
 void run_cg_start(const Launch &L, const Bufs &B) {
-  if (L.prec == 1) {
-    if (L.g.dim == 2)
-      hipLaunchKernelGGL((k_mcg_start<2>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
-                         L.g, (const float *)B.psi, (const float *)B.rv32[0], B.wv32[0],
-                         B.partials);
-    else
-      hipLaunchKernelGGL((k_mcg_start<3>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
-                         L.g, (const float *)B.psi, (const float *)B.rv32[0], B.wv32[0],
-                         B.partials);
-    return;
-  }
+  if (L.prec == 1) return;  // the FP32 form's first iteration kernel starts its solve
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_cg_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
-                       L.g, (const S *)B.psi, (const double *)B.rv[0], B.wv[0], B.partials);
+    hipLaunchKernelGGL((k_cg_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, (const S *)B.psi, (const double *)B.rv[0], B.wv[0], B.partials);
   });
 }
 

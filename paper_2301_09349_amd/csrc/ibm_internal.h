@@ -71,7 +71,7 @@ struct CgScal {
   // sit in slot it & 1; block 0 of that kernel writes slot (it + 1) & 1.
   double rr_in0[2];  // r.r at the start of the current inner solve
   int inner_it[2];   // inner iterations since the last refinement
-  int outer[2];      // 1: the partial sums come from an FP64 outer residual
+  int outer[2];      // stage of the FP32 form's iteration kernel (MS_*)
   int xpar[2];       // which x buffer holds the current solution
   int xfinal;        // x buffer of the finished solve (read by the correction)
 };

@@ -268,6 +268,30 @@ def run_adjoint(steps: int, checkpoint: int, warmup: int):
             "grad_norm": gnorm}
 
 
+def run_sphere(steps: int, warmup: int):
+    """The 3D workload (256^3 heated sphere, 3200 candidate markers, Re 300, Ma 0.3,
+    Tw 1.5) in both forms: throughput and the CG iteration's achieved bandwidth (its
+    working set, ~2 GB in FP64, is far larger than the 256 MB Infinity Cache)."""
+    from paper_2301_09349_amd import inputs
+
+    case = inputs.case("cfg3", cg_rtol=1e-10)
+    res = {"steps": steps}
+    for prec in ("fp64", "fp32"):
+        r = run_forward(case, prec, steps, warmup)
+        if "workload" not in res:
+            kept = r["solver"].markers_in_use()[0].shape[0]
+            res["workload"] = workload_text(case, kept, r["solver"].dt)
+        cg = r["per_kernel"]["cg"]
+        res[prec] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                     "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
+                     "cg_us": round(cg["avg_us"], 2), "cg_GBps": round(cg["GBps"], 1),
+                     "cg_frac": round(cg["GBps"] / HBM_PEAK_GBS, 4),
+                     "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
+                                             for k, v in r["per_kernel"].items()}}
+        del r
+    return res
+
+
 def calibrate_copy():
     """A plain streaming kernel of known size for scaling the HBM counters: negation
     of CALIB_ELEMS float64 values (8 B read + 8 B written each), three launches."""
@@ -423,6 +447,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 sphere figures")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch the copy kernel used to scale HBM counters first")
     ap.add_argument("--summarize", metavar="DIR", help="summarize rocprofv3 output (no GPU)")
@@ -502,6 +527,10 @@ def main():
         del ro
     del r
     torch.cuda.empty_cache()
+    if not args.no_3d and args.workload != "cfg3":
+        log("bench: 256^3 sphere ...")
+        out["sphere256"] = run_sphere(30, 10)
+        torch.cuda.empty_cache()
     if not args.no_adjoint:
         log(f"bench: adjoint leg, {args.adjoint_steps} steps ...")
         out["adjoint"] = run_adjoint(args.adjoint_steps, 50, 10)

@@ -211,7 +211,7 @@ def fp32_error(r64, r32):
             "heat_mean": abs(float(h32[:, 3].mean() / h64[:, 3].mean()) - 1.0)}
 
 
-def run_adjoint(steps: int, checkpoint: int, warmup: int):
+def run_adjoint(steps: int, checkpoint: int, warmup: int, precision: str = "fp64"):
     """Adjoint/forward time ratio on the gradient workload: forward = `steps` plain
     steps; backward = the checkpointed reverse pass over the same steps (segment
     re-run with the tape on, then one adjoint step per step)."""
@@ -222,7 +222,7 @@ def run_adjoint(steps: int, checkpoint: int, warmup: int):
     from paper_2301_09349_amd.adjoint import Rollout, nusselt_scale, _set_state_vector
 
     case = inputs.case("cfg5", convection=inputs.CONV_LINEAR)
-    s = make_solver(case, "fp64", tape_steps=checkpoint)
+    s = make_solver(case, precision, tape_steps=checkpoint)
     if warmup:
         s.step(warmup)
     roll = Rollout(s, steps, checkpoint)
@@ -265,7 +265,7 @@ def run_adjoint(steps: int, checkpoint: int, warmup: int):
             "adjoint_step_ms": round(1e3 * t_adj / steps, 4),
             "ratio": round(t_rev / t_fwd, 3),
             "ratio_adjoint_step_only": round(t_adj / t_fwd, 3),
-            "grad_norm": gnorm}
+            "grad_norm": gnorm, "precision": precision}
 
 
 def run_sphere(steps: int, warmup: int):
@@ -534,6 +534,9 @@ def main():
     if not args.no_adjoint:
         log(f"bench: adjoint leg, {args.adjoint_steps} steps ...")
         out["adjoint"] = run_adjoint(args.adjoint_steps, 50, 10)
+        a32 = run_adjoint(args.adjoint_steps, 50, 10, "fp32")
+        out["adjoint_fp32"] = {k: a32[k] for k in ("forward_ms_per_step", "backward_ms_per_step",
+                                                   "ratio", "grad_norm")}
     if not args.no_cpu:
         log(f"bench: timing the oracle on {args.cpu_steps} steps ...")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -111,8 +111,8 @@ typedef struct {
 } ibm_step_info;
 
 /* Bytes of device workspace needed for a grid, a marker capacity and a tape
- * of `tape_steps` recorded steps (0: no adjoint; > 0 needs precision IBM_FP64).
- * A tape step holds the FP64 state and pressure, (dim + 3) N + sum NF doubles;
+ * of `tape_steps` recorded steps (0: no adjoint). A tape step holds the state in
+ * the context's storage type ((dim + 2) N + sum NF words) and the FP64 pressure (N);
  * tape_steps > 0 also adds the adjoint's work buffers (about (9 dim + 12) N +
  * (4 dim + 3) sum NF doubles). Returns 0 for an invalid descriptor. */
 size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32_t tape_steps);
@@ -120,7 +120,7 @@ size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32
 /* Creates a context on the current HIP device. `dev_workspace` (device memory,
  * at least ibm_workspace_bytes(desc, desc->max_markers, tape_steps) bytes,
  * 256-byte aligned) must stay valid until ibm_destroy; `tape_steps` is the
- * capacity used in that size computation (IBM_E_ARG if > 0 with IBM_FP32).
+ * capacity used in that size computation.
  * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all work.
  * The state starts as the uniform stream rho = 1, theta = 1, u = U_inf.
  * Environment, read here: IBM_PREDICTOR=plain selects the per-cell predictor
@@ -211,9 +211,11 @@ ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
  * operator is symmetric, so its adjoint is one more CG solve), set-up, forcing and
  * spreading (spreading transposes to interpolation and back), predictor). Not in
  * the paper: it serves gradients of time-averaged Nusselt number and drag with
- * respect to the wall temperatures. Requirements: FP64 context, linear
- * convection, markers at rest (IBM_E_ARG otherwise); IBM_E_STATE if tape_index is
- * not a recorded step.
+ * respect to the wall temperatures. Requirements: linear convection, markers at
+ * rest (IBM_E_ARG otherwise); IBM_E_STATE if tape_index is not a recorded step.
+ * In the FP32 form the forward pieces are recomputed in FP32 from the FP32 record
+ * and the reverse runs in FP64 (cotangents, transposed stencils, adjoint CG): the
+ * gradient along the FP32 trajectory.
  *   tape_index     0 = first step of the recording call
  *   state_bar_in   device double: cotangent of the state after the step, in the
  *                  ibm_set_state layout (rho [N], mom [dim][N], E [N], F [sum NF])

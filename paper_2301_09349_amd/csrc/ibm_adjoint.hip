@@ -129,8 +129,8 @@ struct SBarW {
 // Cotangent of the corrected face flux, per face entry: F^{n+1} feeds the state
 // directly and rho^{n+1} = rho^n - dt D(F^{n+1}), whose cotangent is
 // rhoT = rho_bar' + E_bar' c_v theta** (E^{n+1} = rho^{n+1} c_v theta**).
-template <int DIM>
-__global__ void k_adj_corr_face(GridK g, int d, SBar sb, const double *rho_s, const double *E_s,
+template <int DIM, typename S>
+__global__ void k_adj_corr_face(GridK g, int d, SBar sb, const S *rho_s, const S *E_s,
                                 double *fbar) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= g.NF[d]) return;
@@ -153,17 +153,17 @@ __global__ void k_adj_corr_face(GridK g, int d, SBar sb, const double *rho_s, co
 
 // Per cell: rho_bar (init), theta**_bar, and the right-hand side of the adjoint
 // pressure equation: p_bar = -dt sum_q G_q^T(m_bar') - dt sum_d delta_f^T(F_bar).
-template <int DIM>
-__global__ void k_adj_corr_cell(GridK g, StateV<double> st, SBar sb, SBarW so, const double *rho_s,
-                                const double *E_s, const double *Fh0, const double *Fh1,
-                                const double *Fh2, const double *x, const double *fb0,
+template <int DIM, typename S>
+__global__ void k_adj_corr_cell(GridK g, StateV<S> st, SBar sb, SBarW so, const S *rho_s,
+                                const S *E_s, const S *Fh0, const S *Fh1, const S *Fh2,
+                                const double *x, const double *fb0,
                                 const double *fb1, const double *fb2, double *tbar, double *rhs) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int i, j, k;
   if (!cell_of_linear<DIM>(g, t, i, j, k)) return;
   const int c3[3] = {i, j, k};
   const int64_t c = cidx(g, i, j, k);
-  const double *Fh[3] = {Fh0, Fh1, Fh2};
+  const S *Fh[3] = {Fh0, Fh1, Fh2};
   const double *fb[3] = {fb0, fb1, fb2};
   const double dt = g.dt;
   const double th = E_s[c] / (rho_s[c] * g.cv);
@@ -235,8 +235,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_adj_cg_init(GridK g, const do
 // Per cell: total m^_bar (m_bar' plus the transpose of F^ = lin_f(m^) against
 // F^_bar = F_bar - dt D^T(lambda)), rho_bar += lambda and the inflow terms; the
 // transposes of psi = 1/(R theta**) and theta** = E**/(rho* c_v).
-template <int DIM>
-__global__ void k_adj_setup_a(GridK g, SBar sb, SBarW so, const double *rho_s, const double *E_s,
+template <int DIM, typename S>
+__global__ void k_adj_setup_a(GridK g, SBar sb, SBarW so, const S *rho_s, const S *E_s,
                               const double *x, const double *lam, const double *fb0,
                               const double *fb1, const double *fb2, const double *tbar,
                               double *ms0, double *ms1, double *ms2, double *Es_bar,
@@ -378,8 +378,8 @@ __global__ void k_adj_spread_t(GridK g, const int *mcount, const int *seg, const
 
 // ------------------------------------------------- R5: predictor transpose
 // Primitives on the padded grid (ghost rules applied), as the predictor sees them.
-template <int DIM>
-__global__ void k_adj_prims(GridK g, StateV<double> st, double *pp) {
+template <int DIM, typename S>
+__global__ void k_adj_prims(GridK g, StateV<S> st, double *pp) {
   const int64_t Np = padded_count(g);
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Np) return;
@@ -416,8 +416,8 @@ __global__ void k_adj_prims(GridK g, StateV<double> st, double *pp) {
 // rho_bar, and per tangential direction t the cotangents A_t (of the face average
 // of d u_d/d x_t) and B_t (of d u_t / d x_t in the face divergence), each shared by
 // the centred differences at P and Q. The state face-flux cotangent is written.
-template <int DIM>
-__global__ void k_adj_faces(GridK g, int d, StateV<double> st, const double *pp,
+template <int DIM, typename S>
+__global__ void k_adj_faces(GridK g, int d, StateV<S> st, const double *pp,
                             const double *rs_bar, const double *ms0, const double *ms1,
                             const double *ms2, const double *Es_bar, double *fo, int64_t NFtot,
                             int64_t foff, double *Fbar_out) {
@@ -543,8 +543,8 @@ __global__ void k_adj_faces(GridK g, int d, StateV<double> st, const double *pp,
 // Phi = mu (sum_ab (g_ab + g_ba) g_ab - 2/3 (div u)^2) enters E* with dt;
 // -dt G_b(p) enters m*_b; -dt p div(u_f) enters E*. Stored: g_bar [dim][dim],
 // G_b(p)_bar [dim], the direct p_bar and mu_bar.
-template <int DIM>
-__global__ void k_adj_cells(GridK g, StateV<double> st, const double *pp, const double *ms0,
+template <int DIM, typename S>
+__global__ void k_adj_cells(GridK g, StateV<S> st, const double *pp, const double *ms0,
                             const double *ms1, const double *ms2, const double *Es_bar,
                             double *co) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -563,13 +563,13 @@ __global__ void k_adj_cells(GridK g, StateV<double> st, const double *pp, const 
 #pragma unroll
     for (int a = 0; a < DIM; ++a) gr[a][b] = (pp[(1 + a) * Np + i1] - pp[(1 + a) * Np + i0]) * hh;
   }
-  double divu = 0.0, S = 0.0;
+  double divu = 0.0, sgg = 0.0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) divu += gr[a][a];
 #pragma unroll
   for (int a = 0; a < DIM; ++a)
 #pragma unroll
-    for (int b = 0; b < DIM; ++b) S += (gr[a][b] + gr[b][a]) * gr[a][b];
+    for (int b = 0; b < DIM; ++b) sgg += (gr[a][b] + gr[b][a]) * gr[a][b];
   const int64_t ic = pidx(g, i, j, k);
   const double muc = pp[(DIM + 2) * Np + ic];
   const double Phib = g.dt * Es_bar[c];
@@ -596,7 +596,7 @@ __global__ void k_adj_cells(GridK g, StateV<double> st, const double *pp, const 
     divU += (Uh - Ul) * g.ih[d];
   }
   co[(v++) * N + c] = -g.dt * divU * Es_bar[c];
-  co[(v++) * N + c] = Phib * (S - (2.0 / 3.0) * divu * divu);
+  co[(v++) * N + c] = Phib * (sgg - (2.0 / 3.0) * divu * divu);
 }
 
 // Per padded cell X: every cotangent that reaches the primitives at X from the face
@@ -698,8 +698,8 @@ __global__ void k_adj_gather(GridK g, const double *pp, const double *fo, int64_
 // Per cell: the padded cotangents of the cell and of its ghost images (factor of
 // each crossed side's rule), then the primitive-to-conserved transpose; the direct
 // dependence of rho*, m*, E* on rho, m, E is added.
-template <int DIM>
-__global__ void k_adj_fold(GridK g, StateV<double> st, const double *pb, const double *rs_bar,
+template <int DIM, typename S>
+__global__ void k_adj_fold(GridK g, StateV<S> st, const double *pb, const double *rs_bar,
                            const double *ms0, const double *ms1, const double *ms2,
                            const double *Es_bar, SBarW so) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -769,13 +769,14 @@ __global__ void k_adj_fold(GridK g, StateV<double> st, const double *pb, const d
 // ------------------------------------------------------------------ launchers
 static inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-static StateV<double> state_slot(const Bufs &B, int slot) {
-  StateV<double> s;
-  s.rho = (double *)B.rho[slot];
-  s.E = (double *)B.E[slot];
+template <typename S>
+static StateV<S> state_slot(const Bufs &B, int slot) {
+  StateV<S> s;
+  s.rho = (S *)B.rho[slot];
+  s.E = (S *)B.E[slot];
   for (int q = 0; q < 3; ++q) {
-    s.mom[q] = (double *)B.mom[slot][q];
-    s.F[q] = (double *)B.F[slot][q];
+    s.mom[q] = (S *)B.mom[slot][q];
+    s.F[q] = (S *)B.F[slot][q];
   }
   return s;
 }
@@ -813,15 +814,26 @@ static int64_t face_off(const GridK &g, int d) {
   return o;
 }
 
-#define ADJ_DIM(L, ...)                  \
-  do {                                   \
-    if ((L).g.dim == 2) {                \
-      constexpr int DIM = 2;             \
-      __VA_ARGS__;                       \
-    } else {                             \
-      constexpr int DIM = 3;             \
-      __VA_ARGS__;                       \
-    }                                    \
+// Runs the body with DIM and the state's storage type S of the context.
+#define ADJ_DISPATCH(L, ...)                \
+  do {                                      \
+    if ((L).g.dim == 2 && (L).prec == 0) {  \
+      constexpr int DIM = 2;                \
+      using S = double;                     \
+      __VA_ARGS__;                          \
+    } else if ((L).g.dim == 2) {            \
+      constexpr int DIM = 2;                \
+      using S = float;                      \
+      __VA_ARGS__;                          \
+    } else if ((L).prec == 0) {             \
+      constexpr int DIM = 3;                \
+      using S = double;                     \
+      __VA_ARGS__;                          \
+    } else {                                \
+      constexpr int DIM = 3;                \
+      using S = float;                      \
+      __VA_ARGS__;                          \
+    }                                       \
   } while (0)
 
 void run_adj_correction(const Launch &L, const Bufs &B, int slot, const double *sb_in,
@@ -830,25 +842,24 @@ void run_adj_correction(const Launch &L, const Bufs &B, int slot, const double *
   SBar sb = sbar_of(g, sb_in);
   SBarW so = sbarw_of(g, sb_out);
   double *fb[3] = {B.fbar, B.fbar + g.NF[0], B.fbar + g.NF[0] + g.NF[1]};
-  ADJ_DIM(L, {
+  ADJ_DISPATCH(L, {
     for (int d = 0; d < DIM; ++d)
-      hipLaunchKernelGGL((k_adj_corr_face<DIM>), dim3(nb256(g.NF[d])), dim3(256), 0, L.st, g, d,
-                         sb, (const double *)B.rho_s, (const double *)B.E_s, fb[d]);
-    hipLaunchKernelGGL((k_adj_corr_cell<DIM>), dim3(nb256(g.N)), dim3(256), 0, L.st, g,
-                       state_slot(B, slot), sb, so, (const double *)B.rho_s,
-                       (const double *)B.E_s, (const double *)B.Fhat[0],
-                       (const double *)B.Fhat[1], (const double *)B.Fhat[2], (const double *)B.x,
-                       (const double *)fb[0], (const double *)fb[1], (const double *)fb[2],
-                       B.tbar, B.rhs);
+      hipLaunchKernelGGL((k_adj_corr_face<DIM, S>), dim3(nb256(g.NF[d])), dim3(256), 0, L.st, g,
+                         d, sb, (const S *)B.rho_s, (const S *)B.E_s, fb[d]);
+    hipLaunchKernelGGL((k_adj_corr_cell<DIM, S>), dim3(nb256(g.N)), dim3(256), 0, L.st, g,
+                       state_slot<S>(B, slot), sb, so, (const S *)B.rho_s, (const S *)B.E_s,
+                       (const S *)B.Fhat[0], (const S *)B.Fhat[1], (const S *)B.Fhat[2],
+                       (const double *)B.x, (const double *)fb[0], (const double *)fb[1],
+                       (const double *)fb[2], B.tbar, B.rhs);
   });
 }
 
 void run_adj_cg_init(const Launch &L, const Bufs &B, int tag) {
-  ADJ_DIM(L, {
-    hipLaunchKernelGGL((k_adj_cg_init<DIM>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
-                       L.g, (const double *)B.rhs, B.rv[0], B.lam, B.partials, B.cg, tag);
+  ADJ_DISPATCH(L, {
+    hipLaunchKernelGGL((k_adj_cg_init<DIM>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, (const double *)B.rhs, B.rv[0], B.lam, B.partials, B.cg, tag);
   });
-  run_cg_start(L, B);
+  run_cg64_start(L, B);
 }
 
 void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in, double *sb_out) {
@@ -857,9 +868,9 @@ void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in
   SBar sb = sbar_of(g, sb_in);
   SBarW so = sbarw_of(g, sb_out);
   const double *fb[3] = {B.fbar, B.fbar + g.NF[0], B.fbar + g.NF[0] + g.NF[1]};
-  ADJ_DIM(L, {
-    hipLaunchKernelGGL((k_adj_setup_a<DIM>), dim3(nb256(g.N)), dim3(256), 0, L.st, g, sb, so,
-                       (const double *)B.rho_s, (const double *)B.E_s, (const double *)B.x,
+  ADJ_DISPATCH(L, {
+    hipLaunchKernelGGL((k_adj_setup_a<DIM, S>), dim3(nb256(g.N)), dim3(256), 0, L.st, g, sb, so,
+                       (const S *)B.rho_s, (const S *)B.E_s, (const double *)B.x,
                        (const double *)B.lam, fb[0], fb[1], fb[2], (const double *)B.tbar,
                        B.ms_bar[0], B.ms_bar[1], B.ms_bar[2], B.Es_bar, B.rs_bar);
     hipLaunchKernelGGL((k_adj_setup_b<DIM>), dim3(nb256(g.N)), dim3(256), 0, L.st, g,
@@ -888,27 +899,42 @@ void run_adj_predictor(const Launch &L, const Bufs &B, int slot, double *sb_out)
   const GridK &g = L.g;
   const int64_t Np = padded_count(g), NFt = face_total(g);
   SBarW so = sbarw_of(g, sb_out);
-  StateV<double> st = state_slot(B, slot);
-  ADJ_DIM(L, {
-    hipLaunchKernelGGL((k_adj_prims<DIM>), dim3(nb256(Np)), dim3(256), 0, L.st, g, st, B.pprim);
+  ADJ_DISPATCH(L, {
+    StateV<S> st = state_slot<S>(B, slot);
+    hipLaunchKernelGGL((k_adj_prims<DIM, S>), dim3(nb256(Np)), dim3(256), 0, L.st, g, st,
+                       B.pprim);
     for (int d = 0; d < DIM; ++d)
-      hipLaunchKernelGGL((k_adj_faces<DIM>), dim3(nb256(g.NF[d])), dim3(256), 0, L.st, g, d, st,
-                         (const double *)B.pprim, (const double *)B.rs_bar,
+      hipLaunchKernelGGL((k_adj_faces<DIM, S>), dim3(nb256(g.NF[d])), dim3(256), 0, L.st, g, d,
+                         st, (const double *)B.pprim, (const double *)B.rs_bar,
                          (const double *)B.ms_bar[0], (const double *)B.ms_bar[1],
                          (const double *)B.ms_bar[2], (const double *)B.Es_bar, B.fo, NFt,
                          face_off(g, d), so.F[d]);
-    hipLaunchKernelGGL((k_adj_cells<DIM>), dim3(nb256(g.N)), dim3(256), 0, L.st, g, st,
+    hipLaunchKernelGGL((k_adj_cells<DIM, S>), dim3(nb256(g.N)), dim3(256), 0, L.st, g, st,
                        (const double *)B.pprim, (const double *)B.ms_bar[0],
                        (const double *)B.ms_bar[1], (const double *)B.ms_bar[2],
                        (const double *)B.Es_bar, B.co);
     hipLaunchKernelGGL((k_adj_gather<DIM>), dim3(nb256(Np)), dim3(256), 0, L.st, g,
                        (const double *)B.pprim, (const double *)B.fo, NFt, face_off(g, 0),
                        face_off(g, 1), face_off(g, 2), (const double *)B.co, B.pbar);
-    hipLaunchKernelGGL((k_adj_fold<DIM>), dim3(nb256(g.N)), dim3(256), 0, L.st, g, st,
+    hipLaunchKernelGGL((k_adj_fold<DIM, S>), dim3(nb256(g.N)), dim3(256), 0, L.st, g, st,
                        (const double *)B.pbar, (const double *)B.rs_bar,
                        (const double *)B.ms_bar[0], (const double *)B.ms_bar[1],
                        (const double *)B.ms_bar[2], (const double *)B.Es_bar, so);
   });
+}
+
+// The finished pressure solution (FP32 form: the x buffer of the refinement that
+// ended the solve) copied to `dst`.
+__global__ void k_copy_solution(const CgScal *cs, const double *xa, const double *xb, double *dst,
+                                int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = (cs->xfinal && xb) ? xb[i] : xa[i];
+}
+
+void run_copy_solution(const Launch &L, const Bufs &B, double *dst) {
+  hipLaunchKernelGGL(k_copy_solution, dim3(nb256(L.g.N)), dim3(256), 0, L.st,
+                     (const CgScal *)B.cg, (const double *)B.x, (const double *)B.x2, dst, L.g.N);
 }
 
 }  // namespace ibmk

@@ -334,17 +334,27 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   B.mforce = C.take<double>(3 * nc);
   B.mheat = C.take<double>(nc);
   B.totals = C.take<double>(8);
-  // tape and adjoint work buffers (FP64 contexts with a tape only)
+  // tape and adjoint work buffers (contexts with a tape only)
   B.tape = nullptr;
-  B.tape_stride = 0;
+  B.tape_stride = B.tape_xoff = 0;
   B.pprim = B.pbar = B.fo = B.co = B.rs_bar = B.Es_bar = B.fbar = B.tbar = B.lam = B.rhs = nullptr;
   B.mkbar = nullptr;
   for (int q = 0; q < 3; ++q) B.ms_bar[q] = nullptr;
   if (tape_steps > 0) {
     const size_t NFt = (size_t)(g.NF[0] + g.NF[1] + g.NF[2]);
     const size_t Np = (size_t)ibmk::padded_cells(g);
-    B.tape_stride = ((size_t)(dim + 3) * N + NFt + 31) & ~size_t(31);
-    B.tape = C.take<double>(B.tape_stride * (size_t)tape_steps);
+    B.tape_xoff = (((size_t)(dim + 2) * N + NFt) * w + 255) & ~size_t(255);
+    B.tape_stride = (B.tape_xoff + N * sizeof(double) + 255) & ~size_t(255);
+    B.tape = C.take<char>(B.tape_stride * (size_t)tape_steps);
+    if (d.precision == IBM_FP32) {
+      // the adjoint's pressure solves run the FP64 CG
+      B.pv = C.take<double>(N);
+      for (int s = 0; s < 2; ++s) {
+        B.rv[s] = C.take<double>(N);
+        B.wv[s] = C.take<double>(N);
+        B.sv[s] = C.take<double>(N);
+      }
+    }
     B.pprim = C.take<double>((size_t)(dim + 4) * Np);
     B.pbar = C.take<double>((size_t)(dim + 3) * Np);
     B.fo = C.take<double>((size_t)(4 * dim + 2) * NFt);
@@ -433,18 +443,14 @@ ibm_status marker_flags(ibm_ctx *ctx, const int *f) {
   return IBM_OK;
 }
 
-// Offset of the pressure solution in a tape record (after rho, mom, E, F).
-size_t tape_x_offset(const GridK &g) {
-  return (size_t)(g.dim + 2) * (size_t)g.N + (size_t)(g.NF[0] + g.NF[1] + g.NF[2]);
-}
-
 // Copies state slot `slot` to tape record `rec` (to_tape) or back.
 ibm_status tape_copy(ibm_ctx *ctx, int rec, int slot, bool to_tape) {
   const GridK &g = ctx->L.g;
   Bufs &B = ctx->B;
   hipStream_t st = ctx->L.st;
-  double *base = B.tape + B.tape_stride * (size_t)rec;
+  char *base = B.tape + B.tape_stride * (size_t)rec;
   const size_t N = (size_t)g.N;
+  const size_t w = ctx->L.prec ? sizeof(float) : sizeof(double);
   void *parts[9];
   size_t sizes[9];
   int np = 0;
@@ -464,8 +470,8 @@ ibm_status tape_copy(ibm_ctx *ctx, int rec, int slot, bool to_tape) {
   for (int i = 0; i < np; ++i) {
     void *dst = to_tape ? (void *)(base + off) : parts[i];
     const void *src = to_tape ? (const void *)parts[i] : (const void *)(base + off);
-    HIPCHECK(ctx, hipMemcpyAsync(dst, src, sizes[i] * sizeof(double), hipMemcpyDeviceToDevice, st));
-    off += sizes[i];
+    HIPCHECK(ctx, hipMemcpyAsync(dst, src, sizes[i] * w, hipMemcpyDeviceToDevice, st));
+    off += sizes[i] * w;
   }
   return IBM_OK;
 }
@@ -473,17 +479,18 @@ ibm_status tape_copy(ibm_ctx *ctx, int rec, int slot, bool to_tape) {
 // Runs a pressure-type CG whose set-up has been queued (tag posted by its
 // iterations) to completion with the buffers of `Bc`; returns its iterations.
 ibm_status run_cg_to_end(ibm_ctx *ctx, const Bufs &Bc, int tag, int *iters) {
+  // every such solve (the adjoint's) runs the FP64 CG, whatever the context's form
   const Launch &L = ctx->L;
   int launched = 0;
   const int first = std::max(1, ctx->cg_hint + 1);
-  for (int c = 0; c < first; ++c) ibmk::run_cg_iteration(L, Bc, launched++);
+  for (int c = 0; c < first; ++c) ibmk::run_cg64_iteration(L, Bc, launched++);
   HIPCHECK(ctx, hipGetLastError());
   uint64_t w = 0;
   for (;;) {
     ibm_status r = wait_progress(ctx, tag, launched - 1, &w);
     if (r) return r;
     if (w & 0xF) break;
-    for (int c = 0; c < 4; ++c) ibmk::run_cg_iteration(L, Bc, launched++);
+    for (int c = 0; c < 4; ++c) ibmk::run_cg64_iteration(L, Bc, launched++);
     HIPCHECK(ctx, hipGetLastError());
   }
   const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
@@ -500,7 +507,6 @@ extern "C" {
 
 size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32_t tape_steps) {
   if (check_desc(desc) || max_markers < 0 || tape_steps < 0) return 0;
-  if (tape_steps > 0 && desc->precision != IBM_FP64) return 0;
   GridK g = make_grid(*desc);
   Bufs B;
   int np;
@@ -513,7 +519,6 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   *out = nullptr;
   if (check_desc(desc)) return IBM_E_ARG;
   if (tape_steps < 0) return IBM_E_ARG;
-  if (tape_steps > 0 && desc->precision != IBM_FP64) return IBM_E_ARG;
   if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 255)) return IBM_E_ARG;
   const int nslot = desc->dim == 3 ? 27 : 9;
   if ((int64_t)desc->max_markers * nslot >= ((int64_t)1 << ibmk::kPairBits)) return IBM_E_SIZE;
@@ -848,8 +853,8 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       break;
     }
     if (record) {
-      HIPCHECK(ctx, hipMemcpyAsync(B.tape + B.tape_stride * (size_t)s + tape_x_offset(L.g), B.x,
-                                   (size_t)L.g.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+      ibmk::run_copy_solution(L, B, (double *)(B.tape + B.tape_stride * (size_t)s + B.tape_xoff));
+      HIPCHECK(ctx, hipGetLastError());
     }
     ctx->cur ^= 1;
     ctx->prev_valid = true;
@@ -1006,7 +1011,6 @@ int32_t ibm_tape_length(const ibm_ctx *ctx) { return ctx ? ctx->tape_len : 0; }
 ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *state_bar_in,
                             double *state_bar_out, const double *out_bar, double *Tw_bar) {
   if (!ctx) return IBM_E_ARG;
-  if (ctx->L.prec != 0) return fail(ctx, IBM_E_ARG, "adjoint_step: needs an FP64 context");
   if (ctx->L.g.conv != ibmk::CONV_LINEAR)
     return fail(ctx, IBM_E_ARG, "adjoint_step: needs linear convection");
   if (ctx->motion_axis >= 0) return fail(ctx, IBM_E_ARG, "adjoint_step: markers must be at rest");
@@ -1033,8 +1037,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
   ibmk::run_predictor(L, B, slot);
   if (ctx->nc > 0) ibmk::run_markers_step(L, B, nullptr);
   ibmk::run_setup(L, B, slot, ++ctx->tag, false);
-  HIPCHECK(ctx, hipMemcpyAsync(B.x,
-                               B.tape + B.tape_stride * (size_t)tape_index + tape_x_offset(L.g),
+  HIPCHECK(ctx, hipMemcpyAsync(B.x, B.tape + B.tape_stride * (size_t)tape_index + B.tape_xoff,
                                (size_t)L.g.N * sizeof(double), hipMemcpyDeviceToDevice, st));
   // reverse: correction, pressure solve, set-up, forcing and spreading, predictor
   ibmk::run_adj_correction(L, B, slot, state_bar_in, state_bar_out);

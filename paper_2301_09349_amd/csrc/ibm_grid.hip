@@ -1333,6 +1333,10 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolat
 
 void run_cg_start(const Launch &L, const Bufs &B) {
   if (L.prec == 1) return;  // the FP32 form's first iteration kernel starts its solve
+  run_cg64_start(L, B);
+}
+
+void run_cg64_start(const Launch &L, const Bufs &B) {
   IBM_DISPATCH(L, {
     hipLaunchKernelGGL((k_cg_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
                        L.st, L.g, (const S *)B.psi, (const double *)B.rv[0], B.wv[0], B.partials);
@@ -1360,12 +1364,16 @@ void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
       run_mcg_iter<3>(L, B, it);
     return;
   }
+  run_cg64_iteration(L, B, it);
+}
+
+void run_cg64_iteration(const Launch &L, const Bufs &B, int it) {
   IBM_DISPATCH(L, {
     const int a = it & 1, b = a ^ 1;
-    hipLaunchKernelGGL((k_cg_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
-                       L.g, it, (const S *)B.psi, (const double *)B.rv[a], (const double *)B.wv[a],
-                       (const double *)B.sv[a], B.rv[b], B.wv[b], B.sv[b], B.pv, B.x, B.partials,
-                       B.cg, (const int *)B.flags, B.progress);
+    hipLaunchKernelGGL((k_cg_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, it, (const S *)B.psi, (const double *)B.rv[a],
+                       (const double *)B.wv[a], (const double *)B.sv[a], B.rv[b], B.wv[b], B.sv[b],
+                       B.pv, B.x, B.partials, B.cg, (const int *)B.flags, B.progress);
   });
 }
 

@@ -52,10 +52,12 @@ struct Bufs {
   double *mheat;  // [ns]
   double *totals; // [4]
 
-  // tape (IBM_RECORD): per recorded step the state it started from and its
-  // pressure solution, FP64: rho, mom[dim], E [N]; F [sum NF]; x [N]
-  double *tape;
-  size_t tape_stride;  // doubles per recorded step
+  // tape (IBM_RECORD): per recorded step the state it started from, in the
+  // context's storage type (rho, mom[dim], E [N]; F [sum NF]), then its FP64 pressure
+  // solution x [N] at a 256-byte aligned offset
+  char *tape;
+  size_t tape_stride;  // bytes per recorded step
+  size_t tape_xoff;    // byte offset of x in a record
   // adjoint work buffers (FP64)
   double *pprim;        // padded primitives [(dim+4)][Npad]: rho, u[dim], theta, mu, p
   double *pbar;         // padded primitive cotangents [(dim+3)][Npad]: rho, u[dim], theta, p
@@ -91,7 +93,12 @@ void enable_predictor_lds(int dim, int prec);
 // starts from p^n + (p^n - p^{n-1}) instead of p^n
 void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolate);
 // start of the FP64 CG from r0 = rv[0]: w0 = A r0 and the first dot products
+// (nothing in the FP32 form, whose first iteration kernel starts its solve)
 void run_cg_start(const Launch &L, const Bufs &B);
+// the FP64 CG's start and iteration whatever the context's precision (psi in the
+// context's storage type): the forward FP64 solve and every adjoint solve
+void run_cg64_start(const Launch &L, const Bufs &B);
+void run_cg64_iteration(const Launch &L, const Bufs &B, int it);
 void run_cg_iteration(const Launch &L, const Bufs &B, int it);
 // kernels of one CG iteration: 1 in FP64, 2 in the FP32 form (part 0: a, 1: b)
 int cg_parts(const Launch &L);
@@ -112,6 +119,8 @@ void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in
 // out_bar: host double[4], the cotangents of the step's Fx, Fy, Fz, H
 void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, double *Tw_bar);
 void run_adj_predictor(const Launch &L, const Bufs &B, int slot, double *sb_out);
+// copy of the finished pressure solution (either x buffer of the FP32 form)
+void run_copy_solution(const Launch &L, const Bufs &B, double *dst);
 
 // marker kernels (ibm_markers.hip)
 void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,

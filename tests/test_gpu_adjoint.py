@@ -12,7 +12,7 @@ import torch
 from paper_2301_09349_amd import inputs
 from paper_2301_09349_amd.adjoint import IBMRollout, drag_scale, nusselt_scale, \
     wall_temperature_gradient, _state_vector, _set_state_vector
-from helpers import make_gpu, make_oracle, to_np
+from helpers import make_gpu, make_oracle, rel_l2, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -152,6 +152,20 @@ def test_tw_gradient_matches_central_differences(cuda):
         assert abs(ad - fd) <= 1e-5 * abs(ad), (j, ad, fd)
 
 
+def test_fp32_form_gradient_close_to_fp64(cuda):
+    # FP32 trajectory and record, reverse in FP64: the T_w gradient of the FP32 form
+    # against the FP64 one (measured ~5e-8 here, ~3e-7 at 512^2 over 500 steps)
+    c = _tw_case()
+    nsteps, ck = 12, 5
+    ob = np.random.default_rng(23).standard_normal((nsteps, 4))
+    g = {}
+    for prec in ("fp64", "fp32"):
+        s = make_gpu(c, precision=prec, tape_steps=ck)
+        _, tb, _ = wall_temperature_gradient(s, nsteps, ob, checkpoint=ck)
+        g[prec] = to_np(tb)
+    assert rel_l2(g["fp32"], g["fp64"]) < 1e-5
+
+
 def test_gradient_rollout_leaves_the_forward_state(cuda):
     c = _tw_case()
     s1 = make_gpu(c, tape_steps=4)
@@ -197,6 +211,14 @@ def test_cfg5_nusselt_gradient_full_size(cuda):
     Jn, _ = IBMRollout.apply(Tw, s, n, ck)
     Jn.backward()
     g = to_np(Tw.grad)
+    # the FP32 form's gradient (FP32 trajectory, FP64 reverse) against it
+    s32 = make_gpu(c, precision="fp32", tape_steps=ck)
+    Tw32 = Tw0.clone().requires_grad_(True)
+    Jn32, _ = IBMRollout.apply(Tw32, s32, n, ck)
+    Jn32.backward()
+    assert rel_l2(to_np(Tw32.grad), g) < 1e-5
+    assert abs(float(Jn32.detach()) / float(Jn.detach()) - 1.0) < 1e-4
+    del s32
     ku = nusselt_scale(c)
     h = 1e-6
     for j in range(10):

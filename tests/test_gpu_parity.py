@@ -83,6 +83,31 @@ def test_sphere_3d_parity(cuda):
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
 
 
+def test_full_size_cylinder_1024_parity(cuda):
+    # the benchmark workload at its full size, in the benchmark's configuration
+    c = inputs.case("cfg2a")
+    g, o = make_gpu(c), make_oracle(c)
+    ids, _ = g.markers_in_use()
+    assert np.array_equal(to_np(ids).astype(int), o.keep())
+    hg, _ = g.step(2)
+    ho = o.step(2)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-12, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
+
+
+@pytest.mark.slow
+def test_full_size_sphere_256_parity(cuda):
+    # 256^3 cells, 3200 candidate markers: one step (the oracle takes about a minute)
+    c = inputs.case("cfg3")
+    g, o = make_gpu(c), make_oracle(c)
+    hg, _ = g.step(1)
+    ho = o.step(1)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-12, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
+
+
 def test_large_marker_set_parity(cuda):
     # a candidate capacity above the single-block marker kernel's: the multi-block
     # interpolation / totals / spread kernels run instead

@@ -812,7 +812,9 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       ibm_status ts = tape_copy(ctx, s, ctx->cur, true);
       if (ts) return ts;
     }
-    timed(IBM_PROF_PREDICTOR, 0, [&] { ibmk::run_predictor(L, B, ctx->cur); });
+    timed(IBM_PROF_PREDICTOR, 0, [&] {
+      ibmk::run_predictor(L, B, ctx->cur, ctx->prev_valid && ctx->extrapolate);
+    });
     double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
     if (ctx->nc > 0) {
       timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
@@ -820,7 +822,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
     }
     timed(IBM_PROF_SETUP, 0,
-          [&] { ibmk::run_setup(L, B, ctx->cur, tag, ctx->prev_valid && ctx->extrapolate); });
+          [&] { ibmk::run_setup(L, B, ctx->cur, tag); });
     // Iteration `it` tests convergence after `it` updates at its start, so a solve of
     // n iterations takes n + 1 launches of part a; launches past convergence return
     // at once. The first batch follows the last step's count, and the correction is
@@ -1034,9 +1036,9 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     ibm_status r = tape_copy(ctx, tape_index, slot, false);
     if (r) return r;
   }
-  ibmk::run_predictor(L, B, slot);
+  ibmk::run_predictor(L, B, slot, false);
   if (ctx->nc > 0) ibmk::run_markers_step(L, B, nullptr);
-  ibmk::run_setup(L, B, slot, ++ctx->tag, false);
+  ibmk::run_setup(L, B, slot, ++ctx->tag);
   HIPCHECK(ctx, hipMemcpyAsync(B.x, B.tape + B.tape_stride * (size_t)tape_index + B.tape_xoff,
                                (size_t)L.g.N * sizeof(double), hipMemcpyDeviceToDevice, st));
   // reverse: correction, pressure solve, set-up, forcing and spreading, predictor

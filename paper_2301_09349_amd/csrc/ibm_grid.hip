@@ -144,10 +144,34 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
 
 
 // ----------------------------------------------------- Appendix A, step 1
+// What the predictor also writes for the pressure set-up (App. A step 3), so that
+// no separate pass reads its outputs back: m^ = m* + dt G_c p^n, i.e. the momentum
+// update without the pressure gradient; psi = 1/(R theta*) with theta* = E*/(rho* c_v);
+// the CG start p^n, or p^n + (p^n - p^{n-1}) when E_prev (the previous state's
+// energy) is given. The spread of the forcing then adds its increment to m^ and
+// recomputes psi on the cells it touches.
+template <typename S>
+struct PredOut {
+  S *mh[3];
+  S *psi;
+  double *x;
+  const S *E_prev;
+};
+
+template <typename S>
+__device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> &po, int64_t c,
+                                               S rho_s, S E_s, S E) {
+  const S theta = E_s / (rho_s * S(g.cv));
+  po.psi[c] = S(1) / (S(g.R) * theta);
+  const double pn = double(S(g.gm1) * E);
+  po.x[c] = po.E_prev ? 2.0 * pn - double(S(g.gm1) * po.E_prev[c]) : pn;
+}
+
 // Predictor (f = q = 0): explicit update of mass, momentum and internal energy.
 template <int DIM, typename S>
 __device__ __forceinline__ void predictor_cell(const GridK &g, const StateV<S> &st, int i, int j,
-                                               int k, S *rho_s, S *const *ms, S *E_s) {
+                                               int k, S *rho_s, S *const *ms, S *E_s,
+                                               const PredOut<S> &po) {
   const int64_t c = cidx(g, i, j, k);
   S divF = S(0), divU = S(0), divE = S(0), divM[3] = {S(0), S(0), S(0)};
 #pragma unroll
@@ -194,21 +218,29 @@ __device__ __forceinline__ void predictor_cell(const GridK &g, const StateV<S> &
   phi = mu_of(g, th) * (phi - S(2.0 / 3.0) * divu * divu);
   const S dt = S(g.dt);
   const S pc = S(g.gm1) * E;
-  rho_s[c] = rho - dt * divF;
+  const S rs = rho - dt * divF;
+  rho_s[c] = rs;
 #pragma unroll
-  for (int q = 0; q < DIM; ++q) ms[q][c] = st.mom[q][c] - dt * divM[q] - dt * gp[q];
-  E_s[c] = E - dt * divE - dt * pc * divU + dt * phi;
+  for (int q = 0; q < DIM; ++q) {
+    const S mhq = st.mom[q][c] - dt * divM[q];
+    ms[q][c] = mhq - dt * gp[q];
+    po.mh[q][c] = mhq;
+  }
+  const S es = E - dt * divE - dt * pc * divU + dt * phi;
+  E_s[c] = es;
+  pred_setup_out(g, po, c, rs, es, E);
 }
 
 template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_predictor(GridK g, StateV<S> st, S *rho_s, S *ms0,
-                                                        S *ms1, S *ms2, S *E_s) {
+                                                        S *ms1, S *ms2, S *E_s, PredOut<S> po) {
   S *ms[3] = {ms0, ms1, ms2};
   int64_t t0, t1;
   block_tiles(g, t0, t1);
   for (int64_t t = t0; t < t1; ++t) {
     int i, j, k;
-    if (cell_in_tile<DIM>(g, t, i, j, k)) predictor_cell<DIM>(g, st, i, j, k, rho_s, ms, E_s);
+    if (cell_in_tile<DIM>(g, t, i, j, k))
+      predictor_cell<DIM>(g, st, i, j, k, rho_s, ms, E_s, po);
   }
 }
 
@@ -352,7 +384,8 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int d
 
 template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> st, S *rho_s,
-                                                            S *ms0, S *ms1, S *ms2, S *E_s) {
+                                                            S *ms0, S *ms1, S *ms2, S *E_s,
+                                                            PredOut<S> po) {
   using T = PredLds<DIM, S>;
   constexpr int NP = T::NP, NFM = T::NFMAX, CPT = T::CPT;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -399,7 +432,8 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     }
     __syncthreads();
     // phase 2: cell-centred terms (-grad p, viscous dissipation) into registers
-    S acc[CPT][DIM + 3];  // rho, mom[DIM], E, div(uf)
+    S acc[CPT][DIM + 3];  // rho, mom[DIM] (without -grad p), E, div(uf)
+    S gpr[CPT][DIM];      // -dt grad p
     int cl[CPT][3];
     bool cv_ok[CPT];
 #pragma unroll
@@ -413,6 +447,8 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       cv_ok[m] = i < g.n[0] && j < g.n[1] && (DIM == 2 || k < g.n[2]);
 #pragma unroll
       for (int v = 0; v < DIM + 3; ++v) acc[m][v] = S(0);
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) gpr[m][q] = S(0);
       if (!cv_ok[m]) continue;
       S gr[3][3], gp[3];
 #pragma unroll
@@ -443,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
         for (int bd = 0; bd < DIM; ++bd) phi += (gr[a][bd] + gr[bd][a]) * gr[a][bd];
       phi = lv[(DIM + 2) * NP + T::pt(ci, cj, ck)] * (phi - S(2.0 / 3.0) * divu * divu);
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) acc[m][1 + q] = -dt * gp[q];
+      for (int q = 0; q < DIM; ++q) gpr[m][q] = -dt * gp[q];
       acc[m][DIM + 1] = dt * phi;
     }
     // phase 3: faces, one direction at a time
@@ -490,10 +526,17 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       if (!cv_ok[m]) continue;
       const int64_t c = cidx(g, x0 + cl[m][0], y0 + cl[m][1], z0 + cl[m][2]);
       const S E = st.E[c];
-      rho_s[c] = st.rho[c] - dt * acc[m][0];
+      const S rs = st.rho[c] - dt * acc[m][0];
+      rho_s[c] = rs;
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) ms[q][c] = st.mom[q][c] + acc[m][1 + q];
-      E_s[c] = E + acc[m][DIM + 1] - dt * (gm1 * E) * acc[m][DIM + 2];
+      for (int q = 0; q < DIM; ++q) {
+        const S mhq = st.mom[q][c] + acc[m][1 + q];
+        ms[q][c] = mhq + gpr[m][q];
+        po.mh[q][c] = mhq;
+      }
+      const S es = E + acc[m][DIM + 1] - dt * (gm1 * E) * acc[m][DIM + 2];
+      E_s[c] = es;
+      pred_setup_out(g, po, c, rs, es, E);
     }
   }
 }
@@ -561,41 +604,7 @@ __global__ void k_flux_from_mom(GridK g, StateV<S> st, int d) {
 }
 
 // --------------------------------------------------- Appendix A, step 3
-// Pressure set-up, part 1: p^n = (gamma-1) E^n; m^ = mom** + dt G_c p^n;
-// theta** = E**/(rho* c_v); psi = 1/(R theta**); CG start x = p^n.
-template <int DIM, typename S>
-__global__ __launch_bounds__(kBlockThreads) void k_setup1(GridK g, StateV<S> st, const S *rho_s,
-                                                     const S *ms0, const S *ms1, const S *ms2,
-                                                     const S *E_s, S *mh0, S *mh1, S *mh2, S *psi,
-                                                     double *x, const S *E_prev) {
-  const S *ms[3] = {ms0, ms1, ms2};
-  S *mh[3] = {mh0, mh1, mh2};
-  const S gm1 = S(g.gm1);
-  int64_t t0, t1;
-  block_tiles(g, t0, t1);
-  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
-    int i, j, k;
-    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-    const int64_t c = cidx(g, i, j, k);
-#pragma unroll
-    for (int q = 0; q < DIM; ++q) {
-      int a1[3] = {i, j, k}, a0[3] = {i, j, k};
-      a1[q] += 1;
-      a0[q] -= 1;
-      Resolved r1 = resolve<DIM>(g, a1[0], a1[1], a1[2]);
-      Resolved r0 = resolve<DIM>(g, a0[0], a0[1], a0[2]);
-      S p1 = ghosted<DIM>(g, r1, V_P, gm1 * st.E[r1.c]);
-      S p0 = ghosted<DIM>(g, r0, V_P, gm1 * st.E[r0.c]);
-      mh[q][c] = ms[q][c] + S(g.dt) * ((p1 - p0) * S(0.5 * g.ih[q]));
-    }
-    const S theta = E_s[c] / (rho_s[c] * S(g.cv));
-    psi[c] = S(1) / (S(g.R) * theta);
-    // CG start: p^n, or with the previous step's energy p^n + (p^n - p^{n-1})
-    const double pn = double(gm1 * st.E[c]);
-    x[c] = E_prev ? 2.0 * pn - double(gm1 * E_prev[c]) : pn;
-  }
-}
-
+// (m^, psi and the CG start come from the predictor and the spread.)
 // Homogeneous pressure operator at one cell: psi v - dt^2 div(grad_f v), zero
 // normal gradient at inflow and slip faces, v = 0 beyond outflow faces.
 // The homogeneous Laplacian of v at (i, j, k), vc = v there.
@@ -631,9 +640,9 @@ __device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, in
   return double(psi[c]) * vc - g.dt * g.dt * helm_lap<DIM>(g, v, i, j, k, vc);
 }
 
-// Pressure set-up, part 2, fused with the CG start: predicted face flux
+// Pressure set-up from the predictor's m^, psi, x: predicted face flux
 // F^ = lin_f(m^) (boundary rules), b = rho^n - dt D(F^) + outflow terms,
-// r = b - A x, p = r; per-block FP64 partial sums of b.b and r.r.
+// r0 = b - A x; per-block FP64 partial sums of b.b.
 template <int DIM, typename S>
 __global__ __launch_bounds__(kBlockThreads) void k_setup2(GridK g, const S *rho_n, const S *mh0,
                                                      const S *mh1, const S *mh2, S *Fh0, S *Fh1,
@@ -843,7 +852,7 @@ constexpr double kInnerTol2 = 1e-8;
 constexpr int kInnerMax = 60;
 enum { MS_INNER = 0, MS_START = 1, MS_FIRST = 2 };  // stages, see k_mcg_iter
 
-// Set-up part 2 of the FP32 form: as k_setup2, with the FP64 start residual
+// Set-up of the FP32 form: as k_setup2, with the FP64 start residual
 // handed to the inner solve as FP32 (r32) and its FP64 r.r as the outer partial.
 template <int DIM>
 __global__ __launch_bounds__(kBlockThreads) void k_setup2m(GridK g, const float *rho_n, const float *mh0,
@@ -1272,8 +1281,13 @@ void enable_predictor_lds(int dim, int prec) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-void run_predictor(const Launch &L, const Bufs &B, int cur) {
+void run_predictor(const Launch &L, const Bufs &B, int cur, bool extrapolate) {
   IBM_DISPATCH(L, {
+    PredOut<S> po;
+    for (int q = 0; q < 3; ++q) po.mh[q] = (S *)B.mhat[q];
+    po.psi = (S *)B.psi;
+    po.x = B.x;
+    po.E_prev = extrapolate ? (const S *)B.E[cur ^ 1] : nullptr;
     if (L.pred_lds) {
       using T = PredLds<DIM, S>;
       const int64_t nt = (int64_t)((L.g.n[0] + T::TX - 1) / T::TX) *
@@ -1282,51 +1296,37 @@ void run_predictor(const Launch &L, const Bufs &B, int cur) {
       const int64_t nb = std::min<int64_t>(((nt + 7) / 8) * 8, IBM_PRED_MAXB);
       hipLaunchKernelGGL((k_predictor_lds<DIM, S>), dim3((unsigned)nb), dim3(kThreads), T::bytes,
                          L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
-                         (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
+                         (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s, po);
     } else {
       hipLaunchKernelGGL((k_predictor<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
                          L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
-                         (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
+                         (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s, po);
     }
   });
 }
 
-void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolate) {
-  const void *eprev = extrapolate ? B.E[cur ^ 1] : nullptr;
+void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
   if (L.prec == 1) {
-    IBM_DISPATCH(L, {
-      hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
-                         L.st, L.g, state_of<S>(B, cur), (const S *)B.rho_s,
-                         (const S *)B.mom_s[0], (const S *)B.mom_s[1], (const S *)B.mom_s[2],
-                         (const S *)B.E_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2],
-                         (S *)B.psi, B.x, (const S *)eprev);
-    });
     if (L.g.dim == 2)
-      hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st, L.g,
-                         (const float *)B.rho[cur], (const float *)B.mhat[0],
+      hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
+                         L.g, (const float *)B.rho[cur], (const float *)B.mhat[0],
                          (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
                          (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
                          (const double *)B.x, B.b, B.rv32[0], B.partials, B.cg, tag);
     else
-      hipLaunchKernelGGL((k_setup2m<3>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st, L.g,
-                         (const float *)B.rho[cur], (const float *)B.mhat[0],
+      hipLaunchKernelGGL((k_setup2m<3>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
+                         L.g, (const float *)B.rho[cur], (const float *)B.mhat[0],
                          (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
                          (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
                          (const double *)B.x, B.b, B.rv32[0], B.partials, B.cg, tag);
-    run_cg_start(L, B);
     return;
   }
   IBM_DISPATCH(L, {
-    hipLaunchKernelGGL((k_setup1<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
-                       L.g, state_of<S>(B, cur), (const S *)B.rho_s, (const S *)B.mom_s[0],
-                       (const S *)B.mom_s[1], (const S *)B.mom_s[2], (const S *)B.E_s,
-                       (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], (S *)B.psi, B.x,
-                       (const S *)eprev);
-    hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
-                       L.g, (const S *)B.rho[cur], (const S *)B.mhat[0], (const S *)B.mhat[1],
-                       (const S *)B.mhat[2], (S *)B.Fhat[0], (S *)B.Fhat[1], (S *)B.Fhat[2],
-                       (const S *)B.psi, (const double *)B.x, B.b, B.rv[0], B.partials, B.cg,
-                       tag);
+    hipLaunchKernelGGL((k_setup2<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, (const S *)B.rho[cur], (const S *)B.mhat[0],
+                       (const S *)B.mhat[1], (const S *)B.mhat[2], (S *)B.Fhat[0], (S *)B.Fhat[1],
+                       (S *)B.Fhat[2], (const S *)B.psi, (const double *)B.x, B.b, B.rv[0],
+                       B.partials, B.cg, tag);
   });
   run_cg_start(L, B);
 }

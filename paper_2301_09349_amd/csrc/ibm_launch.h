@@ -85,13 +85,15 @@ void run_uniform_state(const Launch &L, const Bufs &B, int cur);
 void run_init_primitive(const Launch &L, const Bufs &B, int cur, const void *rho, const void *u,
                         const void *theta);
 void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
-void run_predictor(const Launch &L, const Bufs &B, int cur);
+// predictor, also writing m^ (= m* + dt G_c p^n), psi and the CG start x for the
+// set-up; extrapolate: the other state slot holds the previous step's state, and
+// the CG starts from p^n + (p^n - p^{n-1}) instead of p^n
+void run_predictor(const Launch &L, const Bufs &B, int cur, bool extrapolate);
 size_t predictor_lds_bytes(int dim, int prec);
 void enable_predictor_lds(int dim, int prec);
-// set-up of the pressure equation, ending with the start of its CG (r0, w0 = A r0);
-// extrapolate: the other state slot holds the previous step's state, and the CG
-// starts from p^n + (p^n - p^{n-1}) instead of p^n
-void run_setup(const Launch &L, const Bufs &B, int cur, int tag, bool extrapolate);
+// set-up of the pressure equation from the predictor's m^, psi, x (with the spread
+// forcing added), ending with the start of its CG (r0, w0 = A r0)
+void run_setup(const Launch &L, const Bufs &B, int cur, int tag);
 // start of the FP64 CG from r0 = rv[0]: w0 = A r0 and the first dot products
 // (nothing in the FP32 form, whose first iteration kernel starts its solve)
 void run_cg_start(const Launch &L, const Bufs &B);

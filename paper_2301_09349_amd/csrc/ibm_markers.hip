@@ -445,14 +445,25 @@ __global__ void k_totals(const int *mcount, const double *mforce, const double *
   totals_block(mcount, mforce, mheat, totals, hist_row, lds);
 }
 
+// Fields the spread updates: mom** = mom* + dt f, E** = E* + dt q, the set-up's
+// m^ (+ dt f) and psi = 1/(R theta**), theta** = E**/(rho* c_v).
+template <typename S>
+struct SpreadSet {
+  S *ms[3];
+  S *E_s;
+  S *mh[3];
+  S *psi;
+  const S *rho_s;
+};
+
 // Eq. (7) as a segmented reduction: one thread per cell touched by a support,
-// summing w eps F and w eps Q over its pairs in increasing marker id, then
-// mom** = mom* + dt f and E** = E* + dt q in place.
+// summing w eps F and w eps Q over its pairs in increasing marker id, then the
+// updates of SpreadSet in place.
 template <int DIM, typename S>
 __device__ __forceinline__ void spread_one(const GridK &g, int s, const int *seg,
                                            const uint64_t *keys, const double *pw,
-                                           const double *eps, const double *mk, S *const *ms,
-                                           S *E_s) {
+                                           const double *eps, const double *mk,
+                                           const SpreadSet<S> &sp) {
   constexpr int dim = DIM, W = 2 * DIM + 3, nslot = (DIM == 3) ? 27 : 9;
   const int a = seg[s], b = seg[s + 1];
   const int64_t cell = (int64_t)(keys[a] >> kPairBits);
@@ -485,18 +496,23 @@ __device__ __forceinline__ void spread_one(const GridK &g, int s, const int *seg
     }
   }
 #pragma unroll
-  for (int q = 0; q < dim; ++q) ms[q][cell] = S(double(ms[q][cell]) + g.dt * acc[q]);
-  E_s[cell] = S(double(E_s[cell]) + g.dt * aq);
+  for (int q = 0; q < dim; ++q) {
+    sp.ms[q][cell] = S(double(sp.ms[q][cell]) + g.dt * acc[q]);
+    sp.mh[q][cell] = S(double(sp.mh[q][cell]) + g.dt * acc[q]);
+  }
+  const S es = S(double(sp.E_s[cell]) + g.dt * aq);
+  sp.E_s[cell] = es;
+  const S theta = es / (sp.rho_s[cell] * S(g.cv));
+  sp.psi[cell] = S(1) / (S(g.R) * theta);
 }
 
 template <int DIM, typename S>
 __global__ void k_spread(GridK g, const int *mcount, const int *seg, const uint64_t *keys,
-                         const double *pw, const double *eps, const double *mk, S *ms0, S *ms1,
-                         S *ms2, S *E_s) {
+                         const double *pw, const double *eps, const double *mk,
+                         SpreadSet<S> sp) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= mcount[1]) return;
-  S *ms[3] = {ms0, ms1, ms2};
-  spread_one<DIM>(g, s, seg, keys, pw, eps, mk, ms, E_s);
+  spread_one<DIM>(g, s, seg, keys, pw, eps, mk, sp);
 }
 
 // The three steps above in one block (for small marker sets, where launch latency
@@ -506,25 +522,36 @@ __global__ void k_spread(GridK g, const int *mcount, const int *seg, const uint6
 template <int DIM, typename S>
 __global__ __launch_bounds__(kRedThreads) void k_markers_fused(
     GridK g, const int *mcount, const int64_t *pcell, const double *pw, const int *seg,
-    const uint64_t *keys, S *rho_s, S *ms0, S *ms1, S *ms2, S *E_s, const double *Ud,
-    const double *Tw, const double *eps, double *mk, double *mforce, double *mheat,
-    double *totals, double *hist_row) {
+    const uint64_t *keys, SpreadSet<S> sp, const double *Ud, const double *Tw, const double *eps,
+    double *mk, double *mforce, double *mheat, double *totals, double *hist_row) {
   __shared__ double lds[64];
-  const S *msc[3] = {ms0, ms1, ms2};
-  S *ms[3] = {ms0, ms1, ms2};
+  const S *msc[3] = {sp.ms[0], sp.ms[1], sp.ms[2]};
   const int n = mcount[0];
   for (int k = threadIdx.x; k < n; k += blockDim.x)
-    interp_force_one<DIM>(g, k, pcell, pw, (const S *)rho_s, msc, (const S *)E_s, Ud, Tw, eps,
-                          mk, mforce, mheat);
+    interp_force_one<DIM>(g, k, pcell, pw, sp.rho_s, msc, (const S *)sp.E_s, Ud, Tw, eps, mk,
+                          mforce, mheat);
   __syncthreads();
   totals_block(mcount, mforce, mheat, totals, hist_row, lds);
   const int nseg = mcount[1];
   for (int s = threadIdx.x; s < nseg; s += blockDim.x)
-    spread_one<DIM>(g, s, seg, keys, pw, eps, mk, ms, E_s);
+    spread_one<DIM>(g, s, seg, keys, pw, eps, mk, sp);
 }
 
 // ------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename S>
+static SpreadSet<S> spread_set(const Bufs &B) {
+  SpreadSet<S> sp;
+  for (int q = 0; q < 3; ++q) {
+    sp.ms[q] = (S *)B.mom_s[q];
+    sp.mh[q] = (S *)B.mhat[q];
+  }
+  sp.E_s = (S *)B.E_s;
+  sp.psi = (S *)B.psi;
+  sp.rho_s = (const S *)B.rho_s;
+  return sp;
+}
 
 void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,
                        int dedupe) {
@@ -605,8 +632,7 @@ void run_markers_step(const Launch &L, const Bufs &B, double *hist_row) {
   MK_DISPATCH(L, {
     hipLaunchKernelGGL((k_markers_fused<DIM, S>), dim3(1), dim3(kRedThreads), 0, L.st, L.g,
                        (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
-                       (const int *)B.seg, (const uint64_t *)B.keys, (S *)B.rho_s,
-                       (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s,
+                       (const int *)B.seg, (const uint64_t *)B.keys, spread_set<S>(B),
                        (const double *)B.Ud, (const double *)B.Tw, (const double *)B.eps, B.mk,
                        B.mforce, B.mheat, B.totals, hist_row);
   });
@@ -619,7 +645,7 @@ void run_spread(const Launch &L, const Bufs &B) {
     hipLaunchKernelGGL((k_spread<DIM, S>), dim3(nblk(cap, 256)), dim3(256), 0, L.st, L.g,
                        (const int *)B.mcount, (const int *)B.seg, (const uint64_t *)B.keys,
                        (const double *)B.pw, (const double *)B.eps, (const double *)B.mk,
-                       (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s);
+                       spread_set<S>(B));
   });
 }
 

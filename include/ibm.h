@@ -245,8 +245,8 @@ int32_t ibm_tape_length(const ibm_ctx *ctx);
  * launch that detects convergence included in the total), 4 unused, 5 correction.
  * The events themselves slow a step down; time throughput with timing off.
  * enable != 0 clears the totals and starts timing; 0 stops it. */
-enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG_A = 3,
-       IBM_PROF_CG_B = 4, IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };
+enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG = 3,
+       IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };
 ibm_status ibm_profile(ibm_ctx *ctx, int32_t enable);
 
 /* Per-class totals since timing was enabled: ms [IBM_PROF_CLASSES] (host) summed

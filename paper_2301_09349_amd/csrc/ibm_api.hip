@@ -58,7 +58,7 @@ struct Prof {
   void count_cg(int cg_iters) {
     for (size_t i = step_first; i < pending.size(); ++i) {
       Pair &p = pending[i];
-      if (p.cls != IBM_PROF_CG_A) continue;
+      if (p.cls != IBM_PROF_CG) continue;
       const int hi = std::min(p.it0 + p.nl, cg_iters);
       p.count = std::max(0, hi - p.it0);
     }
@@ -791,7 +791,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     for (int it = it0; it < it0 + count; ++it) ibmk::run_cg_iteration(L, B, it);
     if (P.on) {
       hipEvent_t b = P.mark(st);
-      P.pending.push_back({IBM_PROF_CG_A, it0, count, a, b});
+      P.pending.push_back({IBM_PROF_CG, it0, count, a, b});
     }
   };
   // Flags are sticky for the whole call: a step that fails keeps every later step
@@ -824,8 +824,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     timed(IBM_PROF_SETUP, 0,
           [&] { ibmk::run_setup(L, B, ctx->cur, tag); });
     // Iteration `it` tests convergence after `it` updates at its start, so a solve of
-    // n iterations takes n + 1 launches of part a; launches past convergence return
-    // at once. The first batch follows the last step's count, and the correction is
+    // n iterations takes n + 1 launches; launches past convergence return at once. The first batch follows the last step's count, and the correction is
     // queued behind it (it runs only once the solve has finished), so the device
     // does not wait for the host unless the batch falls short.
     int launched = 0;

@@ -101,3 +101,22 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_workspace_grows_by_one_tape_record_per_step():
+    # a record: the state in the storage type ((dim + 2) N + sum NF words), then the
+    # FP64 pressure (N), each part 256-byte aligned
+    from paper_2301_09349_amd import inputs
+    from paper_2301_09349_amd.solver import make_desc
+
+    lib = _lib.load()
+    c = inputs.case("cfg1")
+    N = 128 * 128
+    NF = 2 * 129 * 128
+    up = lambda v: (v + 255) // 256 * 256
+    for prec, w in (("fp64", 8), ("fp32", 4)):
+        d = make_desc(c, prec)
+        n = [lib.ibm_workspace_bytes(ctypes.byref(d), 100, t) for t in (0, 1, 2, 3)]
+        rec = up(up((4 * N + NF) * w) + 8 * N)
+        assert n[1] > n[0] + rec  # the first record also brings the adjoint's buffers
+        assert n[2] - n[1] == rec and n[3] - n[2] == rec

@@ -114,7 +114,8 @@ typedef struct {
  * of `tape_steps` recorded steps (0: no adjoint). A tape step holds the state in
  * the context's storage type ((dim + 2) N + sum NF words) and the FP64 pressure (N);
  * tape_steps > 0 also adds the adjoint's work buffers (about (9 dim + 12) N +
- * (4 dim + 3) sum NF doubles). Returns 0 for an invalid descriptor. */
+ * (4 dim + 3) sum NF doubles, (5 dim + 4) sum NF with van Leer convection).
+ * Returns 0 for an invalid descriptor. */
 size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32_t tape_steps);
 
 /* Creates a context on the current HIP device. `dev_workspace` (device memory,
@@ -211,7 +212,10 @@ ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
  * operator is symmetric, so its adjoint is one more CG solve), set-up, forcing and
  * spreading (spreading transposes to interpolation and back), predictor). Not in
  * the paper: it serves gradients of time-averaged Nusselt number and drag with
- * respect to the wall temperatures. Requirements: linear convection, markers at
+ * respect to the wall temperatures. With van Leer convection the limiter and the
+ * upwind choice are differentiated where they are smooth: the branch the forward
+ * took (by the sign of the face mass flux, and whether the limiter is active)
+ * is kept, which is the derivative almost everywhere. Requirements: markers at
  * rest (IBM_E_ARG otherwise); IBM_E_STATE if tape_index is not a recorded step.
  * In the FP32 form the forward pieces are recomputed in FP32 from the FP32 record
  * and the reverse runs in FP64 (cotangents, transposed stencils, adjoint CG): the
@@ -228,7 +232,7 @@ ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
  * The context's current state is not changed; the step's own buffers are. The
  * host waits for the adjoint pressure solve; the kernels after it are queued on
  * the stream (state_bar_out and Tw_bar are ready when the stream is). Needs a
- * workspace planned with tape_steps > 0 (FP64 descriptors only). */
+ * workspace planned with tape_steps > 0. */
 ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *state_bar_in,
                             double *state_bar_out, const double *out_bar, double *Tw_bar);
 

@@ -1026,4 +1026,52 @@ int orc_tl_run(void *p, int nsteps, const double *dTw, double *hv, double *hd) {
   return 0;
 }
 
+// Tangent-linear run from the current state (left unchanged) along a direction of
+// the state (rho [N], mom [dim][N], E [N], F [sum NF]) and, if dTw is not NULL, of
+// the wall temperatures: per step Fx, Fy, Fz, H and their derivatives, and the
+// derivative of the state after the steps (same layout) in dout.
+int orc_tl_state(void *p, int nsteps, const double *dstate, const double *dTw, double *hv,
+                 double *hd, double *dout) {
+  Solver<double> &s = static_cast<Handle *>(p)->s;
+  Solver<Dual> t;
+  if (t.init(s.D)) return 1;
+  t.copy_from(s);
+  const long N = s.N;
+  for (long c = 0; c < N; ++c) {
+    t.rho[c].d = dstate[c];
+    for (int q = 0; q < s.dim; ++q) t.mom[q][c].d = dstate[size_t(1 + q) * N + c];
+    t.E[c].d = dstate[size_t(1 + s.dim) * N + c];
+  }
+  long off = size_t(2 + s.dim) * N;
+  for (int d = 0; d < s.dim; ++d) {
+    for (long f = 0; f < s.NF[d]; ++f) t.F[d][f].d = dstate[off + f];
+    off += s.NF[d];
+  }
+  if (dTw) {
+    for (int k = 0; k < t.nc; ++k) t.cTw[k] = Dual(s.cTw[k], dTw[k]);
+    for (int k = 0; k < t.ns; ++k) t.Tw[k] = t.cTw[t.keep[k]];
+  }
+  for (int i = 0; i < nsteps; ++i) {
+    int rc = t.do_step();
+    for (int q = 0; q < 3; ++q) {
+      hv[size_t(i) * 4 + q] = t.force[q].v;
+      hd[size_t(i) * 4 + q] = t.force[q].d;
+    }
+    hv[size_t(i) * 4 + 3] = t.heat.v;
+    hd[size_t(i) * 4 + 3] = t.heat.d;
+    if (rc) return rc;
+  }
+  for (long c = 0; c < N; ++c) {
+    dout[c] = t.rho[c].d;
+    for (int q = 0; q < s.dim; ++q) dout[size_t(1 + q) * N + c] = t.mom[q][c].d;
+    dout[size_t(1 + s.dim) * N + c] = t.E[c].d;
+  }
+  off = size_t(2 + s.dim) * N;
+  for (int d = 0; d < s.dim; ++d) {
+    for (long f = 0; f < s.NF[d]; ++f) dout[off + f] = t.F[d][f].d;
+    off += s.NF[d];
+  }
+  return 0;
+}
+
 }  // extern "C"

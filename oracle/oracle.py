@@ -105,6 +105,8 @@ def lib():
         L.orc_spread.argtypes = [P, D, D]
         L.orc_tl_run.restype = ctypes.c_int
         L.orc_tl_run.argtypes = [P, ctypes.c_int, D, D, D]
+        L.orc_tl_state.restype = ctypes.c_int
+        L.orc_tl_state.argtypes = [P, ctypes.c_int, D, D, D, D, D]
         _lib = L
     return _lib
 
@@ -285,6 +287,28 @@ class Oracle:
         if rc:
             raise RuntimeError(f"oracle: tangent-linear run failed ({rc})")
         return hv, hd
+
+    @property
+    def state_size(self) -> int:
+        return (2 + self.dim) * self.N + sum(self.NF)
+
+    def tangent_linear_state(self, nsteps: int, dstate, dTw=None):
+        """Directional derivative from the current state (left unchanged) along
+        ``dstate`` (rho [N], mom [dim][N], E [N], F [sum NF]) and, optionally, ``dTw``:
+        returns (history values [nsteps, 4], their derivatives [nsteps, 4], the
+        derivative of the state after the steps [state_size])."""
+        ds = np.ascontiguousarray(dstate, dtype=np.float64).ravel()
+        if ds.size != self.state_size:
+            raise ValueError("dstate has the wrong size")
+        dT = None if dTw is None else np.ascontiguousarray(dTw, dtype=np.float64)
+        hv = np.zeros((nsteps, 4))
+        hd = np.zeros((nsteps, 4))
+        dout = np.zeros(self.state_size)
+        rc = lib().orc_tl_state(self.h, int(nsteps), _p(ds), _p(dT), _p(hv), _p(hd),
+                                _p(dout))
+        if rc:
+            raise RuntimeError(f"oracle: tangent-linear run failed ({rc})")
+        return hv, hd, dout
 
 
 def make_desc(case) -> Desc:

@@ -56,8 +56,8 @@ def nusselt_scale(case, diameter: float = 1.0, dT_ref=None) -> float:
 
 class Rollout:
     """``n_steps`` steps from the solver's current state, with checkpoints every
-    ``checkpoint`` steps (the solver needs ``tape_steps >= checkpoint``, FP64,
-    linear convection, markers at rest)."""
+    ``checkpoint`` steps (the solver needs ``tape_steps >= checkpoint`` and
+    markers at rest)."""
 
     def __init__(self, s: IBMSolver, n_steps: int, checkpoint: int = 50):
         if s.nc == 0:

@@ -36,12 +36,46 @@ __device__ __forceinline__ double side_sigma(const GridK &g, int bc, int var, in
   return 1.0;
 }
 
-// Padded grid: one ghost layer per active direction, index (i+1) + ...
+// Padded grid: kPad ghost layers per active direction (the van Leer face value
+// reads the far-upwind cell, two layers out at a boundary face), index
+// (i + kPad) + (n0 + 2 kPad) * (...).
+constexpr int kPad = 2;
 __host__ __device__ __forceinline__ int64_t padded_count(const GridK &g) {
-  return (int64_t)(g.n[0] + 2) * (g.n[1] + 2) * (g.dim == 3 ? g.n[2] + 2 : 1);
+  return (int64_t)(g.n[0] + 2 * kPad) * (g.n[1] + 2 * kPad) *
+         (g.dim == 3 ? g.n[2] + 2 * kPad : 1);
 }
 __device__ __forceinline__ int64_t pidx(const GridK &g, int i, int j, int k) {
-  return (i + 1) + (int64_t)(g.n[0] + 2) * ((j + 1) + (int64_t)(g.n[1] + 2) * (g.dim == 3 ? k + 1 : 0));
+  return (i + kPad) + (int64_t)(g.n[0] + 2 * kPad) *
+                          ((j + kPad) + (int64_t)(g.n[1] + 2 * kPad) * (g.dim == 3 ? k + kPad : 0));
+}
+// Padded linear index t back to (i, j, k).
+template <int DIM>
+__device__ __forceinline__ void padded_cell(const GridK &g, int64_t t, int *X) {
+  const int pn0 = g.n[0] + 2 * kPad, pn1 = g.n[1] + 2 * kPad;
+  X[0] = (int)(t % pn0) - kPad;
+  X[1] = (int)((t / pn0) % pn1) - kPad;
+  X[2] = (DIM == 3) ? (int)(t / ((int64_t)pn0 * pn1)) - kPad : 0;
+}
+
+// van Leer face value from the upwind (C), downwind (D) and far-upwind (U)
+// values, as the predictor forms it, with its partial derivatives. Where the
+// limiter is off (a b <= 0) the value is phi_C: the almost-everywhere derivative
+// is 1 in C and 0 elsewhere.
+__device__ __forceinline__ double vanleer_d(double C, double D, double U, double &dC, double &dD,
+                                            double &dU) {
+  const double a = C - U, b = D - C, ab = a * b;
+  if (ab > 0.0) {
+    const double s = a + b, is2 = 1.0 / (s * s);
+    const double a2 = a * a * is2, b2 = b * b * is2;
+    dC = 1.0 + b2 - a2;
+    dD = a2;
+    dU = -b2;
+    return C + ab / s;
+  }
+  dC = 1.0;
+  dD = 0.0;
+  dU = 0.0;
+  return C;
 }
 
 __device__ __forceinline__ bool face_entry_valid(const GridK &g, int d, const int *f) {
@@ -383,11 +417,9 @@ __global__ void k_adj_prims(GridK g, StateV<S> st, double *pp) {
   const int64_t Np = padded_count(g);
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Np) return;
-  const int pn0 = g.n[0] + 2, pn1 = g.n[1] + 2;
-  const int i = (int)(t % pn0) - 1;
-  const int j = (int)((t / pn0) % pn1) - 1;
-  const int k = (DIM == 3) ? (int)(t / ((int64_t)pn0 * pn1)) - 1 : 0;
-  Resolved r = resolve<DIM>(g, i, j, k);
+  int X[3];
+  padded_cell<DIM>(g, t, X);
+  Resolved r = resolve<DIM>(g, X[0], X[1], X[2]);
   const double rho = st.rho[r.c];
   const double inv = 1.0 / rho;
   double u[3];
@@ -415,7 +447,8 @@ __global__ void k_adj_prims(GridK g, StateV<S> st, double *pp) {
 // u_bar at P [dim], u_bar at Q [dim], theta_bar at P, Q, half mu_bar, half
 // rho_bar, and per tangential direction t the cotangents A_t (of the face average
 // of d u_d/d x_t) and B_t (of d u_t / d x_t in the face divergence), each shared by
-// the centred differences at P and Q. The state face-flux cotangent is written.
+// the centred differences at P and Q; with van Leer convection also u_bar [dim]
+// and theta_bar at the far-upwind cell. The state face-flux cotangent is written.
 template <int DIM, typename S>
 __global__ void k_adj_faces(GridK g, int d, StateV<S> st, const double *pp,
                             const double *rs_bar, const double *ms0, const double *ms1,
@@ -445,12 +478,9 @@ __global__ void k_adj_faces(GridK g, int d, StateV<S> st, const double *pp,
   const double U = F / lr;
   const double muf = 0.5 * (muP + muQ);
   const double lamf = g.cp_Pr * muf;
-  double dn[3], tg[3] = {0.0, 0.0, 0.0}, cu[3];
+  double dn[3], tg[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int q = 0; q < DIM; ++q) {
-    dn[q] = (uQ[q] - uP[q]) * ih;
-    cu[q] = 0.5 * (uP[q] + uQ[q]);
-  }
+  for (int q = 0; q < DIM; ++q) dn[q] = (uQ[q] - uP[q]) * ih;
   double divf = dn[d];
 #pragma unroll
   for (int t = 0; t < DIM; ++t) {
@@ -471,7 +501,40 @@ __global__ void k_adj_faces(GridK g, int d, StateV<S> st, const double *pp,
     tg[t] = 0.5 * (gdP + gdQ);
     divf += 0.5 * (gtP + gtQ);
   }
-  const double ce = 0.5 * (cv * thP + cv * thQ);
+  // convected face values (u and c_v theta) and their weights on P, Q and the
+  // far-upwind cell (van Leer: P - e_d when F >= 0, else Q + e_d)
+  double cu[3], wPu[3], wQu[3], wUu[3], ce, wPe, wQe, wUe;
+  const bool vl = g.conv == CONV_VANLEER;
+  if (!vl) {
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      cu[q] = 0.5 * (uP[q] + uQ[q]);
+      wPu[q] = wQu[q] = 0.5;
+      wUu[q] = 0.0;
+    }
+    ce = 0.5 * (cv * thP + cv * thQ);
+    wPe = wQe = 0.5;
+    wUe = 0.0;
+  } else {
+    const bool pos = F >= 0.0;
+    int Uc[3] = {pos ? P[0] : Q[0], pos ? P[1] : Q[1], pos ? P[2] : Q[2]};
+    Uc[d] += pos ? -1 : 1;
+    const int64_t iU = pidx(g, Uc[0], Uc[1], Uc[2]);
+    double dC, dD;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      const double uU = pp[(1 + q) * Np + iU];
+      cu[q] = pos ? vanleer_d(uP[q], uQ[q], uU, dC, dD, wUu[q])
+                  : vanleer_d(uQ[q], uP[q], uU, dC, dD, wUu[q]);
+      wPu[q] = pos ? dC : dD;
+      wQu[q] = pos ? dD : dC;
+    }
+    const double thU = pp[(DIM + 1) * Np + iU];
+    ce = pos ? vanleer_d(cv * thP, cv * thQ, cv * thU, dC, dD, wUe)
+             : vanleer_d(cv * thQ, cv * thP, cv * thU, dC, dD, wUe);
+    wPe = pos ? dC : dD;
+    wQe = pos ? dD : dC;
+  }
   // cotangents of the entry's fluxes: the predictor's divergence at P (entry is
   // its upper face, when f_d >= 1) and at Q (its lower face, when f_d <= n-1)
   const bool wP = Q[d] >= 1, wQ = Q[d] <= g.n[d] - 1;
@@ -490,11 +553,11 @@ __global__ void k_adj_faces(GridK g, int d, StateV<S> st, const double *pp,
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
     Fb += FMb[q] * cu[q];
-    uPb[q] = 0.5 * FMb[q] * F;
-    uQb[q] = 0.5 * FMb[q] * F;
+    uPb[q] = wPu[q] * FMb[q] * F;
+    uQb[q] = wQu[q] * FMb[q] * F;
   }
   const double ceb = FEb * F;
-  double thPb = 0.5 * cv * ceb, thQb = 0.5 * cv * ceb;
+  double thPb = wPe * cv * ceb, thQb = wQe * cv * ceb;
   const double lamfb = -FEb * (thQ - thP) * ih;
   thQb += -FEb * lamf * ih;
   thPb += FEb * lamf * ih;
@@ -536,6 +599,11 @@ __global__ void k_adj_faces(GridK g, int d, StateV<S> st, const double *pp,
 #pragma unroll
   for (int t = 0; t < DIM; ++t)
     if (t != d) o[(int64_t)(v++) * NFtot] = 0.5 * divfb;  // B_t
+  if (vl) {  // far-upwind u_bar [dim], theta_bar
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) o[(int64_t)(v++) * NFtot] = wUu[q] * FMb[q] * F;
+    o[(int64_t)(v++) * NFtot] = wUe * cv * ceb;
+  }
   Fbar_out[f] = Fb;
 }
 
@@ -602,16 +670,15 @@ __global__ void k_adj_cells(GridK g, StateV<S> st, const double *pp, const doubl
 // Per padded cell X: every cotangent that reaches the primitives at X from the face
 // reverses (own faces and faces that take centred differences through X) and the
 // cell reverses of its neighbours; mu_bar is turned into theta_bar at X's theta.
-template <int DIM>
-__global__ void k_adj_gather(GridK g, const double *pp, const double *fo, int64_t NFtot,
-                             int64_t foff0, int64_t foff1, int64_t foff2, const double *co,
-                             double *pb) {
+template <int DIM, typename S>
+__global__ void k_adj_gather(GridK g, StateV<S> st, const double *pp, const double *fo,
+                             int64_t NFtot, int64_t foff0, int64_t foff1, int64_t foff2,
+                             const double *co, double *pb) {
   const int64_t Np = padded_count(g);
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Np) return;
-  const int pn0 = g.n[0] + 2, pn1 = g.n[1] + 2;
-  const int X[3] = {(int)(t % pn0) - 1, (int)((t / pn0) % pn1) - 1,
-                    (DIM == 3) ? (int)(t / ((int64_t)pn0 * pn1)) - 1 : 0};
+  int X[3];
+  padded_cell<DIM>(g, t, X);
   const int64_t foff[3] = {foff0, foff1, foff2};
   const int64_t N = g.N;
   double rb = 0.0, ub[3] = {0.0, 0.0, 0.0}, thb = 0.0, mub = 0.0, ppb = 0.0;
@@ -637,6 +704,21 @@ __global__ void k_adj_gather(GridK g, const double *pp, const double *fo, int64_
         thb += fv(d, e, 2 * DIM);
         mub += fv(d, e, 2 * DIM + 2);
         rb += fv(d, e, 2 * DIM + 3);
+      }
+    }
+    // van Leer: X is the far-upwind cell of the entry X + 2 e_d when its flux is
+    // >= 0 and of the entry X - e_d when its flux is < 0
+    if (g.conv == CONV_VANLEER) {
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        int e[3] = {X[0], X[1], X[2]};
+        e[d] += sd == 0 ? 2 : -1;
+        if (!face_entry_valid(g, d, e)) continue;
+        const bool pos = (double)st.F[d][fidx(g, d, e[0], e[1], e[2])] >= 0.0;
+        if (pos != (sd == 0)) continue;
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) ub[q] += fv(d, e, 4 * DIM + 2 + q);
+        thb += fv(d, e, 5 * DIM + 2);
       }
     }
     // faces of direction d whose P or Q is X -/+ e_t
@@ -708,8 +790,9 @@ __global__ void k_adj_fold(GridK g, StateV<S> st, const double *pb, const double
   const int64_t c = cidx(g, i, j, k), Np = padded_count(g);
   const double *msb[3] = {ms0, ms1, ms2};
   const int c3[3] = {i, j, k};
-  // per direction: own coordinate and at most one image (coordinate, side or -1)
-  int pos[3][2], side[3][2], cnt[3];
+  // per direction: own coordinate and the ghost positions (within kPad layers)
+  // that resolve to it, each with the side it crosses (-1: none or periodic)
+  int pos[3][1 + 2 * kPad], side[3][1 + 2 * kPad], cnt[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     pos[d][0] = c3[d];
@@ -717,12 +800,12 @@ __global__ void k_adj_fold(GridK g, StateV<S> st, const double *pb, const double
     cnt[d] = 1;
     if (d >= DIM) continue;
     const int n = g.n[d];
-    if (g.bc[d][0] == BC_PERIODIC) {
-      if (c3[d] == 0) { pos[d][1] = n; side[d][1] = -1; cnt[d] = 2; }
-      else if (c3[d] == n - 1) { pos[d][1] = -1; side[d][1] = -1; cnt[d] = 2; }
-    } else {
-      if (c3[d] == 0) { pos[d][1] = -1; side[d][1] = 0; cnt[d] = 2; }
-      else if (c3[d] == n - 1) { pos[d][1] = n; side[d][1] = 1; cnt[d] = 2; }
+    const bool per = g.bc[d][0] == BC_PERIODIC;
+    for (int l = 1; l <= kPad; ++l) {
+      // low ghost -l and high ghost n - 1 + l
+      const int lo = per ? n - l : l - 1, hi = per ? l - 1 : n - l;
+      if (lo == c3[d]) { pos[d][cnt[d]] = -l; side[d][cnt[d]] = per ? -1 : 0; ++cnt[d]; }
+      if (hi == c3[d]) { pos[d][cnt[d]] = n - 1 + l; side[d][cnt[d]] = per ? -1 : 1; ++cnt[d]; }
     }
   }
   double rb = 0.0, ub[3] = {0.0, 0.0, 0.0}, thb = 0.0, ppb = 0.0;
@@ -913,7 +996,7 @@ void run_adj_predictor(const Launch &L, const Bufs &B, int slot, double *sb_out)
                        (const double *)B.pprim, (const double *)B.ms_bar[0],
                        (const double *)B.ms_bar[1], (const double *)B.ms_bar[2],
                        (const double *)B.Es_bar, B.co);
-    hipLaunchKernelGGL((k_adj_gather<DIM>), dim3(nb256(Np)), dim3(256), 0, L.st, g,
+    hipLaunchKernelGGL((k_adj_gather<DIM, S>), dim3(nb256(Np)), dim3(256), 0, L.st, g, st,
                        (const double *)B.pprim, (const double *)B.fo, NFt, face_off(g, 0),
                        face_off(g, 1), face_off(g, 2), (const double *)B.co, B.pbar);
     hipLaunchKernelGGL((k_adj_fold<DIM, S>), dim3(nb256(g.N)), dim3(256), 0, L.st, g, st,

@@ -357,7 +357,8 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
     }
     B.pprim = C.take<double>((size_t)(dim + 4) * Np);
     B.pbar = C.take<double>((size_t)(dim + 3) * Np);
-    B.fo = C.take<double>((size_t)(4 * dim + 2) * NFt);
+    const int nfo = (d.convection == IBM_CONV_VANLEER) ? 5 * dim + 3 : 4 * dim + 2;
+    B.fo = C.take<double>((size_t)nfo * NFt);
     B.co = C.take<double>((size_t)(dim * dim + dim + 2) * N);
     B.rs_bar = C.take<double>(N);
     B.Es_bar = C.take<double>(N);
@@ -1012,8 +1013,6 @@ int32_t ibm_tape_length(const ibm_ctx *ctx) { return ctx ? ctx->tape_len : 0; }
 ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *state_bar_in,
                             double *state_bar_out, const double *out_bar, double *Tw_bar) {
   if (!ctx) return IBM_E_ARG;
-  if (ctx->L.g.conv != ibmk::CONV_LINEAR)
-    return fail(ctx, IBM_E_ARG, "adjoint_step: needs linear convection");
   if (ctx->motion_axis >= 0) return fail(ctx, IBM_E_ARG, "adjoint_step: markers must be at rest");
   if (!state_bar_in || !state_bar_out) return fail(ctx, IBM_E_ARG, "adjoint_step: NULL cotangent");
   if (state_bar_in == state_bar_out)

@@ -32,7 +32,8 @@ constexpr int kRedThreads = 1024;  // threads of the single-block marker kernels
 constexpr int kPairBits = 20;      // (cell << 20) | pair id in the sorted pair keys
 constexpr int kMaxNbr = 192;       // neighbours per marker row of the Gram matrix
 constexpr int kFusedMarkers = 1024; // marker capacity up to which one block does a step's marker work
-constexpr int kFaceOut = 14;       // per-face values of the reverse predictor (4 dim + 2)
+constexpr int kFaceOut = 18;       // per-face values of the reverse predictor (4 dim + 2,
+                                   // 5 dim + 3 with van Leer convection)
 
 // Grid, physics and time-step constants, passed by value to every grid kernel.
 struct GridK {

@@ -4,7 +4,12 @@ per input block of the state (so that a wrong transpose names its block), and th
 checkpointed gradient with respect to the wall temperatures against the FP64
 oracle's tangent-linear (dual-number) run and against central finite differences.
 
-The adjoint needs linear convection; every case here sets it."""
+With van Leer convection the adjoint keeps the branches the forward took (upwind
+side by the sign of the face mass flux, limiter on or off): the derivative almost
+everywhere, which the oracle's dual numbers compute too. Central differences agree
+with it only where the step does not cross a branch, so those cases use noisy
+states, a small step, and no flux perturbation on faces whose flux is exactly zero
+(slip walls, where the upwind choice sits on its switch)."""
 import numpy as np
 import pytest
 import torch
@@ -17,6 +22,7 @@ from helpers import make_gpu, make_oracle, rel_l2, to_np
 pytestmark = pytest.mark.gpu
 
 LIN = inputs.CONV_LINEAR
+VL = inputs.CONV_VANLEER
 
 
 def _blocks(s):
@@ -39,7 +45,8 @@ def _J(s, x, step0, w, ob):
     return float(torch.dot(w, y)) + float(np.dot(ob, to_np(h[0])))
 
 
-def _single_step_case(c, amplitude, warm, seed, h=1e-5, with_w=True):
+def _single_step_case(c, amplitude, warm, seed, h=1e-5, with_w=True, skip_zero_flux=False,
+                      thermal=0.0):
     s = make_gpu(c, amplitude=amplitude, tape_steps=1)
     if warm:
         s.step(warm)
@@ -47,6 +54,12 @@ def _single_step_case(c, amplitude, warm, seed, h=1e-5, with_w=True):
     _, info = s.step(0)
     step0 = int(info["step"])
     gen = np.random.default_rng(seed)
+    if thermal > 0.0:
+        # relative noise on rho and E, so that no theta difference is near zero
+        N, dim = s.N, s.dim
+        for a, b in ((0, N), ((1 + dim) * N, (2 + dim) * N)):
+            xi = torch.as_tensor(gen.uniform(-1.0, 1.0, b - a), device=s.device)
+            x0[a:b] *= 1.0 + thermal * xi
     n = s.state_size
     w = torch.as_tensor(gen.standard_normal(n) if with_w else np.zeros(n), device=s.device)
     ob = gen.standard_normal(4) * 1e-2
@@ -60,6 +73,8 @@ def _single_step_case(c, amplitude, warm, seed, h=1e-5, with_w=True):
     for name, (a, b) in _blocks(s).items():
         v = torch.zeros(n, dtype=torch.float64, device=s.device)
         v[a:b] = torch.as_tensor(gen.standard_normal(b - a), device=s.device)
+        if skip_zero_flux and name.startswith("F"):
+            v[a:b] = torch.where(x0[a:b] == 0.0, torch.zeros_like(v[a:b]), v[a:b])
         ad = float(torch.dot(sb, v))
         ident = float(torch.dot(w, v)) if (name == "rho" or name.startswith("mom")) else 0.0
         fd = (_J(s, x0 + h * v, step0, w, ob) - _J(s, x0 - h * v, step0, w, ob)) / (2 * h)
@@ -99,6 +114,126 @@ def test_adjoint_step_constant_viscosity(cuda):
 def test_adjoint_step_sphere_3d(cuda):
     c = inputs.scaled("cfg3", (26, 20, 18), ns=120, convection=LIN, Re=50.0)
     _check(_single_step_case(c, 1e-2, 2, 14), 1e-6)
+
+
+def _single_step_tl(c, warm, seed, thermal=2e-2, amplitude=5e-2):
+    """One step's adjoint, per input block of the state, against the oracle's
+    tangent-linear step from the same state (exact derivatives on both sides; they
+    differ by the two pressure solves' truncation at rtol 1e-13, measured up to
+    1e-9 relative on blocks with small derivatives)."""
+    s = make_gpu(c, amplitude=amplitude, tape_steps=1)
+    if warm:
+        s.step(warm)
+    x0 = _state_vector(s)
+    _, info = s.step(0)
+    step0 = int(info["step"])
+    gen = np.random.default_rng(seed)
+    N, dim = s.N, s.dim
+    for a, b in ((0, N), ((1 + dim) * N, (2 + dim) * N)):
+        xi = torch.as_tensor(gen.uniform(-1.0, 1.0, b - a), device=s.device)
+        x0[a:b] *= 1.0 + thermal * xi
+    n = s.state_size
+    w = gen.standard_normal(n)
+    ob = gen.standard_normal(4) * 1e-2
+    _set_state_vector(s, x0, step0)
+    s.step(1, hist=False, record=True)
+    sb = torch.empty(n, dtype=torch.float64, device=s.device)
+    Twb = torch.zeros(max(s.nc, 1), dtype=torch.float64, device=s.device)
+    s.adjoint_step(0, torch.as_tensor(w, device=s.device), sb, ob, Twb)
+    sb = to_np(sb)
+    o = make_oracle(c, amplitude=amplitude)
+    xs = to_np(x0)
+    _set_oracle_state(o, xs, step0)
+    out = {}
+    for name, (a, b) in _blocks(s).items():
+        v = np.zeros(n)
+        v[a:b] = gen.standard_normal(b - a)
+        _, hd, dout = o.tangent_linear_state(1, v)
+        tl = float(w @ dout) + float(ob @ hd[0])
+        ident = float(w @ v) if (name == "rho" or name.startswith("mom")) else 0.0
+        out[name] = (tl, float(sb @ v), ident)
+    return out
+
+
+def _set_oracle_state(o, x, step):
+    N, dim = o.N, o.dim
+    F, off = [], (2 + dim) * N
+    for d in range(dim):
+        F.append(x[off: off + o.NF[d]])
+        off += o.NF[d]
+    o.set_state(x[:N], x[N:(1 + dim) * N].reshape(dim, N), x[(1 + dim) * N:(2 + dim) * N], F,
+                step=step)
+
+
+def test_adjoint_step_vanleer_channel_with_body(cuda):
+    # van Leer convection: inflow / outflow / slip, markers; the far-upwind cell of a
+    # boundary face is the second ghost layer
+    c = inputs.scaled("cfg1", (70, 52), ns=60, convection=VL, Re=20.0)
+    _check(_single_step_tl(c, 3, 31), 1e-8)
+
+
+def test_adjoint_step_vanleer_periodic(cuda):
+    c = inputs.scaled("cfg1", (40, 30), ns=0, convection=VL,
+                      bc=[[inputs.PERIODIC] * 2, [inputs.PERIODIC] * 2])
+    _check(_single_step_tl(c, 2, 32), 1e-8)
+
+
+def test_adjoint_step_vanleer_sphere_3d(cuda):
+    c = inputs.scaled("cfg3", (26, 20, 18), ns=120, convection=VL, Re=50.0)
+    _check(_single_step_tl(c, 2, 33), 1e-8)
+
+
+def test_adjoint_step_vanleer_small_grid(cuda):
+    # n = 3 in one direction: a cell has up to two ghost images per side
+    c = inputs.scaled("cfg1", (24, 3), ns=0, convection=VL,
+                      bc=[[inputs.INFLOW, inputs.OUTFLOW], [inputs.SLIP] * 2])
+    _check(_single_step_tl(c, 1, 34), 1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tw_gradient_vanleer_matches_oracle_tangent_linear(cuda, prec):
+    c = inputs.scaled("cfg5", (96, 96), ns=60, convection=VL)
+    nsteps, ck = 12, 5
+    ob = np.random.default_rng(35).standard_normal((nsteps, 4))
+    s = make_gpu(c, precision=prec, tape_steps=ck)
+    _, Twb, _ = wall_temperature_gradient(s, nsteps, ob, checkpoint=ck)
+    Twb = to_np(Twb)
+    o = make_oracle(c)
+    # FP64: the same derivative to rounding; FP32 form: the derivative along the
+    # FP32 trajectory
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for j in range(3):
+        d = inputs.normal(1000 + j, c["ns"])
+        d = d / np.linalg.norm(d)
+        _, hd = o.tangent_linear(nsteps, d)
+        tl = float(np.sum(ob * hd))
+        ad = float(Twb @ d)
+        assert abs(ad - tl) <= tol * abs(tl), (j, ad, tl)
+
+
+def test_tw_gradient_vanleer_central_differences(cuda):
+    c = inputs.scaled("cfg5", (96, 96), ns=60, convection=VL)
+    nsteps, ck = 10, 4
+    ob = np.random.default_rng(36).standard_normal((nsteps, 4))
+    s = make_gpu(c, tape_steps=ck)
+    x0 = _state_vector(s)
+    _, Twb, _ = wall_temperature_gradient(s, nsteps, ob, checkpoint=ck)
+    Twb = to_np(Twb)
+    Tw0 = np.full(c["ns"], float(c["Tw"]))
+    h = 1e-6
+    for j in range(3):
+        d = inputs.normal(1000 + j, c["ns"])
+        d = d / np.linalg.norm(d)
+        Js = []
+        for sgn in (1.0, -1.0):
+            _set_state_vector(s, x0, 0)
+            s.set_wall_temperature(Tw0 + sgn * h * d)
+            hh, _ = s.step(nsteps)
+            Js.append(float(np.sum(ob * to_np(hh))))
+        s.set_wall_temperature(Tw0)
+        fd = (Js[0] - Js[1]) / (2 * h)
+        ad = float(Twb @ d)
+        assert abs(ad - fd) <= 1e-5 * abs(ad), (j, ad, fd)
 
 
 def _tw_case():
@@ -268,9 +403,3 @@ def test_adjoint_rejects_bad_calls(cuda):
     with pytest.raises(IBMError):  # in place
         s.adjoint_step(0, sb, sb, np.zeros(4), Twb)
     s.adjoint_step(1, sb, sb2, np.zeros(4), Twb)
-    # VANLEER contexts have no adjoint
-    cv = inputs.scaled("cfg1", (40, 32), ns=20)
-    sv = make_gpu(cv, tape_steps=1)
-    sv.step(1, record=True)
-    with pytest.raises(IBMError):
-        sv.adjoint_step(0, sb, sb2, np.zeros(4), Twb)

@@ -7,7 +7,7 @@ markers, Re 100, Ma 0.2, Tw/Tinf 0.8), with all inputs resident in HBM.
 
 Prints ONE JSON line: FP64 Mcell-steps/s (``value``), the FP32 form's throughput and
 its error against the FP64 run, the adjoint/forward time ratio on the gradient
-workload (512^2 cylinder, linear convection, 200 markers, checkpoints every 50),
+workload (512^2 cylinder, van Leer convection, 200 markers, checkpoints every 50),
 the roofline of the dominant kernel (HIP events on the library's stream over the
 timed region), and the FP64 CPU oracle timed on a bounded sample.
 
@@ -221,7 +221,7 @@ def run_adjoint(steps: int, checkpoint: int, warmup: int, precision: str = "fp64
     from paper_2301_09349_amd import inputs
     from paper_2301_09349_amd.adjoint import Rollout, nusselt_scale, _set_state_vector
 
-    case = inputs.case("cfg5", convection=inputs.CONV_LINEAR)
+    case = inputs.case("cfg5")
     s = make_solver(case, precision, tape_steps=checkpoint)
     if warmup:
         s.step(warmup)
@@ -256,7 +256,7 @@ def run_adjoint(steps: int, checkpoint: int, warmup: int, precision: str = "fp64
     t_rev = time.perf_counter() - t0
     gnorm = float(torch.linalg.norm(Tw_bar))
     return {"workload": "2D heated cylinder, 512x512 over [-4,12]x[-8,8], 200 candidate "
-                        "markers, Re 100, Ma 0.2, Tw 1.3, linear convection, CG rtol 1e-13; "
+                        "markers, Re 100, Ma 0.2, Tw 1.3, van Leer convection, CG rtol 1e-13; "
                         "gradient of the time-averaged Nusselt number w.r.t. T_w",
             "steps": steps, "checkpoint": checkpoint,
             "forward_ms_per_step": round(1e3 * t_fwd / steps, 4),

@@ -332,12 +332,18 @@ def test_autograd_function_matches_the_driver(cuda):
     assert float(Jn.detach()) > 0.0  # the wall is hotter than the stream
 
 
-def test_cfg5_nusselt_gradient_full_size(cuda):
+@pytest.mark.parametrize("conv", [LIN, VL], ids=["linear", "vanleer"])
+def test_cfg5_nusselt_gradient_full_size(cuda, conv):
     """The gradient workload at full size: 512^2, 200 markers, T_w = 1.3, time-averaged
-    Nusselt number over 500 steps, checkpoints every 50; central differences with step
-    1e-6 on 10 seeded unit directions, and the oracle's tangent-linear over the first
-    10 steps."""
-    c = inputs.case("cfg5", convection=LIN)
+    Nusselt number over 500 steps, checkpoints every 50; central differences on 10
+    seeded unit directions, and the oracle's tangent-linear over the first 10 steps.
+    The step is 1e-6 with linear convection; with van Leer convection it is 1e-7: over
+    500 steps the wake holds limiter branch points that a step of 1e-6 crosses
+    (measured disagreement 4e-6..8e-5 at 1e-4..1e-6, 3e-8..1.4e-7 at 1e-7). Even at
+    1e-7 a direction can cross one (2.2e-5 measured on one of ten), so with van Leer
+    every direction must agree to 1e-4 and all but two to 1e-6; the exact check is
+    the tangent-linear one."""
+    c = inputs.case("cfg5", convection=conv)
     n, ck = int(c["steps"]), int(c["checkpoint"])
     s = make_gpu(c, tape_steps=ck)
     x0 = _state_vector(s)
@@ -351,11 +357,17 @@ def test_cfg5_nusselt_gradient_full_size(cuda):
     Tw32 = Tw0.clone().requires_grad_(True)
     Jn32, _ = IBMRollout.apply(Tw32, s32, n, ck)
     Jn32.backward()
-    assert rel_l2(to_np(Tw32.grad), g) < 1e-5
+    e32 = rel_l2(to_np(Tw32.grad), g)
+    print(f"\nfull-size gradient, convection {conv}: FP32 form vs FP64 rel L2 {e32:.2e}")
+    # linear: ~3e-7 measured; van Leer: 1.5e-5 measured -- the limiter's weights
+    # (a^2 / (a + b)^2 and the like) move more under the FP32 trajectory's rounding
+    # where a + b is small than the linear scheme's constant halves
+    assert e32 < (1e-5 if conv == LIN else 1e-4)
     assert abs(float(Jn32.detach()) / float(Jn.detach()) - 1.0) < 1e-4
     del s32
     ku = nusselt_scale(c)
-    h = 1e-6
+    h = 1e-6 if conv == LIN else 1e-7
+    errs = []
     for j in range(10):
         d = inputs.normal(1000 + j, c["ns"])
         d = d / np.linalg.norm(d)
@@ -367,7 +379,13 @@ def test_cfg5_nusselt_gradient_full_size(cuda):
             Js.append(ku * float(hh[:, 3].mean()))
         fd = (Js[0] - Js[1]) / (2 * h)
         ad = float(g @ d)
-        assert abs(ad - fd) <= 1e-5 * abs(ad), (j, ad, fd)
+        errs.append(abs(ad - fd) / abs(ad))
+        print(f"  direction {j}: adjoint {ad:.10e} central difference {fd:.10e} "
+              f"rel {errs[-1]:.1e}")
+    if conv == LIN:
+        assert max(errs) <= 1e-5, errs
+    else:
+        assert max(errs) <= 1e-4 and sorted(errs)[-3] <= 1e-6, errs
     # oracle tangent-linear over the first steps
     m = 10
     _set_state_vector(s, x0, 0)
@@ -381,6 +399,7 @@ def test_cfg5_nusselt_gradient_full_size(cuda):
     _, hd = o.tangent_linear(m, d)
     tl = float(np.sum(hd[:, 3]))
     ad = float(to_np(Twb) @ d)
+    print(f"  oracle tangent-linear over {m} steps: rel {abs(ad - tl) / abs(tl):.1e}")
     assert abs(ad - tl) <= 1e-10 * abs(tl), (ad, tl)
 
 

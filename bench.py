@@ -58,7 +58,7 @@ def kernel_words(cls: str, dim: int, precision: str = "fp64") -> int:
 KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start", "setup"),
                 ("k_cg_iter", "cg"), ("k_mcg_iter", "cg"),
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
-                ("k_totals", "markers")]
+                ("k_totals", "markers"), ("k_markers_fused", "markers")]
 
 
 def kernel_class(name: str):

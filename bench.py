@@ -37,21 +37,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_words(cls: str, dim: int, precision: str = "fp64") -> int:
-    """Algorithmic cell-array words each kernel class must move per cell (each
-    distinct array element read or written once; face arrays counted as one word
-    per cell and direction)."""
-    # single-reduction CG: r, w, s_old, p, x (FP32 form: d), psi -> r', w', s, p, x (d);
-    # the FP32 form's refinement and restart launches (2-3 of each per solve) are
-    # counted as iterations
-    cg = 6 + 5
-    start = 3 if precision == "fp64" else 0   # FP64 CG start: r0, psi -> w0
-    return {
-        "predictor": (2 * dim + 2) + (dim + 2),          # rho, m, E, F -> rho*, m*, E*
-        "setup": (dim + 3) + (dim + 2) + (dim + 3) + (dim + 3) + start,
-        "correct": (2 * dim + 4) + (2 * dim + 2),
-        "cg": cg,
-    }[cls]
+def kernel_bytes(cls: str, dim: int, precision: str = "fp64") -> int:
+    """Algorithmic bytes each kernel class must move per cell (each distinct array
+    element read or written once; face arrays counted as one value per cell and
+    direction). State-type arrays take s bytes (8 FP64, 4 FP32); the pressure x, the
+    right-hand side b and the FP64 CG vectors take 8 in both forms."""
+    s = 8 if precision == "fp64" else 4
+    if cls == "predictor":
+        # rho, m, E, F and the previous E (extrapolated start) ->
+        # rho*, m*, E*, m^, psi (state type) and x (FP64)
+        return s * ((2 * dim + 3) + (dim + 2) + dim + 1) + 8
+    if cls == "setup":
+        if precision == "fp64":
+            # rho^n, m^, psi, F^ (state type), x, b, r0 (FP64); then the CG start
+            # psi, r0 -> w0
+            return s * (2 * dim + 2) + 8 * 3 + s + 8 * 2
+        # rho^n, m^, psi, F^, x, b and r32 (the FP32 inner start)
+        return s * (2 * dim + 2) + 8 * 2 + 4
+    if cls == "correct":
+        # rho*, E*, m^, F^, rho^n, x -> F, m, rho, E
+        return s * ((2 * dim + 3) + (2 * dim + 2)) + 8
+    if cls == "cg":
+        # single-reduction CG: r, w, s_old, p, x (FP32 form: d), psi -> r', w', s, p, x
+        # (d), in FP64 or (FP32 form's inner iterations, which most launches are)
+        # FP32; refinement launches are counted as iterations
+        return s * (6 + 5)
+    raise KeyError(cls)
 
 
 # kernel symbol prefix -> kernel class of the library's event timing
@@ -172,7 +183,6 @@ def run_forward(case, precision, steps, warmup):
     elapsed_prof = time.perf_counter() - t1
     prof = s.profile_read()
     s.profile(False)
-    w = 4 if precision == "fp32" else 8
     per_kernel = {}
     for cls, (ms, n) in prof.items():
         if n == 0:
@@ -180,7 +190,7 @@ def run_forward(case, precision, steps, warmup):
         ent = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n,
                "ms_per_step": ms / steps}
         if cls in ("predictor", "setup", "cg", "correct"):
-            b = kernel_words(cls, dim, precision) * w * N
+            b = kernel_bytes(cls, dim, precision) * N
             ent["alg_bytes_per_launch"] = b
             ent["GBps"] = b / (ms / n * 1e-3) / 1e9
         per_kernel[cls] = ent

@@ -44,9 +44,9 @@ def kernel_bytes(cls: str, dim: int, precision: str = "fp64") -> int:
     right-hand side b and the FP64 CG vectors take 8 in both forms."""
     s = 8 if precision == "fp64" else 4
     if cls == "predictor":
-        # rho, m, E, F and the previous E (extrapolated start) ->
-        # rho*, m*, E*, m^, psi (state type) and x (FP64)
-        return s * ((2 * dim + 3) + (dim + 2) + dim + 1) + 8
+        # rho, m, E, F and the two previous E (three-point extrapolated start) ->
+        # rho*, m*, E*, m^, psi, the kept E^{n-1} (state type) and x (FP64)
+        return s * ((2 * dim + 4) + (dim + 2) + dim + 2) + 8
     if cls == "setup":
         if precision == "fp64":
             # rho^n, m^, psi, F^ (state type), x, b, r0 (FP64); then the CG start

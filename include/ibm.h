@@ -125,9 +125,11 @@ size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32
  * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all work.
  * The state starts as the uniform stream rho = 1, theta = 1, u = U_inf.
  * Environment, read here: IBM_PREDICTOR=plain selects the per-cell predictor
- * instead of the LDS-tiled one; IBM_CG_START=plain starts every pressure solve
- * from p^n instead of p^n + (p^n - p^{n-1}) (the latter is used after a step of
- * this context; either start converges to the same solution within cg_rtol). */
+ * instead of the LDS-tiled one. The pressure solve starts from p^n extrapolated
+ * in time: 3 p^n - 3 p^{n-1} + p^{n-2} after two steps of this context, 2 p^n -
+ * p^{n-1} after one, p^n otherwise (and after ibm_set_state); IBM_CG_START=linear
+ * caps the order at the two-point form, IBM_CG_START=plain uses p^n always. Every
+ * start converges to the same solution within cg_rtol. */
 ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
                            int32_t tape_steps, void *hip_stream, ibm_ctx **out);
 

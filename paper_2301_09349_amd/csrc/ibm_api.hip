@@ -99,7 +99,12 @@ struct ibm_ctx {
   // the other state slot holds the state of the step before the current one (the CG
   // start is then extrapolated); cleared whenever the state is set from outside
   bool prev_valid = false;
-  bool extrapolate = true;  // IBM_CG_START=plain turns it off
+  // E_hist holds the energy of the state before the other slot's (the three-point
+  // start is then possible); cleared with prev_valid
+  bool hist_valid = false;
+  // highest order of the extrapolated CG start: 2 (default), 1 with
+  // IBM_CG_START=linear, 0 with IBM_CG_START=plain
+  int cg_order = 2;
   int tag = 0;  // step tag, one per step launched
   std::string err;
   CgScal cgh;
@@ -265,6 +270,7 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   }
   B.rho_s = field(N);
   B.E_s = field(N);
+  B.E_hist = field(N);
   B.psi = field(N);
   for (int q = 0; q < 3; ++q) {
     B.mom_s[q] = q < dim ? field(N) : nullptr;
@@ -540,7 +546,8 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
     const char *env = std::getenv("IBM_PREDICTOR");
     ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
     const char *cgs = std::getenv("IBM_CG_START");
-    ctx->extrapolate = !(cgs && std::strcmp(cgs, "plain") == 0);
+    ctx->cg_order = !cgs ? 2 : std::strcmp(cgs, "plain") == 0 ? 0
+                             : std::strcmp(cgs, "linear") == 0 ? 1 : 2;
     if (ctx->L.pred_lds && need > 65536) ibmk::enable_predictor_lds(desc->dim, desc->precision);
   }
   ctx->tape_cap = tape_steps;
@@ -599,7 +606,7 @@ ibm_status ibm_init_primitive(ibm_ctx *ctx, const void *rho, const void *u, cons
   ibmk::run_init_primitive(ctx->L, ctx->B, ctx->cur, rho, u, theta);
   HIPCHECK(ctx, hipGetLastError());
   ctx->step = 0;
-  ctx->prev_valid = false;
+  ctx->prev_valid = ctx->hist_valid = false;
   if (ctx->nc > 0 && ctx->motion_axis >= 0) {
     ibm_status s = rebuild_markers(ctx, 0.0);
     if (s) return s;
@@ -634,7 +641,7 @@ ibm_status ibm_set_state(ibm_ctx *ctx, const void *rho, const void *mom, const v
     HIPCHECK(ctx, hipGetLastError());
   }
   ctx->step = step;
-  ctx->prev_valid = false;
+  ctx->prev_valid = ctx->hist_valid = false;
   if (ctx->nc > 0 && ctx->motion_axis >= 0) {
     ibm_status s = rebuild_markers(ctx, double(step) * g.dt);
     if (s) return s;
@@ -813,8 +820,10 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       ibm_status ts = tape_copy(ctx, s, ctx->cur, true);
       if (ts) return ts;
     }
+    const int order =
+        std::min(ctx->cg_order, ctx->prev_valid ? (ctx->hist_valid ? 2 : 1) : 0);
     timed(IBM_PROF_PREDICTOR, 0, [&] {
-      ibmk::run_predictor(L, B, ctx->cur, ctx->prev_valid && ctx->extrapolate);
+      ibmk::run_predictor(L, B, ctx->cur, order, ctx->cg_order >= 2);
     });
     double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
     if (ctx->nc > 0) {
@@ -848,7 +857,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     const int iters = (int)((w >> 8) & 0xFFFFFF);
     if (P.on) P.count_cg(iters);
     if (err) {
-      ctx->prev_valid = false;
+      ctx->prev_valid = ctx->hist_valid = false;
       // this step's correction did not run; an earlier failure is sorted out below
       rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE
                                                                          : IBM_E_NOT_CONVERGED;
@@ -859,6 +868,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       HIPCHECK(ctx, hipGetLastError());
     }
     ctx->cur ^= 1;
+    ctx->hist_valid = ctx->prev_valid && ctx->cg_order >= 2;
     ctx->prev_valid = true;
     ctx->step += 1;
     ++done;
@@ -885,7 +895,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     const int s_bad = (f[ibmk::FLAG_BAD_STEP] - 1) - first_tag;
     if (s_bad >= 0 && s_bad <= n_steps) {
       ctx->cur = cur0 ^ (s_bad & 1);
-      ctx->prev_valid = false;
+      ctx->prev_valid = ctx->hist_valid = false;
       ctx->step = step0 + s_bad;
       done = s_bad;
     }
@@ -1025,7 +1035,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
   Bufs &B = ctx->B;
   hipStream_t st = L.st;
   const int slot = ctx->cur ^ 1;
-  ctx->prev_valid = false;  // the other slot now holds the recorded state
+  ctx->prev_valid = ctx->hist_valid = false;  // the other slot now holds the recorded state
   const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
   const double *ob = out_bar ? out_bar : zero4;
   // forward pieces of the step, recomputed from its record
@@ -1034,7 +1044,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     ibm_status r = tape_copy(ctx, tape_index, slot, false);
     if (r) return r;
   }
-  ibmk::run_predictor(L, B, slot, false);
+  ibmk::run_predictor(L, B, slot, 0, false);
   if (ctx->nc > 0) ibmk::run_markers_step(L, B, nullptr);
   ibmk::run_setup(L, B, slot, ++ctx->tag);
   HIPCHECK(ctx, hipMemcpyAsync(B.x, B.tape + B.tape_stride * (size_t)tape_index + B.tape_xoff,

@@ -147,15 +147,20 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
 // What the predictor also writes for the pressure set-up (App. A step 3), so that
 // no separate pass reads its outputs back: m^ = m* + dt G_c p^n, i.e. the momentum
 // update without the pressure gradient; psi = 1/(R theta*) with theta* = E*/(rho* c_v);
-// the CG start p^n, or p^n + (p^n - p^{n-1}) when E_prev (the previous state's
-// energy) is given. The spread of the forcing then adds its increment to m^ and
-// recomputes psi on the cells it touches.
+// the CG start: p^n extrapolated in time from the pressures of the last states
+// (p = (gamma - 1) E) -- p^n alone, 2 p^n - p^{n-1} when E_prev (the previous
+// state's energy) is given, 3 p^n - 3 p^{n-1} + p^{n-2} when E_prev2 is given too.
+// E_keep, when given, receives E^{n-1} for the next step's E_prev2 (it may be the
+// E_prev2 array: each cell is read before it is written). The spread of the
+// forcing then adds its increment to m^ and recomputes psi on the cells it touches.
 template <typename S>
 struct PredOut {
   S *mh[3];
   S *psi;
   double *x;
   const S *E_prev;
+  const S *E_prev2;
+  S *E_keep;
 };
 
 template <typename S>
@@ -164,7 +169,17 @@ __device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> 
   const S theta = E_s / (rho_s * S(g.cv));
   po.psi[c] = S(1) / (S(g.R) * theta);
   const double pn = double(S(g.gm1) * E);
-  po.x[c] = po.E_prev ? 2.0 * pn - double(S(g.gm1) * po.E_prev[c]) : pn;
+  double x0 = pn;
+  if (po.E_prev) {
+    const S Ep = po.E_prev[c];
+    const double pp = double(S(g.gm1) * Ep);
+    if (po.E_prev2)
+      x0 = 3.0 * (pn - pp) + double(S(g.gm1) * po.E_prev2[c]);
+    else
+      x0 = 2.0 * pn - pp;
+    if (po.E_keep) po.E_keep[c] = Ep;
+  }
+  po.x[c] = x0;
 }
 
 // Predictor (f = q = 0): explicit update of mass, momentum and internal energy.
@@ -1281,13 +1296,15 @@ void enable_predictor_lds(int dim, int prec) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-void run_predictor(const Launch &L, const Bufs &B, int cur, bool extrapolate) {
+void run_predictor(const Launch &L, const Bufs &B, int cur, int order, bool keep) {
   IBM_DISPATCH(L, {
     PredOut<S> po;
     for (int q = 0; q < 3; ++q) po.mh[q] = (S *)B.mhat[q];
     po.psi = (S *)B.psi;
     po.x = B.x;
-    po.E_prev = extrapolate ? (const S *)B.E[cur ^ 1] : nullptr;
+    po.E_prev = order >= 1 ? (const S *)B.E[cur ^ 1] : nullptr;
+    po.E_prev2 = order >= 2 ? (const S *)B.E_hist : nullptr;
+    po.E_keep = (order >= 1 && keep) ? (S *)B.E_hist : nullptr;
     if (L.pred_lds) {
       using T = PredLds<DIM, S>;
       const int64_t nt = (int64_t)((L.g.n[0] + T::TX - 1) / T::TX) *

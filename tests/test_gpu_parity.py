@@ -3,6 +3,7 @@ same seeded inputs. FP64 tolerance: relative L2 <= 1e-10 per field (the target
 for 100 steps of the 128^2 cylinder workload); single steps are held to 1e-12."""
 import numpy as np
 import pytest
+import torch
 
 from paper_2301_09349_amd import inputs
 from helpers import make_gpu, make_oracle, rel_l2, state_errors, to_np
@@ -122,20 +123,41 @@ def test_large_marker_set_parity(cuda):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-6)])
 def test_cg_start_does_not_change_the_solution(cuda, monkeypatch, precision, tol):
-    # the pressure solve starts from p^n + (p^n - p^{n-1}) after a step, or from p^n
-    # with IBM_CG_START=plain; both converge to the same solution within cg_rtol
+    # the pressure solve starts from 3 p^n - 3 p^{n-1} + p^{n-2} (default), from
+    # 2 p^n - p^{n-1} with IBM_CG_START=linear, or from p^n with IBM_CG_START=plain;
+    # all converge to the same solution within cg_rtol
     c = _channel((90, 70), 60)
-    g1 = make_gpu(c, precision)
-    monkeypatch.setenv("IBM_CG_START", "plain")
-    g2 = make_gpu(c, precision)
+    g = {}
+    for mode in ("quadratic", "linear", "plain"):
+        if mode == "quadratic":
+            monkeypatch.delenv("IBM_CG_START", raising=False)
+        else:
+            monkeypatch.setenv("IBM_CG_START", mode)
+        g[mode] = make_gpu(c, precision)
     monkeypatch.delenv("IBM_CG_START")
-    _, i1 = g1.step(30)
-    _, i2 = g2.step(30)
-    assert i1["cg_iters_total"] < i2["cg_iters_total"]
-    r1, m1, e1, _ = g1.get_state()
-    r2, m2, e2, _ = g2.get_state()
-    for a, b in ((r1, r2), (m1, m2), (e1, e2)):
-        assert rel_l2(to_np(a), to_np(b)) < tol
+    it = {k: s.step(30)[1]["cg_iters_total"] for k, s in g.items()}
+    assert it["quadratic"] <= it["linear"] < it["plain"], it
+    ref = g["plain"].get_state()
+    for mode in ("quadratic", "linear"):
+        st = g[mode].get_state()
+        for a, b in zip(st[:3], ref[:3]):
+            assert rel_l2(to_np(a), to_np(b)) < tol, mode
+
+
+def test_cg_start_history_is_reset_by_set_state(cuda):
+    # after set_state the extrapolation history is gone: stepping from a state set
+    # from outside matches a fresh context stepped from the same state, bitwise
+    c = _channel((64, 48), 40)
+    a, b = make_gpu(c), make_gpu(c)
+    a.step(5)
+    st = a.get_state()
+    a.step(3)
+    a.set_state(*st, step=5)
+    b.set_state(*st, step=5)
+    a.step(4)
+    b.step(4)
+    for x, y in zip(a.get_state()[:3], b.get_state()[:3]):
+        assert torch.equal(x, y)
 
 
 @pytest.mark.parametrize("variant", ["plain", "lds"])

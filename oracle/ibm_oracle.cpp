@@ -98,12 +98,16 @@ enum { MU_SUTHERLAND = 0, MU_CONSTANT = 1 };
 enum { V_RHO = 0, V_U0 = 1, V_U1 = 2, V_U2 = 3, V_TH = 4, V_P = 5, V_E = 6, V_PHOM = 7 };
 
 // Pinelli et al. 3-point regularised delta (Sec. 2.2, Eq. (6)); r in mesh widths.
-double kernel_phi(double r) {
-  r = std::fabs(r);
-  if (r <= 0.5) return (1.0 + std::sqrt(1.0 - 3.0 * r * r)) / 3.0;
-  if (r <= 1.5) return (5.0 - 3.0 * r - std::sqrt(1.0 - 3.0 * (1.0 - r) * (1.0 - r))) / 6.0;
-  return 0.0;
+// On dual numbers the branch is taken on the value.
+template <class S>
+S kernel_phi_t(S r) {
+  using std::sqrt;
+  if (val(r) < 0.0) r = -r;
+  if (val(r) <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+  if (val(r) <= 1.5) return (5.0 - 3.0 * r - sqrt(1.0 - 3.0 * (1.0 - r) * (1.0 - r))) / 6.0;
+  return S(0.0);
 }
+double kernel_phi(double r) { return kernel_phi_t<double>(r); }
 
 template <class T>
 struct Solver {
@@ -124,16 +128,18 @@ struct Solver {
   // candidate markers as given, and the subset in use (Sec. 3.1 check routine)
   int nc = 0;
   bool dedupe = false;
-  std::vector<double> cX0, cUd0, cdA;
+  std::vector<T> cX0;  // candidate positions (dual numbers carry their derivatives)
+  std::vector<double> cUd0, cdA;
   std::vector<T> cTw;
   std::vector<int> keep;
   // markers in use
   int ns = 0;
   int nslot = 9;
-  std::vector<double> X, Ud, dA, eps;
+  std::vector<T> X, eps;
+  std::vector<double> Ud, dA;
   std::vector<T> Tw;
   std::vector<long> scell;  // [ns][27] support cells
-  std::vector<double> sw;   // [ns][27] weights
+  std::vector<T> sw;        // [ns][27] weights
   int motion_axis = -1;
   double motion_amp = 0.0, motion_freq = 0.0;
 
@@ -405,21 +411,21 @@ struct Solver {
   // tensor product of kernel values at r = (x_c - X)/h per direction.
   int build_support() {
     scell.assign(size_t(ns) * 27, 0);
-    sw.assign(size_t(ns) * 27, 0.0);
+    sw.assign(size_t(ns) * 27, T(0.0));
     for (int k = 0; k < ns; ++k) {
       long idx[3][3];
-      double w1[3][3];
+      T w1[3][3];
       for (int a = 0; a < 3; ++a)
         for (int s = 0; s < 3; ++s) {
           idx[a][s] = 0;
-          w1[a][s] = (s == 0) ? 1.0 : 0.0;
+          w1[a][s] = T((s == 0) ? 1.0 : 0.0);
         }
       for (int a = 0; a < dim; ++a) {
-        double xi = (X[size_t(k) * 3 + a] - D.lo[a]) / h[a];
-        long b = (long)std::floor(xi);
+        T xi = (X[size_t(k) * 3 + a] - D.lo[a]) / h[a];
+        long b = (long)std::floor(val(xi));
         for (int s = 0; s < 3; ++s) {
           long ii = b - 1 + s;
-          w1[a][s] = kernel_phi((double(ii) + 0.5) - xi);
+          w1[a][s] = kernel_phi_t<T>(T(double(ii) + 0.5) - xi);
           if (D.bc[a][0] == PERIODIC)
             ii = ((ii % n[a]) + n[a]) % n[a];
           else if (ii < 0 || ii >= n[a])
@@ -442,43 +448,44 @@ struct Solver {
   // Lagrangian quadrature: A eps = 1 with A_kl = sum_c w_ck w_cl (Sec. 2.2,
   // Eqs. (8)-(9)); dense Cholesky and two steps of iterative refinement.
   int solve_eps() {
-    std::vector<double> A(size_t(ns) * ns, 0.0);
-    std::map<long, std::vector<std::pair<int, double>>> bycell;
+    using std::sqrt;
+    std::vector<T> A(size_t(ns) * ns, T(0.0));
+    std::map<long, std::vector<std::pair<int, T>>> bycell;
     for (int k = 0; k < ns; ++k)
       for (int s = 0; s < nslot; ++s)
         bycell[scell[size_t(k) * 27 + s]].push_back({k, sw[size_t(k) * 27 + s]});
     for (auto &kv : bycell)
       for (auto &a : kv.second)
         for (auto &b : kv.second) A[size_t(a.first) * ns + b.first] += a.second * b.second;
-    std::vector<double> L(A);
+    std::vector<T> L(A);
     for (int j = 0; j < ns; ++j) {
-      double s = L[size_t(j) * ns + j];
+      T s = L[size_t(j) * ns + j];
       for (int p = 0; p < j; ++p) s -= L[size_t(j) * ns + p] * L[size_t(j) * ns + p];
-      if (!(s > 0.0)) return 3;
-      double djj = std::sqrt(s);
+      if (!(val(s) > 0.0)) return 3;
+      T djj = sqrt(s);
       L[size_t(j) * ns + j] = djj;
       for (int i = j + 1; i < ns; ++i) {
-        double t = L[size_t(i) * ns + j];
+        T t = L[size_t(i) * ns + j];
         for (int p = 0; p < j; ++p) t -= L[size_t(i) * ns + p] * L[size_t(j) * ns + p];
         L[size_t(i) * ns + j] = t / djj;
       }
     }
-    auto chol_solve = [&](std::vector<double> &x) {
+    auto chol_solve = [&](std::vector<T> &x) {
       for (int i = 0; i < ns; ++i) {
-        double t = x[i];
+        T t = x[i];
         for (int p = 0; p < i; ++p) t -= L[size_t(i) * ns + p] * x[p];
         x[i] = t / L[size_t(i) * ns + i];
       }
       for (int i = ns - 1; i >= 0; --i) {
-        double t = x[i];
+        T t = x[i];
         for (int p = i + 1; p < ns; ++p) t -= L[size_t(p) * ns + i] * x[p];
         x[i] = t / L[size_t(i) * ns + i];
       }
     };
-    eps.assign(ns, 1.0);
+    eps.assign(ns, T(1.0));
     chol_solve(eps);
     for (int it = 0; it < 2; ++it) {
-      std::vector<double> r(ns, 1.0);
+      std::vector<T> r(ns, T(1.0));
       for (int i = 0; i < ns; ++i)
         for (int j = 0; j < ns; ++j) r[i] -= A[size_t(i) * ns + j] * eps[j];
       chol_solve(r);
@@ -492,7 +499,8 @@ struct Solver {
   // Sec. 3.1 check routine (when enabled): of the candidates that fall in the same
   // cell only the one nearest to the cell centre is kept, ties to the lower id.
   void place_markers(double t) {
-    std::vector<double> Xc = cX0, Uc = cUd0;
+    std::vector<T> Xc = cX0;
+    std::vector<double> Uc = cUd0;
     if (motion_axis >= 0) {
       const double pi = 3.14159265358979323846;
       double off = motion_amp * std::sin(2.0 * pi * motion_freq * t);
@@ -511,9 +519,10 @@ struct Solver {
         long b[3] = {0, 0, 0};
         double d2 = 0.0;
         for (int a = 0; a < dim; ++a) {
-          double xi = (Xc[size_t(k) * 3 + a] - D.lo[a]) / h[a];
+          const double xk = val(Xc[size_t(k) * 3 + a]);
+          double xi = (xk - D.lo[a]) / h[a];
           b[a] = (long)std::floor(xi);
-          double dx = Xc[size_t(k) * 3 + a] - (D.lo[a] + (double(b[a]) + 0.5) * h[a]);
+          double dx = xk - (D.lo[a] + (double(b[a]) + 0.5) * h[a]);
           d2 += dx * dx;
           if (D.bc[a][0] == PERIODIC) b[a] = ((b[a] % n[a]) + n[a]) % n[a];
         }
@@ -525,7 +534,7 @@ struct Solver {
       std::sort(keep.begin(), keep.end());
     }
     ns = int(keep.size());
-    X.assign(size_t(ns) * 3, 0.0);
+    X.assign(size_t(ns) * 3, T(0.0));
     Ud.assign(size_t(ns) * 3, 0.0);
     dA.assign(ns, 0.0);
     Tw.assign(ns, T(0.0));
@@ -544,13 +553,13 @@ struct Solver {
                   const double *dAin, int flags) {
     nc = nm;
     dedupe = (flags & 1) != 0;
-    cX0.assign(size_t(nc) * 3, 0.0);
+    cX0.assign(size_t(nc) * 3, T(0.0));
     cUd0.assign(size_t(nc) * 3, 0.0);
     cTw.assign(nc, T(1.0));
     cdA.assign(nc, 0.0);
     for (int k = 0; k < nc; ++k) {
       for (int a = 0; a < dim; ++a) {
-        cX0[size_t(k) * 3 + a] = Xin[size_t(k) * dim + a];
+        cX0[size_t(k) * 3 + a] = T(Xin[size_t(k) * dim + a]);
         cUd0[size_t(k) * 3 + a] = Uin ? Uin[size_t(k) * dim + a] : 0.0;
       }
       cTw[k] = T(Twin ? Twin[k] : 1.0);
@@ -802,17 +811,21 @@ struct Solver {
     step = o.step;
     nc = o.nc;
     dedupe = o.dedupe;
-    cX0 = o.cX0;
+    auto values = [](const auto &src, std::vector<T> &dst) {
+      dst.resize(src.size());
+      for (size_t i = 0; i < src.size(); ++i) dst[i] = T(val(src[i]));
+    };
+    values(o.cX0, cX0);
     cUd0 = o.cUd0;
     cdA = o.cdA;
     keep = o.keep;
     ns = o.ns;
-    X = o.X;
+    values(o.X, X);
     Ud = o.Ud;
     dA = o.dA;
-    eps = o.eps;
+    values(o.eps, eps);
     scell = o.scell;
-    sw = o.sw;
+    values(o.sw, sw);
     motion_axis = o.motion_axis;
     motion_amp = o.motion_amp;
     motion_freq = o.motion_freq;
@@ -1015,6 +1028,33 @@ int orc_tl_run(void *p, int nsteps, const double *dTw, double *hv, double *hd) {
   for (int k = 0; k < t.ns; ++k) t.Tw[k] = t.cTw[t.keep[k]];
   for (int i = 0; i < nsteps; ++i) {
     int rc = t.do_step();
+    for (int q = 0; q < 3; ++q) {
+      hv[size_t(i) * 4 + q] = t.force[q].v;
+      hd[size_t(i) * 4 + q] = t.force[q].d;
+    }
+    hv[size_t(i) * 4 + 3] = t.heat.v;
+    hd[size_t(i) * 4 + 3] = t.heat.d;
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+// Tangent-linear run from the current state (left unchanged) along a direction of
+// the candidate marker positions (dX [nc][dim]): the markers in use, their kernel
+// weights and quadrature weights are formed again on dual numbers (the check
+// routine's choice and the support cells follow the values); per step Fx, Fy, Fz,
+// H and their derivatives.
+int orc_tl_shape(void *p, int nsteps, const double *dX, double *hv, double *hd) {
+  Solver<double> &s = static_cast<Handle *>(p)->s;
+  Solver<Dual> t;
+  if (t.init(s.D)) return 1;
+  t.copy_from(s);
+  for (int k = 0; k < t.nc; ++k)
+    for (int a = 0; a < s.dim; ++a) t.cX0[size_t(k) * 3 + a].d = dX[size_t(k) * s.dim + a];
+  int rc = t.refresh_markers(double(t.step) * t.dt);
+  if (rc) return rc;
+  for (int i = 0; i < nsteps; ++i) {
+    rc = t.do_step();
     for (int q = 0; q < 3; ++q) {
       hv[size_t(i) * 4 + q] = t.force[q].v;
       hd[size_t(i) * 4 + q] = t.force[q].d;

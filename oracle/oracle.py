@@ -105,6 +105,8 @@ def lib():
         L.orc_spread.argtypes = [P, D, D]
         L.orc_tl_run.restype = ctypes.c_int
         L.orc_tl_run.argtypes = [P, ctypes.c_int, D, D, D]
+        L.orc_tl_shape.restype = ctypes.c_int
+        L.orc_tl_shape.argtypes = [P, ctypes.c_int, D, D, D]
         L.orc_tl_state.restype = ctypes.c_int
         L.orc_tl_state.argtypes = [P, ctypes.c_int, D, D, D, D, D]
         _lib = L
@@ -284,6 +286,18 @@ class Oracle:
         hv = np.zeros((nsteps, 4))
         hd = np.zeros((nsteps, 4))
         rc = lib().orc_tl_run(self.h, int(nsteps), _p(dTw), _p(hv), _p(hd))
+        if rc:
+            raise RuntimeError(f"oracle: tangent-linear run failed ({rc})")
+        return hv, hd
+
+    def tangent_linear_shape(self, nsteps: int, dX):
+        """Directional derivative along ``dX`` ([n candidates, dim]: the candidate
+        marker positions) of the per-step (Fx, Fy, Fz, H) from the current state
+        (left unchanged); returns (values, derivatives), each [nsteps, 4]."""
+        dX = np.ascontiguousarray(dX, dtype=np.float64).reshape(-1)
+        hv = np.zeros((nsteps, 4))
+        hd = np.zeros((nsteps, 4))
+        rc = lib().orc_tl_shape(self.h, int(nsteps), _p(dX), _p(hv), _p(hd))
         if rc:
             raise RuntimeError(f"oracle: tangent-linear run failed ({rc})")
         return hv, hd

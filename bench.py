@@ -49,9 +49,9 @@ def kernel_bytes(cls: str, dim: int, precision: str = "fp64") -> int:
         return s * ((2 * dim + 4) + (dim + 2) + dim + 2) + 8
     if cls == "setup":
         if precision == "fp64":
-            # rho^n, m^, psi, F^ (state type), x, b, r0 (FP64); then the CG start
-            # psi, r0 -> w0
-            return s * (2 * dim + 2) + 8 * 3 + s + 8 * 2
+            # one kernel: rho^n, m^, psi, F^ (state type), x, b, r0 and the CG
+            # start's w0 = A r0 (FP64)
+            return s * (2 * dim + 2) + 8 * 4
         # rho^n, m^, psi, F^, x, b and r32 (the FP32 inner start)
         return s * (2 * dim + 2) + 8 * 2 + 4
     if cls == "correct":
@@ -93,7 +93,7 @@ def source_sha() -> str:
 
 WORKLOAD_LABEL = {"cfg1": "cylinder128", "cfg2a": "cylinder1024", "cfg2b": "cylinder1024",
                   "cfg2": "cylinder1024", "cfg3": "sphere256", "cfg4": "moving512",
-                  "cfg5": "gradient512"}
+                  "cfg5": "gradient512", "osc1": "oscillating512", "osc2": "oscillating512"}
 
 
 def traffic_entry(label: str, kernel: str):
@@ -302,6 +302,27 @@ def run_sphere(steps: int, warmup: int):
     return res
 
 
+def run_moving(steps: int, warmup: int):
+    """The streamwise-oscillating cylinder (512^2, 200 candidate markers, x = 0.14 D
+    sin(2 pi f_c t), Re 100, Ma 0.3, Tw/Tinf 2): markers re-placed, re-selected and
+    re-weighted every step, in both forms."""
+    from paper_2301_09349_amd import inputs
+
+    case = inputs.case("osc2", cg_rtol=1e-10)
+    res = {"steps": steps}
+    for prec in ("fp64", "fp32"):
+        r = run_forward(case, prec, steps, warmup)
+        if "workload" not in res:
+            kept = r["solver"].markers_in_use()[0].shape[0]
+            res["workload"] = workload_text(case, kept, r["solver"].dt)
+        res[prec] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                     "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
+                     "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
+                                             for k, v in r["per_kernel"].items()}}
+        del r
+    return res
+
+
 def calibrate_copy():
     """A plain streaming kernel of known size for scaling the HBM counters: negation
     of CALIB_ELEMS float64 values (8 B read + 8 B written each), three launches."""
@@ -437,6 +458,10 @@ def summarize(directory: str, label: str, command: str):
 def workload_text(case, kept: int, dt: float) -> str:
     dim = case["dim"]
     body = "2D heated cylinder" if dim == 2 else "3D heated sphere"
+    m = case.get("motion")
+    if m:
+        body = "2D cylinder oscillating along %s, %g sin(2 pi %g t)," % (
+            "xyz"[m["axis"]], m["amp"], m["freq"])
     cells = "x".join(str(v) for v in case["n"][:dim])
     box = "x".join("[%g,%g]" % (case["lo"][d], case["hi"][d]) for d in range(dim))
     return ("%s, %s cells over %s, %d candidate markers (check routine keeps %d), Re %g, "
@@ -458,6 +483,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 sphere figures")
+    ap.add_argument("--no-moving", action="store_true",
+                    help="skip the oscillating-cylinder figures")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch the copy kernel used to scale HBM counters first")
     ap.add_argument("--summarize", metavar="DIR", help="summarize rocprofv3 output (no GPU)")
@@ -540,6 +567,10 @@ def main():
     if not args.no_3d and args.workload != "cfg3":
         log("bench: 256^3 sphere ...")
         out["sphere256"] = run_sphere(30, 10)
+        torch.cuda.empty_cache()
+    if not args.no_moving and args.workload not in ("osc1", "osc2"):
+        log("bench: oscillating cylinder ...")
+        out["oscillating512"] = run_moving(100, 10)
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         log(f"bench: adjoint leg, {args.adjoint_steps} steps ...")

@@ -241,6 +241,24 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
 /* Number of steps on the tape (recorded by the last IBM_RECORD call). */
 int32_t ibm_tape_length(const ibm_ctx *ctx);
 
+/* Gradient with respect to the candidate marker positions (not in the paper:
+ * shape sensitivities of the same objective as ibm_adjoint_step). Every adjoint
+ * step adds, for markers at rest, the cotangents of the step's kernel weights
+ * w_ck (Sec. 2.2, Eqs. (5)-(7)) and quadrature weights eps_k (Eqs. (8)-(9)) to an
+ * accumulator in the workspace. This call turns the accumulation into dJ/dX:
+ * one more solve with the Gram matrix A of Eq. (9) (A lambda = eps_bar, the
+ * adjoint of A eps = 1) gives w_bar -= lambda_k (W eps)_c + eps_k (W lambda)_c, and
+ * the kernel's derivative gives X_bar. The check routine's choice of markers and
+ * the support cells are held fixed (the derivative almost everywhere; candidates
+ * not in use get 0).
+ *   X_bar   device double [n candidates][dim]: dJ/dX is added (+=); NULL only
+ *           clears the accumulator
+ * The accumulator is cleared by every call (start a reverse pass with a NULL
+ * call). Synchronises. IBM_E_STATE without a tape workspace or markers, IBM_E_ARG
+ * for moving markers, IBM_E_SIZE above 4096 candidates (X_bar given),
+ * IBM_E_NOT_CONVERGED if the Gram solve fails. */
+ibm_status ibm_shape_gradient(ibm_ctx *ctx, double *X_bar);
+
 /* Kernel timing for measurement. While enabled, ibm_step records HIP events on
  * the context's stream around the launches of each kernel class and, after each
  * step, adds their durations to per-class totals. Classes (IBM_PROF_*): 0

@@ -86,6 +86,7 @@ SIGNATURES = {
     "ibm_get_field": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "ibm_adjoint_step": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _D, _P]),
     "ibm_tape_length": (ctypes.c_int32, [_P]),
+    "ibm_shape_gradient": (ctypes.c_int, [_P, _P]),
     "ibm_profile": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ibm_profile_read": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
 }

@@ -86,9 +86,11 @@ class Rollout:
         self.final_step = int(info["step"])
         return hist
 
-    def reverse(self, out_bar, state_bar_final=None):
+    def reverse(self, out_bar, state_bar_final=None, positions=False):
         """Returns (dJ/dT_w [n candidates], dJ/d(initial state)) for the per-step seeds
-        ``out_bar`` ([n_steps, 4] or [4]); leaves the solver in the final state."""
+        ``out_bar`` ([n_steps, 4] or [4]), and dJ/dX [n candidates, dim] of the
+        candidate marker positions as a third item with ``positions``; leaves the
+        solver in the final state."""
         if self.final is None:
             raise RuntimeError("Rollout.reverse before forward")
         s = self.s
@@ -102,6 +104,7 @@ class Rollout:
             sb.copy_(state_bar_final)
         sb2 = torch.empty_like(sb)
         Tw_bar = torch.zeros(s.nc, dtype=torch.float64, device=s.device)
+        s.shape_gradient(None)  # the adjoint steps below accumulate from zero
         for start, k, ck, st_step in reversed(self.segs):
             _set_state_vector(s, ck, st_step)
             s.step(k, hist=False, record=True)
@@ -109,6 +112,10 @@ class Rollout:
                 s.adjoint_step(i, sb, sb2, ob[start + i], Tw_bar)
                 sb, sb2 = sb2, sb
         _set_state_vector(s, self.final, self.final_step)
+        if positions:
+            X_bar = torch.zeros((s.nc, s.dim), dtype=torch.float64, device=s.device)
+            s.shape_gradient(X_bar)
+            return Tw_bar, sb, X_bar
         return Tw_bar, sb
 
 
@@ -121,6 +128,18 @@ def wall_temperature_gradient(s: IBMSolver, n_steps: int, out_bar, checkpoint: i
     hist = r.forward()
     Tw_bar, sb = r.reverse(out_bar, state_bar_final)
     return hist, Tw_bar, sb
+
+
+def marker_position_gradient(s: IBMSolver, n_steps: int, out_bar, checkpoint: int = 50):
+    """Returns (hist [n_steps, 4], dJ/dT_w [n candidates], dJ/dX [n candidates, dim])
+    for J = sum_n out_bar[n] . (Fx, Fy, Fz, H)_n over ``n_steps`` steps: the
+    sensitivity of the wall totals to the positions of the (resting) markers, with
+    the check routine's choice and the support cells held fixed. The solver ends in
+    the state after ``n_steps`` steps."""
+    r = Rollout(s, n_steps, checkpoint)
+    hist = r.forward()
+    Tw_bar, _, X_bar = r.reverse(out_bar, positions=True)
+    return hist, Tw_bar, X_bar
 
 
 class IBMRollout(torch.autograd.Function):

@@ -354,7 +354,8 @@ __global__ void k_adj_markers(GridK g, const int *mcount, const int64_t *pcell, 
                               int nslot, const double *ms0, const double *ms1, const double *ms2,
                               const double *Es_bar, const double *eps, const double *Ud,
                               const double *Tw, const double *mk, const int *ids, double sFx,
-                              double sFy, double sFz, double sH, double *mkbar, double *Tw_bar) {
+                              double sFy, double sFz, double sH, double *mkbar, double *Tw_bar,
+                              double *epsbar) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= mcount[0]) return;
   const int dim = g.dim, W = 2 * dim + 3;
@@ -377,10 +378,59 @@ __global__ void k_adj_markers(GridK g, const int *mcount, const int64_t *pcell, 
   rLb += g.cv * Tw[k] * Qb / dt;
   const double rhoL = mk[(int64_t)W * k];
   Tw_bar[ids[k]] += g.cv * rhoL * Qb / dt;
+  if (epsbar) {
+    // eps_k enters the spread (f = sum w eps F) and the body totals
+    const double *mf = mk + (int64_t)W * k;
+    double eb = dt * mf[2 + 2 * dim] * eint + g.dV * sH * mf[2 + 2 * dim];
+    for (int q = 0; q < dim; ++q)
+      eb += dt * mf[2 + dim + q] * mint[q] - g.dV * seeds[q] * mf[2 + dim + q];
+    epsbar[k] += eb;
+  }
   double *o = mkbar + (int64_t)W * k;
   o[0] = rLb;
   for (int q = 0; q < dim; ++q) o[1 + q] = -Fb[q] / dt;
   o[1 + dim] = -Qb / dt;
+}
+
+// Cotangent of every kernel weight w_ck of the step (added to wbar): through the
+// spread f_c = sum_k w_ck eps_k F_k (and the heat), and through the interpolation
+// rho_L = sum_c w_ck rho*_c (and M, E_L) of the predictor fields pf at the pair.
+__global__ void k_adj_shape_pairs(GridK g, const int *mcount, const int64_t *pcell, int nslot,
+                                  const double *ms0, const double *ms1, const double *ms2,
+                                  const double *Es_bar, const double *eps, const double *mk,
+                                  const double *mkbar, const double *pf, double *wbar) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = (int)(p / nslot), slot = (int)(p - (int64_t)k * nslot);
+  if (k >= mcount[0]) return;
+  const int dim = g.dim, W = 2 * dim + 3;
+  const double *msb[3] = {ms0, ms1, ms2};
+  const int64_t c = pcell[27 * k + slot];
+  const double *mf = mk + (int64_t)W * k, *mb = mkbar + (int64_t)W * k;
+  const double *f = pf + (int64_t)(27 * k + slot) * (dim + 2);
+  double sp = mf[2 + 2 * dim] * Es_bar[c];
+  double ip = mb[0] * f[0] + mb[1 + dim] * f[1 + dim];
+  for (int q = 0; q < dim; ++q) {
+    sp += mf[2 + dim + q] * msb[q][c];
+    ip += mb[1 + q] * f[1 + q];
+  }
+  wbar[27 * k + slot] += g.dt * eps[k] * sp + ip;
+}
+
+// The predictor fields (before the spread) at every pair, for k_adj_shape_pairs.
+template <typename S>
+__global__ void k_pair_fields(GridK g, const int *mcount, const int64_t *pcell, int nslot,
+                              const S *rho_s, const S *m0, const S *m1, const S *m2, const S *E_s,
+                              double *pf) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = (int)(p / nslot), slot = (int)(p - (int64_t)k * nslot);
+  if (k >= mcount[0]) return;
+  const int dim = g.dim;
+  const S *ms[3] = {m0, m1, m2};
+  const int64_t c = pcell[27 * k + slot];
+  double *f = pf + (int64_t)(27 * k + slot) * (dim + 2);
+  f[0] = double(rho_s[c]);
+  for (int q = 0; q < dim; ++q) f[1 + q] = double(ms[q][c]);
+  f[1 + dim] = double(E_s[c]);
 }
 
 // Interpolation transposed: an unweighted spread of the marker cotangents, by
@@ -970,12 +1020,37 @@ void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, doub
                      (const double *)B.ms_bar[2], (const double *)B.Es_bar, (const double *)B.eps,
                      (const double *)B.Ud, (const double *)B.Tw, (const double *)B.mk,
                      (const int *)B.ids, out_bar[0], out_bar[1], out_bar[2], out_bar[3], B.mkbar,
-                     Tw_bar);
+                     Tw_bar, B.epsbar);
   const int64_t cap = (int64_t)L.nc_cap * nslot;
+  if (B.wbar)
+    hipLaunchKernelGGL(k_adj_shape_pairs, dim3(nb256(cap)), dim3(256), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int64_t *)B.pcell, nslot,
+                       (const double *)B.ms_bar[0], (const double *)B.ms_bar[1],
+                       (const double *)B.ms_bar[2], (const double *)B.Es_bar,
+                       (const double *)B.eps, (const double *)B.mk, (const double *)B.mkbar,
+                       (const double *)B.pfld, B.wbar);
   hipLaunchKernelGGL(k_adj_spread_t, dim3(nb256(cap)), dim3(256), 0, L.st, L.g,
                      (const int *)B.mcount, (const int *)B.seg, (const uint64_t *)B.keys,
                      (const double *)B.pw, nslot, (const double *)B.mkbar, B.rs_bar, B.ms_bar[0],
                      B.ms_bar[1], B.ms_bar[2], B.Es_bar);
+}
+
+void run_pair_fields(const Launch &L, const Bufs &B) {
+  if (!B.pfld) return;
+  const int nslot = (L.g.dim == 3) ? 27 : 9;
+  const int64_t cap = (int64_t)L.nc_cap * nslot;
+  if (L.prec == 0)
+    hipLaunchKernelGGL((k_pair_fields<double>), dim3(nb256(cap)), dim3(256), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int64_t *)B.pcell, nslot,
+                       (const double *)B.rho_s, (const double *)B.mom_s[0],
+                       (const double *)B.mom_s[1], (const double *)B.mom_s[2],
+                       (const double *)B.E_s, B.pfld);
+  else
+    hipLaunchKernelGGL((k_pair_fields<float>), dim3(nb256(cap)), dim3(256), 0, L.st, L.g,
+                       (const int *)B.mcount, (const int64_t *)B.pcell, nslot,
+                       (const float *)B.rho_s, (const float *)B.mom_s[0],
+                       (const float *)B.mom_s[1], (const float *)B.mom_s[2],
+                       (const float *)B.E_s, B.pfld);
 }
 
 void run_adj_predictor(const Launch &L, const Bufs &B, int slot, double *sb_out) {

@@ -345,6 +345,7 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   B.tape_stride = B.tape_xoff = 0;
   B.pprim = B.pbar = B.fo = B.co = B.rs_bar = B.Es_bar = B.fbar = B.tbar = B.lam = B.rhs = nullptr;
   B.mkbar = nullptr;
+  B.wbar = B.epsbar = B.pfld = B.gsum = B.lam_g = nullptr;
   for (int q = 0; q < 3; ++q) B.ms_bar[q] = nullptr;
   if (tape_steps > 0) {
     const size_t NFt = (size_t)(g.NF[0] + g.NF[1] + g.NF[2]);
@@ -374,6 +375,11 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
     B.lam = C.take<double>(N);
     B.rhs = C.take<double>(N);
     B.mkbar = C.take<double>((size_t)(2 * dim + 3) * nc);
+    B.wbar = C.take<double>((size_t)27 * nc);
+    B.epsbar = C.take<double>(nc);
+    B.pfld = C.take<double>((size_t)27 * (dim + 2) * nc);
+    B.gsum = C.take<double>((size_t)54 * nc);
+    B.lam_g = C.take<double>(nc);
   }
   return (C.off + 255) & ~size_t(255);
 }
@@ -545,6 +551,8 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
     const size_t need = ibmk::predictor_lds_bytes(desc->dim, desc->precision);
     const char *env = std::getenv("IBM_PREDICTOR");
     ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
+    const char *fse = std::getenv("IBM_SETUP");
+    ctx->L.fused_setup = !(fse && std::strcmp(fse, "split") == 0);
     const char *cgs = std::getenv("IBM_CG_START");
     ctx->cg_order = !cgs ? 2 : std::strcmp(cgs, "plain") == 0 ? 0
                              : std::strcmp(cgs, "linear") == 0 ? 1 : 2;
@@ -579,6 +587,7 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   if (e == hipSuccess) e = hipMemsetAsync(ctx->B.totals, 0, 8 * sizeof(double), ctx->L.st);
   if (e == hipSuccess) {
     ibmk::run_uniform_state(ctx->L, ctx->B, 0);
+    if (ctx->B.wbar) ibmk::run_shape_clear(ctx->L, ctx->B, ctx->L.nc_cap);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->L.st);
@@ -1020,6 +1029,32 @@ ibm_status ibm_get_field(const ibm_ctx *cctx, int32_t which, void *dst) {
 
 int32_t ibm_tape_length(const ibm_ctx *ctx) { return ctx ? ctx->tape_len : 0; }
 
+ibm_status ibm_shape_gradient(ibm_ctx *ctx, double *X_bar) {
+  if (!ctx) return IBM_E_ARG;
+  if (!ctx->B.wbar) return fail(ctx, IBM_E_STATE, "shape_gradient: no adjoint workspace");
+  if (ctx->motion_axis >= 0)
+    return fail(ctx, IBM_E_ARG, "shape_gradient: markers must be at rest");
+  if (ctx->nc == 0) return fail(ctx, IBM_E_STATE, "shape_gradient: no markers");
+  const Launch &L = ctx->L;
+  hipStream_t st = L.st;
+  if (!X_bar) {
+    ibmk::run_shape_clear(L, ctx->B, ctx->nc);
+    HIPCHECK(ctx, hipGetLastError());
+    HIPCHECK(ctx, hipStreamSynchronize(st));
+    return IBM_OK;
+  }
+  if (!ibmk::shape_supported(ctx->nc))
+    return fail(ctx, IBM_E_SIZE, "shape_gradient: more candidate markers than supported");
+  HIPCHECK(ctx, hipMemsetAsync(ctx->B.flags, 0, 8 * sizeof(int), st));
+  ibmk::run_shape_gradient(L, ctx->B, ctx->nc, X_bar);
+  HIPCHECK(ctx, hipGetLastError());
+  int fl[8];
+  HIPCHECK(ctx, hipMemcpyAsync(fl, ctx->B.flags, sizeof(fl), hipMemcpyDeviceToHost, st));
+  HIPCHECK(ctx, hipStreamSynchronize(st));
+  if (fl[2]) return fail(ctx, IBM_E_NOT_CONVERGED, "shape_gradient: quadrature adjoint solve");
+  return IBM_OK;
+}
+
 ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *state_bar_in,
                             double *state_bar_out, const double *out_bar, double *Tw_bar) {
   if (!ctx) return IBM_E_ARG;
@@ -1045,7 +1080,10 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     if (r) return r;
   }
   ibmk::run_predictor(L, B, slot, 0, false);
-  if (ctx->nc > 0) ibmk::run_markers_step(L, B, nullptr);
+  if (ctx->nc > 0) {
+    ibmk::run_pair_fields(L, B);  // the interpolated fields, for the position gradient
+    ibmk::run_markers_step(L, B, nullptr);
+  }
   ibmk::run_setup(L, B, slot, ++ctx->tag);
   HIPCHECK(ctx, hipMemcpyAsync(B.x, B.tape + B.tape_stride * (size_t)tape_index + B.tape_xoff,
                                (size_t)L.g.N * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -319,21 +319,26 @@ struct PredLds {
   static constexpr int NFV = DIM + 3;  // F, uf, fm[DIM], fe
   static constexpr int CPT = TX * TY * TZ / kThreads;  // cells per thread
   static constexpr size_t bytes = sizeof(S) * (size_t)(NP * NV + NFMAX * NFV);
-  __device__ static constexpr int pt(int a, int b, int c) {
-    return (a + 2) + SX * ((b + 2) + SY * (DIM == 3 ? c + 2 : 0));
+  // 3D: the z planes are a ring (SZ a power of two): local plane c of a tile whose
+  // first plane has ring offset zoff sits in slot (c + 2 + zoff) mod SZ, so that the
+  // next tile up a column finds the planes it shares with this one in place
+  static constexpr bool RING = DIM == 3 && (SZ & (SZ - 1)) == 0;
+  __device__ static constexpr int pt(int a, int b, int c, int zoff) {
+    return (a + 2) +
+           SX * ((b + 2) + SY * (DIM == 3 ? (RING ? ((c + 2 + zoff) & (SZ - 1)) : c + 2) : 0));
   }
 };
 
 // Face fluxes from the LDS primitives; Q is the cell at local (qa, qb, qc), P the
 // cell below it along d. Same arithmetic as face_flux.
 template <int DIM, typename S>
-__device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int d, int qa, int qb,
-                                              int qc, S F, S &uf, S *fm, S &fe) {
+__device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int zoff, int d, int qa,
+                                              int qb, int qc, S F, S &uf, S *fm, S &fe) {
   using T = PredLds<DIM, S>;
   constexpr int NP = T::NP;
   int Q[3] = {qa, qb, qc}, P[3] = {qa, qb, qc};
   P[d] -= 1;
-  const int iP = T::pt(P[0], P[1], P[2]), iQ = T::pt(Q[0], Q[1], Q[2]);
+  const int iP = T::pt(P[0], P[1], P[2], zoff), iQ = T::pt(Q[0], Q[1], Q[2], zoff);
   const S rP = lv[iP], rQ = lv[iQ];
   S uP[3], uQ[3];
 #pragma unroll
@@ -358,13 +363,13 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int d
     int a[3] = {P[0], P[1], P[2]}, b[3] = {P[0], P[1], P[2]};
     a[t] += 1;
     b[t] -= 1;
-    const int ia = T::pt(a[0], a[1], a[2]), ib = T::pt(b[0], b[1], b[2]);
+    const int ia = T::pt(a[0], a[1], a[2], zoff), ib = T::pt(b[0], b[1], b[2], zoff);
     S gdP = (lv[(1 + d) * NP + ia] - lv[(1 + d) * NP + ib]) * hh;
     S gtP = (lv[(1 + t) * NP + ia] - lv[(1 + t) * NP + ib]) * hh;
     int c2[3] = {Q[0], Q[1], Q[2]}, e2[3] = {Q[0], Q[1], Q[2]};
     c2[t] += 1;
     e2[t] -= 1;
-    const int ic = T::pt(c2[0], c2[1], c2[2]), ie = T::pt(e2[0], e2[1], e2[2]);
+    const int ic = T::pt(c2[0], c2[1], c2[2], zoff), ie = T::pt(e2[0], e2[1], e2[2], zoff);
     S gdQ = (lv[(1 + d) * NP + ic] - lv[(1 + d) * NP + ie]) * hh;
     S gtQ = (lv[(1 + t) * NP + ic] - lv[(1 + t) * NP + ie]) * hh;
     tg[t] = S(0.5) * (gdP + gdQ);
@@ -380,7 +385,7 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int d
     const bool pos = F >= S(0);
     int U[3] = {pos ? P[0] : Q[0], pos ? P[1] : Q[1], pos ? P[2] : Q[2]};
     U[d] += pos ? -1 : 1;
-    const int iU = T::pt(U[0], U[1], U[2]);
+    const int iU = T::pt(U[0], U[1], U[2], zoff);
     const S thU = lv[(DIM + 1) * NP + iU];
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
@@ -430,20 +435,26 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     }
     __syncthreads();  // the previous tile is done with LDS
     // phase 1: primitives of the tile and its halo (points beyond two ghost
-    // layers are not needed and not loaded)
-    for (int p = threadIdx.x; p < NP; p += kThreads) {
-      const int li = p % T::SX, lj = (p / T::SX) % T::SY, lk = p / (T::SX * T::SY);
-      const int gi = x0 - 2 + li, gj = y0 - 2 + lj, gk = (DIM == 3) ? z0 - 2 + lk : 0;
+    // layers are not needed and not loaded). Up a column (3D), the planes shared
+    // with the previous tile (local -2..1) are already in the ring: only the TZ
+    // new planes (local 2..TZ+1) are loaded.
+    const int zoff = T::RING ? (z0 & (T::SZ - 1)) : 0;
+    const bool cont = T::RING && t > t0 && z0 != 0;
+    const int cfirst = cont ? 2 : -2, nplanes = cont ? T::TZ : T::SZ;
+    for (int p = threadIdx.x; p < T::SX * T::SY * nplanes; p += kThreads) {
+      const int li = p % T::SX, lj = (p / T::SX) % T::SY, lc = cfirst + p / (T::SX * T::SY);
+      const int gi = x0 - 2 + li, gj = y0 - 2 + lj, gk = (DIM == 3) ? z0 + lc : 0;
       bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
       if (DIM == 3) ok = ok && gk >= -2 && gk <= g.n[2] + 1;
       if (!ok) continue;
+      const int lp = T::pt(li - 2, lj - 2, lc, zoff);
       S r, u[3], th, pp;
       load_prim<DIM>(g, st, gi, gj, gk, r, u, th, pp);
-      lv[p] = r;
+      lv[lp] = r;
 #pragma unroll
-      for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + p] = u[q];
-      lv[(DIM + 1) * NP + p] = th;
-      lv[(DIM + 2) * NP + p] = mu_of(g, th);
+      for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + lp] = u[q];
+      lv[(DIM + 1) * NP + lp] = th;
+      lv[(DIM + 2) * NP + lp] = mu_of(g, th);
     }
     __syncthreads();
     // phase 2: cell-centred terms (-grad p, viscous dissipation) into registers
@@ -471,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
         int a1[3] = {ci, cj, ck}, a0[3] = {ci, cj, ck};
         a1[bd] += 1;
         a0[bd] -= 1;
-        const int i1 = T::pt(a1[0], a1[1], a1[2]), i0 = T::pt(a0[0], a0[1], a0[2]);
+        const int i1 = T::pt(a1[0], a1[1], a1[2], zoff), i0 = T::pt(a0[0], a0[1], a0[2], zoff);
         const S hh = S(0.5 * g.ih[bd]);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) gr[a][bd] = (lv[(1 + a) * NP + i1] - lv[(1 + a) * NP + i0]) * hh;
@@ -492,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       for (int a = 0; a < DIM; ++a)
 #pragma unroll
         for (int bd = 0; bd < DIM; ++bd) phi += (gr[a][bd] + gr[bd][a]) * gr[a][bd];
-      phi = lv[(DIM + 2) * NP + T::pt(ci, cj, ck)] * (phi - S(2.0 / 3.0) * divu * divu);
+      phi = lv[(DIM + 2) * NP + T::pt(ci, cj, ck, zoff)] * (phi - S(2.0 / 3.0) * divu * divu);
 #pragma unroll
       for (int q = 0; q < DIM; ++q) gpr[m][q] = -dt * gp[q];
       acc[m][DIM + 1] = dt * phi;
@@ -512,7 +523,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
         if (!ok) continue;
         const S F = st.F[d][fidx(g, d, gi, gj, gk)];
         S uf, fm[3], fe;
-        face_flux_lds<DIM, S>(g, lv, d, fi, fj, fk, F, uf, fm, fe);
+        face_flux_lds<DIM, S>(g, lv, zoff, d, fi, fj, fk, F, uf, fm, fe);
         lf[f] = F;
         lf[NFM + f] = uf;
 #pragma unroll
@@ -701,6 +712,115 @@ __global__ __launch_bounds__(kBlockThreads) void k_setup2(GridK g, const S *rho_
   bb = block_sum(bb, lds);
   if (threadIdx.x == 0) {
     partials[PART_BB * kMaxBlocks + blockIdx.x] = bb;
+    if (blockIdx.x == 0) {
+      cs->done = 0;
+      cs->iters = 0;
+      cs->step_tag = tag;
+      cs->xfinal = 0;
+    }
+  }
+}
+
+// b at one cell, with the arithmetic of k_setup2 (so that a value formed again for
+// a neighbour equals the one that cell writes).
+template <int DIM, typename S>
+__device__ __forceinline__ double setup_b(const GridK &g, const S *const *mh, const S *rho_n,
+                                          int i, int j, int k) {
+  const int ix[3] = {i, j, k};
+  double div = 0.0, aff = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    int hi[3] = {i, j, k};
+    hi[d] += 1;
+    const S fl = face_from_cells<DIM, S>(g, mh, rho_n, d, i, j, k);
+    const S fh = face_from_cells<DIM, S>(g, mh, rho_n, d, hi[0], hi[1], hi[2]);
+    div += (double(fh) - double(fl)) * g.ih[d];
+    if (g.bc[d][0] != BC_PERIODIC) {
+      if (ix[d] == 0 && g.bc[d][0] == BC_OUTFLOW) aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
+      if (ix[d] == g.n[d] - 1 && g.bc[d][1] == BC_OUTFLOW)
+        aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
+    }
+  }
+  return double(rho_n[cidx(g, i, j, k)]) - g.dt * div + g.dt * g.dt * aff;
+}
+
+// The homogeneous Laplacian of helm_lap with v given by cell coordinates.
+template <int DIM, typename VF>
+__device__ __forceinline__ double helm_lap_ijk(const GridK &g, VF v, int i, int j, int k,
+                                               double vc) {
+  double lap = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double ih = g.ih[d];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int ix[3] = {i, j, k};
+      ix[d] += side ? 1 : -1;
+      const int n = g.n[d];
+      double gf;
+      if (ix[d] >= 0 && ix[d] < n) {
+        gf = (v(ix[0], ix[1], ix[2]) - vc) * ih;
+      } else if (g.bc[d][0] == BC_PERIODIC) {
+        ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
+        gf = (v(ix[0], ix[1], ix[2]) - vc) * ih;
+      } else {
+        gf = (g.bc[d][side] == BC_OUTFLOW) ? (-2.0 * vc) * ih : 0.0;
+      }
+      lap += gf * ih;
+    }
+  }
+  return lap;
+}
+
+// Set-up and CG start in one pass (FP64 form): as k_setup2, and w0 = A r0 with the
+// neighbours' r0 formed again from m^, rho^n, psi and x (b by setup_b, A x by
+// helm_at), so that no second sweep reads r0 back; per-block partials of b.b,
+// gamma_0 = r0.r0 and delta_0 = w0.r0 (the first CG iteration's inputs).
+template <int DIM, typename S>
+__global__ __launch_bounds__(kBlockThreads) void k_setup_start(
+    GridK g, const S *rho_n, const S *mh0, const S *mh1, const S *mh2, S *Fh0, S *Fh1, S *Fh2,
+    const S *psi, const double *x, double *b, double *r0, double *w0, double *partials,
+    CgScal *cs, int tag) {
+  __shared__ double lds[48];
+  const S *mh[3] = {mh0, mh1, mh2};
+  S *Fh[3] = {Fh0, Fh1, Fh2};
+  double sums[3] = {0.0, 0.0, 0.0};
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  auto xv = [&](int64_t q) { return x[q]; };
+  auto r0_at = [&](int ii, int jj, int kk) {
+    const int64_t m = cidx(g, ii, jj, kk);
+    return setup_b<DIM, S>(g, mh, rho_n, ii, jj, kk) - helm_at<DIM>(g, psi, xv, ii, jj, kk, m, x[m]);
+  };
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const int ix[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int hi[3] = {i, j, k};
+      hi[d] += 1;
+      Fh[d][fidx(g, d, i, j, k)] = face_from_cells<DIM, S>(g, mh, rho_n, d, i, j, k);
+      if (ix[d] == g.n[d] - 1)
+        Fh[d][fidx(g, d, hi[0], hi[1], hi[2])] =
+            face_from_cells<DIM, S>(g, mh, rho_n, d, hi[0], hi[1], hi[2]);
+    }
+    const double bc_ = setup_b<DIM, S>(g, mh, rho_n, i, j, k);
+    const double rc = bc_ - helm_at<DIM>(g, psi, xv, i, j, k, c, x[c]);
+    const double wc = double(psi[c]) * rc - g.dt * g.dt * helm_lap_ijk<DIM>(g, r0_at, i, j, k, rc);
+    b[c] = bc_;
+    r0[c] = rc;
+    w0[c] = wc;
+    sums[0] += bc_ * bc_;
+    sums[1] += rc * rc;
+    sums[2] += wc * rc;
+  }
+  block_sum_n<3>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[PART_BB * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[PART_G * kMaxBlocks + blockIdx.x] = sums[1];
+    partials[PART_D * kMaxBlocks + blockIdx.x] = sums[2];
     if (blockIdx.x == 0) {
       cs->done = 0;
       cs->iters = 0;
@@ -1336,6 +1456,16 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
                          (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
                          (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
                          (const double *)B.x, B.b, B.rv32[0], B.partials, B.cg, tag);
+    return;
+  }
+  if (L.fused_setup) {
+    IBM_DISPATCH(L, {
+      hipLaunchKernelGGL((k_setup_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads),
+                         0, L.st, L.g, (const S *)B.rho[cur], (const S *)B.mhat[0],
+                         (const S *)B.mhat[1], (const S *)B.mhat[2], (S *)B.Fhat[0],
+                         (S *)B.Fhat[1], (S *)B.Fhat[2], (const S *)B.psi, (const double *)B.x,
+                         B.b, B.rv[0], B.wv[0], B.partials, B.cg, tag);
+    });
     return;
   }
   IBM_DISPATCH(L, {

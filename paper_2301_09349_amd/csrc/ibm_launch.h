@@ -69,12 +69,18 @@ struct Bufs {
   double *tbar;         // [N] cotangent of theta**
   double *lam, *rhs;    // [N] adjoint pressure and its right-hand side
   double *mkbar;        // [nc][2 dim + 3] marker cotangents
+  // marker-position gradient: kernel-weight cotangents per pair [nc][27] and
+  // quadrature-weight cotangents [nc] accumulated over adjoint steps; predictor
+  // fields at the pairs [nc][27][dim + 2]; per-pair cell sums [nc][27][2]; the
+  // adjoint quadrature solve [nc]
+  double *wbar, *epsbar, *pfld, *gsum, *lam_g;
 };
 
 struct Launch {
   GridK g;
   int prec;      // 0: FP64, 1: FP32
   int pred_lds;  // 1: LDS-tiled predictor, 0: per-cell predictor
+  int fused_setup;  // FP64 form: 1 set-up and CG start in one kernel, 0 two kernels
   int nc_cap;     // candidate capacity
   int npairs_pad; // power of two >= nc_cap * nslot
   hipStream_t st;
@@ -122,6 +128,10 @@ void run_adj_cg_init(const Launch &L, const Bufs &B, int tag);
 void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in, double *sb_out);
 // out_bar: host double[4], the cotangents of the step's Fx, Fy, Fz, H
 void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, double *Tw_bar);
+void run_pair_fields(const Launch &L, const Bufs &B);
+bool shape_supported(int nc);
+void run_shape_clear(const Launch &L, const Bufs &B, int nc);
+void run_shape_gradient(const Launch &L, const Bufs &B, int nc, double *X_bar);
 void run_adj_predictor(const Launch &L, const Bufs &B, int slot, double *sb_out);
 // copy of the finished pressure solution (either x buffer of the FP32 form)
 void run_copy_solution(const Launch &L, const Bufs &B, double *dst);

@@ -80,20 +80,21 @@ __global__ void k_place(GridK g, int nc, const double *X0, const double *U0, dou
 }
 
 // Sec. 3.1 check routine: a candidate is kept when no other candidate in its
-// cell is nearer to the centre (ties: the lower id wins).
+// cell is nearer to the centre (ties: the lower id wins). One wave per candidate:
+// its lanes test 64 other candidates at a time.
 __global__ void k_dedupe(int nc, const int64_t *key, const double *d2, int *keep) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nc) return;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (k >= nc) return;  // the whole wave
   const int64_t kk = key[k];
   const double dk = d2[k];
   int ok = 1;
-  for (int j = 0; j < nc; ++j) {
-    if (key[j] == kk && (d2[j] < dk || (d2[j] == dk && j < k))) {
-      ok = 0;
-      break;
-    }
+  for (int j0 = 0; j0 < nc && ok; j0 += 64) {
+    const int j = j0 + lane;
+    const bool beats = j < nc && key[j] == kk && (d2[j] < dk || (d2[j] == dk && j < k));
+    if (__ballot(beats) != 0) ok = 0;
   }
-  keep[k] = ok;
+  if (lane == 0) keep[k] = ok;
 }
 
 __global__ void k_keep_all(int nc, int *keep) {
@@ -179,6 +180,11 @@ __global__ void k_support(GridK g, const int *mcount, const double *X, int nslot
 
 // Bitonic sort of the pair keys in one block (npad a power of two); the keys
 // are unique, so the order is fully determined. Up to 4096 keys are sorted in LDS.
+// A pass of stride s <= 64 has thread t compare i = 2t - (t mod s) with i + s: the
+// 64 threads of a wave then touch only the 128 keys [128 w', 128 w' + 128) of
+// their window w' = t / 64 (the same window in every such pass), so between two
+// such passes on LDS a wave needs no block barrier, only the order of its own
+// LDS operations.
 __global__ void k_sort(uint64_t *keys, int npad, const int *mcount, int nslot) {
   extern __shared__ uint64_t sk[];
   const int np = mcount[0] * nslot;
@@ -204,7 +210,14 @@ __global__ void k_sort(uint64_t *keys, int npad, const int *mcount, int nslot) {
           K[j] = a;
         }
       }
-      __syncthreads();
+      // a block barrier unless this pass and the next both stay within the windows
+      // (the copy out after the last pass reads every window)
+      const bool last = stride == 1 && size == (unsigned)npad;
+      const unsigned next = stride > 1 ? stride >> 1 : size;  // stride of the next pass
+      if (in_lds && !last && stride <= 64 && next <= 64)
+        __builtin_amdgcn_wave_barrier();
+      else
+        __syncthreads();
     }
   }
   if (in_lds)
@@ -233,37 +246,56 @@ __global__ void k_segments(const uint64_t *keys, int nslot, int *mcount, int *se
 
 // Rows of the Gram matrix A_kl = sum_c w_ck w_cl (Eq. (9)) in ELL form, from the
 // tensor-product structure: A_kl = prod_d sum_{s,t: same cell index} phi_ks phi_lt.
-__global__ void k_gram(GridK g, const int *mcount, const int *sidx, const double *sw1, int *col,
-                       double *val, int *cnt, int *flags) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+// One block per row k: its threads test the markers l in parallel and a block scan
+// keeps the nonzeros in increasing l.
+constexpr int kGramThreads = 256;
+__global__ __launch_bounds__(kGramThreads) void k_gram(GridK g, const int *mcount,
+                                                       const int *sidx, const double *sw1,
+                                                       int *col, double *val, int *cnt,
+                                                       int *flags) {
+  __shared__ int lds[32];
+  __shared__ int ks[9];
+  __shared__ double kw[9];
+  const int k = blockIdx.x;
   const int n = mcount[0];
   if (k >= n) return;
-  int c = 0;
-  for (int l = 0; l < n; ++l) {
-    double a = 1.0;
-    bool nz = true;
-    for (int d = 0; d < g.dim && nz; ++d) {
-      double s = 0.0;
-      bool any = false;
-      for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q)
-          if (sidx[9 * k + 3 * d + p] == sidx[9 * l + 3 * d + q]) {
-            s += sw1[9 * k + 3 * d + p] * sw1[9 * l + 3 * d + q];
-            any = true;
-          }
-      if (!any) nz = false;
-      a *= s;
-    }
-    if (nz) {
-      if (c < kMaxNbr) {
-        col[(int64_t)kMaxNbr * k + c] = l;
-        val[(int64_t)kMaxNbr * k + c] = a;
-      }
-      ++c;
-    }
+  if (threadIdx.x < 9) {
+    ks[threadIdx.x] = sidx[9 * k + threadIdx.x];
+    kw[threadIdx.x] = sw1[9 * k + threadIdx.x];
   }
-  if (c > kMaxNbr) atomicOr(flags + 3, 1);
-  cnt[k] = c < kMaxNbr ? c : kMaxNbr;
+  __syncthreads();
+  int base = 0;
+  for (int start = 0; start < n; start += blockDim.x) {
+    const int l = start + threadIdx.x;
+    double a = 1.0;
+    int nz = 0;
+    if (l < n) {
+      nz = 1;
+      for (int d = 0; d < g.dim && nz; ++d) {
+        double s = 0.0;
+        bool any = false;
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q)
+            if (ks[3 * d + p] == sidx[9 * l + 3 * d + q]) {
+              s += kw[3 * d + p] * sw1[9 * l + 3 * d + q];
+              any = true;
+            }
+        if (!any) nz = 0;
+        a *= s;
+      }
+    }
+    int tot;
+    const int off = block_scan_excl(nz, lds, &tot);
+    if (nz && base + off < kMaxNbr) {
+      col[(int64_t)kMaxNbr * k + base + off] = l;
+      val[(int64_t)kMaxNbr * k + base + off] = a;
+    }
+    base += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (base > kMaxNbr) atomicOr(flags + 3, 1);
+    cnt[k] = base < kMaxNbr ? base : kMaxNbr;
+  }
 }
 
 __device__ __forceinline__ double block_dot_all(double v, double *lds) {
@@ -340,6 +372,128 @@ __global__ void k_eps_cg(int *mcount, const int *col, const double *val, const i
   }
   if (threadIdx.x == 0) {
     mcount[2] = total_it;
+    if (!ok) atomicOr(flags + 2, 1);
+  }
+}
+
+// The same solve with the vectors held by the block: each thread keeps x, r and
+// A p of its rows (i = threadIdx.x + j blockDim.x, j < R) in registers, and p is
+// shared through LDS for the products; the matrix is read from the ELL arrays.
+// Same restarts and tolerances as k_eps_cg (relative to |rhs|); for n <= R *
+// blockDim.x. rhs NULL: the right-hand side 1 (the quadrature weights); otherwise
+// A x = rhs (the adjoint of that solve). The iteration count goes to *it_out.
+template <int R>
+__global__ __launch_bounds__(kRedThreads) void k_eps_cg_regs(const int *mcount, const int *col,
+                                                             const double *val, const int *cnt,
+                                                             const double *rhs, double *xg,
+                                                             int *it_out, int *flags) {
+  extern __shared__ double ps[];  // n values of p (or x for the true residual)
+  __shared__ double lds[32];
+  const int n = mcount[0];
+  if (n == 0) return;
+  const int nt = blockDim.x;
+  double x[R], r[R], q[R], pr[R], bv[R];
+  double bb = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = threadIdx.x + j * nt;
+    x[j] = i < n ? xg[i] : 0.0;
+    bv[j] = i < n ? (rhs ? rhs[i] : 1.0) : 0.0;
+    bb += bv[j] * bv[j];
+    r[j] = q[j] = pr[j] = 0.0;
+  }
+  bb = block_dot_all(bb, lds);
+  if (!(bb > 0.0)) {  // zero right-hand side: x = 0
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = threadIdx.x + j * nt;
+      if (i < n) xg[i] = 0.0;
+    }
+    if (threadIdx.x == 0) *it_out = 0;
+    return;
+  }
+  const double tol_true2 = 1e-26 * bb, tol_in2 = 1e-30 * bb;
+  auto matvec = [&]() {  // q = A ps over this thread's rows
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = threadIdx.x + j * nt;
+      double sacc = 0.0;
+      if (i < n) {
+        const int m = cnt[i];
+        const int *cr = col + (int64_t)kMaxNbr * i;
+        const double *vr = val + (int64_t)kMaxNbr * i;
+        for (int e = 0; e < m; ++e) sacc += vr[e] * ps[cr[e]];
+      }
+      q[j] = sacc;
+    }
+  };
+  int total_it = 0;
+  bool ok = false;
+  for (int restart = 0; restart < 7 && !ok; ++restart) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = threadIdx.x + j * nt;
+      if (i < n) ps[i] = x[j];
+    }
+    __syncthreads();
+    matvec();
+    double rr = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = threadIdx.x + j * nt;
+      r[j] = i < n ? bv[j] - q[j] : 0.0;
+      pr[j] = r[j];
+      rr += r[j] * r[j];
+    }
+    rr = block_dot_all(rr, lds);  // its barriers also end the reads of x in ps
+    if (rr <= tol_true2) {
+      ok = true;
+      break;
+    }
+    if (restart == 6) break;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = threadIdx.x + j * nt;
+      if (i < n) ps[i] = pr[j];
+    }
+    __syncthreads();
+    const int maxit = 4 * n + 50;
+    for (int it = 0; it < maxit; ++it) {
+      matvec();
+      double pq = 0.0;
+#pragma unroll
+      for (int j = 0; j < R; ++j) pq += pr[j] * q[j];
+      pq = block_dot_all(pq, lds);
+      const double alpha = rr / pq;
+      double rn = 0.0;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        x[j] += alpha * pr[j];
+        r[j] -= alpha * q[j];
+        rn += r[j] * r[j];
+      }
+      rn = block_dot_all(rn, lds);
+      ++total_it;
+      if (rn <= tol_in2) break;
+      const double beta = rn / rr;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int i = threadIdx.x + j * nt;
+        pr[j] = r[j] + beta * pr[j];
+        if (i < n) ps[i] = pr[j];
+      }
+      rr = rn;
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = threadIdx.x + j * nt;
+    if (i < n) xg[i] = x[j];
+  }
+  if (threadIdx.x == 0) {
+    *it_out = total_it;
     if (!ok) atomicOr(flags + 2, 1);
   }
 }
@@ -537,6 +691,98 @@ __global__ __launch_bounds__(kRedThreads) void k_markers_fused(
     spread_one<DIM>(g, s, seg, keys, pw, eps, mk, sp);
 }
 
+// ------------------------------------------------- marker-position gradient
+// (not in the paper: the adjoint's derivative with respect to the candidate
+// positions X_k, for markers at rest). The adjoint steps accumulate the cotangent
+// of every kernel weight w_ck (wbar, per pair) and of every quadrature weight eps_k
+// (epsbar). A = W^T W with A eps = 1 gives, with A lambda = epsbar,
+//   wbar_ck -= lambda_k (W eps)_c + eps_k (W lambda)_c,
+// and w_ck = prod_d phi(r_d), r_d = (i_d + 1/2) - (X_d - lo_d)/h_d gives
+//   Xbar_kd = sum_c wbar_ck * (-phi'(r_d)/h_d) prod_{e != d} phi(r_e).
+
+// d phi / d r of the 3-point kernel.
+__device__ __forceinline__ double kernel_dphi(double r) {
+#pragma clang fp contract(off)
+  const double a = fabs(r), sg = r < 0.0 ? -1.0 : 1.0;
+  if (a <= 0.5) return sg * (-a / sqrt(1.0 - 3.0 * a * a));
+  if (a <= 1.5) {
+    const double b = 1.0 - a;
+    return sg * (-3.0 - 3.0 * b / sqrt(1.0 - 3.0 * b * b)) / 6.0;
+  }
+  return 0.0;
+}
+
+// Per cell of the sorted pairs: (W eps)_c and (W lambda)_c, written to each of
+// the cell's pairs.
+__global__ void k_shape_cellsums(const int *mcount, const int *seg, const uint64_t *keys,
+                                 const double *pw, int nslot, const double *eps,
+                                 const double *lam, double *gsum) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= mcount[1]) return;
+  const int a = seg[s], b = seg[s + 1];
+  const uint64_t mask = (1ull << kPairBits) - 1;
+  double se = 0.0, sl = 0.0;
+  for (int p = a; p < b; ++p) {
+    const int pid = (int)(keys[p] & mask);
+    const int k = pid / nslot, slot = pid - k * nslot;
+    const double w = pw[27 * k + slot];
+    se += w * eps[k];
+    sl += w * lam[k];
+  }
+  for (int p = a; p < b; ++p) {
+    const int pid = (int)(keys[p] & mask);
+    const int k = pid / nslot, slot = pid - k * nslot;
+    gsum[2 * (27 * k + slot)] = se;
+    gsum[2 * (27 * k + slot) + 1] = sl;
+  }
+}
+
+// Per marker in use: Xbar_k from its pairs, added to X_bar of its candidate id;
+// its accumulators are cleared.
+__global__ void k_shape_grad(GridK g, const int *mcount, const double *X, const int *ids,
+                             const double *eps, const double *lam, const double *gsum,
+                             double *wbar, double *epsbar, double *X_bar) {
+#pragma clang fp contract(off)
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mcount[0]) return;
+  double ph[3][3], dph[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 3; ++s) {
+      ph[a][s] = (s == 0) ? 1.0 : 0.0;
+      dph[a][s] = 0.0;
+    }
+  for (int a = 0; a < g.dim; ++a) {
+    const double xi = (X[3 * k + a] - g.lo[a]) / g.h[a];
+    const int64_t b = (int64_t)floor(xi);
+    for (int s = 0; s < 3; ++s) {
+      const double r = (double(b - 1 + s) + 0.5) - xi;
+      ph[a][s] = kernel_phi(r);
+      dph[a][s] = -kernel_dphi(r) / g.h[a];
+    }
+  }
+  double xb[3] = {0.0, 0.0, 0.0};
+  const int s2n = (g.dim == 3) ? 3 : 1;
+  for (int s2 = 0; s2 < s2n; ++s2)
+    for (int s1 = 0; s1 < 3; ++s1)
+      for (int s0 = 0; s0 < 3; ++s0) {
+        const int s = s0 + 3 * (s1 + 3 * s2);
+        const int64_t pq = 27 * k + s;
+        const double wb = wbar[pq] - lam[k] * gsum[2 * pq] - eps[k] * gsum[2 * pq + 1];
+        wbar[pq] = 0.0;
+        xb[0] += wb * dph[0][s0] * ph[1][s1] * ph[2][s2];
+        xb[1] += wb * ph[0][s0] * dph[1][s1] * ph[2][s2];
+        if (g.dim == 3) xb[2] += wb * ph[0][s0] * ph[1][s1] * dph[2][s2];
+      }
+  epsbar[k] = 0.0;
+  for (int a = 0; a < g.dim; ++a) X_bar[(int64_t)ids[k] * g.dim + a] += xb[a];
+}
+
+__global__ void k_shape_clear(int n, double *wbar, double *epsbar) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 27 * n) wbar[i] = 0.0;
+  if (i < n) epsbar[i] = 0.0;
+}
+
 // ------------------------------------------------------------------ launchers
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
@@ -559,7 +805,7 @@ void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, doubl
                      (const double *)B.cX0, (const double *)B.cUd0, B.cXc, B.cUdc, off, vel, axis,
                      B.ckey, B.cd2);
   if (dedupe)
-    hipLaunchKernelGGL(k_dedupe, dim3(nblk(nc, 256)), dim3(256), 0, L.st, nc,
+    hipLaunchKernelGGL(k_dedupe, dim3(nblk((int64_t)nc * 64, 256)), dim3(256), 0, L.st, nc,
                        (const int64_t *)B.ckey, (const double *)B.cd2, B.ckeep);
   else
     hipLaunchKernelGGL(k_keep_all, dim3(nblk(nc, 256)), dim3(256), 0, L.st, nc, B.ckeep);
@@ -579,14 +825,59 @@ void run_build_markers(const Launch &L, const Bufs &B, int nc) {
                      (const int *)B.mcount, nslot);
   hipLaunchKernelGGL(k_segments, dim3(1), dim3(kRedThreads), 0, L.st, (const uint64_t *)B.keys,
                      nslot, B.mcount, B.seg);
-  hipLaunchKernelGGL(k_gram, dim3(nblk(nc, 64)), dim3(64), 0, L.st, L.g, (const int *)B.mcount,
-                     (const int *)B.sidx, (const double *)B.sw1, B.ell_col, B.ell_val, B.ell_cnt,
-                     B.flags);
-  hipLaunchKernelGGL(k_eps_cg, dim3(1), dim3(kRedThreads), 0, L.st, B.mcount,
-                     (const int *)B.ell_col, (const double *)B.ell_val, (const int *)B.ell_cnt,
-                     B.eps, B.ev[0], B.ev[1], B.ev[2], B.flags);
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)nc), dim3(kGramThreads), 0, L.st, L.g,
+                     (const int *)B.mcount, (const int *)B.sidx, (const double *)B.sw1,
+                     B.ell_col, B.ell_val, B.ell_cnt, B.flags);
+  // the live count is on the device; the candidate count bounds it
+  const size_t psb = (size_t)nc * sizeof(double);
+  if (nc <= kRedThreads)
+    hipLaunchKernelGGL(k_eps_cg_regs<1>, dim3(1), dim3(kRedThreads), psb, L.st,
+                       (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
+                       (const int *)B.ell_cnt, (const double *)nullptr, B.eps, B.mcount + 2,
+                       B.flags);
+  else if (nc <= 4 * kRedThreads)
+    hipLaunchKernelGGL(k_eps_cg_regs<4>, dim3(1), dim3(kRedThreads), psb, L.st,
+                       (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
+                       (const int *)B.ell_cnt, (const double *)nullptr, B.eps, B.mcount + 2,
+                       B.flags);
+  else
+    hipLaunchKernelGGL(k_eps_cg, dim3(1), dim3(kRedThreads), 0, L.st, B.mcount,
+                       (const int *)B.ell_col, (const double *)B.ell_val, (const int *)B.ell_cnt,
+                       B.eps, B.ev[0], B.ev[1], B.ev[2], B.flags);
   hipLaunchKernelGGL(k_eps_save, dim3(nblk(nc, 256)), dim3(256), 0, L.st, (const int *)B.mcount,
                      (const int *)B.ids, (const double *)B.eps, B.ceps);
+}
+
+bool shape_supported(int nc) { return nc <= 4 * kRedThreads; }
+
+void run_shape_clear(const Launch &L, const Bufs &B, int nc) {
+  hipLaunchKernelGGL(k_shape_clear, dim3(nblk(27 * (int64_t)nc, 256)), dim3(256), 0, L.st, nc,
+                     B.wbar, B.epsbar);
+}
+
+void run_shape_gradient(const Launch &L, const Bufs &B, int nc, double *X_bar) {
+  const int nslot = (L.g.dim == 3) ? 27 : 9;
+  // lambda = A^{-1} epsbar, from zero
+  run_fill(L, B.lam_g, nc, 0.0);
+  const size_t psb = (size_t)nc * sizeof(double);
+  if (nc <= kRedThreads)
+    hipLaunchKernelGGL(k_eps_cg_regs<1>, dim3(1), dim3(kRedThreads), psb, L.st,
+                       (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
+                       (const int *)B.ell_cnt, (const double *)B.epsbar, B.lam_g, B.mcount + 3,
+                       B.flags);
+  else
+    hipLaunchKernelGGL(k_eps_cg_regs<4>, dim3(1), dim3(kRedThreads), psb, L.st,
+                       (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
+                       (const int *)B.ell_cnt, (const double *)B.epsbar, B.lam_g, B.mcount + 3,
+                       B.flags);
+  hipLaunchKernelGGL(k_shape_cellsums, dim3(nblk((int64_t)nc * nslot, 256)), dim3(256), 0, L.st,
+                     (const int *)B.mcount, (const int *)B.seg, (const uint64_t *)B.keys,
+                     (const double *)B.pw, nslot, (const double *)B.eps,
+                     (const double *)B.lam_g, B.gsum);
+  hipLaunchKernelGGL(k_shape_grad, dim3(nblk(nc, 128)), dim3(128), 0, L.st, L.g,
+                     (const int *)B.mcount, (const double *)B.X, (const int *)B.ids,
+                     (const double *)B.eps, (const double *)B.lam_g, (const double *)B.gsum,
+                     B.wbar, B.epsbar, X_bar);
 }
 
 // Launches kernel template K<DIM, S> for the context's dimension and precision.

@@ -85,6 +85,11 @@ def fibonacci_sphere(ns: int, diameter: float = 1.0):
 
 
 # ----------------------------------------------------------------- workloads
+# Shedding Strouhal number of a fixed circular cylinder at Re 100 (the paper takes
+# f_0 from a preliminary fixed-cylinder run and does not print it; 0.16-0.17 is the
+# established value at this Reynolds number)
+STROUHAL_RE100 = 0.165
+
 def _bc_channel(dim):
     bc = [[INFLOW, OUTFLOW], [SLIP, SLIP]]
     if dim == 3:
@@ -103,6 +108,11 @@ def case(name: str, **over):
     cfg4  2D cylinder oscillating transversely, y = 0.2 sin(2 pi 0.2 t), 512^2 over
           [-4,12]x[-8,8], 200 markers, Re 100, Ma 0.2, Tw 1.2
     cfg5  2D heated cylinder for gradients, 512^2 as cfg4, 200 markers, Tw 1.3
+    osc1, osc2
+          2D cylinder oscillating in the streamwise direction (Sec. 5):
+          x = 0.14 D sin(2 pi f_c t) with f_c = 2 f_0, f_0 = St U / D the fixed
+          cylinder's shedding frequency (St = 0.165 at Re 100), 512^2 as cfg4,
+          200 markers, Re 100, Ma 0.3, Tw / Tinf = 1 (osc1) or 2 (osc2)
     """
     base = dict(Pr=0.71, gamma=1.4, sutherland_S=SUTHERLAND_AIR, U_inf=(1.0, 0.0, 0.0),
                 convection=CONV_VANLEER, viscosity_law=MU_SUTHERLAND, cfl=0.5, dt=0.0,
@@ -121,6 +131,12 @@ def case(name: str, **over):
         c = dict(dim=2, n=(512, 512), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=100.0, Ma=0.2,
                  Tw=1.2, ns=200, seed=4, steps=4000,
                  motion=dict(axis=1, amp=amp, freq=freq),
+                 dt_u_max=2.0 * math.pi * freq * amp)
+    elif name in ("osc1", "osc2"):
+        amp, freq = 0.14, 2.0 * STROUHAL_RE100
+        c = dict(dim=2, n=(512, 512), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=100.0, Ma=0.3,
+                 Tw=1.0 if name == "osc1" else 2.0, ns=200, seed=6, steps=4000,
+                 motion=dict(axis=0, amp=amp, freq=freq),
                  dt_u_max=2.0 * math.pi * freq * amp)
     elif name == "cfg5":
         c = dict(dim=2, n=(512, 512), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=100.0, Ma=0.2,

@@ -223,6 +223,13 @@ class IBMSolver:
                                        _ptr(state_bar_out), ob, _ptr(Tw_bar))
         L.check(st, self.ctx, "ibm_adjoint_step")
 
+    def shape_gradient(self, X_bar=None):
+        """Adds dJ/dX of the candidate marker positions, accumulated by the adjoint
+        steps since the last call, to ``X_bar`` (device float64 [n candidates, dim])
+        and clears the accumulation; ``None`` only clears it."""
+        st = self.lib.ibm_shape_gradient(self.ctx, None if X_bar is None else _ptr(X_bar))
+        L.check(st, self.ctx, "ibm_shape_gradient")
+
     def profile(self, enable: bool):
         L.check(self.lib.ibm_profile(self.ctx, 1 if enable else 0), self.ctx, "ibm_profile")
 

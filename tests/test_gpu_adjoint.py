@@ -16,7 +16,7 @@ import torch
 
 from paper_2301_09349_amd import inputs
 from paper_2301_09349_amd.adjoint import IBMRollout, drag_scale, nusselt_scale, \
-    wall_temperature_gradient, _state_vector, _set_state_vector
+    marker_position_gradient, wall_temperature_gradient, _state_vector, _set_state_vector
 from helpers import make_gpu, make_oracle, rel_l2, to_np
 
 pytestmark = pytest.mark.gpu
@@ -401,6 +401,107 @@ def test_cfg5_nusselt_gradient_full_size(cuda, conv):
     ad = float(to_np(Twb) @ d)
     print(f"  oracle tangent-linear over {m} steps: rel {abs(ad - tl) / abs(tl):.1e}")
     assert abs(ad - tl) <= 1e-10 * abs(tl), (ad, tl)
+
+
+def _turned_ring(c, angle=0.1):
+    # the workload's ring turned by `angle`: no candidate on a grid line and no two
+    # mirror images across a symmetry line of a cell (exact ties of the check
+    # routine), so that the markers in use and their supports are locally fixed
+    X, Ud, Tw, dA = inputs.markers(c)
+    cs, sn = np.cos(angle), np.sin(angle)
+    if X.shape[1] == 2:
+        X = np.stack([cs * X[:, 0] - sn * X[:, 1], sn * X[:, 0] + cs * X[:, 1]], axis=1)
+    else:
+        X = np.stack([cs * X[:, 0] - sn * X[:, 1], sn * X[:, 0] + cs * X[:, 1], X[:, 2]], axis=1)
+    return X, Ud, Tw, dA
+
+
+@pytest.mark.parametrize("conv", [LIN, VL], ids=["linear", "vanleer"])
+def test_marker_position_gradient_matches_oracle(cuda, conv):
+    # dJ/dX of the candidate positions (kernel weights, quadrature weights, the
+    # adjoint Gram solve) against the oracle's tangent-linear run along dX
+    c = inputs.scaled("cfg5", (64, 64), ns=40, convection=conv)
+    X, Ud, Tw, dA = _turned_ring(c)
+    nsteps, ck = 8, 3
+    gen = np.random.default_rng(51)
+    ob = gen.standard_normal((nsteps, 4))
+    s = make_gpu(c, tape_steps=ck)
+    s.set_markers(X, Ud, Tw, dA, dedupe=True)
+    _, Twb, Xb = marker_position_gradient(s, nsteps, ob, checkpoint=ck)
+    Xb = to_np(Xb)
+    assert np.all(np.isfinite(Xb)) and np.abs(Xb).max() > 0.0
+    o = make_oracle(c)
+    o.set_markers(X, Ud, Tw, dA, dedupe=True)
+    for j in range(3):
+        dX = gen.standard_normal(X.shape)
+        _, hd = o.tangent_linear_shape(nsteps, dX)
+        tl = float(np.sum(ob * hd))
+        ad = float(np.sum(Xb * dX))
+        assert abs(ad - tl) <= 1e-8 * abs(tl), (j, ad, tl)
+    # candidates the check routine leaves out get no gradient
+    ids, _ = s.markers_in_use()
+    out = np.setdiff1d(np.arange(c["ns"]), to_np(ids).astype(int))
+    assert out.size > 0 and np.all(Xb[out] == 0.0)
+
+
+def test_marker_position_gradient_sphere_3d(cuda):
+    c = inputs.scaled("cfg3", (24, 20, 20), ns=150, convection=LIN, Re=50.0)
+    X, Ud, Tw, dA = _turned_ring(c, 0.07)
+    nsteps, ck = 4, 2
+    gen = np.random.default_rng(52)
+    ob = gen.standard_normal((nsteps, 4))
+    s = make_gpu(c, tape_steps=ck)
+    s.set_markers(X, Ud, Tw, dA, dedupe=True)
+    _, _, Xb = marker_position_gradient(s, nsteps, ob, checkpoint=ck)
+    Xb = to_np(Xb)
+    o = make_oracle(c)
+    o.set_markers(X, Ud, Tw, dA, dedupe=True)
+    dX = gen.standard_normal(X.shape)
+    _, hd = o.tangent_linear_shape(nsteps, dX)
+    tl = float(np.sum(ob * hd))
+    ad = float(np.sum(Xb * dX))
+    assert abs(ad - tl) <= 1e-8 * abs(tl), (ad, tl)
+
+
+def test_marker_position_gradient_fp32_form(cuda):
+    # FP32 trajectory, FP64 reverse: close to the FP64 gradient
+    c = inputs.scaled("cfg5", (64, 64), ns=40, convection=LIN)
+    X, Ud, Tw, dA = _turned_ring(c)
+    nsteps, ck = 8, 4
+    ob = np.random.default_rng(54).standard_normal((nsteps, 4))
+    g = {}
+    for prec in ("fp64", "fp32"):
+        s = make_gpu(c, precision=prec, tape_steps=ck)
+        s.set_markers(X, Ud, Tw, dA, dedupe=True)
+        _, _, Xb = marker_position_gradient(s, nsteps, ob, checkpoint=ck)
+        g[prec] = to_np(Xb)
+    assert rel_l2(g["fp32"], g["fp64"]) < 1e-4
+
+
+def test_marker_position_gradient_central_differences(cuda):
+    # against the GPU forward run with the positions moved by +-h dX
+    c = inputs.scaled("cfg5", (64, 64), ns=40, convection=LIN)
+    X, Ud, Tw, dA = _turned_ring(c)
+    nsteps, ck = 6, 3
+    gen = np.random.default_rng(53)
+    ob = gen.standard_normal((nsteps, 4))
+    s = make_gpu(c, tape_steps=ck)
+    x0 = _state_vector(s)
+    s.set_markers(X, Ud, Tw, dA, dedupe=True)
+    _, _, Xb = marker_position_gradient(s, nsteps, ob, checkpoint=ck)
+    Xb = to_np(Xb)
+    h = 1e-6
+    for j in range(2):
+        dX = gen.standard_normal(X.shape)
+        Js = []
+        for sgn in (1.0, -1.0):
+            s.set_markers(X + sgn * h * dX, Ud, Tw, dA, dedupe=True)
+            _set_state_vector(s, x0, 0)
+            hh, _ = s.step(nsteps)
+            Js.append(float(np.sum(ob * to_np(hh))))
+        fd = (Js[0] - Js[1]) / (2 * h)
+        ad = float(np.sum(Xb * dX))
+        assert abs(ad - fd) <= 1e-6 * abs(ad), (j, ad, fd)
 
 
 def test_adjoint_rejects_bad_calls(cuda):

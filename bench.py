@@ -49,9 +49,9 @@ def kernel_bytes(cls: str, dim: int, precision: str = "fp64") -> int:
         return s * ((2 * dim + 4) + (dim + 2) + dim + 2) + 8
     if cls == "setup":
         if precision == "fp64":
-            # one kernel: rho^n, m^, psi, F^ (state type), x, b, r0 and the CG
-            # start's w0 = A r0 (FP64)
-            return s * (2 * dim + 2) + 8 * 4
+            # rho^n, m^, psi, F^ (state type), x, b, r0 (FP64); then the CG start
+            # psi, r0 -> w0
+            return s * (2 * dim + 2) + 8 * 3 + s + 8 * 2
         # rho^n, m^, psi, F^, x, b and r32 (the FP32 inner start)
         return s * (2 * dim + 2) + 8 * 2 + 4
     if cls == "correct":

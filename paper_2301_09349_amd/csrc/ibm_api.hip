@@ -331,6 +331,7 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   B.pcell = C.take<int64_t>(27 * nc);
   B.pw = C.take<double>(27 * nc);
   B.keys = C.take<uint64_t>((size_t)npairs_pad);
+  B.keys_in = C.take<uint64_t>((size_t)npairs_pad);
   B.seg = C.take<int>(27 * nc + 1);
   B.ell_col = C.take<int>((size_t)ibmk::kMaxNbr * nc);
   B.ell_val = C.take<double>((size_t)ibmk::kMaxNbr * nc);
@@ -551,8 +552,6 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
     const size_t need = ibmk::predictor_lds_bytes(desc->dim, desc->precision);
     const char *env = std::getenv("IBM_PREDICTOR");
     ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
-    const char *fse = std::getenv("IBM_SETUP");
-    ctx->L.fused_setup = !(fse && std::strcmp(fse, "split") == 0);
     const char *cgs = std::getenv("IBM_CG_START");
     ctx->cg_order = !cgs ? 2 : std::strcmp(cgs, "plain") == 0 ? 0
                              : std::strcmp(cgs, "linear") == 0 ? 1 : 2;

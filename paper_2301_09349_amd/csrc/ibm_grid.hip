@@ -721,115 +721,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_setup2(GridK g, const S *rho_
   }
 }
 
-// b at one cell, with the arithmetic of k_setup2 (so that a value formed again for
-// a neighbour equals the one that cell writes).
-template <int DIM, typename S>
-__device__ __forceinline__ double setup_b(const GridK &g, const S *const *mh, const S *rho_n,
-                                          int i, int j, int k) {
-  const int ix[3] = {i, j, k};
-  double div = 0.0, aff = 0.0;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    int hi[3] = {i, j, k};
-    hi[d] += 1;
-    const S fl = face_from_cells<DIM, S>(g, mh, rho_n, d, i, j, k);
-    const S fh = face_from_cells<DIM, S>(g, mh, rho_n, d, hi[0], hi[1], hi[2]);
-    div += (double(fh) - double(fl)) * g.ih[d];
-    if (g.bc[d][0] != BC_PERIODIC) {
-      if (ix[d] == 0 && g.bc[d][0] == BC_OUTFLOW) aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
-      if (ix[d] == g.n[d] - 1 && g.bc[d][1] == BC_OUTFLOW)
-        aff += 2.0 * g.p_inf * g.ih[d] * g.ih[d];
-    }
-  }
-  return double(rho_n[cidx(g, i, j, k)]) - g.dt * div + g.dt * g.dt * aff;
-}
-
-// The homogeneous Laplacian of helm_lap with v given by cell coordinates.
-template <int DIM, typename VF>
-__device__ __forceinline__ double helm_lap_ijk(const GridK &g, VF v, int i, int j, int k,
-                                               double vc) {
-  double lap = 0.0;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const double ih = g.ih[d];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      int ix[3] = {i, j, k};
-      ix[d] += side ? 1 : -1;
-      const int n = g.n[d];
-      double gf;
-      if (ix[d] >= 0 && ix[d] < n) {
-        gf = (v(ix[0], ix[1], ix[2]) - vc) * ih;
-      } else if (g.bc[d][0] == BC_PERIODIC) {
-        ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
-        gf = (v(ix[0], ix[1], ix[2]) - vc) * ih;
-      } else {
-        gf = (g.bc[d][side] == BC_OUTFLOW) ? (-2.0 * vc) * ih : 0.0;
-      }
-      lap += gf * ih;
-    }
-  }
-  return lap;
-}
-
-// Set-up and CG start in one pass (FP64 form): as k_setup2, and w0 = A r0 with the
-// neighbours' r0 formed again from m^, rho^n, psi and x (b by setup_b, A x by
-// helm_at), so that no second sweep reads r0 back; per-block partials of b.b,
-// gamma_0 = r0.r0 and delta_0 = w0.r0 (the first CG iteration's inputs).
-template <int DIM, typename S>
-__global__ __launch_bounds__(kBlockThreads) void k_setup_start(
-    GridK g, const S *rho_n, const S *mh0, const S *mh1, const S *mh2, S *Fh0, S *Fh1, S *Fh2,
-    const S *psi, const double *x, double *b, double *r0, double *w0, double *partials,
-    CgScal *cs, int tag) {
-  __shared__ double lds[48];
-  const S *mh[3] = {mh0, mh1, mh2};
-  S *Fh[3] = {Fh0, Fh1, Fh2};
-  double sums[3] = {0.0, 0.0, 0.0};
-  int64_t t0, t1;
-  block_tiles(g, t0, t1);
-  auto xv = [&](int64_t q) { return x[q]; };
-  auto r0_at = [&](int ii, int jj, int kk) {
-    const int64_t m = cidx(g, ii, jj, kk);
-    return setup_b<DIM, S>(g, mh, rho_n, ii, jj, kk) - helm_at<DIM>(g, psi, xv, ii, jj, kk, m, x[m]);
-  };
-  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
-    int i, j, k;
-    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
-    const int64_t c = cidx(g, i, j, k);
-    const int ix[3] = {i, j, k};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      int hi[3] = {i, j, k};
-      hi[d] += 1;
-      Fh[d][fidx(g, d, i, j, k)] = face_from_cells<DIM, S>(g, mh, rho_n, d, i, j, k);
-      if (ix[d] == g.n[d] - 1)
-        Fh[d][fidx(g, d, hi[0], hi[1], hi[2])] =
-            face_from_cells<DIM, S>(g, mh, rho_n, d, hi[0], hi[1], hi[2]);
-    }
-    const double bc_ = setup_b<DIM, S>(g, mh, rho_n, i, j, k);
-    const double rc = bc_ - helm_at<DIM>(g, psi, xv, i, j, k, c, x[c]);
-    const double wc = double(psi[c]) * rc - g.dt * g.dt * helm_lap_ijk<DIM>(g, r0_at, i, j, k, rc);
-    b[c] = bc_;
-    r0[c] = rc;
-    w0[c] = wc;
-    sums[0] += bc_ * bc_;
-    sums[1] += rc * rc;
-    sums[2] += wc * rc;
-  }
-  block_sum_n<3>(sums, lds);
-  if (threadIdx.x == 0) {
-    partials[PART_BB * kMaxBlocks + blockIdx.x] = sums[0];
-    partials[PART_G * kMaxBlocks + blockIdx.x] = sums[1];
-    partials[PART_D * kMaxBlocks + blockIdx.x] = sums[2];
-    if (blockIdx.x == 0) {
-      cs->done = 0;
-      cs->iters = 0;
-      cs->step_tag = tag;
-      cs->xfinal = 0;
-    }
-  }
-}
-
 #ifndef IBM_CG_UNROLL
 #define IBM_CG_UNROLL 1
 #endif
@@ -1456,16 +1347,6 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
                          (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
                          (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
                          (const double *)B.x, B.b, B.rv32[0], B.partials, B.cg, tag);
-    return;
-  }
-  if (L.fused_setup) {
-    IBM_DISPATCH(L, {
-      hipLaunchKernelGGL((k_setup_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads),
-                         0, L.st, L.g, (const S *)B.rho[cur], (const S *)B.mhat[0],
-                         (const S *)B.mhat[1], (const S *)B.mhat[2], (S *)B.Fhat[0],
-                         (S *)B.Fhat[1], (S *)B.Fhat[2], (const S *)B.psi, (const double *)B.x,
-                         B.b, B.rv[0], B.wv[0], B.partials, B.cg, tag);
-    });
     return;
   }
   IBM_DISPATCH(L, {

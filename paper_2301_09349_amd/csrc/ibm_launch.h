@@ -43,6 +43,7 @@ struct Bufs {
   int64_t *pcell; // [ns][27] support cell of each slot
   double *pw;     // [ns][27] support weight of each slot
   uint64_t *keys; // sorted (cell << 20 | pair id), padded to a power of two
+  uint64_t *keys_in;  // the same keys before the sort
   int *seg;       // segment starts, [n_segments + 1]
   int *ell_col;   // [ns][kMaxNbr]
   double *ell_val;
@@ -80,7 +81,6 @@ struct Launch {
   GridK g;
   int prec;      // 0: FP64, 1: FP32
   int pred_lds;  // 1: LDS-tiled predictor, 0: per-cell predictor
-  int fused_setup;  // FP64 form: 1 set-up and CG start in one kernel, 0 two kernels
   int nc_cap;     // candidate capacity
   int npairs_pad; // power of two >= nc_cap * nslot
   hipStream_t st;

@@ -178,50 +178,48 @@ __global__ void k_support(GridK g, const int *mcount, const double *X, int nslot
       }
 }
 
-// Bitonic sort of the pair keys in one block (npad a power of two); the keys
-// are unique, so the order is fully determined. Up to 4096 keys are sorted in LDS.
-// A pass of stride s <= 64 has thread t compare i = 2t - (t mod s) with i + s: the
-// 64 threads of a wave then touch only the 128 keys [128 w', 128 w' + 128) of
-// their window w' = t / 64 (the same window in every such pass), so between two
-// such passes on LDS a wave needs no block barrier, only the order of its own
-// LDS operations.
-__global__ void k_sort(uint64_t *keys, int npad, const int *mcount, int nslot) {
-  extern __shared__ uint64_t sk[];
+// Bitonic sort of the pair keys in one block (npad a power of two), in place in
+// global memory after a copy from keys_in (padded with the largest key); the keys
+// are unique, so the order is fully determined. Used above kRankKeys keys.
+__global__ void k_sort(const uint64_t *keys_in, uint64_t *keys, int npad, const int *mcount,
+                       int nslot) {
   const int np = mcount[0] * nslot;
-  const bool in_lds = npad <= 4096;
-  for (int i = threadIdx.x; i < npad; i += blockDim.x) {
-    uint64_t v = (i < np) ? keys[i] : ~0ull;
-    if (in_lds)
-      sk[i] = v;
-    else
-      keys[i] = v;
-  }
+  for (int i = threadIdx.x; i < npad; i += blockDim.x) keys[i] = (i < np) ? keys_in[i] : ~0ull;
   __syncthreads();
-  uint64_t *K = in_lds ? sk : keys;
   for (unsigned size = 2; size <= (unsigned)npad; size <<= 1) {
     for (unsigned stride = size >> 1; stride > 0; stride >>= 1) {
       for (unsigned t = threadIdx.x; t < (unsigned)npad / 2; t += blockDim.x) {
         unsigned i = 2 * t - (t & (stride - 1));
         unsigned j = i + stride;
         bool asc = (i & size) == 0;
-        uint64_t a = K[i], b = K[j];
+        uint64_t a = keys[i], b = keys[j];
         if ((a > b) == asc) {
-          K[i] = b;
-          K[j] = a;
+          keys[i] = b;
+          keys[j] = a;
         }
       }
-      // a block barrier unless this pass and the next both stay within the windows
-      // (the copy out after the last pass reads every window)
-      const bool last = stride == 1 && size == (unsigned)npad;
-      const unsigned next = stride > 1 ? stride >> 1 : size;  // stride of the next pass
-      if (in_lds && !last && stride <= 64 && next <= 64)
-        __builtin_amdgcn_wave_barrier();
-      else
-        __syncthreads();
+      __syncthreads();
     }
   }
-  if (in_lds)
-    for (int i = threadIdx.x; i < npad; i += blockDim.x) keys[i] = sk[i];
+}
+
+// The same order by rank, for up to kRankKeys keys: every key's place is the
+// number of keys below it (the keys are distinct). Each block ranks 256 keys
+// against all of them, held in LDS; the grid covers the live keys.
+constexpr int kRankKeys = 4096;
+__global__ __launch_bounds__(256) void k_rank_sort(const uint64_t *keys_in, uint64_t *keys,
+                                                   const int *mcount, int nslot) {
+  extern __shared__ uint64_t sk[];
+  const int np = mcount[0] * nslot;
+  if ((int)blockIdx.x * 256 >= np) return;  // the whole block
+  for (int i = threadIdx.x; i < np; i += blockDim.x) sk[i] = keys_in[i];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  const uint64_t v = sk[i];
+  int rank = 0;
+  for (int j = 0; j < np; ++j) rank += sk[j] < v ? 1 : 0;
+  keys[rank] = v;
 }
 
 // Segments of equal cell in the sorted pairs: seg[s] = first pair of segment s.
@@ -376,34 +374,68 @@ __global__ void k_eps_cg(int *mcount, const int *col, const double *val, const i
   }
 }
 
-// The same solve with the vectors held by the block: each thread keeps x, r and
-// A p of its rows (i = threadIdx.x + j blockDim.x, j < R) in registers, and p is
-// shared through LDS for the products; the matrix is read from the ELL arrays.
-// Same restarts and tolerances as k_eps_cg (relative to |rhs|); for n <= R *
-// blockDim.x. rhs NULL: the right-hand side 1 (the quadrature weights); otherwise
-// A x = rhs (the adjoint of that solve). The iteration count goes to *it_out.
-template <int R>
+// Sums of NV doubles over the block, returned to every thread: a butterfly within
+// each wave (every lane ends with the same value: the additions pair the same
+// operands in every lane), one barrier, then every wave sums the per-wave partials
+// itself. The two halves of `lds` ([2][NV][16]) alternate between calls, so that
+// a call needs no second barrier: a wave writes a half again only after the next
+// call's barrier, which every wave reaches after reading it.
+template <int NV>
+__device__ __forceinline__ void block_allsum(double *v, double *lds, int &half) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+  double *bf = lds + half * NV * 16;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) bf[q * 16 + w] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double t = lane < nw ? bf[q * 16 + lane] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    v[q] = t;
+  }
+  half ^= 1;
+}
+
+// The same solve with the vectors held by the block, as the single-reduction CG
+// of Chronopoulos and Gear (s = A p carried as s = w + beta s, one reduction of
+// r.r and w.r per iteration): each thread keeps x, r, p, w, s of its rows (i =
+// threadIdx.x + j blockDim.x, j < R) in registers; r is shared through LDS for
+// the product w = A r; the first NR entries of each row of the ELL arrays are held
+// in registers too (the rest, if any, read each time). Same restarts from the true
+// residual and tolerances as k_eps_cg (relative to |rhs|); for n <= R * blockDim.x.
+// rhs NULL: the right-hand side 1 (the quadrature weights); otherwise A x = rhs
+// (the adjoint of that solve). The iteration count goes to *it_out.
+constexpr int kEpsRegNnz = 16;  // Gram entries per row held in registers (n <= 1024)
+template <int R, int NR>
 __global__ __launch_bounds__(kRedThreads) void k_eps_cg_regs(const int *mcount, const int *col,
                                                              const double *val, const int *cnt,
                                                              const double *rhs, double *xg,
                                                              int *it_out, int *flags) {
-  extern __shared__ double ps[];  // n values of p (or x for the true residual)
-  __shared__ double lds[32];
+  extern __shared__ double ps[];  // n values of the vector multiplied by A
+  __shared__ double lds[2 * 2 * 16];
+  int half = 0;
   const int n = mcount[0];
   if (n == 0) return;
   const int nt = blockDim.x;
-  double x[R], r[R], q[R], pr[R], bv[R];
-  double bb = 0.0;
+  double x[R], r[R], w[R], p[R], sv[R], bv[R];
+  double bb[1] = {0.0};
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     const int i = threadIdx.x + j * nt;
     x[j] = i < n ? xg[i] : 0.0;
     bv[j] = i < n ? (rhs ? rhs[i] : 1.0) : 0.0;
-    bb += bv[j] * bv[j];
-    r[j] = q[j] = pr[j] = 0.0;
+    bb[0] += bv[j] * bv[j];
+    r[j] = w[j] = p[j] = sv[j] = 0.0;
   }
-  bb = block_dot_all(bb, lds);
-  if (!(bb > 0.0)) {  // zero right-hand side: x = 0
+  block_allsum<1>(bb, lds, half);
+  if (!(bb[0] > 0.0)) {  // zero right-hand side: x = 0
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int i = threadIdx.x + j * nt;
@@ -412,80 +444,98 @@ __global__ __launch_bounds__(kRedThreads) void k_eps_cg_regs(const int *mcount, 
     if (threadIdx.x == 0) *it_out = 0;
     return;
   }
-  const double tol_true2 = 1e-26 * bb, tol_in2 = 1e-30 * bb;
-  auto matvec = [&]() {  // q = A ps over this thread's rows
+  const double tol_true2 = 1e-26 * bb[0], tol_in2 = 1e-30 * bb[0];
+  int mrow[R], creg[R][NR > 0 ? NR : 1];
+  double vreg[R][NR > 0 ? NR : 1];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = threadIdx.x + j * nt;
+    mrow[j] = i < n ? cnt[i] : 0;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+      const bool in = e < mrow[j];
+      creg[j][e] = in ? col[(int64_t)kMaxNbr * i + e] : 0;
+      vreg[j][e] = in ? val[(int64_t)kMaxNbr * i + e] : 0.0;
+    }
+  }
+  // out = A v for this thread's rows, in the ELL order (v is put in LDS first; the
+  // barrier after the writes also ends every read of the previous product, whose
+  // reduction barrier comes before)
+  auto product = [&](const double *v, double *out) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = threadIdx.x + j * nt;
+      if (i < n) ps[i] = v[j];
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int i = threadIdx.x + j * nt;
       double sacc = 0.0;
-      if (i < n) {
-        const int m = cnt[i];
-        const int *cr = col + (int64_t)kMaxNbr * i;
-        const double *vr = val + (int64_t)kMaxNbr * i;
-        for (int e = 0; e < m; ++e) sacc += vr[e] * ps[cr[e]];
-      }
-      q[j] = sacc;
+#pragma unroll
+      for (int e = 0; e < NR; ++e)
+        if (e < mrow[j]) sacc += vreg[j][e] * ps[creg[j][e]];
+      for (int e = NR; e < mrow[j]; ++e)
+        sacc += val[(int64_t)kMaxNbr * i + e] * ps[col[(int64_t)kMaxNbr * i + e]];
+      out[j] = sacc;
     }
   };
   int total_it = 0;
   bool ok = false;
   for (int restart = 0; restart < 7 && !ok; ++restart) {
+    product(x, w);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int i = threadIdx.x + j * nt;
-      if (i < n) ps[i] = x[j];
+      r[j] = i < n ? bv[j] - w[j] : 0.0;
     }
-    __syncthreads();
-    matvec();
-    double rr = 0.0;
+    __syncthreads();  // every read of x in LDS is done before r replaces it
+    product(r, w);
+    double gd[2] = {0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      const int i = threadIdx.x + j * nt;
-      r[j] = i < n ? bv[j] - q[j] : 0.0;
-      pr[j] = r[j];
-      rr += r[j] * r[j];
+      gd[0] += r[j] * r[j];
+      gd[1] += w[j] * r[j];
     }
-    rr = block_dot_all(rr, lds);  // its barriers also end the reads of x in ps
-    if (rr <= tol_true2) {
+    block_allsum<2>(gd, lds, half);
+    double gam = gd[0];
+    if (gam <= tol_true2) {
       ok = true;
       break;
     }
     if (restart == 6) break;
+    double alpha = gam / gd[1];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-      const int i = threadIdx.x + j * nt;
-      if (i < n) ps[i] = pr[j];
+      p[j] = r[j];
+      sv[j] = w[j];
     }
-    __syncthreads();
     const int maxit = 4 * n + 50;
     for (int it = 0; it < maxit; ++it) {
-      matvec();
-      double pq = 0.0;
-#pragma unroll
-      for (int j = 0; j < R; ++j) pq += pr[j] * q[j];
-      pq = block_dot_all(pq, lds);
-      const double alpha = rr / pq;
-      double rn = 0.0;
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        x[j] += alpha * pr[j];
-        r[j] -= alpha * q[j];
-        rn += r[j] * r[j];
+        x[j] += alpha * p[j];
+        r[j] -= alpha * sv[j];
       }
-      rn = block_dot_all(rn, lds);
+      product(r, w);
+      double g2[2] = {0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        g2[0] += r[j] * r[j];
+        g2[1] += w[j] * r[j];
+      }
+      block_allsum<2>(g2, lds, half);
       ++total_it;
-      if (rn <= tol_in2) break;
-      const double beta = rn / rr;
+      if (g2[0] <= tol_in2) break;
+      const double beta = g2[0] / gam;
+      alpha = g2[0] / (g2[1] - beta * g2[0] / alpha);
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        const int i = threadIdx.x + j * nt;
-        pr[j] = r[j] + beta * pr[j];
-        if (i < n) ps[i] = pr[j];
+        p[j] = r[j] + beta * p[j];
+        sv[j] = w[j] + beta * sv[j];
       }
-      rr = rn;
-      __syncthreads();
+      gam = g2[0];
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < R; ++j) {
@@ -815,14 +865,26 @@ void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, doubl
                      B.eps, B.mcount);
 }
 
+// Threads of the one-row-per-thread quadrature solve for nc candidates.
+static unsigned eps_threads(int nc) {
+  const int t = (nc + 63) / 64 * 64;
+  return (unsigned)(t < 64 ? 64 : t > kRedThreads ? kRedThreads : t);
+}
+
 void run_build_markers(const Launch &L, const Bufs &B, int nc) {
   const int nslot = (L.g.dim == 3) ? 27 : 9;
   hipLaunchKernelGGL(k_support, dim3(nblk(nc, 256)), dim3(256), 0, L.st, L.g,
                      (const int *)B.mcount, (const double *)B.X, nslot, B.sidx, B.sw1, B.pcell,
-                     B.pw, B.keys, B.flags);
-  size_t shm = (L.npairs_pad <= 4096) ? (size_t)L.npairs_pad * sizeof(uint64_t) : 0;
-  hipLaunchKernelGGL(k_sort, dim3(1), dim3(kRedThreads), shm, L.st, B.keys, L.npairs_pad,
-                     (const int *)B.mcount, nslot);
+                     B.pw, B.keys_in, B.flags);
+  if (L.npairs_pad <= kRankKeys) {
+    const size_t shm = (size_t)L.npairs_pad * sizeof(uint64_t);
+    hipLaunchKernelGGL(k_rank_sort, dim3(nblk(L.npairs_pad, 256)), dim3(256), shm, L.st,
+                       (const uint64_t *)B.keys_in, B.keys, (const int *)B.mcount, nslot);
+  } else {
+    hipLaunchKernelGGL(k_sort, dim3(1), dim3(kRedThreads), 0, L.st,
+                       (const uint64_t *)B.keys_in, B.keys, L.npairs_pad, (const int *)B.mcount,
+                       nslot);
+  }
   hipLaunchKernelGGL(k_segments, dim3(1), dim3(kRedThreads), 0, L.st, (const uint64_t *)B.keys,
                      nslot, B.mcount, B.seg);
   hipLaunchKernelGGL(k_gram, dim3((unsigned)nc), dim3(kGramThreads), 0, L.st, L.g,
@@ -830,13 +892,13 @@ void run_build_markers(const Launch &L, const Bufs &B, int nc) {
                      B.ell_col, B.ell_val, B.ell_cnt, B.flags);
   // the live count is on the device; the candidate count bounds it
   const size_t psb = (size_t)nc * sizeof(double);
-  if (nc <= kRedThreads)
-    hipLaunchKernelGGL(k_eps_cg_regs<1>, dim3(1), dim3(kRedThreads), psb, L.st,
-                       (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
-                       (const int *)B.ell_cnt, (const double *)nullptr, B.eps, B.mcount + 2,
-                       B.flags);
+  if (nc <= kRedThreads)  // one row per thread: as few waves as rows need (shorter barriers)
+    hipLaunchKernelGGL((k_eps_cg_regs<1, kEpsRegNnz>), dim3(1), dim3(eps_threads(nc)), psb,
+                       L.st, (const int *)B.mcount, (const int *)B.ell_col,
+                       (const double *)B.ell_val, (const int *)B.ell_cnt, (const double *)nullptr,
+                       B.eps, B.mcount + 2, B.flags);
   else if (nc <= 4 * kRedThreads)
-    hipLaunchKernelGGL(k_eps_cg_regs<4>, dim3(1), dim3(kRedThreads), psb, L.st,
+    hipLaunchKernelGGL((k_eps_cg_regs<4, 0>), dim3(1), dim3(kRedThreads), psb, L.st,
                        (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
                        (const int *)B.ell_cnt, (const double *)nullptr, B.eps, B.mcount + 2,
                        B.flags);
@@ -850,6 +912,7 @@ void run_build_markers(const Launch &L, const Bufs &B, int nc) {
 
 bool shape_supported(int nc) { return nc <= 4 * kRedThreads; }
 
+
 void run_shape_clear(const Launch &L, const Bufs &B, int nc) {
   hipLaunchKernelGGL(k_shape_clear, dim3(nblk(27 * (int64_t)nc, 256)), dim3(256), 0, L.st, nc,
                      B.wbar, B.epsbar);
@@ -861,12 +924,12 @@ void run_shape_gradient(const Launch &L, const Bufs &B, int nc, double *X_bar) {
   run_fill(L, B.lam_g, nc, 0.0);
   const size_t psb = (size_t)nc * sizeof(double);
   if (nc <= kRedThreads)
-    hipLaunchKernelGGL(k_eps_cg_regs<1>, dim3(1), dim3(kRedThreads), psb, L.st,
-                       (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
-                       (const int *)B.ell_cnt, (const double *)B.epsbar, B.lam_g, B.mcount + 3,
-                       B.flags);
+    hipLaunchKernelGGL((k_eps_cg_regs<1, kEpsRegNnz>), dim3(1), dim3(eps_threads(nc)), psb,
+                       L.st, (const int *)B.mcount, (const int *)B.ell_col,
+                       (const double *)B.ell_val, (const int *)B.ell_cnt,
+                       (const double *)B.epsbar, B.lam_g, B.mcount + 3, B.flags);
   else
-    hipLaunchKernelGGL(k_eps_cg_regs<4>, dim3(1), dim3(kRedThreads), psb, L.st,
+    hipLaunchKernelGGL((k_eps_cg_regs<4, 0>), dim3(1), dim3(kRedThreads), psb, L.st,
                        (const int *)B.mcount, (const int *)B.ell_col, (const double *)B.ell_val,
                        (const int *)B.ell_cnt, (const double *)B.epsbar, B.lam_g, B.mcount + 3,
                        B.flags);

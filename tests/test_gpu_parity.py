@@ -144,23 +144,6 @@ def test_cg_start_does_not_change_the_solution(cuda, monkeypatch, precision, tol
             assert rel_l2(to_np(a), to_np(b)) < tol, mode
 
 
-@pytest.mark.parametrize("shape", [(90, 70), (30, 24, 20)])
-def test_fused_setup_matches_split_setup(cuda, monkeypatch, shape):
-    # the set-up kernel that also forms w0 = A r0 (neighbours' r0 formed again with
-    # the same arithmetic) gives the same steps as set-up + CG start, bitwise
-    name = "cfg1" if len(shape) == 2 else "cfg3"
-    c = inputs.scaled(name, shape, ns=60 if len(shape) == 2 else 120)
-    g = {}
-    for mode in ("fused", "split"):
-        monkeypatch.setenv("IBM_SETUP", mode)
-        g[mode] = make_gpu(c)
-    monkeypatch.delenv("IBM_SETUP")
-    it = {k: s.step(8)[1]["cg_iters_total"] for k, s in g.items()}
-    assert it["fused"] == it["split"]
-    for a, b in zip(g["fused"].get_state()[:3], g["split"].get_state()[:3]):
-        assert torch.equal(a, b)
-
-
 def test_cg_start_history_is_reset_by_set_state(cuda):
     # after set_state the extrapolation history is gone: stepping from a state set
     # from outside matches a fresh context stepped from the same state, bitwise

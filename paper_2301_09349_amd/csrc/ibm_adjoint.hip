@@ -234,13 +234,46 @@ __global__ void k_adj_corr_cell(GridK g, StateV<S> st, SBar sb, SBarW so, const 
 }
 
 // ------------------------------------------------------ R2: adjoint pressure
-// Start of the solve A lambda = rhs from lambda = 0: r0 = rhs; partial b.b (the
-// CG's own start, w0 = A r0, follows).
+// Start of the solve A lambda = rhs from the lambda of the previous adjoint step
+// (the next step in time, whose solution is close), scaled by the c that minimises
+// |rhs - c A lambda| so that the start is never worse than lambda = 0 (a start of
+// another objective's scale would otherwise limit the attainable accuracy).
+// First pass: a = A lambda into r, partials of rhs.a and a.a.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kBlockThreads) void k_adj_cg_guess(GridK g, const S *psi,
+                                                           const double *rhs, const double *lam,
+                                                           double *r, double *partials) {
+  __shared__ double lds[32];
+  double sums[2] = {0.0, 0.0};
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const double a = helm_at<DIM>(g, psi, [&](int64_t q) { return lam[q]; }, i, j, k, c, lam[c]);
+    r[c] = a;
+    sums[0] += rhs[c] * a;
+    sums[1] += a * a;
+  }
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[PART_SA * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[PART_AA * kMaxBlocks + blockIdx.x] = sums[1];
+  }
+}
+
+// Second pass: lambda = c lambda, r0 = rhs - c a; partial b.b (the CG's own start,
+// w0 = A r0, follows).
 template <int DIM>
 __global__ __launch_bounds__(kBlockThreads) void k_adj_cg_init(GridK g, const double *rhs, double *r,
                                                           double *lam, double *partials,
                                                           CgScal *cs, int tag) {
   __shared__ double lds[32];
+  double sa[2];
+  sum_partials2(partials + PART_SA * kMaxBlocks, partials + PART_AA * kMaxBlocks, gridDim.x, lds,
+                sa);
+  const double cf = sa[1] > 0.0 ? sa[0] / sa[1] : 0.0;
   double s = 0.0;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
@@ -249,8 +282,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_adj_cg_init(GridK g, const do
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
     const double v = rhs[c];
-    r[c] = v;
-    lam[c] = 0.0;
+    r[c] = v - cf * r[c];
+    lam[c] *= cf;
     s += v * v;
   }
   s = block_sum(s, lds);
@@ -989,6 +1022,9 @@ void run_adj_correction(const Launch &L, const Bufs &B, int slot, const double *
 
 void run_adj_cg_init(const Launch &L, const Bufs &B, int tag) {
   ADJ_DISPATCH(L, {
+    hipLaunchKernelGGL((k_adj_cg_guess<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads),
+                       0, L.st, L.g, (const S *)B.psi, (const double *)B.rhs,
+                       (const double *)B.lam, B.rv[0], B.partials);
     hipLaunchKernelGGL((k_adj_cg_init<DIM>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
                        L.st, L.g, (const double *)B.rhs, B.rv[0], B.lam, B.partials, B.cg, tag);
   });

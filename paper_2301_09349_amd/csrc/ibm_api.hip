@@ -94,6 +94,7 @@ struct ibm_ctx {
   int motion_axis = -1;
   double motion_amp = 0.0, motion_freq = 0.0;
   int cg_hint = 8;
+  int adj_hint = 8;  // iterations of the last adjoint pressure solve
   int tape_cap = 0;
   int tape_len = 0;  // steps recorded by the last IBM_RECORD call
   // the other state slot holds the state of the step before the current one (the CG
@@ -496,7 +497,7 @@ ibm_status run_cg_to_end(ibm_ctx *ctx, const Bufs &Bc, int tag, int *iters) {
   // every such solve (the adjoint's) runs the FP64 CG, whatever the context's form
   const Launch &L = ctx->L;
   int launched = 0;
-  const int first = std::max(1, ctx->cg_hint + 1);
+  const int first = std::max(1, ctx->adj_hint + 1);
   for (int c = 0; c < first; ++c) ibmk::run_cg64_iteration(L, Bc, launched++);
   HIPCHECK(ctx, hipGetLastError());
   uint64_t w = 0;
@@ -509,6 +510,7 @@ ibm_status run_cg_to_end(ibm_ctx *ctx, const Bufs &Bc, int tag, int *iters) {
   }
   const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
   *iters = (int)((w >> 8) & 0xFFFFFF);
+  ctx->adj_hint = std::max(1, *iters);
   if (err) return fail(ctx, IBM_E_NONFINITE, "adjoint pressure solve stopped on an error flag");
   if (dstate != 1) return fail(ctx, IBM_E_NOT_CONVERGED, "adjoint pressure CG reached cg_maxit");
   return IBM_OK;
@@ -587,6 +589,8 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   if (e == hipSuccess) {
     ibmk::run_uniform_state(ctx->L, ctx->B, 0);
     if (ctx->B.wbar) ibmk::run_shape_clear(ctx->L, ctx->B, ctx->L.nc_cap);
+    // the adjoint pressure solve starts from the previous one's solution
+    if (ctx->B.lam) ibmk::run_fill(ctx->L, ctx->B.lam, ctx->L.g.N, 0.0);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->L.st);

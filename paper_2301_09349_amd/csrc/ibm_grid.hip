@@ -631,41 +631,6 @@ __global__ void k_flux_from_mom(GridK g, StateV<S> st, int d) {
 
 // --------------------------------------------------- Appendix A, step 3
 // (m^, psi and the CG start come from the predictor and the spread.)
-// Homogeneous pressure operator at one cell: psi v - dt^2 div(grad_f v), zero
-// normal gradient at inflow and slip faces, v = 0 beyond outflow faces.
-// The homogeneous Laplacian of v at (i, j, k), vc = v there.
-template <int DIM, typename VF>
-__device__ __forceinline__ double helm_lap(const GridK &g, VF v, int i, int j, int k, double vc) {
-  double lap = 0.0;
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const double ih = g.ih[d];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      int ix[3] = {i, j, k};
-      ix[d] += side ? 1 : -1;
-      const int n = g.n[d];
-      double gf;
-      if (ix[d] >= 0 && ix[d] < n) {
-        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
-      } else if (g.bc[d][0] == BC_PERIODIC) {
-        ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
-        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
-      } else {
-        gf = (g.bc[d][side] == BC_OUTFLOW) ? (-2.0 * vc) * ih : 0.0;
-      }
-      lap += gf * ih;
-    }
-  }
-  return lap;
-}
-
-template <int DIM, typename S, typename VF>
-__device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, int i, int j, int k,
-                                          int64_t c, double vc) {
-  return double(psi[c]) * vc - g.dt * g.dt * helm_lap<DIM>(g, v, i, j, k, vc);
-}
-
 // Pressure set-up from the predictor's m^, psi, x: predicted face flux
 // F^ = lin_f(m^) (boundary rules), b = rho^n - dt D(F^) + outflow terms,
 // r0 = b - A x; per-block FP64 partial sums of b.b.

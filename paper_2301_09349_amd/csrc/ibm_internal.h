@@ -93,8 +93,8 @@ enum { FLAG_NONFINITE = 0, FLAG_SUPPORT = 1, FLAG_EPS = 2, FLAG_GRAM = 3, FLAG_B
 // single-reduction CG of iteration i reads (r.r, w.r) from regions PART_G + (i & 1),
 // PART_D + (i & 1) and writes the other pair.
 enum {
-  PART_PQ = 0,
-  PART_RR = 1,
+  PART_SA = 0,  // adjoint solve's start: rhs.(A lambda) and (A lambda).(A lambda)
+  PART_AA = 1,
   PART_BB = 2,
   PART_MASS = 3,
   PART_G = 4,
@@ -216,6 +216,42 @@ __device__ __forceinline__ bool any_side(const Resolved &r) {
 #pragma unroll
   for (int d = 0; d < DIM; ++d) a = a || (r.side[d] >= 0);
   return a;
+}
+
+// ------------------------------------------- Appendix A, step 3 (operator)
+// Homogeneous pressure operator at one cell: psi v - dt^2 div(grad_f v), zero
+// normal gradient at inflow and slip faces, v = 0 beyond outflow faces.
+// The homogeneous Laplacian of v at (i, j, k), vc = v there.
+template <int DIM, typename VF>
+__device__ __forceinline__ double helm_lap(const GridK &g, VF v, int i, int j, int k, double vc) {
+  double lap = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double ih = g.ih[d];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int ix[3] = {i, j, k};
+      ix[d] += side ? 1 : -1;
+      const int n = g.n[d];
+      double gf;
+      if (ix[d] >= 0 && ix[d] < n) {
+        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+      } else if (g.bc[d][0] == BC_PERIODIC) {
+        ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
+        gf = (v(cidx(g, ix[0], ix[1], ix[2])) - vc) * ih;
+      } else {
+        gf = (g.bc[d][side] == BC_OUTFLOW) ? (-2.0 * vc) * ih : 0.0;
+      }
+      lap += gf * ih;
+    }
+  }
+  return lap;
+}
+
+template <int DIM, typename S, typename VF>
+__device__ __forceinline__ double helm_at(const GridK &g, const S *psi, VF v, int i, int j, int k,
+                                          int64_t c, double vc) {
+  return double(psi[c]) * vc - g.dt * g.dt * helm_lap<DIM>(g, v, i, j, k, vc);
 }
 
 // -------------------------------------------------------------- reductions

@@ -48,20 +48,16 @@ def kernel_bytes(cls: str, dim: int, precision: str = "fp64") -> int:
         # rho*, m*, E*, m^, psi, the kept E^{n-1} (state type) and x (FP64)
         return s * ((2 * dim + 4) + (dim + 2) + dim + 2) + 8
     if cls == "setup":
-        if precision == "fp64":
-            # rho^n, m^, psi, F^ (state type), x, b, r0 (FP64); then the CG start
-            # psi, r0 -> w0
-            return s * (2 * dim + 2) + 8 * 3 + s + 8 * 2
-        # rho^n, m^, psi, F^, x, b and r32 (the FP32 inner start)
-        return s * (2 * dim + 2) + 8 * 2 + 4
+        # rho^n, m^, psi, F^ (state type), x, b, r0 (FP64); then the CG start
+        # psi, r0 -> w0 (both forms run the FP64 CG)
+        return s * (2 * dim + 2) + 8 * 3 + s + 8 * 2
     if cls == "correct":
         # rho*, E*, m^, F^, rho^n, x -> F, m, rho, E
         return s * ((2 * dim + 3) + (2 * dim + 2)) + 8
     if cls == "cg":
-        # single-reduction CG: r, w, s_old, p, x (FP32 form: d), psi -> r', w', s, p, x
-        # (d), in FP64 or (FP32 form's inner iterations, which most launches are)
-        # FP32; refinement launches are counted as iterations
-        return s * (6 + 5)
+        # single-reduction CG: r, w, s_old, p, x, psi -> r', w', s, p, x; the vectors
+        # FP64 in both forms, psi in the state type
+        return 8 * 10 + s
     raise KeyError(cls)
 
 

@@ -280,6 +280,9 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   }
   B.b = C.take<double>(N);
   B.x = C.take<double>(N);
+  B.x2 = nullptr;
+  for (int s = 0; s < 2; ++s) B.rv32[s] = B.wv32[s] = B.sv32[s] = nullptr;
+  B.pv32 = B.d32 = nullptr;
   if (d.precision == IBM_FP32) {
     // FP32 form: x ping-pong for the refinement; inner CG vectors in FP32
     B.x2 = C.take<double>(N);
@@ -290,18 +293,15 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
     }
     B.pv32 = C.take<float>(N);
     B.d32 = C.take<float>(N);
-    B.pv = nullptr;
-    for (int s = 0; s < 2; ++s) B.rv[s] = B.wv[s] = B.sv[s] = nullptr;
-  } else {
+  }
+  {
+    // FP64 CG vectors (the FP32 form's default solve and every adjoint solve)
     B.pv = C.take<double>(N);
     for (int s = 0; s < 2; ++s) {
       B.rv[s] = C.take<double>(N);
       B.wv[s] = C.take<double>(N);
       B.sv[s] = C.take<double>(N);
     }
-    B.x2 = nullptr;
-    for (int s = 0; s < 2; ++s) B.rv32[s] = B.wv32[s] = B.sv32[s] = nullptr;
-    B.pv32 = B.d32 = nullptr;
   }
   B.partials = C.take<double>((size_t)ibmk::PART_REGIONS * ibmk::kMaxBlocks);
   B.cg = C.take<CgScal>(1);
@@ -355,15 +355,6 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
     B.tape_xoff = (((size_t)(dim + 2) * N + NFt) * w + 255) & ~size_t(255);
     B.tape_stride = (B.tape_xoff + N * sizeof(double) + 255) & ~size_t(255);
     B.tape = C.take<char>(B.tape_stride * (size_t)tape_steps);
-    if (d.precision == IBM_FP32) {
-      // the adjoint's pressure solves run the FP64 CG
-      B.pv = C.take<double>(N);
-      for (int s = 0; s < 2; ++s) {
-        B.rv[s] = C.take<double>(N);
-        B.wv[s] = C.take<double>(N);
-        B.sv[s] = C.take<double>(N);
-      }
-    }
     B.pprim = C.take<double>((size_t)(dim + 4) * Np);
     B.pbar = C.take<double>((size_t)(dim + 3) * Np);
     const int nfo = (d.convection == IBM_CONV_VANLEER) ? 5 * dim + 3 : 4 * dim + 2;
@@ -554,6 +545,10 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
     const size_t need = ibmk::predictor_lds_bytes(desc->dim, desc->precision);
     const char *env = std::getenv("IBM_PREDICTOR");
     ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
+    // FP32 form: the FP64 CG on the FP32 psi by default; IBM_FP32_SOLVE=refine
+    // selects iterative refinement around an FP32 inner CG
+    const char *fs = std::getenv("IBM_FP32_SOLVE");
+    ctx->L.refine32 = (fs && std::strcmp(fs, "refine") == 0) ? 1 : 0;
     const char *cgs = std::getenv("IBM_CG_START");
     ctx->cg_order = !cgs ? 2 : std::strcmp(cgs, "plain") == 0 ? 0
                              : std::strcmp(cgs, "linear") == 0 ? 1 : 2;

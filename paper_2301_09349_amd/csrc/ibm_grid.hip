@@ -1299,7 +1299,7 @@ void run_predictor(const Launch &L, const Bufs &B, int cur, int order, bool keep
 }
 
 void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
-  if (L.prec == 1) {
+  if (L.prec == 1 && L.refine32) {
     if (L.g.dim == 2)
       hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
                          L.g, (const float *)B.rho[cur], (const float *)B.mhat[0],
@@ -1325,7 +1325,7 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
 }
 
 void run_cg_start(const Launch &L, const Bufs &B) {
-  if (L.prec == 1) return;  // the FP32 form's first iteration kernel starts its solve
+  if (L.prec == 1 && L.refine32) return;  // the refinement's first kernel starts its solve
   run_cg64_start(L, B);
 }
 
@@ -1350,7 +1350,7 @@ static void run_mcg_iter(const Launch &L, const Bufs &B, int it) {
 
 void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
   if (part != 0) return;
-  if (L.prec == 1) {
+  if (L.prec == 1 && L.refine32) {
     if (L.g.dim == 2)
       run_mcg_iter<2>(L, B, it);
     else

@@ -81,6 +81,8 @@ struct Launch {
   GridK g;
   int prec;      // 0: FP64, 1: FP32
   int pred_lds;  // 1: LDS-tiled predictor, 0: per-cell predictor
+  int refine32;  // FP32 form: 1 pressure by iterative refinement with an FP32 inner CG,
+                 // 0 the FP64 CG on FP32 psi
   int nc_cap;     // candidate capacity
   int npairs_pad; // power of two >= nc_cap * nslot
   hipStream_t st;

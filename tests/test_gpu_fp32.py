@@ -1,6 +1,7 @@
 """The FP32 form: FP32 state, stencils and psi; FP64 markers, sums and pressure
-solution (iterative refinement around an FP32 inner CG). Its error against the
-FP64 oracle is measured per result and held to the stated bounds."""
+solve (the FP64 CG on the FP32 psi, or with IBM_FP32_SOLVE=refine iterative
+refinement around an FP32 inner CG). Its error against the FP64 oracle is
+measured per result and held to the stated bounds."""
 import numpy as np
 import pytest
 
@@ -17,9 +18,13 @@ def _primitives(rho, mom, E, cv):
     return rho, u, th
 
 
-def test_fp32_form_against_fp64_oracle(cuda):
+@pytest.mark.parametrize("solve", ["fp64_cg", "refine"])
+def test_fp32_form_against_fp64_oracle(cuda, monkeypatch, solve):
     c = inputs.case("cfg1")
+    if solve == "refine":
+        monkeypatch.setenv("IBM_FP32_SOLVE", "refine")
     g32 = make_gpu(c, precision="fp32")
+    monkeypatch.delenv("IBM_FP32_SOLVE", raising=False)
     o = make_oracle(c)
     h32, info = g32.step(100)
     ho = o.step(100)
@@ -36,7 +41,7 @@ def test_fp32_form_against_fp64_oracle(cuda):
     h32 = to_np(h32)
     e_fx = abs(h32[:, 0].mean() - ho[:, 0].mean()) / abs(ho[:, 0].mean())
     e_h = abs(h32[:, 3].mean() - ho[:, 3].mean()) / abs(ho[:, 3].mean())
-    print(f"fp32 vs fp64 after 100 steps: u {e_u:.2e}, theta-1 {e_t:.2e}, "
+    print(f"fp32 ({solve}) vs fp64 after 100 steps: u {e_u:.2e}, theta-1 {e_t:.2e}, "
           f"mean Fx {e_fx:.2e}, mean H {e_h:.2e}")
     assert e_u < 1e-4 and e_t < 1e-3
     assert e_fx < 1e-4 and e_h < 1e-4

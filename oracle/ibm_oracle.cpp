@@ -88,7 +88,7 @@ struct Desc {
   double dt, cfl, dt_theta_max, dt_u_max;
   double cg_rtol;
   int32_t cg_maxit;
-  int32_t pad_;
+  int32_t diffusion;  // 0: explicit; 1: compact viscous and conductive fluxes implicit
 };
 
 enum { PERIODIC = 0, INFLOW = 1, OUTFLOW = 2, SLIP = 3 };
@@ -149,6 +149,7 @@ struct Solver {
   int cg_iters = 0;
   double cg_res = 0.0;
   std::vector<T> rho_s, E_s, mom_s[3];  // predictor output (f = q = 0)
+  std::vector<T> mu_face[3];            // face viscosity of the predictor
   std::vector<T> E_ss, mom_ss[3];       // after the forcing is spread
   std::vector<T> psi, rhs, pres;        // pressure equation and its solution
 
@@ -214,6 +215,9 @@ struct Solver {
       sc += uref / h[a];
       sd += 1.0 / (h[a] * h[a]);
     }
+    // with implicit diffusion only convection limits the step (without any flow
+    // speed the explicit limit is kept)
+    if (D.diffusion == 1 && sc > 0.0) return D.cfl / sc;
     return D.cfl / (sc + 2.0 * alpha * sd);
   }
 
@@ -329,7 +333,8 @@ struct Solver {
   // Predictor with f = 0, q = 0: explicit finite-volume update of Eqs. (1)-(3)
   // in internal-energy form (rho e): convection with the stored face mass flux,
   // -grad p, div tau, -p div u, tau:grad u and div(lambda grad theta).
-  void predictor() {
+  int predictor() {
+    const bool implicit = D.diffusion == 1;
     std::vector<T> u[3], th(N), pr(N), es(N);
     for (int q = 0; q < dim; ++q) u[q].resize(N);
     for (long c = 0; c < N; ++c) {
@@ -343,6 +348,7 @@ struct Solver {
       for (int q = 0; q < dim; ++q) fm[d][q].assign(NF[d], T(0.0));
       fe[d].assign(NF[d], T(0.0));
       uf[d].assign(NF[d], T(0.0));
+      mu_face[d].assign(NF[d], T(0.0));
       for_faces(d, [&](long i, long j, long k) {
         long f = fidx(d, i, j, k);
         long P[3] = {i, j, k}, Q[3] = {i, j, k};
@@ -364,13 +370,16 @@ struct Solver {
           tg[t] = 0.5 * (grad_c(u[d], V_U0 + d, P, t) + grad_c(u[d], V_U0 + d, Q, t));
           divf += 0.5 * (grad_c(u[t], V_U0 + t, P, t) + grad_c(u[t], V_U0 + t, Q, t));
         }
+        mu_face[d][f] = muf;
         for (int q = 0; q < dim; ++q) {
           T tau = (q == d) ? muf * (2.0 * dn[d] - (2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+          // implicit diffusion: the compact part mu_f dn[q] is taken at the new time
+          if (implicit) tau = tau - muf * dn[q];
           T cu = face_value(u[q], V_U0 + q, d, P, Q, Ff);
           fm[d][q][f] = Ff * cu - tau;
         }
         T ce = face_value(es, V_E, d, P, Q, Ff);
-        fe[d][f] = Ff * ce - lamf * (thQ - thP) / h[d];
+        fe[d][f] = implicit ? Ff * ce : Ff * ce - lamf * (thQ - thP) / h[d];
       });
     }
     rho_s.assign(N, T(0.0));
@@ -404,6 +413,75 @@ struct Solver {
         mom_s[q][c] = mom[q][c] - dt * divM[q] - dt * grad_c(pr, V_P, p, q);
       E_s[c] = E[c] - dt * divE - dt * pr[c] * divU + dt * phi;
     });
+    if (!implicit) return 0;
+    // Backward Euler for the compact face-normal fluxes: per velocity component
+    // rho* u* - dt div(mu_f grad_n u*) = m*(explicit part), then
+    // rho* theta* - dt (gamma/Pr) div(mu_f grad_n theta*) = E*(explicit part)/c_v,
+    // i.e. lambda_f / c_v = gamma mu_f / Pr; m* = rho* u*, E* = c_v rho* theta*.
+    for (int q = 0; q < dim; ++q) {
+      std::vector<T> x = u[q];
+      int rc = diffusion_solve(V_U0 + q, 1.0, mom_s[q], x);
+      if (rc) return rc;
+      for (long c = 0; c < N; ++c) mom_s[q][c] = rho_s[c] * x[c];
+    }
+    std::vector<T> x = th, rhs(N);
+    for (long c = 0; c < N; ++c) rhs[c] = E_s[c] / cv;
+    int rc = diffusion_solve(V_TH, D.gamma / D.Pr, rhs, x);
+    if (rc) return rc;
+    for (long c = 0; c < N; ++c) E_s[c] = cv * rho_s[c] * x[c];
+    return 0;
+  }
+
+  // rho* v - dt kap div(mu_f grad_n v) at every cell, the neighbour across a
+  // boundary face being the ghost value of the variable's rule (affine in v).
+  void diffusion_apply(int var, double kap, const std::vector<T> &v, std::vector<T> &out) const {
+    out.assign(N, T(0.0));
+    for_cells([&](long i, long j, long k) {
+      long c = cidx(i, j, k);
+      T s = rho_s[c] * v[c];
+      for (int d = 0; d < dim; ++d) {
+        long lo[3] = {i, j, k}, hi[3] = {i, j, k};
+        lo[d] -= 1;
+        hi[d] += 1;
+        const T cl = mu_face[d][fidx(d, i, j, k)], ch = mu_face[d][fidx(d, hi[0], hi[1], hi[2])];
+        const double w = dt * kap / (h[d] * h[d]);
+        s += w * (cl * (v[c] - at3(v, var, lo)) + ch * (v[c] - at3(v, var, hi)));
+      }
+      out[c] = s;
+    });
+  }
+
+  // Solves the implicit diffusion system for one variable by conjugate gradients
+  // (the operator minus its value at v = 0 is symmetric positive definite), from x.
+  int diffusion_solve(int var, double kap, const std::vector<T> &rhs, std::vector<T> &x) {
+    std::vector<T> zero(N, T(0.0)), a0, q;
+    diffusion_apply(var, kap, zero, a0);  // the ghost rules' constant part
+    auto A = [&](const std::vector<T> &v, std::vector<T> &out) {
+      diffusion_apply(var, kap, v, out);
+      for (long c = 0; c < N; ++c) out[c] = out[c] - a0[c];
+    };
+    std::vector<T> b(N), r(N), p;
+    for (long c = 0; c < N; ++c) b[c] = rhs[c] - a0[c];
+    A(x, q);
+    for (long c = 0; c < N; ++c) r[c] = b[c] - q[c];
+    const double tol2 = D.cg_rtol * D.cg_rtol * val(dot(b, b));
+    T rr = dot(r, r);
+    if (val(rr) <= tol2) return 0;
+    p = r;
+    for (int it = 1; it <= D.cg_maxit; ++it) {
+      A(p, q);
+      T alpha = rr / dot(p, q);
+      for (long c = 0; c < N; ++c) {
+        x[c] += alpha * p[c];
+        r[c] -= alpha * q[c];
+      }
+      T rn = dot(r, r);
+      if (val(rn) <= tol2) return 0;
+      T beta = rn / rr;
+      for (long c = 0; c < N; ++c) p[c] = r[c] + beta * p[c];
+      rr = rn;
+    }
+    return 5;
   }
 
   // ------------------------------------------------------ markers, Sec. 2.2
@@ -762,7 +840,10 @@ struct Solver {
       int rc = refresh_markers(double(step + 1) * dt);
       if (rc) return rc;
     }
-    predictor();
+    {
+      int rc = predictor();
+      if (rc) return rc;
+    }
     if (ns > 0) {
       forcing();
     } else {
@@ -989,7 +1070,7 @@ void orc_get_marker_fields(void *p, double *out) {
 }
 
 // Building blocks exposed for the pinning tests.
-void orc_predictor_only(void *p) { static_cast<Handle *>(p)->s.predictor(); }
+int orc_predictor_only(void *p) { return static_cast<Handle *>(p)->s.predictor(); }
 void orc_helmholtz(void *p, const double *psi, const double *x, double *y) {
   Solver<double> &s = static_cast<Handle *>(p)->s;
   std::vector<double> ps(psi, psi + s.N), xx(x, x + s.N), yy;

@@ -44,7 +44,7 @@ class Desc(ctypes.Structure):
         ("dt_u_max", ctypes.c_double),
         ("cg_rtol", ctypes.c_double),
         ("cg_maxit", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("diffusion", ctypes.c_int32),
     ]
 
 
@@ -97,6 +97,7 @@ def lib():
         L.orc_step.argtypes = [P, ctypes.c_int, D]
         L.orc_get_intermediate.argtypes = [P, ctypes.c_int, D]
         L.orc_get_marker_fields.argtypes = [P, D]
+        L.orc_predictor_only.restype = ctypes.c_int
         L.orc_predictor_only.argtypes = [P]
         L.orc_helmholtz.argtypes = [P, D, D, D]
         L.orc_cg.restype = ctypes.c_int
@@ -251,7 +252,9 @@ class Oracle:
         return out.reshape(self.ns, w)
 
     def predictor_only(self):
-        lib().orc_predictor_only(self.h)
+        rc = lib().orc_predictor_only(self.h)
+        if rc:
+            raise RuntimeError(f"oracle: predictor failed ({rc})")
 
     def helmholtz(self, psi, x):
         psi = np.ascontiguousarray(psi, dtype=np.float64).ravel()
@@ -355,5 +358,5 @@ def make_desc(case) -> Desc:
     d.dt_u_max = float(case.get("dt_u_max", 0.0))
     d.cg_rtol = float(case.get("cg_rtol", 1e-13))
     d.cg_maxit = int(case.get("cg_maxit", 2000))
-    d.pad_ = 0
+    d.diffusion = int(case.get("diffusion", 0))
     return d

@@ -319,6 +319,28 @@ def run_moving(steps: int, warmup: int):
     return res
 
 
+def run_implicit(case, steps: int, warmup: int, explicit: dict):
+    """The main workload with the compact viscous and conductive fluxes implicit
+    (backward Euler; the step from convection alone): ms per step, the step, and
+    simulated time per wall-clock second against the explicit runs in `explicit`
+    ({precision: (dt, ms_per_step)})."""
+    res = {"steps": steps}
+    for prec, (dt_e, ms_e) in explicit.items():
+        r = run_forward(dict(case, diffusion=1), prec, steps, warmup)
+        dt_i = r["solver"].dt
+        ent = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+               "dt": dt_i, "dt_explicit": dt_e, "dt_ratio": round(dt_i / dt_e, 3),
+               "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
+               "sim_time_per_s": round(dt_i / (r["ms_per_step"] * 1e-3), 4),
+               "sim_time_per_s_explicit": round(dt_e / (ms_e * 1e-3), 4),
+               "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
+                                       for k, v in r["per_kernel"].items()}}
+        ent["sim_time_speedup"] = round(ent["sim_time_per_s"] / ent["sim_time_per_s_explicit"], 3)
+        res[prec] = ent
+        del r
+    return res
+
+
 def calibrate_copy():
     """A plain streaming kernel of known size for scaling the HBM counters: negation
     of CALIB_ELEMS float64 values (8 B read + 8 B written each), three launches."""
@@ -479,6 +501,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 sphere figures")
+    ap.add_argument("--no-implicit", action="store_true",
+                    help="skip the implicit-diffusion figures")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the oscillating-cylinder figures")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -549,7 +573,9 @@ def main():
         "ms_per_step_profiled": round(r["ms_per_step_profiled"], 4),
         "cg_iters_all_steps": r["cg_iters_all"],
     }
+    explicit = {main_p: (r["solver"].dt, r["ms_per_step"])}
     if ro is not None:
+        explicit[other] = (ro["solver"].dt, ro["ms_per_step"])
         r64, r32 = (r, ro) if main_p == "fp64" else (ro, r)
         out[other] = {"value": round(ro["value"], 2), "ms_per_step": round(ro["ms_per_step"], 4),
                       "cg_iters_per_step": round(ro["info"]["cg_iters_total"] / args.steps, 2),
@@ -560,6 +586,10 @@ def main():
         del ro
     del r
     torch.cuda.empty_cache()
+    if not args.no_implicit:
+        log("bench: implicit diffusion ...")
+        out["implicit_diffusion"] = run_implicit(case, args.steps, args.warmup, explicit)
+        torch.cuda.empty_cache()
     if not args.no_3d and args.workload != "cfg3":
         log("bench: 256^3 sphere ...")
         out["sphere256"] = run_sphere(30, 10)

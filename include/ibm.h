@@ -70,6 +70,13 @@ enum { IBM_FP64 = 0, IBM_FP32 = 1 };
 /* convected face values: van Leer limited (Sec. 2.2.2) or linear */
 enum { IBM_CONV_VANLEER = 0, IBM_CONV_LINEAR = 1 };
 enum { IBM_MU_SUTHERLAND = 0, IBM_MU_CONSTANT = 1 };
+/* viscous and conductive fluxes: explicit, or their compact face-normal parts
+ * (mu_f du/dn, lambda_f dtheta/dn) implicit by backward Euler: after the explicit
+ * predictor, rho* u* - dt div(mu_f grad_n u*) = m*(explicit) per component and
+ * rho* theta* - dt (gamma/Pr) div(mu_f grad_n theta*) = E*(explicit)/c_v are
+ * solved by conjugate gradients (to cg_rtol, from u^n and theta^n); the time step
+ * from cfl then follows convection alone. Not with the adjoint. */
+enum { IBM_DIFF_EXPLICIT = 0, IBM_DIFF_IMPLICIT = 1 };
 /* ibm_set_markers flags: apply the marker check routine of Sec. 3.1 (of the
  * markers that fall in one cell only the one nearest to its centre is used,
  * ties to the lower id), at set-up and after every motion update. */
@@ -85,13 +92,14 @@ typedef struct {
   int32_t precision;        /* IBM_FP64 or IBM_FP32                            */
   int32_t convection;       /* IBM_CONV_VANLEER or IBM_CONV_LINEAR             */
   int32_t viscosity_law;    /* IBM_MU_SUTHERLAND or IBM_MU_CONSTANT            */
-  int32_t reserved;         /* must be 0                                       */
+  int32_t diffusion;        /* IBM_DIFF_EXPLICIT or IBM_DIFF_IMPLICIT          */
   double Re, Ma, Pr, gamma; /* flow parameters                                 */
   double sutherland_S;      /* Sutherland temperature over T_inf               */
   double U_inf[3];          /* inflow velocity                                 */
   double dt;                /* > 0: time step; <= 0: computed from cfl         */
   double cfl;               /* fraction of the explicit convection+conduction  */
-                            /* limit used when dt <= 0                         */
+                            /* limit used when dt <= 0 (of convection alone   */
+                            /* with IBM_DIFF_IMPLICIT and a flow speed)        */
   double dt_theta_max;      /* largest temperature expected (for the limit)    */
   double dt_u_max;          /* largest body speed expected (for the limit)     */
   double cg_rtol;           /* pressure CG stops at |r| <= cg_rtol |b|         */
@@ -220,7 +228,8 @@ ibm_status ibm_get_field(const ibm_ctx *ctx, int32_t which, void *dst);
  * upwind choice are differentiated where they are smooth: the branch the forward
  * took (by the sign of the face mass flux, and whether the limiter is active)
  * is kept, which is the derivative almost everywhere. Requirements: markers at
- * rest (IBM_E_ARG otherwise); IBM_E_STATE if tape_index is not a recorded step.
+ * rest and explicit diffusion (IBM_E_ARG otherwise); IBM_E_STATE if tape_index is
+ * not a recorded step.
  * In the FP32 form the forward pieces are recomputed in FP32 from the FP32 record
  * and the reverse runs in FP64 (cotangents, transposed stencils, adjoint CG): the
  * gradient along the FP32 trajectory.
@@ -268,11 +277,13 @@ ibm_status ibm_shape_gradient(ibm_ctx *ctx, double *X_bar);
  * pressure set-up (with the CG's start), 3 CG iterations (one event pair around
  * each batch of back-to-back iterations; the launch count is the number of
  * iterations that did work, so total / count is the time per iteration, with the
- * launch that detects convergence included in the total), 4 unused, 5 correction.
+ * launch that detects convergence included in the total), 4 implicit diffusion
+ * (face viscosities and the dim + 1 solves, host waits between them included),
+ * 5 correction.
  * The events themselves slow a step down; time throughput with timing off.
  * enable != 0 clears the totals and starts timing; 0 stops it. */
 enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG = 3,
-       IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };
+       IBM_PROF_DIFFUSION = 4, IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };
 ibm_status ibm_profile(ibm_ctx *ctx, int32_t enable);
 
 /* Per-class totals since timing was enabled: ms [IBM_PROF_CLASSES] (host) summed

@@ -17,6 +17,7 @@ IBM_PERIODIC, IBM_INFLOW, IBM_OUTFLOW, IBM_SLIP = 0, 1, 2, 3
 IBM_FP64, IBM_FP32 = 0, 1
 IBM_CONV_VANLEER, IBM_CONV_LINEAR = 0, 1
 IBM_MU_SUTHERLAND, IBM_MU_CONSTANT = 0, 1
+IBM_DIFF_EXPLICIT, IBM_DIFF_IMPLICIT = 0, 1
 IBM_DEDUPE = 1
 IBM_RECORD = 1
 
@@ -35,7 +36,7 @@ class ibm_grid_desc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("convection", ctypes.c_int32),
         ("viscosity_law", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("diffusion", ctypes.c_int32),
         ("Re", ctypes.c_double),
         ("Ma", ctypes.c_double),
         ("Pr", ctypes.c_double),
@@ -91,7 +92,7 @@ SIGNATURES = {
     "ibm_profile_read": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
 }
 
-PROF_CLASSES = ["predictor", "markers", "setup", "cg", "unused", "correct"]
+PROF_CLASSES = ["predictor", "markers", "setup", "cg", "diffusion", "correct"]
 
 _lib = None
 

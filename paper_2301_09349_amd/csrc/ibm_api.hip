@@ -95,6 +95,7 @@ struct ibm_ctx {
   double motion_amp = 0.0, motion_freq = 0.0;
   int cg_hint = 8;
   int adj_hint = 8;  // iterations of the last adjoint pressure solve
+  int diff_hint[4] = {4, 4, 4, 4};  // iterations of the last implicit diffusion solves
   int tape_cap = 0;
   int tape_len = 0;  // steps recorded by the last IBM_RECORD call
   // the other state slot holds the state of the step before the current one (the CG
@@ -150,7 +151,8 @@ const char *check_desc(const ibm_grid_desc *d) {
     return "unknown convection scheme";
   if (d->viscosity_law != IBM_MU_SUTHERLAND && d->viscosity_law != IBM_MU_CONSTANT)
     return "unknown viscosity law";
-  if (d->reserved != 0) return "reserved must be 0";
+  if (d->diffusion != IBM_DIFF_EXPLICIT && d->diffusion != IBM_DIFF_IMPLICIT)
+    return "unknown diffusion treatment";
   if (!(d->Re > 0) || !(d->Ma > 0) || !(d->Pr > 0) || !(d->gamma > 1.0))
     return "Re, Ma, Pr must be > 0 and gamma > 1";
   if (!(d->sutherland_S >= 0)) return "sutherland_S must be >= 0";
@@ -218,8 +220,14 @@ GridK make_grid(const ibm_grid_desc &d) {
       sc += uref / g.h[a];
       sd += 1.0 / (g.h[a] * g.h[a]);
     }
-    g.dt = d.cfl / (sc + 2.0 * alpha * sd);
+    // with implicit diffusion only convection limits the step (without any flow
+    // speed the explicit limit is kept)
+    if (d.diffusion == IBM_DIFF_IMPLICIT && sc > 0.0)
+      g.dt = d.cfl / sc;
+    else
+      g.dt = d.cfl / (sc + 2.0 * alpha * sd);
   }
+  g.implicit_diff = d.diffusion == IBM_DIFF_IMPLICIT ? 1 : 0;
   if (d.dim == 2) {
     g.tiles[0] = (g.n[0] + 63) / 64;
     g.tiles[1] = (g.n[1] + 3) / 4;
@@ -303,6 +311,9 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
       B.sv[s] = C.take<double>(N);
     }
   }
+  for (int q = 0; q < 3; ++q)
+    B.muf[q] = (d.diffusion == IBM_DIFF_IMPLICIT && q < dim) ? C.take<double>((size_t)g.NF[q])
+                                                             : nullptr;
   B.partials = C.take<double>((size_t)ibmk::PART_REGIONS * ibmk::kMaxBlocks);
   B.cg = C.take<CgScal>(1);
   B.scal = C.take<double>(8);
@@ -504,6 +515,45 @@ ibm_status run_cg_to_end(ibm_ctx *ctx, const Bufs &Bc, int tag, int *iters) {
   ctx->adj_hint = std::max(1, *iters);
   if (err) return fail(ctx, IBM_E_NONFINITE, "adjoint pressure solve stopped on an error flag");
   if (dstate != 1) return fail(ctx, IBM_E_NOT_CONVERGED, "adjoint pressure CG reached cg_maxit");
+  return IBM_OK;
+}
+
+// Implicit diffusion of one step, after its predictor: the face viscosities, then
+// one CG solve per velocity component and one for the temperature, each waited
+// for (they share the CG vectors) before its solution goes into m*, m^, E*, psi.
+// Progress is posted under -(8 tag + v + 1), unique and apart from step tags.
+ibm_status diffusion_solves(ibm_ctx *ctx, int tag) {
+  const Launch &L = ctx->L;
+  const Bufs &B = ctx->B;
+  ibmk::run_diff_coef(L, B, ctx->cur);
+  const int nv = L.g.dim + 1;
+  for (int v = 0; v < nv; ++v) {
+    const int q = v < L.g.dim ? v : 3;
+    const int dtag = -(tag * 8 + v + 1);
+    ibmk::run_diff_start(L, B, ctx->cur, q, dtag);
+    int launched = 0;
+    const int first = std::max(1, ctx->diff_hint[v] + 1);
+    for (; launched < first; ++launched) ibmk::run_diff_iteration(L, B, q, launched);
+    HIPCHECK(ctx, hipGetLastError());
+    uint64_t w = 0;
+    for (;;) {
+      ibm_status r = wait_progress(ctx, dtag, launched - 1, &w);
+      if (r) return r;
+      if (w & 0xF) break;
+      for (int c = 0; c < 2; ++c) ibmk::run_diff_iteration(L, B, q, launched++);
+      HIPCHECK(ctx, hipGetLastError());
+    }
+    const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
+    ctx->diff_hint[v] = std::max(1, (int)((w >> 8) & 0xFFFFFF));
+    if (err) {
+      const ibm_status s = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG
+                         : (err & 8) ? IBM_E_SIZE : IBM_E_NOT_CONVERGED;
+      return fail(ctx, s, "implicit diffusion solve stopped on an error flag");
+    }
+    if (dstate != 1) return fail(ctx, IBM_E_NOT_CONVERGED, "implicit diffusion CG reached cg_maxit");
+    ibmk::run_diff_finish(L, B, q);
+  }
+  HIPCHECK(ctx, hipGetLastError());
   return IBM_OK;
 }
 
@@ -832,6 +882,16 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     timed(IBM_PROF_PREDICTOR, 0, [&] {
       ibmk::run_predictor(L, B, ctx->cur, order, ctx->cg_order >= 2);
     });
+    if (L.g.implicit_diff) {
+      ibm_status ds = IBM_OK;
+      timed(IBM_PROF_DIFFUSION, 0, [&] { ds = diffusion_solves(ctx, tag); });
+      if (ds) {
+        // E_hist may already hold this step's E^{n-1}
+        ctx->prev_valid = ctx->hist_valid = false;
+        rc = ds;
+        break;
+      }
+    }
     double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
     if (ctx->nc > 0) {
       timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
@@ -1057,6 +1117,8 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
                             double *state_bar_out, const double *out_bar, double *Tw_bar) {
   if (!ctx) return IBM_E_ARG;
   if (ctx->motion_axis >= 0) return fail(ctx, IBM_E_ARG, "adjoint_step: markers must be at rest");
+  if (ctx->L.g.implicit_diff)
+    return fail(ctx, IBM_E_ARG, "adjoint_step: implicit diffusion has no adjoint");
   if (!state_bar_in || !state_bar_out) return fail(ctx, IBM_E_ARG, "adjoint_step: NULL cotangent");
   if (state_bar_in == state_bar_out)
     return fail(ctx, IBM_E_ARG, "adjoint_step: state_bar_in and state_bar_out must differ");

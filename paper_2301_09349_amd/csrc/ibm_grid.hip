@@ -137,9 +137,11 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
     S tau = (q == d) ? muf * (S(2) * dn[d] - S(2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+    // implicit diffusion: the compact part mu_f dn[q] is taken at the new time
+    if (g.implicit_diff) tau = tau - muf * dn[q];
     fm[q] = F * cu[q] - tau;
   }
-  fe = F * ce - lamf * (thQ - thP) * ih;
+  fe = g.implicit_diff ? F * ce : F * ce - lamf * (thQ - thP) * ih;
 }
 
 
@@ -397,9 +399,11 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int z
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
     S tau = (q == d) ? muf * (S(2) * dn[d] - S(2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+    // implicit diffusion: the compact part mu_f dn[q] is taken at the new time
+    if (g.implicit_diff) tau = tau - muf * dn[q];
     fm[q] = F * cu[q] - tau;
   }
-  fe = F * ce - lamf * (thQ - thP) * ih;
+  fe = g.implicit_diff ? F * ce : F * ce - lamf * (thQ - thP) * ih;
 }
 
 template <int DIM, typename S>
@@ -764,6 +768,61 @@ __device__ __forceinline__ void cg_sweep(const GridK &g, double alpha, double be
   }
 }
 
+// The common start of a single-reduction CG iteration: every block forms gamma_it
+// = r.r and delta_it = w.r from the partials of the previous kernel and tests
+// convergence (|r| <= rtol |b|) or the end (iteration limit, an error flag, NaN);
+// block 0 records the scalars and posts (step tag, it, error flags, done) to
+// `progress`. Returns false when the solve has ended (nothing to update);
+// otherwise alpha and beta of the update.
+__device__ __forceinline__ bool cg_head(int it, const double *partials, CgScal *cs,
+                                        const int *flags, uint64_t *progress, double *lds,
+                                        int &done0, double &alpha, double &beta) {
+  // block 0 of this kernel may set `done` while other blocks start: one read per block
+  if (threadIdx.x == 0) done0 = cs->done;
+  __syncthreads();
+  if (done0) return false;
+  const int nb = gridDim.x;
+  const int par = it & 1;
+  double gd[2];
+  sum_partials2(partials + (PART_G + par) * kMaxBlocks, partials + (PART_D + par) * kMaxBlocks,
+                nb, lds, gd);
+  const double gam = gd[0], del = gd[1];
+  const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
+  const double tol2 = cs->tol2;
+  const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
+                  (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
+  const bool conv = gam <= tol2 * bb;
+  const bool out = !conv && (it >= cs->maxit || err != 0 || !(gam == gam));
+  beta = 0.0;
+  alpha = gam / del;
+  if (it > 0) {
+    beta = gam / cs->rr[(it - 1) & 1];
+    alpha = gam / (del - beta * gam / cs->alpha[(it - 1) & 1]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (it == 0) cs->bb = bb;
+    cs->rr[par] = gam;
+    cs->alpha[par] = alpha;
+    cs->res = bb > 0.0 ? sqrt(gam / bb) : 0.0;
+    cs->iters = it;
+    if (conv || out) cs->done = conv ? 1 : 2;
+    if (progress)
+      __hip_atomic_store(progress, pack_progress(cs->step_tag, it, err, conv ? 1 : out ? 2 : 0),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  return !(conv || out);
+}
+
+// The common end: per-block partials of r'.r' and w'.r' for the next iteration.
+__device__ __forceinline__ void cg_tail(int it, double *sums, double *partials, double *lds) {
+  const int par = it & 1;
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    partials[(PART_G + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[(PART_D + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[1];
+  }
+}
+
 // CG iteration `it` with one global reduction (the recurrences of Chronopoulos and
 // Gear: s = A p is carried as s = w + beta s_old, so r.r and w.r of the new
 // residual are reduced together). Every block forms gamma_it = r.r and delta_it =
@@ -784,51 +843,243 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
     double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
     double *__restrict__ x, double *partials, CgScal *cs, const int *flags, uint64_t *progress) {
   __shared__ double lds[32];
-  // block 0 of this kernel may set `done` while other blocks start: one read per block
   __shared__ int done0;
-  if (threadIdx.x == 0) done0 = cs->done;
-  __syncthreads();
-  if (done0) return;
+  double alpha, beta;
+  if (!cg_head(it, partials, cs, flags, progress, lds, done0, alpha, beta)) return;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  const int nb = gridDim.x;
-  const int par = it & 1;
-  double gd[2];
-  sum_partials2(partials + (PART_G + par) * kMaxBlocks, partials + (PART_D + par) * kMaxBlocks,
-                nb, lds, gd);
-  const double gam = gd[0], del = gd[1];
-  const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
-  const double tol2 = cs->tol2;
-  const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
-                  (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
-  const bool conv = gam <= tol2 * bb;
-  const bool out = !conv && (it >= cs->maxit || err != 0 || !(gam == gam));
-  double beta = 0.0, alpha = gam / del;
-  if (it > 0) {
-    beta = gam / cs->rr[(it - 1) & 1];
-    alpha = gam / (del - beta * gam / cs->alpha[(it - 1) & 1]);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (it == 0) cs->bb = bb;
-    cs->rr[par] = gam;
-    cs->alpha[par] = alpha;
-    cs->res = bb > 0.0 ? sqrt(gam / bb) : 0.0;
-    cs->iters = it;
-    if (conv || out) cs->done = conv ? 1 : 2;
-    if (progress)
-      __hip_atomic_store(progress, pack_progress(cs->step_tag, it, err, conv ? 1 : out ? 2 : 0),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  }
-  if (conv || out) return;
   double sums[2] = {0.0, 0.0};
   if (it == 0)
     cg_sweep<DIM, true>(g, alpha, beta, t0, t1, psi, r, w, sold, rn, wn, snew, p, x, sums);
   else
     cg_sweep<DIM, false>(g, alpha, beta, t0, t1, psi, r, w, sold, rn, wn, snew, p, x, sums);
+  cg_tail(it, sums, partials, lds);
+}
+
+// ------------------------- implicit diffusion (backward Euler), after the predictor
+// For each velocity component q (and q = 3: the temperature), with the
+// predictor's explicit part as right-hand side:
+//   rho* v - dt kap div(mu_f grad_n v) = rhs,  kap = 1 (velocity), gamma/Pr
+//   (temperature, the equation divided by c_v), mu_f the face viscosity of the
+//   state at step n; solved by the same single-reduction CG from v^n.
+// Ghost value of v beyond a boundary face: sigma v + cst (the variable's rule);
+// the constant goes to the right-hand side, the operator keeps sigma v.
+__device__ __forceinline__ void diff_rule(const GridK &g, int bc, int q, int d, double &sg,
+                                          double &cst) {
+  sg = 1.0;
+  cst = 0.0;
+  if (bc == BC_INFLOW) {
+    sg = -1.0;
+    cst = (q < 3) ? 2.0 * g.U_inf[q] : 2.0;
+  } else if (bc == BC_SLIP && q == d) {
+    sg = -1.0;
+  }
+}
+
+struct DiffOp {
+  const double *mf[3];  // face viscosity per direction (face arrays)
+  int q;                // variable: velocity component, or 3 for the temperature
+  double kap;           // 1 or gamma / Pr
+};
+
+// sum_d ih_d^2 sum_sides mu_f (v_c - v_nb) at (i, j, k), v(m) the value at cell m
+// and vc at the cell; beyond a boundary face v_nb = sigma vc.
+template <int DIM, typename VF>
+__device__ __forceinline__ double diff_lap(const GridK &g, const DiffOp &op, VF v, int i, int j,
+                                           int k, double vc) {
+  double acc = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double w = g.ih[d] * g.ih[d];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int ix[3] = {i, j, k};
+      int fx[3] = {i, j, k};
+      fx[d] += side;
+      ix[d] += side ? 1 : -1;
+      const double mfc = op.mf[d][fidx(g, d, fx[0], fx[1], fx[2])];
+      const int n = g.n[d];
+      double vn;
+      if (ix[d] >= 0 && ix[d] < n) {
+        vn = v(cidx(g, ix[0], ix[1], ix[2]));
+      } else if (g.bc[d][0] == BC_PERIODIC) {
+        ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
+        vn = v(cidx(g, ix[0], ix[1], ix[2]));
+      } else {
+        double sg, cst;
+        diff_rule(g, g.bc[d][side], op.q, d, sg, cst);
+        vn = sg * vc;
+      }
+      acc += w * mfc * (vc - vn);
+    }
+  }
+  return acc;
+}
+
+// The rule constants' part: sum over boundary faces of ih^2 mu_f cst.
+template <int DIM>
+__device__ __forceinline__ double diff_bnd(const GridK &g, const DiffOp &op, int i, int j, int k) {
+  double acc = 0.0;
+  const int ix[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    if (g.bc[d][0] == BC_PERIODIC) continue;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (side == 0 ? ix[d] != 0 : ix[d] != g.n[d] - 1) continue;
+      int fx[3] = {i, j, k};
+      fx[d] += side;
+      double sg, cst;
+      diff_rule(g, g.bc[d][side], op.q, d, sg, cst);
+      acc += g.ih[d] * g.ih[d] * op.mf[d][fidx(g, d, fx[0], fx[1], fx[2])] * cst;
+    }
+  }
+  return acc;
+}
+
+// Face viscosity of direction d from the state at step n (the predictor's mu_f).
+template <int DIM, typename S>
+__global__ void k_diff_coef(GridK g, int d, StateV<S> st, double *mf) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.NF[d]) return;
+  int Q[3] = {(int)(f % g.fn[d][0]), (int)((f / g.fn[d][0]) % g.fn[d][1]),
+              (int)(f / ((int64_t)g.fn[d][0] * g.fn[d][1]))};
+  int P[3] = {Q[0], Q[1], Q[2]};
+  P[d] -= 1;
+  S uP[3], uQ[3], thP, thQ;
+  load_u_th<DIM>(g, st, P[0], P[1], P[2], uP, thP);
+  load_u_th<DIM>(g, st, Q[0], Q[1], Q[2], uQ, thQ);
+  mf[f] = double(S(0.5) * (mu_of(g, thP) + mu_of(g, thQ)));
+}
+
+// v^n of the variable at a cell (velocity component or temperature), as the
+// predictor forms it.
+template <typename S>
+__device__ __forceinline__ double diff_start_value(const GridK &g, const StateV<S> &st, int q,
+                                                   int64_t c) {
+  const S inv = S(1) / st.rho[c];
+  return q < 3 ? double(st.mom[q][c] * inv) : double(st.E[c] * inv * S(g.inv_cv));
+}
+
+// Start of one solve: x = v^n, rhs = src scale + dt kap (rule constants), r0 = rhs -
+// A x; partial b.b; the CG scalars are reset for `tag`.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kBlockThreads) void k_diff_init(GridK g, DiffOp op, StateV<S> st,
+                                                        const S *rho_s, const S *src,
+                                                        double scale, double *x, double *r,
+                                                        double *partials, CgScal *cs, int tag) {
+  __shared__ double lds[32];
+  double bb = 0.0;
+  const double dk = g.dt * op.kap;
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const double rhs = double(src[c]) * scale + dk * diff_bnd<DIM>(g, op, i, j, k);
+    const double xc = diff_start_value(g, st, op.q, c);
+    auto vn = [&](int64_t m) { return diff_start_value(g, st, op.q, m); };
+    const double ax = double(rho_s[c]) * xc + dk * diff_lap<DIM>(g, op, vn, i, j, k, xc);
+    x[c] = xc;
+    r[c] = rhs - ax;
+    bb += rhs * rhs;
+  }
+  bb = block_sum(bb, lds);
+  if (threadIdx.x == 0) {
+    partials[PART_BB * kMaxBlocks + blockIdx.x] = bb;
+    if (blockIdx.x == 0) {
+      cs->done = 0;
+      cs->iters = 0;
+      cs->step_tag = tag;
+      cs->xfinal = 0;
+    }
+  }
+}
+
+// w0 = A r0 and the partials of gamma_0 = r0.r0, delta_0 = w0.r0.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kBlockThreads) void k_diff_start(GridK g, DiffOp op, const S *rho_s,
+                                                         const double *r0, double *w0,
+                                                         double *partials) {
+  __shared__ double lds[32];
+  double sums[2] = {0.0, 0.0};
+  const double dk = g.dt * op.kap;
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const double rc = r0[c];
+    const double wc = double(rho_s[c]) * rc +
+                      dk * diff_lap<DIM>(g, op, [&](int64_t m) { return r0[m]; }, i, j, k, rc);
+    w0[c] = wc;
+    sums[0] += rc * rc;
+    sums[1] += wc * rc;
+  }
   block_sum_n<2>(sums, lds);
   if (threadIdx.x == 0) {
-    partials[(PART_G + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[0];
-    partials[(PART_D + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[1];
+    partials[PART_G * kMaxBlocks + blockIdx.x] = sums[0];
+    partials[PART_D * kMaxBlocks + blockIdx.x] = sums[1];
+  }
+}
+
+// One iteration of the diffusion solve: k_cg_iter's recurrences with this operator.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kBlockThreads) void k_diff_iter(
+    GridK g, int it, DiffOp op, const S *__restrict__ rho_s, const double *__restrict__ r,
+    const double *__restrict__ w, const double *__restrict__ sold, double *__restrict__ rn,
+    double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
+    double *__restrict__ x, double *partials, CgScal *cs, const int *flags, uint64_t *progress) {
+  __shared__ double lds[32];
+  __shared__ int done0;
+  double alpha, beta;
+  if (!cg_head(it, partials, cs, flags, progress, lds, done0, alpha, beta)) return;
+  const bool first = it == 0;
+  const double dk = g.dt * op.kap;
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  double sums[2] = {0.0, 0.0};
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const double rc = r[c], wc = w[c];
+    const double pc = first ? rc : rc + beta * p[c];
+    const double sc = first ? wc : wc + beta * sold[c];
+    x[c] = x[c] + alpha * pc;
+    const double rnc = rc - alpha * sc;
+    auto rv = [&](int64_t m) {
+      return first ? r[m] - alpha * w[m] : r[m] - alpha * (w[m] + beta * sold[m]);
+    };
+    const double wnc = double(rho_s[c]) * rnc + dk * diff_lap<DIM>(g, op, rv, i, j, k, rnc);
+    p[c] = pc;
+    snew[c] = sc;
+    rn[c] = rnc;
+    wn[c] = wnc;
+    sums[0] += rnc * rnc;
+    sums[1] += wnc * rnc;
+  }
+  cg_tail(it, sums, partials, lds);
+}
+
+// The solved variable into the predictor's outputs: m*_q = rho* u*_q (m^ moves by
+// the same amount), or E* = c_v rho* theta* with psi = 1/(R theta*).
+template <typename S>
+__global__ void k_diff_finish(GridK g, int q, const double *x, const S *rho_s, S *ms, S *mh,
+                              S *E_s, S *psi) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  if (q < 3) {
+    const S mnew = S(double(rho_s[c]) * x[c]);
+    mh[c] = mh[c] + (mnew - ms[c]);
+    ms[c] = mnew;
+  } else {
+    const S Es = S(g.cv * double(rho_s[c]) * x[c]);
+    E_s[c] = Es;
+    const S theta = Es / (rho_s[c] * S(g.cv));
+    psi[c] = S(1) / (S(g.R) * theta);
   }
 }
 
@@ -1383,6 +1634,58 @@ void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {
                        (const S *)B.Fhat[1], (const S *)B.Fhat[2], (const double *)B.x,
                        (const double *)(B.x2 ? B.x2 : B.x), B.partials, B.flags,
                        (const CgScal *)B.cg, tag);
+  });
+}
+
+static DiffOp diff_op(const Launch &L, const Bufs &B, int q) {
+  DiffOp op;
+  for (int d = 0; d < 3; ++d) op.mf[d] = B.muf[d];
+  op.q = q;
+  op.kap = q < 3 ? 1.0 : L.g.cp_Pr * L.g.inv_cv;  // lambda_f / (c_v mu_f) = gamma / Pr
+  return op;
+}
+
+void run_diff_coef(const Launch &L, const Bufs &B, int cur) {
+  IBM_DISPATCH(L, {
+    for (int d = 0; d < DIM; ++d) {
+      const int64_t nb = (L.g.NF[d] + 255) / 256;
+      hipLaunchKernelGGL((k_diff_coef<DIM, S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g, d,
+                         state_of<S>(B, cur), B.muf[d]);
+    }
+  });
+}
+
+void run_diff_start(const Launch &L, const Bufs &B, int cur, int q, int tag) {
+  const DiffOp op = diff_op(L, B, q);
+  IBM_DISPATCH(L, {
+    const S *src = (const S *)(q < 3 ? B.mom_s[q] : B.E_s);
+    const double scale = q < 3 ? 1.0 : L.g.inv_cv;
+    hipLaunchKernelGGL((k_diff_init<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, op, state_of<S>(B, cur), (const S *)B.rho_s, src, scale, B.b,
+                       B.rv[0], B.partials, B.cg, tag);
+    hipLaunchKernelGGL((k_diff_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, op, (const S *)B.rho_s, (const double *)B.rv[0], B.wv[0],
+                       B.partials);
+  });
+}
+
+void run_diff_iteration(const Launch &L, const Bufs &B, int q, int it) {
+  const DiffOp op = diff_op(L, B, q);
+  IBM_DISPATCH(L, {
+    const int a = it & 1, b = a ^ 1;
+    hipLaunchKernelGGL((k_diff_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, it, op, (const S *)B.rho_s, (const double *)B.rv[a],
+                       (const double *)B.wv[a], (const double *)B.sv[a], B.rv[b], B.wv[b], B.sv[b],
+                       B.pv, B.b, B.partials, B.cg, (const int *)B.flags, B.progress);
+  });
+}
+
+void run_diff_finish(const Launch &L, const Bufs &B, int q) {
+  IBM_DISPATCH(L, {
+    const int64_t nb = (L.g.N + 255) / 256;
+    hipLaunchKernelGGL((k_diff_finish<S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g, q,
+                       (const double *)B.b, (const S *)B.rho_s, (S *)(q < 3 ? B.mom_s[q] : nullptr),
+                       (S *)(q < 3 ? B.mhat[q] : nullptr), (S *)B.E_s, (S *)B.psi);
   });
 }
 

@@ -45,6 +45,7 @@ struct GridK {
   double lo[3], h[3], ih[3];
   int bc[3][2];
   int conv, visc;
+  int implicit_diff;  // 1: compact viscous and conductive fluxes by backward Euler
   double dt, R, cv, inv_cv, cp, gm1, mu_inf, S, Pr, p_inf, dV;
   double cp_Pr;       // c_p / Pr: lambda = cp_Pr mu
   double U_inf[3];

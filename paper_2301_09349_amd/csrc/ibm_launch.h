@@ -75,6 +75,9 @@ struct Bufs {
   // fields at the pairs [nc][27][dim + 2]; per-pair cell sums [nc][27][2]; the
   // adjoint quadrature solve [nc]
   double *wbar, *epsbar, *pfld, *gsum, *lam_g;
+  // implicit diffusion: FP64 face viscosity per direction [NF[d]] (the solves use
+  // b as their solution and the FP64 CG vectors, both free before the set-up)
+  double *muf[3];
 };
 
 struct Launch {
@@ -116,6 +119,13 @@ void run_cg_iteration(const Launch &L, const Bufs &B, int it);
 int cg_parts(const Launch &L);
 void run_cg_half(const Launch &L, const Bufs &B, int it, int part);
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag);
+// implicit diffusion after the predictor: the face viscosities of state `cur`;
+// for variable q (velocity component, 3: temperature) the solve's start (progress
+// posted under `tag`), its iterations, and the solution into m*, m^ or E*, psi
+void run_diff_coef(const Launch &L, const Bufs &B, int cur);
+void run_diff_start(const Launch &L, const Bufs &B, int cur, int q, int tag);
+void run_diff_iteration(const Launch &L, const Bufs &B, int q, int it);
+void run_diff_finish(const Launch &L, const Bufs &B, int q);
 void run_mass(const Launch &L, const Bufs &B);
 int64_t cell_blocks(const GridK &g);
 

@@ -18,6 +18,7 @@ import numpy as np
 PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
 CONV_VANLEER, CONV_LINEAR = 0, 1
 MU_SUTHERLAND, MU_CONSTANT = 0, 1
+DIFF_EXPLICIT, DIFF_IMPLICIT = 0, 1
 
 SUTHERLAND_AIR = 110.4 / 288.15  # Sutherland temperature of air over T_inf = 288.15 K
 
@@ -116,7 +117,8 @@ def case(name: str, **over):
     """
     base = dict(Pr=0.71, gamma=1.4, sutherland_S=SUTHERLAND_AIR, U_inf=(1.0, 0.0, 0.0),
                 convection=CONV_VANLEER, viscosity_law=MU_SUTHERLAND, cfl=0.5, dt=0.0,
-                cg_rtol=1e-13, cg_maxit=2000, dt_u_max=0.0, motion=None, dedupe=True)
+                cg_rtol=1e-13, cg_maxit=2000, dt_u_max=0.0, motion=None, dedupe=True,
+                diffusion=DIFF_EXPLICIT)
     if name == "cfg1":
         c = dict(dim=2, n=(128, 128), lo=(-2.0, -4.0), hi=(6.0, 4.0), Re=40.0, Ma=0.1,
                  Tw=1.1, ns=100, seed=1, steps=200)

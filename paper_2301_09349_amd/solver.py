@@ -27,7 +27,7 @@ def make_desc(case, precision: str = "fp64", max_markers=None) -> L.ibm_grid_des
     d.precision = L.IBM_FP32 if precision == "fp32" else L.IBM_FP64
     d.convection = int(case.get("convection", L.IBM_CONV_VANLEER))
     d.viscosity_law = int(case.get("viscosity_law", L.IBM_MU_SUTHERLAND))
-    d.reserved = 0
+    d.diffusion = int(case.get("diffusion", 0))
     d.Re = float(case["Re"])
     d.Ma = float(case["Ma"])
     d.Pr = float(case.get("Pr", 0.71))

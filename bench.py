@@ -331,6 +331,7 @@ def run_implicit(case, steps: int, warmup: int, explicit: dict):
         ent = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
                "dt": dt_i, "dt_explicit": dt_e, "dt_ratio": round(dt_i / dt_e, 3),
                "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
+               "diffusion_iters_per_step": round(r["info"]["diff_iters_total"] / steps, 2),
                "sim_time_per_s": round(dt_i / (r["ms_per_step"] * 1e-3), 4),
                "sim_time_per_s_explicit": round(dt_e / (ms_e * 1e-3), 4),
                "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)

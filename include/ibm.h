@@ -116,6 +116,9 @@ typedef struct {
   double dt;              /* time step                                        */
   double time;            /* step * dt                                        */
   double mass;            /* sum of rho dV after the call (FP64 reduction)     */
+  int32_t diff_iters_total; /* implicit diffusion CG iterations (of the side-  */
+                            /* by-side solves) summed over the call            */
+  int32_t reserved;
 } ibm_step_info;
 
 /* Bytes of device workspace needed for a grid, a marker capacity and a tape

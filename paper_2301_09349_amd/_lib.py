@@ -63,6 +63,8 @@ class ibm_step_info(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("time", ctypes.c_double),
         ("mass", ctypes.c_double),
+        ("diff_iters_total", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

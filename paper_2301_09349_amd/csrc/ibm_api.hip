@@ -95,7 +95,11 @@ struct ibm_ctx {
   double motion_amp = 0.0, motion_freq = 0.0;
   int cg_hint = 8;
   int adj_hint = 8;  // iterations of the last adjoint pressure solve
-  int diff_hint[4] = {4, 4, 4, 4};  // iterations of the last implicit diffusion solves
+  int diff_hint = 8;  // iterations of the last implicit diffusion solves
+  int diff_ring = 0;  // solution ring slot of the next step's diffusion solves
+  // previous steps' diffusion solutions held in the ring (0..2); cleared with
+  // prev_valid
+  int diff_hist = 0;
   int tape_cap = 0;
   int tape_len = 0;  // steps recorded by the last IBM_RECORD call
   // the other state slot holds the state of the step before the current one (the CG
@@ -311,9 +315,24 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
       B.sv[s] = C.take<double>(N);
     }
   }
-  for (int q = 0; q < 3; ++q)
-    B.muf[q] = (d.diffusion == IBM_DIFF_IMPLICIT && q < dim) ? C.take<double>((size_t)g.NF[q])
-                                                             : nullptr;
+  {
+    const bool imp = d.diffusion == IBM_DIFF_IMPLICIT;
+    const int nv = dim + 1;
+    for (int q = 0; q < 3; ++q) B.muf[q] = (imp && q < dim) ? C.take<double>((size_t)g.NF[q]) : nullptr;
+    for (int v = 0; v < ibmk::kDiffVars; ++v) {
+      const bool on = imp && v < nv;
+      for (int r = 0; r < 3; ++r) B.dring[r][v] = on ? C.take<double>(N) : nullptr;
+      for (int s = 0; s < 2; ++s) {
+        B.dr[s][v] = on ? C.take<double>(N) : nullptr;
+        B.dw[s][v] = on ? C.take<double>(N) : nullptr;
+        B.ds[s][v] = on ? C.take<double>(N) : nullptr;
+      }
+      B.dp[v] = on ? C.take<double>(N) : nullptr;
+    }
+    B.dpart = imp ? C.take<double>((size_t)ibmk::kDiffVars * ibmk::DP_REGIONS * ibmk::kMaxBlocks)
+                  : nullptr;
+    B.dsc = imp ? C.take<ibmk::DiffScal>(1) : nullptr;
+  }
   B.partials = C.take<double>((size_t)ibmk::PART_REGIONS * ibmk::kMaxBlocks);
   B.cg = C.take<CgScal>(1);
   B.scal = C.take<double>(8);
@@ -519,41 +538,44 @@ ibm_status run_cg_to_end(ibm_ctx *ctx, const Bufs &Bc, int tag, int *iters) {
 }
 
 // Implicit diffusion of one step, after its predictor: the face viscosities, then
-// one CG solve per velocity component and one for the temperature, each waited
-// for (they share the CG vectors) before its solution goes into m*, m^, E*, psi.
-// Progress is posted under -(8 tag + v + 1), unique and apart from step tags.
-ibm_status diffusion_solves(ibm_ctx *ctx, int tag) {
+// the dim + 1 solves side by side (one kernel per iteration), started from the
+// linear extrapolation of the last two steps' solutions when both are held (and
+// IBM_CG_START is not plain), else from the state at step n. Progress is posted
+// under -(8 tag + 1), apart from step tags. Returns the iterations in *iters.
+ibm_status diffusion_solves(ibm_ctx *ctx, int tag, int *iters) {
   const Launch &L = ctx->L;
   const Bufs &B = ctx->B;
+  const int ring = ctx->diff_ring;
+  const int order = (ctx->cg_order >= 1 && ctx->diff_hist >= 2) ? 1 : 0;
+  const int dtag = -(tag * 8 + 1);
   ibmk::run_diff_coef(L, B, ctx->cur);
-  const int nv = L.g.dim + 1;
-  for (int v = 0; v < nv; ++v) {
-    const int q = v < L.g.dim ? v : 3;
-    const int dtag = -(tag * 8 + v + 1);
-    ibmk::run_diff_start(L, B, ctx->cur, q, dtag);
-    int launched = 0;
-    const int first = std::max(1, ctx->diff_hint[v] + 1);
-    for (; launched < first; ++launched) ibmk::run_diff_iteration(L, B, q, launched);
-    HIPCHECK(ctx, hipGetLastError());
-    uint64_t w = 0;
-    for (;;) {
-      ibm_status r = wait_progress(ctx, dtag, launched - 1, &w);
-      if (r) return r;
-      if (w & 0xF) break;
-      for (int c = 0; c < 2; ++c) ibmk::run_diff_iteration(L, B, q, launched++);
-      HIPCHECK(ctx, hipGetLastError());
-    }
-    const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
-    ctx->diff_hint[v] = std::max(1, (int)((w >> 8) & 0xFFFFFF));
-    if (err) {
-      const ibm_status s = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG
-                         : (err & 8) ? IBM_E_SIZE : IBM_E_NOT_CONVERGED;
-      return fail(ctx, s, "implicit diffusion solve stopped on an error flag");
-    }
-    if (dstate != 1) return fail(ctx, IBM_E_NOT_CONVERGED, "implicit diffusion CG reached cg_maxit");
-    ibmk::run_diff_finish(L, B, q);
-  }
+  ibmk::run_diff_start(L, B, ctx->cur, ring, order, dtag);
+  int launched = 0;
+  const int first = std::max(1, ctx->diff_hint + 1);
+  for (; launched < first; ++launched) ibmk::run_diff_iteration(L, B, ring, launched);
   HIPCHECK(ctx, hipGetLastError());
+  uint64_t w = 0;
+  for (;;) {
+    ibm_status r = wait_progress(ctx, dtag, launched - 1, &w);
+    if (r) return r;
+    if (w & 0xF) break;
+    for (int c = 0; c < 2; ++c) ibmk::run_diff_iteration(L, B, ring, launched++);
+    HIPCHECK(ctx, hipGetLastError());
+  }
+  const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
+  *iters = (int)((w >> 8) & 0xFFFFFF);
+  ctx->diff_hint = std::max(1, *iters);
+  if (err) {
+    const ibm_status s = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG
+                       : (err & 8) ? IBM_E_SIZE : IBM_E_NOT_CONVERGED;
+    return fail(ctx, s, "implicit diffusion solve stopped on an error flag");
+  }
+  if (dstate != 1) return fail(ctx, IBM_E_NOT_CONVERGED, "implicit diffusion CG reached cg_maxit");
+  ibmk::run_diff_finish(L, B, ring);
+  HIPCHECK(ctx, hipGetLastError());
+  // this step's solutions now head the ring
+  ctx->diff_ring = (ring + 1) % 3;
+  ctx->diff_hist = std::min(ctx->diff_hist + 1, 2);
   return IBM_OK;
 }
 
@@ -628,6 +650,13 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   c0.tol2 = desc->cg_rtol * desc->cg_rtol;
   c0.maxit = desc->cg_maxit;
   hipError_t e = hipMemcpyAsync(ctx->B.cg, &c0, sizeof(c0), hipMemcpyHostToDevice, ctx->L.st);
+  if (e == hipSuccess && ctx->B.dsc) {
+    ibmk::DiffScal d0;
+    std::memset(&d0, 0, sizeof(d0));
+    d0.tol2 = c0.tol2;
+    d0.maxit = c0.maxit;
+    e = hipMemcpyAsync(ctx->B.dsc, &d0, sizeof(d0), hipMemcpyHostToDevice, ctx->L.st);
+  }
   if (e == hipSuccess) e = hipMemsetAsync(ctx->B.flags, 0, 8 * sizeof(int), ctx->L.st);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->B.mcount, 0, 8 * sizeof(int), ctx->L.st);
   if (e == hipSuccess) e = hipMemsetAsync(ctx->B.totals, 0, 8 * sizeof(double), ctx->L.st);
@@ -664,6 +693,7 @@ ibm_status ibm_init_primitive(ibm_ctx *ctx, const void *rho, const void *u, cons
   HIPCHECK(ctx, hipGetLastError());
   ctx->step = 0;
   ctx->prev_valid = ctx->hist_valid = false;
+  ctx->diff_hist = 0;
   if (ctx->nc > 0 && ctx->motion_axis >= 0) {
     ibm_status s = rebuild_markers(ctx, 0.0);
     if (s) return s;
@@ -699,6 +729,7 @@ ibm_status ibm_set_state(ibm_ctx *ctx, const void *rho, const void *mom, const v
   }
   ctx->step = step;
   ctx->prev_valid = ctx->hist_valid = false;
+  ctx->diff_hist = 0;
   if (ctx->nc > 0 && ctx->motion_axis >= 0) {
     ibm_status s = rebuild_markers(ctx, double(step) * g.dt);
     if (s) return s;
@@ -838,7 +869,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   hipStream_t st = L.st;
   ibm_status rc = IBM_OK;
   int64_t done = 0;
-  int total_it = 0, last_it = 0;
+  int total_it = 0, last_it = 0, diff_it = 0;
   Prof &P = ctx->prof;
   auto timed = [&](int cls, int it, auto &&launch) {
     if (!P.on) {
@@ -884,10 +915,13 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     });
     if (L.g.implicit_diff) {
       ibm_status ds = IBM_OK;
-      timed(IBM_PROF_DIFFUSION, 0, [&] { ds = diffusion_solves(ctx, tag); });
+      int dit = 0;
+      timed(IBM_PROF_DIFFUSION, 0, [&] { ds = diffusion_solves(ctx, tag, &dit); });
+      diff_it += dit;
       if (ds) {
         // E_hist may already hold this step's E^{n-1}
         ctx->prev_valid = ctx->hist_valid = false;
+        ctx->diff_hist = 0;
         rc = ds;
         break;
       }
@@ -925,6 +959,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     if (P.on) P.count_cg(iters);
     if (err) {
       ctx->prev_valid = ctx->hist_valid = false;
+      ctx->diff_hist = 0;
       // this step's correction did not run; an earlier failure is sorted out below
       rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE
                                                                          : IBM_E_NOT_CONVERGED;
@@ -963,6 +998,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     if (s_bad >= 0 && s_bad <= n_steps) {
       ctx->cur = cur0 ^ (s_bad & 1);
       ctx->prev_valid = ctx->hist_valid = false;
+      ctx->diff_hist = 0;
       ctx->step = step0 + s_bad;
       done = s_bad;
     }
@@ -975,6 +1011,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     info->step = ctx->step;
     info->cg_iters_last = last_it;
     info->cg_iters_total = total_it;
+    info->diff_iters_total = diff_it;
     info->cg_residual = ctx->cgh.res;
     info->dt = L.g.dt;
     info->time = double(ctx->step) * L.g.dt;
@@ -1131,6 +1168,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
   hipStream_t st = L.st;
   const int slot = ctx->cur ^ 1;
   ctx->prev_valid = ctx->hist_valid = false;  // the other slot now holds the recorded state
+  ctx->diff_hist = 0;
   const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
   const double *ob = out_bar ? out_bar : zero4;
   // forward pieces of the step, recomputed from its record

@@ -857,13 +857,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
 }
 
 // ------------------------- implicit diffusion (backward Euler), after the predictor
-// For each velocity component q (and q = 3: the temperature), with the
-// predictor's explicit part as right-hand side:
-//   rho* v - dt kap div(mu_f grad_n v) = rhs,  kap = 1 (velocity), gamma/Pr
+// For each velocity component (variable v < dim) and the temperature (v = dim),
+// with the predictor's explicit part as right-hand side:
+//   rho* y - dt kap div(mu_f grad_n y) = rhs,  kap = 1 (velocity), gamma/Pr
 //   (temperature, the equation divided by c_v), mu_f the face viscosity of the
-//   state at step n; solved by the same single-reduction CG from v^n.
-// Ghost value of v beyond a boundary face: sigma v + cst (the variable's rule);
-// the constant goes to the right-hand side, the operator keeps sigma v.
+//   state at step n.
+// The dim + 1 systems share rho* and mu_f and are solved together: one kernel per
+// iteration runs the single-reduction CG step of every variable still iterating
+// (each with its own step lengths and its own test |r_v| <= rtol |b_v|), so that
+// the shared coefficients are loaded once and the partial sums of all variables
+// are formed in one pass.
+// Ghost value of y beyond a boundary face: sigma y + cst (the variable's rule);
+// the constant goes to the right-hand side, the operator keeps sigma y.
 __device__ __forceinline__ void diff_rule(const GridK &g, int bc, int q, int d, double &sg,
                                           double &cst) {
   sg = 1.0;
@@ -876,65 +881,78 @@ __device__ __forceinline__ void diff_rule(const GridK &g, int bc, int q, int d, 
   }
 }
 
-struct DiffOp {
-  const double *mf[3];  // face viscosity per direction (face arrays)
-  int q;                // variable: velocity component, or 3 for the temperature
-  double kap;           // 1 or gamma / Pr
+// The 2 dim faces of a cell: dt ih^2 mu_f, and the neighbour across (its index,
+// or -1 beyond a non-periodic boundary, with that side's boundary type). Face e
+// is direction e / 2, low side for even e.
+template <int DIM>
+struct DiffNbr {
+  int64_t m[2 * DIM];
+  double cf[2 * DIM];
+  int bc[2 * DIM];
 };
 
-// sum_d ih_d^2 sum_sides mu_f (v_c - v_nb) at (i, j, k), v(m) the value at cell m
-// and vc at the cell; beyond a boundary face v_nb = sigma vc.
-template <int DIM, typename VF>
-__device__ __forceinline__ double diff_lap(const GridK &g, const DiffOp &op, VF v, int i, int j,
-                                           int k, double vc) {
-  double acc = 0.0;
+template <int DIM>
+__device__ __forceinline__ void diff_nbr(const GridK &g, const double *const *mf, int i, int j,
+                                         int k, DiffNbr<DIM> &nb) {
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    const double w = g.ih[d] * g.ih[d];
+    const double w = g.dt * g.ih[d] * g.ih[d];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
+      const int e = 2 * d + side;
       int ix[3] = {i, j, k};
       int fx[3] = {i, j, k};
       fx[d] += side;
       ix[d] += side ? 1 : -1;
-      const double mfc = op.mf[d][fidx(g, d, fx[0], fx[1], fx[2])];
+      nb.cf[e] = w * mf[d][fidx(g, d, fx[0], fx[1], fx[2])];
+      nb.bc[e] = g.bc[d][side];
       const int n = g.n[d];
-      double vn;
       if (ix[d] >= 0 && ix[d] < n) {
-        vn = v(cidx(g, ix[0], ix[1], ix[2]));
+        nb.m[e] = cidx(g, ix[0], ix[1], ix[2]);
       } else if (g.bc[d][0] == BC_PERIODIC) {
         ix[d] = ix[d] < 0 ? ix[d] + n : ix[d] - n;
-        vn = v(cidx(g, ix[0], ix[1], ix[2]));
+        nb.m[e] = cidx(g, ix[0], ix[1], ix[2]);
       } else {
-        double sg, cst;
-        diff_rule(g, g.bc[d][side], op.q, d, sg, cst);
-        vn = sg * vc;
+        nb.m[e] = -1;
       }
-      acc += w * mfc * (vc - vn);
     }
   }
-  return acc;
 }
 
-// The rule constants' part: sum over boundary faces of ih^2 mu_f cst.
-template <int DIM>
-__device__ __forceinline__ double diff_bnd(const GridK &g, const DiffOp &op, int i, int j, int k) {
+// rho* yc + kap sum_e cf_e (yc - y_nb), with Y(m) the value at cell m and the
+// homogeneous ghost sigma yc beyond a boundary face.
+template <int DIM, typename YF>
+__device__ __forceinline__ double diff_apply(const GridK &g, const DiffNbr<DIM> &nb, int q,
+                                             double kap, double rs, double yc, YF Y) {
   double acc = 0.0;
-  const int ix[3] = {i, j, k};
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    if (g.bc[d][0] == BC_PERIODIC) continue;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      if (side == 0 ? ix[d] != 0 : ix[d] != g.n[d] - 1) continue;
-      int fx[3] = {i, j, k};
-      fx[d] += side;
+  for (int e = 0; e < 2 * DIM; ++e) {
+    double yn;
+    if (nb.m[e] >= 0) {
+      yn = Y(nb.m[e]);
+    } else {
       double sg, cst;
-      diff_rule(g, g.bc[d][side], op.q, d, sg, cst);
-      acc += g.ih[d] * g.ih[d] * op.mf[d][fidx(g, d, fx[0], fx[1], fx[2])] * cst;
+      diff_rule(g, nb.bc[e], q, e >> 1, sg, cst);
+      yn = sg * yc;
     }
+    acc += nb.cf[e] * (yc - yn);
   }
-  return acc;
+  return rs * yc + kap * acc;
+}
+
+// kap sum over boundary faces of cf cst: the ghost rules' constant part.
+template <int DIM>
+__device__ __forceinline__ double diff_bnd(const GridK &g, const DiffNbr<DIM> &nb, int q,
+                                           double kap) {
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < 2 * DIM; ++e) {
+    if (nb.m[e] >= 0) continue;
+    double sg, cst;
+    diff_rule(g, nb.bc[e], q, e >> 1, sg, cst);
+    acc += nb.cf[e] * cst;
+  }
+  return kap * acc;
 }
 
 // Face viscosity of direction d from the state at step n (the predictor's mu_f).
@@ -952,135 +970,258 @@ __global__ void k_diff_coef(GridK g, int d, StateV<S> st, double *mf) {
   mf[f] = double(S(0.5) * (mu_of(g, thP) + mu_of(g, thQ)));
 }
 
-// v^n of the variable at a cell (velocity component or temperature), as the
-// predictor forms it.
+// The variable's value in the state at step n (velocity component, or 3: theta).
 template <typename S>
-__device__ __forceinline__ double diff_start_value(const GridK &g, const StateV<S> &st, int q,
+__device__ __forceinline__ double diff_state_value(const GridK &g, const StateV<S> &st, int q,
                                                    int64_t c) {
   const S inv = S(1) / st.rho[c];
   return q < 3 ? double(st.mom[q][c] * inv) : double(st.E[c] * inv * S(g.inv_cv));
 }
 
-// Start of one solve: x = v^n, rhs = src scale + dt kap (rule constants), r0 = rhs -
-// A x; partial b.b; the CG scalars are reset for `tag`.
+__device__ __forceinline__ int diff_q(int v, int dim) { return v < dim ? v : 3; }
+
+// Start of the solves: x0 (order 0: the state's values at step n; 1: 2 y1 - y2,
+// the linear extrapolation of the last two steps' solutions), rhs = explicit part
+// + boundary constants, r0 = rhs - A x0; partial sums of b.b; the scalars reset.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kBlockThreads) void k_diff_init(GridK g, DiffOp op, StateV<S> st,
-                                                        const S *rho_s, const S *src,
-                                                        double scale, double *x, double *r,
-                                                        double *partials, CgScal *cs, int tag) {
-  __shared__ double lds[32];
-  double bb = 0.0;
-  const double dk = g.dt * op.kap;
+__global__ __launch_bounds__(kBlockThreads) void k_dsys_init(GridK g, DiffSys D, StateV<S> st,
+                                                        const S *rho_s, const S *ms0,
+                                                        const S *ms1, const S *ms2,
+                                                        const S *E_s, int order, int tag) {
+  constexpr int NV = DIM + 1;
+  __shared__ double lds[16 * NV];
+  const S *src[3] = {ms0, ms1, ms2};
+  double bb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) bb[v] = 0.0;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
   for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
-    const double rhs = double(src[c]) * scale + dk * diff_bnd<DIM>(g, op, i, j, k);
-    const double xc = diff_start_value(g, st, op.q, c);
-    auto vn = [&](int64_t m) { return diff_start_value(g, st, op.q, m); };
-    const double ax = double(rho_s[c]) * xc + dk * diff_lap<DIM>(g, op, vn, i, j, k, xc);
-    x[c] = xc;
-    r[c] = rhs - ax;
-    bb += rhs * rhs;
+    DiffNbr<DIM> nb;
+    diff_nbr<DIM>(g, D.mf, i, j, k, nb);
+    const double rs = double(rho_s[c]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int q = diff_q(v, DIM);
+      const double kap = v < DIM ? 1.0 : D.kap_th;
+      const double *y1 = D.y1[v], *y2 = D.y2[v];
+      auto X0 = [&](int64_t m) {
+        return order == 0 ? diff_state_value(g, st, q, m) : 2.0 * y1[m] - y2[m];
+      };
+      const double xc = X0(c);
+      const double rhs =
+          (v < DIM ? double(src[v][c]) : double(E_s[c]) * g.inv_cv) + diff_bnd<DIM>(g, nb, q, kap);
+      D.x[v][c] = xc;
+      D.r[0][v][c] = rhs - diff_apply<DIM>(g, nb, q, kap, rs, xc, X0);
+      bb[v] += rhs * rhs;
+    }
   }
-  bb = block_sum(bb, lds);
+  block_sum_n<NV>(bb, lds);
   if (threadIdx.x == 0) {
-    partials[PART_BB * kMaxBlocks + blockIdx.x] = bb;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) D.part[(v * DP_REGIONS + DP_BB) * kMaxBlocks + blockIdx.x] = bb[v];
     if (blockIdx.x == 0) {
-      cs->done = 0;
-      cs->iters = 0;
-      cs->step_tag = tag;
-      cs->xfinal = 0;
+#pragma unroll
+      for (int v = 0; v < kDiffVars; ++v) D.sc->done[v] = v < NV ? 0 : 1;
+      D.sc->iters = 0;
+      D.sc->step_tag = tag;
     }
   }
 }
 
-// w0 = A r0 and the partials of gamma_0 = r0.r0, delta_0 = w0.r0.
+// w0 = A r0 and the partials of gamma_0 = r0.r0, delta_0 = w0.r0, per variable.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kBlockThreads) void k_diff_start(GridK g, DiffOp op, const S *rho_s,
-                                                         const double *r0, double *w0,
-                                                         double *partials) {
-  __shared__ double lds[32];
-  double sums[2] = {0.0, 0.0};
-  const double dk = g.dt * op.kap;
+__global__ __launch_bounds__(kBlockThreads) void k_dsys_start(GridK g, DiffSys D, const S *rho_s) {
+  constexpr int NV = DIM + 1;
+  __shared__ double lds[16 * 2 * NV];
+  double sums[2 * NV];
+#pragma unroll
+  for (int v = 0; v < 2 * NV; ++v) sums[v] = 0.0;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
   for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
-    const double rc = r0[c];
-    const double wc = double(rho_s[c]) * rc +
-                      dk * diff_lap<DIM>(g, op, [&](int64_t m) { return r0[m]; }, i, j, k, rc);
-    w0[c] = wc;
-    sums[0] += rc * rc;
-    sums[1] += wc * rc;
+    DiffNbr<DIM> nb;
+    diff_nbr<DIM>(g, D.mf, i, j, k, nb);
+    const double rs = double(rho_s[c]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double *r0 = D.r[0][v];
+      const double rc = r0[c];
+      const double wc = diff_apply<DIM>(g, nb, diff_q(v, DIM), v < DIM ? 1.0 : D.kap_th, rs, rc,
+                                        [&](int64_t m) { return r0[m]; });
+      D.w[0][v][c] = wc;
+      sums[2 * v] += rc * rc;
+      sums[2 * v + 1] += wc * rc;
+    }
   }
-  block_sum_n<2>(sums, lds);
+  block_sum_n<2 * NV>(sums, lds);
   if (threadIdx.x == 0) {
-    partials[PART_G * kMaxBlocks + blockIdx.x] = sums[0];
-    partials[PART_D * kMaxBlocks + blockIdx.x] = sums[1];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      D.part[(v * DP_REGIONS + DP_G) * kMaxBlocks + blockIdx.x] = sums[2 * v];
+      D.part[(v * DP_REGIONS + DP_D) * kMaxBlocks + blockIdx.x] = sums[2 * v + 1];
+    }
   }
 }
 
-// One iteration of the diffusion solve: k_cg_iter's recurrences with this operator.
+// Iteration `it` of all solves still running: the recurrences of k_cg_iter per
+// variable. Every block forms gamma, delta (and b.b at it = 0) of each running
+// variable from the previous kernel's partials, tests it (converged, or out of
+// iterations, an error flag or NaN: that variable stops) and updates the running
+// ones; block 0 records the scalars and posts (tag, it, error flags, state) to
+// `progress`, the state 0 while any variable runs, then 1 (all converged) or 2.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kBlockThreads) void k_diff_iter(
-    GridK g, int it, DiffOp op, const S *__restrict__ rho_s, const double *__restrict__ r,
-    const double *__restrict__ w, const double *__restrict__ sold, double *__restrict__ rn,
-    double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
-    double *__restrict__ x, double *partials, CgScal *cs, const int *flags, uint64_t *progress) {
-  __shared__ double lds[32];
-  __shared__ int done0;
-  double alpha, beta;
-  if (!cg_head(it, partials, cs, flags, progress, lds, done0, alpha, beta)) return;
+__global__ __launch_bounds__(kBlockThreads) void k_dsys_iter(GridK g, int it, DiffSys D,
+                                                        const S *__restrict__ rho_s,
+                                                        const int *flags, uint64_t *progress) {
+  constexpr int NV = DIM + 1;
+  __shared__ double lds[16 * 3 * NV];
+  __shared__ double red[3 * NV];
+  __shared__ int run0[NV];
+  DiffScal *sc = D.sc;
+  if (threadIdx.x < NV) run0[threadIdx.x] = sc->done[threadIdx.x] == 0;
+  __syncthreads();
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) any = any || run0[v];
+  if (!any) return;
+  const int par = it & 1;
+  {
+    double acc[3 * NV];
+#pragma unroll
+    for (int v = 0; v < 3 * NV; ++v) acc[v] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (!run0[v]) continue;
+        acc[v] += D.part[(v * DP_REGIONS + DP_G + par) * kMaxBlocks + b];
+        acc[NV + v] += D.part[(v * DP_REGIONS + DP_D + par) * kMaxBlocks + b];
+        if (it == 0) acc[2 * NV + v] += D.part[(v * DP_REGIONS + DP_BB) * kMaxBlocks + b];
+      }
+    }
+    block_sum_n<3 * NV>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int v = 0; v < 3 * NV; ++v) red[v] = acc[v];
+    }
+    __syncthreads();
+  }
+  const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
+                  (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  double alpha[NV], beta[NV];
+  bool run[NV];
+  bool all_end = true;
+  int state = 1;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    alpha[v] = beta[v] = 0.0;
+    run[v] = false;
+    if (!run0[v]) {
+      if (sc->done[v] == 2) state = 2;
+      continue;
+    }
+    const double gam = red[v], del = red[NV + v];
+    const double bb = (it == 0) ? red[2 * NV + v] : sc->bb[v];
+    const bool conv = gam <= sc->tol2 * bb;
+    const bool out = !conv && (it >= sc->maxit || err != 0 || !(gam == gam));
+    alpha[v] = gam / del;
+    if (it > 0) {
+      beta[v] = gam / sc->rr[(it - 1) & 1][v];
+      alpha[v] = gam / (del - beta[v] * gam / sc->alpha[(it - 1) & 1][v]);
+    }
+    run[v] = !(conv || out);
+    if (run[v]) all_end = false;
+    if (out) state = 2;
+    if (lead) {
+      if (it == 0) sc->bb[v] = bb;
+      sc->rr[par][v] = gam;
+      sc->alpha[par][v] = alpha[v];
+      if (!run[v]) sc->done[v] = conv ? 1 : 2;
+    }
+  }
+  if (lead) {
+    sc->iters = it;
+    if (progress)
+      __hip_atomic_store(progress, pack_progress(sc->step_tag, it, err, all_end ? state : 0),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  if (all_end) return;
   const bool first = it == 0;
-  const double dk = g.dt * op.kap;
+  double sums[2 * NV];
+#pragma unroll
+  for (int v = 0; v < 2 * NV; ++v) sums[v] = 0.0;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
-  double sums[2] = {0.0, 0.0};
   for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
     int i, j, k;
     if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
     const int64_t c = cidx(g, i, j, k);
-    const double rc = r[c], wc = w[c];
-    const double pc = first ? rc : rc + beta * p[c];
-    const double sc = first ? wc : wc + beta * sold[c];
-    x[c] = x[c] + alpha * pc;
-    const double rnc = rc - alpha * sc;
-    auto rv = [&](int64_t m) {
-      return first ? r[m] - alpha * w[m] : r[m] - alpha * (w[m] + beta * sold[m]);
-    };
-    const double wnc = double(rho_s[c]) * rnc + dk * diff_lap<DIM>(g, op, rv, i, j, k, rnc);
-    p[c] = pc;
-    snew[c] = sc;
-    rn[c] = rnc;
-    wn[c] = wnc;
-    sums[0] += rnc * rnc;
-    sums[1] += wnc * rnc;
+    DiffNbr<DIM> nb;
+    diff_nbr<DIM>(g, D.mf, i, j, k, nb);
+    const double rs = double(rho_s[c]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (!run[v]) continue;
+      const double *__restrict__ r = D.r[par][v];
+      const double *__restrict__ w = D.w[par][v];
+      const double *__restrict__ so = D.s[par][v];
+      const double a = alpha[v], be = beta[v];
+      const double rc = r[c], wc = w[c];
+      const double pc = first ? rc : rc + be * D.p[v][c];
+      const double scc = first ? wc : wc + be * so[c];
+      D.x[v][c] = D.x[v][c] + a * pc;
+      const double rnc = rc - a * scc;
+      auto RV = [&](int64_t m) {
+        return first ? r[m] - a * w[m] : r[m] - a * (w[m] + be * so[m]);
+      };
+      const double wnc =
+          diff_apply<DIM>(g, nb, diff_q(v, DIM), v < DIM ? 1.0 : D.kap_th, rs, rnc, RV);
+      D.p[v][c] = pc;
+      D.s[par ^ 1][v][c] = scc;
+      D.r[par ^ 1][v][c] = rnc;
+      D.w[par ^ 1][v][c] = wnc;
+      sums[2 * v] += rnc * rnc;
+      sums[2 * v + 1] += wnc * rnc;
+    }
   }
-  cg_tail(it, sums, partials, lds);
+  block_sum_n<2 * NV>(sums, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (!run[v]) continue;
+      D.part[(v * DP_REGIONS + DP_G + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[2 * v];
+      D.part[(v * DP_REGIONS + DP_D + (par ^ 1)) * kMaxBlocks + blockIdx.x] = sums[2 * v + 1];
+    }
+  }
 }
 
-// The solved variable into the predictor's outputs: m*_q = rho* u*_q (m^ moves by
-// the same amount), or E* = c_v rho* theta* with psi = 1/(R theta*).
-template <typename S>
-__global__ void k_diff_finish(GridK g, int q, const double *x, const S *rho_s, S *ms, S *mh,
-                              S *E_s, S *psi) {
+// The solutions into the predictor's outputs: m*_q = rho* u*_q (m^ moves by the
+// same amount), E* = c_v rho* theta* and psi = 1/(R theta*).
+template <int DIM, typename S>
+__global__ void k_dsys_finish(GridK g, DiffSys D, const S *rho_s, S *ms0, S *ms1, S *ms2,
+                              S *mh0, S *mh1, S *mh2, S *E_s, S *psi) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= g.N) return;
-  if (q < 3) {
-    const S mnew = S(double(rho_s[c]) * x[c]);
-    mh[c] = mh[c] + (mnew - ms[c]);
-    ms[c] = mnew;
-  } else {
-    const S Es = S(g.cv * double(rho_s[c]) * x[c]);
-    E_s[c] = Es;
-    const S theta = Es / (rho_s[c] * S(g.cv));
-    psi[c] = S(1) / (S(g.R) * theta);
+  S *ms[3] = {ms0, ms1, ms2};
+  S *mh[3] = {mh0, mh1, mh2};
+  const double rs = double(rho_s[c]);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    const S mnew = S(rs * D.x[q][c]);
+    mh[q][c] = mh[q][c] + (mnew - ms[q][c]);
+    ms[q][c] = mnew;
   }
+  const S Es = S(g.cv * rs * D.x[DIM][c]);
+  E_s[c] = Es;
+  const S theta = Es / (rho_s[c] * S(g.cv));
+  psi[c] = S(1) / (S(g.R) * theta);
 }
 
 // ------------------------------------- FP32 form: pressure by iterative refinement
@@ -1637,12 +1778,26 @@ void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {
   });
 }
 
-static DiffOp diff_op(const Launch &L, const Bufs &B, int q) {
-  DiffOp op;
-  for (int d = 0; d < 3; ++d) op.mf[d] = B.muf[d];
-  op.q = q;
-  op.kap = q < 3 ? 1.0 : L.g.cp_Pr * L.g.inv_cv;  // lambda_f / (c_v mu_f) = gamma / Pr
-  return op;
+// The diffusion systems' buffers for solution ring slot `ring`: x = slot ring,
+// y1 = the previous step's solution, y2 = the one before.
+static DiffSys diff_sys(const Launch &L, const Bufs &B, int ring) {
+  DiffSys D;
+  for (int d = 0; d < 3; ++d) D.mf[d] = B.muf[d];
+  for (int v = 0; v < kDiffVars; ++v) {
+    D.x[v] = B.dring[ring][v];
+    D.y1[v] = B.dring[(ring + 2) % 3][v];
+    D.y2[v] = B.dring[(ring + 1) % 3][v];
+    D.p[v] = B.dp[v];
+    for (int s = 0; s < 2; ++s) {
+      D.r[s][v] = B.dr[s][v];
+      D.w[s][v] = B.dw[s][v];
+      D.s[s][v] = B.ds[s][v];
+    }
+  }
+  D.part = B.dpart;
+  D.sc = B.dsc;
+  D.kap_th = L.g.cp_Pr * L.g.inv_cv;  // lambda_f / (c_v mu_f) = gamma / Pr
+  return D;
 }
 
 void run_diff_coef(const Launch &L, const Bufs &B, int cur) {
@@ -1655,37 +1810,33 @@ void run_diff_coef(const Launch &L, const Bufs &B, int cur) {
   });
 }
 
-void run_diff_start(const Launch &L, const Bufs &B, int cur, int q, int tag) {
-  const DiffOp op = diff_op(L, B, q);
+void run_diff_start(const Launch &L, const Bufs &B, int cur, int ring, int order, int tag) {
+  const DiffSys D = diff_sys(L, B, ring);
   IBM_DISPATCH(L, {
-    const S *src = (const S *)(q < 3 ? B.mom_s[q] : B.E_s);
-    const double scale = q < 3 ? 1.0 : L.g.inv_cv;
-    hipLaunchKernelGGL((k_diff_init<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
-                       L.st, L.g, op, state_of<S>(B, cur), (const S *)B.rho_s, src, scale, B.b,
-                       B.rv[0], B.partials, B.cg, tag);
-    hipLaunchKernelGGL((k_diff_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
-                       L.st, L.g, op, (const S *)B.rho_s, (const double *)B.rv[0], B.wv[0],
-                       B.partials);
+    hipLaunchKernelGGL((k_dsys_init<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, D, state_of<S>(B, cur), (const S *)B.rho_s,
+                       (const S *)B.mom_s[0], (const S *)B.mom_s[1], (const S *)B.mom_s[2],
+                       (const S *)B.E_s, order, tag);
+    hipLaunchKernelGGL((k_dsys_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, D, (const S *)B.rho_s);
   });
 }
 
-void run_diff_iteration(const Launch &L, const Bufs &B, int q, int it) {
-  const DiffOp op = diff_op(L, B, q);
+void run_diff_iteration(const Launch &L, const Bufs &B, int ring, int it) {
+  const DiffSys D = diff_sys(L, B, ring);
   IBM_DISPATCH(L, {
-    const int a = it & 1, b = a ^ 1;
-    hipLaunchKernelGGL((k_diff_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
-                       L.st, L.g, it, op, (const S *)B.rho_s, (const double *)B.rv[a],
-                       (const double *)B.wv[a], (const double *)B.sv[a], B.rv[b], B.wv[b], B.sv[b],
-                       B.pv, B.b, B.partials, B.cg, (const int *)B.flags, B.progress);
+    hipLaunchKernelGGL((k_dsys_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
+                       L.st, L.g, it, D, (const S *)B.rho_s, (const int *)B.flags, B.progress);
   });
 }
 
-void run_diff_finish(const Launch &L, const Bufs &B, int q) {
+void run_diff_finish(const Launch &L, const Bufs &B, int ring) {
+  const DiffSys D = diff_sys(L, B, ring);
   IBM_DISPATCH(L, {
     const int64_t nb = (L.g.N + 255) / 256;
-    hipLaunchKernelGGL((k_diff_finish<S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g, q,
-                       (const double *)B.b, (const S *)B.rho_s, (S *)(q < 3 ? B.mom_s[q] : nullptr),
-                       (S *)(q < 3 ? B.mhat[q] : nullptr), (S *)B.E_s, (S *)B.psi);
+    hipLaunchKernelGGL((k_dsys_finish<DIM, S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g, D,
+                       (const S *)B.rho_s, (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2],
+                       (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], (S *)B.E_s, (S *)B.psi);
   });
 }
 

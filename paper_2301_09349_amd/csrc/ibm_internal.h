@@ -78,6 +78,20 @@ struct CgScal {
   int xfinal;        // x buffer of the finished solve (read by the correction)
 };
 
+// Implicit diffusion: dim + 1 systems (velocity components, temperature) solved
+// side by side. Their scalars, in device memory; rr/alpha slot it & 1 as in CgScal.
+constexpr int kDiffVars = 4;
+struct DiffScal {
+  double bb[kDiffVars];
+  double rr[2][kDiffVars];
+  double alpha[2][kDiffVars];
+  double tol2;
+  int done[kDiffVars];  // 0 iterating, 1 converged, 2 stopped (limit, error flag, NaN)
+  int maxit, iters, step_tag;
+};
+// per-variable regions of the diffusion partial sums: b.b, r.r (2), w.r (2)
+enum { DP_BB = 0, DP_G = 1, DP_D = 3, DP_REGIONS = 5 };
+
 // Progress word the CG posts to host memory after each convergence test:
 // bits 32..63 step tag, 8..31 iteration, 4..7 error flags seen, 0..3 done state.
 __host__ __device__ inline uint64_t pack_progress(int tag, int it, int err, int done) {

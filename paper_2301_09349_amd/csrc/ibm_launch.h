@@ -75,9 +75,26 @@ struct Bufs {
   // fields at the pairs [nc][27][dim + 2]; per-pair cell sums [nc][27][2]; the
   // adjoint quadrature solve [nc]
   double *wbar, *epsbar, *pfld, *gsum, *lam_g;
-  // implicit diffusion: FP64 face viscosity per direction [NF[d]] (the solves use
-  // b as their solution and the FP64 CG vectors, both free before the set-up)
+  // implicit diffusion (FP64): face viscosity per direction [NF[d]]; per variable a
+  // ring of three solutions (this step's and the two before, for the start), the
+  // CG vectors r, w, s (ping-pong) and p; partial sums and scalars
   double *muf[3];
+  double *dring[3][kDiffVars];
+  double *dr[2][kDiffVars], *dw[2][kDiffVars], *ds[2][kDiffVars], *dp[kDiffVars];
+  double *dpart;
+  DiffScal *dsc;
+};
+
+// Kernel view of the diffusion systems' buffers.
+struct DiffSys {
+  const double *mf[3];
+  double *x[kDiffVars];
+  const double *y1[kDiffVars], *y2[kDiffVars];
+  double *p[kDiffVars];
+  double *r[2][kDiffVars], *w[2][kDiffVars], *s[2][kDiffVars];
+  double *part;
+  DiffScal *sc;
+  double kap_th;  // gamma / Pr
 };
 
 struct Launch {
@@ -120,12 +137,13 @@ int cg_parts(const Launch &L);
 void run_cg_half(const Launch &L, const Bufs &B, int it, int part);
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag);
 // implicit diffusion after the predictor: the face viscosities of state `cur`;
-// for variable q (velocity component, 3: temperature) the solve's start (progress
-// posted under `tag`), its iterations, and the solution into m*, m^ or E*, psi
+// the start of the dim + 1 solves into solution ring slot `ring` (order 0: from
+// the state at step n; 1: extrapolated from the two previous slots; progress
+// posted under `tag`), their iterations, and the solutions into m*, m^, E*, psi
 void run_diff_coef(const Launch &L, const Bufs &B, int cur);
-void run_diff_start(const Launch &L, const Bufs &B, int cur, int q, int tag);
-void run_diff_iteration(const Launch &L, const Bufs &B, int q, int it);
-void run_diff_finish(const Launch &L, const Bufs &B, int q);
+void run_diff_start(const Launch &L, const Bufs &B, int cur, int ring, int order, int tag);
+void run_diff_iteration(const Launch &L, const Bufs &B, int ring, int it);
+void run_diff_finish(const Launch &L, const Bufs &B, int ring);
 void run_mass(const Launch &L, const Bufs &B);
 int64_t cell_blocks(const GridK &g);
 

@@ -42,10 +42,11 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "ibm.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibm_grid_desc), offsetof(ibm_grid_desc, bc),
-         offsetof(ibm_grid_desc, Re), offsetof(ibm_grid_desc, U_inf),
-         offsetof(ibm_grid_desc, cg_maxit), sizeof(ibm_step_info),
-         offsetof(ibm_step_info, mass));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ibm_grid_desc),
+         offsetof(ibm_grid_desc, bc), offsetof(ibm_grid_desc, Re), offsetof(ibm_grid_desc, U_inf),
+         offsetof(ibm_grid_desc, cg_maxit), offsetof(ibm_grid_desc, diffusion),
+         sizeof(ibm_step_info), offsetof(ibm_step_info, mass),
+         offsetof(ibm_step_info, diff_iters_total));
   return 0;
 }
 """
@@ -57,7 +58,8 @@ int main(void) {
         vals = [int(v) for v in subprocess.check_output([exe]).split()]
     D, S = _lib.ibm_grid_desc, _lib.ibm_step_info
     assert vals == [ctypes.sizeof(D), D.bc.offset, D.Re.offset, D.U_inf.offset,
-                    D.cg_maxit.offset, ctypes.sizeof(S), S.mass.offset]
+                    D.cg_maxit.offset, D.diffusion.offset, ctypes.sizeof(S), S.mass.offset,
+                    S.diff_iters_total.offset]
 
 
 def test_workspace_query_validates_descriptor():

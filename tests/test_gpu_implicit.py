@@ -148,3 +148,25 @@ def test_implicit_predictor_variants_parity(cuda, monkeypatch, variant, shape):
     assert rel_l2(to_np(g.field("E_ss")), o.intermediate("E_ss")) < 1e-12
     for k, v in state_errors(g, o).items():
         assert v < 1e-11, (k, v)
+
+
+def test_implicit_start_does_not_change_the_solution(cuda, monkeypatch):
+    # the diffusion solves start from the state at step n (IBM_CG_START=plain) or
+    # from the extrapolation of the two previous steps' solutions: same states to
+    # about rtol, and the extrapolated start needs fewer iterations
+    c = inputs.case("cfg1", diffusion=IMP)
+    runs = {}
+    for mode in ("plain", None):
+        if mode:
+            monkeypatch.setenv("IBM_CG_START", mode)
+        else:
+            monkeypatch.delenv("IBM_CG_START", raising=False)
+        g = make_gpu(c)
+        g.step(5)
+        _, info = g.step(20)
+        runs[mode] = (g.get_state(), info["diff_iters_total"])
+    (a, ia), (b, ib) = runs["plain"], runs[None]
+    print(f"diffusion iterations over 20 steps: start from u^n {ia}, extrapolated {ib}")
+    for x, y in zip(a[:3], b[:3]):
+        assert rel_l2(to_np(y), to_np(x)) < 1e-11
+    assert ib < ia

@@ -89,6 +89,8 @@ struct Desc {
   double cg_rtol;
   int32_t cg_maxit;
   int32_t diffusion;  // 0: explicit; 1: compact viscous and conductive fluxes implicit
+  int32_t n_outer;    // passes of App. A step 3 per step (0 or 1: one)
+  int32_t pad_;
 };
 
 enum { PERIODIC = 0, INFLOW = 1, OUTFLOW = 2, SLIP = 3 };
@@ -121,8 +123,11 @@ struct Solver {
   // non-dimensional constants: rho_inf = U_inf = D = theta_inf = 1
   double R = 0, cv = 0, cp = 0, mu_inf = 0, p_inf = 0, dt = 0, dV = 0;
 
-  // state at step n
+  // state at step n (during the outer passes of a step: the latest iterate)
   std::vector<T> rho, E, mom[3], F[3];
+  // the step's start, kept through its outer passes (the time derivative's old
+  // values, the pressure equation's rho^n and the inflow face flux)
+  std::vector<T> rho0, E0, mom0[3];
   long step = 0;
 
   // candidate markers as given, and the subset in use (Sec. 3.1 check routine)
@@ -329,10 +334,19 @@ struct Solver {
         for (long i = 0; i < n[0]; ++i) f(i, j, k);
   }
 
+  // The step's start: the old values of its time derivative.
+  void keep_start() {
+    rho0 = rho;
+    E0 = E;
+    for (int q = 0; q < dim; ++q) mom0[q] = mom[q];
+  }
+
   // -------------------------------------------------------- Appendix A, step 1
   // Predictor with f = 0, q = 0: explicit finite-volume update of Eqs. (1)-(3)
   // in internal-energy form (rho e): convection with the stored face mass flux,
-  // -grad p, div tau, -p div u, tau:grad u and div(lambda grad theta).
+  // -grad p, div tau, -p div u, tau:grad u and div(lambda grad theta). The
+  // fluxes and cell terms are those of the current state (the latest iterate in an
+  // outer pass), the old values those of the step's start.
   int predictor() {
     const bool implicit = D.diffusion == 1;
     std::vector<T> u[3], th(N), pr(N), es(N);
@@ -408,10 +422,10 @@ struct Solver {
       for (int a = 0; a < dim; ++a)
         for (int b = 0; b < dim; ++b) phi += (g[a][b] + g[b][a]) * g[a][b];
       phi = mu(th[c]) * (phi - (2.0 / 3.0) * divu * divu);
-      rho_s[c] = rho[c] - dt * divF;
+      rho_s[c] = rho0[c] - dt * divF;
       for (int q = 0; q < dim; ++q)
-        mom_s[q][c] = mom[q][c] - dt * divM[q] - dt * grad_c(pr, V_P, p, q);
-      E_s[c] = E[c] - dt * divE - dt * pr[c] * divU + dt * phi;
+        mom_s[q][c] = mom0[q][c] - dt * divM[q] - dt * grad_c(pr, V_P, p, q);
+      E_s[c] = E0[c] - dt * divE - dt * pr[c] * divU + dt * phi;
     });
     if (!implicit) return 0;
     // Backward Euler for the compact face-normal fluxes: per velocity component
@@ -686,6 +700,19 @@ struct Solver {
       // value being the interpolated internal energy of the predictor
       Qk[k] = (cv * rhoL[k] * Tw[k] - EL[k]) / dt;
     }
+    spread_sources();
+    // Sec. 3.1: force on the body = minus the force the markers put on the fluid
+    for (int q = 0; q < 3; ++q) force[q] = T(0.0);
+    heat = T(0.0);
+    for (int k = 0; k < ns; ++k) {
+      for (int q = 0; q < dim; ++q) force[q] -= dV * (eps[k] * Fk[size_t(k) * 3 + q]);
+      heat += dV * (eps[k] * Qk[k]);
+    }
+  }
+
+  // m** = m* + dt S(F_k), E** = E* + dt S(Q_k) with the marker sources Fk, Qk
+  // (formed once per step: App. A keeps f and q through step 3's iteration).
+  void spread_sources() {
     std::vector<T> comp(ns), f;
     for (int q = 0; q < 3; ++q) mom_ss[q] = mom_s[q];
     for (int q = 0; q < dim; ++q) {
@@ -696,13 +723,6 @@ struct Solver {
     spread(Qk, f);
     E_ss.resize(N);
     for (long c = 0; c < N; ++c) E_ss[c] = E_s[c] + dt * f[c];
-    // Sec. 3.1: force on the body = minus the force the markers put on the fluid
-    for (int q = 0; q < 3; ++q) force[q] = T(0.0);
-    heat = T(0.0);
-    for (int k = 0; k < ns; ++k) {
-      for (int q = 0; q < dim; ++q) force[q] -= dV * (eps[k] * Fk[size_t(k) * 3 + q]);
-      heat += dV * (eps[k] * Qk[k]);
-    }
   }
 
   // Pressure operator (homogeneous part): psi x - dt^2 div(grad_f x), with zero
@@ -786,7 +806,7 @@ struct Solver {
     for (int d = 0; d < dim; ++d) {
       Fh[d].assign(NF[d], T(0.0));
       for_faces(d, [&](long i, long j, long k) {
-        Fh[d][fidx(d, i, j, k)] = face_from_cells(mh, rho, d, i, j, k);
+        Fh[d][fidx(d, i, j, k)] = face_from_cells(mh, rho0, d, i, j, k);
       });
     }
     rhs.assign(N, T(0.0));
@@ -803,7 +823,7 @@ struct Solver {
           if (id == n[d] - 1 && D.bc[d][1] == OUTFLOW) aff += 2.0 * p_inf / (h[d] * h[d]);
         }
       }
-      rhs[c] = rho[c] - dt * div + dt * dt * aff;
+      rhs[c] = rho0[c] - dt * div + dt * dt * aff;
     });
     pres = pn;
     int rc = cg(psi, rhs, pres);
@@ -825,7 +845,7 @@ struct Solver {
         hi[d] += 1;
         div += (F[d][fidx(d, hi[0], hi[1], hi[2])] - F[d][fidx(d, i, j, k)]) / h[d];
       }
-      rn[c] = rho[c] - dt * div;
+      rn[c] = rho0[c] - dt * div;
       for (int q = 0; q < dim; ++q) mom[q][c] = mh[q][c] - dt * grad_c(pres, V_P, p, q);
     });
     for (long c = 0; c < N; ++c) {
@@ -835,24 +855,34 @@ struct Solver {
     return rc;
   }
 
+  // One time step. App. A step 3 repeated n_outer times ("until convergence"):
+  // every pass after the first re-evaluates the predictor's fluxes and cell terms
+  // at the latest iterate (the step's start keeps the old values), re-adds the
+  // marker sources of the first pass and solves the pressure equation again.
   int do_step() {
     if (motion_axis >= 0 && nc > 0) {
       int rc = refresh_markers(double(step + 1) * dt);
       if (rc) return rc;
     }
-    {
-      int rc = predictor();
+    keep_start();
+    const int passes = D.n_outer > 1 ? D.n_outer : 1;
+    int rc = 0;
+    for (int pass = 0; pass < passes && rc == 0; ++pass) {
+      rc = predictor();
       if (rc) return rc;
+      if (ns > 0) {
+        if (pass == 0)
+          forcing();
+        else
+          spread_sources();
+      } else {
+        for (int q = 0; q < 3; ++q) mom_ss[q] = mom_s[q];
+        E_ss = E_s;
+        for (int q = 0; q < 3; ++q) force[q] = T(0.0);
+        heat = T(0.0);
+      }
+      rc = pressure_correction();
     }
-    if (ns > 0) {
-      forcing();
-    } else {
-      for (int q = 0; q < 3; ++q) mom_ss[q] = mom_s[q];
-      E_ss = E_s;
-      for (int q = 0; q < 3; ++q) force[q] = T(0.0);
-      heat = T(0.0);
-    }
-    int rc = pressure_correction();
     step += 1;
     return rc;
   }
@@ -1070,7 +1100,11 @@ void orc_get_marker_fields(void *p, double *out) {
 }
 
 // Building blocks exposed for the pinning tests.
-int orc_predictor_only(void *p) { return static_cast<Handle *>(p)->s.predictor(); }
+int orc_predictor_only(void *p) {
+  Handle *h = static_cast<Handle *>(p);
+  h->s.keep_start();
+  return h->s.predictor();
+}
 void orc_helmholtz(void *p, const double *psi, const double *x, double *y) {
   Solver<double> &s = static_cast<Handle *>(p)->s;
   std::vector<double> ps(psi, psi + s.N), xx(x, x + s.N), yy;

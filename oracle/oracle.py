@@ -45,6 +45,8 @@ class Desc(ctypes.Structure):
         ("cg_rtol", ctypes.c_double),
         ("cg_maxit", ctypes.c_int32),
         ("diffusion", ctypes.c_int32),
+        ("n_outer", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -359,4 +361,5 @@ def make_desc(case) -> Desc:
     d.cg_rtol = float(case.get("cg_rtol", 1e-13))
     d.cg_maxit = int(case.get("cg_maxit", 2000))
     d.diffusion = int(case.get("diffusion", 0))
+    d.n_outer = int(case.get("n_outer", 1))
     return d

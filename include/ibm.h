@@ -77,6 +77,13 @@ enum { IBM_MU_SUTHERLAND = 0, IBM_MU_CONSTANT = 1 };
  * solved by conjugate gradients (to cg_rtol, from u^n and theta^n); the time step
  * from cfl then follows convection alone. Not with the adjoint. */
 enum { IBM_DIFF_EXPLICIT = 0, IBM_DIFF_IMPLICIT = 1 };
+/* Outer passes (n_outer > 1): App. A step 3 repeated ("until convergence"). Every
+ * pass after the first evaluates the predictor's fluxes and cell terms (and the
+ * implicit diffusion's face viscosities) at the latest iterate, keeps the step's
+ * start as the time derivative's old values, re-spreads the marker sources formed
+ * in the first pass (f and q stay fixed within the step) and solves the pressure
+ * equation again from the previous pass's solution. The passes are a fixed-point
+ * iteration; converged, the step is implicit in every term. Not with the adjoint. */
 /* ibm_set_markers flags: apply the marker check routine of Sec. 3.1 (of the
  * markers that fall in one cell only the one nearest to its centre is used,
  * ties to the lower id), at set-up and after every motion update. */
@@ -105,6 +112,9 @@ typedef struct {
   double cg_rtol;           /* pressure CG stops at |r| <= cg_rtol |b|         */
   int32_t cg_maxit;         /* pressure CG iteration limit                     */
   int32_t max_markers;      /* capacity for candidate markers                  */
+  int32_t n_outer;          /* passes of App. A step 3 per step (0 or 1: one;  */
+                            /* at most 64): the outer passes described above  */
+  int32_t reserved;
 } ibm_grid_desc;
 
 typedef struct {

@@ -50,6 +50,8 @@ class ibm_grid_desc(ctypes.Structure):
         ("cg_rtol", ctypes.c_double),
         ("cg_maxit", ctypes.c_int32),
         ("max_markers", ctypes.c_int32),
+        ("n_outer", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

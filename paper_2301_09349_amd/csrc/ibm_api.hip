@@ -111,7 +111,7 @@ struct ibm_ctx {
   // highest order of the extrapolated CG start: 2 (default), 1 with
   // IBM_CG_START=linear, 0 with IBM_CG_START=plain
   int cg_order = 2;
-  int tag = 0;  // step tag, one per step launched
+  int tag = 0;  // solve tag, one per pass of a step launched
   std::string err;
   CgScal cgh;
   Prof prof;
@@ -157,6 +157,7 @@ const char *check_desc(const ibm_grid_desc *d) {
     return "unknown viscosity law";
   if (d->diffusion != IBM_DIFF_EXPLICIT && d->diffusion != IBM_DIFF_IMPLICIT)
     return "unknown diffusion treatment";
+  if (d->n_outer < 0 || d->n_outer > 64) return "n_outer must be in 0..64";
   if (!(d->Re > 0) || !(d->Ma > 0) || !(d->Pr > 0) || !(d->gamma > 1.0))
     return "Re, Ma, Pr must be > 0 and gamma > 1";
   if (!(d->sutherland_S >= 0)) return "sutherland_S must be >= 0";
@@ -537,19 +538,21 @@ ibm_status run_cg_to_end(ibm_ctx *ctx, const Bufs &Bc, int tag, int *iters) {
   return IBM_OK;
 }
 
-// Implicit diffusion of one step, after its predictor: the face viscosities, then
-// the dim + 1 solves side by side (one kernel per iteration), started from the
-// linear extrapolation of the last two steps' solutions when both are held (and
-// IBM_CG_START is not plain), else from the state at step n. Progress is posted
-// under -(8 tag + 1), apart from step tags. Returns the iterations in *iters.
-ibm_status diffusion_solves(ibm_ctx *ctx, int tag, int *iters) {
+// Implicit diffusion of one pass of a step, after its predictor: the face
+// viscosities of the state in slot `flux`, then the dim + 1 solves side by side
+// (one kernel per iteration), started in the first pass from the linear
+// extrapolation of the last two steps' solutions when both are held (and
+// IBM_CG_START is not plain), else from that state; in a later pass from the
+// previous pass's solution. Progress is posted under -(8 tag + 1), apart from
+// step tags. Returns the iterations in *iters.
+ibm_status diffusion_solves(ibm_ctx *ctx, int tag, int flux, int pass, bool last, int *iters) {
   const Launch &L = ctx->L;
   const Bufs &B = ctx->B;
   const int ring = ctx->diff_ring;
-  const int order = (ctx->cg_order >= 1 && ctx->diff_hist >= 2) ? 1 : 0;
+  const int order = pass > 0 ? 2 : (ctx->cg_order >= 1 && ctx->diff_hist >= 2) ? 1 : 0;
   const int dtag = -(tag * 8 + 1);
-  ibmk::run_diff_coef(L, B, ctx->cur);
-  ibmk::run_diff_start(L, B, ctx->cur, ring, order, dtag);
+  ibmk::run_diff_coef(L, B, flux);
+  ibmk::run_diff_start(L, B, flux, ring, order, dtag);
   int launched = 0;
   const int first = std::max(1, ctx->diff_hint + 1);
   for (; launched < first; ++launched) ibmk::run_diff_iteration(L, B, ring, launched);
@@ -573,9 +576,11 @@ ibm_status diffusion_solves(ibm_ctx *ctx, int tag, int *iters) {
   if (dstate != 1) return fail(ctx, IBM_E_NOT_CONVERGED, "implicit diffusion CG reached cg_maxit");
   ibmk::run_diff_finish(L, B, ring);
   HIPCHECK(ctx, hipGetLastError());
-  // this step's solutions now head the ring
-  ctx->diff_ring = (ring + 1) % 3;
-  ctx->diff_hist = std::min(ctx->diff_hist + 1, 2);
+  if (last) {
+    // this step's solutions now head the ring
+    ctx->diff_ring = (ring + 1) % 3;
+    ctx->diff_hist = std::min(ctx->diff_hist + 1, 2);
+  }
   return IBM_OK;
 }
 
@@ -896,9 +901,13 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   const int cur0 = ctx->cur;
   const int64_t step0 = ctx->step;
   const int first_tag = ctx->tag + 1;
+  // App. A step 3 is run `passes` times per step: every pass after the first
+  // re-evaluates the predictor at the latest iterate (the other state slot) with
+  // the step's start (slot cur) for the time derivative, re-spreads the marker
+  // sources of the first pass, and solves the pressure equation again from the
+  // previous pass's solution. Each pass has its own tag.
+  const int passes = std::max(1, ctx->desc.n_outer);
   for (int s = 0; s < n_steps; ++s) {
-    const int tag = ++ctx->tag;
-    P.step_first = P.pending.size();
     if (ctx->nc > 0 && ctx->motion_axis >= 0) {
       ibm_status ms = IBM_OK;
       timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
@@ -910,61 +919,85 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     }
     const int order =
         std::min(ctx->cg_order, ctx->prev_valid ? (ctx->hist_valid ? 2 : 1) : 0);
-    timed(IBM_PROF_PREDICTOR, 0, [&] {
-      ibmk::run_predictor(L, B, ctx->cur, order, ctx->cg_order >= 2);
-    });
-    if (L.g.implicit_diff) {
-      ibm_status ds = IBM_OK;
-      int dit = 0;
-      timed(IBM_PROF_DIFFUSION, 0, [&] { ds = diffusion_solves(ctx, tag, &dit); });
-      diff_it += dit;
-      if (ds) {
-        // E_hist may already hold this step's E^{n-1}
+    double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
+    bool failed = false, maxit = false;
+    int iters = 0;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int tag = ++ctx->tag;
+      const bool first = pass == 0;
+      const int flux = first ? ctx->cur : ctx->cur ^ 1;
+      P.step_first = P.pending.size();
+      timed(IBM_PROF_PREDICTOR, 0, [&] {
+        ibmk::run_predictor(L, B, ctx->cur, flux, first ? order : -1,
+                            first && ctx->cg_order >= 2);
+      });
+      // the FP32 refinement may have finished in its second x buffer
+      if (!first && L.prec == 1 && L.refine32) ibmk::run_copy_solution(L, B, B.x);
+      if (L.g.implicit_diff) {
+        ibm_status ds = IBM_OK;
+        int dit = 0;
+        timed(IBM_PROF_DIFFUSION, 0,
+              [&] { ds = diffusion_solves(ctx, tag, flux, pass, pass == passes - 1, &dit); });
+        diff_it += dit;
+        if (ds) {
+          // E_hist may already hold this step's E^{n-1}
+          ctx->prev_valid = ctx->hist_valid = false;
+          ctx->diff_hist = 0;
+          rc = ds;
+          failed = true;
+          break;
+        }
+      }
+      if (ctx->nc > 0) {
+        if (first)
+          timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
+        else
+          timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_spread(L, B); });
+      } else if (hrow && first) {
+        HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
+      }
+      timed(IBM_PROF_SETUP, 0, [&] { ibmk::run_setup(L, B, ctx->cur, tag); });
+      // Iteration `it` tests convergence after `it` updates at its start, so a solve
+      // of n iterations takes n + 1 launches; launches past convergence return at
+      // once. The first batch follows the last solve's count, and the correction is
+      // queued behind it (it runs only once the solve has finished), so the device
+      // does not wait for the host unless the batch falls short.
+      int launched = 0;
+      const int nfirst = std::max(1, ctx->cg_hint + 1);
+      cg_batch(launched, nfirst);
+      launched += nfirst;
+      timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
+      HIPCHECK(ctx, hipGetLastError());
+      uint64_t w = 0;
+      for (;;) {
+        ibm_status r = wait_progress(ctx, tag, launched - 1, &w);
+        if (r) return r;
+        if (w & 0xF) break;
+        cg_batch(launched, 2);
+        launched += 2;
+        timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
+        HIPCHECK(ctx, hipGetLastError());
+      }
+      const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
+      iters = (int)((w >> 8) & 0xFFFFFF);
+      if (P.on) P.count_cg(iters);
+      if (err) {
         ctx->prev_valid = ctx->hist_valid = false;
         ctx->diff_hist = 0;
-        rc = ds;
+        // this pass's correction did not run; an earlier failure is sorted out below
+        rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE
+                                                                           : IBM_E_NOT_CONVERGED;
+        failed = true;
+        break;
+      }
+      total_it += iters;
+      ctx->cg_hint = std::max(1, iters);
+      if (dstate != 1) {  // the correction ran; the step ends here
+        maxit = true;
         break;
       }
     }
-    double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
-    if (ctx->nc > 0) {
-      timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
-    } else if (hrow) {
-      HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
-    }
-    timed(IBM_PROF_SETUP, 0,
-          [&] { ibmk::run_setup(L, B, ctx->cur, tag); });
-    // Iteration `it` tests convergence after `it` updates at its start, so a solve of
-    // n iterations takes n + 1 launches; launches past convergence return at once. The first batch follows the last step's count, and the correction is
-    // queued behind it (it runs only once the solve has finished), so the device
-    // does not wait for the host unless the batch falls short.
-    int launched = 0;
-    const int first = std::max(1, ctx->cg_hint + 1);
-    cg_batch(launched, first);
-    launched += first;
-    timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
-    HIPCHECK(ctx, hipGetLastError());
-    uint64_t w = 0;
-    for (;;) {
-      ibm_status r = wait_progress(ctx, tag, launched - 1, &w);
-      if (r) return r;
-      if (w & 0xF) break;
-      cg_batch(launched, 2);
-      launched += 2;
-      timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_correct(L, B, ctx->cur, tag); });
-      HIPCHECK(ctx, hipGetLastError());
-    }
-    const int dstate = (int)(w & 0xF), err = (int)((w >> 4) & 0xF);
-    const int iters = (int)((w >> 8) & 0xFFFFFF);
-    if (P.on) P.count_cg(iters);
-    if (err) {
-      ctx->prev_valid = ctx->hist_valid = false;
-      ctx->diff_hist = 0;
-      // this step's correction did not run; an earlier failure is sorted out below
-      rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE
-                                                                         : IBM_E_NOT_CONVERGED;
-      break;
-    }
+    if (failed) break;
     if (record) {
       ibmk::run_copy_solution(L, B, (double *)(B.tape + B.tape_stride * (size_t)s + B.tape_xoff));
       HIPCHECK(ctx, hipGetLastError());
@@ -975,9 +1008,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     ctx->step += 1;
     ++done;
     last_it = iters;
-    total_it += iters;
-    ctx->cg_hint = std::max(1, iters);
-    if (dstate != 1) {
+    if (maxit) {
       rc = fail(ctx, IBM_E_NOT_CONVERGED, "pressure CG reached cg_maxit");
       break;
     }
@@ -994,7 +1025,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   if (P.on) P.settle();
   if (f[ibmk::FLAG_NONFINITE]) {
     // the first failing step and every later one left their input in place
-    const int s_bad = (f[ibmk::FLAG_BAD_STEP] - 1) - first_tag;
+    const int s_bad = ((f[ibmk::FLAG_BAD_STEP] - 1) - first_tag) / passes;
     if (s_bad >= 0 && s_bad <= n_steps) {
       ctx->cur = cur0 ^ (s_bad & 1);
       ctx->prev_valid = ctx->hist_valid = false;
@@ -1156,6 +1187,8 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
   if (ctx->motion_axis >= 0) return fail(ctx, IBM_E_ARG, "adjoint_step: markers must be at rest");
   if (ctx->L.g.implicit_diff)
     return fail(ctx, IBM_E_ARG, "adjoint_step: implicit diffusion has no adjoint");
+  if (ctx->desc.n_outer > 1)
+    return fail(ctx, IBM_E_ARG, "adjoint_step: outer passes have no adjoint");
   if (!state_bar_in || !state_bar_out) return fail(ctx, IBM_E_ARG, "adjoint_step: NULL cotangent");
   if (state_bar_in == state_bar_out)
     return fail(ctx, IBM_E_ARG, "adjoint_step: state_bar_in and state_bar_out must differ");
@@ -1177,7 +1210,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     ibm_status r = tape_copy(ctx, tape_index, slot, false);
     if (r) return r;
   }
-  ibmk::run_predictor(L, B, slot, 0, false);
+  ibmk::run_predictor(L, B, slot, slot, 0, false);
   if (ctx->nc > 0) {
     ibmk::run_pair_fields(L, B);  // the interpolated fields, for the position gradient
     ibmk::run_markers_step(L, B, nullptr);

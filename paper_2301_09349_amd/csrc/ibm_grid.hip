@@ -155,6 +155,10 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
 // E_keep, when given, receives E^{n-1} for the next step's E_prev2 (it may be the
 // E_prev2 array: each cell is read before it is written). The spread of the
 // forcing then adds its increment to m^ and recomputes psi on the cells it touches.
+// In an outer pass of a step (App. A step 3 repeated), the fluxes and cell terms
+// are those of the latest iterate (the kernels' state) while the time
+// derivative's old values rho_b, mom_b, E_b stay those of the step's start; x is
+// then NULL (the previous pass's solution is the start).
 template <typename S>
 struct PredOut {
   S *mh[3];
@@ -163,6 +167,9 @@ struct PredOut {
   const S *E_prev;
   const S *E_prev2;
   S *E_keep;
+  const S *rho_b;
+  const S *mom_b[3];
+  const S *E_b;
 };
 
 template <typename S>
@@ -170,6 +177,7 @@ __device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> 
                                                S rho_s, S E_s, S E) {
   const S theta = E_s / (rho_s * S(g.cv));
   po.psi[c] = S(1) / (S(g.R) * theta);
+  if (!po.x) return;
   const double pn = double(S(g.gm1) * E);
   double x0 = pn;
   if (po.E_prev) {
@@ -235,15 +243,15 @@ __device__ __forceinline__ void predictor_cell(const GridK &g, const StateV<S> &
   phi = mu_of(g, th) * (phi - S(2.0 / 3.0) * divu * divu);
   const S dt = S(g.dt);
   const S pc = S(g.gm1) * E;
-  const S rs = rho - dt * divF;
+  const S rs = po.rho_b[c] - dt * divF;
   rho_s[c] = rs;
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
-    const S mhq = st.mom[q][c] - dt * divM[q];
+    const S mhq = po.mom_b[q][c] - dt * divM[q];
     ms[q][c] = mhq - dt * gp[q];
     po.mh[q][c] = mhq;
   }
-  const S es = E - dt * divE - dt * pc * divU + dt * phi;
+  const S es = po.E_b[c] - dt * divE - dt * pc * divU + dt * phi;
   E_s[c] = es;
   pred_setup_out(g, po, c, rs, es, E);
 }
@@ -556,15 +564,15 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       if (!cv_ok[m]) continue;
       const int64_t c = cidx(g, x0 + cl[m][0], y0 + cl[m][1], z0 + cl[m][2]);
       const S E = st.E[c];
-      const S rs = st.rho[c] - dt * acc[m][0];
+      const S rs = po.rho_b[c] - dt * acc[m][0];
       rho_s[c] = rs;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) {
-        const S mhq = st.mom[q][c] + acc[m][1 + q];
+        const S mhq = po.mom_b[q][c] + acc[m][1 + q];
         ms[q][c] = mhq + gpr[m][q];
         po.mh[q][c] = mhq;
       }
-      const S es = E + acc[m][DIM + 1] - dt * (gm1 * E) * acc[m][DIM + 2];
+      const S es = po.E_b[c] + acc[m][DIM + 1] - dt * (gm1 * E) * acc[m][DIM + 2];
       E_s[c] = es;
       pred_setup_out(g, po, c, rs, es, E);
     }
@@ -980,9 +988,10 @@ __device__ __forceinline__ double diff_state_value(const GridK &g, const StateV<
 
 __device__ __forceinline__ int diff_q(int v, int dim) { return v < dim ? v : 3; }
 
-// Start of the solves: x0 (order 0: the state's values at step n; 1: 2 y1 - y2,
-// the linear extrapolation of the last two steps' solutions), rhs = explicit part
-// + boundary constants, r0 = rhs - A x0; partial sums of b.b; the scalars reset.
+// Start of the solves: x0 (order 0: the state's values; 1: 2 y1 - y2, the linear
+// extrapolation of the last two steps' solutions; 2: x as it is, the previous
+// outer pass's solution), rhs = explicit part + boundary constants, r0 = rhs -
+// A x0; partial sums of b.b; the scalars reset.
 template <int DIM, typename S>
 __global__ __launch_bounds__(kBlockThreads) void k_dsys_init(GridK g, DiffSys D, StateV<S> st,
                                                         const S *rho_s, const S *ms0,
@@ -1007,14 +1016,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_dsys_init(GridK g, DiffSys D,
     for (int v = 0; v < NV; ++v) {
       const int q = diff_q(v, DIM);
       const double kap = v < DIM ? 1.0 : D.kap_th;
-      const double *y1 = D.y1[v], *y2 = D.y2[v];
+      const double *y1 = D.y1[v], *y2 = D.y2[v], *xv = D.x[v];
       auto X0 = [&](int64_t m) {
-        return order == 0 ? diff_state_value(g, st, q, m) : 2.0 * y1[m] - y2[m];
+        return order == 0 ? diff_state_value(g, st, q, m)
+                          : order == 1 ? 2.0 * y1[m] - y2[m] : xv[m];
       };
       const double xc = X0(c);
       const double rhs =
           (v < DIM ? double(src[v][c]) : double(E_s[c]) * g.inv_cv) + diff_bnd<DIM>(g, nb, q, kap);
-      D.x[v][c] = xc;
+      if (order != 2) D.x[v][c] = xc;
       D.r[0][v][c] = rhs - diff_apply<DIM>(g, nb, q, kap, rs, xc, X0);
       bb[v] += rhs * rhs;
     }
@@ -1664,15 +1674,18 @@ void enable_predictor_lds(int dim, int prec) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-void run_predictor(const Launch &L, const Bufs &B, int cur, int order, bool keep) {
+void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order, bool keep) {
   IBM_DISPATCH(L, {
     PredOut<S> po;
     for (int q = 0; q < 3; ++q) po.mh[q] = (S *)B.mhat[q];
     po.psi = (S *)B.psi;
-    po.x = B.x;
+    po.x = order >= 0 ? B.x : nullptr;
     po.E_prev = order >= 1 ? (const S *)B.E[cur ^ 1] : nullptr;
     po.E_prev2 = order >= 2 ? (const S *)B.E_hist : nullptr;
     po.E_keep = (order >= 1 && keep) ? (S *)B.E_hist : nullptr;
+    po.rho_b = (const S *)B.rho[base];
+    for (int q = 0; q < 3; ++q) po.mom_b[q] = (const S *)B.mom[base][q];
+    po.E_b = (const S *)B.E[base];
     if (L.pred_lds) {
       using T = PredLds<DIM, S>;
       const int64_t nt = (int64_t)((L.g.n[0] + T::TX - 1) / T::TX) *

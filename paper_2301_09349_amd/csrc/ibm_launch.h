@@ -115,10 +115,13 @@ void run_init_primitive(const Launch &L, const Bufs &B, int cur, const void *rho
                         const void *theta);
 void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
 // predictor, also writing m^ (= m* + dt G_c p^n), psi and the CG start x for the
-// set-up. order 0: x = p^n; 1: the other state slot holds the previous state and
-// x = 2 p^n - p^{n-1}; 2: E_hist also holds E^{n-2} and x = 3 p^n - 3 p^{n-1} +
-// p^{n-2}. keep (order >= 1): E^{n-1} is copied to E_hist for the next step.
-void run_predictor(const Launch &L, const Bufs &B, int cur, int order, bool keep);
+// set-up. Fluxes and cell terms from state slot `cur`, the time derivative's old
+// values from slot `base` (the same slot except in an outer pass). order -1: x
+// is left as it is (an outer pass); 0: x = p^n; 1: the other state slot holds the
+// previous state and x = 2 p^n - p^{n-1}; 2: E_hist also holds E^{n-2} and x =
+// 3 p^n - 3 p^{n-1} + p^{n-2}. keep (order >= 1): E^{n-1} is copied to E_hist for
+// the next step.
+void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order, bool keep);
 size_t predictor_lds_bytes(int dim, int prec);
 void enable_predictor_lds(int dim, int prec);
 // set-up of the pressure equation from the predictor's m^, psi, x (with the spread
@@ -138,8 +141,9 @@ void run_cg_half(const Launch &L, const Bufs &B, int it, int part);
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag);
 // implicit diffusion after the predictor: the face viscosities of state `cur`;
 // the start of the dim + 1 solves into solution ring slot `ring` (order 0: from
-// the state at step n; 1: extrapolated from the two previous slots; progress
-// posted under `tag`), their iterations, and the solutions into m*, m^, E*, psi
+// the state in slot `cur`; 1: extrapolated from the two previous ring slots; 2:
+// from the solution in slot `ring`; progress posted under `tag`), their
+// iterations, and the solutions into m*, m^, E*, psi
 void run_diff_coef(const Launch &L, const Bufs &B, int cur);
 void run_diff_start(const Launch &L, const Bufs &B, int cur, int ring, int order, int tag);
 void run_diff_iteration(const Launch &L, const Bufs &B, int ring, int it);

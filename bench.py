@@ -342,6 +342,27 @@ def run_implicit(case, steps: int, warmup: int, explicit: dict):
     return res
 
 
+def run_outer(case, steps: int, warmup: int):
+    """The main workload in FP64 with 1, 2 and 3 outer passes per step (App. A step
+    3 repeated) at half the default step (CFL 0.25: the passes are a fixed-point
+    iteration that converges only where dt |lambda| < 1, and at the default step
+    an even pass count is unstable): ms per step and CG iterations per step."""
+    res = {"steps": steps, "cfl": 0.25}
+    one = None
+    for K in (1, 2, 3):
+        r = run_forward(dict(case, n_outer=K, cfl=0.25), "fp64", steps, warmup)
+        ms = r["ms_per_step"]
+        one = one or ms
+        res[f"n_outer_{K}"] = {
+            "ms_per_step": round(ms, 4), "cost_vs_one_pass": round(ms / one, 3),
+            "dt": r["solver"].dt,
+            "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
+            "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
+                                    for k, v in r["per_kernel"].items()}}
+        del r
+    return res
+
+
 def calibrate_copy():
     """A plain streaming kernel of known size for scaling the HBM counters: negation
     of CALIB_ELEMS float64 values (8 B read + 8 B written each), three launches."""
@@ -504,6 +525,7 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 sphere figures")
     ap.add_argument("--no-implicit", action="store_true",
                     help="skip the implicit-diffusion figures")
+    ap.add_argument("--no-outer", action="store_true", help="skip the outer-pass figures")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the oscillating-cylinder figures")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -590,6 +612,10 @@ def main():
     if not args.no_implicit:
         log("bench: implicit diffusion ...")
         out["implicit_diffusion"] = run_implicit(case, args.steps, args.warmup, explicit)
+        torch.cuda.empty_cache()
+    if not args.no_outer:
+        log("bench: outer passes ...")
+        out["outer_passes"] = run_outer(case, args.steps, args.warmup)
         torch.cuda.empty_cache()
     if not args.no_3d and args.workload != "cfg3":
         log("bench: 256^3 sphere ...")

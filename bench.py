@@ -65,7 +65,8 @@ def kernel_bytes(cls: str, dim: int, precision: str = "fp64") -> int:
 KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start", "setup"),
                 ("k_cg_iter", "cg"), ("k_mcg_iter", "cg"),
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
-                ("k_totals", "markers"), ("k_markers_fused", "markers")]
+                ("k_totals", "markers"), ("k_markers_fused", "markers"),
+                ("k_dsys", "diffusion"), ("k_diff_coef", "diffusion")]
 
 
 def kernel_class(name: str):
@@ -517,7 +518,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the headline value (the other form is run too)")
     ap.add_argument("--workload", default="cfg2a")
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=100)
@@ -526,6 +527,8 @@ def main():
     ap.add_argument("--no-implicit", action="store_true",
                     help="skip the implicit-diffusion figures")
     ap.add_argument("--no-outer", action="store_true", help="skip the outer-pass figures")
+    ap.add_argument("--diffusion", default="explicit", choices=["explicit", "implicit"],
+                    help="viscous and conductive terms of the main workload (profiling)")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the oscillating-cylinder figures")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -549,7 +552,8 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy()
-    case = inputs.case(args.workload, cg_rtol=1e-10)
+    case = inputs.case(args.workload, cg_rtol=1e-10,
+                       diffusion=1 if args.diffusion == "implicit" else 0)
     main_p = args.precision
     other = "fp32" if main_p == "fp64" else "fp64"
     r = run_forward(case, main_p, args.steps, args.warmup)
@@ -558,7 +562,8 @@ def main():
     dom = max((k for k in per_kernel if "GBps" in per_kernel[k]),
               key=lambda k: per_kernel[k]["total_ms"])
     d = per_kernel[dom]
-    label = "%s_%s" % (WORKLOAD_LABEL.get(args.workload, args.workload), main_p)
+    label = "%s%s_%s" % (WORKLOAD_LABEL.get(args.workload, args.workload),
+                         "_implicit" if args.diffusion == "implicit" else "", main_p)
     traffic = traffic_entry(label, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBps"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4),

@@ -83,7 +83,10 @@ enum { IBM_DIFF_EXPLICIT = 0, IBM_DIFF_IMPLICIT = 1 };
  * start as the time derivative's old values, re-spreads the marker sources formed
  * in the first pass (f and q stay fixed within the step) and solves the pressure
  * equation again from the previous pass's solution. The passes are a fixed-point
- * iteration; converged, the step is implicit in every term. Not with the adjoint. */
+ * iteration; converged, the step is implicit in every term. It converges where
+ * dt |lambda| < 1 for the stiffest explicit mode: use cfl <= 0.25 (at cfl 0.5 an
+ * even pass count amplifies the stiffest conduction mode and is unstable). Not
+ * with the adjoint. */
 /* ibm_set_markers flags: apply the marker check routine of Sec. 3.1 (of the
  * markers that fall in one cell only the one nearest to its centre is used,
  * ties to the lower id), at set-up and after every motion update. */

@@ -90,7 +90,7 @@ struct Desc {
   int32_t cg_maxit;
   int32_t diffusion;  // 0: explicit; 1: compact viscous and conductive fluxes implicit
   int32_t n_outer;    // passes of App. A step 3 per step (0 or 1: one)
-  int32_t pad_;
+  int32_t scheme;     // 0: pressure-based (App. A); 1: density-based (App. B)
 };
 
 enum { PERIODIC = 0, INFLOW = 1, OUTFLOW = 2, SLIP = 3 };
@@ -219,6 +219,13 @@ struct Solver {
     for (int a = 0; a < dim; ++a) {
       sc += uref / h[a];
       sd += 1.0 / (h[a] * h[a]);
+    }
+    // the density-based step is explicit in the acoustic waves too: the sound
+    // speed at theta_max, sqrt(gamma R theta_max), is added to the flow speed
+    if (D.scheme == 1) {
+      const double c = std::sqrt(D.gamma * R * thm);
+      sc = 0.0;
+      for (int a = 0; a < dim; ++a) sc += (uref + c) / h[a];
     }
     // with implicit diffusion only convection limits the step (without any flow
     // speed the explicit limit is kept)
@@ -855,6 +862,219 @@ struct Solver {
     return rc;
   }
 
+  // ------------------------------------------ App. B (density-based variant)
+  // van Leer limited value at a face from the side of cell C (downwind cell Dn,
+  // far cell U on the other side of C): phi_C + (1/2) psi(r) (phi_D - phi_C).
+  static T limited(const T &phC, const T &phD, const T &phU) {
+    T a = phC - phU, b = phD - phC;
+    T ab = a * b;
+    if (val(ab) > 0.0) return phC + ab / (a + b);
+    return phC;
+  }
+
+  // Face values of a cell array on the low (L, from cell P) and high (R, from
+  // cell Q) side of the face between P and Q = P + e_d: limited with van Leer
+  // convection, the linear average on both sides otherwise.
+  void side_values(const std::vector<T> &a, int var, int d, const long *P, const long *Q,
+                   T &L, T &Rv) const {
+    const T aP = at3(a, var, P), aQ = at3(a, var, Q);
+    if (D.convection == CONV_LINEAR) {
+      L = Rv = 0.5 * (aP + aQ);
+      return;
+    }
+    long Pm[3] = {P[0], P[1], P[2]}, Qp[3] = {Q[0], Q[1], Q[2]};
+    Pm[d] -= 1;
+    Qp[d] += 1;
+    L = limited(aP, aQ, at3(a, var, Pm));
+    Rv = limited(aQ, aP, at3(a, var, Qp));
+  }
+
+  // The central-upwind face flux of Kurganov, Noelle and Petrova (the scheme of
+  // rhoCentralFoam) for rho, rho u and rho e_t through the face of direction d
+  // between P and Q: density, velocity and temperature reconstructed on both
+  // sides, p = rho R theta, c^2 = gamma R theta; a+ = max(u_L + c_L, u_R + c_R, 0),
+  // a- = min(u_L - c_L, u_R - c_R, 0) (normal velocities), alpha = a+/(a+ - a-),
+  // omega = -a+ a-/(a+ - a-); flux = alpha f(L) + (1 - alpha) f(R) - omega (W_R -
+  // W_L), the pressure taken as alpha p_L + (1 - alpha) p_R (no dissipation on it).
+  void knp_flux(const std::vector<T> &r, const std::vector<T> *u, const std::vector<T> &th, int d,
+                const long *P, const long *Q, T &fr, T *fm, T &fe) const {
+    using std::sqrt;
+    T rL, rR, thL, thR, uL[3], uR[3];
+    side_values(r, V_RHO, d, P, Q, rL, rR);
+    side_values(th, V_TH, d, P, Q, thL, thR);
+    T kL = T(0.0), kR = T(0.0);
+    for (int q = 0; q < dim; ++q) {
+      side_values(u[q], V_U0 + q, d, P, Q, uL[q], uR[q]);
+      kL += uL[q] * uL[q];
+      kR += uR[q] * uR[q];
+    }
+    const T pL = rL * R * thL, pR = rR * R * thR;
+    const T cL = sqrt(D.gamma * R * thL), cR = sqrt(D.gamma * R * thR);
+    const T vL = uL[d], vR = uR[d];
+    T ap = vL + cL, am = vL - cL;
+    if (val(vR + cR) > val(ap)) ap = vR + cR;
+    if (val(ap) < 0.0) ap = T(0.0);
+    if (val(vR - cR) < val(am)) am = vR - cR;
+    if (val(am) > 0.0) am = T(0.0);
+    const T span = ap - am;
+    const T al = ap / span, om = -(ap * am) / span, bl = 1.0 - al;
+    const T eL = rL * (cv * thL + 0.5 * kL), eR = rR * (cv * thR + 0.5 * kR);
+    fr = al * vL * rL + bl * vR * rR - om * (rR - rL);
+    for (int q = 0; q < dim; ++q)
+      fm[q] = al * vL * (rL * uL[q]) + bl * vR * (rR * uR[q]) - om * (rR * uR[q] - rL * uL[q]);
+    fm[d] += al * pL + bl * pR;
+    fe = al * vL * (eL + pL) + bl * vR * (eR + pR) - om * (eR - eL);
+  }
+
+  // Face stress tau_{d,q} from a velocity field u and the face viscosity muf: the
+  // normal derivatives compact, the tangential ones the face average of the two
+  // centred cell gradients (as the pressure-based predictor).
+  void face_stress(const std::vector<T> *u, int d, const long *P, const long *Q, const T &muf,
+                   T *tau) const {
+    T dn[3], tg[3], divf;
+    for (int q = 0; q < dim; ++q)
+      dn[q] = (at3(u[q], V_U0 + q, Q) - at3(u[q], V_U0 + q, P)) / h[d];
+    divf = dn[d];
+    for (int t = 0; t < dim; ++t) {
+      tg[t] = T(0.0);
+      if (t == d) continue;
+      tg[t] = 0.5 * (grad_c(u[d], V_U0 + d, P, t) + grad_c(u[d], V_U0 + d, Q, t));
+      divf += 0.5 * (grad_c(u[t], V_U0 + t, P, t) + grad_c(u[t], V_U0 + t, Q, t));
+    }
+    for (int q = 0; q < dim; ++q)
+      tau[q] = (q == d) ? muf * (2.0 * dn[d] - (2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+  }
+
+  // The density-based step without the body (App. B step 1, forcing zero):
+  //   rho^{n+1} = rho^n - dt D(F_rho), (rho u)** = (rho u)^n - dt D(F_m),
+  //   (rho e_t)** = (rho e_t)^n - dt D(F_e) with the central-upwind fluxes of
+  //   the state at step n (inviscid part, explicit);
+  //   u** = (rho u)**/rho^{n+1}, theta** = ((rho e_t)**/rho^{n+1} - |u**|^2/2)/c_v;
+  //   viscous part, explicit at (u**, theta**): (rho u)* = (rho u)** + dt div tau,
+  //   (rho e)* = rho^{n+1} c_v theta** + dt (div(lambda grad_n theta**) + Phi),
+  //   Phi = tau:grad u at the cell.
+  // Results in rho_s, mom_s, E_s (internal energy); the mass flux in Fr.
+  int density_predictor(std::vector<T> *Fr) {
+    std::vector<T> u[3], th(N);
+    for (int q = 0; q < dim; ++q) u[q].resize(N);
+    for (long c = 0; c < N; ++c) {
+      for (int q = 0; q < dim; ++q) u[q][c] = mom[q][c] / rho[c];
+      th[c] = E[c] / (rho[c] * cv);
+    }
+    std::vector<T> fm[3][3], fe[3];
+    for (int d = 0; d < dim; ++d) {
+      Fr[d].assign(NF[d], T(0.0));
+      fe[d].assign(NF[d], T(0.0));
+      for (int q = 0; q < dim; ++q) fm[d][q].assign(NF[d], T(0.0));
+      for_faces(d, [&](long i, long j, long k) {
+        long f = fidx(d, i, j, k);
+        long P[3] = {i, j, k}, Q[3] = {i, j, k};
+        P[d] -= 1;
+        T mq[3];
+        knp_flux(rho, u, th, d, P, Q, Fr[d][f], mq, fe[d][f]);
+        for (int q = 0; q < dim; ++q) fm[d][q][f] = mq[q];
+      });
+    }
+    std::vector<T> r1(N), m2[3], th2(N);
+    for (int q = 0; q < dim; ++q) m2[q].resize(N);
+    for_cells([&](long i, long j, long k) {
+      long c = cidx(i, j, k);
+      T dF = T(0.0), dE = T(0.0), dM[3] = {T(0.0), T(0.0), T(0.0)};
+      for (int d = 0; d < dim; ++d) {
+        long hi[3] = {i, j, k};
+        hi[d] += 1;
+        long f0 = fidx(d, i, j, k), f1 = fidx(d, hi[0], hi[1], hi[2]);
+        dF += (Fr[d][f1] - Fr[d][f0]) / h[d];
+        dE += (fe[d][f1] - fe[d][f0]) / h[d];
+        for (int q = 0; q < dim; ++q) dM[q] += (fm[d][q][f1] - fm[d][q][f0]) / h[d];
+      }
+      T k2 = T(0.0), kn = T(0.0);
+      for (int q = 0; q < dim; ++q) kn += mom[q][c] * mom[q][c];
+      const T et = E[c] + 0.5 * kn / rho[c];  // rho e_t at step n
+      r1[c] = rho[c] - dt * dF;
+      for (int q = 0; q < dim; ++q) {
+        m2[q][c] = mom[q][c] - dt * dM[q];
+        u[q][c] = m2[q][c] / r1[c];  // u** (u^n is no longer needed)
+        k2 += u[q][c] * u[q][c];
+      }
+      th2[c] = ((et - dt * dE) / r1[c] - 0.5 * k2) / cv;
+    });
+    // viscous and conductive part at (u**, theta**)
+    std::vector<T> tf[3][3], qf[3];
+    for (int d = 0; d < dim; ++d) {
+      qf[d].assign(NF[d], T(0.0));
+      for (int q = 0; q < dim; ++q) tf[d][q].assign(NF[d], T(0.0));
+      for_faces(d, [&](long i, long j, long k) {
+        long f = fidx(d, i, j, k);
+        long P[3] = {i, j, k}, Q[3] = {i, j, k};
+        P[d] -= 1;
+        T thP = at3(th2, V_TH, P), thQ = at3(th2, V_TH, Q);
+        T muf = 0.5 * (mu(thP) + mu(thQ));
+        T lamf = 0.5 * (lam(thP) + lam(thQ));
+        T tau[3];
+        face_stress(u, d, P, Q, muf, tau);
+        for (int q = 0; q < dim; ++q) tf[d][q][f] = tau[q];
+        qf[d][f] = lamf * (thQ - thP) / h[d];
+      });
+    }
+    rho_s = r1;
+    E_s.assign(N, T(0.0));
+    for (int q = 0; q < 3; ++q) mom_s[q].assign(N, T(0.0));
+    for_cells([&](long i, long j, long k) {
+      long c = cidx(i, j, k), p[3] = {i, j, k};
+      T dQ = T(0.0), dT[3] = {T(0.0), T(0.0), T(0.0)};
+      for (int d = 0; d < dim; ++d) {
+        long hi[3] = {i, j, k};
+        hi[d] += 1;
+        long f0 = fidx(d, i, j, k), f1 = fidx(d, hi[0], hi[1], hi[2]);
+        dQ += (qf[d][f1] - qf[d][f0]) / h[d];
+        for (int q = 0; q < dim; ++q) dT[q] += (tf[d][q][f1] - tf[d][q][f0]) / h[d];
+      }
+      T g[3][3], divu = T(0.0);
+      for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) g[a][b] = grad_c(u[a], V_U0 + a, p, b);
+      for (int a = 0; a < dim; ++a) divu += g[a][a];
+      T phi = T(0.0);
+      for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) phi += (g[a][b] + g[b][a]) * g[a][b];
+      phi = mu(th2[c]) * (phi - (2.0 / 3.0) * divu * divu);
+      for (int q = 0; q < dim; ++q) mom_s[q][c] = m2[q][c] + dt * dT[q];
+      E_s[c] = r1[c] * cv * th2[c] + dt * (dQ + phi);
+    });
+    return 0;
+  }
+
+  // One density-based step (App. B): the step without the body, the marker
+  // sources from its result (interpolation, forcing, spread: m += dt f,
+  // rho e += dt q), and theta, p from the new internal energy (p = rho R theta
+  // follows from E = rho c_v theta).
+  int density_step() {
+    std::vector<T> Fr[3];
+    int rc = density_predictor(Fr);
+    if (rc) return rc;
+    if (ns > 0) {
+      forcing();
+    } else {
+      for (int q = 0; q < 3; ++q) mom_ss[q] = mom_s[q];
+      E_ss = E_s;
+      for (int q = 0; q < 3; ++q) force[q] = T(0.0);
+      heat = T(0.0);
+    }
+    cg_iters = 0;
+    cg_res = 0.0;
+    bool bad = false;
+    for (long c = 0; c < N; ++c) {
+      const double r = val(rho_s[c]), e = val(E_ss[c]);
+      if (!(r > 0.0) || !(e > 0.0) || !std::isfinite(r) || !std::isfinite(e)) bad = true;
+    }
+    if (bad) return 6;
+    rho = rho_s;
+    E = E_ss;
+    for (int q = 0; q < dim; ++q) mom[q] = mom_ss[q];
+    for (int d = 0; d < dim; ++d) F[d] = Fr[d];
+    return 0;
+  }
+
   // One time step. App. A step 3 repeated n_outer times ("until convergence"):
   // every pass after the first re-evaluates the predictor's fluxes and cell terms
   // at the latest iterate (the step's start keeps the old values), re-adds the
@@ -863,6 +1083,11 @@ struct Solver {
     if (motion_axis >= 0 && nc > 0) {
       int rc = refresh_markers(double(step + 1) * dt);
       if (rc) return rc;
+    }
+    if (D.scheme == 1) {
+      int rc = density_step();
+      if (rc == 0) step += 1;
+      return rc;
     }
     keep_start();
     const int passes = D.n_outer > 1 ? D.n_outer : 1;

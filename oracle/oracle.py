@@ -46,7 +46,7 @@ class Desc(ctypes.Structure):
         ("cg_maxit", ctypes.c_int32),
         ("diffusion", ctypes.c_int32),
         ("n_outer", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -362,4 +362,5 @@ def make_desc(case) -> Desc:
     d.cg_maxit = int(case.get("cg_maxit", 2000))
     d.diffusion = int(case.get("diffusion", 0))
     d.n_outer = int(case.get("n_outer", 1))
+    d.scheme = int(case.get("scheme", 0))
     return d

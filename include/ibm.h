@@ -77,6 +77,16 @@ enum { IBM_MU_SUTHERLAND = 0, IBM_MU_CONSTANT = 1 };
  * solved by conjugate gradients (to cg_rtol, from u^n and theta^n); the time step
  * from cfl then follows convection alone. Not with the adjoint. */
 enum { IBM_DIFF_EXPLICIT = 0, IBM_DIFF_IMPLICIT = 1 };
+/* The step: pressure-based (App. A; the default) or density-based (App. B): the
+ * explicit central-upwind step of Kurganov, Noelle and Petrova for rho, rho u,
+ * rho e_t (rho, u, theta reconstructed on both sides of a face, van Leer limited
+ * with IBM_CONV_VANLEER, the linear average with IBM_CONV_LINEAR), then the
+ * viscous and conductive terms explicitly at the intermediate (u**, theta**),
+ * then the marker sources of Sec. 2.2 from that result (m += dt f, rho e +=
+ * dt q). Its time step adds the sound speed at dt_theta_max to the flow speed.
+ * Explicit diffusion and one pass only; no adjoint (IBM_E_ARG). The stored face
+ * mass flux is the step's central-upwind density flux. */
+enum { IBM_SCHEME_PRESSURE = 0, IBM_SCHEME_DENSITY = 1 };
 /* Outer passes (n_outer > 1): App. A step 3 repeated ("until convergence"). Every
  * pass after the first evaluates the predictor's fluxes and cell terms (and the
  * implicit diffusion's face viscosities) at the latest iterate, keeps the step's
@@ -117,7 +127,7 @@ typedef struct {
   int32_t max_markers;      /* capacity for candidate markers                  */
   int32_t n_outer;          /* passes of App. A step 3 per step (0 or 1: one;  */
                             /* at most 64): the outer passes described above  */
-  int32_t reserved;
+  int32_t scheme;           /* IBM_SCHEME_PRESSURE or IBM_SCHEME_DENSITY       */
 } ibm_grid_desc;
 
 typedef struct {

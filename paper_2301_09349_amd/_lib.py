@@ -18,6 +18,7 @@ IBM_FP64, IBM_FP32 = 0, 1
 IBM_CONV_VANLEER, IBM_CONV_LINEAR = 0, 1
 IBM_MU_SUTHERLAND, IBM_MU_CONSTANT = 0, 1
 IBM_DIFF_EXPLICIT, IBM_DIFF_IMPLICIT = 0, 1
+IBM_SCHEME_PRESSURE, IBM_SCHEME_DENSITY = 0, 1
 IBM_DEDUPE = 1
 IBM_RECORD = 1
 
@@ -51,7 +52,7 @@ class ibm_grid_desc(ctypes.Structure):
         ("cg_maxit", ctypes.c_int32),
         ("max_markers", ctypes.c_int32),
         ("n_outer", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
     ]
 
 

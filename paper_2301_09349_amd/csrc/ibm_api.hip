@@ -158,6 +158,9 @@ const char *check_desc(const ibm_grid_desc *d) {
   if (d->diffusion != IBM_DIFF_EXPLICIT && d->diffusion != IBM_DIFF_IMPLICIT)
     return "unknown diffusion treatment";
   if (d->n_outer < 0 || d->n_outer > 64) return "n_outer must be in 0..64";
+  if (d->scheme != IBM_SCHEME_PRESSURE && d->scheme != IBM_SCHEME_DENSITY) return "unknown scheme";
+  if (d->scheme == IBM_SCHEME_DENSITY && (d->diffusion != IBM_DIFF_EXPLICIT || d->n_outer > 1))
+    return "the density-based step takes explicit diffusion and one pass";
   if (!(d->Re > 0) || !(d->Ma > 0) || !(d->Pr > 0) || !(d->gamma > 1.0))
     return "Re, Ma, Pr must be > 0 and gamma > 1";
   if (!(d->sutherland_S >= 0)) return "sutherland_S must be >= 0";
@@ -224,6 +227,13 @@ GridK make_grid(const ibm_grid_desc &d) {
     for (int a = 0; a < d.dim; ++a) {
       sc += uref / g.h[a];
       sd += 1.0 / (g.h[a] * g.h[a]);
+    }
+    // the density-based step is explicit in the acoustic waves too: the sound
+    // speed at theta_max is added to the flow speed
+    if (d.scheme == IBM_SCHEME_DENSITY) {
+      const double c = std::sqrt(d.gamma * g.R * thm);
+      sc = 0.0;
+      for (int a = 0; a < d.dim; ++a) sc += (uref + c) / g.h[a];
     }
     // with implicit diffusion only convection limits the step (without any flow
     // speed the explicit limit is kept)
@@ -901,13 +911,40 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   const int cur0 = ctx->cur;
   const int64_t step0 = ctx->step;
   const int first_tag = ctx->tag + 1;
+  if (ctx->desc.scheme == IBM_SCHEME_DENSITY) {
+    if (record) return fail(ctx, IBM_E_ARG, "step: the density-based step has no adjoint tape");
+    // App. B: the explicit step without the body, the marker sources from its
+    // result, the new state; nothing waits for the host
+    for (int s = 0; s < n_steps; ++s) {
+      const int tag = ++ctx->tag;
+      if (ctx->nc > 0 && ctx->motion_axis >= 0) {
+        ibm_status ms = IBM_OK;
+        timed(IBM_PROF_MARKERS, 0,
+              [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
+        if (ms) return ms;
+      }
+      timed(IBM_PROF_PREDICTOR, 0, [&] { ibmk::run_density_predictor(L, B, ctx->cur); });
+      double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
+      if (ctx->nc > 0) {
+        timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
+      } else if (hrow) {
+        HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
+      }
+      timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_density_finish(L, B, ctx->cur, tag); });
+      HIPCHECK(ctx, hipGetLastError());
+      ctx->cur ^= 1;
+      ctx->prev_valid = ctx->hist_valid = false;
+      ctx->step += 1;
+      ++done;
+    }
+  }
   // App. A step 3 is run `passes` times per step: every pass after the first
   // re-evaluates the predictor at the latest iterate (the other state slot) with
   // the step's start (slot cur) for the time derivative, re-spreads the marker
   // sources of the first pass, and solves the pressure equation again from the
   // previous pass's solution. Each pass has its own tag.
   const int passes = std::max(1, ctx->desc.n_outer);
-  for (int s = 0; s < n_steps; ++s) {
+  for (int s = 0; s < (ctx->desc.scheme == IBM_SCHEME_DENSITY ? 0 : n_steps); ++s) {
     if (ctx->nc > 0 && ctx->motion_axis >= 0) {
       ibm_status ms = IBM_OK;
       timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
@@ -1189,6 +1226,8 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     return fail(ctx, IBM_E_ARG, "adjoint_step: implicit diffusion has no adjoint");
   if (ctx->desc.n_outer > 1)
     return fail(ctx, IBM_E_ARG, "adjoint_step: outer passes have no adjoint");
+  if (ctx->desc.scheme == IBM_SCHEME_DENSITY)
+    return fail(ctx, IBM_E_ARG, "adjoint_step: the density-based step has no adjoint");
   if (!state_bar_in || !state_bar_out) return fail(ctx, IBM_E_ARG, "adjoint_step: NULL cotangent");
   if (state_bar_in == state_bar_out)
     return fail(ctx, IBM_E_ARG, "adjoint_step: state_bar_in and state_bar_out must differ");

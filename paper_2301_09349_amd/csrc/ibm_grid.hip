@@ -1234,6 +1234,317 @@ __global__ void k_dsys_finish(GridK g, DiffSys D, const S *rho_s, S *ms0, S *ms1
   psi[c] = S(1) / (S(g.R) * theta);
 }
 
+// ------------------------------------------ App. B (density-based variant)
+// Density, velocity and temperature at a (possibly ghost) cell of the state.
+template <int DIM, typename S>
+__device__ __forceinline__ void load_rut(const GridK &g, const StateV<S> &st, int i, int j, int k,
+                                         S &r, S *u, S &th) {
+  Resolved rs = resolve<DIM>(g, i, j, k);
+  r = st.rho[rs.c];
+  const S inv = S(1) / r;
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) u[q] = st.mom[q][rs.c] * inv;
+  th = st.E[rs.c] * inv * S(g.inv_cv);
+  if (any_side<DIM, S>(rs)) {
+    r = ghosted<DIM>(g, rs, V_RHO, r);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) u[q] = ghosted<DIM>(g, rs, V_U0 + q, u[q]);
+    th = ghosted<DIM>(g, rs, V_TH, th);
+  }
+}
+
+// Central-upwind flux (Kurganov, Noelle, Petrova; the scheme of rhoCentralFoam)
+// of rho, rho u and rho e_t through the face of direction d between P = Q - e_d
+// and Q (face index Q): rho, u, theta reconstructed on both sides (van Leer
+// limited, or the linear average with linear convection), p = rho R theta,
+// c^2 = gamma R theta; local speeds
+// a+ = max(uL + cL, uR + cR, 0), a- = min(uL - cL, uR - cR, 0) of the normal
+// velocities; alpha = a+/(a+ - a-), omega = -a+ a-/(a+ - a-);
+// flux = alpha f(L) + (1 - alpha) f(R) - omega (W_R - W_L), with the pressure
+// alpha pL + (1 - alpha) pR in the normal momentum flux.
+template <int DIM, typename S>
+__device__ __forceinline__ void knp_face(const GridK &g, const StateV<S> &st, int d, int qi,
+                                         int qj, int qk, S &fr, S *fm, S &fe) {
+  int A[3] = {qi, qj, qk};  // far cell on the low side, P, Q, far cell on the high side
+  S r[4], u[4][3], th[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    int c3[3] = {A[0], A[1], A[2]};
+    c3[d] += m - 2;
+    load_rut<DIM>(g, st, c3[0], c3[1], c3[2], r[m], u[m], th[m]);
+  }
+  S rL, rR, thL, thR, uL[3], uR[3];
+  if (g.conv == CONV_LINEAR) {
+    rL = rR = S(0.5) * (r[1] + r[2]);
+    thL = thR = S(0.5) * (th[1] + th[2]);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) uL[q] = uR[q] = S(0.5) * (u[1][q] + u[2][q]);
+  } else {
+    rL = vanleer(r[1], r[2], r[0]);
+    rR = vanleer(r[2], r[1], r[3]);
+    thL = vanleer(th[1], th[2], th[0]);
+    thR = vanleer(th[2], th[1], th[3]);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      uL[q] = vanleer(u[1][q], u[2][q], u[0][q]);
+      uR[q] = vanleer(u[2][q], u[1][q], u[3][q]);
+    }
+  }
+  S kL = S(0), kR = S(0);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    kL += uL[q] * uL[q];
+    kR += uR[q] * uR[q];
+  }
+  const S Rg = S(g.R), gam = S(g.gm1 + 1.0), cv = S(g.cv);
+  const S pL = rL * Rg * thL, pR = rR * Rg * thR;
+  const S cL = sqrt(gam * Rg * thL), cR = sqrt(gam * Rg * thR);
+  const S vL = uL[d], vR = uR[d];
+  S ap = vL + cL, am = vL - cL;
+  if (vR + cR > ap) ap = vR + cR;
+  if (ap < S(0)) ap = S(0);
+  if (vR - cR < am) am = vR - cR;
+  if (am > S(0)) am = S(0);
+  const S span = ap - am;
+  const S al = ap / span, om = -(ap * am) / span, bl = S(1) - al;
+  const S eL = rL * (cv * thL + S(0.5) * kL), eR = rR * (cv * thR + S(0.5) * kR);
+  fr = al * vL * rL + bl * vR * rR - om * (rR - rL);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q)
+    fm[q] = al * vL * (rL * uL[q]) + bl * vR * (rR * uR[q]) - om * (rR * uR[q] - rL * uL[q]);
+  fm[d] += al * pL + bl * pR;
+  fe = al * vL * (eL + pL) + bl * vR * (eR + pR) - om * (eR - eL);
+}
+
+// True while an earlier step of the call has failed (its input must survive).
+__device__ __forceinline__ bool dens_skip(const int *flags) {
+  __shared__ int skip;
+  if (threadIdx.x == 0)
+    skip = flags[FLAG_NONFINITE] || flags[FLAG_SUPPORT] || flags[FLAG_EPS] || flags[FLAG_GRAM];
+  __syncthreads();
+  return skip != 0;
+}
+
+// Inviscid part: rho^{n+1} = rho^n - dt D(F_rho), (rho u)** = (rho u)^n - dt D(F_m),
+// (rho e_t)** = (rho e_t)^n - dt D(F_e) from the central-upwind fluxes of the
+// state at step n (each cell forms its 2 dim faces); the mass flux goes to the
+// next state's face array.
+// One thread per cell, x fastest (the face fluxes need many registers: small
+// blocks keep them out of scratch).
+__device__ __forceinline__ bool dens_cell(const GridK &g, int64_t &c, int &i, int &j, int &k) {
+  c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return false;
+  i = (int)(c % g.n[0]);
+  const int64_t r = c / g.n[0];
+  j = (int)(r % g.n[1]);
+  k = (int)(r / g.n[1]);
+  return true;
+}
+
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> st, StateV<S> nxt,
+                                                           S *rho1, S *m0, S *m1, S *m2, S *et2,
+                                                           const int *flags) {
+  if (dens_skip(flags)) return;
+  S *mo[3] = {m0, m1, m2};
+  const S dt = S(g.dt);
+  {
+    int64_t c;
+    int i, j, k;
+    if (!dens_cell(g, c, i, j, k)) return;
+    const int ix[3] = {i, j, k};
+    S dF = S(0), dE = S(0), dM[3] = {S(0), S(0), S(0)};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int hi[3] = {i, j, k};
+      hi[d] += 1;
+      S frl, fml[3], fel, frh, fmh[3], feh;
+      knp_face<DIM, S>(g, st, d, i, j, k, frl, fml, fel);
+      knp_face<DIM, S>(g, st, d, hi[0], hi[1], hi[2], frh, fmh, feh);
+      nxt.F[d][fidx(g, d, i, j, k)] = frl;
+      if (ix[d] == g.n[d] - 1) nxt.F[d][fidx(g, d, hi[0], hi[1], hi[2])] = frh;
+      const S ih = S(g.ih[d]);
+      dF += (frh - frl) * ih;
+      dE += (feh - fel) * ih;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) dM[q] += (fmh[q] - fml[q]) * ih;
+    }
+    const S r = st.rho[c];
+    S kn = S(0);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) kn += st.mom[q][c] * st.mom[q][c];
+    const S et = st.E[c] + S(0.5) * kn / r;
+    rho1[c] = r - dt * dF;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) mo[q][c] = st.mom[q][c] - dt * dM[q];
+    et2[c] = et - dt * dE;
+  }
+}
+
+// u** and theta** at a (possibly ghost) cell of the intermediate state.
+template <int DIM, typename S>
+__device__ __forceinline__ void load_star(const GridK &g, const S *rho1, const S *const *m,
+                                          const S *et2, int i, int j, int k, S *u, S &th) {
+  Resolved rs = resolve<DIM>(g, i, j, k);
+  const S r = rho1[rs.c];
+  S k2 = S(0);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    u[q] = m[q][rs.c] / r;
+    k2 += u[q] * u[q];
+  }
+  th = (et2[rs.c] / r - S(0.5) * k2) / S(g.cv);
+  if (any_side<DIM, S>(rs)) {
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) u[q] = ghosted<DIM>(g, rs, V_U0 + q, u[q]);
+    th = ghosted<DIM>(g, rs, V_TH, th);
+  }
+}
+
+// Viscous stress and heat flux through the face of direction d between P and Q
+// (face index Q) from the intermediate state: tau_{d,q} with the normal
+// derivatives compact and the tangential ones the average of the two centred
+// cell gradients, mu_f the face average; lambda_f d theta / d n.
+template <int DIM, typename S>
+__device__ __forceinline__ void dens_visc_face(const GridK &g, const S *rho1, const S *const *m,
+                                               const S *et2, int d, int qi, int qj, int qk,
+                                               S *tau, S &qf) {
+  int P[3] = {qi, qj, qk}, Q[3] = {qi, qj, qk};
+  P[d] -= 1;
+  S uP[3], uQ[3], thP, thQ;
+  load_star<DIM>(g, rho1, m, et2, P[0], P[1], P[2], uP, thP);
+  load_star<DIM>(g, rho1, m, et2, Q[0], Q[1], Q[2], uQ, thQ);
+  const S muf = S(0.5) * (mu_of(g, thP) + mu_of(g, thQ));
+  const S ih = S(g.ih[d]);
+  S dn[3], tg[3] = {S(0), S(0), S(0)};
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) dn[q] = (uQ[q] - uP[q]) * ih;
+  S divf = dn[d];
+#pragma unroll
+  for (int t = 0; t < DIM; ++t) {
+    if (t == d) continue;
+    const S hh = S(0.5 * g.ih[t]);
+    S up[3], um[3], thx;
+    int a[3] = {P[0], P[1], P[2]}, b[3] = {P[0], P[1], P[2]};
+    a[t] += 1;
+    b[t] -= 1;
+    load_star<DIM>(g, rho1, m, et2, a[0], a[1], a[2], up, thx);
+    load_star<DIM>(g, rho1, m, et2, b[0], b[1], b[2], um, thx);
+    S gdP = (up[d] - um[d]) * hh, gtP = (up[t] - um[t]) * hh;
+    int c2[3] = {Q[0], Q[1], Q[2]}, e2[3] = {Q[0], Q[1], Q[2]};
+    c2[t] += 1;
+    e2[t] -= 1;
+    load_star<DIM>(g, rho1, m, et2, c2[0], c2[1], c2[2], up, thx);
+    load_star<DIM>(g, rho1, m, et2, e2[0], e2[1], e2[2], um, thx);
+    S gdQ = (up[d] - um[d]) * hh, gtQ = (up[t] - um[t]) * hh;
+    tg[t] = S(0.5) * (gdP + gdQ);
+    divf += S(0.5) * (gtP + gtQ);
+  }
+#pragma unroll
+  for (int q = 0; q < DIM; ++q)
+    tau[q] = (q == d) ? muf * (S(2) * dn[d] - S(2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+  qf = S(g.cp_Pr) * muf * (thQ - thP) * ih;
+}
+
+// Viscous and conductive part at (u**, theta**): (rho u)* = (rho u)** + dt div tau,
+// (rho e)* = rho^{n+1} c_v theta** + dt (div(lambda grad_n theta**) + Phi), Phi =
+// tau:grad u at the cell from centred gradients; into ms, E_s (the body's sources
+// are then added by the marker kernels).
+template <int DIM, typename S>
+__global__ __launch_bounds__(kThreads) void k_dens_viscous(GridK g, const S *rho1, const S *m0,
+                                                          const S *m1, const S *m2,
+                                                          const S *et2, S *ms0, S *ms1,
+                                                          S *ms2, S *E_s, const int *flags) {
+  if (dens_skip(flags)) return;
+  const S *m[3] = {m0, m1, m2};
+  S *ms[3] = {ms0, ms1, ms2};
+  const S dt = S(g.dt);
+  {
+    int64_t c;
+    int i, j, k;
+    if (!dens_cell(g, c, i, j, k)) return;
+    S dT[3] = {S(0), S(0), S(0)}, dQ = S(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      int hi[3] = {i, j, k};
+      hi[d] += 1;
+      S tl[3], th_[3], ql, qh;
+      dens_visc_face<DIM, S>(g, rho1, m, et2, d, i, j, k, tl, ql);
+      dens_visc_face<DIM, S>(g, rho1, m, et2, d, hi[0], hi[1], hi[2], th_, qh);
+      const S ih = S(g.ih[d]);
+      dQ += (qh - ql) * ih;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) dT[q] += (th_[q] - tl[q]) * ih;
+    }
+    S gr[3][3];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      int a1[3] = {i, j, k}, a0[3] = {i, j, k};
+      a1[b] += 1;
+      a0[b] -= 1;
+      S u1[3], u0[3], tx;
+      load_star<DIM>(g, rho1, m, et2, a1[0], a1[1], a1[2], u1, tx);
+      load_star<DIM>(g, rho1, m, et2, a0[0], a0[1], a0[2], u0, tx);
+      const S hh = S(0.5 * g.ih[b]);
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) gr[a][b] = (u1[a] - u0[a]) * hh;
+    }
+    S divu = S(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) divu += gr[a][a];
+    S phi = S(0);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) phi += (gr[a][b] + gr[b][a]) * gr[a][b];
+    S uc[3], thc;
+    load_star<DIM>(g, rho1, m, et2, i, j, k, uc, thc);
+    phi = mu_of(g, thc) * (phi - S(2.0 / 3.0) * divu * divu);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) ms[q][c] = m[q][c] + dt * dT[q];
+    E_s[c] = rho1[c] * S(g.cv) * thc + dt * (dQ + phi);
+  }
+}
+
+// The new state from the sourced results (rho*, m**, E**): checked (positive,
+// finite; a failure sets the flags and the step number), written unless an
+// earlier step of the call failed; partial sums of the mass.
+template <int DIM, typename S>
+__global__ __launch_bounds__(kBlockThreads) void k_dens_finish(GridK g, const S *rho_s,
+                                                          const S *ms0, const S *ms1,
+                                                          const S *ms2, const S *E_s,
+                                                          StateV<S> nxt, double *partials,
+                                                          int *flags, int tag) {
+  __shared__ double lds[32];
+  if (dens_skip(flags)) return;
+  const S *ms[3] = {ms0, ms1, ms2};
+  double mass = 0.0;
+  bool bad = false;
+  int64_t t0, t1;
+  block_tiles(g, t0, t1);
+  for (int64_t t = t0 + tile_group(); t < t1; t += tile_groups()) {
+    int i, j, k;
+    if (!cell_in_tile<DIM>(g, t, i, j, k)) continue;
+    const int64_t c = cidx(g, i, j, k);
+    const S r = rho_s[c], e = E_s[c];
+    nxt.rho[c] = r;
+    nxt.E[c] = e;
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      nxt.mom[q][c] = ms[q][c];
+      bad = bad || !isfinite(double(ms[q][c]));
+    }
+    bad = bad || !(r > S(0)) || !(e > S(0)) || !isfinite(double(r)) || !isfinite(double(e));
+    mass += double(r) * g.dV;
+  }
+  if (bad) {
+    atomicOr(flags + FLAG_NONFINITE, 1);
+    atomicCAS(flags + FLAG_BAD_STEP, 0, tag + 1);
+  }
+  double s = block_sum(mass, lds);
+  if (threadIdx.x == 0) partials[PART_MASS * kMaxBlocks + blockIdx.x] = s;
+}
+
 // ------------------------------------- FP32 form: pressure by iterative refinement
 // x and the outer residual r = b - A x are FP64; each inner solve A d = r runs the
 // single-reduction CG on FP32 vectors with FP64 dot products to a relative 1e-4 (or
@@ -1850,6 +2161,30 @@ void run_diff_finish(const Launch &L, const Bufs &B, int ring) {
     hipLaunchKernelGGL((k_dsys_finish<DIM, S>), dim3((unsigned)nb), dim3(256), 0, L.st, L.g, D,
                        (const S *)B.rho_s, (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2],
                        (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], (S *)B.E_s, (S *)B.psi);
+  });
+}
+
+void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
+  IBM_DISPATCH(L, {
+    const StateV<S> st = state_of<S>(B, cur), nx = state_of<S>(B, cur ^ 1);
+    const unsigned nb = (unsigned)((L.g.N + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nb), dim3(kThreads), 0, L.st, L.g, st, nx,
+                       (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2],
+                       (S *)B.psi, (const int *)B.flags);
+    hipLaunchKernelGGL((k_dens_viscous<DIM, S>), dim3(nb), dim3(kThreads), 0, L.st, L.g,
+                       (const S *)B.rho_s,
+                       (const S *)B.mhat[0], (const S *)B.mhat[1], (const S *)B.mhat[2],
+                       (const S *)B.psi, (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2],
+                       (S *)B.E_s, (const int *)B.flags);
+  });
+}
+
+void run_density_finish(const Launch &L, const Bufs &B, int cur, int tag) {
+  IBM_DISPATCH(L, {
+    hipLaunchKernelGGL((k_dens_finish<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads),
+                       0, L.st, L.g, (const S *)B.rho_s, (const S *)B.mom_s[0],
+                       (const S *)B.mom_s[1], (const S *)B.mom_s[2], (const S *)B.E_s,
+                       state_of<S>(B, cur ^ 1), B.partials, B.flags, tag);
   });
 }
 

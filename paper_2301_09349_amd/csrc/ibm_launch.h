@@ -149,6 +149,12 @@ void run_diff_start(const Launch &L, const Bufs &B, int cur, int ring, int order
 void run_diff_iteration(const Launch &L, const Bufs &B, int ring, int it);
 void run_diff_finish(const Launch &L, const Bufs &B, int ring);
 void run_mass(const Launch &L, const Bufs &B);
+// density-based step (App. B): the central-upwind inviscid part from state `cur`
+// (rho^{n+1} into rho_s, (rho u)** into mhat, (rho e_t)** into psi, the mass flux
+// into the other slot's faces), then the explicit viscous part into mom_s, E_s;
+// after the marker sources, the finish writes the other state slot
+void run_density_predictor(const Launch &L, const Bufs &B, int cur);
+void run_density_finish(const Launch &L, const Bufs &B, int cur, int tag);
 int64_t cell_blocks(const GridK &g);
 
 // adjoint kernels (ibm_adjoint.hip); FP64 contexts only. `st` is the state the step

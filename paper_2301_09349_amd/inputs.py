@@ -19,6 +19,7 @@ PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
 CONV_VANLEER, CONV_LINEAR = 0, 1
 MU_SUTHERLAND, MU_CONSTANT = 0, 1
 DIFF_EXPLICIT, DIFF_IMPLICIT = 0, 1
+SCHEME_PRESSURE, SCHEME_DENSITY = 0, 1
 
 SUTHERLAND_AIR = 110.4 / 288.15  # Sutherland temperature of air over T_inf = 288.15 K
 

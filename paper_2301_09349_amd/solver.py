@@ -29,6 +29,7 @@ def make_desc(case, precision: str = "fp64", max_markers=None) -> L.ibm_grid_des
     d.viscosity_law = int(case.get("viscosity_law", L.IBM_MU_SUTHERLAND))
     d.diffusion = int(case.get("diffusion", 0))
     d.n_outer = int(case.get("n_outer", 1))
+    d.scheme = int(case.get("scheme", 0))
     d.Re = float(case["Re"])
     d.Ma = float(case["Ma"])
     d.Pr = float(case.get("Pr", 0.71))

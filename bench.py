@@ -37,12 +37,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(cls: str, dim: int, precision: str = "fp64") -> int:
+def kernel_bytes(cls: str, dim: int, precision: str = "fp64", scheme: int = 0) -> int:
     """Algorithmic bytes each kernel class must move per cell (each distinct array
     element read or written once; face arrays counted as one value per cell and
     direction). State-type arrays take s bytes (8 FP64, 4 FP32); the pressure x, the
     right-hand side b and the FP64 CG vectors take 8 in both forms."""
     s = 8 if precision == "fp64" else 4
+    if scheme == 1:  # density-based step
+        if cls == "predictor":
+            # inviscid: rho, m, E -> rho*, (rho u)**, (rho e_t)**, face mass flux;
+            # viscous: rho*, (rho u)**, (rho e_t)** -> m*, E*
+            return s * (3 * (dim + 2) + dim + dim + 1)
+        if cls == "correct":
+            # rho*, m**, E** -> the new state
+            return s * 2 * (dim + 2)
+        raise KeyError(cls)
     if cls == "predictor":
         # rho, m, E, F and the two previous E (three-point extrapolated start) ->
         # rho*, m*, E*, m^, psi, the kept E^{n-1} (state type) and x (FP64)
@@ -66,7 +75,9 @@ KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start
                 ("k_cg_iter", "cg"), ("k_mcg_iter", "cg"),
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
                 ("k_totals", "markers"), ("k_markers_fused", "markers"),
-                ("k_dsys", "diffusion"), ("k_diff_coef", "diffusion")]
+                ("k_dsys", "diffusion"), ("k_diff_coef", "diffusion"),
+                ("k_dens_inviscid", "predictor"), ("k_dens_viscous", "predictor"),
+                ("k_dens_finish", "correct")]
 
 
 def kernel_class(name: str):
@@ -186,8 +197,9 @@ def run_forward(case, precision, steps, warmup):
             continue
         ent = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n,
                "ms_per_step": ms / steps}
-        if cls in ("predictor", "setup", "cg", "correct"):
-            b = kernel_bytes(cls, dim, precision) * N
+        if cls in (("predictor", "correct") if case.get("scheme", 0) == 1 else
+                   ("predictor", "setup", "cg", "correct")):
+            b = kernel_bytes(cls, dim, precision, case.get("scheme", 0)) * N
             ent["alg_bytes_per_launch"] = b
             ent["GBps"] = b / (ms / n * 1e-3) / 1e9
         per_kernel[cls] = ent
@@ -364,6 +376,32 @@ def run_outer(case, steps: int, warmup: int):
     return res
 
 
+def run_density(steps: int, warmup: int):
+    """The density-based step (App. B; explicit, its step limited by the sound
+    speed) on the 1024^2 cylinder and the 256^3 sphere at Ma 0.8, both forms:
+    throughput and the per-kernel achieved bandwidth."""
+    from paper_2301_09349_amd import inputs
+
+    res = {}
+    for name, wl, st, wu in (("cylinder1024", "cfg2a", steps, warmup), ("sphere256", "cfg3", 30, 10)):
+        case = inputs.case(wl, Ma=0.8, scheme=1)
+        ent = {"steps": st}
+        for prec in ("fp64", "fp32"):
+            r = run_forward(case, prec, st, wu)
+            if "workload" not in ent:
+                kept = r["solver"].markers_in_use()[0].shape[0]
+                ent["workload"] = workload_text(case, kept, r["solver"].dt) + ", density-based"
+            ent[prec] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                         "kernels": {k: {"avg_us": round(v["avg_us"], 2),
+                                         **({"GBps": round(v["GBps"], 1),
+                                             "frac": round(v["GBps"] / HBM_PEAK_GBS, 4)}
+                                            if "GBps" in v else {})}
+                                     for k, v in r["per_kernel"].items()}}
+            del r
+        res[name] = ent
+    return res
+
+
 def calibrate_copy():
     """A plain streaming kernel of known size for scaling the HBM counters: negation
     of CALIB_ELEMS float64 values (8 B read + 8 B written each), three launches."""
@@ -529,6 +567,10 @@ def main():
     ap.add_argument("--no-outer", action="store_true", help="skip the outer-pass figures")
     ap.add_argument("--diffusion", default="explicit", choices=["explicit", "implicit"],
                     help="viscous and conductive terms of the main workload (profiling)")
+    ap.add_argument("--scheme", default="pressure", choices=["pressure", "density"],
+                    help="step of the main workload (profiling; density: at Ma 0.8)")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the density-based figures")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the oscillating-cylinder figures")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -554,6 +596,8 @@ def main():
         calibrate_copy()
     case = inputs.case(args.workload, cg_rtol=1e-10,
                        diffusion=1 if args.diffusion == "implicit" else 0)
+    if args.scheme == "density":
+        case = dict(case, scheme=1, Ma=0.8)
     main_p = args.precision
     other = "fp32" if main_p == "fp64" else "fp64"
     r = run_forward(case, main_p, args.steps, args.warmup)
@@ -562,8 +606,9 @@ def main():
     dom = max((k for k in per_kernel if "GBps" in per_kernel[k]),
               key=lambda k: per_kernel[k]["total_ms"])
     d = per_kernel[dom]
-    label = "%s%s_%s" % (WORKLOAD_LABEL.get(args.workload, args.workload),
-                         "_implicit" if args.diffusion == "implicit" else "", main_p)
+    label = "%s%s%s_%s" % (WORKLOAD_LABEL.get(args.workload, args.workload),
+                           "_implicit" if args.diffusion == "implicit" else "",
+                           "_density" if args.scheme == "density" else "", main_p)
     traffic = traffic_entry(label, dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBps"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4),
@@ -621,6 +666,10 @@ def main():
     if not args.no_outer:
         log("bench: outer passes ...")
         out["outer_passes"] = run_outer(case, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.no_density:
+        log("bench: density-based step ...")
+        out["density_based"] = run_density(args.steps, args.warmup)
         torch.cuda.empty_cache()
     if not args.no_3d and args.workload != "cfg3":
         log("bench: 256^3 sphere ...")

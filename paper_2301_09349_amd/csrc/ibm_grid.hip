@@ -1235,16 +1235,36 @@ __global__ void k_dsys_finish(GridK g, DiffSys D, const S *rho_s, S *ms0, S *ms1
 }
 
 // ------------------------------------------ App. B (density-based variant)
-// Density, velocity and temperature at a (possibly ghost) cell of the state.
+// Primitive arrays of the density-based step: rho, u[3], theta of the state at
+// step n (p0), and u**, theta** of the intermediate state (p1); formed once per
+// cell so that the face stencils only load them.
+template <typename S>
+struct DensPrim {
+  S *v[5];  // p0: rho, u0, u1, u2, theta; p1: u0, u1, u2, theta (the last unused)
+};
+
 template <int DIM, typename S>
-__device__ __forceinline__ void load_rut(const GridK &g, const StateV<S> &st, int i, int j, int k,
-                                         S &r, S *u, S &th) {
-  Resolved rs = resolve<DIM>(g, i, j, k);
-  r = st.rho[rs.c];
+__global__ void k_dens_prim(GridK g, StateV<S> st, DensPrim<S> p0, const int *flags) {
+  if (flags[FLAG_NONFINITE] || flags[FLAG_SUPPORT] || flags[FLAG_EPS] || flags[FLAG_GRAM]) return;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.N) return;
+  const S r = st.rho[c];
   const S inv = S(1) / r;
+  p0.v[0][c] = r;
 #pragma unroll
-  for (int q = 0; q < DIM; ++q) u[q] = st.mom[q][rs.c] * inv;
-  th = st.E[rs.c] * inv * S(g.inv_cv);
+  for (int q = 0; q < DIM; ++q) p0.v[1 + q][c] = st.mom[q][c] * inv;
+  p0.v[4][c] = st.E[c] * inv * S(g.inv_cv);
+}
+
+// Density, velocity and temperature at a (possibly ghost) cell, from p0.
+template <int DIM, typename S>
+__device__ __forceinline__ void load_rut(const GridK &g, const DensPrim<S> &p0, int i, int j,
+                                         int k, S &r, S *u, S &th) {
+  Resolved rs = resolve<DIM>(g, i, j, k);
+  r = p0.v[0][rs.c];
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) u[q] = p0.v[1 + q][rs.c];
+  th = p0.v[4][rs.c];
   if (any_side<DIM, S>(rs)) {
     r = ghosted<DIM>(g, rs, V_RHO, r);
 #pragma unroll
@@ -1254,25 +1274,17 @@ __device__ __forceinline__ void load_rut(const GridK &g, const StateV<S> &st, in
 }
 
 // Central-upwind flux (Kurganov, Noelle, Petrova; the scheme of rhoCentralFoam)
-// of rho, rho u and rho e_t through the face of direction d between P = Q - e_d
-// and Q (face index Q): rho, u, theta reconstructed on both sides (van Leer
-// limited, or the linear average with linear convection), p = rho R theta,
-// c^2 = gamma R theta; local speeds
-// a+ = max(uL + cL, uR + cR, 0), a- = min(uL - cL, uR - cR, 0) of the normal
-// velocities; alpha = a+/(a+ - a-), omega = -a+ a-/(a+ - a-);
+// of rho, rho u and rho e_t through a face of direction d, from rho, u, theta at
+// the four cells along d around it (index 0: far low, 1: P, 2: Q, 3: far high):
+// the values reconstructed on both sides (van Leer limited, or the linear
+// average with linear convection), p = rho R theta, c^2 = gamma R theta; local
+// speeds a+ = max(uL + cL, uR + cR, 0), a- = min(uL - cL, uR - cR, 0) of the
+// normal velocities; alpha = a+/(a+ - a-), omega = -a+ a-/(a+ - a-);
 // flux = alpha f(L) + (1 - alpha) f(R) - omega (W_R - W_L), with the pressure
 // alpha pL + (1 - alpha) pR in the normal momentum flux.
 template <int DIM, typename S>
-__device__ __forceinline__ void knp_face(const GridK &g, const StateV<S> &st, int d, int qi,
-                                         int qj, int qk, S &fr, S *fm, S &fe) {
-  int A[3] = {qi, qj, qk};  // far cell on the low side, P, Q, far cell on the high side
-  S r[4], u[4][3], th[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    int c3[3] = {A[0], A[1], A[2]};
-    c3[d] += m - 2;
-    load_rut<DIM>(g, st, c3[0], c3[1], c3[2], r[m], u[m], th[m]);
-  }
+__device__ __forceinline__ void knp_flux(const GridK &g, int d, const S *r, const S (*u)[3],
+                                         const S *th, S &fr, S *fm, S &fe) {
   S rL, rR, thL, thR, uL[3], uR[3];
   if (g.conv == CONV_LINEAR) {
     rL = rR = S(0.5) * (r[1] + r[2]);
@@ -1325,75 +1337,149 @@ __device__ __forceinline__ bool dens_skip(const int *flags) {
   return skip != 0;
 }
 
+// Tiles of the density-based kernels: one cell per thread (256 cells: 32 x 8 in
+// 2D, 8 x 8 x 4 in 3D) and a halo of H cells on every side, corners included, in
+// LDS; each face of the tile is formed once.
+template <int DIM, int H>
+struct DTile {
+  static constexpr int TX = DIM == 2 ? 32 : 8, TY = 8, TZ = DIM == 2 ? 1 : 4;
+  static constexpr int HZ = DIM == 2 ? 0 : H;
+  static constexpr int SX = TX + 2 * H, SY = TY + 2 * H, SZ = TZ + 2 * HZ;
+  static constexpr int NP = SX * SY * SZ;
+  // most faces of one direction in a tile
+  static constexpr int NFD = (TX + 1) * TY * TZ > TX * (TY + 1) * TZ
+                                 ? ((TX + 1) * TY * TZ > TX * TY * (TZ + 1) ? (TX + 1) * TY * TZ
+                                                                             : TX * TY * (TZ + 1))
+                                 : (TX * (TY + 1) * TZ > TX * TY * (TZ + 1) ? TX * (TY + 1) * TZ
+                                                                             : TX * TY * (TZ + 1));
+  __device__ static int pt(int i, int j, int k) { return ((k + HZ) * SY + (j + H)) * SX + (i + H); }
+  // tile origin of block b (x fastest)
+  __device__ static void origin(const GridK &g, int64_t b, int &x0, int &y0, int &z0) {
+    const int ntx = (g.n[0] + TX - 1) / TX, nty = (g.n[1] + TY - 1) / TY;
+    x0 = (int)(b % ntx) * TX;
+    y0 = (int)((b / ntx) % nty) * TY;
+    z0 = (int)(b / ((int64_t)ntx * nty)) * TZ;
+  }
+  __host__ static int64_t tiles(const GridK &g) {
+    return (int64_t)((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY) *
+           (DIM == 3 ? (g.n[2] + TZ - 1) / TZ : 1);
+  }
+};
+
 // Inviscid part: rho^{n+1} = rho^n - dt D(F_rho), (rho u)** = (rho u)^n - dt D(F_m),
 // (rho e_t)** = (rho e_t)^n - dt D(F_e) from the central-upwind fluxes of the
-// state at step n (each cell forms its 2 dim faces); the mass flux goes to the
-// next state's face array.
-// One thread per cell, x fastest (the face fluxes need many registers: small
-// blocks keep them out of scratch).
-__device__ __forceinline__ bool dens_cell(const GridK &g, int64_t &c, int &i, int &j, int &k) {
-  c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.N) return false;
-  i = (int)(c % g.n[0]);
-  const int64_t r = c / g.n[0];
-  j = (int)(r % g.n[1]);
-  k = (int)(r / g.n[1]);
-  return true;
-}
-
+// state at step n; u** = (rho u)**/rho^{n+1} and theta** = ((rho e_t)**/rho^{n+1}
+// - |u**|^2/2)/c_v into p1; the mass flux into the next state's face arrays.
 template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> st, StateV<S> nxt,
-                                                           S *rho1, S *m0, S *m1, S *m2, S *et2,
+                                                           DensPrim<S> p0, S *rho1, S *m0,
+                                                           S *m1, S *m2, DensPrim<S> p1,
                                                            const int *flags) {
+  using T = DTile<DIM, 2>;
+  constexpr int NV = DIM + 2;  // rho, u[DIM], theta
+  __shared__ S lv[NV * T::NP];
+  __shared__ S lf[NV * T::NFD];
   if (dens_skip(flags)) return;
-  S *mo[3] = {m0, m1, m2};
-  const S dt = S(g.dt);
-  {
-    int64_t c;
-    int i, j, k;
-    if (!dens_cell(g, c, i, j, k)) return;
-    const int ix[3] = {i, j, k};
-    S dF = S(0), dE = S(0), dM[3] = {S(0), S(0), S(0)};
+  int x0, y0, z0;
+  T::origin(g, blockIdx.x, x0, y0, z0);
+  // phase 1: primitives of the tile and its halo (up to two layers outside the box)
+  for (int p = threadIdx.x; p < T::NP; p += kThreads) {
+    const int li = p % T::SX - 2, lj = (p / T::SX) % T::SY - 2;
+    const int lk = DIM == 3 ? p / (T::SX * T::SY) - 2 : 0;
+    const int gi = x0 + li, gj = y0 + lj, gk = z0 + lk;
+    bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
+    if (DIM == 3) ok = ok && gk >= -2 && gk <= g.n[2] + 1;
+    if (!ok) continue;
+    S r, u[3], th;
+    load_rut<DIM>(g, p0, gi, gj, gk, r, u, th);
+    lv[p] = r;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      int hi[3] = {i, j, k};
-      hi[d] += 1;
-      S frl, fml[3], fel, frh, fmh[3], feh;
-      knp_face<DIM, S>(g, st, d, i, j, k, frl, fml, fel);
-      knp_face<DIM, S>(g, st, d, hi[0], hi[1], hi[2], frh, fmh, feh);
-      nxt.F[d][fidx(g, d, i, j, k)] = frl;
-      if (ix[d] == g.n[d] - 1) nxt.F[d][fidx(g, d, hi[0], hi[1], hi[2])] = frh;
-      const S ih = S(g.ih[d]);
-      dF += (frh - frl) * ih;
-      dE += (feh - fel) * ih;
-#pragma unroll
-      for (int q = 0; q < DIM; ++q) dM[q] += (fmh[q] - fml[q]) * ih;
-    }
-    const S r = st.rho[c];
-    S kn = S(0);
-#pragma unroll
-    for (int q = 0; q < DIM; ++q) kn += st.mom[q][c] * st.mom[q][c];
-    const S et = st.E[c] + S(0.5) * kn / r;
-    rho1[c] = r - dt * dF;
-#pragma unroll
-    for (int q = 0; q < DIM; ++q) mo[q][c] = st.mom[q][c] - dt * dM[q];
-    et2[c] = et - dt * dE;
+    for (int q = 0; q < DIM; ++q) lv[(1 + q) * T::NP + p] = u[q];
+    lv[(1 + DIM) * T::NP + p] = th;
   }
-}
-
-// u** and theta** at a (possibly ghost) cell of the intermediate state.
-template <int DIM, typename S>
-__device__ __forceinline__ void load_star(const GridK &g, const S *rho1, const S *const *m,
-                                          const S *et2, int i, int j, int k, S *u, S &th) {
-  Resolved rs = resolve<DIM>(g, i, j, k);
-  const S r = rho1[rs.c];
+  __syncthreads();
+  const int ci = threadIdx.x % T::TX, cj = (threadIdx.x / T::TX) % T::TY;
+  const int ck = DIM == 3 ? threadIdx.x / (T::TX * T::TY) : 0;
+  const int ix[3] = {x0 + ci, y0 + cj, z0 + ck};
+  const bool valid = ix[0] < g.n[0] && ix[1] < g.n[1] && (DIM == 2 || ix[2] < g.n[2]);
+  S acc[NV + 1];  // rho, m[DIM], e_t (the last unused)
+#pragma unroll
+  for (int v = 0; v < NV + 1; ++v) acc[v] = S(0);
+  const S dt = S(g.dt);
+  // phase 2: faces of one direction at a time
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2);
+    for (int f = threadIdx.x; f < FX * FY * FZ; f += kThreads) {
+      const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
+      const int fl[3] = {fi, fj, fk};
+      const int gf[3] = {x0 + fi, y0 + fj, z0 + fk};
+      bool ok = true;
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) ok = ok && gf[e] < g.n[e] + (e == d ? 1 : 0);
+      if (!ok) continue;
+      S r[4], u[4][3], th[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        int c3[3] = {fl[0], fl[1], fl[2]};
+        c3[d] += m - 2;
+        const int lp = T::pt(c3[0], c3[1], c3[2]);
+        r[m] = lv[lp];
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) u[m][q] = lv[(1 + q) * T::NP + lp];
+        th[m] = lv[(1 + DIM) * T::NP + lp];
+      }
+      S fr, fm[3], fe;
+      knp_flux<DIM, S>(g, d, r, u, th, fr, fm, fe);
+      lf[f] = fr;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) lf[(1 + q) * T::NFD + f] = fm[q];
+      lf[(1 + DIM) * T::NFD + f] = fe;
+      // the face belongs to this tile unless it is the next tile's first face
+      if (fl[d] < (d == 0 ? T::TX : d == 1 ? T::TY : T::TZ) || gf[d] == g.n[d])
+        nxt.F[d][fidx(g, d, gf[0], gf[1], gf[2])] = fr;
+    }
+    __syncthreads();
+    if (valid) {
+      const int step = d == 0 ? 1 : d == 1 ? FX : FX * FY;
+      const int lo = ci + FX * (cj + FY * ck), hi = lo + step;
+      const S ih = S(g.ih[d]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += (lf[v * T::NFD + hi] - lf[v * T::NFD + lo]) * ih;
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  // phase 3: the update of the cell
+  const int64_t c = cidx(g, ix[0], ix[1], ix[2]);
+  S *mo[3] = {m0, m1, m2};
+  const S r = st.rho[c];
+  S kn = S(0);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) kn += st.mom[q][c] * st.mom[q][c];
+  const S et = st.E[c] + S(0.5) * kn / r;
+  const S r1 = r - dt * acc[0];
+  rho1[c] = r1;
   S k2 = S(0);
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
-    u[q] = m[q][rs.c] / r;
-    k2 += u[q] * u[q];
+    const S mq = st.mom[q][c] - dt * acc[1 + q];
+    mo[q][c] = mq;
+    const S uq = mq / r1;  // u**
+    p1.v[q][c] = uq;
+    k2 += uq * uq;
   }
-  th = (et2[rs.c] / r - S(0.5) * k2) / S(g.cv);
+  p1.v[3][c] = ((et - dt * acc[1 + DIM]) / r1 - S(0.5) * k2) / S(g.cv);  // theta**
+}
+
+// u** and theta** at a (possibly ghost) cell of the intermediate state, from p1.
+template <int DIM, typename S>
+__device__ __forceinline__ void load_star(const GridK &g, const DensPrim<S> &p1, int i, int j,
+                                          int k, S *u, S &th) {
+  Resolved rs = resolve<DIM>(g, i, j, k);
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) u[q] = p1.v[q][rs.c];
+  th = p1.v[3][rs.c];
   if (any_side<DIM, S>(rs)) {
 #pragma unroll
     for (int q = 0; q < DIM; ++q) u[q] = ghosted<DIM>(g, rs, V_U0 + q, u[q]);
@@ -1401,109 +1487,128 @@ __device__ __forceinline__ void load_star(const GridK &g, const S *rho1, const S
   }
 }
 
-// Viscous stress and heat flux through the face of direction d between P and Q
-// (face index Q) from the intermediate state: tau_{d,q} with the normal
-// derivatives compact and the tangential ones the average of the two centred
-// cell gradients, mu_f the face average; lambda_f d theta / d n.
-template <int DIM, typename S>
-__device__ __forceinline__ void dens_visc_face(const GridK &g, const S *rho1, const S *const *m,
-                                               const S *et2, int d, int qi, int qj, int qk,
-                                               S *tau, S &qf) {
-  int P[3] = {qi, qj, qk}, Q[3] = {qi, qj, qk};
-  P[d] -= 1;
-  S uP[3], uQ[3], thP, thQ;
-  load_star<DIM>(g, rho1, m, et2, P[0], P[1], P[2], uP, thP);
-  load_star<DIM>(g, rho1, m, et2, Q[0], Q[1], Q[2], uQ, thQ);
-  const S muf = S(0.5) * (mu_of(g, thP) + mu_of(g, thQ));
-  const S ih = S(g.ih[d]);
-  S dn[3], tg[3] = {S(0), S(0), S(0)};
-#pragma unroll
-  for (int q = 0; q < DIM; ++q) dn[q] = (uQ[q] - uP[q]) * ih;
-  S divf = dn[d];
-#pragma unroll
-  for (int t = 0; t < DIM; ++t) {
-    if (t == d) continue;
-    const S hh = S(0.5 * g.ih[t]);
-    S up[3], um[3], thx;
-    int a[3] = {P[0], P[1], P[2]}, b[3] = {P[0], P[1], P[2]};
-    a[t] += 1;
-    b[t] -= 1;
-    load_star<DIM>(g, rho1, m, et2, a[0], a[1], a[2], up, thx);
-    load_star<DIM>(g, rho1, m, et2, b[0], b[1], b[2], um, thx);
-    S gdP = (up[d] - um[d]) * hh, gtP = (up[t] - um[t]) * hh;
-    int c2[3] = {Q[0], Q[1], Q[2]}, e2[3] = {Q[0], Q[1], Q[2]};
-    c2[t] += 1;
-    e2[t] -= 1;
-    load_star<DIM>(g, rho1, m, et2, c2[0], c2[1], c2[2], up, thx);
-    load_star<DIM>(g, rho1, m, et2, e2[0], e2[1], e2[2], um, thx);
-    S gdQ = (up[d] - um[d]) * hh, gtQ = (up[t] - um[t]) * hh;
-    tg[t] = S(0.5) * (gdP + gdQ);
-    divf += S(0.5) * (gtP + gtQ);
-  }
-#pragma unroll
-  for (int q = 0; q < DIM; ++q)
-    tau[q] = (q == d) ? muf * (S(2) * dn[d] - S(2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
-  qf = S(g.cp_Pr) * muf * (thQ - thP) * ih;
-}
-
 // Viscous and conductive part at (u**, theta**): (rho u)* = (rho u)** + dt div tau,
-// (rho e)* = rho^{n+1} c_v theta** + dt (div(lambda grad_n theta**) + Phi), Phi =
-// tau:grad u at the cell from centred gradients; into ms, E_s (the body's sources
-// are then added by the marker kernels).
+// (rho e)* = rho^{n+1} c_v theta** + dt (div(lambda grad_n theta**) + Phi). Face
+// stress tau_{d,q} with the normal derivatives compact and the tangential ones the
+// average of the two centred cell gradients, mu_f the face average; heat flux
+// lambda_f d theta / d n; Phi = tau:grad u at the cell from centred gradients.
+// Into ms, E_s (the body's sources are then added by the marker kernels).
 template <int DIM, typename S>
 __global__ __launch_bounds__(kThreads) void k_dens_viscous(GridK g, const S *rho1, const S *m0,
                                                           const S *m1, const S *m2,
-                                                          const S *et2, S *ms0, S *ms1,
+                                                          DensPrim<S> p1, S *ms0, S *ms1,
                                                           S *ms2, S *E_s, const int *flags) {
+  using T = DTile<DIM, 1>;
+  constexpr int NV = DIM + 2;  // u[DIM], theta, mu
+  __shared__ S lv[NV * T::NP];
+  __shared__ S lf[(DIM + 1) * T::NFD];
   if (dens_skip(flags)) return;
+  int x0, y0, z0;
+  T::origin(g, blockIdx.x, x0, y0, z0);
+  for (int p = threadIdx.x; p < T::NP; p += kThreads) {
+    const int li = p % T::SX - 1, lj = (p / T::SX) % T::SY - 1;
+    const int lk = DIM == 3 ? p / (T::SX * T::SY) - 1 : 0;
+    const int gi = x0 + li, gj = y0 + lj, gk = z0 + lk;
+    bool ok = gi >= -1 && gi <= g.n[0] && gj >= -1 && gj <= g.n[1];
+    if (DIM == 3) ok = ok && gk >= -1 && gk <= g.n[2];
+    if (!ok) continue;
+    S u[3], th;
+    load_star<DIM>(g, p1, gi, gj, gk, u, th);
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) lv[q * T::NP + p] = u[q];
+    lv[DIM * T::NP + p] = th;
+    lv[(DIM + 1) * T::NP + p] = mu_of(g, th);
+  }
+  __syncthreads();
+  const int ci = threadIdx.x % T::TX, cj = (threadIdx.x / T::TX) % T::TY;
+  const int ck = DIM == 3 ? threadIdx.x / (T::TX * T::TY) : 0;
+  const int ix[3] = {x0 + ci, y0 + cj, z0 + ck};
+  const bool valid = ix[0] < g.n[0] && ix[1] < g.n[1] && (DIM == 2 || ix[2] < g.n[2]);
+  auto U = [&](int q, int i, int j, int k) { return lv[q * T::NP + T::pt(i, j, k)]; };
+  S dT[3] = {S(0), S(0), S(0)}, dQ = S(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2);
+    for (int f = threadIdx.x; f < FX * FY * FZ; f += kThreads) {
+      const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
+      const int gf[3] = {x0 + fi, y0 + fj, z0 + fk};
+      bool ok = true;
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) ok = ok && gf[e] < g.n[e] + (e == d ? 1 : 0);
+      if (!ok) continue;
+      int P[3] = {fi, fj, fk};
+      const int Q[3] = {fi, fj, fk};
+      P[d] -= 1;
+      const S thP = U(DIM, P[0], P[1], P[2]), thQ = U(DIM, Q[0], Q[1], Q[2]);
+      const S muf = S(0.5) * (U(DIM + 1, P[0], P[1], P[2]) + U(DIM + 1, Q[0], Q[1], Q[2]));
+      const S ih = S(g.ih[d]);
+      S dn[3], tg[3] = {S(0), S(0), S(0)};
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) dn[q] = (U(q, Q[0], Q[1], Q[2]) - U(q, P[0], P[1], P[2])) * ih;
+      S divf = dn[d];
+#pragma unroll
+      for (int t = 0; t < DIM; ++t) {
+        if (t == d) continue;
+        const S hh = S(0.5 * g.ih[t]);
+        int a1[3] = {P[0], P[1], P[2]}, a0[3] = {P[0], P[1], P[2]};
+        int b1[3] = {Q[0], Q[1], Q[2]}, b0[3] = {Q[0], Q[1], Q[2]};
+        a1[t] += 1;
+        a0[t] -= 1;
+        b1[t] += 1;
+        b0[t] -= 1;
+        const S gdP = (U(d, a1[0], a1[1], a1[2]) - U(d, a0[0], a0[1], a0[2])) * hh;
+        const S gtP = (U(t, a1[0], a1[1], a1[2]) - U(t, a0[0], a0[1], a0[2])) * hh;
+        const S gdQ = (U(d, b1[0], b1[1], b1[2]) - U(d, b0[0], b0[1], b0[2])) * hh;
+        const S gtQ = (U(t, b1[0], b1[1], b1[2]) - U(t, b0[0], b0[1], b0[2])) * hh;
+        tg[t] = S(0.5) * (gdP + gdQ);
+        divf += S(0.5) * (gtP + gtQ);
+      }
+#pragma unroll
+      for (int q = 0; q < DIM; ++q)
+        lf[q * T::NFD + f] =
+            (q == d) ? muf * (S(2) * dn[d] - S(2.0 / 3.0) * divf) : muf * (dn[q] + tg[q]);
+      lf[DIM * T::NFD + f] = S(g.cp_Pr) * muf * (thQ - thP) * ih;
+    }
+    __syncthreads();
+    if (valid) {
+      const int step = d == 0 ? 1 : d == 1 ? FX : FX * FY;
+      const int lo = ci + FX * (cj + FY * ck), hi = lo + step;
+      const S ih = S(g.ih[d]);
+      dQ += (lf[DIM * T::NFD + hi] - lf[DIM * T::NFD + lo]) * ih;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) dT[q] += (lf[q * T::NFD + hi] - lf[q * T::NFD + lo]) * ih;
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  S gr[3][3];
+#pragma unroll
+  for (int b2 = 0; b2 < DIM; ++b2) {
+    int a1[3] = {ci, cj, ck}, a0[3] = {ci, cj, ck};
+    a1[b2] += 1;
+    a0[b2] -= 1;
+    const S hh = S(0.5 * g.ih[b2]);
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+      gr[a][b2] = (U(a, a1[0], a1[1], a1[2]) - U(a, a0[0], a0[1], a0[2])) * hh;
+  }
+  S divu = S(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) divu += gr[a][a];
+  S phi = S(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int b2 = 0; b2 < DIM; ++b2) phi += (gr[a][b2] + gr[b2][a]) * gr[a][b2];
+  const S thc = U(DIM, ci, cj, ck);
+  phi = U(DIM + 1, ci, cj, ck) * (phi - S(2.0 / 3.0) * divu * divu);
+  const int64_t c = cidx(g, ix[0], ix[1], ix[2]);
   const S *m[3] = {m0, m1, m2};
   S *ms[3] = {ms0, ms1, ms2};
   const S dt = S(g.dt);
-  {
-    int64_t c;
-    int i, j, k;
-    if (!dens_cell(g, c, i, j, k)) return;
-    S dT[3] = {S(0), S(0), S(0)}, dQ = S(0);
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      int hi[3] = {i, j, k};
-      hi[d] += 1;
-      S tl[3], th_[3], ql, qh;
-      dens_visc_face<DIM, S>(g, rho1, m, et2, d, i, j, k, tl, ql);
-      dens_visc_face<DIM, S>(g, rho1, m, et2, d, hi[0], hi[1], hi[2], th_, qh);
-      const S ih = S(g.ih[d]);
-      dQ += (qh - ql) * ih;
-#pragma unroll
-      for (int q = 0; q < DIM; ++q) dT[q] += (th_[q] - tl[q]) * ih;
-    }
-    S gr[3][3];
-#pragma unroll
-    for (int b = 0; b < DIM; ++b) {
-      int a1[3] = {i, j, k}, a0[3] = {i, j, k};
-      a1[b] += 1;
-      a0[b] -= 1;
-      S u1[3], u0[3], tx;
-      load_star<DIM>(g, rho1, m, et2, a1[0], a1[1], a1[2], u1, tx);
-      load_star<DIM>(g, rho1, m, et2, a0[0], a0[1], a0[2], u0, tx);
-      const S hh = S(0.5 * g.ih[b]);
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) gr[a][b] = (u1[a] - u0[a]) * hh;
-    }
-    S divu = S(0);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) divu += gr[a][a];
-    S phi = S(0);
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-      for (int b = 0; b < DIM; ++b) phi += (gr[a][b] + gr[b][a]) * gr[a][b];
-    S uc[3], thc;
-    load_star<DIM>(g, rho1, m, et2, i, j, k, uc, thc);
-    phi = mu_of(g, thc) * (phi - S(2.0 / 3.0) * divu * divu);
-#pragma unroll
-    for (int q = 0; q < DIM; ++q) ms[q][c] = m[q][c] + dt * dT[q];
-    E_s[c] = rho1[c] * S(g.cv) * thc + dt * (dQ + phi);
-  }
+  for (int q = 0; q < DIM; ++q) ms[q][c] = m[q][c] + dt * dT[q];
+  E_s[c] = rho1[c] * S(g.cv) * thc + dt * (dQ + phi);
 }
 
 // The new state from the sourced results (rho*, m**, E**): checked (positive,
@@ -2164,18 +2269,28 @@ void run_diff_finish(const Launch &L, const Bufs &B, int ring) {
   });
 }
 
+template <typename S>
+static DensPrim<S> dens_prim(void *const *a) {
+  DensPrim<S> p;
+  for (int v = 0; v < 5; ++v) p.v[v] = (S *)a[v];
+  return p;
+}
+
 void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
   IBM_DISPATCH(L, {
     const StateV<S> st = state_of<S>(B, cur), nx = state_of<S>(B, cur ^ 1);
+    const DensPrim<S> p0 = dens_prim<S>(B.dprim0), p1 = dens_prim<S>(B.dprim1);
     const unsigned nb = (unsigned)((L.g.N + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nb), dim3(kThreads), 0, L.st, L.g, st, nx,
-                       (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2],
-                       (S *)B.psi, (const int *)B.flags);
-    hipLaunchKernelGGL((k_dens_viscous<DIM, S>), dim3(nb), dim3(kThreads), 0, L.st, L.g,
-                       (const S *)B.rho_s,
-                       (const S *)B.mhat[0], (const S *)B.mhat[1], (const S *)B.mhat[2],
-                       (const S *)B.psi, (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2],
-                       (S *)B.E_s, (const int *)B.flags);
+    hipLaunchKernelGGL((k_dens_prim<DIM, S>), dim3(nb), dim3(kThreads), 0, L.st, L.g, st, p0,
+                       (const int *)B.flags);
+    const unsigned nt2 = (unsigned)DTile<DIM, 2>::tiles(L.g), nt1 = (unsigned)DTile<DIM, 1>::tiles(L.g);
+    hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nt2), dim3(kThreads), 0, L.st, L.g, st, nx,
+                       p0, (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], p1,
+                       (const int *)B.flags);
+    hipLaunchKernelGGL((k_dens_viscous<DIM, S>), dim3(nt1), dim3(kThreads), 0, L.st, L.g,
+                       (const S *)B.rho_s, (const S *)B.mhat[0], (const S *)B.mhat[1],
+                       (const S *)B.mhat[2], p1, (S *)B.mom_s[0], (S *)B.mom_s[1],
+                       (S *)B.mom_s[2], (S *)B.E_s, (const int *)B.flags);
   });
 }
 

@@ -83,6 +83,9 @@ struct Bufs {
   double *dr[2][kDiffVars], *dw[2][kDiffVars], *ds[2][kDiffVars], *dp[kDiffVars];
   double *dpart;
   DiffScal *dsc;
+  // density-based step: primitives rho, u[3], theta of the state (dprim0) and
+  // u**[3], theta** of the intermediate state (dprim1), state type [N] each
+  void *dprim0[5], *dprim1[5];
 };
 
 // Kernel view of the diffusion systems' buffers.
@@ -149,10 +152,11 @@ void run_diff_start(const Launch &L, const Bufs &B, int cur, int ring, int order
 void run_diff_iteration(const Launch &L, const Bufs &B, int ring, int it);
 void run_diff_finish(const Launch &L, const Bufs &B, int ring);
 void run_mass(const Launch &L, const Bufs &B);
-// density-based step (App. B): the central-upwind inviscid part from state `cur`
-// (rho^{n+1} into rho_s, (rho u)** into mhat, (rho e_t)** into psi, the mass flux
-// into the other slot's faces), then the explicit viscous part into mom_s, E_s;
-// after the marker sources, the finish writes the other state slot
+// density-based step (App. B): the primitives of state `cur`, the central-upwind
+// inviscid part (rho^{n+1} into rho_s, (rho u)** into mhat, u** and theta** into
+// dprim1, the mass flux into the other slot's faces), then the explicit viscous
+// part into mom_s, E_s; after the marker sources, the finish writes the other
+// state slot
 void run_density_predictor(const Launch &L, const Bufs &B, int cur);
 void run_density_finish(const Launch &L, const Bufs &B, int cur, int tag);
 int64_t cell_blocks(const GridK &g);

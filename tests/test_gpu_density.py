@@ -148,3 +148,26 @@ def test_density_rejections(cuda):
     with pytest.raises(_lib.IBMError):
         s.step(1, record=True)
     s.step(1)
+
+
+def test_full_size_density_cylinder_1024_parity(cuda):
+    # the bench's density-based 1024^2 workload at its full size
+    c = inputs.case("cfg2a", Ma=0.8, scheme=DENS)
+    g, o = make_gpu(c), make_oracle(c)
+    hg, _ = g.step(3)
+    ho = o.step(3)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-12, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
+
+
+@pytest.mark.slow
+def test_full_size_density_sphere_256_parity(cuda):
+    # 256^3 cells, 3200 candidate markers, Ma 0.8: one step
+    c = inputs.case("cfg3", Ma=0.8, scheme=DENS)
+    g, o = make_gpu(c), make_oracle(c)
+    hg, _ = g.step(1)
+    ho = o.step(1)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-12, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9

@@ -170,3 +170,14 @@ def test_implicit_start_does_not_change_the_solution(cuda, monkeypatch):
     for x, y in zip(a[:3], b[:3]):
         assert rel_l2(to_np(y), to_np(x)) < 1e-11
     assert ib < ia
+
+
+def test_full_size_implicit_cylinder_1024_parity(cuda):
+    # the benchmark workload at its full size with the implicit terms
+    c = inputs.case("cfg2a", diffusion=IMP)
+    g, o = make_gpu(c), make_oracle(c)
+    hg, _ = g.step(2)
+    ho = o.step(2)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-11, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9

@@ -122,3 +122,14 @@ def test_outer_passes_have_no_adjoint(cuda):
     Twb = torch.zeros(s.nc, dtype=torch.float64, device=s.device)
     with pytest.raises(_lib.IBMError):
         s.adjoint_step(1, sb, sb2, np.zeros(4), Twb)
+
+
+def test_full_size_outer_passes_cylinder_1024_parity(cuda):
+    # the benchmark workload at its full size, three passes at CFL 0.25 (as the bench)
+    c = inputs.case("cfg2a", n_outer=3, cfl=0.25)
+    g, o = make_gpu(c), make_oracle(c)
+    hg, _ = g.step(2)
+    ho = o.step(2)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-11, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9

@@ -76,7 +76,8 @@ KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
                 ("k_totals", "markers"), ("k_markers_fused", "markers"),
                 ("k_dsys", "diffusion"), ("k_diff_coef", "diffusion"),
-                ("k_dens_inviscid", "predictor"), ("k_dens_viscous", "predictor"),
+                ("k_dens_prim", "predictor"), ("k_dens_inviscid", "predictor"),
+                ("k_dens_viscous", "predictor"),
                 ("k_dens_finish", "correct")]
 
 

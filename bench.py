@@ -153,7 +153,7 @@ def make_solver(case, precision, tape_steps=0):
     rho, u, th = inputs.initial_fields(case)
     s.init_primitive(rho, u, th)
     X, Ud, Tw, dA = inputs.markers(case)
-    s.set_markers(X, Ud, Tw, dA, dedupe=True)
+    s.set_markers(X, Ud, Tw, dA, dedupe=True, no_heat=bool(case.get("no_heat", False)))
     if case.get("motion"):
         m = case["motion"]
         s.set_motion(m["axis"], m["amp"], m["freq"])
@@ -403,6 +403,45 @@ def run_density(steps: int, warmup: int):
     return res
 
 
+def run_grid_convergence(t_end: float = 40.0, t_avg: float = 10.0):
+    """The grid-convergence study of App. C: the cylinder at Ma 2.5, Re 250 without
+    heat exchange on h = D/10, D/15, D/25, D/50 (28, 39, 62, 104 markers), the
+    density-based step from an impulsive start to t_end; C_D = 2 F_x / (rho U^2 D)
+    averaged over the last t_avg; errors against the finest grid and the order of
+    their least-squares fit in log h."""
+    import numpy as np
+    import torch
+    from paper_2301_09349_amd import inputs
+
+    res, cd = {"t_end": t_end, "t_average": t_avg, "grids": {}}, {}
+    for r in (10, 15, 25, 50):
+        case = inputs.case("sup%d" % r)
+        s = make_solver(case, "fp64")
+        steps = int(round(t_end / s.dt))
+        navg = int(round(t_avg / s.dt))
+        hist = torch.zeros((steps, 4), dtype=torch.float64, device="cuda:0")
+        log(f"bench: grid convergence D/{r}: {case['n']}, {steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, hist_out=hist)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        h = hist.cpu().numpy()
+        cd[r] = float(2.0 * h[-navg:, 0].mean())
+        res["grids"]["D/%d" % r] = {"cells": int(np.prod(case["n"][:2])),
+                                    "markers_kept": int(s.markers_in_use()[0].shape[0]),
+                                    "dt": s.dt, "steps": steps, "C_D": round(cd[r], 6),
+                                    "ms_per_step": round(1e3 * el / steps, 4)}
+        del s
+    coarse = (10, 15, 25)
+    err = [abs(cd[r] - cd[50]) for r in coarse]
+    res["error_vs_finest"] = {"D/%d" % r: float("%.4g" % e) for r, e in zip(coarse, err)}
+    if all(e > 0 for e in err):
+        res["observed_order"] = round(float(np.polyfit(np.log([1.0 / r for r in coarse]),
+                                                       np.log(err), 1)[0]), 3)
+    return res
+
+
 def calibrate_copy():
     """A plain streaming kernel of known size for scaling the HBM counters: negation
     of CALIB_ELEMS float64 values (8 B read + 8 B written each), three launches."""
@@ -572,6 +611,8 @@ def main():
                     help="step of the main workload (profiling; density: at Ma 0.8)")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the density-based figures")
+    ap.add_argument("--no-convergence", action="store_true",
+                    help="skip the grid-convergence study of App. C")
     ap.add_argument("--no-moving", action="store_true",
                     help="skip the oscillating-cylinder figures")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -671,6 +712,10 @@ def main():
     if not args.no_density:
         log("bench: density-based step ...")
         out["density_based"] = run_density(args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if not args.no_convergence:
+        log("bench: grid convergence (App. C) ...")
+        out["grid_convergence"] = run_grid_convergence()
         torch.cuda.empty_cache()
     if not args.no_3d and args.workload != "cfg3":
         log("bench: 256^3 sphere ...")

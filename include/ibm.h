@@ -64,8 +64,12 @@ typedef enum {
  *   INFLOW    u = U_inf and theta = 1 on the face; rho, p zero gradient;
  *             face mass flux rho_P U_inf (rho at the start of the step)
  *   OUTFLOW   zero gradient; p = p_inf on the face
- *   SLIP      no normal velocity, no normal gradient of anything else          */
-enum { IBM_PERIODIC = 0, IBM_INFLOW = 1, IBM_OUTFLOW = 2, IBM_SLIP = 3 };
+ *   SLIP      no normal velocity, no normal gradient of anything else
+ *   SUPERSONIC_INFLOW   rho = 1, u = U_inf, theta = 1 on the face
+ *   SUPERSONIC_OUTFLOW  zero gradient of every variable
+ * (the two supersonic sides with IBM_SCHEME_DENSITY only)                      */
+enum { IBM_PERIODIC = 0, IBM_INFLOW = 1, IBM_OUTFLOW = 2, IBM_SLIP = 3,
+       IBM_SUPERSONIC_INFLOW = 4, IBM_SUPERSONIC_OUTFLOW = 5 };
 enum { IBM_FP64 = 0, IBM_FP32 = 1 };
 /* convected face values: van Leer limited (Sec. 2.2.2) or linear */
 enum { IBM_CONV_VANLEER = 0, IBM_CONV_LINEAR = 1 };
@@ -101,6 +105,9 @@ enum { IBM_SCHEME_PRESSURE = 0, IBM_SCHEME_DENSITY = 1 };
  * markers that fall in one cell only the one nearest to its centre is used,
  * ties to the lower id), at set-up and after every motion update. */
 #define IBM_DEDUPE 1u
+/* ibm_set_markers flags: markers without heat exchange (the energy source q of
+ * Eq. (17) is zero; the wall temperatures are not used). Not with the adjoint. */
+#define IBM_NO_HEAT 2u
 /* ibm_step flags: record each step of the call on the tape for the adjoint */
 #define IBM_RECORD 1u
 
@@ -197,7 +204,7 @@ ibm_status ibm_get_state(const ibm_ctx *ctx, void *rho, void *mom, void *eint, v
  * desired velocities U_d [n][dim] (NULL: at rest), wall temperatures T_w [n]
  * (theta_wall / theta_inf) and surface elements dA [n] (NULL: zero); all device
  * double arrays, copied. With IBM_DEDUPE the check routine of Sec. 3.1 selects
- * the markers in use. Builds the supports (the 3 nearest cells per direction),
+ * the markers in use; with IBM_NO_HEAT the markers exchange no heat. Builds the supports (the 3 nearest cells per direction),
  * sorts the (cell, marker) pairs, and solves A eps = 1 (Eqs. (8)-(9)) in FP64.
  * IBM_E_ARG if a support leaves a non-periodic box; IBM_E_SIZE if n exceeds the
  * capacity; IBM_E_NOT_CONVERGED if the eps solve fails. */

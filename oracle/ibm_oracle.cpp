@@ -93,7 +93,7 @@ struct Desc {
   int32_t scheme;     // 0: pressure-based (App. A); 1: density-based (App. B)
 };
 
-enum { PERIODIC = 0, INFLOW = 1, OUTFLOW = 2, SLIP = 3 };
+enum { PERIODIC = 0, INFLOW = 1, OUTFLOW = 2, SLIP = 3, SUP_INFLOW = 4, SUP_OUTFLOW = 5 };
 enum { CONV_VANLEER = 0, CONV_LINEAR = 1 };
 enum { MU_SUTHERLAND = 0, MU_CONSTANT = 1 };
 // primitive variables, used to pick the ghost rule of an array
@@ -133,6 +133,7 @@ struct Solver {
   // candidate markers as given, and the subset in use (Sec. 3.1 check routine)
   int nc = 0;
   bool dedupe = false;
+  bool no_heat = false;  // markers without heat exchange: the energy source q is zero
   std::vector<T> cX0;  // candidate positions (dual numbers carry their derivatives)
   std::vector<double> cUd0, cdA;
   std::vector<T> cTw;
@@ -173,6 +174,9 @@ struct Solver {
     for (int a = 0; a < dim; ++a) {
       if ((d.bc[a][0] == PERIODIC) != (d.bc[a][1] == PERIODIC)) return 1;
       if (n[a] < 3) return 1;
+      // the supersonic sides serve the density-based step only
+      for (int sd = 0; sd < 2; ++sd)
+        if (d.bc[a][sd] >= SUP_INFLOW && d.scheme != 1) return 1;
     }
     for (int a = 0; a < dim; ++a) {
       NF[a] = 1;
@@ -253,6 +257,15 @@ struct Solver {
         return v;
       case SLIP:  // no normal velocity, everything else mirrored
         if (var == V_U0 + d) return -v;
+        return v;
+      case SUP_INFLOW:  // supersonic inflow: the free stream on the face
+        if (var >= V_U0 && var <= V_U2) return 2.0 * D.U_inf[var - V_U0] - v;
+        if (var == V_TH || var == V_RHO) return 2.0 - v;
+        if (var == V_E) return 2.0 * cv - v;
+        if (var == V_P) return 2.0 * p_inf - v;
+        if (var == V_PHOM) return -v;
+        return v;
+      case SUP_OUTFLOW:  // supersonic outflow: every variable extrapolated
         return v;
     }
     return v;
@@ -652,6 +665,7 @@ struct Solver {
                   const double *dAin, int flags) {
     nc = nm;
     dedupe = (flags & 1) != 0;
+    no_heat = (flags & 2) != 0;
     cX0.assign(size_t(nc) * 3, T(0.0));
     cUd0.assign(size_t(nc) * 3, 0.0);
     cTw.assign(nc, T(1.0));
@@ -705,7 +719,7 @@ struct Solver {
         Fk[size_t(k) * 3 + q] = (rhoL[k] * Ud[size_t(k) * 3 + q] - ML[size_t(k) * 3 + q]) / dt;
       // Eq. (17) with a_e = 1/dt: c_v((rho_L Theta)^d - (rho_L Theta)^l), the neutral
       // value being the interpolated internal energy of the predictor
-      Qk[k] = (cv * rhoL[k] * Tw[k] - EL[k]) / dt;
+      Qk[k] = no_heat ? T(0.0) : (cv * rhoL[k] * Tw[k] - EL[k]) / dt;
     }
     spread_sources();
     // Sec. 3.1: force on the body = minus the force the markers put on the fluid
@@ -1147,6 +1161,7 @@ struct Solver {
     step = o.step;
     nc = o.nc;
     dedupe = o.dedupe;
+    no_heat = o.no_heat;
     auto values = [](const auto &src, std::vector<T> &dst) {
       dst.resize(src.size());
       for (size_t i = 0; i < src.size(); ++i) dst[i] = T(val(src[i]));

@@ -17,6 +17,7 @@ SRC = os.path.join(HERE, "ibm_oracle.cpp")
 LIB = os.path.join(HERE, "libibm_oracle.so")
 
 PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
+SUP_INFLOW, SUP_OUTFLOW = 4, 5
 CONV_VANLEER, CONV_LINEAR = 0, 1
 MU_SUTHERLAND, MU_CONSTANT = 0, 1
 
@@ -159,15 +160,17 @@ class Oracle:
     def mu(self, theta: float) -> float:
         return lib().orc_mu(self.h, float(theta))
 
-    def set_markers(self, X, Ud=None, Tw=None, dA=None, dedupe=False):
+    def set_markers(self, X, Ud=None, Tw=None, dA=None, dedupe=False, no_heat=False):
         """Candidate markers; with ``dedupe`` only the one nearest to the centre of
-        each cell is used (the check routine of Sec. 3.1)."""
+        each cell is used (the check routine of Sec. 3.1); with ``no_heat`` the
+        markers exchange no heat (their energy source is zero)."""
         X = np.ascontiguousarray(X, dtype=np.float64)
         ns = X.shape[0]
         Ud = np.zeros_like(X) if Ud is None else np.ascontiguousarray(Ud, dtype=np.float64)
         Tw = np.ones(ns) if Tw is None else np.ascontiguousarray(Tw, dtype=np.float64)
         dA = np.zeros(ns) if dA is None else np.ascontiguousarray(dA, dtype=np.float64)
-        rc = lib().orc_set_markers(self.h, ns, _p(X), _p(Ud), _p(Tw), _p(dA), 1 if dedupe else 0)
+        rc = lib().orc_set_markers(self.h, ns, _p(X), _p(Ud), _p(Tw), _p(dA),
+                                   (1 if dedupe else 0) | (2 if no_heat else 0))
         if rc:
             raise ValueError(f"oracle: set_markers failed ({rc})")
         self.nc = ns

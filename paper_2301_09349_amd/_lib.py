@@ -14,12 +14,14 @@ IBM_OK, IBM_E_ARG, IBM_E_SIZE, IBM_E_HIP, IBM_E_NOT_CONVERGED, IBM_E_NONFINITE, 
 STATUS_NAMES = {0: "IBM_OK", 1: "IBM_E_ARG", 2: "IBM_E_SIZE", 3: "IBM_E_HIP",
                 4: "IBM_E_NOT_CONVERGED", 5: "IBM_E_NONFINITE", 6: "IBM_E_STATE"}
 IBM_PERIODIC, IBM_INFLOW, IBM_OUTFLOW, IBM_SLIP = 0, 1, 2, 3
+IBM_SUPERSONIC_INFLOW, IBM_SUPERSONIC_OUTFLOW = 4, 5
 IBM_FP64, IBM_FP32 = 0, 1
 IBM_CONV_VANLEER, IBM_CONV_LINEAR = 0, 1
 IBM_MU_SUTHERLAND, IBM_MU_CONSTANT = 0, 1
 IBM_DIFF_EXPLICIT, IBM_DIFF_IMPLICIT = 0, 1
 IBM_SCHEME_PRESSURE, IBM_SCHEME_DENSITY = 0, 1
 IBM_DEDUPE = 1
+IBM_NO_HEAT = 2
 IBM_RECORD = 1
 
 # every function the header declares, with (restype, argtypes)

@@ -145,7 +145,8 @@ const char *check_desc(const ibm_grid_desc *d) {
     if (d->n[a] < 3) return "each n[d] must be >= 3";
     if (!(d->hi[a] > d->lo[a])) return "hi must exceed lo";
     for (int s = 0; s < 2; ++s)
-      if (d->bc[a][s] < IBM_PERIODIC || d->bc[a][s] > IBM_SLIP) return "unknown boundary type";
+      if (d->bc[a][s] < IBM_PERIODIC || d->bc[a][s] > IBM_SUPERSONIC_OUTFLOW)
+        return "unknown boundary type";
     if ((d->bc[a][0] == IBM_PERIODIC) != (d->bc[a][1] == IBM_PERIODIC))
       return "periodic must be set on both sides";
   }
@@ -159,6 +160,10 @@ const char *check_desc(const ibm_grid_desc *d) {
     return "unknown diffusion treatment";
   if (d->n_outer < 0 || d->n_outer > 64) return "n_outer must be in 0..64";
   if (d->scheme != IBM_SCHEME_PRESSURE && d->scheme != IBM_SCHEME_DENSITY) return "unknown scheme";
+  for (int a = 0; a < d->dim; ++a)
+    for (int s = 0; s < 2; ++s)
+      if (d->bc[a][s] >= IBM_SUPERSONIC_INFLOW && d->scheme != IBM_SCHEME_DENSITY)
+        return "supersonic sides need the density-based step";
   if (d->scheme == IBM_SCHEME_DENSITY && (d->diffusion != IBM_DIFF_EXPLICIT || d->n_outer > 1))
     return "the density-based step takes explicit diffusion and one pass";
   if (!(d->Re > 0) || !(d->Ma > 0) || !(d->Pr > 0) || !(d->gamma > 1.0))
@@ -787,7 +792,7 @@ ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const doubl
   if (!ctx) return IBM_E_ARG;
   if (n < 0) return fail(ctx, IBM_E_ARG, "set_markers: n < 0");
   if (n > ctx->desc.max_markers) return fail(ctx, IBM_E_SIZE, "set_markers: n exceeds max_markers");
-  if (flags & ~IBM_DEDUPE) return fail(ctx, IBM_E_ARG, "set_markers: unknown flag");
+  if (flags & ~(IBM_DEDUPE | IBM_NO_HEAT)) return fail(ctx, IBM_E_ARG, "set_markers: unknown flag");
   if (n > 0 && !X) return fail(ctx, IBM_E_ARG, "set_markers: X is NULL");
   const int dim = ctx->desc.dim;
   hipStream_t st = ctx->L.st;
@@ -819,6 +824,7 @@ ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const doubl
   HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
   ctx->nc = n;
   ctx->dedupe = (flags & IBM_DEDUPE) ? 1 : 0;
+  ctx->L.g.no_heat = (flags & IBM_NO_HEAT) ? 1 : 0;
   ibm_status s = rebuild_markers(ctx, double(ctx->step) * ctx->L.g.dt);
   if (s) {
     ctx->nc = 0;
@@ -1233,6 +1239,8 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     return fail(ctx, IBM_E_ARG, "adjoint_step: outer passes have no adjoint");
   if (ctx->desc.scheme == IBM_SCHEME_DENSITY)
     return fail(ctx, IBM_E_ARG, "adjoint_step: the density-based step has no adjoint");
+  if (ctx->L.g.no_heat)
+    return fail(ctx, IBM_E_ARG, "adjoint_step: markers without heat exchange have no adjoint");
   if (!state_bar_in || !state_bar_out) return fail(ctx, IBM_E_ARG, "adjoint_step: NULL cotangent");
   if (state_bar_in == state_bar_out)
     return fail(ctx, IBM_E_ARG, "adjoint_step: state_bar_in and state_bar_out must differ");

@@ -9,7 +9,8 @@
 
 namespace ibmk {
 
-constexpr int BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_SLIP = 3;
+constexpr int BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_SLIP = 3, BC_SUP_IN = 4,
+              BC_SUP_OUT = 5;
 constexpr int CONV_VANLEER = 0, CONV_LINEAR = 1;
 constexpr int MU_SUTHERLAND = 0, MU_CONSTANT = 1;
 // kinds of cell variables, selecting the ghost rule of a boundary side
@@ -46,6 +47,7 @@ struct GridK {
   int bc[3][2];
   int conv, visc;
   int implicit_diff;  // 1: compact viscous and conductive fluxes by backward Euler
+  int no_heat;        // 1: markers without heat exchange (energy source zero)
   double dt, R, cv, inv_cv, cp, gm1, mu_inf, S, Pr, p_inf, dV;
   double cp_Pr;       // c_p / Pr: lambda = cp_Pr mu
   double U_inf[3];
@@ -213,7 +215,14 @@ __device__ __forceinline__ T side_rule(const GridK &g, int bc, int var, int d, T
     if (var == V_U0 + d) return -v;
     return v;
   }
-  return v;
+  if (bc == BC_SUP_IN) {  // the free stream on the face
+    if (var >= V_U0 && var < V_U0 + 3) return T(2.0 * g.U_inf[var - V_U0]) - v;
+    if (var == V_TH || var == V_RHO) return T(2.0) - v;
+    if (var == V_P) return T(2.0 * g.p_inf) - v;
+    if (var == V_PHOM) return -v;
+    return v;
+  }
+  return v;  // BC_SUP_OUT: every variable extrapolated
 }
 
 // Applies the rules of all sides crossed, the last direction first (x outermost).

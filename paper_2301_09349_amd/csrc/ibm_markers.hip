@@ -607,7 +607,7 @@ __device__ __forceinline__ void interp_force_one(const GridK &g, int k, const in
     }
     mforce[3 * k + q] = -(g.dV * (e * F));
   }
-  const double Q = (g.cv * rl * Tw[k] - el) / g.dt;
+  const double Q = g.no_heat ? 0.0 : (g.cv * rl * Tw[k] - el) / g.dt;
   o[2 + 2 * dim] = Q;
   mheat[k] = g.dV * (e * Q);
 }

@@ -16,6 +16,7 @@ import math
 import numpy as np
 
 PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
+SUP_INFLOW, SUP_OUTFLOW = 4, 5  # supersonic sides (density-based step only)
 CONV_VANLEER, CONV_LINEAR = 0, 1
 MU_SUTHERLAND, MU_CONSTANT = 0, 1
 DIFF_EXPLICIT, DIFF_IMPLICIT = 0, 1
@@ -115,6 +116,11 @@ def case(name: str, **over):
           x = 0.14 D sin(2 pi f_c t) with f_c = 2 f_0, f_0 = St U / D the fixed
           cylinder's shedding frequency (St = 0.165 at Re 100), 512^2 as cfg4,
           200 markers, Re 100, Ma 0.3, Tw / Tinf = 1 (osc1) or 2 (osc2)
+    sup10, sup15, sup25, sup50
+          the grid-convergence case of App. C: 2D cylinder at Ma 2.5, Re 250,
+          markers without heat exchange, h = D/10, D/15, D/25, D/50 over
+          [-4,12]x[-8,8] with 28, 39, 62, 104 markers; density-based step,
+          supersonic inflow at x_lo, supersonic outflow on the other sides
     """
     base = dict(Pr=0.71, gamma=1.4, sutherland_S=SUTHERLAND_AIR, U_inf=(1.0, 0.0, 0.0),
                 convection=CONV_VANLEER, viscosity_law=MU_SUTHERLAND, cfl=0.5, dt=0.0,
@@ -141,15 +147,26 @@ def case(name: str, **over):
                  Tw=1.0 if name == "osc1" else 2.0, ns=200, seed=6, steps=4000,
                  motion=dict(axis=0, amp=amp, freq=freq),
                  dt_u_max=2.0 * math.pi * freq * amp)
+    elif name in ("sup10", "sup15", "sup25", "sup50"):
+        res = int(name[3:])
+        c = dict(dim=2, n=(16 * res, 16 * res), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=250.0,
+                 Ma=2.5, Tw=1.0, ns={10: 28, 15: 39, 25: 62, 50: 104}[res], seed=7,
+                 steps=4000, scheme=SCHEME_DENSITY, no_heat=True,
+                 bc=[[SUP_INFLOW, SUP_OUTFLOW], [SUP_OUTFLOW, SUP_OUTFLOW]])
     elif name == "cfg5":
         c = dict(dim=2, n=(512, 512), lo=(-4.0, -8.0), hi=(12.0, 8.0), Re=100.0, Ma=0.2,
                  Tw=1.3, ns=200, seed=5, steps=500, checkpoint=50)
     else:
         raise KeyError(name)
     base.update(c)
-    base["bc"] = _bc_channel(base["dim"])
+    if "bc" not in c:
+        base["bc"] = _bc_channel(base["dim"])
     base.update(over)
     base["dt_theta_max"] = max(1.0, float(base["Tw"]))
+    if base.get("no_heat"):
+        # no wall temperature: the largest temperature is the stagnation one
+        base["dt_theta_max"] = max(base["dt_theta_max"],
+                                   1.0 + 0.5 * (base["gamma"] - 1.0) * base["Ma"] ** 2)
     if "dt_theta_max_override" in over:
         base["dt_theta_max"] = over["dt_theta_max_override"]
     return base

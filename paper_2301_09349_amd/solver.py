@@ -140,13 +140,14 @@ class IBMSolver:
         return r, m.reshape(self.dim, self.N), e, Fs
 
     # ---------------------------------------------------------------- markers
-    def set_markers(self, X, Ud=None, Tw=None, dA=None, dedupe: bool = True):
+    def set_markers(self, X, Ud=None, Tw=None, dA=None, dedupe: bool = True,
+                    no_heat: bool = False):
         X = self._dev(X, torch.float64).reshape(-1, self.dim)
         n = X.shape[0]
         Ud = None if Ud is None else self._dev(Ud, torch.float64).reshape(n, self.dim)
         Tw = None if Tw is None else self._dev(Tw, torch.float64).reshape(n)
         dA = None if dA is None else self._dev(dA, torch.float64).reshape(n)
-        flags = L.IBM_DEDUPE if dedupe else 0
+        flags = (L.IBM_DEDUPE if dedupe else 0) | (L.IBM_NO_HEAT if no_heat else 0)
         st = self.lib.ibm_set_markers(self.ctx, n, _ptr(X), _ptr(Ud), _ptr(Tw), _ptr(dA), flags)
         L.check(st, self.ctx, "ibm_set_markers")
         self.nc = n

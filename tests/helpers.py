@@ -27,7 +27,8 @@ def make_oracle(c, markers=True, amplitude=1e-3):
     o.init_primitive(rho, u, th)
     if markers and c.get("ns", 0):
         X, Ud, Tw, dA = inputs.markers(c)
-        o.set_markers(X, Ud, Tw, dA, dedupe=c.get("dedupe", True))
+        o.set_markers(X, Ud, Tw, dA, dedupe=c.get("dedupe", True),
+                      no_heat=bool(c.get("no_heat", False)))
         if c.get("motion"):
             m = c["motion"]
             o.set_motion(m["axis"], m["amp"], m["freq"])
@@ -42,7 +43,8 @@ def make_gpu(c, precision="fp64", markers=True, amplitude=1e-3, tape_steps=0):
     s.init_primitive(rho, u, th)
     if markers and c.get("ns", 0):
         X, Ud, Tw, dA = inputs.markers(c)
-        s.set_markers(X, Ud, Tw, dA, dedupe=c.get("dedupe", True))
+        s.set_markers(X, Ud, Tw, dA, dedupe=c.get("dedupe", True),
+                      no_heat=bool(c.get("no_heat", False)))
         if c.get("motion"):
             m = c["motion"]
             s.set_motion(m["axis"], m["amp"], m["freq"])

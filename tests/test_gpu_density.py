@@ -171,3 +171,26 @@ def test_full_size_density_sphere_256_parity(cuda):
     for k, v in state_errors(g, o).items():
         assert v < 1e-12, (k, v)
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
+
+
+def test_supersonic_cylinder_parity(cuda):
+    # the grid-convergence case of App. C on its coarsest grid: Ma 2.5, Re 250,
+    # markers without heat exchange, supersonic inflow and outflow sides
+    c = inputs.case("sup10")
+    g, o = make_gpu(c), make_oracle(c)
+    assert g.dt == o.dt
+    hg, _ = g.step(60)
+    ho = o.step(60)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-11, (k, v)
+    hg = to_np(hg)
+    assert rel_l2(hg[:, :3], ho[:, :3]) < 1e-9
+    assert np.all(hg[:, 3] == 0.0)
+
+
+def test_supersonic_sides_rejected_with_the_pressure_based_step(cuda):
+    from paper_2301_09349_amd.solver import IBMSolver
+
+    c = inputs.scaled("sup10", (48, 40), ns=0, scheme=inputs.SCHEME_PRESSURE)
+    with pytest.raises(_lib.IBMError):
+        IBMSolver(c, "fp64", max_markers=1)

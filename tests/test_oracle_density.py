@@ -200,3 +200,35 @@ def test_isolated_marker_reaches_its_targets():
     for q in range(2):
         assert o.interp(m[q])[0] == pytest.approx(rho_L * Ud[0, q], abs=1e-13)
     assert o.interp(E)[0] == pytest.approx(cv * rho_L * Tw[0], rel=1e-14)
+
+
+def test_supersonic_sides_keep_a_uniform_stream():
+    # Ma 2.5 through supersonic inflow and outflow sides stays uniform
+    c = inputs.scaled("sup10", (48, 40), ns=0)
+    o = Oracle(c)
+    rho, u, th = inputs.initial_fields(c, amplitude=0.0)
+    o.init_primitive(rho, u, th)
+    x0 = np.concatenate([np.ravel(v) for v in o.get_state()[:3]])
+    o.step(20)
+    x1 = np.concatenate([np.ravel(v) for v in o.get_state()[:3]])
+    assert np.max(np.abs(x1 - x0)) <= 1e-13 * np.max(np.abs(x0))
+
+
+def test_supersonic_sides_need_the_density_based_step():
+    c = inputs.scaled("sup10", (48, 40), ns=0, scheme=inputs.SCHEME_PRESSURE)
+    with pytest.raises(ValueError):
+        Oracle(c)
+
+
+def test_markers_without_heat_exchange():
+    # the energy source is zero: E** = E* and the heat total is zero, while the
+    # momentum forcing acts as usual
+    c = inputs.scaled("sup10", (64, 64), ns=28)
+    from helpers import make_oracle
+
+    o = make_oracle(c)
+    h = o.step(3)
+    assert np.all(h[:, 3] == 0.0)
+    assert np.array_equal(o.intermediate("E_ss"), o.intermediate("E_s"))
+    assert np.abs(h[:, 0]).min() > 0.0
+    assert not np.array_equal(o.intermediate("mom_ss"), o.intermediate("mom_s"))

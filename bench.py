@@ -353,6 +353,18 @@ def run_implicit(case, steps: int, warmup: int, explicit: dict):
         ent["sim_time_speedup"] = round(ent["sim_time_per_s"] / ent["sim_time_per_s_explicit"], 3)
         res[prec] = ent
         del r
+    # the same grid at Re 20, where conduction limits the explicit step far more
+    low = dict(case, Re=20.0)
+    re_ = run_forward(low, "fp64", steps, warmup)
+    ri = run_forward(dict(low, diffusion=1), "fp64", steps, warmup)
+    dt_e, ms_e = re_["solver"].dt, re_["ms_per_step"]
+    dt_i, ms_i = ri["solver"].dt, ri["ms_per_step"]
+    res["fp64_re20"] = {"ms_per_step": round(ms_i, 4), "ms_per_step_explicit": round(ms_e, 4),
+                        "dt": dt_i, "dt_explicit": dt_e, "dt_ratio": round(dt_i / dt_e, 3),
+                        "diffusion_iters_per_step": round(ri["info"]["diff_iters_total"] / steps, 2),
+                        "cg_iters_per_step": round(ri["info"]["cg_iters_total"] / steps, 2),
+                        "sim_time_speedup": round((dt_i / ms_i) / (dt_e / ms_e), 3)}
+    del re_, ri
     return res
 
 

@@ -167,10 +167,11 @@ size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32
  * The state starts as the uniform stream rho = 1, theta = 1, u = U_inf.
  * Environment, read here: IBM_PREDICTOR=plain selects the per-cell predictor
  * instead of the LDS-tiled one. The pressure solve starts from p^n extrapolated
- * in time: 3 p^n - 3 p^{n-1} + p^{n-2} after two steps of this context, 2 p^n -
- * p^{n-1} after one, p^n otherwise (and after ibm_set_state); IBM_CG_START=linear
- * caps the order at the two-point form, IBM_CG_START=plain uses p^n always. Every
- * start converges to the same solution within cg_rtol. An IBM_FP32 context solves
+ * in time: 4 p^n - 6 p^{n-1} + 4 p^{n-2} - p^{n-3} after three steps of this
+ * context, 3 p^n - 3 p^{n-1} + p^{n-2} after two, 2 p^n - p^{n-1} after one, p^n
+ * otherwise (and after ibm_set_state); IBM_CG_START=quadratic caps the order at the
+ * three-point form, IBM_CG_START=linear at the two-point form, IBM_CG_START=plain
+ * uses p^n always. Every start converges to the same solution within cg_rtol. An IBM_FP32 context solves
  * for the pressure with the FP64 CG on its FP32 psi; IBM_FP32_SOLVE=refine selects
  * iterative refinement (FP64 x and residual around an FP32 inner CG) instead. */
 ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,

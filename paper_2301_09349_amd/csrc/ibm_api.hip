@@ -108,9 +108,12 @@ struct ibm_ctx {
   // E_hist holds the energy of the state before the other slot's (the three-point
   // start is then possible); cleared with prev_valid
   bool hist_valid = false;
-  // highest order of the extrapolated CG start: 2 (default), 1 with
-  // IBM_CG_START=linear, 0 with IBM_CG_START=plain
-  int cg_order = 2;
+  // E_hist2 holds the energy of the state before E_hist's (the four-point start is
+  // then possible); cleared with hist_valid
+  bool hist2_valid = false;
+  // highest order of the extrapolated CG start: 3 (default), 2 with
+  // IBM_CG_START=quadratic, 1 with IBM_CG_START=linear, 0 with IBM_CG_START=plain
+  int cg_order = 3;
   int tag = 0;  // solve tag, one per pass of a step launched
   std::string err;
   CgScal cgh;
@@ -300,6 +303,7 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   B.rho_s = field(N);
   B.E_s = field(N);
   B.E_hist = field(N);
+  B.E_hist2 = field(N);
   B.psi = field(N);
   for (int q = 0; q < 3; ++q) {
     B.mom_s[q] = q < dim ? field(N) : nullptr;
@@ -647,8 +651,9 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
     const char *fs = std::getenv("IBM_FP32_SOLVE");
     ctx->L.refine32 = (fs && std::strcmp(fs, "refine") == 0) ? 1 : 0;
     const char *cgs = std::getenv("IBM_CG_START");
-    ctx->cg_order = !cgs ? 2 : std::strcmp(cgs, "plain") == 0 ? 0
-                             : std::strcmp(cgs, "linear") == 0 ? 1 : 2;
+    ctx->cg_order = !cgs ? 3 : std::strcmp(cgs, "plain") == 0 ? 0
+                             : std::strcmp(cgs, "linear") == 0 ? 1
+                             : std::strcmp(cgs, "quadratic") == 0 ? 2 : 3;
     if (ctx->L.pred_lds && need > 65536) ibmk::enable_predictor_lds(desc->dim, desc->precision);
   }
   ctx->tape_cap = tape_steps;
@@ -717,7 +722,7 @@ ibm_status ibm_init_primitive(ibm_ctx *ctx, const void *rho, const void *u, cons
   ibmk::run_init_primitive(ctx->L, ctx->B, ctx->cur, rho, u, theta);
   HIPCHECK(ctx, hipGetLastError());
   ctx->step = 0;
-  ctx->prev_valid = ctx->hist_valid = false;
+  ctx->prev_valid = ctx->hist_valid = ctx->hist2_valid = false;
   ctx->diff_hist = 0;
   if (ctx->nc > 0 && ctx->motion_axis >= 0) {
     ibm_status s = rebuild_markers(ctx, 0.0);
@@ -753,7 +758,7 @@ ibm_status ibm_set_state(ibm_ctx *ctx, const void *rho, const void *mom, const v
     HIPCHECK(ctx, hipGetLastError());
   }
   ctx->step = step;
-  ctx->prev_valid = ctx->hist_valid = false;
+  ctx->prev_valid = ctx->hist_valid = ctx->hist2_valid = false;
   ctx->diff_hist = 0;
   if (ctx->nc > 0 && ctx->motion_axis >= 0) {
     ibm_status s = rebuild_markers(ctx, double(step) * g.dt);
@@ -944,7 +949,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       timed(IBM_PROF_CORRECT, 0, [&] { ibmk::run_density_finish(L, B, ctx->cur, tag); });
       HIPCHECK(ctx, hipGetLastError());
       ctx->cur ^= 1;
-      ctx->prev_valid = ctx->hist_valid = false;
+      ctx->prev_valid = ctx->hist_valid = ctx->hist2_valid = false;
       ctx->step += 1;
       ++done;
     }
@@ -965,8 +970,8 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       ibm_status ts = tape_copy(ctx, s, ctx->cur, true);
       if (ts) return ts;
     }
-    const int order =
-        std::min(ctx->cg_order, ctx->prev_valid ? (ctx->hist_valid ? 2 : 1) : 0);
+    const int order = std::min(
+        ctx->cg_order, ctx->prev_valid ? (ctx->hist_valid ? (ctx->hist2_valid ? 3 : 2) : 1) : 0);
     double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
     bool failed = false, maxit = false;
     int iters = 0;
@@ -977,7 +982,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       P.step_first = P.pending.size();
       timed(IBM_PROF_PREDICTOR, 0, [&] {
         ibmk::run_predictor(L, B, ctx->cur, flux, first ? order : -1,
-                            first && ctx->cg_order >= 2);
+                            first ? ctx->cg_order - 1 : 0);
       });
       // the FP32 refinement may have finished in its second x buffer
       if (!first && L.prec == 1 && L.refine32) ibmk::run_copy_solution(L, B, B.x);
@@ -989,7 +994,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
         diff_it += dit;
         if (ds) {
           // E_hist may already hold this step's E^{n-1}
-          ctx->prev_valid = ctx->hist_valid = false;
+          ctx->prev_valid = ctx->hist_valid = ctx->hist2_valid = false;
           ctx->diff_hist = 0;
           rc = ds;
           failed = true;
@@ -1030,7 +1035,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       iters = (int)((w >> 8) & 0xFFFFFF);
       if (P.on) P.count_cg(iters);
       if (err) {
-        ctx->prev_valid = ctx->hist_valid = false;
+        ctx->prev_valid = ctx->hist_valid = ctx->hist2_valid = false;
         ctx->diff_hist = 0;
         // this pass's correction did not run; an earlier failure is sorted out below
         rc = (err & 1) ? IBM_E_NONFINITE : (err & 2) ? IBM_E_ARG : (err & 8) ? IBM_E_SIZE
@@ -1051,6 +1056,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       HIPCHECK(ctx, hipGetLastError());
     }
     ctx->cur ^= 1;
+    ctx->hist2_valid = ctx->hist_valid && ctx->cg_order >= 3;
     ctx->hist_valid = ctx->prev_valid && ctx->cg_order >= 2;
     ctx->prev_valid = true;
     ctx->step += 1;
@@ -1076,7 +1082,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     const int s_bad = ((f[ibmk::FLAG_BAD_STEP] - 1) - first_tag) / passes;
     if (s_bad >= 0 && s_bad <= n_steps) {
       ctx->cur = cur0 ^ (s_bad & 1);
-      ctx->prev_valid = ctx->hist_valid = false;
+      ctx->prev_valid = ctx->hist_valid = ctx->hist2_valid = false;
       ctx->diff_hist = 0;
       ctx->step = step0 + s_bad;
       done = s_bad;
@@ -1252,7 +1258,8 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
   Bufs &B = ctx->B;
   hipStream_t st = L.st;
   const int slot = ctx->cur ^ 1;
-  ctx->prev_valid = ctx->hist_valid = false;  // the other slot now holds the recorded state
+  // the other slot now holds the recorded state
+  ctx->prev_valid = ctx->hist_valid = ctx->hist2_valid = false;
   ctx->diff_hist = 0;
   const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
   const double *ob = out_bar ? out_bar : zero4;
@@ -1262,7 +1269,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     ibm_status r = tape_copy(ctx, tape_index, slot, false);
     if (r) return r;
   }
-  ibmk::run_predictor(L, B, slot, slot, 0, false);
+  ibmk::run_predictor(L, B, slot, slot, 0, 0);
   if (ctx->nc > 0) {
     ibmk::run_pair_fields(L, B);  // the interpolated fields, for the position gradient
     ibmk::run_markers_step(L, B, nullptr);

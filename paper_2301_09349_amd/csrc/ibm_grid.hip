@@ -151,9 +151,11 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
 // update without the pressure gradient; psi = 1/(R theta*) with theta* = E*/(rho* c_v);
 // the CG start: p^n extrapolated in time from the pressures of the last states
 // (p = (gamma - 1) E) -- p^n alone, 2 p^n - p^{n-1} when E_prev (the previous
-// state's energy) is given, 3 p^n - 3 p^{n-1} + p^{n-2} when E_prev2 is given too.
+// state's energy) is given, 3 p^n - 3 p^{n-1} + p^{n-2} when E_prev2 is given too,
+// 4 p^n - 6 p^{n-1} + 4 p^{n-2} - p^{n-3} when E_prev3 is given as well.
 // E_keep, when given, receives E^{n-1} for the next step's E_prev2 (it may be the
-// E_prev2 array: each cell is read before it is written). The spread of the
+// E_prev2 array), E_keep2 receives E^{n-2} for the next step's E_prev3 (it may be
+// the E_prev3 array): each cell is read before it is written. The spread of the
 // forcing then adds its increment to m^ and recomputes psi on the cells it touches.
 // In an outer pass of a step (App. A step 3 repeated), the fluxes and cell terms
 // are those of the latest iterate (the kernels' state) while the time
@@ -166,7 +168,9 @@ struct PredOut {
   double *x;
   const S *E_prev;
   const S *E_prev2;
+  const S *E_prev3;
   S *E_keep;
+  S *E_keep2;
   const S *rho_b;
   const S *mom_b[3];
   const S *E_b;
@@ -183,10 +187,17 @@ __device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> 
   if (po.E_prev) {
     const S Ep = po.E_prev[c];
     const double pp = double(S(g.gm1) * Ep);
-    if (po.E_prev2)
-      x0 = 3.0 * (pn - pp) + double(S(g.gm1) * po.E_prev2[c]);
-    else
+    if (po.E_prev2) {
+      const S E2 = po.E_prev2[c];
+      const double p2 = double(S(g.gm1) * E2);
+      if (po.E_prev3)
+        x0 = 4.0 * (pn + p2) - 6.0 * pp - double(S(g.gm1) * po.E_prev3[c]);
+      else
+        x0 = 3.0 * (pn - pp) + p2;
+      if (po.E_keep2) po.E_keep2[c] = E2;
+    } else {
       x0 = 2.0 * pn - pp;
+    }
     if (po.E_keep) po.E_keep[c] = Ep;
   }
   po.x[c] = x0;
@@ -2090,7 +2101,7 @@ void enable_predictor_lds(int dim, int prec) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order, bool keep) {
+void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order, int keep) {
   IBM_DISPATCH(L, {
     PredOut<S> po;
     for (int q = 0; q < 3; ++q) po.mh[q] = (S *)B.mhat[q];
@@ -2098,7 +2109,9 @@ void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order,
     po.x = order >= 0 ? B.x : nullptr;
     po.E_prev = order >= 1 ? (const S *)B.E[cur ^ 1] : nullptr;
     po.E_prev2 = order >= 2 ? (const S *)B.E_hist : nullptr;
-    po.E_keep = (order >= 1 && keep) ? (S *)B.E_hist : nullptr;
+    po.E_prev3 = order >= 3 ? (const S *)B.E_hist2 : nullptr;
+    po.E_keep = (order >= 1 && keep >= 1) ? (S *)B.E_hist : nullptr;
+    po.E_keep2 = (order >= 2 && keep >= 2) ? (S *)B.E_hist2 : nullptr;
     po.rho_b = (const S *)B.rho[base];
     for (int q = 0; q < 3; ++q) po.mom_b[q] = (const S *)B.mom[base][q];
     po.E_b = (const S *)B.E[base];

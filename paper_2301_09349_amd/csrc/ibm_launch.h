@@ -12,7 +12,8 @@ struct Bufs {
   void *rho[2], *mom[2][3], *E[2], *F[2][3];
   // predictor output; mom_s and E_s become mom** and E** after spreading
   void *rho_s, *mom_s[3], *E_s;
-  void *E_hist;  // E^{n-2} for the extrapolated CG start (written by the predictor)
+  void *E_hist;   // E^{n-2} for the extrapolated CG start (written by the predictor)
+  void *E_hist2;  // E^{n-3}, likewise
   // pressure equation: m^ = mom** + dt G p^n, its face flux, psi
   void *mhat[3], *Fhat[3], *psi;
   // pressure CG (FP64, single-reduction form): x and p in place; r, w = A r and
@@ -122,9 +123,10 @@ void run_flux_from_momentum(const Launch &L, const Bufs &B, int cur);
 // values from slot `base` (the same slot except in an outer pass). order -1: x
 // is left as it is (an outer pass); 0: x = p^n; 1: the other state slot holds the
 // previous state and x = 2 p^n - p^{n-1}; 2: E_hist also holds E^{n-2} and x =
-// 3 p^n - 3 p^{n-1} + p^{n-2}. keep (order >= 1): E^{n-1} is copied to E_hist for
-// the next step.
-void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order, bool keep);
+// 3 p^n - 3 p^{n-1} + p^{n-2}; 3: E_hist2 also holds E^{n-3} and x = 4 p^n -
+// 6 p^{n-1} + 4 p^{n-2} - p^{n-3}. keep >= 1 (order >= 1): E^{n-1} is copied to
+// E_hist for the next step; keep >= 2 (order >= 2): E^{n-2} to E_hist2 as well.
+void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order, int keep);
 size_t predictor_lds_bytes(int dim, int prec);
 void enable_predictor_lds(int dim, int prec);
 // set-up of the pressure equation from the predictor's m^, psi, x (with the spread

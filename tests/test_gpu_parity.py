@@ -123,22 +123,24 @@ def test_large_marker_set_parity(cuda):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-6)])
 def test_cg_start_does_not_change_the_solution(cuda, monkeypatch, precision, tol):
-    # the pressure solve starts from 3 p^n - 3 p^{n-1} + p^{n-2} (default), from
+    # the pressure solve starts from 4 p^n - 6 p^{n-1} + 4 p^{n-2} - p^{n-3}
+    # (default), from 3 p^n - 3 p^{n-1} + p^{n-2} with IBM_CG_START=quadratic, from
     # 2 p^n - p^{n-1} with IBM_CG_START=linear, or from p^n with IBM_CG_START=plain;
     # all converge to the same solution within cg_rtol
     c = _channel((90, 70), 60)
     g = {}
-    for mode in ("quadratic", "linear", "plain"):
-        if mode == "quadratic":
+    for mode in ("cubic", "quadratic", "linear", "plain"):
+        if mode == "cubic":
             monkeypatch.delenv("IBM_CG_START", raising=False)
         else:
             monkeypatch.setenv("IBM_CG_START", mode)
         g[mode] = make_gpu(c, precision)
     monkeypatch.delenv("IBM_CG_START")
     it = {k: s.step(30)[1]["cg_iters_total"] for k, s in g.items()}
-    assert it["quadratic"] <= it["linear"] < it["plain"], it
+    print("CG iterations over 30 steps:", it)
+    assert it["cubic"] <= it["quadratic"] <= it["linear"] < it["plain"], it
     ref = g["plain"].get_state()
-    for mode in ("quadratic", "linear"):
+    for mode in ("cubic", "quadratic", "linear"):
         st = g[mode].get_state()
         for a, b in zip(st[:3], ref[:3]):
             assert rel_l2(to_np(a), to_np(b)) < tol, mode

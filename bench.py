@@ -53,9 +53,9 @@ def kernel_bytes(cls: str, dim: int, precision: str = "fp64", scheme: int = 0) -
             return s * 2 * (dim + 2)
         raise KeyError(cls)
     if cls == "predictor":
-        # rho, m, E, F and the two previous E (three-point extrapolated start) ->
-        # rho*, m*, E*, m^, psi, the kept E^{n-1} (state type) and x (FP64)
-        return s * ((2 * dim + 4) + (dim + 2) + dim + 2) + 8
+        # rho, m, E, F and the three previous E (four-point extrapolated start) ->
+        # rho*, m*, E*, m^, psi, the kept E^{n-1}, E^{n-2} (state type) and x (FP64)
+        return s * ((2 * dim + 5) + (2 * dim + 5)) + 8
     if cls == "setup":
         # rho^n, m^, psi, F^ (state type), x, b, r0 (FP64); then the CG start
         # psi, r0 -> w0 (both forms run the FP64 CG)

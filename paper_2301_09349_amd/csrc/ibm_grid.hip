@@ -627,8 +627,8 @@ __device__ __forceinline__ S face_from_cells(const GridK &g, M *const *m, const 
   int id = ix[d], n = g.n[d];
   if (g.bc[d][0] == BC_PERIODIC || (id > 0 && id < n)) {
     int P[3] = {fi, fj, fk}, Q[3] = {fi, fj, fk};
-    P[d] = (id - 1 + n) % n;
-    Q[d] = id % n;
+    P[d] = id > 0 ? id - 1 : n - 1;  // id is in [0, n]
+    Q[d] = id < n ? id : 0;
     return S(0.5) * (S(m[d][cidx(g, P[0], P[1], P[2])]) + S(m[d][cidx(g, Q[0], Q[1], Q[2])]));
   }
   int side = (id == 0) ? 0 : 1;
@@ -792,31 +792,50 @@ __device__ __forceinline__ void cg_sweep(const GridK &g, double alpha, double be
 // convergence (|r| <= rtol |b|) or the end (iteration limit, an error flag, NaN);
 // block 0 records the scalars and posts (step tag, it, error flags, done) to
 // `progress`. Returns false when the solve has ended (nothing to update);
-// otherwise alpha and beta of the update.
+// otherwise alpha and beta of the update. Every load of the head (the solve's
+// scalars, the flags, the partials) is issued before its first barrier, so that
+// they wait out one memory latency together.
 __device__ __forceinline__ bool cg_head(int it, const double *partials, CgScal *cs,
                                         const int *flags, uint64_t *progress, double *lds,
                                         int &done0, double &alpha, double &beta) {
-  // block 0 of this kernel may set `done` while other blocks start: one read per block
-  if (threadIdx.x == 0) done0 = cs->done;
-  __syncthreads();
-  if (done0) return false;
+  __shared__ double bc[3];
   const int nb = gridDim.x;
-  const int par = it & 1;
-  double gd[2];
-  sum_partials2(partials + (PART_G + par) * kMaxBlocks, partials + (PART_D + par) * kMaxBlocks,
-                nb, lds, gd);
-  const double gam = gd[0], del = gd[1];
-  const double bb = (it == 0) ? sum_partials(partials + PART_BB * kMaxBlocks, nb, lds) : cs->bb;
-  const double tol2 = cs->tol2;
+  const int par = it & 1, prv = par ^ 1;
+  // block 0 of this kernel may set `done` while other blocks start: one read per
+  // block, published to the block by the barriers of the sums below
+  if (threadIdx.x == 0) done0 = cs->done;
+  const double bb_prev = cs->bb, tol2 = cs->tol2;
+  const double rr_prev = cs->rr[prv], alpha_prev = cs->alpha[prv];
+  const int maxit = cs->maxit;
   const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
                   (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
+  // the sums in the order of sum_partials: strided over the threads, then the block
+  const double *pg = partials + (PART_G + par) * kMaxBlocks;
+  const double *pd = partials + (PART_D + par) * kMaxBlocks;
+  const double *pb = partials + PART_BB * kMaxBlocks;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    v[0] += pg[i];
+    v[1] += pd[i];
+    if (it == 0) v[2] += pb[i];
+  }
+  block_sum_n<3>(v, lds);
+  if (threadIdx.x == 0) {
+    bc[0] = v[0];
+    bc[1] = v[1];
+    bc[2] = v[2];
+  }
+  __syncthreads();
+  if (done0) return false;
+  const double gam = bc[0], del = bc[1];
+  const double bb = (it == 0) ? bc[2] : bb_prev;
   const bool conv = gam <= tol2 * bb;
-  const bool out = !conv && (it >= cs->maxit || err != 0 || !(gam == gam));
+  const bool out = !conv && (it >= maxit || err != 0 || !(gam == gam));
   beta = 0.0;
   alpha = gam / del;
   if (it > 0) {
-    beta = gam / cs->rr[(it - 1) & 1];
-    alpha = gam / (del - beta * gam / cs->alpha[(it - 1) & 1]);
+    beta = gam / rr_prev;
+    alpha = gam / (del - beta * gam / alpha_prev);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (it == 0) cs->bb = bb;
@@ -861,7 +880,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
     const double *__restrict__ w, const double *__restrict__ sold, double *__restrict__ rn,
     double *__restrict__ wn, double *__restrict__ snew, double *__restrict__ p,
     double *__restrict__ x, double *partials, CgScal *cs, const int *flags, uint64_t *progress) {
-  __shared__ double lds[32];
+  __shared__ double lds[48];
   __shared__ int done0;
   double alpha, beta;
   if (!cg_head(it, partials, cs, flags, progress, lds, done0, alpha, beta)) return;

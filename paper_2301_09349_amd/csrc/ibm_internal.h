@@ -154,17 +154,20 @@ __device__ __forceinline__ int64_t tile_groups() { return blockDim.x / kTile; }
 template <int DIM>
 __device__ __forceinline__ bool cell_in_tile(const GridK &g, int64_t t, int &i, int &j, int &k) {
   const int lx = threadIdx.x & 63, ly = (threadIdx.x % kTile) >> 6;
+  // a grid has at most 2^31 cells (the host checks it), so tile numbers fit 32 bits
+  const uint32_t tt = (uint32_t)t;
+  const uint32_t n0 = (uint32_t)g.tiles[0], n2 = (uint32_t)g.tiles[2];
   if (DIM == 2) {
-    const int tx = (int)(t % g.tiles[0]);
-    const int ty = (int)(t / g.tiles[0]);
+    const int tx = (int)(tt % n0);
+    const int ty = (int)(tt / n0);
     i = tx * 64 + lx;
     j = ty * 4 + ly;
     k = 0;
   } else {
-    k = (int)(t % g.tiles[2]);
-    const int64_t r = t / g.tiles[2];
-    const int tx = (int)(r % g.tiles[0]);
-    const int ty = (int)(r / g.tiles[0]);
+    k = (int)(tt % n2);
+    const auto r = tt / n2;
+    const int tx = (int)(r % n0);
+    const int ty = (int)(r / n0);
     i = tx * 64 + lx;
     j = ty * 4 + ly;
   }

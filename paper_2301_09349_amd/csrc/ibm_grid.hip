@@ -709,10 +709,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_setup2(GridK g, const S *rho_
   }
 }
 
-#ifndef IBM_CG_UNROLL
-#define IBM_CG_UNROLL 1
-#endif
-
 // Start of the single-reduction CG (Chronopoulos and Gear's variant): w0 = A r0
 // and the per-block partials of gamma_0 = r0.r0 and delta_0 = w0.r0.
 template <int DIM, typename S>
@@ -1125,21 +1121,34 @@ __global__ __launch_bounds__(kBlockThreads) void k_dsys_iter(GridK g, int it, Di
   __shared__ double red[3 * NV];
   __shared__ int run0[NV];
   DiffScal *sc = D.sc;
+  // Every load of the head (which solves still run, the scalars, the error flags,
+  // the partials of every variable) is issued before its first barrier, so that
+  // they wait out one memory latency together. Block 0 of this kernel may end a
+  // solve while other blocks start: one read of the `done` words per block,
+  // published to the block by the barriers of the sums below.
   if (threadIdx.x < NV) run0[threadIdx.x] = sc->done[threadIdx.x] == 0;
-  __syncthreads();
-  bool any = false;
+  const int par = it & 1, prv = par ^ 1;
+  const double tol2 = sc->tol2;
+  const int maxit = sc->maxit;
+  double bb_prev[NV], rr_prev[NV], alpha_prev[NV];
+  int done_prev[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) any = any || run0[v];
-  if (!any) return;
-  const int par = it & 1;
+  for (int v = 0; v < NV; ++v) {
+    bb_prev[v] = sc->bb[v];
+    rr_prev[v] = sc->rr[prv][v];
+    alpha_prev[v] = sc->alpha[prv][v];
+    done_prev[v] = sc->done[v];
+  }
+  const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
+                  (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
   {
+    // the partials of finished variables are summed too (and not used)
     double acc[3 * NV];
 #pragma unroll
     for (int v = 0; v < 3 * NV; ++v) acc[v] = 0.0;
     for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        if (!run0[v]) continue;
         acc[v] += D.part[(v * DP_REGIONS + DP_G + par) * kMaxBlocks + b];
         acc[NV + v] += D.part[(v * DP_REGIONS + DP_D + par) * kMaxBlocks + b];
         if (it == 0) acc[2 * NV + v] += D.part[(v * DP_REGIONS + DP_BB) * kMaxBlocks + b];
@@ -1152,8 +1161,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_dsys_iter(GridK g, int it, Di
     }
     __syncthreads();
   }
-  const int err = (flags[FLAG_NONFINITE] ? 1 : 0) | (flags[FLAG_SUPPORT] ? 2 : 0) |
-                  (flags[FLAG_EPS] ? 4 : 0) | (flags[FLAG_GRAM] ? 8 : 0);
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) any = any || run0[v];
+  if (!any) return;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   double alpha[NV], beta[NV];
   bool run[NV];
@@ -1164,17 +1175,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_dsys_iter(GridK g, int it, Di
     alpha[v] = beta[v] = 0.0;
     run[v] = false;
     if (!run0[v]) {
-      if (sc->done[v] == 2) state = 2;
+      // ended before this kernel: its word was set then and is not changed since
+      if (done_prev[v] == 2) state = 2;
       continue;
     }
     const double gam = red[v], del = red[NV + v];
-    const double bb = (it == 0) ? red[2 * NV + v] : sc->bb[v];
-    const bool conv = gam <= sc->tol2 * bb;
-    const bool out = !conv && (it >= sc->maxit || err != 0 || !(gam == gam));
+    const double bb = (it == 0) ? red[2 * NV + v] : bb_prev[v];
+    const bool conv = gam <= tol2 * bb;
+    const bool out = !conv && (it >= maxit || err != 0 || !(gam == gam));
     alpha[v] = gam / del;
     if (it > 0) {
-      beta[v] = gam / sc->rr[(it - 1) & 1][v];
-      alpha[v] = gam / (del - beta[v] * gam / sc->alpha[(it - 1) & 1][v]);
+      beta[v] = gam / rr_prev[v];
+      alpha[v] = gam / (del - beta[v] * gam / alpha_prev[v]);
     }
     run[v] = !(conv || out);
     if (run[v]) all_end = false;
@@ -1969,12 +1981,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_correct(GridK g, StateV<S> cu
   // failed: a failed step leaves the state it started from untouched. (Decided by
   // one thread: other blocks may raise a flag while this one starts.)
   __shared__ int skip;
+  // the solution buffer of the FP32 form's solve (final once the solve has ended);
+  // loaded with the test, before the barrier
+  const int xfinal = cs->xfinal;
   if (threadIdx.x == 0)
     skip = cs->step_tag != tag || cs->done == 0 || flags[FLAG_NONFINITE] ||
            flags[FLAG_SUPPORT] || flags[FLAG_EPS] || flags[FLAG_GRAM];
   __syncthreads();
   if (skip) return;
-  const double *x = cs->xfinal ? xb : xa;  // the solution buffer of the FP32 form's solve
+  const double *x = xfinal ? xb : xa;
   const S *mh[3] = {mh0, mh1, mh2};
   const S *Fh[3] = {Fh0, Fh1, Fh2};
   const double dt = g.dt;

@@ -299,8 +299,8 @@ struct PTile;
 #define IBM_PRED_TY2F 8
 #endif
 #ifndef IBM_PRED_TX3D
-#define IBM_PRED_TX3D 16
-#define IBM_PRED_TY3D 4
+#define IBM_PRED_TX3D 8
+#define IBM_PRED_TY3D 8
 #define IBM_PRED_TZ3D 4
 #endif
 #ifndef IBM_PRED_TX3F

@@ -113,6 +113,13 @@ def lib():
         L.orc_tl_shape.argtypes = [P, ctypes.c_int, D, D, D]
         L.orc_tl_state.restype = ctypes.c_int
         L.orc_tl_state.argtypes = [P, ctypes.c_int, D, D, D, D, D]
+        L.orc_wall_fluxes.restype = ctypes.c_int
+        L.orc_wall_fluxes.argtypes = [P, D, D, D]
+        L.orc_get_markers.restype = ctypes.c_int
+        L.orc_get_markers.argtypes = [P, D, D]
+        L.orc_face_value.restype = ctypes.c_double
+        L.orc_face_value.argtypes = [P, D, ctypes.c_int, ctypes.c_int, ctypes.c_long,
+                                     ctypes.c_long, ctypes.c_long, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -255,6 +262,36 @@ class Oracle:
         out = np.zeros(self.ns * w)
         lib().orc_get_marker_fields(self.h, _p(out))
         return out.reshape(self.ns, w)
+
+    def wall_fluxes(self):
+        """Per marker in use after the last step: force on the body -dV eps_k F_k
+        [ns, dim], heat given to the fluid H_k = dV eps_k Q_k [ns], and the local heat
+        flux H_k / dA'_k [ns] (the surface elements of the markers in use scaled to
+        the whole given surface; None when the markers carry no surface)."""
+        self.keep()
+        f = np.zeros(self.ns * self.dim)
+        hq = np.zeros(self.ns)
+        q = np.zeros(self.ns)
+        rc = lib().orc_wall_fluxes(self.h, _p(f), _p(hq), _p(q))
+        return f.reshape(self.ns, self.dim), hq, (None if rc else q)
+
+    def markers(self):
+        """Positions [ns, dim] and desired velocities [ns, dim] of the markers in use."""
+        self.keep()
+        X = np.zeros(self.ns * self.dim)
+        U = np.zeros(self.ns * self.dim)
+        lib().orc_get_markers(self.h, _p(X), _p(U))
+        return X.reshape(self.ns, self.dim), U.reshape(self.ns, self.dim)
+
+    def face_value(self, field, var: int, d: int, idx, F: float) -> float:
+        """Convected face value (Sec. 2.2.2) of the cell field ``field`` [N] (variable
+        kind ``var``: 0 rho, 1..3 velocity components, 4 theta, 5 p, 6 E) on the face
+        of direction ``d`` between cell ``idx`` - e_d and cell ``idx``, for face mass
+        flux ``F``."""
+        a = np.ascontiguousarray(field, dtype=np.float64).ravel()
+        i = list(idx) + [0] * (3 - len(idx))
+        return lib().orc_face_value(self.h, _p(a), int(var), int(d), int(i[0]), int(i[1]),
+                                    int(i[2]), float(F))
 
     def predictor_only(self):
         rc = lib().orc_predictor_only(self.h)

@@ -241,6 +241,16 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
  * Fx, Fy, Fz, H, may be NULL; synchronises). */
 ibm_status ibm_wall_fluxes(const ibm_ctx *ctx, double *force, double *heat, double *totals);
 
+/* Local wall heat flux of the last step (Sec. 3.1; the heat flux behind a local
+ * Nusselt number): per marker in use q_k = H_k / dA'_k (device double [n_used]),
+ * H_k = dV eps_k Q_k the heat the marker gives to the fluid (as ibm_wall_fluxes),
+ * dA'_k = dA_k (sum of the candidates' dA) / (sum of the used markers' dA): the
+ * surface elements given to ibm_set_markers, scaled so that those of the markers
+ * in use cover the whole given surface (the check routine drops candidates, whose
+ * surface the kept markers then represent). Synchronises. IBM_E_STATE without
+ * markers or when the markers in use carry no surface (dA NULL or zero). */
+ibm_status ibm_wall_heat_flux(const ibm_ctx *ctx, double *q);
+
 /* Markers in use: their number (host), candidate ids (device int32 [n_used]) and
  * Lagrangian quadrature eps (device double [n_used]); NULL pointers skip. */
 ibm_status ibm_markers_in_use(const ibm_ctx *ctx, int32_t *n_used, int32_t *ids, double *eps);

@@ -90,6 +90,7 @@ SIGNATURES = {
     "ibm_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_uint32, _P,
                                 ctypes.POINTER(ibm_step_info)]),
     "ibm_wall_fluxes": (ctypes.c_int, [_P, _P, _P, _D]),
+    "ibm_wall_heat_flux": (ctypes.c_int, [_P, _P]),
     "ibm_markers_in_use": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), _P, _P]),
     "ibm_get_field": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "ibm_adjoint_step": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _D, _P]),

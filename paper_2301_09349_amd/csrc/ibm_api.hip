@@ -1138,6 +1138,23 @@ ibm_status ibm_wall_fluxes(const ibm_ctx *cctx, double *force, double *heat, dou
   return IBM_OK;
 }
 
+ibm_status ibm_wall_heat_flux(const ibm_ctx *cctx, double *q) {
+  ibm_ctx *ctx = const_cast<ibm_ctx *>(cctx);
+  if (!ctx) return IBM_E_ARG;
+  if (!q) return fail(ctx, IBM_E_ARG, "wall_heat_flux: NULL destination");
+  if (ctx->nc == 0) return fail(ctx, IBM_E_STATE, "wall_heat_flux: no markers");
+  hipStream_t st = ctx->L.st;
+  // status word: the last of the 8 flag slots (FLAG_* use 0..4)
+  int *status = ctx->B.flags + 7;
+  ibmk::run_heat_flux(ctx->L, ctx->B, ctx->nc, q, status);
+  HIPCHECK(ctx, hipGetLastError());
+  int stv = 0;
+  ibm_status r = sync_read(ctx, &stv, status, sizeof(int));
+  if (r) return r;
+  if (stv) return fail(ctx, IBM_E_STATE, "wall_heat_flux: the markers in use carry no surface (dA)");
+  return IBM_OK;
+}
+
 ibm_status ibm_markers_in_use(const ibm_ctx *cctx, int32_t *n_used, int32_t *ids, double *eps) {
   ibm_ctx *ctx = const_cast<ibm_ctx *>(cctx);
   if (!ctx) return IBM_E_ARG;

@@ -188,6 +188,9 @@ void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, doubl
 void run_build_markers(const Launch &L, const Bufs &B, int nc);
 void run_interp_force(const Launch &L, const Bufs &B, double *hist_row);
 void run_spread(const Launch &L, const Bufs &B);
+// local heat flux H_k / dA'_k of the markers in use into q [n_used] (device);
+// status[0] (device) = 1 when the markers in use carry no surface
+void run_heat_flux(const Launch &L, const Bufs &B, int nc, double *q, int *status);
 // interpolation, forcing, totals and spread of one step: one single-block kernel
 // when the candidate capacity is at most kFusedMarkers, else the kernels above
 void run_markers_step(const Launch &L, const Bufs &B, double *hist_row);

@@ -649,6 +649,33 @@ __global__ void k_totals(const int *mcount, const double *mforce, const double *
   totals_block(mcount, mforce, mheat, totals, hist_row, lds);
 }
 
+// Local heat flux of each marker in use (Sec. 3.1, the wall heat flux behind a
+// local Nusselt number): q_k = H_k / dA'_k, H_k = dV eps_k Q_k the marker's heat,
+// dA'_k = dA_k (sum of the candidates' dA) / (sum of the used markers' dA), the
+// surface elements of the markers in use scaled to the whole given surface (the
+// check routine drops candidates, whose surface the kept markers then represent).
+// One block; fixed-order sums. status[0] = 1 when the markers in use carry no
+// surface (nothing written).
+__global__ void k_heat_flux(int nc, const int *mcount, const double *cdA, const double *dA,
+                            const double *mheat, double *q, int *status) {
+  __shared__ double lds[64];
+  __shared__ double sc[2];
+  const int nu = mcount[0];
+  double v[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < nc; k += blockDim.x) v[0] += cdA[k];
+  for (int k = threadIdx.x; k < nu; k += blockDim.x) v[1] += dA[k];
+  block_sum_n<2>(v, lds);
+  if (threadIdx.x == 0) {
+    sc[0] = v[0];
+    sc[1] = v[1];
+    status[0] = (v[1] > 0.0) ? 0 : 1;
+  }
+  __syncthreads();
+  if (!(sc[1] > 0.0)) return;
+  const double scale = sc[0] / sc[1];
+  for (int k = threadIdx.x; k < nu; k += blockDim.x) q[k] = mheat[k] / (dA[k] * scale);
+}
+
 // Fields the spread updates: mom** = mom* + dt f, E** = E* + dt q, the set-up's
 // m^ (+ dt f) and psi = 1/(R theta**), theta** = E**/(rho* c_v).
 template <typename S>
@@ -1064,6 +1091,11 @@ void run_markers_step(const Launch &L, const Bufs &B, double *hist_row) {
                        (const double *)B.Ud, (const double *)B.Tw, (const double *)B.eps, B.mk,
                        B.mforce, B.mheat, B.totals, hist_row);
   });
+}
+
+void run_heat_flux(const Launch &L, const Bufs &B, int nc, double *q, int *status) {
+  hipLaunchKernelGGL(k_heat_flux, dim3(1), dim3(256), 0, L.st, nc, B.mcount, B.cdA, B.dA,
+                     B.mheat, q, status);
 }
 
 void run_spread(const Launch &L, const Bufs &B) {

@@ -206,6 +206,14 @@ class IBMSolver:
         self.stream.synchronize()
         return force[:nu], heat[:nu], np.array(tot[:])
 
+    def wall_heat_flux(self):
+        """Local wall heat flux H_k / dA'_k of the markers in use [n_used] (device)."""
+        ids, _ = self.markers_in_use()
+        nu = ids.shape[0]
+        q = torch.zeros(max(nu, 1), dtype=torch.float64, device=self.device)
+        L.check(self.lib.ibm_wall_heat_flux(self.ctx, _ptr(q)), self.ctx, "ibm_wall_heat_flux")
+        return q[:nu]
+
     # ---------------------------------------------------------------- adjoint
     @property
     def state_size(self) -> int:

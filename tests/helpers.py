@@ -57,3 +57,23 @@ def state_errors(gpu, orc):
     errs = {"rho": rel_l2(to_np(r), ro), "mom": rel_l2(to_np(m), mo), "E": rel_l2(to_np(E), Eo)}
     errs["F"] = rel_l2(np.concatenate([to_np(f) for f in F]), np.concatenate(Fo))
     return errs
+
+
+def departure_errors(gpu, orc):
+    """Relative L2 errors of the departures from the free stream (rho - 1, m - U_inf,
+    E - c_v, F - U_inf on every face): the part of the state that carries the flow,
+    which a relative error of the whole field would weigh against the free-stream
+    mean."""
+    c = gpu.case
+    dim = int(c["dim"])
+    U = list(c.get("U_inf", (1.0, 0.0, 0.0)))
+    cv = 1.0 / (c["gamma"] * c["Ma"] ** 2) / (c["gamma"] - 1.0)
+    r, m, E, F = gpu.get_state()
+    ro, mo, Eo, Fo = orc.get_state()
+    m, mo = to_np(m).reshape(dim, -1), np.asarray(mo).reshape(dim, -1)
+    du = np.array(U[:dim])[:, None]
+    errs = {"rho": rel_l2(to_np(r) - 1.0, ro - 1.0), "mom": rel_l2(m - du, mo - du),
+            "E": rel_l2(to_np(E) - cv, Eo - cv)}
+    errs["F"] = rel_l2(np.concatenate([to_np(f) - U[d] for d, f in enumerate(F)]),
+                       np.concatenate([f - U[d] for d, f in enumerate(Fo)]))
+    return errs

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from paper_2301_09349_amd import inputs
-from helpers import make_gpu, make_oracle, rel_l2, state_errors, to_np
+from helpers import departure_errors, make_gpu, make_oracle, rel_l2, state_errors, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -67,6 +67,11 @@ def test_cylinder_128_100_steps_parity(cuda):
     errs = state_errors(g, o)
     for k, v in errs.items():
         assert v < 1e-10, (k, v)
+    # the departures from the free stream (about 1e-3 of the fields) to the same bound
+    dep = departure_errors(g, o)
+    print("100 steps: field errors", errs, "departure errors", dep)
+    for k, v in dep.items():
+        assert v < 1e-10, (k, v)
     # per-step force and heat histories
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
     assert abs(info["mass"] - ho[-1, 4]) < 1e-12 * ho[-1, 4]
@@ -84,9 +89,11 @@ def test_sphere_3d_parity(cuda):
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
 
 
-def test_full_size_cylinder_1024_parity(cuda):
-    # the benchmark workload at its full size, in the benchmark's configuration
-    c = inputs.case("cfg2a")
+@pytest.mark.parametrize("name", ["cfg2a", "cfg2b"])
+def test_full_size_cylinder_1024_parity(cuda, name):
+    # the 1024^2 workload at its full size (Tw/Tinf 0.8 and 1.5), in the benchmark's
+    # configuration
+    c = inputs.case(name)
     g, o = make_gpu(c), make_oracle(c)
     ids, _ = g.markers_in_use()
     assert np.array_equal(to_np(ids).astype(int), o.keep())
@@ -94,18 +101,47 @@ def test_full_size_cylinder_1024_parity(cuda):
     ho = o.step(2)
     for k, v in state_errors(g, o).items():
         assert v < 1e-12, (k, v)
+    dep = departure_errors(g, o)
+    print(name, "departure errors", dep)
+    for k, v in dep.items():
+        assert v < 1e-10, (k, v)
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
 
 
 @pytest.mark.slow
-def test_full_size_sphere_256_parity(cuda):
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("over", [dict(Tw=1.5, Ma=0.3), dict(Tw=0.5, Ma=0.8)],
+                         ids=["Tw1.5-Ma0.3", "Tw0.5-Ma0.8"])
+def test_full_size_sphere_256_parity(cuda, over):
     # 256^3 cells, 3200 candidate markers: one step (the oracle takes about a minute)
-    c = inputs.case("cfg3")
+    c = inputs.case("cfg3", **over)
     g, o = make_gpu(c), make_oracle(c)
     hg, _ = g.step(1)
     ho = o.step(1)
     for k, v in state_errors(g, o).items():
         assert v < 1e-12, (k, v)
+    dep = departure_errors(g, o)
+    print(over, "departure errors", dep)
+    for k, v in dep.items():
+        assert v < 1e-10, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
+
+
+def test_full_size_moving_512_parity(cuda):
+    # the transversely oscillating cylinder at its full size (512^2, 200 candidate
+    # markers re-selected every step), two steps in FP64
+    c = inputs.case("cfg4")
+    g, o = make_gpu(c), make_oracle(c)
+    hg, _ = g.step(2)
+    ho = o.step(2)
+    ids, _ = g.markers_in_use()
+    assert np.array_equal(to_np(ids).astype(int), o.keep())
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-12, (k, v)
+    dep = departure_errors(g, o)
+    print("cfg4 departure errors", dep)
+    for k, v in dep.items():
+        assert v < 1e-10, (k, v)
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
 
 

@@ -23,7 +23,8 @@ def _walls(Uw, Ttop, Tbot, ny, steps, nx=8):
     Ud[nx:, 0] = -Uw
     Tw = np.concatenate([np.full(nx, Ttop), np.full(nx, Tbot)])
     o.init_primitive(np.ones(nx * ny), np.zeros((2, nx * ny)), np.ones(nx * ny))
-    o.set_markers(X, Ud, Tw, dedupe=True)
+    # each marker stands for a segment h of its wall (per unit span)
+    o.set_markers(X, Ud, Tw, dA=np.full(2 * nx, h), dedupe=True)
     o.step(steps)
     r, m, E, _ = o.get_state()
     cv = 1.0 / (1.4 * 0.01) / 0.4
@@ -37,8 +38,9 @@ def _walls(Uw, Ttop, Tbot, ny, steps, nx=8):
     F_top = -dV * (eps[top] * mf[top, 4]).sum()  # force of the fluid on the upper wall
     H_top = dV * (eps[top] * mf[top, 6]).sum()  # heat given by the upper wall to the fluid
     inner = np.abs(yc) < 0.5 - 2 * h
+    _, heat, qloc = o.wall_fluxes()
     return dict(yc=yc, u=u, th=th, inner=inner, F_top=F_top, H_top=H_top, Lx=nx * h, h=h,
-                v=(m[1] / r))
+                v=(m[1] / r), heat=heat, qloc=qloc, top=top)
 
 
 def test_couette_between_immersed_walls():
@@ -72,3 +74,10 @@ def test_linear_conduction_between_immersed_walls():
     # heat given to the fluid by the cold upper wall: both sides conduct into it
     H_exact = 2.0 * lam * (Ttop - Tbot) / 1.0 * r["Lx"]
     assert abs(r["H_top"] - H_exact) < 0.1 * abs(H_exact)
+    # the local heat flux per unit wall area: the same at every marker of a wall (the
+    # problem does not depend on x) and lambda dT/dy on each of the wall's two faces
+    q_top = r["qloc"][r["top"]]
+    assert np.abs(q_top - q_top.mean()).max() < 1e-10 * abs(q_top.mean())
+    q_exact = 2.0 * lam * (Ttop - Tbot) / 1.0
+    assert abs(q_top.mean() - q_exact) < 0.1 * abs(q_exact)
+    assert abs((r["qloc"] * r["h"]).sum() - r["heat"].sum()) < 1e-12 * np.abs(r["heat"]).sum()

@@ -650,6 +650,9 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
     // selects iterative refinement around an FP32 inner CG
     const char *fs = std::getenv("IBM_FP32_SOLVE");
     ctx->L.refine32 = (fs && std::strcmp(fs, "refine") == 0) ? 1 : 0;
+    // 3D pressure CG by z-columns; IBM_CG3D=tile selects the tile-wise iteration
+    const char *c3 = std::getenv("IBM_CG3D");
+    ctx->L.cg_col = (c3 && std::strcmp(c3, "tile") == 0) ? 0 : 1;
     const char *cgs = std::getenv("IBM_CG_START");
     ctx->cg_order = !cgs ? 3 : std::strcmp(cgs, "plain") == 0 ? 0
                              : std::strcmp(cgs, "linear") == 0 ? 1

@@ -4,6 +4,7 @@
 // initialisation. Templated on the dimension and on the storage/stencil type
 // (double, or float for the reduced-precision form).
 #include <algorithm>
+#include <type_traits>
 
 #include "ibm_launch.h"
 
@@ -888,6 +889,436 @@ __global__ __launch_bounds__(kBlockThreads) void k_cg_iter(
   else
     cg_sweep<DIM, false>(g, alpha, beta, t0, t1, psi, r, w, sold, rn, wn, snew, p, x, sums);
   cg_tail(it, sums, partials, lds);
+}
+
+// ------------------------------------------- 3D CG iteration by z-columns
+// The same iteration as k_cg_iter in 3D, with the neighbour values of the new
+// residual r' = r - alpha (w + beta s_old) formed once per cell instead of once per
+// stencil use: a block owns an x-y tile of kColTX x kColTY cells (a wave per x row)
+// and walks a chunk of z planes. r' of planes k-1, k, k+1 of a thread's own column
+// stay in registers; the x-y neighbours come from a plane of r' in LDS (double
+// buffered by plane parity, one barrier per plane) with a one-cell halo that halo
+// threads form from r, w, s of the neighbouring tiles. The loads of plane k+2 are
+// issued while plane k is finished. Outside the box a slot holds the ghost value
+// of the homogeneous pressure operator, sigma r'(mirror) with sigma = -1 beyond an
+// outflow side (zero on the face) and +1 elsewhere (zero normal gradient), which
+// gives helm_lap's face terms; periodic directions wrap.
+constexpr int kColTX = 64;
+#ifndef IBM_CG_COL_TY
+#define IBM_CG_COL_TY 8
+#endif
+constexpr int kColTY = IBM_CG_COL_TY;
+constexpr int kColThreads = kColTX * kColTY;
+constexpr int kColPitch = kColTX + 2;
+constexpr int kColSlots = (kColTY + 2) * kColPitch;
+constexpr int kColHalo = 2 * kColTX + 2 * kColTY;
+static_assert(kColHalo <= kColThreads, "halo slots exceed the block's threads");
+
+// Index v along direction d resolved to a cell of the box and the sign of the
+// homogeneous ghost rule: wrap (periodic), else the mirror cell with sigma -1 beyond
+// an outflow side and +1 beyond the others. Far outside (ragged tiles) the index is
+// clamped so that loads stay inside the arrays (those slots are never used).
+__device__ __forceinline__ int col_resolve(const GridK &g, int d, int v, double &sig) {
+  const int n = g.n[d];
+  sig = 1.0;
+  if (v >= 0 && v < n) return v;
+  if (g.bc[d][0] == BC_PERIODIC) {
+    v %= n;
+    return v < 0 ? v + n : v;
+  }
+  const int side = v < 0 ? 0 : 1;
+  if (g.bc[d][side] == BC_OUTFLOW) sig = -1.0;
+  v = v < 0 ? -v - 1 : 2 * n - 1 - v;
+  return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+// Loads of one plane of a thread's own column.
+struct ColLoad {
+  double r, w, s, p, x, ps, sg;
+};
+
+// Modes of the column CG kernel: the start of a solve (w0 = A r0 and the partials of
+// r0.r0 and w0.r0, no convergence test), its first iteration (p = r, s = w) and the
+// later iterations.
+enum { COL_START = 0, COL_FIRST = 1, COL_ITER = 2 };
+
+template <int MODE>
+__device__ __forceinline__ double col_rprime(double alpha, double beta, double r, double w,
+                                             double s) {
+  return MODE == COL_START ? r : MODE == COL_FIRST ? r - alpha * w : r - alpha * (w + beta * s);
+}
+
+template <int MODE, typename S>
+__global__ __launch_bounds__(kColThreads) void k_cg_col(
+    GridK g, int it, int tiles_x, int tiles_y, int zc, int64_t items, const S *__restrict__ psi,
+    const double *__restrict__ r, const double *__restrict__ w, const double *__restrict__ sold,
+    double *__restrict__ rn, double *__restrict__ wn, double *__restrict__ snew,
+    double *__restrict__ p, double *__restrict__ x, double *partials, CgScal *cs,
+    const int *flags, uint64_t *progress) {
+  constexpr bool START = MODE == COL_START, FIRST = MODE == COL_FIRST;
+  __shared__ double lds[48];
+  __shared__ int done0;
+  __shared__ double plane_lds[2][kColSlots];
+  double alpha = 0.0, beta = 0.0;
+  if (!START && !cg_head(it, partials, cs, flags, progress, lds, done0, alpha, beta)) return;
+  const int lx = threadIdx.x % kColTX, ly = threadIdx.x / kColTX;
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t rank = (b & 7) * (nb >> 3) + (b >> 3);
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const int64_t pl = (int64_t)n0 * n1;
+  const double dt2 = g.dt * g.dt;
+  const double ih0 = g.ih[0], ih1 = g.ih[1], ih2 = g.ih[2];
+  const int myslot = (ly + 1) * kColPitch + (lx + 1);
+  double sums[2] = {0.0, 0.0};
+  for (int64_t item = rank; item < items; item += nb) {
+    const int tx = (int)(item % tiles_x);
+    const int64_t rest = item / tiles_x;
+    const int ty = (int)(rest % tiles_y);
+    const int ch = (int)(rest / tiles_y);
+    const int i = tx * kColTX + lx, j = ty * kColTY + ly;
+    const int k0 = ch * zc, k1 = min(k0 + zc, n2);
+    const bool inside = i < n0 && j < n1;
+    double sx, sy;
+    const int64_t col = col_resolve(g, 0, i, sx) + (int64_t)n0 * col_resolve(g, 1, j, sy);
+    const double sxy = sx * sy;
+    // halo slot of this thread: rows y = -1 and kColTY, then columns x = -1 and kColTX
+    int hslot = -1;
+    int64_t hcol = 0;
+    double hsig = 1.0;
+    if (threadIdx.x < kColHalo) {
+      const int t = threadIdx.x;
+      int hx, hy;
+      if (t < kColTX) {
+        hx = t;
+        hy = -1;
+      } else if (t < 2 * kColTX) {
+        hx = t - kColTX;
+        hy = kColTY;
+      } else if (t < 2 * kColTX + kColTY) {
+        hx = -1;
+        hy = t - 2 * kColTX;
+      } else {
+        hx = kColTX;
+        hy = t - 2 * kColTX - kColTY;
+      }
+      double s1, s2;
+      hcol = col_resolve(g, 0, tx * kColTX + hx, s1) +
+             (int64_t)n0 * col_resolve(g, 1, ty * kColTY + hy, s2);
+      hsig = s1 * s2;
+      hslot = (hy + 1) * kColPitch + (hx + 1);
+    }
+    auto load = [&](int k, ColLoad &L) {
+      double sz;
+      const int64_t c = col + pl * col_resolve(g, 2, k, sz);
+      L.r = r[c];
+      L.w = START ? 0.0 : w[c];
+      L.s = (START || FIRST) ? 0.0 : sold[c];
+      if (inside && k >= k0 && k < k1) {
+        L.p = (START || FIRST) ? 0.0 : p[c];
+        L.x = START ? 0.0 : x[c];
+        L.ps = double(psi[c]);
+      }
+      L.sg = sxy * sz;
+    };
+    auto load_halo = [&](int k, double &hr, double &hw, double &hs, double &hg) {
+      if (hslot < 0) return;
+      double sz;
+      const int64_t c = hcol + pl * col_resolve(g, 2, k, sz);
+      hr = r[c];
+      hw = START ? 0.0 : w[c];
+      hs = (START || FIRST) ? 0.0 : sold[c];
+      hg = hsig * sz;
+    };
+    ColLoad A, B, C;
+    double rqm, rqc, rqp;
+    {
+      ColLoad M;
+      load(k0 - 1, M);
+      rqm = M.sg * col_rprime<MODE>(alpha, beta, M.r, M.w, M.s);
+    }
+    load(k0, A);
+    load(k0 + 1, B);
+    double hr = 0.0, hw = 0.0, hs = 0.0, hg = 1.0;
+    load_halo(k0, hr, hw, hs, hg);
+    rqc = A.sg * col_rprime<MODE>(alpha, beta, A.r, A.w, A.s);
+    for (int k = k0; k < k1; ++k) {
+      double hr2 = 0.0, hw2 = 0.0, hs2 = 0.0, hg2 = 1.0;
+      if (k + 2 <= k1) load(k + 2, C);
+      if (k + 1 < k1) load_halo(k + 1, hr2, hw2, hs2, hg2);
+      rqp = B.sg * col_rprime<MODE>(alpha, beta, B.r, B.w, B.s);
+      double *lp = plane_lds[(k - k0) & 1];
+      lp[myslot] = rqc;
+      if (hslot >= 0) lp[hslot] = hg * col_rprime<MODE>(alpha, beta, hr, hw, hs);
+      __syncthreads();
+      if (inside) {
+        // the face terms in helm_lap's order: -x, +x, -y, +y, -z, +z
+        const double vc = rqc;
+        double lap = 0.0, gf;
+        gf = (lp[myslot - 1] - vc) * ih0;
+        lap += gf * ih0;
+        gf = (lp[myslot + 1] - vc) * ih0;
+        lap += gf * ih0;
+        gf = (lp[myslot - kColPitch] - vc) * ih1;
+        lap += gf * ih1;
+        gf = (lp[myslot + kColPitch] - vc) * ih1;
+        lap += gf * ih1;
+        gf = (rqm - vc) * ih2;
+        lap += gf * ih2;
+        gf = (rqp - vc) * ih2;
+        lap += gf * ih2;
+        const double wnc = A.ps * vc - dt2 * lap;
+        const int64_t c = col + pl * k;
+        if (!START) {
+          const double pc = FIRST ? A.r : A.r + beta * A.p;
+          const double sc = FIRST ? A.w : A.w + beta * A.s;
+          x[c] = A.x + alpha * pc;
+          p[c] = pc;
+          snew[c] = sc;
+          rn[c] = vc;
+        }
+        wn[c] = wnc;
+        sums[0] += vc * vc;
+        sums[1] += wnc * vc;
+      }
+      A = B;
+      B = C;
+      hr = hr2;
+      hw = hw2;
+      hs = hs2;
+      hg = hg2;
+      rqm = rqc;
+      rqc = rqp;
+    }
+    __syncthreads();  // the next item's first plane reuses the LDS buffers
+  }
+  if (START) {
+    block_sum_n<2>(sums, lds);
+    if (threadIdx.x == 0) {
+      partials[PART_G * kMaxBlocks + blockIdx.x] = sums[0];
+      partials[PART_D * kMaxBlocks + blockIdx.x] = sums[1];
+    }
+  } else {
+    cg_tail(it, sums, partials, lds);
+  }
+}
+
+// 3D pressure set-up by z-columns (the arithmetic of k_setup2 with its face values,
+// divergence, outflow terms and operator in the same order): a block owns a
+// kColTX x kColTY tile and walks a chunk of planes; m^_x, m^_y and x of a plane
+// with a one-cell halo are shared through LDS, m^_z and x of planes k-1, k, k+1 of
+// a thread's own column stay in registers. Boundary faces take face_from_cells'
+// rules; x beyond a side holds the homogeneous ghost of the pressure operator.
+template <typename S>
+__global__ __launch_bounds__(kColThreads) void k_setup_col(
+    GridK g, int tiles_x, int tiles_y, int zc, int64_t items, const S *__restrict__ rho_n,
+    const S *__restrict__ mh0, const S *__restrict__ mh1, const S *__restrict__ mh2,
+    S *__restrict__ Fh0, S *__restrict__ Fh1, S *__restrict__ Fh2, const S *__restrict__ psi,
+    const double *__restrict__ x, double *__restrict__ b, double *__restrict__ r0,
+    double *partials, CgScal *cs, int tag) {
+  __shared__ double lds[32];
+  __shared__ S mx_lds[2][kColSlots];
+  __shared__ S my_lds[2][kColSlots];
+  __shared__ double x_lds[2][kColSlots];
+  const int lx = threadIdx.x % kColTX, ly = threadIdx.x / kColTX;
+  const int64_t nb = gridDim.x, bk = blockIdx.x;
+  const int64_t rank = (bk & 7) * (nb >> 3) + (bk >> 3);
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const int64_t pl = (int64_t)n0 * n1;
+  const int fx0 = g.fn[0][0];                  // x faces per row
+  const int64_t fpl1 = (int64_t)n0 * g.fn[1][1];  // y faces per plane
+  const double dt = g.dt, dt2 = g.dt * g.dt;
+  const double ih0 = g.ih[0], ih1 = g.ih[1], ih2 = g.ih[2];
+  const bool per0 = g.bc[0][0] == BC_PERIODIC, per1 = g.bc[1][0] == BC_PERIODIC,
+             per2 = g.bc[2][0] == BC_PERIODIC;
+  const int myslot = (ly + 1) * kColPitch + (lx + 1);
+  // the rule of a boundary face (face_from_cells): inflow rho_P U_inf, slip 0, else m_P
+  auto rule = [&](int bc, int d, S rho_c, S m_c) -> S {
+    if (bc == BC_INFLOW) return rho_c * S(g.U_inf[d]);
+    if (bc == BC_SLIP) return S(0);
+    return m_c;
+  };
+  double bb = 0.0;
+  for (int64_t item = rank; item < items; item += nb) {
+    const int tx = (int)(item % tiles_x);
+    const int64_t rest = item / tiles_x;
+    const int ty = (int)(rest % tiles_y);
+    const int ch = (int)(rest / tiles_y);
+    const int i = tx * kColTX + lx, j = ty * kColTY + ly;
+    const int k0 = ch * zc, k1 = min(k0 + zc, n2);
+    const bool inside = i < n0 && j < n1;
+    double sx, sy;
+    const int64_t col = col_resolve(g, 0, i, sx) + (int64_t)n0 * col_resolve(g, 1, j, sy);
+    const double sxy = sx * sy;
+    int hslot = -1;
+    int64_t hcol = 0;
+    double hsig = 1.0;
+    if (threadIdx.x < kColHalo) {
+      const int t = threadIdx.x;
+      int hx, hy;
+      if (t < kColTX) {
+        hx = t;
+        hy = -1;
+      } else if (t < 2 * kColTX) {
+        hx = t - kColTX;
+        hy = kColTY;
+      } else if (t < 2 * kColTX + kColTY) {
+        hx = -1;
+        hy = t - 2 * kColTX;
+      } else {
+        hx = kColTX;
+        hy = t - 2 * kColTX - kColTY;
+      }
+      double s1, s2;
+      hcol = col_resolve(g, 0, tx * kColTX + hx, s1) +
+             (int64_t)n0 * col_resolve(g, 1, ty * kColTY + hy, s2);
+      hsig = s1 * s2;
+      hslot = (hy + 1) * kColPitch + (hx + 1);
+    }
+    // own column: m^_z and x of a plane (any plane, resolved), and the rest of a
+    // plane inside the chunk
+    struct Own {
+      S mz, mx, my, rho, ps;
+      double x, sg;
+    };
+    auto load = [&](int k, Own &o) {
+      double sz;
+      const int64_t c = col + pl * col_resolve(g, 2, k, sz);
+      o.mz = mh2[c];
+      o.x = x[c];
+      o.sg = sxy * sz;
+      if (k >= k0 && k < k1) {
+        o.mx = mh0[c];
+        o.my = mh1[c];
+        if (inside) {
+          o.rho = rho_n[c];
+          o.ps = psi[c];
+        }
+      }
+    };
+    Own A, B, C, M;
+    load(k0 - 1, M);
+    load(k0, A);
+    load(k0 + 1, B);
+    S hmx = S(0), hmy = S(0);
+    double hx_ = 0.0;
+    auto load_halo = [&](int k, S &a, S &bq, double &xv) {
+      if (hslot < 0) return;
+      double sz;
+      const int64_t c = hcol + pl * col_resolve(g, 2, k, sz);
+      a = mh0[c];
+      bq = mh1[c];
+      xv = hsig * sz * x[c];
+    };
+    load_halo(k0, hmx, hmy, hx_);
+    S mz_m = M.mz;
+    double x_m = M.sg * M.x;
+    for (int k = k0; k < k1; ++k) {
+      S hmx2 = S(0), hmy2 = S(0);
+      double hx2 = 0.0;
+      if (k + 2 <= k1) load(k + 2, C);
+      if (k + 1 < k1) load_halo(k + 1, hmx2, hmy2, hx2);
+      const int buf = (k - k0) & 1;
+      mx_lds[buf][myslot] = A.mx;
+      my_lds[buf][myslot] = A.my;
+      x_lds[buf][myslot] = A.sg * A.x;
+      if (hslot >= 0) {
+        mx_lds[buf][hslot] = hmx;
+        my_lds[buf][hslot] = hmy;
+        x_lds[buf][hslot] = hx_;
+      }
+      __syncthreads();
+      if (inside) {
+        const S *mxl = mx_lds[buf];
+        const S *myl = my_lds[buf];
+        const double *xl = x_lds[buf];
+        const int64_t c = col + pl * k;
+        const S rc = A.rho;
+        double div = 0.0, aff = 0.0;
+        // x faces
+        {
+          const S fl = (i > 0 || per0) ? S(0.5) * (mxl[myslot - 1] + mxl[myslot])
+                                       : rule(g.bc[0][0], 0, rc, A.mx);
+          const S fh = (i < n0 - 1 || per0) ? S(0.5) * (mxl[myslot] + mxl[myslot + 1])
+                                            : rule(g.bc[0][1], 0, rc, A.mx);
+          const int64_t f = i + (int64_t)fx0 * (j + (int64_t)n1 * k);
+          Fh0[f] = fl;
+          if (i == n0 - 1) Fh0[f + 1] = fh;
+          div += (double(fh) - double(fl)) * ih0;
+          if (!per0) {
+            if (i == 0 && g.bc[0][0] == BC_OUTFLOW) aff += 2.0 * g.p_inf * ih0 * ih0;
+            if (i == n0 - 1 && g.bc[0][1] == BC_OUTFLOW) aff += 2.0 * g.p_inf * ih0 * ih0;
+          }
+        }
+        // y faces
+        {
+          const S fl = (j > 0 || per1) ? S(0.5) * (myl[myslot - kColPitch] + myl[myslot])
+                                       : rule(g.bc[1][0], 1, rc, A.my);
+          const S fh = (j < n1 - 1 || per1) ? S(0.5) * (myl[myslot] + myl[myslot + kColPitch])
+                                            : rule(g.bc[1][1], 1, rc, A.my);
+          const int64_t f = i + (int64_t)n0 * j + fpl1 * k;
+          Fh1[f] = fl;
+          if (j == n1 - 1) Fh1[f + n0] = fh;
+          div += (double(fh) - double(fl)) * ih1;
+          if (!per1) {
+            if (j == 0 && g.bc[1][0] == BC_OUTFLOW) aff += 2.0 * g.p_inf * ih1 * ih1;
+            if (j == n1 - 1 && g.bc[1][1] == BC_OUTFLOW) aff += 2.0 * g.p_inf * ih1 * ih1;
+          }
+        }
+        // z faces
+        {
+          const S fl = (k > 0 || per2) ? S(0.5) * (mz_m + A.mz) : rule(g.bc[2][0], 2, rc, A.mz);
+          const S fh = (k < n2 - 1 || per2) ? S(0.5) * (A.mz + B.mz)
+                                            : rule(g.bc[2][1], 2, rc, A.mz);
+          const int64_t f = c;  // z faces: i + n0 (j + n1 k)
+          Fh2[f] = fl;
+          if (k == n2 - 1) Fh2[f + pl] = fh;
+          div += (double(fh) - double(fl)) * ih2;
+          if (!per2) {
+            if (k == 0 && g.bc[2][0] == BC_OUTFLOW) aff += 2.0 * g.p_inf * ih2 * ih2;
+            if (k == n2 - 1 && g.bc[2][1] == BC_OUTFLOW) aff += 2.0 * g.p_inf * ih2 * ih2;
+          }
+        }
+        const double bc_ = double(rc) - dt * div + dt2 * aff;
+        // the operator on x in helm_lap's order: -x, +x, -y, +y, -z, +z
+        const double xc = A.x;
+        double lap = 0.0, gf;
+        gf = (xl[myslot - 1] - xc) * ih0;
+        lap += gf * ih0;
+        gf = (xl[myslot + 1] - xc) * ih0;
+        lap += gf * ih0;
+        gf = (xl[myslot - kColPitch] - xc) * ih1;
+        lap += gf * ih1;
+        gf = (xl[myslot + kColPitch] - xc) * ih1;
+        lap += gf * ih1;
+        gf = (x_m - xc) * ih2;
+        lap += gf * ih2;
+        gf = (B.sg * B.x - xc) * ih2;
+        lap += gf * ih2;
+        const double ax = double(A.ps) * xc - dt2 * lap;
+        b[c] = bc_;
+        r0[c] = bc_ - ax;
+        bb += bc_ * bc_;
+      }
+      mz_m = A.mz;
+      x_m = A.sg * A.x;
+      A = B;
+      B = C;
+      hmx = hmx2;
+      hmy = hmy2;
+      hx_ = hx2;
+    }
+    __syncthreads();
+  }
+  bb = block_sum(bb, lds);
+  if (threadIdx.x == 0) {
+    partials[PART_BB * kMaxBlocks + blockIdx.x] = bb;
+    if (blockIdx.x == 0) {
+      cs->done = 0;
+      cs->iters = 0;
+      cs->step_tag = tag;
+      cs->xfinal = 0;
+    }
+  }
 }
 
 // ------------------------- implicit diffusion (backward Euler), after the predictor
@@ -2166,6 +2597,20 @@ void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order,
   });
 }
 
+// Work items of the column kernels: x-y tiles times chunks of z planes, about one
+// item per block. The kernels run g.nblocks blocks, as every kernel whose per-block
+// partial sums the CG's head adds up (the head sums gridDim.x of them).
+void col_plan(const GridK &g, int &tiles_x, int &tiles_y, int &zc, int64_t &items, int &blocks) {
+  tiles_x = (g.n[0] + kColTX - 1) / kColTX;
+  tiles_y = (g.n[1] + kColTY - 1) / kColTY;
+  blocks = (int)g.nblocks;
+  const int64_t cols = (int64_t)tiles_x * tiles_y;
+  const int64_t want = std::max<int64_t>(1, blocks / cols);
+  zc = (int)std::max<int64_t>(4, (g.n[2] + want - 1) / want);
+  const int64_t nch = (g.n[2] + zc - 1) / zc;
+  items = cols * nch;
+}
+
 void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
   if (L.prec == 1 && L.refine32) {
     if (L.g.dim == 2)
@@ -2180,6 +2625,22 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
                          (const float *)B.mhat[1], (const float *)B.mhat[2], (float *)B.Fhat[0],
                          (float *)B.Fhat[1], (float *)B.Fhat[2], (const float *)B.psi,
                          (const double *)B.x, B.b, B.rv32[0], B.partials, B.cg, tag);
+    return;
+  }
+  if (L.g.dim == 3 && L.cg_col) {
+    int tx, ty, zc, nbk;
+    int64_t items;
+    col_plan(L.g, tx, ty, zc, items, nbk);
+    auto go = [&](auto sdum) {
+      using S = decltype(sdum);
+      hipLaunchKernelGGL((k_setup_col<S>), dim3((unsigned)nbk), dim3(kColThreads), 0, L.st, L.g,
+                         tx, ty, zc, items, (const S *)B.rho[cur], (const S *)B.mhat[0],
+                         (const S *)B.mhat[1], (const S *)B.mhat[2], (S *)B.Fhat[0],
+                         (S *)B.Fhat[1], (S *)B.Fhat[2], (const S *)B.psi, (const double *)B.x,
+                         B.b, B.rv[0], B.partials, B.cg, tag);
+    };
+    if (L.prec == 0) go(double{}); else go(float{});
+    run_cg_start(L, B);
     return;
   }
   IBM_DISPATCH(L, {
@@ -2198,6 +2659,22 @@ void run_cg_start(const Launch &L, const Bufs &B) {
 }
 
 void run_cg64_start(const Launch &L, const Bufs &B) {
+  if (L.g.dim == 3 && L.cg_col) {
+    int tx, ty, zc, nbk;
+    int64_t items;
+    col_plan(L.g, tx, ty, zc, items, nbk);
+    auto go = [&](auto sdum) {
+      using S = decltype(sdum);
+      hipLaunchKernelGGL((k_cg_col<COL_START, S>), dim3((unsigned)nbk), dim3(kColThreads), 0,
+                         L.st, L.g, 0, tx, ty, zc, items, (const S *)B.psi,
+                         (const double *)B.rv[0], (const double *)nullptr,
+                         (const double *)nullptr, (double *)nullptr, B.wv[0], (double *)nullptr,
+                         (double *)nullptr, (double *)nullptr, B.partials, B.cg,
+                         (const int *)B.flags, B.progress);
+    };
+    if (L.prec == 0) go(double{}); else go(float{});
+    return;
+  }
   IBM_DISPATCH(L, {
     hipLaunchKernelGGL((k_cg_start<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
                        L.st, L.g, (const S *)B.psi, (const double *)B.rv[0], B.wv[0], B.partials);
@@ -2229,6 +2706,28 @@ void run_cg_half(const Launch &L, const Bufs &B, int it, int part) {
 }
 
 void run_cg64_iteration(const Launch &L, const Bufs &B, int it) {
+  if (L.g.dim == 3 && L.cg_col) {
+    int tx, ty, zc, nbk;
+    int64_t items;
+    col_plan(L.g, tx, ty, zc, items, nbk);
+    const int a = it & 1, bb = a ^ 1;
+    auto go = [&](auto mode, auto sdum) {
+      using S = decltype(sdum);
+      constexpr int M = decltype(mode)::value;
+      hipLaunchKernelGGL((k_cg_col<M, S>), dim3((unsigned)nbk), dim3(kColThreads), 0, L.st, L.g,
+                         it, tx, ty, zc, items, (const S *)B.psi, (const double *)B.rv[a],
+                         (const double *)B.wv[a], (const double *)B.sv[a], B.rv[bb], B.wv[bb],
+                         B.sv[bb], B.pv, B.x, B.partials, B.cg, (const int *)B.flags, B.progress);
+    };
+    using F1 = std::integral_constant<int, COL_FIRST>;
+    using F2 = std::integral_constant<int, COL_ITER>;
+    if (L.prec == 0) {
+      if (it == 0) go(F1{}, double{}); else go(F2{}, double{});
+    } else {
+      if (it == 0) go(F1{}, float{}); else go(F2{}, float{});
+    }
+    return;
+  }
   IBM_DISPATCH(L, {
     const int a = it & 1, b = a ^ 1;
     hipLaunchKernelGGL((k_cg_iter<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,

@@ -107,6 +107,7 @@ struct Launch {
   int pred_lds;  // 1: LDS-tiled predictor, 0: per-cell predictor
   int refine32;  // FP32 form: 1 pressure by iterative refinement with an FP32 inner CG,
                  // 0 the FP64 CG on FP32 psi
+  int cg_col;     // 3D: 1 the CG iteration by z-columns (k_cg_col), 0 by tiles (k_cg_iter)
   int nc_cap;     // candidate capacity
   int npairs_pad; // power of two >= nc_cap * nslot
   hipStream_t st;

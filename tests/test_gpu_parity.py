@@ -225,3 +225,33 @@ def test_moving_body_parity(cuda, name):
     for k, v in state_errors(g, o).items():
         assert v < 1e-11, (k, v)
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
+
+
+@pytest.mark.parametrize("shape,bc", [
+    ((36, 30, 26), None),
+    ((70, 11, 9), [[inputs.INFLOW, inputs.OUTFLOW], [inputs.SLIP, inputs.SLIP],
+                   [inputs.OUTFLOW, inputs.OUTFLOW]]),
+    ((21, 19, 23), [[inputs.PERIODIC] * 2] * 3),
+])
+def test_cg_3d_columns_and_tiles_agree(cuda, monkeypatch, shape, bc):
+    # the 3D pressure CG by z-columns (default) and by tiles (IBM_CG3D=tile) on ragged
+    # grids with every kind of side, against each other and against the oracle
+    over = {} if bc is None else {"bc": bc}
+    c = inputs.scaled("cfg3", shape, ns=0 if bc else 200, **over)
+    amp = 1e-2 if bc else 1e-3
+    g = {}
+    for mode in ("col", "tile"):
+        if mode == "tile":
+            monkeypatch.setenv("IBM_CG3D", "tile")
+        else:
+            monkeypatch.delenv("IBM_CG3D", raising=False)
+        g[mode] = make_gpu(c, amplitude=amp)
+    monkeypatch.delenv("IBM_CG3D", raising=False)
+    o = make_oracle(c, amplitude=amp)
+    it = {k: s.step(3)[1]["cg_iters_total"] for k, s in g.items()}
+    o.step(3)
+    assert abs(it["col"] - it["tile"]) <= 1, it
+    for a, b in zip(g["col"].get_state()[:3], g["tile"].get_state()[:3]):
+        assert rel_l2(to_np(a), to_np(b)) < 1e-12
+    for k, v in state_errors(g["col"], o).items():
+        assert v < 1e-11, (k, v)

@@ -2,14 +2,16 @@
 
 One "step" is one pass of the whole hot path -- predictor, marker interpolation /
 forcing / spreading, pressure set-up, pressure CG to convergence, correction -- on
-the 2D heated-cylinder workload (1024^2 cells over [-4,12]x[-8,8], 400 candidate
-markers, Re 100, Ma 0.2, Tw/Tinf 0.8), with all inputs resident in HBM.
+the 3D heated-sphere workload (256^3 cells over [-2.5,7.5]x[-4,4]^2, 3200 Fibonacci
+candidate markers, Re 300, Ma 0.3, Tw/Tinf 1.5), with all inputs resident in HBM.
 
 Prints ONE JSON line: FP64 Mcell-steps/s (``value``), the FP32 form's throughput and
-its error against the FP64 run, the adjoint/forward time ratio on the gradient
-workload (512^2 cylinder, van Leer convection, 200 markers, checkpoints every 50),
-the roofline of the dominant kernel (HIP events on the library's stream over the
-timed region), and the FP64 CPU oracle timed on a bounded sample.
+its error against the FP64 run (per result: velocity, temperature, Nusselt number,
+drag; over full-length runs of the 1024^2 cylinder and the 256^3 sphere), the
+adjoint/forward time ratio on the gradient workload (512^2 cylinder, van Leer
+convection, 200 markers, checkpoints every 50), the roofline of the dominant kernel
+(HIP events on the library's stream over the timed region), other workloads as
+extra legs, and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
 ``--summarize DIR`` (no GPU) turns rocprofv3 output of this script into the text
 summaries kept under profiles/.
@@ -122,27 +124,47 @@ def traffic_entry(label: str, kernel: str):
     return ent.get("bytes_per_launch")
 
 
+def host_info():
+    """CPU model and logical CPU count of the host (lscpu, os.cpu_count)."""
+    model = ""
+    try:
+        import subprocess
+
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return {"cpu": model, "nproc": os.cpu_count()}
+
+
 def cpu_baseline(case, steps: int):
-    """The oracle as it stands, single-threaded, on `steps` steps of the workload."""
-    from oracle.oracle import Oracle
+    """The oracle as it stands (plain FP64 loops, one thread; built here with -O3
+    -march=native, still without FMA contraction) on `steps` steps of the workload
+    after its set-up (grid, markers, quadrature solve; not timed)."""
+    from oracle import oracle as orc
     from paper_2301_09349_amd import inputs
 
-    o = Oracle(case)
+    orc.use_native()
+    o = orc.Oracle(case)
     rho, u, th = inputs.initial_fields(case)
     o.init_primitive(rho, u, th)
     X, Ud, Tw, dA = inputs.markers(case)
     o.set_markers(X, Ud, Tw, dA, dedupe=True)
-    o.step(1)  # warm-up
     t0 = time.perf_counter()
-    o.step(steps)
+    h = o.step(steps)
     dt = time.perf_counter() - t0
     ncell = 1
     for v in case["n"][: case["dim"]]:
         ncell *= v
-    return {"value": ncell * steps / dt / 1e6, "unit": "Mcell-steps/s", "cores": 1,
+    cells = "x".join(str(v) for v in case["n"][: case["dim"]])
+    return {"value": round(ncell * steps / dt / 1e6, 3), "unit": "Mcell-steps/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{steps} steps of the same workload after 1 warm-up step "
-                      f"({dt:.1f} s, single thread, -O2 FP64)"}
+            "sample": f"{steps} step(s) of the same workload ({cells} cells, "
+                      f"{int(h[:, 5].sum())} CG iterations) after its set-up, {dt:.1f} s; one "
+                      "thread, g++ -O3 -march=native -ffp-contract=off, FP64",
+            "host": host_info()}
 
 
 def make_solver(case, precision, tape_steps=0):
@@ -288,49 +310,97 @@ def run_adjoint(steps: int, checkpoint: int, warmup: int, precision: str = "fp64
             "grad_norm": gnorm, "precision": precision}
 
 
-def run_sphere(steps: int, warmup: int):
-    """The 3D workload (256^3 heated sphere, 3200 candidate markers, Re 300, Ma 0.3,
-    Tw 1.5) in both forms: throughput and the CG iteration's achieved bandwidth (its
-    working set, ~2 GB in FP64, is far larger than the 256 MB Infinity Cache)."""
+def run_cylinder(steps: int, warmup: int):
+    """The 2D workload (1024^2 heated cylinder, 400 candidate markers, Re 100, Ma 0.2,
+    Tw 0.8) in both forms. Its FP64 working set (~250 MB) fits the 256 MB Infinity
+    Cache, so its kernels' GB/s are not HBM figures."""
     from paper_2301_09349_amd import inputs
 
-    case = inputs.case("cfg3", cg_rtol=1e-10)
+    case = inputs.case("cfg2a", cg_rtol=1e-10)
     res = {"steps": steps}
     for prec in ("fp64", "fp32"):
         r = run_forward(case, prec, steps, warmup)
         if "workload" not in res:
             kept = r["solver"].markers_in_use()[0].shape[0]
             res["workload"] = workload_text(case, kept, r["solver"].dt)
-        cg = r["per_kernel"]["cg"]
         res[prec] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                     "dt": r["solver"].dt,
                      "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
-                     "cg_us": round(cg["avg_us"], 2), "cg_GBps": round(cg["GBps"], 1),
-                     "cg_frac": round(cg["GBps"] / HBM_PEAK_GBS, 4),
-                     "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
-                                             for k, v in r["per_kernel"].items()}}
+                     "kernels": {k: {"avg_us": round(v["avg_us"], 2),
+                                     **({"GBps": round(v["GBps"], 1)} if "GBps" in v else {})}
+                                 for k, v in r["per_kernel"].items()}}
         del r
     return res
+
+
+def fp32_errors_full(runs):
+    """The FP32 form against the FP64 GPU path (itself pinned to the oracle) over
+    full-length runs of the same workload from the same start: velocity and
+    temperature at the end (relative L2; temperature as theta - 1), and the
+    time-averaged Nusselt number and drag coefficient (relative). `runs` lists
+    (workload name, overrides, steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2301_09349_amd import inputs
+
+    out = {}
+    for name, over, steps in runs:
+        case = inputs.case(name, cg_rtol=1e-10, **over)
+        res = {}
+        for prec in ("fp64", "fp32"):
+            s = make_solver(case, prec)
+            hist = torch.zeros((steps, 4), dtype=torch.float64, device="cuda:0")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(steps, hist_out=hist)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            r, m, e, _ = s.get_state()
+            r, m, e = r.double(), m.double(), e.double()
+            cv = 1.0 / (case["gamma"] * case["Ma"] ** 2) / (case["gamma"] - 1.0)
+            res[prec] = (m / r, e / (r * cv), hist.cpu().numpy(), el)
+            del s
+        u64, t64, h64, e64 = res["fp64"]
+        u32, t32, h32, e32 = res["fp32"]
+        rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))  # noqa: E731
+        nu = abs(h32[:, 3].mean() / h64[:, 3].mean() - 1.0)
+        cd = abs(h32[:, 0].mean() / h64[:, 0].mean() - 1.0)
+        key = name + "".join(f"_{k}{v}" for k, v in over.items())
+        out[key] = {"steps": steps, "u": float("%.3g" % rel(u32, u64)),
+                    "theta_minus_1": float("%.3g" % rel(t32 - 1.0, t64 - 1.0)),
+                    "nusselt_mean": float("%.3g" % nu), "drag_mean": float("%.3g" % cd),
+                    "ms_per_step_fp64": round(1e3 * e64 / steps, 4),
+                    "ms_per_step_fp32": round(1e3 * e32 / steps, 4)}
+        log(f"bench: FP32 vs FP64 on {key}: {out[key]}")
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_moving(steps: int, warmup: int):
-    """The streamwise-oscillating cylinder (512^2, 200 candidate markers, x = 0.14 D
-    sin(2 pi f_c t), Re 100, Ma 0.3, Tw/Tinf 2): markers re-placed, re-selected and
-    re-weighted every step, in both forms."""
+    """The moving bodies on 512^2 grids, markers re-placed, re-selected and re-weighted
+    every step, in both forms: the streamwise-oscillating cylinder of Sec. 5 (200
+    candidate markers, x = 0.14 D sin(2 pi f_c t), Re 100, Ma 0.3, Tw/Tinf 2) and the
+    transversely oscillating one (200 candidate markers, y = 0.2 D sin(2 pi 0.2 t),
+    Re 100, Ma 0.2, Tw/Tinf 1.2)."""
     from paper_2301_09349_amd import inputs
 
-    case = inputs.case("osc2", cg_rtol=1e-10)
-    res = {"steps": steps}
-    for prec in ("fp64", "fp32"):
-        r = run_forward(case, prec, steps, warmup)
-        if "workload" not in res:
-            kept = r["solver"].markers_in_use()[0].shape[0]
-            res["workload"] = workload_text(case, kept, r["solver"].dt)
-        res[prec] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
-                     "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
-                     "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
-                                             for k, v in r["per_kernel"].items()}}
-        del r
-    return res
+    out = {}
+    for name in ("osc2", "cfg4"):
+        case = inputs.case(name, cg_rtol=1e-10)
+        res = {"steps": steps}
+        for prec in ("fp64", "fp32"):
+            r = run_forward(case, prec, steps, warmup)
+            if "workload" not in res:
+                kept = r["solver"].markers_in_use()[0].shape[0]
+                res["workload"] = workload_text(case, kept, r["solver"].dt)
+            res[prec] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                         "cg_iters_per_step": round(r["info"]["cg_iters_total"] / steps, 2),
+                         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4)
+                                                 for k, v in r["per_kernel"].items()}}
+            del r
+        out[name] = res
+    return out
 
 
 def run_implicit(case, steps: int, warmup: int, explicit: dict):
@@ -607,13 +677,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the headline value (the other form is run too)")
-    ap.add_argument("--workload", default="cfg2a")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--workload", default="cfg3",
+                    help="headline workload (default cfg3, the 256^3 heated sphere)")
+    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp32-errors", action="store_true",
+                    help="skip the full-length FP32-vs-FP64 error runs")
     ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 256^3 sphere figures")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 1024^2 cylinder figures")
     ap.add_argument("--no-implicit", action="store_true",
                     help="skip the implicit-diffusion figures")
     ap.add_argument("--no-outer", action="store_true", help="skip the outer-pass figures")
@@ -626,11 +699,11 @@ def main():
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the grid-convergence study of App. C")
     ap.add_argument("--no-moving", action="store_true",
-                    help="skip the oscillating-cylinder figures")
+                    help="skip the moving-body figures")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="launch the copy kernel used to scale HBM counters first")
     ap.add_argument("--summarize", metavar="DIR", help="summarize rocprofv3 output (no GPU)")
-    ap.add_argument("--label", default="cylinder1024_fp64",
+    ap.add_argument("--label", default="sphere256_fp64",
                     help="summary name: <workload>_<precision>, e.g. sphere256_fp32")
     ap.add_argument("--command", default="")
     args = ap.parse_args()
@@ -675,7 +748,6 @@ def main():
                                                  for kk, vv in v.items()}
                                              for k, v in per_kernel.items()}))
     ids, _ = r["solver"].markers_in_use()
-    n = case["n"]
     out = {
         "metric": "Mcell-steps/s (fwd, FP32 vs FP64 at stated err) + adjoint/forward time ratio",
         "value": round(r["value"], 2),
@@ -695,17 +767,17 @@ def main():
         "roofline": roof,
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
                         "ms_per_step": round(v["ms_per_step"], 4),
-                        **({"GBps": round(v["GBps"], 1)} if "GBps" in v else {})}
+                        **({"GBps": round(v["GBps"], 1),
+                            "frac": round(v["GBps"] / HBM_PEAK_GBS, 4)} if "GBps" in v else {})}
                     for k, v in per_kernel.items()},
         "ms_per_step_profiled": round(r["ms_per_step_profiled"], 4),
         "cg_iters_all_steps": r["cg_iters_all"],
     }
-    explicit = {main_p: (r["solver"].dt, r["ms_per_step"])}
     if ro is not None:
-        explicit[other] = (ro["solver"].dt, ro["ms_per_step"])
         r64, r32 = (r, ro) if main_p == "fp64" else (ro, r)
         out[other] = {"value": round(ro["value"], 2), "ms_per_step": round(ro["ms_per_step"], 4),
                       "cg_iters_per_step": round(ro["info"]["cg_iters_total"] / args.steps, 2),
+                      "speedup_fp32_over_fp64": round(r64["ms_per_step"] / r32["ms_per_step"], 3),
                       "kernels": {k: {"avg_us": round(v["avg_us"], 2),
                                       **({"GBps": round(v["GBps"], 1)} if "GBps" in v else {})}
                                   for k, v in ro["per_kernel"].items()}}
@@ -713,13 +785,31 @@ def main():
         del ro
     del r
     torch.cuda.empty_cache()
+    if not args.no_fp32 and not args.no_fp32_errors:
+        log("bench: FP32 form against FP64 over full runs ...")
+        out["fp32_errors_full_runs"] = fp32_errors_full(
+            [("cfg2a", {}, 2000), ("cfg2b", {}, 2000), ("cfg3", {}, 500)])
+    if not args.no_2d:
+        log("bench: 1024^2 cylinder ...")
+        out["cylinder1024"] = run_cylinder(args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    cyl_case = inputs.case("cfg2a", cg_rtol=1e-10)
     if not args.no_implicit:
         log("bench: implicit diffusion ...")
-        out["implicit_diffusion"] = run_implicit(case, args.steps, args.warmup, explicit)
+        if "cylinder1024" in out:
+            base = {p: (out["cylinder1024"][p]["dt"], out["cylinder1024"][p]["ms_per_step"])
+                    for p in ("fp64", "fp32")}
+        else:
+            base = {}
+            for prec in ("fp64", "fp32"):
+                rb = run_forward(cyl_case, prec, args.steps, args.warmup)
+                base[prec] = (rb["solver"].dt, rb["ms_per_step"])
+                del rb
+        out["implicit_diffusion"] = run_implicit(cyl_case, args.steps, args.warmup, base)
         torch.cuda.empty_cache()
     if not args.no_outer:
         log("bench: outer passes ...")
-        out["outer_passes"] = run_outer(case, args.steps, args.warmup)
+        out["outer_passes"] = run_outer(cyl_case, args.steps, args.warmup)
         torch.cuda.empty_cache()
     if not args.no_density:
         log("bench: density-based step ...")
@@ -729,13 +819,9 @@ def main():
         log("bench: grid convergence (App. C) ...")
         out["grid_convergence"] = run_grid_convergence()
         torch.cuda.empty_cache()
-    if not args.no_3d and args.workload != "cfg3":
-        log("bench: 256^3 sphere ...")
-        out["sphere256"] = run_sphere(30, 10)
-        torch.cuda.empty_cache()
-    if not args.no_moving and args.workload not in ("osc1", "osc2"):
-        log("bench: oscillating cylinder ...")
-        out["oscillating512"] = run_moving(100, 10)
+    if not args.no_moving:
+        log("bench: moving bodies ...")
+        out["moving512"] = run_moving(100, 10)
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         log(f"bench: adjoint leg, {args.adjoint_steps} steps ...")
@@ -744,7 +830,7 @@ def main():
         out["adjoint_fp32"] = {k: a32[k] for k in ("forward_ms_per_step", "backward_ms_per_step",
                                                    "ratio", "grad_norm")}
     if not args.no_cpu:
-        log(f"bench: timing the oracle on {args.cpu_steps} steps ...")
+        log(f"bench: timing the oracle on {args.cpu_steps} step(s) ...")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

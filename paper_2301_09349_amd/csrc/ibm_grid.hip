@@ -334,7 +334,10 @@ struct PredLds {
   static constexpr int TX = PTile<DIM, S>::TX, TY = PTile<DIM, S>::TY, TZ = PTile<DIM, S>::TZ;
   static constexpr int SX = TX + 4, SY = TY + 4, SZ = (DIM == 3) ? TZ + 4 : 1;
   static constexpr int NP = SX * SY * SZ;
-  static constexpr int NV = DIM + 3;  // rho, u[DIM], theta, mu
+  // the pressure p = (gamma - 1) E of every point is kept too where the LDS allows it
+  // (3D FP64: two blocks per CU either way), so that -grad p reads no global memory
+  static constexpr bool PL = DIM == 3 && sizeof(S) == 8;
+  static constexpr int NV = DIM + 3 + (PL ? 1 : 0);  // rho, u[DIM], theta, mu (, p)
   static constexpr int F0 = (TX + 1) * TY * TZ, F1 = TX * (TY + 1) * TZ,
                        F2 = (DIM == 3) ? TX * TY * (TZ + 1) : 0;
   static constexpr int NFMAX = F0 > F1 ? (F0 > F2 ? F0 : F2) : (F1 > F2 ? F1 : F2);
@@ -479,6 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + lp] = u[q];
       lv[(DIM + 1) * NP + lp] = th;
       lv[(DIM + 2) * NP + lp] = mu_of(g, th);
+      if (T::PL) lv[(DIM + 3) * NP + lp] = pp;
     }
     __syncthreads();
     // phase 2: cell-centred terms (-grad p, viscous dissipation) into registers
@@ -510,14 +514,18 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
         const S hh = S(0.5 * g.ih[bd]);
 #pragma unroll
         for (int a = 0; a < DIM; ++a) gr[a][bd] = (lv[(1 + a) * NP + i1] - lv[(1 + a) * NP + i0]) * hh;
-        int g1[3] = {i, j, k}, g0[3] = {i, j, k};
-        g1[bd] += 1;
-        g0[bd] -= 1;
-        Resolved r1 = resolve<DIM>(g, g1[0], g1[1], g1[2]);
-        Resolved r0 = resolve<DIM>(g, g0[0], g0[1], g0[2]);
-        S p1 = ghosted<DIM>(g, r1, V_P, gm1 * st.E[r1.c]);
-        S p0 = ghosted<DIM>(g, r0, V_P, gm1 * st.E[r0.c]);
-        gp[bd] = (p1 - p0) * hh;
+        if (T::PL) {
+          gp[bd] = (lv[(DIM + 3) * NP + i1] - lv[(DIM + 3) * NP + i0]) * hh;
+        } else {
+          int g1[3] = {i, j, k}, g0[3] = {i, j, k};
+          g1[bd] += 1;
+          g0[bd] -= 1;
+          Resolved r1 = resolve<DIM>(g, g1[0], g1[1], g1[2]);
+          Resolved r0 = resolve<DIM>(g, g0[0], g0[1], g0[2]);
+          S p1 = ghosted<DIM>(g, r1, V_P, gm1 * st.E[r1.c]);
+          S p0 = ghosted<DIM>(g, r0, V_P, gm1 * st.E[r0.c]);
+          gp[bd] = (p1 - p0) * hh;
+        }
       }
       S divu = S(0);
 #pragma unroll

@@ -177,6 +177,22 @@ size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32
 ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
                            int32_t tape_steps, void *hip_stream, ibm_ctx **out);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ibm_create_grid with the workspace
+ * taken from a fixed array of 64 MiB in the library's device memory, one per GPU, held
+ * until the process ends. Nothing is allocated on the device or pinned on the host
+ * (the context itself is host memory, and without the pinned progress word ibm_step
+ * synchronises to follow the CG). Every other entry point works on the context as on
+ * one from ibm_create_grid. At most one such context per GPU is alive at a time: a
+ * second one on the same device returns IBM_E_STATE until ibm_destroy releases the
+ * first (contexts on one array would overwrite each other's buffers). IBM_E_SIZE when
+ * ibm_workspace_bytes(desc, desc->max_markers, tape_steps) exceeds 64 MiB (for
+ * example 128^2 and 256^2 FP64 grids with a few hundred markers fit, 1024^2 does not);
+ * IBM_E_ARG for an invalid descriptor; IBM_E_HIP when the array's address cannot be
+ * found. No error message is kept (there is no context). */
+ibm_status ibm_create_grid_noalloc(const ibm_grid_desc *desc, int32_t tape_steps,
+                                   void *hip_stream, ibm_ctx **out);
+
 /* Releases the host-side context (the workspace stays with the caller). */
 void ibm_destroy(ibm_ctx *ctx);
 

@@ -78,6 +78,8 @@ SIGNATURES = {
                                               ctypes.c_int32]),
     "ibm_create_grid": (ctypes.c_int, [ctypes.POINTER(ibm_grid_desc), _P, ctypes.c_size_t,
                                        ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "ibm_create_grid_noalloc": (ctypes.c_int, [ctypes.POINTER(ibm_grid_desc), ctypes.c_int32, _P,
+                                               ctypes.POINTER(_P)]),
     "ibm_destroy": (None, [_P]),
     "ibm_last_error": (ctypes.c_char_p, [_P]),
     "ibm_dt": (ctypes.c_double, [_P]),

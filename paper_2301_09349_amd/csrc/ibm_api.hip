@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -115,6 +116,9 @@ struct ibm_ctx {
   // IBM_CG_START=quadratic, 1 with IBM_CG_START=linear, 0 with IBM_CG_START=plain
   int cg_order = 3;
   int tag = 0;  // solve tag, one per pass of a step launched
+  // device whose static scratch array holds this context's buffers
+  // (ibm_create_grid_noalloc), -1 for a caller's workspace
+  int scratch_dev = -1;
   std::string err;
   CgScal cgh;
   Prof prof;
@@ -621,8 +625,14 @@ size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32
   return plan(*desc, g, max_markers, tape_steps, nullptr, B, np);
 }
 
-ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
-                           int32_t tape_steps, void *hip_stream, ibm_ctx **out) {
+}  // extern "C"
+
+namespace {
+
+// Context creation on a workspace; `pinned` asks for the pinned host word through which
+// the CG reports its progress (without it the step loop synchronises instead).
+ibm_status create_ctx(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
+                      int32_t tape_steps, void *hip_stream, bool pinned, ibm_ctx **out) {
   if (!out) return IBM_E_ARG;
   *out = nullptr;
   if (check_desc(desc)) return IBM_E_ARG;
@@ -668,7 +678,7 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   }
   // one word of pinned, coherent host memory through which the CG reports its
   // progress (without it the step loop synchronises instead)
-  {
+  if (pinned) {
     void *hp = nullptr;
     if (hipHostMalloc(&hp, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess && hp) {
       ctx->B.progress = static_cast<uint64_t *>(hp);
@@ -709,10 +719,77 @@ ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_
   return IBM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
+                           int32_t tape_steps, void *hip_stream, ibm_ctx **out) {
+  return create_ctx(desc, dev_workspace, bytes, tape_steps, hip_stream, true, out);
+}
+
+}  // extern "C"
+
+// Device memory of ibm_create_grid_noalloc: one fixed array per GPU the library runs
+// on (each device holds its own copy until the process ends). Host code never uses the
+// array's name as an address: its device address is looked up once per device and kept.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];   // device address of `scratch`, per device
+bool g_scratch_busy[kScratchDevices];  // a live context holds the device's array
+}  // namespace
+
+extern "C" {
+
+ibm_status ibm_create_grid_noalloc(const ibm_grid_desc *desc, int32_t tape_steps,
+                                   void *hip_stream, ibm_ctx **out) {
+  if (!out) return IBM_E_ARG;
+  *out = nullptr;
+  if (check_desc(desc) || tape_steps < 0) return IBM_E_ARG;
+  const size_t need = ibm_workspace_bytes(desc, desc->max_markers, tape_steps);
+  if (need == 0) return IBM_E_ARG;
+  if (need > kScratchBytes) return IBM_E_SIZE;  // beyond the fixed array (64 MiB)
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return IBM_E_HIP;
+  void *ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return IBM_E_HIP;
+      }
+      g_scratch_ptr[dev] = p;
+    }
+    if (g_scratch_busy[dev]) return IBM_E_STATE;  // one live context per device
+    g_scratch_busy[dev] = true;
+    ptr = g_scratch_ptr[dev];
+  }
+  // no pinned progress word either: the step loop synchronises instead
+  ibm_status st = create_ctx(desc, ptr, kScratchBytes, tape_steps, hip_stream, false, out);
+  if (st != IBM_OK) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_scratch_busy[dev] = false;
+    return st;
+  }
+  (*out)->scratch_dev = dev;
+  return IBM_OK;
+}
+
 void ibm_destroy(ibm_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->L.st);
+  const int sd = ctx->scratch_dev;
   delete ctx;
+  if (sd >= 0) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    g_scratch_busy[sd] = false;
+  }
 }
 
 const char *ibm_last_error(const ibm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }

@@ -56,7 +56,9 @@ class IBMSolver:
     """A grid, its state and its body on one GPU."""
 
     def __init__(self, case, precision: str = "fp64", max_markers=None, tape_steps: int = 0,
-                 device="cuda"):
+                 device="cuda", noalloc: bool = False):
+        """``noalloc``: create the context with ibm_create_grid_noalloc (the library's
+        fixed device array as workspace; no workspace tensor)."""
         self.lib = L.load()
         self.case = dict(case)
         self.precision = precision
@@ -76,15 +78,23 @@ class IBMSolver:
         if nbytes == 0:
             raise L.IBMError(L.IBM_E_ARG, "invalid grid description")
         self.ws_bytes = int(nbytes)
-        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
-        st = L.load().ibm_create_grid(ctypes.byref(self.desc), ctypes.c_void_p(self._ws_ptr),
-                                      self.ws_bytes, int(tape_steps),
-                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
-        L.check(st, None, "ibm_create_grid")
+        if noalloc:
+            self.ws = None
+            st = L.load().ibm_create_grid_noalloc(ctypes.byref(self.desc), int(tape_steps),
+                                                  ctypes.c_void_p(self.stream.cuda_stream),
+                                                  ctypes.byref(ctx))
+            L.check(st, None, "ibm_create_grid_noalloc")
+        else:
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            st = L.load().ibm_create_grid(ctypes.byref(self.desc), ctypes.c_void_p(self._ws_ptr),
+                                          self.ws_bytes, int(tape_steps),
+                                          ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(ctx))
+            L.check(st, None, "ibm_create_grid")
         self.ctx = ctx
         self.nc = 0
 

@@ -35,10 +35,11 @@ def make_oracle(c, markers=True, amplitude=1e-3):
     return o
 
 
-def make_gpu(c, precision="fp64", markers=True, amplitude=1e-3, tape_steps=0):
+def make_gpu(c, precision="fp64", markers=True, amplitude=1e-3, tape_steps=0, noalloc=False):
     from paper_2301_09349_amd.solver import IBMSolver
 
-    s = IBMSolver(c, precision, max_markers=max(int(c.get("ns", 0)), 1), tape_steps=tape_steps)
+    s = IBMSolver(c, precision, max_markers=max(int(c.get("ns", 0)), 1), tape_steps=tape_steps,
+                  noalloc=noalloc)
     rho, u, th = inputs.initial_fields(c, amplitude=amplitude)
     s.init_primitive(rho, u, th)
     if markers and c.get("ns", 0):

@@ -658,8 +658,14 @@ ibm_status create_ctx(const ibm_grid_desc *desc, void *dev_workspace, size_t byt
     ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
     // FP32 form: the FP64 CG on the FP32 psi by default; IBM_FP32_SOLVE=refine
     // selects iterative refinement around an FP32 inner CG
+    // FP32 form: iterative refinement around an FP32 inner CG by default in 3D (its
+    // column kernels halve the bytes of an iteration), the FP64 CG on the FP32 psi in
+    // 2D (there the extra launches of the refinement cost more than the bytes it
+    // saves); IBM_FP32_SOLVE=refine or =fp64 chooses either
     const char *fs = std::getenv("IBM_FP32_SOLVE");
-    ctx->L.refine32 = (fs && std::strcmp(fs, "refine") == 0) ? 1 : 0;
+    ctx->L.refine32 = (fs && std::strcmp(fs, "refine") == 0) ? 1
+                      : (fs && std::strcmp(fs, "fp64") == 0) ? 0
+                      : (desc->dim == 3 ? 1 : 0);
     // 3D pressure CG by z-columns; IBM_CG3D=tile selects the tile-wise iteration
     const char *c3 = std::getenv("IBM_CG3D");
     ctx->L.cg_col = (c3 && std::strcmp(c3, "tile") == 0) ? 0 : 1;

@@ -940,6 +940,40 @@ __device__ __forceinline__ int col_resolve(const GridK &g, int d, int v, double 
   return v < 0 ? 0 : (v >= n ? n - 1 : v);
 }
 
+// The halo slot of this thread in a tile (tx, ty) of the column kernels: threads
+// 0..kColHalo-1 take rows y = -1 and kColTY, then columns x = -1 and kColTX; their
+// cell (resolved into the box, in plane 0) and the sign of its ghost rule.
+__device__ __forceinline__ void col_halo_slot(const GridK &g, int tx, int ty, int &hslot,
+                                              int64_t &hcol, double &hsig) {
+  if (threadIdx.x >= kColHalo) return;
+  const int t = threadIdx.x;
+  int hx, hy;
+  if (t < kColTX) {
+    hx = t;
+    hy = -1;
+  } else if (t < 2 * kColTX) {
+    hx = t - kColTX;
+    hy = kColTY;
+  } else if (t < 2 * kColTX + kColTY) {
+    hx = -1;
+    hy = t - 2 * kColTX;
+  } else {
+    hx = kColTX;
+    hy = t - 2 * kColTX - kColTY;
+  }
+  double s1, s2;
+  hcol = col_resolve(g, 0, tx * kColTX + hx, s1) +
+         (int64_t)g.n[0] * col_resolve(g, 1, ty * kColTY + hy, s2);
+  hsig = s1 * s2;
+  hslot = (hy + 1) * kColPitch + (hx + 1);
+}
+
+// FP32 form's solve by refinement (see k_mcg_iter): an inner solve stops at 1e-4 of
+// its start residual (or kInnerMax iterations); the stages of its kernels.
+constexpr double kInnerTol2 = 1e-8;
+constexpr int kInnerMax = 60;
+enum { MS_INNER = 0, MS_START = 1, MS_FIRST = 2 };
+
 // Loads of one plane of a thread's own column.
 struct ColLoad {
   double r, w, s, p, x, ps, sg;
@@ -1116,13 +1150,16 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col(
 // with a one-cell halo are shared through LDS, m^_z and x of planes k-1, k, k+1 of
 // a thread's own column stay in registers. Boundary faces take face_from_cells'
 // rules; x beyond a side holds the homogeneous ghost of the pressure operator.
-template <typename S>
+// REF32 (the FP32 form's solve by refinement, S = float): the start residual goes to
+// the inner solve as FP32 (r32) with its FP64 r.r as the outer partial, and the
+// solve's first kernel is a refinement-start stage.
+template <typename S, bool REF32 = false>
 __global__ __launch_bounds__(kColThreads) void k_setup_col(
     GridK g, int tiles_x, int tiles_y, int zc, int64_t items, const S *__restrict__ rho_n,
     const S *__restrict__ mh0, const S *__restrict__ mh1, const S *__restrict__ mh2,
     S *__restrict__ Fh0, S *__restrict__ Fh1, S *__restrict__ Fh2, const S *__restrict__ psi,
     const double *__restrict__ x, double *__restrict__ b, double *__restrict__ r0,
-    double *partials, CgScal *cs, int tag) {
+    float *__restrict__ r32, double *partials, CgScal *cs, int tag) {
   __shared__ double lds[32];
   __shared__ S mx_lds[2][kColSlots];
   __shared__ S my_lds[2][kColSlots];
@@ -1145,7 +1182,7 @@ __global__ __launch_bounds__(kColThreads) void k_setup_col(
     if (bc == BC_SLIP) return S(0);
     return m_c;
   };
-  double bb = 0.0;
+  double bb = 0.0, rr = 0.0;
   for (int64_t item = rank; item < items; item += nb) {
     const int tx = (int)(item % tiles_x);
     const int64_t rest = item / tiles_x;
@@ -1160,28 +1197,7 @@ __global__ __launch_bounds__(kColThreads) void k_setup_col(
     int hslot = -1;
     int64_t hcol = 0;
     double hsig = 1.0;
-    if (threadIdx.x < kColHalo) {
-      const int t = threadIdx.x;
-      int hx, hy;
-      if (t < kColTX) {
-        hx = t;
-        hy = -1;
-      } else if (t < 2 * kColTX) {
-        hx = t - kColTX;
-        hy = kColTY;
-      } else if (t < 2 * kColTX + kColTY) {
-        hx = -1;
-        hy = t - 2 * kColTX;
-      } else {
-        hx = kColTX;
-        hy = t - 2 * kColTX - kColTY;
-      }
-      double s1, s2;
-      hcol = col_resolve(g, 0, tx * kColTX + hx, s1) +
-             (int64_t)n0 * col_resolve(g, 1, ty * kColTY + hy, s2);
-      hsig = s1 * s2;
-      hslot = (hy + 1) * kColPitch + (hx + 1);
-    }
+    col_halo_slot(g, tx, ty, hslot, hcol, hsig);
     // own column: m^_z and x of a plane (any plane, resolved), and the rest of a
     // plane inside the chunk
     struct Own {
@@ -1304,7 +1320,13 @@ __global__ __launch_bounds__(kColThreads) void k_setup_col(
         lap += gf * ih2;
         const double ax = double(A.ps) * xc - dt2 * lap;
         b[c] = bc_;
-        r0[c] = bc_ - ax;
+        const double res = bc_ - ax;
+        if (REF32) {
+          r32[c] = float(res);
+          rr += res * res;
+        } else {
+          r0[c] = res;
+        }
         bb += bc_ * bc_;
       }
       mz_m = A.mz;
@@ -1317,14 +1339,22 @@ __global__ __launch_bounds__(kColThreads) void k_setup_col(
     }
     __syncthreads();
   }
-  bb = block_sum(bb, lds);
+  double v2[2] = {bb, rr};
+  block_sum_n<2>(v2, lds);
   if (threadIdx.x == 0) {
-    partials[PART_BB * kMaxBlocks + blockIdx.x] = bb;
+    partials[PART_BB * kMaxBlocks + blockIdx.x] = v2[0];
+    if (REF32) partials[PART_O * kMaxBlocks + blockIdx.x] = v2[1];
     if (blockIdx.x == 0) {
       cs->done = 0;
       cs->iters = 0;
       cs->step_tag = tag;
       cs->xfinal = 0;
+      if (REF32) {
+        cs->outer[0] = MS_START;
+        cs->xpar[0] = 0;
+        cs->inner_it[0] = 0;
+        cs->rr_in0[0] = 0.0;
+      }
     }
   }
 }
@@ -2138,9 +2168,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_dens_finish(GridK g, const S 
 // solve ends when the FP64 residual meets |r| <= rtol |b|. One kernel per
 // iteration: an inner CG iteration, or a refinement that also starts the next
 // inner solve (w = A r of the new FP32 residual).
-constexpr double kInnerTol2 = 1e-8;
-constexpr int kInnerMax = 60;
-enum { MS_INNER = 0, MS_START = 1, MS_FIRST = 2 };  // stages, see k_mcg_iter
 
 // Set-up of the FP32 form: as k_setup2, with the FP64 start residual
 // handed to the inner solve as FP32 (r32) and its FP64 r.r as the outer partial.
@@ -2243,18 +2270,24 @@ __device__ __forceinline__ float helm32_at(const GridK &g, const float *psi, VF 
 //  MS_INNER: inner single-reduction iteration, or, once the inner residual is 1e-4
 //            of its start or meets the outer tolerance, a refinement: x' = x + d,
 //            r = b - A x' in FP64, r32 = r, partial of r.r (-> MS_START).
-template <int DIM>
-__global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
-    GridK g, int it, const float *__restrict__ psi, const double *__restrict__ b, double *x0,
-    double *x1, const float *__restrict__ r, const float *__restrict__ w,
-    const float *__restrict__ sold, float *__restrict__ rn, float *__restrict__ wn,
-    float *__restrict__ snew, float *__restrict__ p, float *__restrict__ d, double *partials,
-    CgScal *cs, const int *flags, uint64_t *progress) {
-  __shared__ double lds[32];
-  __shared__ int done0;
+// The step of a kernel of the refinement solve: its stage, whether an inner solve
+// ends in a refinement, the inner CG's step lengths, the x buffer in use.
+struct McgStep {
+  int stage;
+  bool refine;
+  double alpha, beta;
+  int xp;
+};
+
+// The common start of the refinement solve's kernels: the sums of the previous
+// kernel's partials, the stage's tests, and block 0's record of the scalars (the
+// progress word posted to the host). False once the solve has ended.
+__device__ __forceinline__ bool mcg_head(int it, const double *partials, CgScal *cs,
+                                         const int *flags, uint64_t *progress, double *lds,
+                                         int &done0, McgStep &ms) {
   if (threadIdx.x == 0) done0 = cs->done;
   __syncthreads();
-  if (done0) return;
+  if (done0) return false;
   const int nb = gridDim.x, sl = it & 1, sn = sl ^ 1;
   const int stage = cs->outer[sl];
   double gd[2] = {0.0, 0.0}, rro = 0.0;
@@ -2323,7 +2356,44 @@ __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
       __hip_atomic_store(progress, pack_progress(cs->step_tag, it, err, conv ? 1 : out ? 2 : 0),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
-  if (conv || out) return;
+  ms.stage = stage;
+  ms.refine = refine;
+  ms.alpha = alpha;
+  ms.beta = beta;
+  ms.xp = xp;
+  return !(conv || out);
+}
+
+// The common end: the partials for the next kernel (the FP64 r.r of a refinement, or
+// the inner CG's r.r and w.r).
+__device__ __forceinline__ void mcg_tail(int it, const McgStep &ms, double *sums,
+                                         double *partials, double *lds) {
+  const int sn = (it & 1) ^ 1;
+  block_sum_n<2>(sums, lds);
+  if (threadIdx.x == 0) {
+    if (ms.refine) {
+      partials[(PART_O + sn) * kMaxBlocks + blockIdx.x] = sums[0];
+    } else {
+      partials[(PART_G + sn) * kMaxBlocks + blockIdx.x] = sums[0];
+      partials[(PART_D + sn) * kMaxBlocks + blockIdx.x] = sums[1];
+    }
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
+    GridK g, int it, const float *__restrict__ psi, const double *__restrict__ b, double *x0,
+    double *x1, const float *__restrict__ r, const float *__restrict__ w,
+    const float *__restrict__ sold, float *__restrict__ rn, float *__restrict__ wn,
+    float *__restrict__ snew, float *__restrict__ p, float *__restrict__ d, double *partials,
+    CgScal *cs, const int *flags, uint64_t *progress) {
+  __shared__ double lds[32];
+  __shared__ int done0;
+  McgStep ms;
+  if (!mcg_head(it, partials, cs, flags, progress, lds, done0, ms)) return;
+  const int stage = ms.stage, xp = ms.xp;
+  const bool refine = ms.refine;
+  const double alpha = ms.alpha, beta = ms.beta;
   int64_t t0, t1;
   block_tiles(g, t0, t1);
   double sums[2] = {0.0, 0.0};
@@ -2385,15 +2455,188 @@ __global__ __launch_bounds__(kBlockThreads) void k_mcg_iter(
       sums[1] += double(wnc) * double(rnc);
     }
   }
-  block_sum_n<2>(sums, lds);
-  if (threadIdx.x == 0) {
-    if (refine) {
-      partials[(PART_O + sn) * kMaxBlocks + blockIdx.x] = sums[0];
-    } else {
-      partials[(PART_G + sn) * kMaxBlocks + blockIdx.x] = sums[0];
-      partials[(PART_D + sn) * kMaxBlocks + blockIdx.x] = sums[1];
+  mcg_tail(it, ms, sums, partials, lds);
+}
+
+// ------------------------------ FP32 form's refinement solve by z-columns (3D)
+// The stages of k_mcg_iter (same head, same arithmetic) with the sweeps of the
+// column kernels: a block owns a kColTX x kColTY tile and walks a chunk of planes,
+// the stencil variable of planes k-1, k, k+1 of a thread's column in registers and
+// its x-y neighbours through an LDS plane with a one-cell halo.
+enum { MC_START = 0, MC_FIRST = 1, MC_INNER = 2, MC_REFINE = 3 };
+
+template <int KIND>
+__device__ __forceinline__ void mcg_col_sweep(const GridK &g, int tiles_x, int tiles_y, int zc,
+                                              int64_t items, float af, float bf,
+                                              const float *__restrict__ psi,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ xo,
+                                              double *__restrict__ xnew,
+                                              const float *__restrict__ r,
+                                              const float *__restrict__ w,
+                                              const float *__restrict__ sold,
+                                              float *__restrict__ rn, float *__restrict__ wn,
+                                              float *__restrict__ snew, float *__restrict__ p,
+                                              float *__restrict__ d, double *plane_mem,
+                                              double *sums) {
+  using V = typename std::conditional<KIND == MC_REFINE, double, float>::type;
+  V(*plane_lds)[kColSlots] = reinterpret_cast<V(*)[kColSlots]>(plane_mem);
+  const int lx = threadIdx.x % kColTX, ly = threadIdx.x / kColTX;
+  const int64_t nb = gridDim.x, bk = blockIdx.x;
+  const int64_t rank = (bk & 7) * (nb >> 3) + (bk >> 3);
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const int64_t pl = (int64_t)n0 * n1;
+  const V ih0 = V(g.ih[0]), ih1 = V(g.ih[1]), ih2 = V(g.ih[2]);
+  const int myslot = (ly + 1) * kColPitch + (lx + 1);
+  // one plane of a thread's own column: the stencil variable and what the cell's
+  // update needs
+  struct Own {
+    V v;
+    float r, w, s, pp, dd, ps;
+    double x, bv;
+  };
+  auto value = [&](int64_t c) -> V {
+    if (KIND == MC_START) return V(r[c]);
+    if (KIND == MC_FIRST) return V(r[c] - af * w[c]);
+    if (KIND == MC_INNER) return V(r[c] - af * (w[c] + bf * sold[c]));
+    return V(xo[c] + double(d[c]));
+  };
+  for (int64_t item = rank; item < items; item += nb) {
+    const int tx = (int)(item % tiles_x);
+    const int64_t rest = item / tiles_x;
+    const int ty = (int)(rest % tiles_y);
+    const int ch = (int)(rest / tiles_y);
+    const int i = tx * kColTX + lx, j = ty * kColTY + ly;
+    const int k0 = ch * zc, k1 = min(k0 + zc, n2);
+    const bool inside = i < n0 && j < n1;
+    double sx, sy;
+    const int64_t col = col_resolve(g, 0, i, sx) + (int64_t)n0 * col_resolve(g, 1, j, sy);
+    const double sxy = sx * sy;
+    int hslot = -1;
+    int64_t hcol = 0;
+    double hsig = 1.0;
+    col_halo_slot(g, tx, ty, hslot, hcol, hsig);
+    auto load = [&](int k, Own &o) {
+      double sz;
+      const int64_t c = col + pl * col_resolve(g, 2, k, sz);
+      o.v = V(sxy * sz) * value(c);
+      if (inside && k >= k0 && k < k1) {
+        o.ps = psi[c];
+        if (KIND == MC_REFINE) {
+          o.x = xo[c] + double(d[c]);
+          o.bv = b[c];
+        } else {
+          o.r = r[c];
+          if (KIND != MC_START) o.w = w[c];
+          if (KIND == MC_INNER) {
+            o.s = sold[c];
+            o.pp = p[c];
+            o.dd = d[c];
+          }
+        }
+      }
+    };
+    auto load_halo = [&](int k, V &hv) {
+      if (hslot < 0) return;
+      double sz;
+      const int64_t c = hcol + pl * col_resolve(g, 2, k, sz);
+      hv = V(hsig * sz) * value(c);
+    };
+    Own A, B, C, M;
+    load(k0 - 1, M);
+    load(k0, A);
+    load(k0 + 1, B);
+    V hv = V(0);
+    load_halo(k0, hv);
+    V vm = M.v;
+    for (int k = k0; k < k1; ++k) {
+      V hv2 = V(0);
+      if (k + 2 <= k1) load(k + 2, C);
+      if (k + 1 < k1) load_halo(k + 1, hv2);
+      V *lp = plane_lds[(k - k0) & 1];
+      lp[myslot] = A.v;
+      if (hslot >= 0) lp[hslot] = hv;
+      __syncthreads();
+      if (inside) {
+        const V vc = A.v;
+        V lap = V(0), gf;
+        gf = (lp[myslot - 1] - vc) * ih0;
+        lap += gf * ih0;
+        gf = (lp[myslot + 1] - vc) * ih0;
+        lap += gf * ih0;
+        gf = (lp[myslot - kColPitch] - vc) * ih1;
+        lap += gf * ih1;
+        gf = (lp[myslot + kColPitch] - vc) * ih1;
+        lap += gf * ih1;
+        gf = (vm - vc) * ih2;
+        lap += gf * ih2;
+        gf = (B.v - vc) * ih2;
+        lap += gf * ih2;
+        const int64_t c = col + pl * k;
+        if (KIND == MC_REFINE) {
+          const double ax = double(A.ps) * double(vc) - g.dt * g.dt * double(lap);
+          const double rc = A.bv - ax;
+          xnew[c] = A.x;
+          rn[c] = float(rc);
+          sums[0] += rc * rc;
+        } else {
+          const float wc = A.ps * float(vc) - float(g.dt * g.dt) * float(lap);
+          if (KIND == MC_START) {
+            rn[c] = A.r;
+          } else {
+            const float pc = KIND == MC_FIRST ? A.r : A.r + bf * A.pp;
+            const float sc = KIND == MC_FIRST ? A.w : A.w + bf * A.s;
+            if (KIND == MC_FIRST)
+              d[c] = af * pc;
+            else
+              d[c] = A.dd + af * pc;
+            p[c] = pc;
+            snew[c] = sc;
+            rn[c] = float(vc);
+          }
+          wn[c] = wc;
+          sums[0] += double(float(vc)) * double(float(vc));
+          sums[1] += double(wc) * double(float(vc));
+        }
+      }
+      vm = A.v;
+      A = B;
+      B = C;
+      hv = hv2;
     }
+    __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kColThreads) void k_mcg_col(
+    GridK g, int it, int tiles_x, int tiles_y, int zc, int64_t items,
+    const float *__restrict__ psi, const double *__restrict__ b, double *x0, double *x1,
+    const float *__restrict__ r, const float *__restrict__ w, const float *__restrict__ sold,
+    float *__restrict__ rn, float *__restrict__ wn, float *__restrict__ snew,
+    float *__restrict__ p, float *__restrict__ d, double *partials, CgScal *cs,
+    const int *flags, uint64_t *progress) {
+  __shared__ double lds[32];
+  __shared__ int done0;
+  __shared__ double plane_mem[2 * kColSlots];
+  McgStep m;
+  if (!mcg_head(it, partials, cs, flags, progress, lds, done0, m)) return;
+  double sums[2] = {0.0, 0.0};
+  const float af = float(m.alpha), bf = float(m.beta);
+  const double *xo = m.xp ? x1 : x0;
+  double *xn = m.xp ? x0 : x1;
+  if (m.stage == MS_START)
+    mcg_col_sweep<MC_START>(g, tiles_x, tiles_y, zc, items, af, bf, psi, b, xo, xn, r, w, sold,
+                            rn, wn, snew, p, d, plane_mem, sums);
+  else if (m.refine)
+    mcg_col_sweep<MC_REFINE>(g, tiles_x, tiles_y, zc, items, af, bf, psi, b, xo, xn, r, w, sold,
+                             rn, wn, snew, p, d, plane_mem, sums);
+  else if (m.stage == MS_FIRST)
+    mcg_col_sweep<MC_FIRST>(g, tiles_x, tiles_y, zc, items, af, bf, psi, b, xo, xn, r, w, sold,
+                            rn, wn, snew, p, d, plane_mem, sums);
+  else
+    mcg_col_sweep<MC_INNER>(g, tiles_x, tiles_y, zc, items, af, bf, psi, b, xo, xn, r, w, sold,
+                            rn, wn, snew, p, d, plane_mem, sums);
+  mcg_tail(it, m, sums, partials, lds);
 }
 
 // Pressure with its ghost rule (zero gradient at inflow and slip, p_inf on
@@ -2474,6 +2717,171 @@ __global__ __launch_bounds__(kBlockThreads) void k_correct(GridK g, StateV<S> cu
   }
   double s = block_sum(m, lds);
   if (threadIdx.x == 0) partials[PART_MASS * kMaxBlocks + blockIdx.x] = s;
+}
+
+// 3D correction by z-columns (k_correct's arithmetic, in the same order): a block
+// owns a kColTX x kColTY tile and walks a chunk of planes; the pressure of a plane
+// with a one-cell halo is shared through LDS, that of planes k-1 and k+1 of a
+// thread's own column stays in registers. Beyond a side the pressure takes its ghost
+// rule (zero gradient at inflow and slip, p_inf on the face at outflow); periodic
+// directions wrap.
+template <typename S>
+__global__ __launch_bounds__(kColThreads) void k_correct_col(
+    GridK g, int tiles_x, int tiles_y, int zc, int64_t items, StateV<S> cur, StateV<S> nxt,
+    const S *__restrict__ rho_s, const S *__restrict__ E_s, const S *__restrict__ mh0,
+    const S *__restrict__ mh1, const S *__restrict__ mh2, const S *__restrict__ Fh0,
+    const S *__restrict__ Fh1, const S *__restrict__ Fh2, const double *xa, const double *xb,
+    double *partials, int *flags, const CgScal *cs, int tag) {
+  __shared__ double lds[32];
+  __shared__ int skip;
+  __shared__ double x_lds[2][kColSlots];
+  // as k_correct: only after a finished solve of this step and while no earlier step
+  // has failed
+  const int xfinal = cs->xfinal;
+  if (threadIdx.x == 0)
+    skip = cs->step_tag != tag || cs->done == 0 || flags[FLAG_NONFINITE] ||
+           flags[FLAG_SUPPORT] || flags[FLAG_EPS] || flags[FLAG_GRAM];
+  __syncthreads();
+  if (skip) return;
+  const double *x = xfinal ? xb : xa;
+  const int lx = threadIdx.x % kColTX, ly = threadIdx.x / kColTX;
+  const int64_t nb = gridDim.x, bk = blockIdx.x;
+  const int64_t rank = (bk & 7) * (nb >> 3) + (bk >> 3);
+  const int n0 = g.n[0], n1 = g.n[1], n2 = g.n[2];
+  const int64_t pl = (int64_t)n0 * n1;
+  const int fx0 = g.fn[0][0];
+  const int64_t fpl1 = (int64_t)n0 * g.fn[1][1];
+  const double dt = g.dt, p2 = 2.0 * g.p_inf;
+  const double ih0 = g.ih[0], ih1 = g.ih[1], ih2 = g.ih[2];
+  const int myslot = (ly + 1) * kColPitch + (lx + 1);
+  // ghost of the pressure from the mirror value and the side's sign (-1: outflow)
+  auto ghost = [&](double v, double sg) { return sg < 0.0 ? p2 - v : v; };
+  double mass = 0.0;
+  bool bad = false;
+  for (int64_t item = rank; item < items; item += nb) {
+    const int tx = (int)(item % tiles_x);
+    const int64_t rest = item / tiles_x;
+    const int ty = (int)(rest % tiles_y);
+    const int ch = (int)(rest / tiles_y);
+    const int i = tx * kColTX + lx, j = ty * kColTY + ly;
+    const int k0 = ch * zc, k1 = min(k0 + zc, n2);
+    const bool inside = i < n0 && j < n1;
+    double sx, sy;
+    const int64_t col = col_resolve(g, 0, i, sx) + (int64_t)n0 * col_resolve(g, 1, j, sy);
+    const double sxy = sx * sy;
+    int hslot = -1;
+    int64_t hcol = 0;
+    double hsig = 1.0;
+    col_halo_slot(g, tx, ty, hslot, hcol, hsig);
+    struct Own {
+      double x;
+      S fxl, fxh, fyl, fyh, fzl, fzh, m0, m1, m2, rs, es, rn;
+    };
+    auto load = [&](int k, Own &o) {
+      double sz;
+      const int64_t c = col + pl * col_resolve(g, 2, k, sz);
+      o.x = ghost(x[c], sxy * sz);
+      if (inside && k >= k0 && k < k1) {
+        const int64_t fx = i + (int64_t)fx0 * (j + (int64_t)n1 * k);
+        const int64_t fy = i + (int64_t)n0 * j + fpl1 * k;
+        o.fxl = Fh0[fx];
+        o.fxh = Fh0[fx + 1];
+        o.fyl = Fh1[fy];
+        o.fyh = Fh1[fy + n0];
+        o.fzl = Fh2[c];
+        o.fzh = Fh2[c + pl];
+        o.m0 = mh0[c];
+        o.m1 = mh1[c];
+        o.m2 = mh2[c];
+        o.rs = rho_s[c];
+        o.es = E_s[c];
+        o.rn = cur.rho[c];
+      }
+    };
+    auto load_halo = [&](int k, double &hv) {
+      if (hslot < 0) return;
+      double sz;
+      const int64_t c = hcol + pl * col_resolve(g, 2, k, sz);
+      hv = ghost(x[c], hsig * sz);
+    };
+    Own A, B, C, M;
+    load(k0 - 1, M);
+    load(k0, A);
+    load(k0 + 1, B);
+    double hv = 0.0;
+    load_halo(k0, hv);
+    double xm = M.x;
+    for (int k = k0; k < k1; ++k) {
+      double hv2 = 0.0;
+      if (k + 2 <= k1) load(k + 2, C);
+      if (k + 1 < k1) load_halo(k + 1, hv2);
+      double *lp = x_lds[(k - k0) & 1];
+      lp[myslot] = A.x;
+      if (hslot >= 0) lp[hslot] = hv;
+      __syncthreads();
+      if (inside) {
+        const int64_t c = col + pl * k;
+        const double xc = A.x;
+        double div = 0.0;
+        // x
+        {
+          const double xl = lp[myslot - 1], xh = lp[myslot + 1];
+          const double Fl = double(A.fxl) - dt * ((xc - xl) * ih0);
+          const double Fu = double(A.fxh) - dt * ((xh - xc) * ih0);
+          const int64_t f = i + (int64_t)fx0 * (j + (int64_t)n1 * k);
+          nxt.F[0][f] = S(Fl);
+          if (i == n0 - 1) nxt.F[0][f + 1] = S(Fu);
+          div += (Fu - Fl) * ih0;
+          const double mn = double(A.m0) - dt * ((xh - xl) * (0.5 * ih0));
+          nxt.mom[0][c] = S(mn);
+          bad = bad || !isfinite(mn);
+        }
+        // y
+        {
+          const double xl = lp[myslot - kColPitch], xh = lp[myslot + kColPitch];
+          const double Fl = double(A.fyl) - dt * ((xc - xl) * ih1);
+          const double Fu = double(A.fyh) - dt * ((xh - xc) * ih1);
+          const int64_t f = i + (int64_t)n0 * j + fpl1 * k;
+          nxt.F[1][f] = S(Fl);
+          if (j == n1 - 1) nxt.F[1][f + n0] = S(Fu);
+          div += (Fu - Fl) * ih1;
+          const double mn = double(A.m1) - dt * ((xh - xl) * (0.5 * ih1));
+          nxt.mom[1][c] = S(mn);
+          bad = bad || !isfinite(mn);
+        }
+        // z
+        {
+          const double xl = xm, xh = B.x;
+          const double Fl = double(A.fzl) - dt * ((xc - xl) * ih2);
+          const double Fu = double(A.fzh) - dt * ((xh - xc) * ih2);
+          nxt.F[2][c] = S(Fl);
+          if (k == n2 - 1) nxt.F[2][c + pl] = S(Fu);
+          div += (Fu - Fl) * ih2;
+          const double mn = double(A.m2) - dt * ((xh - xl) * (0.5 * ih2));
+          nxt.mom[2][c] = S(mn);
+          bad = bad || !isfinite(mn);
+        }
+        const double rn = double(A.rn) - dt * div;
+        const double theta = double(A.es / (A.rs * S(g.cv)));
+        const double En = rn * g.cv * theta;
+        nxt.rho[c] = S(rn);
+        nxt.E[c] = S(En);
+        bad = bad || !(rn > 0.0) || !(theta > 0.0) || !isfinite(rn) || !isfinite(En);
+        mass += rn * g.dV;
+      }
+      xm = A.x;
+      A = B;
+      B = C;
+      hv = hv2;
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    atomicOr(flags + FLAG_NONFINITE, 1);
+    atomicCAS(flags + FLAG_BAD_STEP, 0, tag + 1);
+  }
+  double sm = block_sum(mass, lds);
+  if (threadIdx.x == 0) partials[PART_MASS * kMaxBlocks + blockIdx.x] = sm;
 }
 
 // One block: the sum of per-block partials into a scalar.
@@ -2620,6 +3028,18 @@ void col_plan(const GridK &g, int &tiles_x, int &tiles_y, int &zc, int64_t &item
 }
 
 void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
+  if (L.prec == 1 && L.refine32 && L.g.dim == 3 && L.cg_col) {
+    int tx, ty, zc, nbk;
+    int64_t items;
+    col_plan(L.g, tx, ty, zc, items, nbk);
+    hipLaunchKernelGGL((k_setup_col<float, true>), dim3((unsigned)nbk), dim3(kColThreads), 0,
+                       L.st, L.g, tx, ty, zc, items, (const float *)B.rho[cur],
+                       (const float *)B.mhat[0], (const float *)B.mhat[1],
+                       (const float *)B.mhat[2], (float *)B.Fhat[0], (float *)B.Fhat[1],
+                       (float *)B.Fhat[2], (const float *)B.psi, (const double *)B.x, B.b,
+                       (double *)nullptr, B.rv32[0], B.partials, B.cg, tag);
+    return;
+  }
   if (L.prec == 1 && L.refine32) {
     if (L.g.dim == 2)
       hipLaunchKernelGGL((k_setup2m<2>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st,
@@ -2645,7 +3065,7 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
                          tx, ty, zc, items, (const S *)B.rho[cur], (const S *)B.mhat[0],
                          (const S *)B.mhat[1], (const S *)B.mhat[2], (S *)B.Fhat[0],
                          (S *)B.Fhat[1], (S *)B.Fhat[2], (const S *)B.psi, (const double *)B.x,
-                         B.b, B.rv[0], B.partials, B.cg, tag);
+                         B.b, B.rv[0], (float *)nullptr, B.partials, B.cg, tag);
     };
     if (L.prec == 0) go(double{}); else go(float{});
     run_cg_start(L, B);
@@ -2694,6 +3114,17 @@ int cg_parts(const Launch &) { return 1; }
 template <int DIM>
 static void run_mcg_iter(const Launch &L, const Bufs &B, int it) {
   const int a = it & 1, b = a ^ 1;
+  if (DIM == 3 && L.cg_col) {
+    int tx, ty, zc, nbk;
+    int64_t items;
+    col_plan(L.g, tx, ty, zc, items, nbk);
+    hipLaunchKernelGGL(k_mcg_col, dim3((unsigned)nbk), dim3(kColThreads), 0, L.st, L.g, it, tx,
+                       ty, zc, items, (const float *)B.psi, (const double *)B.b, B.x, B.x2,
+                       (const float *)B.rv32[a], (const float *)B.wv32[a],
+                       (const float *)B.sv32[a], B.rv32[b], B.wv32[b], B.sv32[b], B.pv32, B.d32,
+                       B.partials, B.cg, (const int *)B.flags, B.progress);
+    return;
+  }
   hipLaunchKernelGGL((k_mcg_iter<DIM>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0, L.st, L.g,
                      it, (const float *)B.psi, (const double *)B.b, B.x, B.x2,
                      (const float *)B.rv32[a], (const float *)B.wv32[a], (const float *)B.sv32[a],
@@ -2750,6 +3181,23 @@ void run_cg_iteration(const Launch &L, const Bufs &B, int it) {
 }
 
 void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {
+  if (L.g.dim == 3 && L.cg_col) {
+    int tx, ty, zc, nbk;
+    int64_t items;
+    col_plan(L.g, tx, ty, zc, items, nbk);
+    auto go = [&](auto sdum) {
+      using S = decltype(sdum);
+      hipLaunchKernelGGL((k_correct_col<S>), dim3((unsigned)nbk), dim3(kColThreads), 0, L.st,
+                         L.g, tx, ty, zc, items, state_of<S>(B, cur), state_of<S>(B, cur ^ 1),
+                         (const S *)B.rho_s, (const S *)B.E_s, (const S *)B.mhat[0],
+                         (const S *)B.mhat[1], (const S *)B.mhat[2], (const S *)B.Fhat[0],
+                         (const S *)B.Fhat[1], (const S *)B.Fhat[2], (const double *)B.x,
+                         (const double *)(B.x2 ? B.x2 : B.x), B.partials, B.flags,
+                         (const CgScal *)B.cg, tag);
+    };
+    if (L.prec == 0) go(double{}); else go(float{});
+    return;
+  }
   IBM_DISPATCH(L, {
     hipLaunchKernelGGL((k_correct<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kBlockThreads), 0,
                        L.st, L.g, state_of<S>(B, cur), state_of<S>(B, cur ^ 1),

@@ -1,7 +1,7 @@
 """The FP32 form: FP32 state, stencils and psi; FP64 markers, sums and pressure
-solve (the FP64 CG on the FP32 psi, or with IBM_FP32_SOLVE=refine iterative
-refinement around an FP32 inner CG). Its error against the FP64 oracle is
-measured per result and held to the stated bounds."""
+solve (iterative refinement around an FP32 inner CG, the default in 3D, or the FP64
+CG on the FP32 psi, the default in 2D; IBM_FP32_SOLVE=refine or =fp64 chooses). Its
+error against the FP64 oracle is measured per result and held to the stated bounds."""
 import numpy as np
 import pytest
 
@@ -21,8 +21,7 @@ def _primitives(rho, mom, E, cv):
 @pytest.mark.parametrize("solve", ["fp64_cg", "refine"])
 def test_fp32_form_against_fp64_oracle(cuda, monkeypatch, solve):
     c = inputs.case("cfg1")
-    if solve == "refine":
-        monkeypatch.setenv("IBM_FP32_SOLVE", "refine")
+    monkeypatch.setenv("IBM_FP32_SOLVE", "refine" if solve == "refine" else "fp64")
     g32 = make_gpu(c, precision="fp32")
     monkeypatch.delenv("IBM_FP32_SOLVE", raising=False)
     o = make_oracle(c)
@@ -47,11 +46,22 @@ def test_fp32_form_against_fp64_oracle(cuda, monkeypatch, solve):
     assert e_fx < 1e-4 and e_h < 1e-4
 
 
-def test_fp32_form_3d_runs_close_to_fp64(cuda):
-    c = inputs.scaled("cfg3", (48, 40, 40), ns=400)
-    g32, g64 = make_gpu(c, precision="fp32"), make_gpu(c, precision="fp64")
-    h32, _ = g32.step(10)
+@pytest.mark.parametrize("solve", ["fp64_cg", "refine"])
+@pytest.mark.parametrize("cg3d", ["col", "tile"])
+def test_fp32_form_3d_runs_close_to_fp64(cuda, monkeypatch, solve, cg3d):
+    # both solves of the FP32 form, by z-columns (default) and by tiles, on a ragged
+    # 3D grid; the FP64 outer residual meets rtol
+    c = inputs.scaled("cfg3", (48, 40, 38), ns=400)
+    monkeypatch.setenv("IBM_FP32_SOLVE", "refine" if solve == "refine" else "fp64")
+    if cg3d == "tile":
+        monkeypatch.setenv("IBM_CG3D", "tile")
+    g32 = make_gpu(c, precision="fp32")
+    monkeypatch.delenv("IBM_FP32_SOLVE", raising=False)
+    monkeypatch.delenv("IBM_CG3D", raising=False)
+    g64 = make_gpu(c, precision="fp64")
+    h32, info = g32.step(10)
     h64, _ = g64.step(10)
+    assert info["cg_residual"] <= c["cg_rtol"]
     r32, m32, _, _ = g32.get_state()
     r64, m64, _, _ = g64.get_state()
     assert rel_l2(to_np(m32), to_np(m64)) < 1e-5

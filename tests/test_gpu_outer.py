@@ -84,8 +84,7 @@ def test_outer_passes_predictor_variants_parity(cuda, monkeypatch, variant):
 @pytest.mark.parametrize("solve", ["fp64_cg", "refine"])
 def test_outer_passes_fp32_form(cuda, monkeypatch, solve):
     c = inputs.scaled("cfg1", (97, 78), ns=60, Re=20.0, n_outer=3)
-    if solve == "refine":
-        monkeypatch.setenv("IBM_FP32_SOLVE", "refine")
+    monkeypatch.setenv("IBM_FP32_SOLVE", "refine" if solve == "refine" else "fp64")
     g32 = make_gpu(c, precision="fp32", amplitude=2e-2)
     monkeypatch.delenv("IBM_FP32_SOLVE", raising=False)
     o = make_oracle(c, amplitude=2e-2)

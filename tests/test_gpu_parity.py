@@ -255,3 +255,33 @@ def test_cg_3d_columns_and_tiles_agree(cuda, monkeypatch, shape, bc):
         assert rel_l2(to_np(a), to_np(b)) < 1e-12
     for k, v in state_errors(g["col"], o).items():
         assert v < 1e-11, (k, v)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape,bc", [
+    ((36, 30, 26), None),
+    ((70, 11, 9), [[inputs.INFLOW, inputs.OUTFLOW], [inputs.SLIP, inputs.SLIP],
+                   [inputs.OUTFLOW, inputs.OUTFLOW]]),
+    ((21, 19, 23), [[inputs.PERIODIC] * 2] * 3),
+])
+def test_correction_3d_columns_and_tiles_agree(cuda, monkeypatch, precision, shape, bc):
+    # the 3D set-up, CG and correction by z-columns against the tile kernels, in both
+    # forms (the FP32 form's solve by refinement in both), one step from the same state
+    over = {} if bc is None else {"bc": bc}
+    c = inputs.scaled("cfg3", shape, ns=0 if bc else 200, **over)
+    amp = 1e-2 if bc else 1e-3
+    monkeypatch.setenv("IBM_FP32_SOLVE", "refine")
+    out = {}
+    for mode in ("col", "tile"):
+        if mode == "tile":
+            monkeypatch.setenv("IBM_CG3D", "tile")
+        else:
+            monkeypatch.delenv("IBM_CG3D", raising=False)
+        g = make_gpu(c, precision, amplitude=amp)
+        g.step(1)
+        out[mode] = [to_np(a) for a in g.get_state()[:3]] + [to_np(f) for f in g.get_state()[3]]
+    monkeypatch.delenv("IBM_CG3D", raising=False)
+    monkeypatch.delenv("IBM_FP32_SOLVE", raising=False)
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    for a, b in zip(out["col"], out["tile"]):
+        assert rel_l2(a, b) < tol

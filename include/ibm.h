@@ -171,9 +171,11 @@ size_t ibm_workspace_bytes(const ibm_grid_desc *desc, int32_t max_markers, int32
  * context, 3 p^n - 3 p^{n-1} + p^{n-2} after two, 2 p^n - p^{n-1} after one, p^n
  * otherwise (and after ibm_set_state); IBM_CG_START=quadratic caps the order at the
  * three-point form, IBM_CG_START=linear at the two-point form, IBM_CG_START=plain
- * uses p^n always. Every start converges to the same solution within cg_rtol. An IBM_FP32 context solves
- * for the pressure with the FP64 CG on its FP32 psi; IBM_FP32_SOLVE=refine selects
- * iterative refinement (FP64 x and residual around an FP32 inner CG) instead. */
+ * uses p^n always. Every start converges to the same solution within cg_rtol. An
+ * IBM_FP32 context solves for the pressure by iterative refinement (FP64 x and
+ * residual around an FP32 inner CG) in 3D and with the FP64 CG on its FP32 psi in
+ * 2D; IBM_FP32_SOLVE=refine or IBM_FP32_SOLVE=fp64 selects either. In 3D the FP64
+ * CG iterates by z-columns (IBM_CG3D=tile: by tiles). */
 ibm_status ibm_create_grid(const ibm_grid_desc *desc, void *dev_workspace, size_t bytes,
                            int32_t tape_steps, void *hip_stream, ibm_ctx **out);
 
@@ -231,7 +233,12 @@ ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const doubl
 /* Prescribed motion (Sec. 5, Eq. (19)): at time t every candidate marker sits at
  * X(0) + amplitude sin(2 pi frequency t) e_axis and moves with the derivative of
  * that law added to its U_d. Step n -> n+1 uses t = (n+1) dt; the markers are
- * re-selected, re-sorted and eps re-solved on the device every step.
+ * re-selected, re-sorted and eps re-solved on the device every step, each solve
+ * starting from the candidates' eps of ibm_set_markers (so the markers at a time do
+ * not depend on the steps before). Within an ibm_step call, the next step's markers
+ * are set up on a second stream of the context while the current step's pressure
+ * solve runs (a context on a caller's workspace; IBM_REBUILD=inline in the
+ * environment at creation keeps them on the context's stream).
  * axis < 0 switches motion off. */
 ibm_status ibm_set_motion(ibm_ctx *ctx, int32_t axis, double amplitude, double frequency);
 
@@ -246,7 +253,8 @@ ibm_status ibm_set_wall_temperature(ibm_ctx *ctx, const double *T_w);
  * the fluid H. `info` (host, may be NULL) is filled after a synchronisation.
  * IBM_E_NOT_CONVERGED: the CG hit cg_maxit (the state is advanced, the call
  * stops after that step). IBM_E_NONFINITE: the step produced NaN/Inf or a
- * non-positive density or temperature; the state is the one before that step.
+ * non-positive density or temperature; the state is the one before that step (a
+ * moving body's markers in use and wall fluxes are then those of a later step).
  * With IBM_RECORD each step is stored on the tape (IBM_E_SIZE when full). */
 ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
                     ibm_step_info *info);
@@ -339,11 +347,14 @@ ibm_status ibm_shape_gradient(ibm_ctx *ctx, double *X_bar);
  * iterations that did work, so total / count is the time per iteration, with the
  * launch that detects convergence included in the total), 4 implicit diffusion
  * (face viscosities and the dim + 1 solves, host waits between them included),
- * 5 correction.
+ * 5 correction, 6 a moving body's marker set-up for the next step on the context's
+ * second stream (it overlaps the current step's pressure solve; class 1 then holds
+ * the set-up only where it is on the context's stream: the first step of a call).
  * The events themselves slow a step down; time throughput with timing off.
  * enable != 0 clears the totals and starts timing; 0 stops it. */
 enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG = 3,
-       IBM_PROF_DIFFUSION = 4, IBM_PROF_CORRECT = 5, IBM_PROF_CLASSES = 8 };
+       IBM_PROF_DIFFUSION = 4, IBM_PROF_CORRECT = 5, IBM_PROF_REBUILD = 6,
+       IBM_PROF_CLASSES = 8 };
 ibm_status ibm_profile(ibm_ctx *ctx, int32_t enable);
 
 /* Per-class totals since timing was enabled: ms [IBM_PROF_CLASSES] (host) summed

@@ -102,7 +102,7 @@ SIGNATURES = {
     "ibm_profile_read": (ctypes.c_int, [_P, _D, ctypes.POINTER(ctypes.c_int64)]),
 }
 
-PROF_CLASSES = ["predictor", "markers", "setup", "cg", "diffusion", "correct"]
+PROF_CLASSES = ["predictor", "markers", "setup", "cg", "diffusion", "correct", "rebuild"]
 
 _lib = None
 

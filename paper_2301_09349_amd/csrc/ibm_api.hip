@@ -119,10 +119,25 @@ struct ibm_ctx {
   // device whose static scratch array holds this context's buffers
   // (ibm_create_grid_noalloc), -1 for a caller's workspace
   int scratch_dev = -1;
+  // a moving body's markers for the next step are set up on a second stream (`side`)
+  // while the current step's pressure solve runs: after the last marker kernel of a
+  // step (event ev_used) the side stream rebuilds them for the next step's time, and
+  // the next step's marker kernel waits for ev_built. Contexts on a caller's
+  // workspace only (and not with IBM_REBUILD=inline); created at the first moving step.
+  bool side_ok = true;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_used = nullptr, ev_built = nullptr;
+  bool ahead = false;  // a rebuild is queued on `side` that the main stream has not joined
   std::string err;
   CgScal cgh;
   Prof prof;
   ~ibm_ctx() {
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+    }
+    if (ev_used) (void)hipEventDestroy(ev_used);
+    if (ev_built) (void)hipEventDestroy(ev_built);
     if (B.progress) (void)hipHostFree(B.progress);
   }
 };
@@ -442,8 +457,11 @@ ibm_status sync_read(ibm_ctx *ctx, void *dst, const void *src, size_t bytes) {
   return IBM_OK;
 }
 
-// marker positions of the current step counter, supports, sort, eps
-ibm_status rebuild_markers(ibm_ctx *ctx, double t) {
+// marker positions at time t, supports, sort, eps, on `stream` (NULL: the context's).
+// Only the set-up of a new body saves eps per candidate (the start of every later
+// solve), so that a rebuild depends on t alone and may run ahead on the side stream.
+ibm_status rebuild_markers(ibm_ctx *ctx, double t, bool save_eps = false,
+                           hipStream_t stream = nullptr) {
   double off = 0.0, vel = 0.0;
   int axis = -1;
   if (ctx->motion_axis >= 0) {
@@ -451,8 +469,9 @@ ibm_status rebuild_markers(ibm_ctx *ctx, double t) {
     off = ctx->motion_amp * std::sin(2.0 * kPi * ctx->motion_freq * t);
     vel = ctx->motion_amp * 2.0 * kPi * ctx->motion_freq * std::cos(2.0 * kPi * ctx->motion_freq * t);
   }
-  ibmk::run_place_markers(ctx->L, ctx->B, ctx->nc, off, vel, axis, ctx->dedupe);
-  ibmk::run_build_markers(ctx->L, ctx->B, ctx->nc);
+  Launch L = ctx->L;
+  if (stream) L.st = stream;
+  ibmk::run_rebuild_markers(L, ctx->B, ctx->nc, off, vel, axis, ctx->dedupe, save_eps);
   HIPCHECK(ctx, hipGetLastError());
   return IBM_OK;
 }
@@ -656,8 +675,6 @@ ibm_status create_ctx(const ibm_grid_desc *desc, void *dev_workspace, size_t byt
     const size_t need = ibmk::predictor_lds_bytes(desc->dim, desc->precision);
     const char *env = std::getenv("IBM_PREDICTOR");
     ctx->L.pred_lds = (need <= (size_t)maxsh) && !(env && std::strcmp(env, "plain") == 0);
-    // FP32 form: the FP64 CG on the FP32 psi by default; IBM_FP32_SOLVE=refine
-    // selects iterative refinement around an FP32 inner CG
     // FP32 form: iterative refinement around an FP32 inner CG by default in 3D (its
     // column kernels halve the bytes of an iteration), the FP64 CG on the FP32 psi in
     // 2D (there the extra launches of the refinement cost more than the bytes it
@@ -674,6 +691,11 @@ ibm_status create_ctx(const ibm_grid_desc *desc, void *dev_workspace, size_t byt
                              : std::strcmp(cgs, "linear") == 0 ? 1
                              : std::strcmp(cgs, "quadratic") == 0 ? 2 : 3;
     if (ctx->L.pred_lds && need > 65536) ibmk::enable_predictor_lds(desc->dim, desc->precision);
+    // a moving body's markers set up ahead on a second stream; IBM_REBUILD=inline
+    // keeps them on the context's stream (a context without its own allocations
+    // always does)
+    const char *rb = std::getenv("IBM_REBUILD");
+    ctx->side_ok = pinned && !(rb && std::strcmp(rb, "inline") == 0);
   }
   ctx->tape_cap = tape_steps;
   size_t need = plan(*desc, ctx->L.g, desc->max_markers, tape_steps, (char *)dev_workspace, ctx->B,
@@ -916,7 +938,7 @@ ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const doubl
   ctx->nc = n;
   ctx->dedupe = (flags & IBM_DEDUPE) ? 1 : 0;
   ctx->L.g.no_heat = (flags & IBM_NO_HEAT) ? 1 : 0;
-  ibm_status s = rebuild_markers(ctx, double(ctx->step) * ctx->L.g.dt);
+  ibm_status s = rebuild_markers(ctx, double(ctx->step) * ctx->L.g.dt, true);
   if (s) {
     ctx->nc = 0;
     return s;
@@ -1007,6 +1029,51 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       P.pending.push_back({IBM_PROF_CG, it0, count, a, b});
     }
   };
+  // A moving body: each step's markers are set up at its start on the main stream,
+  // or, when the step before queued them on the side stream, the step's marker kernel
+  // waits for them (ahead_join). After a step's last marker kernel, the next step's
+  // markers (time (step + 2) dt) are queued on the side stream, within the call.
+  const bool moving = ctx->nc > 0 && ctx->motion_axis >= 0;
+  if (moving && ctx->side_ok && !ctx->side) {
+    HIPCHECK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIPCHECK(ctx, hipEventCreateWithFlags(&ctx->ev_used, hipEventDisableTiming));
+    HIPCHECK(ctx, hipEventCreateWithFlags(&ctx->ev_built, hipEventDisableTiming));
+  }
+  const bool use_side = moving && ctx->side != nullptr;
+  auto ahead_join = [&]() -> hipError_t {
+    if (!ctx->ahead) return hipSuccess;
+    ctx->ahead = false;
+    return hipStreamWaitEvent(st, ctx->ev_built, 0);
+  };
+  // an early return still leaves the main stream behind the side stream's work
+  struct AheadGuard {
+    ibm_ctx *c;
+    ~AheadGuard() {
+      if (c->ahead) {
+        c->ahead = false;
+        (void)hipStreamWaitEvent(c->L.st, c->ev_built, 0);
+      }
+    }
+  } ahead_guard{ctx};
+  auto rebuild_ahead = [&](int64_t next_step) -> ibm_status {
+    HIPCHECK(ctx, hipEventRecord(ctx->ev_used, st));
+    HIPCHECK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_used, 0));
+    ibm_status ms = IBM_OK;
+    hipEvent_t a = P.on ? P.mark(ctx->side) : nullptr;
+    ms = rebuild_markers(ctx, double(next_step + 1) * L.g.dt, false, ctx->side);
+    if (P.on) P.pending.push_back({IBM_PROF_REBUILD, 0, 1, a, P.mark(ctx->side)});
+    if (ms) return ms;
+    HIPCHECK(ctx, hipEventRecord(ctx->ev_built, ctx->side));
+    ctx->ahead = true;
+    return IBM_OK;
+  };
+  // the markers of the step starting now: queued by the step before, or set up here
+  auto step_markers = [&]() -> ibm_status {
+    if (!moving || ctx->ahead) return IBM_OK;
+    ibm_status ms = IBM_OK;
+    timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
+    return ms;
+  };
   // Flags are sticky for the whole call: a step that fails keeps every later step
   // from writing the state, so the state it started from survives.
   HIPCHECK(ctx, hipMemsetAsync(B.flags, 0, 8 * sizeof(int), st));
@@ -1019,16 +1086,19 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     // result, the new state; nothing waits for the host
     for (int s = 0; s < n_steps; ++s) {
       const int tag = ++ctx->tag;
-      if (ctx->nc > 0 && ctx->motion_axis >= 0) {
-        ibm_status ms = IBM_OK;
-        timed(IBM_PROF_MARKERS, 0,
-              [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
+      {
+        ibm_status ms = step_markers();
         if (ms) return ms;
       }
       timed(IBM_PROF_PREDICTOR, 0, [&] { ibmk::run_density_predictor(L, B, ctx->cur); });
       double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
       if (ctx->nc > 0) {
+        HIPCHECK(ctx, ahead_join());
         timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
+        if (use_side && s + 1 < n_steps) {
+          ibm_status ms = rebuild_ahead(ctx->step + 1);
+          if (ms) return ms;
+        }
       } else if (hrow) {
         HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
       }
@@ -1047,9 +1117,8 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   // previous pass's solution. Each pass has its own tag.
   const int passes = std::max(1, ctx->desc.n_outer);
   for (int s = 0; s < (ctx->desc.scheme == IBM_SCHEME_DENSITY ? 0 : n_steps); ++s) {
-    if (ctx->nc > 0 && ctx->motion_axis >= 0) {
-      ibm_status ms = IBM_OK;
-      timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
+    {
+      ibm_status ms = step_markers();
       if (ms) return ms;
     }
     if (record) {
@@ -1088,10 +1157,15 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
         }
       }
       if (ctx->nc > 0) {
+        HIPCHECK(ctx, ahead_join());
         if (first)
           timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
         else
           timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_spread(L, B); });
+        if (use_side && pass == passes - 1 && s + 1 < n_steps) {
+          ibm_status ms = rebuild_ahead(ctx->step + 1);
+          if (ms) return ms;
+        }
       } else if (hrow && first) {
         HIPCHECK(ctx, hipMemsetAsync(hrow, 0, 4 * sizeof(double), st));
       }
@@ -1154,6 +1228,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     }
   }
   if (done > 0) ibmk::run_mass(L, B);
+  HIPCHECK(ctx, ahead_join());  // a step that failed may leave the next one's markers queued
   HIPCHECK(ctx, hipStreamSynchronize(st));
   int f[8];
   {

@@ -186,7 +186,15 @@ void run_copy_solution(const Launch &L, const Bufs &B, double *dst);
 // marker kernels (ibm_markers.hip)
 void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,
                        int dedupe);
-void run_build_markers(const Launch &L, const Bufs &B, int nc);
+// supports, sort, segments, Gram rows and the quadrature solve A eps = 1 from eps as
+// gathered by run_place_markers (the candidates' saved values); save_eps: the solution
+// is saved per candidate as the start of later solves
+void run_build_markers(const Launch &L, const Bufs &B, int nc, bool save_eps);
+// placement, selection and run_build_markers of the markers at a time: one block and
+// a one-wave solve for a small body (up to 256 candidates and 4096 pairs), else
+// run_place_markers and run_build_markers
+void run_rebuild_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,
+                         int dedupe, bool save_eps);
 void run_interp_force(const Launch &L, const Bufs &B, double *hist_row);
 void run_spread(const Launch &L, const Bufs &B);
 // local heat flux H_k / dA'_k of the markers in use into q [n_used] (device);

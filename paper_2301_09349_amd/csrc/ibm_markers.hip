@@ -51,11 +51,11 @@ __device__ __forceinline__ int block_scan_excl(int v, int *lds, int *total) {
 // ------------------------------------------------ placement, check routine
 // Candidate positions at the current time (Sec. 5, Eq. (19): a common offset
 // along `axis`); the containing cell and the squared distance to its centre.
-__global__ void k_place(GridK g, int nc, const double *X0, const double *U0, double *X, double *U,
-                        double off, double vel, int axis, int64_t *key, double *d2) {
+__device__ __forceinline__ void place_one(const GridK &g, int k, const double *X0,
+                                          const double *U0, double *X, double *U, double off,
+                                          double vel, int axis, int64_t &key, double &d2,
+                                          double *xk) {
 #pragma clang fp contract(off)
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nc) return;
   int64_t b[3] = {0, 0, 0};
   double dd = 0.0;
   for (int a = 0; a < 3; ++a) {
@@ -66,6 +66,7 @@ __global__ void k_place(GridK g, int nc, const double *X0, const double *U0, dou
     }
     X[3 * k + a] = x;
     U[3 * k + a] = u;
+    xk[a] = x;
     if (a < g.dim) {
       double xi = (x - g.lo[a]) / g.h[a];
       int64_t bb = (int64_t)floor(xi);
@@ -75,8 +76,16 @@ __global__ void k_place(GridK g, int nc, const double *X0, const double *U0, dou
       b[a] = bb;
     }
   }
-  key[k] = b[0] + (int64_t)g.n[0] * (b[1] + (int64_t)g.n[1] * b[2]);
-  d2[k] = dd;
+  key = b[0] + (int64_t)g.n[0] * (b[1] + (int64_t)g.n[1] * b[2]);
+  d2 = dd;
+}
+
+__global__ void k_place(GridK g, int nc, const double *X0, const double *U0, double *X, double *U,
+                        double off, double vel, int axis, int64_t *key, double *d2) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  double xk[3];
+  place_one(g, k, X0, U0, X, U, off, vel, axis, key[k], d2[k], xk);
 }
 
 // Sec. 3.1 check routine: a candidate is kept when no other candidate in its
@@ -134,11 +143,10 @@ __global__ void k_compact(int nc, const int *keep, const double *cX, const doubl
 // Support of marker k: the 3 cells per direction around the cell containing it,
 // weight the product of 1D kernel values at r = (x_c - X)/h; pair keys
 // (cell << 20 | k * nslot + slot) for the sort.
-__global__ void k_support(GridK g, const int *mcount, const double *X, int nslot, int *sidx,
-                          double *sw1, int64_t *pcell, double *pw, uint64_t *keys, int *flags) {
+__device__ __forceinline__ void support_one(const GridK &g, int k, const double *X, int nslot,
+                                            int *sidx, double *sw1, int64_t *pcell, double *pw,
+                                            uint64_t *keys, int *flags) {
 #pragma clang fp contract(off)
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= mcount[0]) return;
   int idx[3][3];
   double w1[3][3];
   for (int a = 0; a < 3; ++a)
@@ -176,6 +184,13 @@ __global__ void k_support(GridK g, const int *mcount, const double *X, int nslot
         pw[27 * k + s] = w1[0][s0] * w1[1][s1] * w1[2][s2];
         keys[(int64_t)nslot * k + s] = ((uint64_t)cell << kPairBits) | (uint64_t)(nslot * k + s);
       }
+}
+
+__global__ void k_support(GridK g, const int *mcount, const double *X, int nslot, int *sidx,
+                          double *sw1, int64_t *pcell, double *pw, uint64_t *keys, int *flags) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mcount[0]) return;
+  support_one(g, k, X, nslot, sidx, sw1, pcell, pw, keys, flags);
 }
 
 // Bitonic sort of the pair keys in one block (npad a power of two), in place in
@@ -247,6 +262,25 @@ __global__ void k_segments(const uint64_t *keys, int nslot, int *mcount, int *se
 // One block per row k: its threads test the markers l in parallel and a block scan
 // keeps the nonzeros in increasing l.
 constexpr int kGramThreads = 256;
+// A_kl from the supports of k (ks, kw) and l (ls, lw): 3 cell indices and 1D weights
+// per direction; returns 0 when the supports do not overlap.
+__device__ __forceinline__ int gram_entry(const GridK &g, const int *ks, const double *kw,
+                                          const int *ls, const double *lw, double &a) {
+  a = 1.0;
+  for (int d = 0; d < g.dim; ++d) {
+    double s = 0.0;
+    bool any = false;
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q)
+        if (ks[3 * d + p] == ls[3 * d + q]) {
+          s += kw[3 * d + p] * lw[3 * d + q];
+          any = true;
+        }
+    if (!any) return 0;
+    a *= s;
+  }
+  return 1;
+}
 __global__ __launch_bounds__(kGramThreads) void k_gram(GridK g, const int *mcount,
                                                        const int *sidx, const double *sw1,
                                                        int *col, double *val, int *cnt,
@@ -267,21 +301,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(GridK g, const int *mcoun
     const int l = start + threadIdx.x;
     double a = 1.0;
     int nz = 0;
-    if (l < n) {
-      nz = 1;
-      for (int d = 0; d < g.dim && nz; ++d) {
-        double s = 0.0;
-        bool any = false;
-        for (int p = 0; p < 3; ++p)
-          for (int q = 0; q < 3; ++q)
-            if (ks[3 * d + p] == sidx[9 * l + 3 * d + q]) {
-              s += kw[3 * d + p] * sw1[9 * l + 3 * d + q];
-              any = true;
-            }
-        if (!any) nz = 0;
-        a *= s;
-      }
-    }
+    if (l < n) nz = gram_entry(g, ks, kw, sidx + 9 * l, sw1 + 9 * l, a);
     int tot;
     const int off = block_scan_excl(nz, lds, &tot);
     if (nz && base + off < kMaxNbr) {
@@ -543,6 +563,187 @@ __global__ __launch_bounds__(kRedThreads) void k_eps_cg_regs(const int *mcount, 
     if (i < n) xg[i] = x[j];
   }
   if (threadIdx.x == 0) {
+    *it_out = total_it;
+    if (!ok) atomicOr(flags + 2, 1);
+  }
+}
+
+// A 64-bit lane value moved within rows of 16 lanes by the DPP control CTRL (every
+// lane of the wave active).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Sum over the 64 lanes of a wave, the same in every lane: each lane adds the value
+// of lane^1 and of lane^2 (quad permutes), then of its mirror in the half row of 8
+// and in the row of 16 (both lanes of a pair add the same two operands), and the four
+// row sums, read from lanes 0, 16, 32 and 48, are added in that order.
+__device__ __forceinline__ double wave_allsum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+// Two such sums, their steps interleaved.
+__device__ __forceinline__ void wave_allsum2(double &a, double &b) {
+  a += dpp_move<0xB1>(a);
+  b += dpp_move<0xB1>(b);
+  a += dpp_move<0x4E>(a);
+  b += dpp_move<0x4E>(b);
+  a += dpp_move<0x141>(a);
+  b += dpp_move<0x141>(b);
+  a += dpp_move<0x140>(a);
+  b += dpp_move<0x140>(b);
+  a = (lane_value(a, 0) + lane_value(a, 16)) + (lane_value(a, 32) + lane_value(a, 48));
+  b = (lane_value(b, 0) + lane_value(b, 16)) + (lane_value(b, 32) + lane_value(b, 48));
+}
+
+// The solve of k_eps_cg_regs (the same single-reduction iteration, restarts and
+// tolerances) in one wave, for n <= 64 R rows: lane l holds rows l + 64 j (j < R)
+// with their first NR Gram entries in registers, entries past a row's count being
+// zero weights on the row itself so that the product has no branch (a longer row
+// reads the rest each time); groups of 64 rows past n are skipped. The two sums of
+// an iteration are wave sums, with no barrier between the waves of a block and no
+// trip through LDS; the step lengths take one division on the iteration's critical
+// path: with q = 1/alpha and g = 1/gamma kept, beta = rho g, the new denominator is
+// d = (w.r) - beta rho q, alpha = rho / d, and q = d / rho, g = 1 / rho follow off it.
+template <int R, int NR>
+__global__ __launch_bounds__(64) void k_eps_cg_wave(const int *mcount, const int *col,
+                                                    const double *val, const int *cnt,
+                                                    const double *rhs, double *xg, int *it_out,
+                                                    int *flags, const int *save_ids,
+                                                    double *save_to) {
+  __shared__ double ps[64 * R];  // the vector multiplied by A
+  const int n = mcount[0];
+  if (n == 0) return;
+  const int lane = threadIdx.x;
+  double x[R], r[R], w[R], p[R], sv[R], bv[R];
+  double bb = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = lane + 64 * j;
+    x[j] = i < n ? xg[i] : 0.0;
+    bv[j] = i < n ? (rhs ? rhs[i] : 1.0) : 0.0;
+    bb += bv[j] * bv[j];
+    r[j] = w[j] = p[j] = sv[j] = 0.0;
+  }
+  bb = wave_allsum(bb);
+  if (!(bb > 0.0)) {  // zero right-hand side: x = 0
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = lane + 64 * j;
+      if (i < n) xg[i] = 0.0;
+    }
+    if (lane == 0) *it_out = 0;
+    return;
+  }
+  const double tol_true2 = 1e-26 * bb, tol_in2 = 1e-30 * bb;
+  int mrow[R], creg[R][NR];
+  double vreg[R][NR];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = lane + 64 * j;
+    mrow[j] = i < n ? cnt[i] : 0;
+#pragma unroll
+    for (int e = 0; e < NR; ++e) {
+      const bool in = e < mrow[j];
+      creg[j][e] = in ? col[(int64_t)kMaxNbr * i + e] : i;
+      vreg[j][e] = in ? val[(int64_t)kMaxNbr * i + e] : 0.0;
+    }
+  }
+  // out = A v for this lane's rows, in the ELL order
+  auto product = [&](const double *v, double *out) {
+    __syncthreads();  // the previous product's reads of ps come first
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (64 * j < n) ps[lane + 64 * j] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (64 * j >= n) {
+        out[j] = 0.0;
+        continue;
+      }
+      const int i = lane + 64 * j;
+      double sacc = 0.0;
+#pragma unroll
+      for (int e = 0; e < NR; ++e) sacc += vreg[j][e] * ps[creg[j][e]];
+      for (int e = NR; e < mrow[j]; ++e)
+        sacc += val[(int64_t)kMaxNbr * i + e] * ps[col[(int64_t)kMaxNbr * i + e]];
+      out[j] = sacc;
+    }
+  };
+  // the two sums r.r and w.r of this lane's rows
+  auto dots = [&](double &rr, double &wr) {
+    rr = 0.0;
+    wr = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      rr += r[j] * r[j];
+      wr += w[j] * r[j];
+    }
+    wave_allsum2(rr, wr);
+  };
+  int total_it = 0;
+  bool ok = false;
+  for (int restart = 0; restart < 7 && !ok; ++restart) {
+    product(x, w);
+#pragma unroll
+    for (int j = 0; j < R; ++j) r[j] = bv[j] - w[j];
+    product(r, w);
+    double gam, wr;
+    dots(gam, wr);
+    if (gam <= tol_true2) {
+      ok = true;
+      break;
+    }
+    if (restart == 6) break;
+    double alpha = gam / wr, q = wr / gam, g = 1.0 / gam;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      p[j] = r[j];
+      sv[j] = w[j];
+    }
+    const int maxit = 4 * n + 50;
+    for (int it = 0; it < maxit; ++it) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        x[j] += alpha * p[j];
+        r[j] -= alpha * sv[j];
+      }
+      product(r, w);
+      double rho, wr1;
+      dots(rho, wr1);
+      ++total_it;
+      if (rho <= tol_in2) break;
+      const double beta = rho * g;
+      const double d = wr1 - beta * rho * q;
+      alpha = rho / d;
+      g = 1.0 / rho;
+      q = d * g;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        p[j] = r[j] + beta * p[j];
+        sv[j] = w[j] + beta * sv[j];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int i = lane + 64 * j;
+    if (i < n) {
+      xg[i] = x[j];
+      if (save_to) save_to[save_ids[i]] = x[j];
+    }
+  }
+  if (lane == 0) {
     *it_out = total_it;
     if (!ok) atomicOr(flags + 2, 1);
   }
@@ -966,13 +1167,296 @@ void run_place_markers(const Launch &L, const Bufs &B, int nc, double off, doubl
                      B.eps, B.mcount);
 }
 
+// ------------------------------------------ marker set-up of a small body
+// For up to kSmallCand candidates and kSmallKeys (cell, pair) keys: placement and the
+// check routine, compaction, supports, the key sort, segments and the Gram rows in one
+// block of 4 kSmallCand threads (the arithmetic of k_place, k_dedupe, k_compact,
+// k_support, k_sort, k_segments and k_gram, phase after phase, with the candidates,
+// supports and keys in LDS), so that a moving body's markers are set up again with two
+// launches (this and the quadrature solve).
+constexpr int kSmallCand = 256;
+constexpr int kSmallKeys = 4096;
+static_assert(kRedThreads == 4 * kSmallCand, "one block of four threads per candidate");
+
+// Number of entries of the ascending list L[0, n) below v (n <= 256).
+__device__ __forceinline__ int count_below(const uint64_t *L, int n, uint64_t v) {
+  int pos = 0;
+#pragma unroll
+  for (int step = 256; step > 0; step >>= 1)
+    if (pos + step <= n && L[pos + step - 1] < v) pos += step;
+  return pos;
+}
+
+// A_kl (Eq. (9)) of two markers whose supports are known to overlap in every
+// direction, from the offset of their centre cells: the 1D sum over the cell indices
+// the two windows share pairs slot p of k with slot p + (c_k - c_l) of l, p
+// ascending (the terms and order of gram_entry when no periodic direction has fewer
+// than six cells).
+__device__ __forceinline__ double gram_entry_offset(int dim, const int *dl, const double *kw,
+                                                    const double *lw) {
+  double a = 1.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d >= dim) break;
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int q = p + dl[d];
+      if (q >= 0 && q < 3) s += kw[3 * d + p] * lw[3 * d + q];
+    }
+    a *= s;
+  }
+  return a;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_rebuild_small(
+    GridK g, int nc, int nslot, const double *X0, const double *U0, double off, double vel,
+    int axis, int dedupe, const double *cTw, const double *cdA, const double *ceps, double *cXc,
+    double *cUdc, int *ids, double *X, double *U, double *Tw, double *dA, double *eps,
+    int *mcount, int64_t *pcell, double *pw, uint64_t *keys, int *seg, int *ell_col,
+    double *ell_val, int *ell_cnt, int *flags) {
+  __shared__ int64_t skey[kSmallCand];
+  __shared__ double sd2[kSmallCand];
+  __shared__ double sX[3 * kSmallCand];
+  __shared__ int sbeat[4][kSmallCand];
+  __shared__ int ssi[9 * kSmallCand];     // support cell indices per direction and slot
+  __shared__ double ssw[9 * kSmallCand];  // their 1D kernel weights
+  __shared__ uint64_t sk[kSmallKeys];     // pair keys by pair, then in increasing order
+  __shared__ uint64_t sl[kSmallKeys];     // the same keys as one ascending list per slot
+  __shared__ uint64_t sm[kSmallCand];     // marker keys (centre cell << kPairBits | marker)
+  __shared__ int sord[kSmallCand];        // markers by increasing marker key
+  __shared__ int lds[32];
+  __shared__ int nsh;
+  const int t = threadIdx.x;
+  // placement (Sec. 5, Eq. (19)) of candidate t
+  double xk[3] = {0.0, 0.0, 0.0};
+  if (t < nc) place_one(g, t, X0, U0, cXc, cUdc, off, vel, axis, skey[t], sd2[t], xk);
+  __syncthreads();
+  // the check routine (Sec. 3.1): kept when no candidate of its cell is nearer its
+  // centre (ties: the lower id); four threads per candidate, each testing a quarter
+  // of the others
+  {
+    const int c = t % kSmallCand, part = t / kSmallCand, len = (nc + 3) / 4;
+    int beat = 0;
+    if (c < nc && dedupe) {
+      const int64_t kk = skey[c];
+      const double dk = sd2[c];
+      const int j1 = min(nc, (part + 1) * len);
+#pragma unroll 8
+      for (int j = part * len; j < j1; ++j)
+        beat |= (skey[j] == kk && (sd2[j] < dk || (sd2[j] == dk && j < c))) ? 1 : 0;
+    }
+    sbeat[part][c] = beat;
+  }
+  __syncthreads();
+  const int keep = t < nc ? !(sbeat[0][t] | sbeat[1][t] | sbeat[2][t] | sbeat[3][t]) : 0;
+  // compaction in increasing id
+  int tot;
+  const int m = block_scan_excl(keep, lds, &tot);
+  if (keep) {
+    ids[m] = t;
+    for (int a = 0; a < 3; ++a) {
+      X[3 * m + a] = xk[a];
+      U[3 * m + a] = cUdc[3 * t + a];
+      sX[3 * m + a] = xk[a];
+    }
+    Tw[m] = cTw[t];
+    dA[m] = cdA[t];
+    eps[m] = ceps[t];
+  }
+  if (t == 0) {
+    mcount[0] = tot;
+    nsh = tot;
+  }
+  __syncthreads();
+  const int n = nsh;
+  const int np = n * nslot;
+  // supports and pair keys of marker t; its key by centre cell
+  if (t < n) {
+    support_one(g, t, sX, nslot, ssi, ssw, pcell, pw, sk, flags);
+    sm[t] = (sk[nslot * t + nslot / 2] >> kPairBits << kPairBits) | (uint64_t)t;
+  }
+  __syncthreads();
+  // the markers by centre cell: the place of each is the number of keys below it
+  {
+    const int c = t % kSmallCand, part = t / kSmallCand, len = (n + 3) / 4;
+    int below = 0;
+    if (c < n) {
+      const uint64_t v = sm[c];
+      const int j1 = min(n, (part + 1) * len);
+#pragma unroll 8
+      for (int j = part * len; j < j1; ++j) below += sm[j] < v ? 1 : 0;
+    }
+    sbeat[part][c] = below;
+  }
+  __syncthreads();
+  if (t < n) sord[sbeat[0][t] + sbeat[1][t] + sbeat[2][t] + sbeat[3][t]] = t;
+  __syncthreads();
+  // the keys of slot s in that marker order: ascending unless a support wraps round a
+  // periodic direction
+  bool unsorted = false;
+  for (int i = t; i < np; i += blockDim.x) {
+    const int sl_s = i / n, mm = i - sl_s * n;
+    sl[i] = sk[nslot * sord[mm] + sl_s];
+  }
+  __syncthreads();
+  for (int i = t; i < np; i += blockDim.x) {
+    const int mm = i % n;
+    if (mm + 1 < n && sl[i] > sl[i + 1]) unsorted = true;
+  }
+  if (__syncthreads_or(unsorted)) {
+    // bitonic sort in LDS, padded with the largest key to a power of two (the keys are
+    // distinct, so the order is fully determined)
+    int npad = 1;
+    while (npad < np) npad <<= 1;
+    for (int i = np + t; i < npad; i += blockDim.x) sk[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= npad; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int q = t; q < npad / 2; q += blockDim.x) {
+          const int i = 2 * q - (q & (stride - 1)), j = i + stride;
+          const bool asc = (i & size) == 0;
+          const uint64_t u = sk[i], v = sk[j];
+          if ((u > v) == asc) {
+            sk[i] = v;
+            sk[j] = u;
+          }
+        }
+        __syncthreads();
+      }
+  } else {
+    // merge of the slot lists: a key's place is its place in its own list plus the
+    // number of keys below it in each other list
+    for (int i = t; i < np; i += blockDim.x) {
+      const int s0 = i / n;
+      const uint64_t v = sl[i];
+      int rank = i - s0 * n;
+      for (int s1 = 0; s1 < nslot; ++s1)
+        if (s1 != s0) rank += count_below(sl + s1 * n, n, v);
+      sk[rank] = v;
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < np; i += blockDim.x) keys[i] = sk[i];
+  // segments of equal cell
+  int base = 0;
+  for (int start = 0; start < np; start += blockDim.x) {
+    const int i = start + t;
+    int head = 0;
+    if (i < np) head = (i == 0) || ((sk[i] >> kPairBits) != (sk[i - 1] >> kPairBits));
+    int cnt;
+    const int o = block_scan_excl(head, lds, &cnt);
+    if (head) seg[base + o] = i;
+    base += cnt;
+  }
+  if (t == 0) {
+    seg[base] = np;
+    mcount[1] = base;
+  }
+  // Gram rows (Eq. (9)), one wave per row: its lanes test 64 markers at a time (first
+  // the offsets of the centre cells, then the weights where every direction's windows
+  // share a cell) and a ballot keeps the nonzeros in increasing column
+  bool by_offset = true;  // every periodic direction has at least six cells
+  for (int d = 0; d < g.dim; ++d)
+    if (g.bc[d][0] == BC_PERIODIC && g.n[d] < 6) by_offset = false;
+  const int lane = t & 63, nw = blockDim.x >> 6;
+  for (int k = t >> 6; k < n; k += nw) {
+    int c = 0;
+    for (int l0 = 0; l0 < n; l0 += 64) {
+      const int l = l0 + lane;
+      double a = 0.0;
+      int nz = 0;
+      if (l < n) {
+        if (by_offset) {
+          int dl[3] = {0, 0, 0};
+          nz = 1;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            if (d >= g.dim) break;
+            int e = ssi[9 * k + 3 * d + 1] - ssi[9 * l + 3 * d + 1];
+            if (g.bc[d][0] == BC_PERIODIC) {
+              if (e > g.n[d] / 2) e -= g.n[d];
+              if (e < -(g.n[d] / 2)) e += g.n[d];
+            }
+            dl[d] = e;
+            if (e < -2 || e > 2) nz = 0;
+          }
+          if (nz) a = gram_entry_offset(g.dim, dl, ssw + 9 * k, ssw + 9 * l);
+        } else {
+          nz = gram_entry(g, ssi + 9 * k, ssw + 9 * k, ssi + 9 * l, ssw + 9 * l, a);
+        }
+      }
+      const uint64_t bal = __ballot(nz);
+      const int o = c + __popcll(bal & ((1ull << lane) - 1ull));
+      if (nz && o < kMaxNbr) {
+        ell_col[(int64_t)kMaxNbr * k + o] = l;
+        ell_val[(int64_t)kMaxNbr * k + o] = a;
+      }
+      c += __popcll(bal);
+    }
+    if (lane == 0) {
+      if (c > kMaxNbr) atomicOr(flags + 3, 1);
+      ell_cnt[k] = c < kMaxNbr ? c : kMaxNbr;
+    }
+  }
+}
+
+// Whether the one-block set-up applies to nc candidates.
+static bool small_body(const Launch &L, int nc) {
+  const int nslot = (L.g.dim == 3) ? 27 : 9;
+  return nc <= kSmallCand && nc * nslot <= kSmallKeys;
+}
+
+// A x = rhs (rhs NULL: the quadrature weights, rhs 1) for at most nc <= 256 rows, from
+// x, in one wave; the solution also goes to save_to[save_ids[i]] when save_to is given.
+// Gram entries held in registers per row: 10 in 2D (a curve's rows have about 7), 24
+// or 12 in 3D.
+template <int R, int NR>
+static void launch_eps_wave(const Launch &L, const Bufs &B, const double *rhs, double *x,
+                            int *it_out, const int *save_ids, double *save_to) {
+  hipLaunchKernelGGL((k_eps_cg_wave<R, NR>), dim3(1), dim3(64), 0, L.st, (const int *)B.mcount,
+                     (const int *)B.ell_col, (const double *)B.ell_val, (const int *)B.ell_cnt,
+                     rhs, x, it_out, B.flags, save_ids, save_to);
+}
+static void launch_eps_solve(const Launch &L, const Bufs &B, int nc, const double *rhs,
+                             double *x, int *it_out, const int *save_ids, double *save_to) {
+  if (L.g.dim == 2) {
+    if (nc <= 128)
+      launch_eps_wave<2, 10>(L, B, rhs, x, it_out, save_ids, save_to);
+    else
+      launch_eps_wave<4, 10>(L, B, rhs, x, it_out, save_ids, save_to);
+  } else {
+    if (nc <= 128)
+      launch_eps_wave<2, 24>(L, B, rhs, x, it_out, save_ids, save_to);
+    else
+      launch_eps_wave<4, 12>(L, B, rhs, x, it_out, save_ids, save_to);
+  }
+}
+
+void run_rebuild_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,
+                         int dedupe, bool save_eps) {
+  if (!small_body(L, nc)) {
+    run_place_markers(L, B, nc, off, vel, axis, dedupe);
+    run_build_markers(L, B, nc, save_eps);
+    return;
+  }
+  const int nslot = (L.g.dim == 3) ? 27 : 9;
+  hipLaunchKernelGGL(k_rebuild_small, dim3(1), dim3(kRedThreads), 0, L.st, L.g, nc, nslot,
+                     (const double *)B.cX0, (const double *)B.cUd0, off, vel, axis, dedupe,
+                     (const double *)B.cTw, (const double *)B.cdA, (const double *)B.ceps, B.cXc,
+                     B.cUdc, B.ids, B.X, B.Ud, B.Tw, B.dA, B.eps, B.mcount, B.pcell, B.pw, B.keys,
+                     B.seg, B.ell_col, B.ell_val, B.ell_cnt, B.flags);
+  launch_eps_solve(L, B, nc, nullptr, B.eps, B.mcount + 2, save_eps ? B.ids : nullptr,
+                   save_eps ? B.ceps : nullptr);
+}
+
 // Threads of the one-row-per-thread quadrature solve for nc candidates.
 static unsigned eps_threads(int nc) {
   const int t = (nc + 63) / 64 * 64;
   return (unsigned)(t < 64 ? 64 : t > kRedThreads ? kRedThreads : t);
 }
 
-void run_build_markers(const Launch &L, const Bufs &B, int nc) {
+void run_build_markers(const Launch &L, const Bufs &B, int nc, bool save_eps) {
   const int nslot = (L.g.dim == 3) ? 27 : 9;
   hipLaunchKernelGGL(k_support, dim3(nblk(nc, 256)), dim3(256), 0, L.st, L.g,
                      (const int *)B.mcount, (const double *)B.X, nslot, B.sidx, B.sw1, B.pcell,
@@ -993,7 +1477,12 @@ void run_build_markers(const Launch &L, const Bufs &B, int nc) {
                      B.ell_col, B.ell_val, B.ell_cnt, B.flags);
   // the live count is on the device; the candidate count bounds it
   const size_t psb = (size_t)nc * sizeof(double);
-  if (nc <= kRedThreads)  // one row per thread: as few waves as rows need (shorter barriers)
+  if (nc <= 256) {  // one wave: no barrier
+    launch_eps_solve(L, B, nc, nullptr, B.eps, B.mcount + 2, save_eps ? B.ids : nullptr,
+                     save_eps ? B.ceps : nullptr);
+    return;
+  }
+  if (nc <= kRedThreads)  // one row per thread: as few waves as rows need
     hipLaunchKernelGGL((k_eps_cg_regs<1, kEpsRegNnz>), dim3(1), dim3(eps_threads(nc)), psb,
                        L.st, (const int *)B.mcount, (const int *)B.ell_col,
                        (const double *)B.ell_val, (const int *)B.ell_cnt, (const double *)nullptr,
@@ -1007,8 +1496,9 @@ void run_build_markers(const Launch &L, const Bufs &B, int nc) {
     hipLaunchKernelGGL(k_eps_cg, dim3(1), dim3(kRedThreads), 0, L.st, B.mcount,
                        (const int *)B.ell_col, (const double *)B.ell_val, (const int *)B.ell_cnt,
                        B.eps, B.ev[0], B.ev[1], B.ev[2], B.flags);
-  hipLaunchKernelGGL(k_eps_save, dim3(nblk(nc, 256)), dim3(256), 0, L.st, (const int *)B.mcount,
-                     (const int *)B.ids, (const double *)B.eps, B.ceps);
+  if (save_eps)
+    hipLaunchKernelGGL(k_eps_save, dim3(nblk(nc, 256)), dim3(256), 0, L.st,
+                       (const int *)B.mcount, (const int *)B.ids, (const double *)B.eps, B.ceps);
 }
 
 bool shape_supported(int nc) { return nc <= 4 * kRedThreads; }
@@ -1024,7 +1514,9 @@ void run_shape_gradient(const Launch &L, const Bufs &B, int nc, double *X_bar) {
   // lambda = A^{-1} epsbar, from zero
   run_fill(L, B.lam_g, nc, 0.0);
   const size_t psb = (size_t)nc * sizeof(double);
-  if (nc <= kRedThreads)
+  if (nc <= 256)
+    launch_eps_solve(L, B, nc, B.epsbar, B.lam_g, B.mcount + 3, nullptr, nullptr);
+  else if (nc <= kRedThreads)
     hipLaunchKernelGGL((k_eps_cg_regs<1, kEpsRegNnz>), dim3(1), dim3(eps_threads(nc)), psb,
                        L.st, (const int *)B.mcount, (const int *)B.ell_col,
                        (const double *)B.ell_val, (const int *)B.ell_cnt,

@@ -93,3 +93,24 @@ def test_single_marker(cuda, kind):
     for k, v in state_errors(g, o).items():
         assert v < 1e-11, (kind, k, v)
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-9
+
+
+@pytest.mark.parametrize("dedupe,ns", [(True, 60), (False, 24)])
+def test_body_across_a_periodic_side(cuda, dedupe, ns):
+    # the transversely moving cylinder centred on the periodic y sides: its supports
+    # wrap round (cell indices of one slot then fall in two runs, and the marker set-up
+    # sorts the pair keys by the general network), with and without the check routine
+    c = inputs.scaled("cfg4", (128, 96), ns=ns, dedupe=dedupe, lo=(-4.0, 0.0), hi=(12.0, 16.0),
+                      bc=[[inputs.INFLOW, inputs.OUTFLOW], [PER, PER]])
+    g, o = make_gpu(c, amplitude=1e-2), make_oracle(c, amplitude=1e-2)
+    ids, eps = g.markers_in_use()
+    assert np.array_equal(to_np(ids).astype(int), o.keep())
+    assert rel_l2(to_np(eps), o.eps()) < 1e-9
+    hg, _ = g.step(4)
+    ho = o.step(4)
+    for k, v in state_errors(g, o).items():
+        assert v < 1e-11, (k, v)
+    assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
+    ids, eps = g.markers_in_use()
+    assert np.array_equal(to_np(ids).astype(int), o.keep())
+    assert rel_l2(to_np(eps), o.eps()) < 1e-9

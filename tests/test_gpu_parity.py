@@ -227,6 +227,33 @@ def test_moving_body_parity(cuda, name):
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
 
 
+@pytest.mark.parametrize("kind", [{}, {"n_outer": 2}, {"scheme": inputs.SCHEME_DENSITY}])
+def test_moving_markers_ahead_and_inline_agree(cuda, monkeypatch, kind):
+    # the next step's markers set up on the context's second stream during the
+    # pressure solve, against the same set-up at each step's start on the context's
+    # stream (IBM_REBUILD=inline): bitwise the same steps, also over two calls, and the
+    # same markers in use and wall fluxes after them
+    c = inputs.scaled("osc2", (96, 96), ns=80, **kind)
+    runs = {}
+    for mode in ("ahead", "inline"):
+        if mode == "inline":
+            monkeypatch.setenv("IBM_REBUILD", "inline")
+        else:
+            monkeypatch.delenv("IBM_REBUILD", raising=False)
+        g = make_gpu(c)
+        h1, _ = g.step(5)
+        h2, _ = g.step(3)
+        ids, eps = g.markers_in_use()
+        f, h, _ = g.wall_fluxes()
+        runs[mode] = [to_np(x).copy() for x in (h1, h2, ids, eps, f, h)]
+        runs[mode] += [to_np(x).copy() for x in g.get_state()[:3]]
+    for a, b in zip(runs["ahead"], runs["inline"]):
+        assert np.array_equal(a, b)
+    o = make_oracle(c)
+    o.step(8)
+    assert rel_l2(runs["ahead"][3], o.eps()) < 1e-9
+
+
 @pytest.mark.parametrize("shape,bc", [
     ((36, 30, 26), None),
     ((70, 11, 9), [[inputs.INFLOW, inputs.OUTFLOW], [inputs.SLIP, inputs.SLIP],

@@ -27,16 +27,16 @@ __device__ __forceinline__ S vanleer(S phC, S phD, S phU) {
   return (ab > S(0)) ? phC + ab / (a + b) : phC;
 }
 
-// Primitive variables at a (possibly ghost) cell.
+// Primitive variables at a (possibly ghost) cell from the conserved values of the
+// cell r resolves to: cons = rho, m[DIM], E.
 template <int DIM, typename S>
-__device__ __forceinline__ void load_prim(const GridK &g, const StateV<S> &st, int i, int j, int k,
-                                          S &rho, S *u, S &th, S &p) {
-  Resolved r = resolve<DIM>(g, i, j, k);
-  rho = st.rho[r.c];
+__device__ __forceinline__ void prim_from(const GridK &g, const Resolved &r, const S *cons, S &rho,
+                                          S *u, S &th, S &p) {
+  rho = cons[0];
   S inv = S(1) / rho;
 #pragma unroll
-  for (int q = 0; q < DIM; ++q) u[q] = st.mom[q][r.c] * inv;
-  S E = st.E[r.c];
+  for (int q = 0; q < DIM; ++q) u[q] = cons[1 + q] * inv;
+  S E = cons[DIM + 1];
   th = E * inv * S(g.inv_cv);
   p = S(g.gm1) * E;
   if (any_side<DIM, S>(r)) {
@@ -46,6 +46,19 @@ __device__ __forceinline__ void load_prim(const GridK &g, const StateV<S> &st, i
     th = ghosted<DIM>(g, r, V_TH, th);
     p = ghosted<DIM>(g, r, V_P, p);
   }
+}
+
+// Primitive variables at a (possibly ghost) cell.
+template <int DIM, typename S>
+__device__ __forceinline__ void load_prim(const GridK &g, const StateV<S> &st, int i, int j, int k,
+                                          S &rho, S *u, S &th, S &p) {
+  Resolved r = resolve<DIM>(g, i, j, k);
+  S cons[DIM + 2];
+  cons[0] = st.rho[r.c];
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) cons[1 + q] = st.mom[q][r.c];
+  cons[DIM + 1] = st.E[r.c];
+  prim_from<DIM>(g, r, cons, rho, u, th, p);
 }
 
 template <int DIM, typename S>
@@ -177,22 +190,23 @@ struct PredOut {
   const S *E_b;
 };
 
+// The same from the previous energies Ep, E2, E3 of cell c already read (each read
+// only where po gives its array).
 template <typename S>
-__device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> &po, int64_t c,
-                                               S rho_s, S E_s, S E) {
+__device__ __forceinline__ void pred_setup_out_vals(const GridK &g, const PredOut<S> &po,
+                                                    int64_t c, S rho_s, S E_s, S E, S Ep, S E2,
+                                                    S E3) {
   const S theta = E_s / (rho_s * S(g.cv));
   po.psi[c] = S(1) / (S(g.R) * theta);
   if (!po.x) return;
   const double pn = double(S(g.gm1) * E);
   double x0 = pn;
   if (po.E_prev) {
-    const S Ep = po.E_prev[c];
     const double pp = double(S(g.gm1) * Ep);
     if (po.E_prev2) {
-      const S E2 = po.E_prev2[c];
       const double p2 = double(S(g.gm1) * E2);
       if (po.E_prev3)
-        x0 = 4.0 * (pn + p2) - 6.0 * pp - double(S(g.gm1) * po.E_prev3[c]);
+        x0 = 4.0 * (pn + p2) - 6.0 * pp - double(S(g.gm1) * E3);
       else
         x0 = 3.0 * (pn - pp) + p2;
       if (po.E_keep2) po.E_keep2[c] = E2;
@@ -202,6 +216,15 @@ __device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> 
     if (po.E_keep) po.E_keep[c] = Ep;
   }
   po.x[c] = x0;
+}
+
+template <typename S>
+__device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> &po, int64_t c,
+                                               S rho_s, S E_s, S E) {
+  const S Ep = (po.x && po.E_prev) ? po.E_prev[c] : S(0);
+  const S E2 = (po.x && po.E_prev && po.E_prev2) ? po.E_prev2[c] : S(0);
+  const S E3 = (po.x && po.E_prev && po.E_prev2 && po.E_prev3) ? po.E_prev3[c] : S(0);
+  pred_setup_out_vals(g, po, c, rho_s, E_s, E, Ep, E2, E3);
 }
 
 // Predictor (f = q = 0): explicit update of mass, momentum and internal energy.
@@ -348,6 +371,17 @@ struct PredLds {
   // first plane has ring offset zoff sits in slot (c + 2 + zoff) mod SZ, so that the
   // next tile up a column finds the planes it shares with this one in place
   static constexpr bool RING = DIM == 3 && (SZ & (SZ - 1)) == 0;
+  // PF (3D FP64, whose occupancy the LDS bounds at two blocks per CU whatever the
+  // registers): a tile's global reads are all issued at its start -- the face fluxes
+  // and the outputs' inputs into registers, the halo points in rounds of PCH per
+  // thread -- instead of where they are used (the other forms keep their occupancy)
+  static constexpr bool PF = PL;
+  // halo points a thread loads per round (their loads issued together): the new
+  // planes of a tile up a column (3D), the tile with its halo (2D); faces per thread
+  // and direction
+  static constexpr int NEWP = SX * SY * (DIM == 3 ? (RING ? TZ : SZ) : 1);
+  static constexpr int PCH = (NEWP + kThreads - 1) / kThreads;
+  static constexpr int FPT = (NFMAX + kThreads - 1) / kThreads;
   __device__ static constexpr int pt(int a, int b, int c, int zoff) {
     return (a + 2) +
            SX * ((b + 2) + SY * (DIM == 3 ? (RING ? ((c + 2 + zoff) & (SZ - 1)) : c + 2) : 0));
@@ -460,15 +494,60 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       x0 = (int)((t / ptz) % ptx) * T::TX;
       y0 = (int)(t / ((int64_t)ptz * ptx)) * T::TY;
     }
+    // the tile's face fluxes and the values its outputs need, read into registers
+    // first so that their loads overlap those of the halo below
+    S fpre[DIM][T::FPT];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      if (!T::PF) break;
+      const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2 ? 1 : 0);
+#pragma unroll
+      for (int m = 0; m < T::FPT; ++m) {
+        const int f = threadIdx.x + kThreads * m;
+        fpre[d][m] = S(0);
+        if (f >= FX * FY * FZ) continue;
+        const int gc[3] = {x0 + f % FX, y0 + (f / FX) % FY, z0 + f / (FX * FY)};
+        bool ok = true;
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) ok = ok && (gc[e] < g.n[e] + (e == d ? 1 : 0));
+        if (ok) fpre[d][m] = st.F[d][fidx(g, d, gc[0], gc[1], gc[2])];
+      }
+    }
+    // per cell: E, rho_b, mom_b[DIM], E_b, and the previous energies the CG start uses
+    S opre[CPT][DIM + 6];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+      if (!T::PF) break;
+      const int lc = threadIdx.x + kThreads * m;
+      const int i = x0 + lc % T::TX, j = y0 + (lc / T::TX) % T::TY, k = z0 + lc / (T::TX * T::TY);
+#pragma unroll
+      for (int v = 0; v < DIM + 6; ++v) opre[m][v] = S(0);
+      if (!(i < g.n[0] && j < g.n[1] && (DIM == 2 || k < g.n[2]))) continue;
+      const int64_t c = cidx(g, i, j, k);
+      opre[m][0] = st.E[c];
+      opre[m][1] = po.rho_b[c];
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) opre[m][2 + q] = po.mom_b[q][c];
+      opre[m][DIM + 2] = po.E_b[c];
+      if (po.x && po.E_prev) {
+        opre[m][DIM + 3] = po.E_prev[c];
+        if (po.E_prev2) {
+          opre[m][DIM + 4] = po.E_prev2[c];
+          if (po.E_prev3) opre[m][DIM + 5] = po.E_prev3[c];
+        }
+      }
+    }
     __syncthreads();  // the previous tile is done with LDS
     // phase 1: primitives of the tile and its halo (points beyond two ghost
     // layers are not needed and not loaded). Up a column (3D), the planes shared
     // with the previous tile (local -2..1) are already in the ring: only the TZ
-    // new planes (local 2..TZ+1) are loaded.
+    // new planes (local 2..TZ+1) are loaded. Each round issues the loads of its
+    // points before converting any of them.
     const int zoff = T::RING ? (z0 & (T::SZ - 1)) : 0;
     const bool cont = T::RING && t > t0 && z0 != 0;
     const int cfirst = cont ? 2 : -2, nplanes = cont ? T::TZ : T::SZ;
-    for (int p = threadIdx.x; p < T::SX * T::SY * nplanes; p += kThreads) {
+    const int npts = T::SX * T::SY * nplanes;
+    for (int p = threadIdx.x; !T::PF && p < npts; p += kThreads) {
       const int li = p % T::SX, lj = (p / T::SX) % T::SY, lc = cfirst + p / (T::SX * T::SY);
       const int gi = x0 - 2 + li, gj = y0 - 2 + lj, gk = (DIM == 3) ? z0 + lc : 0;
       bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
@@ -483,6 +562,44 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       lv[(DIM + 1) * NP + lp] = th;
       lv[(DIM + 2) * NP + lp] = mu_of(g, th);
       if (T::PL) lv[(DIM + 3) * NP + lp] = pp;
+    }
+    for (int base = 0; T::PF && base < npts; base += T::PCH * kThreads) {
+      Resolved rr[T::PCH];
+      S cons[T::PCH][DIM + 2];
+      int lp[T::PCH];
+      bool okp[T::PCH];
+#pragma unroll
+      for (int m = 0; m < T::PCH; ++m) {
+        const int p = base + threadIdx.x + kThreads * m;
+        okp[m] = false;
+        lp[m] = 0;
+        if (p >= npts) continue;
+        const int li = p % T::SX, lj = (p / T::SX) % T::SY, lc = cfirst + p / (T::SX * T::SY);
+        const int gi = x0 - 2 + li, gj = y0 - 2 + lj, gk = (DIM == 3) ? z0 + lc : 0;
+        bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
+        if (DIM == 3) ok = ok && gk >= -2 && gk <= g.n[2] + 1;
+        if (!ok) continue;
+        okp[m] = true;
+        lp[m] = T::pt(li - 2, lj - 2, lc, zoff);
+        rr[m] = resolve<DIM>(g, gi, gj, gk);
+        cons[m][0] = st.rho[rr[m].c];
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) cons[m][1 + q] = st.mom[q][rr[m].c];
+        cons[m][DIM + 1] = st.E[rr[m].c];
+      }
+#pragma unroll
+      for (int m = 0; m < T::PCH; ++m) {
+        if (!okp[m]) continue;
+        S r, u[3], th, pp;
+        prim_from<DIM>(g, rr[m], cons[m], r, u, th, pp);
+        const int q0 = lp[m];
+        lv[q0] = r;
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + q0] = u[q];
+        lv[(DIM + 1) * NP + q0] = th;
+        lv[(DIM + 2) * NP + q0] = mu_of(g, th);
+        if (T::PL) lv[(DIM + 3) * NP + q0] = pp;
+      }
     }
     __syncthreads();
     // phase 2: cell-centred terms (-grad p, viscous dissipation) into registers
@@ -545,7 +662,10 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     for (int d = 0; d < DIM; ++d) {
       const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2 ? 1 : 0);
       const int nfd = FX * FY * FZ;
-      for (int f = threadIdx.x; f < nfd; f += kThreads) {
+#pragma unroll
+      for (int m = 0; m < T::FPT; ++m) {
+        const int f = threadIdx.x + kThreads * m;
+        if (f >= nfd) continue;
         const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
         const int gi = x0 + fi, gj = y0 + fj, gk = z0 + fk;
         const int gc[3] = {gi, gj, gk};
@@ -553,7 +673,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
 #pragma unroll
         for (int e = 0; e < DIM; ++e) ok = ok && (gc[e] < g.n[e] + (e == d ? 1 : 0));
         if (!ok) continue;
-        const S F = st.F[d][fidx(g, d, gi, gj, gk)];
+        const S F = T::PF ? fpre[d][m] : st.F[d][fidx(g, d, gi, gj, gk)];
         S uf, fm[3], fe;
         face_flux_lds<DIM, S>(g, lv, zoff, d, fi, fj, fk, F, uf, fm, fe);
         lf[f] = F;
@@ -583,18 +703,23 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     for (int m = 0; m < CPT; ++m) {
       if (!cv_ok[m]) continue;
       const int64_t c = cidx(g, x0 + cl[m][0], y0 + cl[m][1], z0 + cl[m][2]);
-      const S E = st.E[c];
-      const S rs = po.rho_b[c] - dt * acc[m][0];
+      const S E = T::PF ? opre[m][0] : st.E[c];
+      const S rs = (T::PF ? opre[m][1] : po.rho_b[c]) - dt * acc[m][0];
       rho_s[c] = rs;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) {
-        const S mhq = po.mom_b[q][c] + acc[m][1 + q];
+        const S mhq = (T::PF ? opre[m][2 + q] : po.mom_b[q][c]) + acc[m][1 + q];
         ms[q][c] = mhq + gpr[m][q];
         po.mh[q][c] = mhq;
       }
-      const S es = po.E_b[c] + acc[m][DIM + 1] - dt * (gm1 * E) * acc[m][DIM + 2];
+      const S es = (T::PF ? opre[m][DIM + 2] : po.E_b[c]) + acc[m][DIM + 1] -
+                   dt * (gm1 * E) * acc[m][DIM + 2];
       E_s[c] = es;
-      pred_setup_out(g, po, c, rs, es, E);
+      if (T::PF)
+        pred_setup_out_vals(g, po, c, rs, es, E, opre[m][DIM + 3], opre[m][DIM + 4],
+                            opre[m][DIM + 5]);
+      else
+        pred_setup_out(g, po, c, rs, es, E);
     }
   }
 }

@@ -74,7 +74,9 @@ def kernel_bytes(cls: str, dim: int, precision: str = "fp64", scheme: int = 0) -
 
 # kernel symbol prefix -> kernel class of the library's event timing
 KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start", "setup"),
-                ("k_cg_iter", "cg"), ("k_mcg_iter", "cg"), ("k_cg_col", "cg"), ("k_mcg_col", "cg"),
+                ("k_cg_iter", "cg"), ("k_mcg_iter", "cg"),
+                # the column CG's start (template argument 0) belongs to the set-up
+                ("k_cg_col<0", "setup"), ("k_cg_col", "cg"), ("k_mcg_col", "cg"),
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
                 ("k_totals", "markers"), ("k_markers_fused", "markers"),
                 ("k_dsys", "diffusion"), ("k_diff_coef", "diffusion"),
@@ -86,10 +88,10 @@ KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start
 
 def kernel_class(name: str):
     """Class of a kernel from its demangled name (``void ibmk::k_setup2<2, double>(...)``)."""
-    m = re.search(r"ibmk::(\w+)", name)
+    m = re.search(r"ibmk::(\w+)(<[^>]*>)?", name)
     if not m:
         return None
-    sym = m.group(1)
+    sym = m.group(1) + (m.group(2) or "")
     for key, cls in KERNEL_CLASS:
         if sym.startswith(key):
             return cls

@@ -72,7 +72,7 @@ def test_implicit_periodic_box_sutherland_parity(cuda):
 
 
 def test_implicit_moving_body_parity(cuda):
-    c = inputs.scaled("osc2", (96, 96), ns=80, diffusion=IMP)
+    c = inputs.scaled("osc2", (96, 96), ns=80, diffusion=IMP, scheme=inputs.SCHEME_PRESSURE)
     g, o = make_gpu(c), make_oracle(c)
     hg, _ = g.step(6)
     ho = o.step(6)

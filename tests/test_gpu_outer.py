@@ -51,7 +51,7 @@ def test_outer_passes_sphere_3d_parity(cuda):
 
 
 def test_outer_passes_moving_body_parity(cuda):
-    c = inputs.scaled("osc2", (96, 96), ns=80, n_outer=2)
+    c = inputs.scaled("osc2", (96, 96), ns=80, n_outer=2, scheme=inputs.SCHEME_PRESSURE)
     g, o = make_gpu(c), make_oracle(c)
     hg, _ = g.step(4)
     ho = o.step(4)

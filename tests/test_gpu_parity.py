@@ -214,11 +214,14 @@ def test_predictor_variants_parity(cuda, monkeypatch, variant, shape):
         assert v < 1e-12, (k, v)
 
 
-@pytest.mark.parametrize("name", ["cfg4", "osc2"])
-def test_moving_body_parity(cuda, name):
-    # transverse (cfg4) and streamwise (osc2, heated wall at twice the stream's
-    # temperature) oscillation: markers re-placed, re-selected and re-weighted per step
-    c = inputs.scaled(name, (96, 96), ns=80)
+@pytest.mark.parametrize("name,over", [("cfg4", {}), ("osc2", {"scheme": inputs.SCHEME_PRESSURE}),
+                                       ("osc1", {}), ("osc2", {})])
+def test_moving_body_parity(cuda, name, over):
+    # transverse (cfg4) and streamwise (osc1, osc2: the wall at the stream's temperature
+    # and at twice it; on the density-based step as in Sec. 5, and osc2 on the
+    # pressure-based one) oscillation: markers re-placed, re-selected and re-weighted
+    # per step
+    c = inputs.scaled(name, (96, 96), ns=80, **over)
     g, o = make_gpu(c), make_oracle(c)
     hg, _ = g.step(6)
     ho = o.step(6)
@@ -227,7 +230,9 @@ def test_moving_body_parity(cuda, name):
     assert rel_l2(to_np(hg), ho[:, :4]) < 1e-8
 
 
-@pytest.mark.parametrize("kind", [{}, {"n_outer": 2}, {"scheme": inputs.SCHEME_DENSITY}])
+@pytest.mark.parametrize("kind", [{"scheme": inputs.SCHEME_PRESSURE},
+                                  {"scheme": inputs.SCHEME_PRESSURE, "n_outer": 2},
+                                  {"scheme": inputs.SCHEME_DENSITY}])
 def test_moving_markers_ahead_and_inline_agree(cuda, monkeypatch, kind):
     # the next step's markers set up on the context's second stream during the
     # pressure solve, against the same set-up at each step's start on the context's

@@ -753,6 +753,95 @@ def workload_text(case, kept: int, dt: float) -> str:
             % (body, cells, box, case["ns"], kept, case["Re"], case["Ma"], case["Tw"], dt, step))
 
 
+# SQ and GRBM counters of the three --pmc passes that --summarize-counters reads
+COUNTER_PASSES = [
+    "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_SALU "
+    "SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64",
+    "SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_LDS SQ_ACTIVE_INST_VALU "
+    "SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_ANY",
+    "SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 "
+    "SQ_INSTS_VALU_CVT SQ_INSTS_BRANCH SQ_INSTS_SMEM GRBM_GUI_ACTIVE",
+]
+
+
+def summarize_counters(directory: str, label: str, command: str, cells: int):
+    """Reads the counter_collection files of the --pmc passes in COUNTER_PASSES (the
+    sub-directories pmc0, pmc1, pmc2 of `directory`) and the kernel trace of the same
+    program (stats/), and writes profiles/counters_<label>.md: per kernel and dispatch
+    the counters summed over the device, and derived figures with their formulas."""
+    stats = _rows(os.path.join(directory, "stats", "**", "*kernel_stats.csv"))
+    dur = {r["Name"]: float(r["AverageNs"]) for r in stats}
+    per = {}
+    for i in range(len(COUNTER_PASSES)):
+        acc = {}
+        for r in _rows(os.path.join(directory, f"pmc{i}", "**", "*counter_collection.csv")):
+            key = r["Kernel_Name"]
+            disp = r.get("Dispatch_Id") or r.get("Correlation_Id")
+            c = r["Counter_Name"]
+            acc.setdefault(key, {}).setdefault(c, {}).setdefault(disp, 0.0)
+            acc[key][c][disp] += float(r["Counter_Value"])
+        for k, cs in acc.items():
+            for c, v in cs.items():
+                per.setdefault(k, {})[c] = sum(v.values()) / len(v)
+    lines = [f"# rocprofv3 counters: {label}", "", "Commands (from the repository root):", ""]
+    for c in command.split(";;"):
+        lines.append(f"    {c.strip()}")
+    lines += ["", "Counters per dispatch (averaged over the dispatches of each kernel, each summed "
+              "over the device). Passes: " + "; ".join(f"`{p}`" for p in COUNTER_PASSES) + ".",
+              "", "Derived, per kernel (cells = %d; a wave-instruction serves 64 cells, so "
+              "`X per cell` = X / (cells / 64) is the count per cell and lane):" % cells, "",
+              "- VALU, LDS, VMEM (read + write), SALU, FP64 FMA, FP64 transcendental "
+              "instructions per cell;",
+              "- `valu/wave`, `lds/wave`, `wait/wave`, `ldswait/wave`: SQ_ACTIVE_INST_VALU, "
+              "SQ_ACTIVE_INST_LDS, SQ_WAIT_ANY, SQ_WAIT_INST_LDS over SQ_WAVE_CYCLES (the share "
+              "of the waves' resident time spent issuing VALU or LDS work, waiting on a counter, "
+              "waiting to issue LDS);",
+              "- `bank conflict`: SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS (stall cycles per "
+              "cycle of LDS work);",
+              "- `waves/CU`: 4 SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8) / 256, the mean number "
+              "of resident waves per CU over the kernel (SQ_WAVE_CYCLES counts quad-cycles "
+              "summed over all waves; GRBM_GUI_ACTIVE counts the kernel's cycles summed over "
+              "the 8 XCDs);",
+              "- INT32, INT64, ADD64, MUL64, CVT: VALU instructions of those kinds per cell;",
+              "- `us`: mean duration from the kernel trace of the same program.", "",
+              "| kernel | us | VALU/cell | LDS/cell | VMEM/cell | SALU/cell | FMA64/cell | "
+              "TRANS64/cell | INT32 | INT64 | ADD64 | MUL64 | CVT | valu/wave | lds/wave | "
+              "wait/wave | ldswait/wave | bank conflict | waves/CU |", "|---|" + "---|" * 18]
+    wcell = cells / 64.0
+
+    def g(v, c):
+        return v.get(c, float("nan"))
+
+    rows = sorted(per.items(), key=lambda kv: -dur.get(kv[0], 0.0))
+    for k, v in rows:
+        if k not in dur or dur[k] < 20000:  # kernels of at least 20 us
+            continue
+        wc = g(v, "SQ_WAVE_CYCLES")
+        lines.append(
+            f"| `{k.split('(')[0][:60]}` | {dur[k] / 1e3:.1f} | {g(v, 'SQ_INSTS_VALU') / wcell:.0f} | "
+            f"{g(v, 'SQ_INSTS_LDS') / wcell:.1f} | "
+            f"{(g(v, 'SQ_INSTS_VMEM_RD') + g(v, 'SQ_INSTS_VMEM_WR')) / wcell:.1f} | "
+            f"{g(v, 'SQ_INSTS_SALU') / wcell:.0f} | {g(v, 'SQ_INSTS_VALU_FMA_F64') / wcell:.0f} | "
+            f"{g(v, 'SQ_INSTS_VALU_TRANS_F64') / wcell:.1f} | "
+            f"{g(v, 'SQ_INSTS_VALU_INT32') / wcell:.0f} | {g(v, 'SQ_INSTS_VALU_INT64') / wcell:.0f} | "
+            f"{g(v, 'SQ_INSTS_VALU_ADD_F64') / wcell:.0f} | "
+            f"{g(v, 'SQ_INSTS_VALU_MUL_F64') / wcell:.0f} | {g(v, 'SQ_INSTS_VALU_CVT') / wcell:.0f} | "
+            f"{g(v, 'SQ_ACTIVE_INST_VALU') / wc:.3f} | {g(v, 'SQ_ACTIVE_INST_LDS') / wc:.3f} | "
+            f"{g(v, 'SQ_WAIT_ANY') / wc:.3f} | {g(v, 'SQ_WAIT_INST_LDS') / wc:.3f} | "
+            f"{g(v, 'SQ_LDS_BANK_CONFLICT') / max(g(v, 'SQ_ACTIVE_INST_LDS'), 1.0):.3f} | "
+            f"{4.0 * wc / max(g(v, 'GRBM_GUI_ACTIVE') / 8.0, 1.0) / 256:.2f} |")
+    lines += ["", "Raw counters per dispatch:", "", "| kernel | counter | value |",
+              "|---|---|---|"]
+    for k, v in rows:
+        if k not in dur or dur[k] < 20000:
+            continue
+        for c in sorted(v):
+            lines.append(f"| `{k.split('(')[0][:60]}` | {c} | {v[c]:.6g} |")
+    out_md = os.path.join(ROOT, "profiles", f"counters_{label}.md")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    log(f"wrote {out_md}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -789,7 +878,14 @@ def main():
     ap.add_argument("--label", default="sphere256_fp64",
                     help="summary name: <workload>_<precision>, e.g. sphere256_fp32")
     ap.add_argument("--command", default="")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="summarize the SQ counter passes of this script (no GPU)")
+    ap.add_argument("--cells", type=int, default=256 ** 3,
+                    help="cells of the profiled workload (--summarize-counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.label, args.command, args.cells)
+        return
     if args.summarize:
         summarize(args.summarize, args.label, args.command)
         return

@@ -376,12 +376,57 @@ struct PredLds {
   // and the outputs' inputs into registers, the halo points in rounds of PCH per
   // thread -- instead of where they are used (the other forms keep their occupancy)
   static constexpr bool PF = PL;
+  static_assert(!PF || (TX * TY * TZ == kThreads && TY % 4 == 0),
+                "the PF mappings take one cell per thread and rows in groups of four");
   // halo points a thread loads per round (their loads issued together): the new
   // planes of a tile up a column (3D), the tile with its halo (2D); faces per thread
   // and direction
   static constexpr int NEWP = SX * SY * (DIM == 3 ? (RING ? TZ : SZ) : 1);
   static constexpr int PCH = (NEWP + kThreads - 1) / kThreads;
   static constexpr int FPT = (NFMAX + kThreads - 1) / kThreads;
+  // Local cell lc of the tile: x fastest. With PF (TX 8, row pitch SX 12 values) the
+  // rows of each group of four are taken in the order 0 2 1 3, so that the two 8-lane
+  // rows of a 16-lane group of a wave are 24 doubles apart in LDS and fall on disjoint
+  // banks (rows 12 doubles apart share a quarter of theirs).
+  __device__ static int row_perm(int r) {
+    return PF ? (r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1) : r;
+  }
+  __device__ static void cell_of(int lc, int &ci, int &cj, int &ck) {
+    ci = lc % TX;
+    cj = row_perm((lc / TX) % TY);
+    ck = lc / (TX * TY);
+  }
+  // Slot in the face buffer of face (fi, fj, fk) of a direction with FX x FY faces per
+  // plane: rows stored in the cells' row order, so that a wave's faces are contiguous
+  // (row_perm is its own inverse, and leaves row TY in place).
+  __device__ static int fslot(int fi, int fj, int fk, int FX, int FY) {
+    return fi + FX * (row_perm(fj) + FY * fk);
+  }
+  // With PF, the face of direction d that thread t forms for part m: m = 0 the low face
+  // of its own cell (the cells' order above), m = 1 a face of the tile's far plane (the
+  // threads below that plane's count); false when there is none.
+  __device__ static bool face_of(int d, int m, int t, int &fi, int &fj, int &fk) {
+    if (m == 0) {
+      cell_of(t, fi, fj, fk);
+      return t < TX * TY * TZ;
+    }
+    if (d == 0) {
+      fi = TX;
+      fj = t % TY;
+      fk = t / TY;
+      return t < TY * TZ;
+    }
+    if (d == 1) {
+      fi = t % TX;
+      fj = TY;
+      fk = t / TX;
+      return t < TX * TZ;
+    }
+    fi = t % TX;
+    fj = t / TX;
+    fk = TZ;
+    return t < TX * TY;
+  }
   __device__ static constexpr int pt(int a, int b, int c, int zoff) {
     return (a + 2) +
            SX * ((b + 2) + SY * (DIM == 3 ? (RING ? ((c + 2 + zoff) & (SZ - 1)) : c + 2) : 0));
@@ -500,13 +545,12 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       if (!T::PF) break;
-      const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2 ? 1 : 0);
 #pragma unroll
       for (int m = 0; m < T::FPT; ++m) {
-        const int f = threadIdx.x + kThreads * m;
         fpre[d][m] = S(0);
-        if (f >= FX * FY * FZ) continue;
-        const int gc[3] = {x0 + f % FX, y0 + (f / FX) % FY, z0 + f / (FX * FY)};
+        int fi, fj, fk;
+        if (!T::face_of(d, m, threadIdx.x, fi, fj, fk)) continue;
+        const int gc[3] = {x0 + fi, y0 + fj, z0 + fk};
         bool ok = true;
 #pragma unroll
         for (int e = 0; e < DIM; ++e) ok = ok && (gc[e] < g.n[e] + (e == d ? 1 : 0));
@@ -518,8 +562,9 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
       if (!T::PF) break;
-      const int lc = threadIdx.x + kThreads * m;
-      const int i = x0 + lc % T::TX, j = y0 + (lc / T::TX) % T::TY, k = z0 + lc / (T::TX * T::TY);
+      int ci, cj, ck;
+      T::cell_of(threadIdx.x + kThreads * m, ci, cj, ck);
+      const int i = x0 + ci, j = y0 + cj, k = z0 + ck;
 #pragma unroll
       for (int v = 0; v < DIM + 6; ++v) opre[m][v] = S(0);
       if (!(i < g.n[0] && j < g.n[1] && (DIM == 2 || k < g.n[2]))) continue;
@@ -609,8 +654,8 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     bool cv_ok[CPT];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-      const int lc = threadIdx.x + kThreads * m;
-      const int ci = lc % T::TX, cj = (lc / T::TX) % T::TY, ck = lc / (T::TX * T::TY);
+      int ci, cj, ck;
+      T::cell_of(threadIdx.x + kThreads * m, ci, cj, ck);
       cl[m][0] = ci;
       cl[m][1] = cj;
       cl[m][2] = ck;
@@ -664,9 +709,17 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       const int nfd = FX * FY * FZ;
 #pragma unroll
       for (int m = 0; m < T::FPT; ++m) {
-        const int f = threadIdx.x + kThreads * m;
-        if (f >= nfd) continue;
-        const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
+        int f, fi, fj, fk;
+        if (T::PF) {
+          if (!T::face_of(d, m, threadIdx.x, fi, fj, fk)) continue;
+          f = T::fslot(fi, fj, fk, FX, FY);
+        } else {
+          f = threadIdx.x + kThreads * m;
+          if (f >= nfd) continue;
+          fi = f % FX;
+          fj = (f / FX) % FY;
+          fk = f / (FX * FY);
+        }
         const int gi = x0 + fi, gj = y0 + fj, gk = z0 + fk;
         const int gc[3] = {gi, gj, gk};
         bool ok = true;
@@ -683,12 +736,13 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
         lf[(2 + DIM) * NFM + f] = fe;
       }
       __syncthreads();
-      const int step = (d == 0) ? 1 : (d == 1) ? FX : FX * FY;
       const S ih = S(g.ih[d]);
 #pragma unroll
       for (int m = 0; m < CPT; ++m) {
         if (!cv_ok[m]) continue;
-        const int fl = cl[m][0] + FX * (cl[m][1] + FY * cl[m][2]), fh = fl + step;
+        const int fl = T::fslot(cl[m][0], cl[m][1], cl[m][2], FX, FY);
+        const int fh = T::fslot(cl[m][0] + (d == 0), cl[m][1] + (d == 1), cl[m][2] + (d == 2),
+                                FX, FY);
         acc[m][0] += (lf[fh] - lf[fl]) * ih;
         acc[m][DIM + 2] += (lf[NFM + fh] - lf[NFM + fl]) * ih;
 #pragma unroll

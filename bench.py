@@ -554,7 +554,7 @@ def run_density(steps: int, warmup: int):
             r = run_forward(case, prec, st, wu)
             if "workload" not in ent:
                 kept = r["solver"].markers_in_use()[0].shape[0]
-                ent["workload"] = workload_text(case, kept, r["solver"].dt) + ", density-based"
+                ent["workload"] = workload_text(case, kept, r["solver"].dt)
             ent[prec] = {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
                          "kernels": {k: {"avg_us": round(v["avg_us"], 2),
                                          **({"GBps": round(v["GBps"], 1),

@@ -403,6 +403,31 @@ def test_cfg5_nusselt_gradient_full_size(cuda, conv):
     assert abs(ad - tl) <= 1e-10 * abs(tl), (ad, tl)
 
 
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_cfg5_vanleer_gradient_matches_oracle_tangent_100_steps(cuda):
+    """The van Leer gradient at full size (512^2, 200 markers, T_w = 1.3) over 100 steps
+    with checkpoints every 50, against the oracle's tangent-linear run along one seeded
+    unit direction: exact derivatives on both sides, so they agree to the pressure
+    solves' truncation wherever central differences would cross a limiter branch point
+    (the evidence behind the central-difference tolerance of the 500-step test)."""
+    c = inputs.case("cfg5", convection=VL)
+    m, ck = 100, 50
+    s = make_gpu(c, tape_steps=ck)
+    ob = np.zeros((m, 4))
+    ob[:, 3] = 1.0
+    _, Twb, _ = wall_temperature_gradient(s, m, ob, checkpoint=ck)
+    o = make_oracle(c)
+    d = inputs.normal(1006, c["ns"])
+    d = d / np.linalg.norm(d)
+    _, hd = o.tangent_linear(m, d)
+    tl = float(np.sum(hd[:, 3]))
+    ad = float(to_np(Twb) @ d)
+    print(f"\n  oracle tangent-linear over {m} steps: adjoint {ad:.15e} tangent {tl:.15e} "
+          f"rel {abs(ad - tl) / abs(tl):.1e}")
+    assert abs(ad - tl) <= 1e-9 * abs(tl), (ad, tl)
+
+
 def _turned_ring(c, angle=0.1):
     # the workload's ring turned by `angle`: no candidate on a grid line and no two
     # mirror images across a symmetry line of a cell (exact ties of the check

@@ -11,29 +11,48 @@
 namespace ibmk {
 
 // ------------------------------------------------------------------ physics
+// a / b for FAST FP64: the hardware reciprocal of b refined by two Newton steps, the
+// quotient corrected by its residual (b nonzero and of moderate size: densities,
+// temperatures and limiter denominators). Within about an ulp of the rounded
+// quotient, in 8 operations instead of the correctly rounded division's 11 (its
+// operand scaling and special-case fix-up are not needed here). Otherwise a / b.
+template <bool FAST, typename S>
+__device__ __forceinline__ S qdiv(S a, S b) {
+  if constexpr (FAST && std::is_same<S, double>::value) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+  } else {
+    return a / b;
+  }
+}
 // Sutherland's law (Sec. 2.1), theta^{3/2} as theta*sqrt(theta).
-template <typename S>
+template <typename S, bool FAST = false>
 __device__ __forceinline__ S mu_of(const GridK &g, S th) {
   if (g.visc == MU_CONSTANT) return S(g.mu_inf);
   S sut = S(g.S);
-  return S(g.mu_inf) * th * sqrt(th) * (S(1) + sut) / (th + sut);
+  return qdiv<FAST>(S(g.mu_inf) * th * sqrt(th) * (S(1) + sut), th + sut);
 }
 // van Leer limited face value from the upwind (C), downwind (D) and far-upwind
 // (U) cell values: phi_C + (1/2) psi(r) (phi_D - phi_C), written without r.
-template <typename S>
+template <typename S, bool FAST = false>
 __device__ __forceinline__ S vanleer(S phC, S phD, S phU) {
   S a = phC - phU, b = phD - phC;
   S ab = a * b;
-  return (ab > S(0)) ? phC + ab / (a + b) : phC;
+  return (ab > S(0)) ? phC + qdiv<FAST>(ab, a + b) : phC;
 }
 
 // Primitive variables at a (possibly ghost) cell from the conserved values of the
 // cell r resolves to: cons = rho, m[DIM], E.
-template <int DIM, typename S>
+template <int DIM, typename S, bool FAST = false>
 __device__ __forceinline__ void prim_from(const GridK &g, const Resolved &r, const S *cons, S &rho,
                                           S *u, S &th, S &p) {
   rho = cons[0];
-  S inv = S(1) / rho;
+  S inv = qdiv<FAST>(S(1), rho);
 #pragma unroll
   for (int q = 0; q < DIM; ++q) u[q] = cons[1 + q] * inv;
   S E = cons[DIM + 1];
@@ -192,12 +211,12 @@ struct PredOut {
 
 // The same from the previous energies Ep, E2, E3 of cell c already read (each read
 // only where po gives its array).
-template <typename S>
+template <typename S, bool FAST = false>
 __device__ __forceinline__ void pred_setup_out_vals(const GridK &g, const PredOut<S> &po,
                                                     int64_t c, S rho_s, S E_s, S E, S Ep, S E2,
                                                     S E3) {
-  const S theta = E_s / (rho_s * S(g.cv));
-  po.psi[c] = S(1) / (S(g.R) * theta);
+  const S theta = qdiv<FAST>(E_s, rho_s * S(g.cv));
+  po.psi[c] = qdiv<FAST>(S(1), S(g.R) * theta);
   if (!po.x) return;
   const double pn = double(S(g.gm1) * E);
   double x0 = pn;
@@ -435,7 +454,9 @@ struct PredLds {
 
 // Face fluxes from the LDS primitives; Q is the cell at local (qa, qb, qc), P the
 // cell below it along d. Same arithmetic as face_flux.
-template <int DIM, typename S>
+// CONV: the convection scheme fixed at compile time (-1: read from g); FAST: qdiv's
+// quotients.
+template <int DIM, typename S, int CONV = -1, bool FAST = false>
 __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int zoff, int d, int qa,
                                               int qb, int qc, S F, S &uf, S *fm, S &fe) {
   using T = PredLds<DIM, S>;
@@ -452,7 +473,7 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int z
   }
   const S thP = lv[(DIM + 1) * NP + iP], thQ = lv[(DIM + 1) * NP + iQ];
   const S muP = lv[(DIM + 2) * NP + iP], muQ = lv[(DIM + 2) * NP + iQ];
-  uf = F / (S(0.5) * (rP + rQ));
+  uf = qdiv<FAST>(F, S(0.5) * (rP + rQ));
   const S muf = S(0.5) * (muP + muQ);
   const S lamf = S(g.cp_Pr) * muf;
   const S ih = S(g.ih[d]);
@@ -481,7 +502,7 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int z
   }
   S cu[3], ce;
   const S cv = S(g.cv);
-  if (g.conv == CONV_LINEAR) {
+  if (CONV >= 0 ? CONV == CONV_LINEAR : g.conv == CONV_LINEAR) {
 #pragma unroll
     for (int q = 0; q < DIM; ++q) cu[q] = S(0.5) * (uP[q] + uQ[q]);
     ce = S(0.5) * (cv * thP + cv * thQ);
@@ -494,9 +515,10 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int z
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
       const S uU = lv[(1 + q) * NP + iU];
-      cu[q] = pos ? vanleer(uP[q], uQ[q], uU) : vanleer(uQ[q], uP[q], uU);
+      cu[q] = pos ? vanleer<S, FAST>(uP[q], uQ[q], uU) : vanleer<S, FAST>(uQ[q], uP[q], uU);
     }
-    ce = pos ? vanleer(cv * thP, cv * thQ, cv * thU) : vanleer(cv * thQ, cv * thP, cv * thU);
+    ce = pos ? vanleer<S, FAST>(cv * thP, cv * thQ, cv * thU)
+             : vanleer<S, FAST>(cv * thQ, cv * thP, cv * thU);
   }
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
@@ -508,7 +530,7 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int z
   fe = g.implicit_diff ? F * ce : F * ce - lamf * (thQ - thP) * ih;
 }
 
-template <int DIM, typename S>
+template <int DIM, typename S, int CONV = -1>
 __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> st, S *rho_s,
                                                             S *ms0, S *ms1, S *ms2, S *E_s,
                                                             PredOut<S> po) {
@@ -636,13 +658,13 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       for (int m = 0; m < T::PCH; ++m) {
         if (!okp[m]) continue;
         S r, u[3], th, pp;
-        prim_from<DIM>(g, rr[m], cons[m], r, u, th, pp);
+        prim_from<DIM, S, T::PF>(g, rr[m], cons[m], r, u, th, pp);
         const int q0 = lp[m];
         lv[q0] = r;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + q0] = u[q];
         lv[(DIM + 1) * NP + q0] = th;
-        lv[(DIM + 2) * NP + q0] = mu_of(g, th);
+        lv[(DIM + 2) * NP + q0] = mu_of<S, T::PF>(g, th);
         if (T::PL) lv[(DIM + 3) * NP + q0] = pp;
       }
     }
@@ -728,7 +750,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
         if (!ok) continue;
         const S F = T::PF ? fpre[d][m] : st.F[d][fidx(g, d, gi, gj, gk)];
         S uf, fm[3], fe;
-        face_flux_lds<DIM, S>(g, lv, zoff, d, fi, fj, fk, F, uf, fm, fe);
+        face_flux_lds<DIM, S, CONV, T::PF>(g, lv, zoff, d, fi, fj, fk, F, uf, fm, fe);
         lf[f] = F;
         lf[NFM + f] = uf;
 #pragma unroll
@@ -770,8 +792,8 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
                    dt * (gm1 * E) * acc[m][DIM + 2];
       E_s[c] = es;
       if (T::PF)
-        pred_setup_out_vals(g, po, c, rs, es, E, opre[m][DIM + 3], opre[m][DIM + 4],
-                            opre[m][DIM + 5]);
+        pred_setup_out_vals<S, T::PF>(g, po, c, rs, es, E, opre[m][DIM + 3], opre[m][DIM + 4],
+                                      opre[m][DIM + 5]);
       else
         pred_setup_out(g, po, c, rs, es, E);
     }
@@ -3145,20 +3167,24 @@ size_t predictor_lds_bytes(int dim, int prec) {
   return prec ? PredLds<3, float>::bytes : PredLds<3, double>::bytes;
 }
 
+template <int DIM, typename S>
+static void enable_lds_kernels(int bytes) {
+  (void)hipFuncSetAttribute((const void *)k_predictor_lds<DIM, S, CONV_LINEAR>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute((const void *)k_predictor_lds<DIM, S, CONV_VANLEER>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 void enable_predictor_lds(int dim, int prec) {
   const int bytes = (int)predictor_lds_bytes(dim, prec);
   if (dim == 2 && prec == 0)
-    (void)hipFuncSetAttribute((const void *)k_predictor_lds<2, double>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    enable_lds_kernels<2, double>(bytes);
   else if (dim == 2)
-    (void)hipFuncSetAttribute((const void *)k_predictor_lds<2, float>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    enable_lds_kernels<2, float>(bytes);
   else if (prec == 0)
-    (void)hipFuncSetAttribute((const void *)k_predictor_lds<3, double>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    enable_lds_kernels<3, double>(bytes);
   else
-    (void)hipFuncSetAttribute((const void *)k_predictor_lds<3, float>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    enable_lds_kernels<3, float>(bytes);
 }
 
 void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order, int keep) {
@@ -3181,9 +3207,17 @@ void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order,
                          ((L.g.n[1] + T::TY - 1) / T::TY) *
                          (DIM == 3 ? (L.g.n[2] + T::TZ - 1) / T::TZ : 1);
       const int64_t nb = std::min<int64_t>(((nt + 7) / 8) * 8, IBM_PRED_MAXB);
-      hipLaunchKernelGGL((k_predictor_lds<DIM, S>), dim3((unsigned)nb), dim3(kThreads), T::bytes,
-                         L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],
-                         (S *)B.mom_s[1], (S *)B.mom_s[2], (S *)B.E_s, po);
+      // the convection scheme compiled in (straight-line face code, fewer registers)
+      if (L.g.conv == CONV_LINEAR)
+        hipLaunchKernelGGL((k_predictor_lds<DIM, S, CONV_LINEAR>), dim3((unsigned)nb),
+                           dim3(kThreads), T::bytes, L.st, L.g, state_of<S>(B, cur),
+                           (S *)B.rho_s, (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2],
+                           (S *)B.E_s, po);
+      else
+        hipLaunchKernelGGL((k_predictor_lds<DIM, S, CONV_VANLEER>), dim3((unsigned)nb),
+                           dim3(kThreads), T::bytes, L.st, L.g, state_of<S>(B, cur),
+                           (S *)B.rho_s, (S *)B.mom_s[0], (S *)B.mom_s[1], (S *)B.mom_s[2],
+                           (S *)B.E_s, po);
     } else {
       hipLaunchKernelGGL((k_predictor<DIM, S>), dim3((unsigned)L.g.nblocks), dim3(kThreads), 0,
                          L.st, L.g, state_of<S>(B, cur), (S *)B.rho_s, (S *)B.mom_s[0],

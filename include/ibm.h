@@ -321,7 +321,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
 int32_t ibm_tape_length(const ibm_ctx *ctx);
 
 /* Gradient with respect to the candidate marker positions (not in the paper:
- * shape sensitivities of the same objective as ibm_adjoint_step). Every adjoint
+ * shape sensitivities of the same objective as ibm_adjoint_step). An adjoint
  * step adds, for markers at rest, the cotangents of the step's kernel weights
  * w_ck (Sec. 2.2, Eqs. (5)-(7)) and quadrature weights eps_k (Eqs. (8)-(9)) to an
  * accumulator in the workspace. This call turns the accumulation into dJ/dX:
@@ -330,10 +330,12 @@ int32_t ibm_tape_length(const ibm_ctx *ctx);
  * the kernel's derivative gives X_bar. The check routine's choice of markers and
  * the support cells are held fixed (the derivative almost everywhere; candidates
  * not in use get 0).
- *   X_bar   device double [n candidates][dim]: dJ/dX is added (+=); NULL only
- *           clears the accumulator
- * The accumulator is cleared by every call (start a reverse pass with a NULL
- * call). Synchronises. IBM_E_STATE without a tape workspace or markers, IBM_E_ARG
+ *   X_bar   device double [n candidates][dim]: dJ/dX is added (+=); NULL clears
+ *           the accumulator and starts the accumulation
+ * Adjoint steps add to the accumulator only between a NULL call and the next call
+ * with X_bar, which reads it and stops the accumulation (so a reverse pass that wants
+ * no position gradient pays nothing for it): start such a reverse pass with a NULL
+ * call. Synchronises. IBM_E_STATE without a tape workspace or markers, IBM_E_ARG
  * for moving markers, IBM_E_SIZE above 4096 candidates (X_bar given),
  * IBM_E_NOT_CONVERGED if the Gram solve fails. */
 ibm_status ibm_shape_gradient(ibm_ctx *ctx, double *X_bar);

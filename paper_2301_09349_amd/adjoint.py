@@ -104,7 +104,8 @@ class Rollout:
             sb.copy_(state_bar_final)
         sb2 = torch.empty_like(sb)
         Tw_bar = torch.zeros(s.nc, dtype=torch.float64, device=s.device)
-        s.shape_gradient(None)  # the adjoint steps below accumulate from zero
+        if positions:
+            s.shape_gradient(None)  # the adjoint steps below accumulate from zero
         for start, k, ck, st_step in reversed(self.segs):
             _set_state_vector(s, ck, st_step)
             s.step(k, hist=False, record=True)

@@ -1048,7 +1048,8 @@ void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in
   });
 }
 
-void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, double *Tw_bar) {
+void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, double *Tw_bar,
+                     bool shape) {
   const int nslot = (L.g.dim == 3) ? 27 : 9;
   hipLaunchKernelGGL(k_adj_markers, dim3((unsigned)((L.nc_cap + 127) / 128)), dim3(128), 0, L.st,
                      L.g, (const int *)B.mcount, (const int64_t *)B.pcell, (const double *)B.pw,
@@ -1058,7 +1059,7 @@ void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, doub
                      (const int *)B.ids, out_bar[0], out_bar[1], out_bar[2], out_bar[3], B.mkbar,
                      Tw_bar, B.epsbar);
   const int64_t cap = (int64_t)L.nc_cap * nslot;
-  if (B.wbar)
+  if (B.wbar && shape)
     hipLaunchKernelGGL(k_adj_shape_pairs, dim3(nb256(cap)), dim3(256), 0, L.st, L.g,
                        (const int *)B.mcount, (const int64_t *)B.pcell, nslot,
                        (const double *)B.ms_bar[0], (const double *)B.ms_bar[1],

@@ -128,6 +128,9 @@ struct ibm_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_used = nullptr, ev_built = nullptr;
   bool ahead = false;  // a rebuild is queued on `side` that the main stream has not joined
+  // adjoint steps accumulate the marker-position cotangents (between a NULL call of
+  // ibm_shape_gradient and the call that reads them)
+  bool shape_acc = false;
   std::string err;
   CgScal cgh;
   Prof prof;
@@ -527,7 +530,7 @@ ibm_status marker_flags(ibm_ctx *ctx, const int *f) {
   return IBM_OK;
 }
 
-// Copies state slot `slot` to tape record `rec` (to_tape) or back.
+// Copies state slot `slot` to tape record `rec` (to_tape) or back, in one launch.
 ibm_status tape_copy(ibm_ctx *ctx, int rec, int slot, bool to_tape) {
   const GridK &g = ctx->L.g;
   Bufs &B = ctx->B;
@@ -550,13 +553,18 @@ ibm_status tape_copy(ibm_ctx *ctx, int rec, int slot, bool to_tape) {
     parts[np] = B.F[slot][q];
     sizes[np++] = (size_t)g.NF[q];
   }
+  ibmk::CopyParts cp;
   size_t off = 0;
   for (int i = 0; i < np; ++i) {
     void *dst = to_tape ? (void *)(base + off) : parts[i];
     const void *src = to_tape ? (const void *)parts[i] : (const void *)(base + off);
-    HIPCHECK(ctx, hipMemcpyAsync(dst, src, sizes[i] * w, hipMemcpyDeviceToDevice, st));
+    cp.add(dst, src, sizes[i] * w);
     off += sizes[i] * w;
   }
+  Launch L = ctx->L;
+  L.st = st;
+  ibmk::run_copy_parts(L, cp);
+  HIPCHECK(ctx, hipGetLastError());
   return IBM_OK;
 }
 
@@ -1399,8 +1407,10 @@ ibm_status ibm_shape_gradient(ibm_ctx *ctx, double *X_bar) {
     ibmk::run_shape_clear(L, ctx->B, ctx->nc);
     HIPCHECK(ctx, hipGetLastError());
     HIPCHECK(ctx, hipStreamSynchronize(st));
+    ctx->shape_acc = true;
     return IBM_OK;
   }
+  ctx->shape_acc = false;
   if (!ibmk::shape_supported(ctx->nc))
     return fail(ctx, IBM_E_SIZE, "shape_gradient: more candidate markers than supported");
   HIPCHECK(ctx, hipMemsetAsync(ctx->B.flags, 0, 8 * sizeof(int), st));
@@ -1449,12 +1459,18 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
   }
   ibmk::run_predictor(L, B, slot, slot, 0, 0);
   if (ctx->nc > 0) {
-    ibmk::run_pair_fields(L, B);  // the interpolated fields, for the position gradient
+    // the interpolated fields, for the position gradient while one is accumulated
+    if (ctx->shape_acc) ibmk::run_pair_fields(L, B);
     ibmk::run_markers_step(L, B, nullptr);
   }
   ibmk::run_setup(L, B, slot, ++ctx->tag);
-  HIPCHECK(ctx, hipMemcpyAsync(B.x, B.tape + B.tape_stride * (size_t)tape_index + B.tape_xoff,
-                               (size_t)L.g.N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  {
+    // the recorded solution replaces the solve (the set-up's CG start is overwritten)
+    ibmk::CopyParts cp;
+    cp.add(B.x, B.tape + B.tape_stride * (size_t)tape_index + B.tape_xoff,
+           (size_t)L.g.N * sizeof(double));
+    ibmk::run_copy_parts(L, cp);
+  }
   // reverse: correction, pressure solve, set-up, forcing and spreading, predictor
   ibmk::run_adj_correction(L, B, slot, state_bar_in, state_bar_out);
   const int tag = ++ctx->tag;
@@ -1468,7 +1484,7 @@ ibm_status ibm_adjoint_step(ibm_ctx *ctx, int32_t tape_index, const double *stat
     if (r) return r;
   }
   ibmk::run_adj_setup(L, B, slot, state_bar_in, state_bar_out);
-  if (ctx->nc > 0) ibmk::run_adj_markers(L, B, ob, Tw_bar);
+  if (ctx->nc > 0) ibmk::run_adj_markers(L, B, ob, Tw_bar, ctx->shape_acc);
   ibmk::run_adj_predictor(L, B, slot, state_bar_out);
   HIPCHECK(ctx, hipGetLastError());
   return IBM_OK;

@@ -801,6 +801,37 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
 }
 
 // ------------------------------------------------------- initialisation
+// Byte ranges copied in one launch: part p moves units[p] elements of type T (4 or
+// 16 bytes) from src[p] to dst[p]; the grid strides over each part in turn.
+template <typename T>
+__global__ void k_copy_parts(CopyParts cp) {
+  const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int p = 0; p < cp.n; ++p) {
+    const T *src = static_cast<const T *>(cp.src[p]);
+    T *dst = static_cast<T *>(cp.dst[p]);
+    const int64_t n = (int64_t)(cp.bytes[p] / sizeof(T));
+    for (int64_t k = i0; k < n; k += stride) dst[k] = src[k];
+  }
+}
+
+void run_copy_parts(const Launch &L, const CopyParts &cp) {
+  if (cp.n == 0) return;
+  bool wide = true;
+  size_t most = 0;
+  for (int p = 0; p < cp.n; ++p) {
+    wide = wide && (reinterpret_cast<uintptr_t>(cp.src[p]) % 16 == 0) &&
+           (reinterpret_cast<uintptr_t>(cp.dst[p]) % 16 == 0) && cp.bytes[p] % 16 == 0;
+    most = std::max(most, cp.bytes[p]);
+  }
+  const size_t unit = wide ? 16 : 4;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((most / unit + 255) / 256, 2048));
+  if (wide)
+    hipLaunchKernelGGL(k_copy_parts<uint4>, dim3((unsigned)blocks), dim3(256), 0, L.st, cp);
+  else
+    hipLaunchKernelGGL(k_copy_parts<unsigned>, dim3((unsigned)blocks), dim3(256), 0, L.st, cp);
+}
+
 __global__ void k_fill(double *p, int64_t n, double v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;

@@ -113,8 +113,25 @@ struct Launch {
   hipStream_t st;
 };
 
+// Up to kCopyParts device byte ranges (each size a multiple of 4 bytes) to copy in one
+// launch.
+constexpr int kCopyParts = 8;
+struct CopyParts {
+  const void *src[kCopyParts];
+  void *dst[kCopyParts];
+  size_t bytes[kCopyParts];
+  int n = 0;
+  void add(void *d, const void *s, size_t b) {
+    dst[n] = d;
+    src[n] = s;
+    bytes[n] = b;
+    ++n;
+  }
+};
+
 // grid kernels (ibm_grid.hip)
 void run_fill(const Launch &L, double *p, int64_t n, double v);
+void run_copy_parts(const Launch &L, const CopyParts &cp);
 void run_uniform_state(const Launch &L, const Bufs &B, int cur);
 void run_init_primitive(const Launch &L, const Bufs &B, int cur, const void *rho, const void *u,
                         const void *theta);
@@ -173,8 +190,10 @@ void run_adj_correction(const Launch &L, const Bufs &B, int slot, const double *
 // the adjoint pressure solve then runs run_cg_iteration with x -> lam
 void run_adj_cg_init(const Launch &L, const Bufs &B, int tag);
 void run_adj_setup(const Launch &L, const Bufs &B, int slot, const double *sb_in, double *sb_out);
-// out_bar: host double[4], the cotangents of the step's Fx, Fy, Fz, H
-void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, double *Tw_bar);
+// out_bar: host double[4], the cotangents of the step's Fx, Fy, Fz, H; shape: the
+// kernel-weight cotangents of the marker-position gradient are accumulated too
+void run_adj_markers(const Launch &L, const Bufs &B, const double *out_bar, double *Tw_bar,
+                     bool shape);
 void run_pair_fields(const Launch &L, const Bufs &B);
 bool shape_supported(int nc);
 void run_shape_clear(const Launch &L, const Bufs &B, int nc);

@@ -342,7 +342,9 @@ def test_cfg5_nusselt_gradient_full_size(cuda, conv):
     (measured disagreement 4e-6..8e-5 at 1e-4..1e-6, 3e-8..1.4e-7 at 1e-7). Even at
     1e-7 a direction can cross one (2.2e-5 measured on one of ten), so with van Leer
     every direction must agree to 1e-4 and all but two to 1e-6; the exact check is
-    the tangent-linear one."""
+    the tangent-linear one. The + and - runs of every direction take the same number
+    of CG iterations (printed; 5347 each with van Leer), so the outlier is not a
+    difference in the pressure solves' truncation."""
     c = inputs.case("cfg5", convection=conv)
     n, ck = int(c["steps"]), int(c["checkpoint"])
     s = make_gpu(c, tape_steps=ck)
@@ -371,17 +373,20 @@ def test_cfg5_nusselt_gradient_full_size(cuda, conv):
     for j in range(10):
         d = inputs.normal(1000 + j, c["ns"])
         d = d / np.linalg.norm(d)
-        Js = []
+        Js, its = [], []
         for sgn in (1.0, -1.0):
             _set_state_vector(s, x0, 0)
             s.set_wall_temperature(Tw0 + sgn * h * torch.as_tensor(d, device=s.device))
-            hh, _ = s.step(n)
+            hh, info = s.step(n)
             Js.append(ku * float(hh[:, 3].mean()))
+            its.append(info["cg_iters_total"])
         fd = (Js[0] - Js[1]) / (2 * h)
         ad = float(g @ d)
         errs.append(abs(ad - fd) / abs(ad))
+        # the pressure solves of the two runs take the same number of iterations or not
+        # (a different count leaves a different truncation in J(+) - J(-))
         print(f"  direction {j}: adjoint {ad:.10e} central difference {fd:.10e} "
-              f"rel {errs[-1]:.1e}")
+              f"rel {errs[-1]:.1e}, CG iterations {its[0]} / {its[1]}")
     if conv == LIN:
         assert max(errs) <= 1e-5, errs
     else:
@@ -418,7 +423,8 @@ def test_cfg5_vanleer_gradient_matches_oracle_tangent_100_steps(cuda):
     ob[:, 3] = 1.0
     _, Twb, _ = wall_temperature_gradient(s, m, ob, checkpoint=ck)
     o = make_oracle(c)
-    d = inputs.normal(1006, c["ns"])
+    # the direction whose central difference at 1e-7 is the outlier of the 500-step test
+    d = inputs.normal(1007, c["ns"])
     d = d / np.linalg.norm(d)
     _, hd = o.tangent_linear(m, d)
     tl = float(np.sum(hd[:, 3]))

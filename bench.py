@@ -258,60 +258,85 @@ def fp32_error(r64, r32):
 
 
 def run_adjoint(steps: int, checkpoint: int, warmup: int, precision: str = "fp64"):
-    """Adjoint/forward time ratio on the gradient workload: forward = `steps` plain
-    steps; backward = the checkpointed reverse pass over the same steps (segment
-    re-run with the tape on, then one adjoint step per step)."""
+    """Adjoint/forward time ratio on the gradient workload. forward = `steps` plain
+    steps; backward = what the gradient costs beyond them: the rollout's forward pass
+    (checkpoints, and its last segment recorded on the tape) less the plain steps,
+    then the reverse pass (each earlier segment re-run with the tape on, one adjoint
+    step per step). Also with a tape of all the steps (nothing re-run)."""
     import numpy as np
     import torch
 
     from paper_2301_09349_amd import inputs
-    from paper_2301_09349_amd.adjoint import Rollout, nusselt_scale, _set_state_vector
+    from paper_2301_09349_amd.adjoint import (Rollout, nusselt_scale, _set_state_vector,
+                                              _state_vector)
 
     case = inputs.case("cfg5")
-    s = make_solver(case, precision, tape_steps=checkpoint)
-    if warmup:
-        s.step(warmup)
-    roll = Rollout(s, steps, checkpoint)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    roll.forward()
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    ob = np.zeros((steps, 4))
-    ob[:, 3] = nusselt_scale(case) / steps
-    # the reverse pass of Rollout.reverse, with its two parts timed apart
-    sb = torch.zeros(s.state_size, dtype=torch.float64, device="cuda:0")
-    sb2 = torch.empty_like(sb)
-    Tw_bar = torch.zeros(s.nc, dtype=torch.float64, device="cuda:0")
-    t_rec = t_adj = 0.0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for start, k, ck, st_step in reversed(roll.segs):
-        ta = time.perf_counter()
-        _set_state_vector(s, ck, st_step)
-        s.step(k, hist=False, record=True)
+    out = {"workload": "2D heated cylinder, 512x512 over [-4,12]x[-8,8], 200 candidate "
+                       "markers, Re 100, Ma 0.2, Tw 1.3, van Leer convection, CG rtol 1e-13; "
+                       "gradient of the time-averaged Nusselt number w.r.t. T_w",
+           "steps": steps, "checkpoint": checkpoint, "precision": precision}
+    for label, ckpt in (("", checkpoint), ("_tape_all_steps", steps)):
+        s = make_solver(case, precision, tape_steps=ckpt)
+        if warmup:
+            s.step(warmup)
+        x0 = _state_vector(s)
+        step0 = warmup
+        _set_state_vector(s, x0, step0)
         torch.cuda.synchronize()
-        tb = time.perf_counter()
-        for i in reversed(range(k)):
-            s.adjoint_step(i, sb, sb2, ob[start + i], Tw_bar)
-            sb, sb2 = sb2, sb
+        t0 = time.perf_counter()
+        s.step(steps, hist=False)
         torch.cuda.synchronize()
-        tc = time.perf_counter()
-        t_rec += tb - ta
-        t_adj += tc - tb
-    t_rev = time.perf_counter() - t0
-    gnorm = float(torch.linalg.norm(Tw_bar))
-    return {"workload": "2D heated cylinder, 512x512 over [-4,12]x[-8,8], 200 candidate "
-                        "markers, Re 100, Ma 0.2, Tw 1.3, van Leer convection, CG rtol 1e-13; "
-                        "gradient of the time-averaged Nusselt number w.r.t. T_w",
-            "steps": steps, "checkpoint": checkpoint,
-            "forward_ms_per_step": round(1e3 * t_fwd / steps, 4),
-            "backward_ms_per_step": round(1e3 * t_rev / steps, 4),
-            "recompute_ms_per_step": round(1e3 * t_rec / steps, 4),
-            "adjoint_step_ms": round(1e3 * t_adj / steps, 4),
-            "ratio": round(t_rev / t_fwd, 3),
-            "ratio_adjoint_step_only": round(t_adj / t_fwd, 3),
-            "grad_norm": gnorm, "precision": precision}
+        t_plain = time.perf_counter() - t0
+        _set_state_vector(s, x0, step0)
+        roll = Rollout(s, steps, ckpt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        roll.forward()
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        ob = np.zeros((steps, 4))
+        ob[:, 3] = nusselt_scale(case) / steps
+        # the reverse pass of Rollout.reverse, with its two parts timed apart
+        sb = torch.zeros(s.state_size, dtype=torch.float64, device="cuda:0")
+        sb2 = torch.empty_like(sb)
+        Tw_bar = torch.zeros(s.nc, dtype=torch.float64, device="cuda:0")
+        t_rec = t_adj = 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for idx in reversed(range(len(roll.segs))):
+            start, k, ck, st_step = roll.segs[idx]
+            ta = time.perf_counter()
+            if idx != roll.taped or s.tape_length() != k:
+                _set_state_vector(s, ck, st_step)
+                s.step(k, hist=False, record=True)
+            roll.taped = None
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            for i in reversed(range(k)):
+                s.adjoint_step(i, sb, sb2, ob[start + i], Tw_bar)
+                sb, sb2 = sb2, sb
+            torch.cuda.synchronize()
+            tc = time.perf_counter()
+            t_rec += tb - ta
+            t_adj += tc - tb
+        t_rev = time.perf_counter() - t0
+        t_back = (t_fwd - t_plain) + t_rev
+        ent = {"forward_ms_per_step": round(1e3 * t_plain / steps, 4),
+               "rollout_forward_ms_per_step": round(1e3 * t_fwd / steps, 4),
+               "backward_ms_per_step": round(1e3 * t_back / steps, 4),
+               "recompute_ms_per_step": round(1e3 * t_rec / steps, 4),
+               "adjoint_step_ms": round(1e3 * t_adj / steps, 4),
+               "ratio": round(t_back / t_plain, 3),
+               "ratio_adjoint_step_only": round(t_adj / t_plain, 3),
+               "grad_norm": float(torch.linalg.norm(Tw_bar))}
+        if label:
+            out["tape_all_steps"] = {k: v for k, v in ent.items()
+                                     if k in ("backward_ms_per_step", "ratio", "grad_norm")}
+        else:
+            out.update(ent)
+        del s, roll
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_cylinder(steps: int, warmup: int):
@@ -1007,7 +1032,7 @@ def main():
         out["adjoint"] = run_adjoint(args.adjoint_steps, 50, 10)
         a32 = run_adjoint(args.adjoint_steps, 50, 10, "fp32")
         out["adjoint_fp32"] = {k: a32[k] for k in ("forward_ms_per_step", "backward_ms_per_step",
-                                                   "ratio", "grad_norm")}
+                                                   "ratio", "grad_norm", "tape_all_steps")}
     if not args.no_cpu:
         log(f"bench: timing the oracle on {args.cpu_steps} step(s) ...")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -7,9 +7,12 @@ The objective is linear in the per-step wall totals of the forcing
 ``J = sum_n out_bar[n] . (Fx, Fy, Fz, H)_n`` over ``n_steps`` steps from the
 current state. Time-averaged drag and Nusselt number are such objectives: their
 normalisations (``drag_scale``, ``nusselt_scale``) only scale ``out_bar``.
-The forward pass stores the state every ``checkpoint`` steps; the reverse pass
-re-runs each segment with the tape on and walks it backwards, so device memory
-grows with ``checkpoint``, not with ``n_steps``.
+The forward pass stores the state every ``checkpoint`` steps and records its last
+segment on the tape as it runs; the reverse pass walks that segment backwards at
+once, then re-runs each earlier segment with the tape on and walks it backwards, so
+device memory grows with ``checkpoint``, not with ``n_steps``. With a tape of all
+the steps (``checkpoint >= n_steps`` and the solver's ``tape_steps`` as large: about
+8 MB per step on a 512^2 FP32 grid, well within one GPU's HBM) nothing is re-run.
 """
 
 from __future__ import annotations
@@ -68,6 +71,7 @@ class Rollout:
         self.segs = []
         self.final = None
         self.final_step = 0
+        self.taped = None  # the segment the forward pass left on the tape
 
     def forward(self) -> torch.Tensor:
         """Runs the steps; returns the history [n_steps, 4] (Fx, Fy, Fz, H)."""
@@ -75,11 +79,15 @@ class Rollout:
         hist = torch.zeros((self.n_steps, 4), dtype=torch.float64, device=s.device)
         self.segs = []
         done = 0
+        self.taped = None
         while done < self.n_steps:
             k = min(self.checkpoint, self.n_steps - done)
             ck = _state_vector(s)
-            h, info = s.step(k)
+            last = done + k == self.n_steps
+            h, info = s.step(k, record=last)
             self.segs.append((done, k, ck, int(info["step"]) - k))
+            if last:
+                self.taped = len(self.segs) - 1
             hist[done: done + k] = h
             done += k
         self.final = _state_vector(s)
@@ -106,9 +114,13 @@ class Rollout:
         Tw_bar = torch.zeros(s.nc, dtype=torch.float64, device=s.device)
         if positions:
             s.shape_gradient(None)  # the adjoint steps below accumulate from zero
-        for start, k, ck, st_step in reversed(self.segs):
-            _set_state_vector(s, ck, st_step)
-            s.step(k, hist=False, record=True)
+        for idx in reversed(range(len(self.segs))):
+            start, k, ck, st_step = self.segs[idx]
+            # the last segment is still on the tape from the forward pass
+            if idx != self.taped or s.tape_length() != k:
+                _set_state_vector(s, ck, st_step)
+                s.step(k, hist=False, record=True)
+            self.taped = None
             for i in reversed(range(k)):
                 s.adjoint_step(i, sb, sb2, ob[start + i], Tw_bar)
                 sb, sb2 = sb2, sb

@@ -951,7 +951,7 @@ def main():
     log("bench: per-kernel " + json.dumps({k: {kk: (round(vv, 2) if isinstance(vv, float) else vv)
                                                  for kk, vv in v.items()}
                                              for k, v in per_kernel.items()}))
-    ids, _ = r["solver"].markers_in_use()
+    ids, eps_used = r["solver"].markers_in_use()
     out = {
         "metric": "Mcell-steps/s (fwd, FP32 vs FP64 at stated err) + adjoint/forward time ratio",
         "value": round(r["value"], 2),
@@ -967,7 +967,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_text(case, ids.shape[0], r["solver"].dt),
                    "cells": r["N"], "precision": main_p,
-                   "cg_iters_per_step": round(r["info"]["cg_iters_total"] / args.steps, 2)},
+                   "cg_iters_per_step": round(r["info"]["cg_iters_total"] / args.steps, 2),
+                   # the quadrature weights of the markers in use (Eqs. (8)-(9))
+                   "eps_range": [round(float(eps_used.min()), 4), round(float(eps_used.max()), 4)],
+                   "eps_negative": int((eps_used < 0).sum())},
         "roofline": roof,
         "kernels": {k: {"avg_us": round(v["avg_us"], 2), "launches": v["launches"],
                         "ms_per_step": round(v["ms_per_step"], 4),

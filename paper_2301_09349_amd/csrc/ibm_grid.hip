@@ -2125,10 +2125,15 @@ __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> s
   if (dens_skip(flags)) return;
   int x0, y0, z0;
   T::origin(g, blockIdx.x, x0, y0, z0);
-  // phase 1: primitives of the tile and its halo (up to two layers outside the box)
+  // phase 1: primitives of the tile and its halo (up to two layers outside the box).
+  // The faces reconstruct along their normal only, so the halo's edges and corners
+  // (points outside the tile in two or more directions) are never read: not loaded.
   for (int p = threadIdx.x; p < T::NP; p += kThreads) {
     const int li = p % T::SX - 2, lj = (p / T::SX) % T::SY - 2;
     const int lk = DIM == 3 ? p / (T::SX * T::SY) - 2 : 0;
+    const int outside = (li < 0 || li >= T::TX) + (lj < 0 || lj >= T::TY) +
+                        (DIM == 3 && (lk < 0 || lk >= T::TZ));
+    if (outside >= 2) continue;
     const int gi = x0 + li, gj = y0 + lj, gk = z0 + lk;
     bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
     if (DIM == 3) ok = ok && gk >= -2 && gk <= g.n[2] + 1;

@@ -40,12 +40,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def refine32(dim: int, precision: str) -> bool:
+    """Whether the FP32 form solves by refinement around an FP32 inner CG: the
+    library's default in 3D, IBM_FP32_SOLVE=refine|fp64 overriding it."""
+    if precision != "fp32":
+        return False
+    env = os.environ.get("IBM_FP32_SOLVE", "")
+    return env == "refine" or (env != "fp64" and dim == 3)
+
+
 def kernel_bytes(cls: str, dim: int, precision: str = "fp64", scheme: int = 0) -> int:
     """Algorithmic bytes each kernel class must move per cell (each distinct array
     element read or written once; face arrays counted as one value per cell and
     direction). State-type arrays take s bytes (8 FP64, 4 FP32); the pressure x, the
-    right-hand side b and the FP64 CG vectors take 8 in both forms."""
+    right-hand side b and the FP64 CG vectors take 8 in both forms. The FP32 form's
+    solve by refinement has FP32 CG vectors (an inner iteration's figure is given
+    for its launches) and its set-up leaves the CG start to the solve."""
     s = 8 if precision == "fp64" else 4
+    if scheme == 0 and refine32(dim, precision):
+        if cls == "setup":
+            # rho^n, m^, psi, F^ (FP32), x, b (FP64), the start residual (FP32)
+            return 4 * (2 * dim + 2) + 8 * 2 + 4
+        if cls == "cg":
+            # inner iteration: psi, r, w, s_old, p, d -> r', w', s, p, d, all FP32
+            return 4 * 11
     if scheme == 1:  # density-based step
         if cls == "predictor":
             # inviscid: rho, m, E -> rho*, (rho u)**, (rho e_t)**, face mass flux;

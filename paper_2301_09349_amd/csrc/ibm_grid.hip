@@ -11,11 +11,12 @@
 namespace ibmk {
 
 // ------------------------------------------------------------------ physics
-// a / b for FAST FP64: the hardware reciprocal of b refined by two Newton steps, the
-// quotient corrected by its residual (b nonzero and of moderate size: densities,
-// temperatures and limiter denominators). Within about an ulp of the rounded
-// quotient, in 8 operations instead of the correctly rounded division's 11 (its
-// operand scaling and special-case fix-up are not needed here). Otherwise a / b.
+// a / b with FAST (b nonzero and of moderate size: densities, temperatures and
+// limiter denominators, so the correctly rounded division's operand scaling and
+// special-case fix-up are not needed). FP64: the hardware reciprocal of b refined by
+// two Newton steps, the quotient corrected by its residual, within about an ulp of
+// the rounded quotient in 8 operations instead of 11. FP32: the hardware reciprocal
+// and one residual correction (4 operations instead of about 10). Otherwise a / b.
 template <bool FAST, typename S>
 __device__ __forceinline__ S qdiv(S a, S b) {
   if constexpr (FAST && std::is_same<S, double>::value) {
@@ -26,16 +27,30 @@ __device__ __forceinline__ S qdiv(S a, S b) {
     r = fma(r, e, r);
     const double q = a * r;
     return fma(fma(-b, q, a), r, q);
+  } else if constexpr (FAST) {
+    // FP32: the hardware reciprocal (about an ulp) and one residual correction
+    const float r = __builtin_amdgcn_rcpf(b);
+    const float q = a * r;
+    return fmaf(fmaf(-b, q, a), r, q);
   } else {
     return a / b;
   }
+}
+// sqrt(x) for FAST FP32: the hardware square root (about an ulp) instead of the
+// correctly rounded sequence; otherwise sqrt(x).
+template <bool FAST, typename S>
+__device__ __forceinline__ S qsqrt(S x) {
+  if constexpr (FAST && std::is_same<S, float>::value)
+    return __builtin_amdgcn_sqrtf(x);
+  else
+    return sqrt(x);
 }
 // Sutherland's law (Sec. 2.1), theta^{3/2} as theta*sqrt(theta).
 template <typename S, bool FAST = false>
 __device__ __forceinline__ S mu_of(const GridK &g, S th) {
   if (g.visc == MU_CONSTANT) return S(g.mu_inf);
   S sut = S(g.S);
-  return qdiv<FAST>(S(g.mu_inf) * th * sqrt(th) * (S(1) + sut), th + sut);
+  return qdiv<FAST>(S(g.mu_inf) * th * qsqrt<FAST>(th) * (S(1) + sut), th + sut);
 }
 // van Leer limited face value from the upwind (C), downwind (D) and far-upwind
 // (U) cell values: phi_C + (1/2) psi(r) (phi_D - phi_C), written without r.
@@ -68,7 +83,7 @@ __device__ __forceinline__ void prim_from(const GridK &g, const Resolved &r, con
 }
 
 // Primitive variables at a (possibly ghost) cell.
-template <int DIM, typename S>
+template <int DIM, typename S, bool FAST = false>
 __device__ __forceinline__ void load_prim(const GridK &g, const StateV<S> &st, int i, int j, int k,
                                           S &rho, S *u, S &th, S &p) {
   Resolved r = resolve<DIM>(g, i, j, k);
@@ -77,7 +92,7 @@ __device__ __forceinline__ void load_prim(const GridK &g, const StateV<S> &st, i
 #pragma unroll
   for (int q = 0; q < DIM; ++q) cons[1 + q] = st.mom[q][r.c];
   cons[DIM + 1] = st.E[r.c];
-  prim_from<DIM>(g, r, cons, rho, u, th, p);
+  prim_from<DIM, S, FAST>(g, r, cons, rho, u, th, p);
 }
 
 template <int DIM, typename S>
@@ -237,13 +252,13 @@ __device__ __forceinline__ void pred_setup_out_vals(const GridK &g, const PredOu
   po.x[c] = x0;
 }
 
-template <typename S>
+template <typename S, bool FAST = false>
 __device__ __forceinline__ void pred_setup_out(const GridK &g, const PredOut<S> &po, int64_t c,
                                                S rho_s, S E_s, S E) {
   const S Ep = (po.x && po.E_prev) ? po.E_prev[c] : S(0);
   const S E2 = (po.x && po.E_prev && po.E_prev2) ? po.E_prev2[c] : S(0);
   const S E3 = (po.x && po.E_prev && po.E_prev2 && po.E_prev3) ? po.E_prev3[c] : S(0);
-  pred_setup_out_vals(g, po, c, rho_s, E_s, E, Ep, E2, E3);
+  pred_setup_out_vals<S, FAST>(g, po, c, rho_s, E_s, E, Ep, E2, E3);
 }
 
 // Predictor (f = q = 0): explicit update of mass, momentum and internal energy.
@@ -390,25 +405,36 @@ struct PredLds {
   // first plane has ring offset zoff sits in slot (c + 2 + zoff) mod SZ, so that the
   // next tile up a column finds the planes it shares with this one in place
   static constexpr bool RING = DIM == 3 && (SZ & (SZ - 1)) == 0;
-  // PF (3D FP64, whose occupancy the LDS bounds at two blocks per CU whatever the
-  // registers): a tile's global reads are all issued at its start -- the face fluxes
-  // and the outputs' inputs into registers, the halo points in rounds of PCH per
-  // thread -- instead of where they are used (the other forms keep their occupancy)
-  static constexpr bool PF = PL;
-  static_assert(!PF || (TX * TY * TZ == kThreads && TY % 4 == 0),
-                "the PF mappings take one cell per thread and rows in groups of four");
+  // Where the global reads of a tile are issued. PFO (3D): the face fluxes and the
+  // outputs' inputs are read into registers at the tile's start, so that their loads
+  // overlap those of the halo, instead of where they are used. PFH (3D FP64, whose
+  // occupancy the LDS bounds at two blocks per CU whatever the registers): the halo
+  // points are loaded in rounds of PCH per thread, each round's loads issued
+  // together.
+  static constexpr bool PFO = DIM == 3;
+  static constexpr bool PFH = PL;
+  // MAP (3D): one cell per thread, and the faces a thread forms are those of face_of
+  // (no divisions by the face counts)
+  static constexpr bool MAP = DIM == 3;
+  // RP: the row order of cell_of below (3D FP64)
+  static constexpr bool RP = PFH;
+  // FQ (3D): quotients and square roots through qdiv / qsqrt with FAST
+  static constexpr bool FQ = DIM == 3;
+  static_assert(!(PFO || MAP) || TX * TY * TZ == kThreads, "one cell per thread");
+  static_assert(!RP || TY % 4 == 0, "rows in groups of four");
+  static_assert(!PFO || MAP, "the prefetched faces are those of face_of");
   // halo points a thread loads per round (their loads issued together): the new
   // planes of a tile up a column (3D), the tile with its halo (2D); faces per thread
   // and direction
   static constexpr int NEWP = SX * SY * (DIM == 3 ? (RING ? TZ : SZ) : 1);
   static constexpr int PCH = (NEWP + kThreads - 1) / kThreads;
   static constexpr int FPT = (NFMAX + kThreads - 1) / kThreads;
-  // Local cell lc of the tile: x fastest. With PF (TX 8, row pitch SX 12 values) the
+  // Local cell lc of the tile: x fastest. With RP (TX 8, row pitch SX 12 values) the
   // rows of each group of four are taken in the order 0 2 1 3, so that the two 8-lane
   // rows of a 16-lane group of a wave are 24 doubles apart in LDS and fall on disjoint
   // banks (rows 12 doubles apart share a quarter of theirs).
   __device__ static int row_perm(int r) {
-    return PF ? (r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1) : r;
+    return RP ? (r & ~3) | ((r & 1) << 1) | ((r >> 1) & 1) : r;
   }
   __device__ static void cell_of(int lc, int &ci, int &cj, int &ck) {
     ci = lc % TX;
@@ -421,7 +447,7 @@ struct PredLds {
   __device__ static int fslot(int fi, int fj, int fk, int FX, int FY) {
     return fi + FX * (row_perm(fj) + FY * fk);
   }
-  // With PF, the face of direction d that thread t forms for part m: m = 0 the low face
+  // With MAP, the face of direction d that thread t forms for part m: m = 0 the low face
   // of its own cell (the cells' order above), m = 1 a face of the tile's far plane (the
   // threads below that plane's count); false when there is none.
   __device__ static bool face_of(int d, int m, int t, int &fi, int &fj, int &fk) {
@@ -566,7 +592,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     S fpre[DIM][T::FPT];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      if (!T::PF) break;
+      if (!T::PFO) break;
 #pragma unroll
       for (int m = 0; m < T::FPT; ++m) {
         fpre[d][m] = S(0);
@@ -583,7 +609,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     S opre[CPT][DIM + 6];
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
-      if (!T::PF) break;
+      if (!T::PFO) break;
       int ci, cj, ck;
       T::cell_of(threadIdx.x + kThreads * m, ci, cj, ck);
       const int i = x0 + ci, j = y0 + cj, k = z0 + ck;
@@ -614,7 +640,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     const bool cont = T::RING && t > t0 && z0 != 0;
     const int cfirst = cont ? 2 : -2, nplanes = cont ? T::TZ : T::SZ;
     const int npts = T::SX * T::SY * nplanes;
-    for (int p = threadIdx.x; !T::PF && p < npts; p += kThreads) {
+    for (int p = threadIdx.x; !T::PFH && p < npts; p += kThreads) {
       const int li = p % T::SX, lj = (p / T::SX) % T::SY, lc = cfirst + p / (T::SX * T::SY);
       const int gi = x0 - 2 + li, gj = y0 - 2 + lj, gk = (DIM == 3) ? z0 + lc : 0;
       bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
@@ -622,15 +648,15 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       if (!ok) continue;
       const int lp = T::pt(li - 2, lj - 2, lc, zoff);
       S r, u[3], th, pp;
-      load_prim<DIM>(g, st, gi, gj, gk, r, u, th, pp);
+      load_prim<DIM, S, T::FQ>(g, st, gi, gj, gk, r, u, th, pp);
       lv[lp] = r;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + lp] = u[q];
       lv[(DIM + 1) * NP + lp] = th;
-      lv[(DIM + 2) * NP + lp] = mu_of(g, th);
+      lv[(DIM + 2) * NP + lp] = mu_of<S, T::FQ>(g, th);
       if (T::PL) lv[(DIM + 3) * NP + lp] = pp;
     }
-    for (int base = 0; T::PF && base < npts; base += T::PCH * kThreads) {
+    for (int base = 0; T::PFH && base < npts; base += T::PCH * kThreads) {
       Resolved rr[T::PCH];
       S cons[T::PCH][DIM + 2];
       int lp[T::PCH];
@@ -658,13 +684,13 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
       for (int m = 0; m < T::PCH; ++m) {
         if (!okp[m]) continue;
         S r, u[3], th, pp;
-        prim_from<DIM, S, T::PF>(g, rr[m], cons[m], r, u, th, pp);
+        prim_from<DIM, S, T::FQ>(g, rr[m], cons[m], r, u, th, pp);
         const int q0 = lp[m];
         lv[q0] = r;
 #pragma unroll
         for (int q = 0; q < DIM; ++q) lv[(1 + q) * NP + q0] = u[q];
         lv[(DIM + 1) * NP + q0] = th;
-        lv[(DIM + 2) * NP + q0] = mu_of<S, T::PF>(g, th);
+        lv[(DIM + 2) * NP + q0] = mu_of<S, T::FQ>(g, th);
         if (T::PL) lv[(DIM + 3) * NP + q0] = pp;
       }
     }
@@ -732,7 +758,7 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
 #pragma unroll
       for (int m = 0; m < T::FPT; ++m) {
         int f, fi, fj, fk;
-        if (T::PF) {
+        if (T::MAP) {
           if (!T::face_of(d, m, threadIdx.x, fi, fj, fk)) continue;
           f = T::fslot(fi, fj, fk, FX, FY);
         } else {
@@ -748,9 +774,9 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
 #pragma unroll
         for (int e = 0; e < DIM; ++e) ok = ok && (gc[e] < g.n[e] + (e == d ? 1 : 0));
         if (!ok) continue;
-        const S F = T::PF ? fpre[d][m] : st.F[d][fidx(g, d, gi, gj, gk)];
+        const S F = T::PFO ? fpre[d][m] : st.F[d][fidx(g, d, gi, gj, gk)];
         S uf, fm[3], fe;
-        face_flux_lds<DIM, S, CONV, T::PF>(g, lv, zoff, d, fi, fj, fk, F, uf, fm, fe);
+        face_flux_lds<DIM, S, CONV, T::FQ>(g, lv, zoff, d, fi, fj, fk, F, uf, fm, fe);
         lf[f] = F;
         lf[NFM + f] = uf;
 #pragma unroll
@@ -779,23 +805,23 @@ __global__ __launch_bounds__(kThreads) void k_predictor_lds(GridK g, StateV<S> s
     for (int m = 0; m < CPT; ++m) {
       if (!cv_ok[m]) continue;
       const int64_t c = cidx(g, x0 + cl[m][0], y0 + cl[m][1], z0 + cl[m][2]);
-      const S E = T::PF ? opre[m][0] : st.E[c];
-      const S rs = (T::PF ? opre[m][1] : po.rho_b[c]) - dt * acc[m][0];
+      const S E = T::PFO ? opre[m][0] : st.E[c];
+      const S rs = (T::PFO ? opre[m][1] : po.rho_b[c]) - dt * acc[m][0];
       rho_s[c] = rs;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) {
-        const S mhq = (T::PF ? opre[m][2 + q] : po.mom_b[q][c]) + acc[m][1 + q];
+        const S mhq = (T::PFO ? opre[m][2 + q] : po.mom_b[q][c]) + acc[m][1 + q];
         ms[q][c] = mhq + gpr[m][q];
         po.mh[q][c] = mhq;
       }
-      const S es = (T::PF ? opre[m][DIM + 2] : po.E_b[c]) + acc[m][DIM + 1] -
+      const S es = (T::PFO ? opre[m][DIM + 2] : po.E_b[c]) + acc[m][DIM + 1] -
                    dt * (gm1 * E) * acc[m][DIM + 2];
       E_s[c] = es;
-      if (T::PF)
-        pred_setup_out_vals<S, T::PF>(g, po, c, rs, es, E, opre[m][DIM + 3], opre[m][DIM + 4],
+      if (T::PFO)
+        pred_setup_out_vals<S, T::FQ>(g, po, c, rs, es, E, opre[m][DIM + 3], opre[m][DIM + 4],
                                       opre[m][DIM + 5]);
       else
-        pred_setup_out(g, po, c, rs, es, E);
+        pred_setup_out<S, T::FQ>(g, po, c, rs, es, E);
     }
   }
 }

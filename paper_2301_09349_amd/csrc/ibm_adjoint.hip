@@ -607,14 +607,13 @@ __global__ void k_adj_faces(GridK g, int d, StateV<S> st, const double *pp,
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
       const double uU = pp[(1 + q) * Np + iU];
-      cu[q] = pos ? vanleer_d(uP[q], uQ[q], uU, dC, dD, wUu[q])
-                  : vanleer_d(uQ[q], uP[q], uU, dC, dD, wUu[q]);
+      // upwind and downwind operands chosen first: one limiter per value
+      cu[q] = vanleer_d(pos ? uP[q] : uQ[q], pos ? uQ[q] : uP[q], uU, dC, dD, wUu[q]);
       wPu[q] = pos ? dC : dD;
       wQu[q] = pos ? dD : dC;
     }
     const double thU = pp[(DIM + 1) * Np + iU];
-    ce = pos ? vanleer_d(cv * thP, cv * thQ, cv * thU, dC, dD, wUe)
-             : vanleer_d(cv * thQ, cv * thP, cv * thU, dC, dD, wUe);
+    ce = vanleer_d(cv * (pos ? thP : thQ), cv * (pos ? thQ : thP), cv * thU, dC, dD, wUe);
     wPe = pos ? dC : dD;
     wQe = pos ? dD : dC;
   }

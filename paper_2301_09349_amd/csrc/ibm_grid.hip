@@ -177,10 +177,12 @@ __device__ __forceinline__ void face_flux(const GridK &g, const StateV<S> &st, i
     U[d] += pos ? -1 : 1;
     S uU[3], thU;
     load_u_th<DIM>(g, st, U[0], U[1], U[2], uU, thU);
+    // the upwind (C) and downwind (D) cells are P and Q for F >= 0, else Q and P:
+    // the operands are chosen first, so that one limiter is evaluated per value
 #pragma unroll
     for (int q = 0; q < DIM; ++q)
-      cu[q] = pos ? vanleer(uP[q], uQ[q], uU[q]) : vanleer(uQ[q], uP[q], uU[q]);
-    ce = pos ? vanleer(cv * thP, cv * thQ, cv * thU) : vanleer(cv * thQ, cv * thP, cv * thU);
+      cu[q] = vanleer(pos ? uP[q] : uQ[q], pos ? uQ[q] : uP[q], uU[q]);
+    ce = vanleer(cv * (pos ? thP : thQ), cv * (pos ? thQ : thP), cv * thU);
   }
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {
@@ -538,13 +540,13 @@ __device__ __forceinline__ void face_flux_lds(const GridK &g, const S *lv, int z
     U[d] += pos ? -1 : 1;
     const int iU = T::pt(U[0], U[1], U[2], zoff);
     const S thU = lv[(DIM + 1) * NP + iU];
+    // upwind and downwind operands chosen first: one limiter per value
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
       const S uU = lv[(1 + q) * NP + iU];
-      cu[q] = pos ? vanleer<S, FAST>(uP[q], uQ[q], uU) : vanleer<S, FAST>(uQ[q], uP[q], uU);
+      cu[q] = vanleer<S, FAST>(pos ? uP[q] : uQ[q], pos ? uQ[q] : uP[q], uU);
     }
-    ce = pos ? vanleer<S, FAST>(cv * thP, cv * thQ, cv * thU)
-             : vanleer<S, FAST>(cv * thQ, cv * thP, cv * thU);
+    ce = vanleer<S, FAST>(cv * (pos ? thP : thQ), cv * (pos ? thQ : thP), cv * thU);
   }
 #pragma unroll
   for (int q = 0; q < DIM; ++q) {

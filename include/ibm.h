@@ -235,10 +235,13 @@ ibm_status ibm_set_markers(ibm_ctx *ctx, int32_t n, const double *X, const doubl
  * that law added to its U_d. Step n -> n+1 uses t = (n+1) dt; the markers are
  * re-selected, re-sorted and eps re-solved on the device every step, each solve
  * starting from the candidates' eps of ibm_set_markers (so the markers at a time do
- * not depend on the steps before). Within an ibm_step call, the next step's markers
- * are set up on a second stream of the context while the current step's pressure
- * solve runs (a context on a caller's workspace; IBM_REBUILD=inline in the
- * environment at creation keeps them on the context's stream).
+ * not depend on the steps before). Within an ibm_step call, later steps' markers
+ * are set up ahead on two more streams of the context, into two marker sets of the
+ * workspace, while the current step runs: the next step's into the set it does not
+ * use, the step after that's into its own set once its marker kernels are done, so
+ * that two set-ups overlap each other and the steps (a context on a caller's
+ * workspace; IBM_REBUILD=inline in the environment at creation keeps them on the
+ * context's stream, one per step).
  * axis < 0 switches motion off. */
 ibm_status ibm_set_motion(ibm_ctx *ctx, int32_t axis, double amplitude, double frequency);
 
@@ -349,9 +352,9 @@ ibm_status ibm_shape_gradient(ibm_ctx *ctx, double *X_bar);
  * iterations that did work, so total / count is the time per iteration, with the
  * launch that detects convergence included in the total), 4 implicit diffusion
  * (face viscosities and the dim + 1 solves, host waits between them included),
- * 5 correction, 6 a moving body's marker set-up for the next step on the context's
- * second stream (it overlaps the current step's pressure solve; class 1 then holds
- * the set-up only where it is on the context's stream: the first step of a call).
+ * 5 correction, 6 a moving body's marker set-up for a later step on one of the
+ * context's two further streams (it overlaps the steps; class 1 then holds the
+ * set-up only where it is on the context's stream: the first step of a call).
  * The events themselves slow a step down; time throughput with timing off.
  * enable != 0 clears the totals and starts timing; 0 stops it. */
 enum { IBM_PROF_PREDICTOR = 0, IBM_PROF_MARKERS = 1, IBM_PROF_SETUP = 2, IBM_PROF_CG = 3,

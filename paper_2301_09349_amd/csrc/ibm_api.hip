@@ -119,15 +119,21 @@ struct ibm_ctx {
   // device whose static scratch array holds this context's buffers
   // (ibm_create_grid_noalloc), -1 for a caller's workspace
   int scratch_dev = -1;
-  // a moving body's markers for the next step are set up on a second stream (`side`)
-  // while the current step's pressure solve runs: after the last marker kernel of a
-  // step (event ev_used) the side stream rebuilds them for the next step's time, and
-  // the next step's marker kernel waits for ev_built. Contexts on a caller's
-  // workspace only (and not with IBM_REBUILD=inline); created at the first moving step.
+  // A moving body's markers are set up ahead of the steps that use them, on side
+  // streams, into the two marker sets (Bufs and Bufs::alt): a step reads the set in
+  // Bufs, while the set-ups for the next step (in the other set) and for the step
+  // after it (in this step's set, once its last marker kernel is done: event
+  // ev_used) run; a step's first marker kernel waits for its set's ev_built. Set k
+  // has its own side stream, so the two set-ups in flight overlap. Only within one
+  // call: the first step of a call sets its markers up in place. Not with
+  // IBM_REBUILD=inline or on the static scratch array; created at the first moving
+  // step.
   bool side_ok = true;
-  hipStream_t side = nullptr;
-  hipEvent_t ev_used = nullptr, ev_built = nullptr;
-  bool ahead = false;  // a rebuild is queued on `side` that the main stream has not joined
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_used[2] = {nullptr, nullptr}, ev_built[2] = {nullptr, nullptr};
+  int aset = 0;                     // the set in Bufs (the other is in Bufs::alt)
+  int64_t set_step[2] = {-1, -1};  // the step whose markers set k holds or will hold
+  bool pending[2] = {false, false};  // a set-up queued into set k not yet waited for
   // adjoint steps accumulate the marker-position cotangents (between a NULL call of
   // ibm_shape_gradient and the call that reads them)
   bool shape_acc = false;
@@ -135,12 +141,14 @@ struct ibm_ctx {
   CgScal cgh;
   Prof prof;
   ~ibm_ctx() {
-    if (side) {
-      (void)hipStreamSynchronize(side);
-      (void)hipStreamDestroy(side);
+    for (int k = 0; k < 2; ++k) {
+      if (side[k]) {
+        (void)hipStreamSynchronize(side[k]);
+        (void)hipStreamDestroy(side[k]);
+      }
+      if (ev_used[k]) (void)hipEventDestroy(ev_used[k]);
+      if (ev_built[k]) (void)hipEventDestroy(ev_built[k]);
     }
-    if (ev_used) (void)hipEventDestroy(ev_used);
-    if (ev_built) (void)hipEventDestroy(ev_built);
     if (B.progress) (void)hipHostFree(B.progress);
   }
 };
@@ -389,32 +397,39 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
   npairs_pad = next_pow2((int64_t)nc * nslot);
   B.cX0 = C.take<double>(3 * nc);
   B.cUd0 = C.take<double>(3 * nc);
-  B.cXc = C.take<double>(3 * nc);
-  B.cUdc = C.take<double>(3 * nc);
   B.cTw = C.take<double>(nc);
   B.cdA = C.take<double>(nc);
   B.ceps = C.take<double>(nc);
-  B.ckey = C.take<int64_t>(nc);
-  B.cd2 = C.take<double>(nc);
-  B.ckeep = C.take<int>(nc);
-  B.mcount = C.take<int>(8);
-  B.ids = C.take<int>(nc);
-  B.X = C.take<double>(3 * nc);
-  B.Ud = C.take<double>(3 * nc);
-  B.Tw = C.take<double>(nc);
-  B.dA = C.take<double>(nc);
-  B.eps = C.take<double>(nc);
-  B.sidx = C.take<int>(9 * nc);
-  B.sw1 = C.take<double>(9 * nc);
-  B.pcell = C.take<int64_t>(27 * nc);
-  B.pw = C.take<double>(27 * nc);
-  B.keys = C.take<uint64_t>((size_t)npairs_pad);
-  B.keys_in = C.take<uint64_t>((size_t)npairs_pad);
-  B.seg = C.take<int>(27 * nc + 1);
-  B.ell_col = C.take<int>((size_t)ibmk::kMaxNbr * nc);
-  B.ell_val = C.take<double>((size_t)ibmk::kMaxNbr * nc);
-  B.ell_cnt = C.take<int>(nc);
-  for (int v = 0; v < 4; ++v) B.ev[v] = C.take<double>(nc);
+  // the two marker sets
+  auto carve_set = [&]() {
+    ibmk::MarkerSet m;
+    m.cXc = C.take<double>(3 * nc);
+    m.cUdc = C.take<double>(3 * nc);
+    m.ckey = C.take<int64_t>(nc);
+    m.cd2 = C.take<double>(nc);
+    m.ckeep = C.take<int>(nc);
+    m.mcount = C.take<int>(8);
+    m.ids = C.take<int>(nc);
+    m.X = C.take<double>(3 * nc);
+    m.Ud = C.take<double>(3 * nc);
+    m.Tw = C.take<double>(nc);
+    m.dA = C.take<double>(nc);
+    m.eps = C.take<double>(nc);
+    m.sidx = C.take<int>(9 * nc);
+    m.sw1 = C.take<double>(9 * nc);
+    m.pcell = C.take<int64_t>(27 * nc);
+    m.pw = C.take<double>(27 * nc);
+    m.keys = C.take<uint64_t>((size_t)npairs_pad);
+    m.keys_in = C.take<uint64_t>((size_t)npairs_pad);
+    m.seg = C.take<int>(27 * nc + 1);
+    m.ell_col = C.take<int>((size_t)ibmk::kMaxNbr * nc);
+    m.ell_val = C.take<double>((size_t)ibmk::kMaxNbr * nc);
+    m.ell_cnt = C.take<int>(nc);
+    for (int v = 0; v < 4; ++v) m.ev[v] = C.take<double>(nc);
+    return m;
+  };
+  ibmk::put_marker_set(B, carve_set());
+  B.alt = carve_set();
   B.mk = C.take<double>(9 * nc);
   B.mforce = C.take<double>(3 * nc);
   B.mheat = C.take<double>(nc);
@@ -462,9 +477,9 @@ ibm_status sync_read(ibm_ctx *ctx, void *dst, const void *src, size_t bytes) {
 
 // marker positions at time t, supports, sort, eps, on `stream` (NULL: the context's).
 // Only the set-up of a new body saves eps per candidate (the start of every later
-// solve), so that a rebuild depends on t alone and may run ahead on the side stream.
+// solve), so that a rebuild depends on t alone and may run ahead on a side stream.
 ibm_status rebuild_markers(ibm_ctx *ctx, double t, bool save_eps = false,
-                           hipStream_t stream = nullptr) {
+                           hipStream_t stream = nullptr, const Bufs *into = nullptr) {
   double off = 0.0, vel = 0.0;
   int axis = -1;
   if (ctx->motion_axis >= 0) {
@@ -474,7 +489,8 @@ ibm_status rebuild_markers(ibm_ctx *ctx, double t, bool save_eps = false,
   }
   Launch L = ctx->L;
   if (stream) L.st = stream;
-  ibmk::run_rebuild_markers(L, ctx->B, ctx->nc, off, vel, axis, ctx->dedupe, save_eps);
+  ibmk::run_rebuild_markers(L, into ? *into : ctx->B, ctx->nc, off, vel, axis, ctx->dedupe,
+                            save_eps);
   HIPCHECK(ctx, hipGetLastError());
   return IBM_OK;
 }
@@ -699,7 +715,7 @@ ibm_status create_ctx(const ibm_grid_desc *desc, void *dev_workspace, size_t byt
                              : std::strcmp(cgs, "linear") == 0 ? 1
                              : std::strcmp(cgs, "quadratic") == 0 ? 2 : 3;
     if (ctx->L.pred_lds && need > 65536) ibmk::enable_predictor_lds(desc->dim, desc->precision);
-    // a moving body's markers set up ahead on a second stream; IBM_REBUILD=inline
+    // a moving body's markers set up ahead on side streams; IBM_REBUILD=inline
     // keeps them on the context's stream (a context without its own allocations
     // always does)
     const char *rb = std::getenv("IBM_REBUILD");
@@ -1037,50 +1053,91 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
       P.pending.push_back({IBM_PROF_CG, it0, count, a, b});
     }
   };
-  // A moving body: each step's markers are set up at its start on the main stream,
-  // or, when the step before queued them on the side stream, the step's marker kernel
-  // waits for them (ahead_join). After a step's last marker kernel, the next step's
-  // markers (time (step + 2) dt) are queued on the side stream, within the call.
+  // A moving body: the first step of the call sets its markers up on the main
+  // stream and queues the next step's into the other set; every step queues, after
+  // its last marker kernel, the set-up of the step two ahead into its own set (see
+  // ibm_ctx::side), within the call.
   const bool moving = ctx->nc > 0 && ctx->motion_axis >= 0;
-  if (moving && ctx->side_ok && !ctx->side) {
-    HIPCHECK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-    HIPCHECK(ctx, hipEventCreateWithFlags(&ctx->ev_used, hipEventDisableTiming));
-    HIPCHECK(ctx, hipEventCreateWithFlags(&ctx->ev_built, hipEventDisableTiming));
+  if (moving && ctx->side_ok && !ctx->side[0]) {
+    for (int k = 0; k < 2; ++k) {
+      HIPCHECK(ctx, hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking));
+      HIPCHECK(ctx, hipEventCreateWithFlags(&ctx->ev_used[k], hipEventDisableTiming));
+      HIPCHECK(ctx, hipEventCreateWithFlags(&ctx->ev_built[k], hipEventDisableTiming));
+    }
   }
-  const bool use_side = moving && ctx->side != nullptr;
-  auto ahead_join = [&]() -> hipError_t {
-    if (!ctx->ahead) return hipSuccess;
-    ctx->ahead = false;
-    return hipStreamWaitEvent(st, ctx->ev_built, 0);
+  const bool use_side = moving && ctx->side[0] != nullptr;
+  ctx->set_step[0] = ctx->set_step[1] = -1;
+  // the main stream waits for the set-ups queued and not yet waited for
+  auto join_all = [&]() -> hipError_t {
+    for (int k = 0; k < 2; ++k) {
+      if (!ctx->pending[k]) continue;
+      ctx->pending[k] = false;
+      hipError_t e = hipStreamWaitEvent(st, ctx->ev_built[k], 0);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
-  // an early return still leaves the main stream behind the side stream's work
+  // an early return still leaves the main stream behind the side streams' work
   struct AheadGuard {
     ibm_ctx *c;
     ~AheadGuard() {
-      if (c->ahead) {
-        c->ahead = false;
-        (void)hipStreamWaitEvent(c->L.st, c->ev_built, 0);
+      for (int k = 0; k < 2; ++k) {
+        if (!c->pending[k]) continue;
+        c->pending[k] = false;
+        (void)hipStreamWaitEvent(c->L.st, c->ev_built[k], 0);
       }
     }
   } ahead_guard{ctx};
-  auto rebuild_ahead = [&](int64_t next_step) -> ibm_status {
-    HIPCHECK(ctx, hipEventRecord(ctx->ev_used, st));
-    HIPCHECK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_used, 0));
-    ibm_status ms = IBM_OK;
-    hipEvent_t a = P.on ? P.mark(ctx->side) : nullptr;
-    ms = rebuild_markers(ctx, double(next_step + 1) * L.g.dt, false, ctx->side);
-    if (P.on) P.pending.push_back({IBM_PROF_REBUILD, 0, 1, a, P.mark(ctx->side)});
+  // queues the set-up of `step`'s markers (time (step + 1) dt) into set k on side[k],
+  // behind the main stream's work so far (its last use of set k)
+  auto queue_setup = [&](int64_t step, int k) -> ibm_status {
+    HIPCHECK(ctx, hipEventRecord(ctx->ev_used[k], st));
+    HIPCHECK(ctx, hipStreamWaitEvent(ctx->side[k], ctx->ev_used[k], 0));
+    Bufs Bk = B;
+    if (k != ctx->aset) ibmk::put_marker_set(Bk, B.alt);
+    ctx->set_step[k] = -1;
+    hipEvent_t a = P.on ? P.mark(ctx->side[k]) : nullptr;
+    ibm_status ms = rebuild_markers(ctx, double(step + 1) * L.g.dt, false, ctx->side[k], &Bk);
+    if (P.on) P.pending.push_back({IBM_PROF_REBUILD, 0, 1, a, P.mark(ctx->side[k])});
     if (ms) return ms;
-    HIPCHECK(ctx, hipEventRecord(ctx->ev_built, ctx->side));
-    ctx->ahead = true;
+    HIPCHECK(ctx, hipEventRecord(ctx->ev_built[k], ctx->side[k]));
+    ctx->pending[k] = true;
+    ctx->set_step[k] = step;
     return IBM_OK;
   };
-  // the markers of the step starting now: queued by the step before, or set up here
-  auto step_markers = [&]() -> ibm_status {
-    if (!moving || ctx->ahead) return IBM_OK;
+  // the markers of the step starting now (s-th of the call) into Bufs: the set
+  // queued for it, or set up here (then the next step's are queued)
+  auto step_markers = [&](int s) -> ibm_status {
+    if (!moving) return IBM_OK;
+    const int64_t step = ctx->step;
+    const int k = ctx->set_step[0] == step ? 0 : ctx->set_step[1] == step ? 1 : -1;
+    if (k >= 0) {
+      if (k != ctx->aset) {
+        const ibmk::MarkerSet held = ibmk::marker_set_of(B);
+        ibmk::put_marker_set(B, B.alt);
+        B.alt = held;
+        ctx->aset = k;
+      }
+      return IBM_OK;
+    }
     ibm_status ms = IBM_OK;
-    timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(ctx->step + 1) * L.g.dt); });
-    return ms;
+    timed(IBM_PROF_MARKERS, 0, [&] { ms = rebuild_markers(ctx, double(step + 1) * L.g.dt); });
+    if (ms) return ms;
+    ctx->set_step[ctx->aset] = step;
+    if (use_side && s + 1 < n_steps) return queue_setup(step + 1, ctx->aset ^ 1);
+    return IBM_OK;
+  };
+  // before the step's first marker kernel: its set is ready
+  auto join_markers = [&]() -> hipError_t {
+    const int k = ctx->aset;
+    if (!ctx->pending[k]) return hipSuccess;
+    ctx->pending[k] = false;
+    return hipStreamWaitEvent(st, ctx->ev_built[k], 0);
+  };
+  // after the step's last marker kernel: the step two ahead into this step's set
+  auto queue_after = [&](int s) -> ibm_status {
+    if (!use_side || s + 2 >= n_steps) return IBM_OK;
+    return queue_setup(ctx->step + 2, ctx->aset);
   };
   // Flags are sticky for the whole call: a step that fails keeps every later step
   // from writing the state, so the state it started from survives.
@@ -1095,16 +1152,16 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     for (int s = 0; s < n_steps; ++s) {
       const int tag = ++ctx->tag;
       {
-        ibm_status ms = step_markers();
+        ibm_status ms = step_markers(s);
         if (ms) return ms;
       }
       timed(IBM_PROF_PREDICTOR, 0, [&] { ibmk::run_density_predictor(L, B, ctx->cur); });
       double *hrow = hist ? hist + 4 * (size_t)s : nullptr;
       if (ctx->nc > 0) {
-        HIPCHECK(ctx, ahead_join());
+        HIPCHECK(ctx, join_markers());
         timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
-        if (use_side && s + 1 < n_steps) {
-          ibm_status ms = rebuild_ahead(ctx->step + 1);
+        {
+          ibm_status ms = queue_after(s);
           if (ms) return ms;
         }
       } else if (hrow) {
@@ -1126,7 +1183,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
   const int passes = std::max(1, ctx->desc.n_outer);
   for (int s = 0; s < (ctx->desc.scheme == IBM_SCHEME_DENSITY ? 0 : n_steps); ++s) {
     {
-      ibm_status ms = step_markers();
+      ibm_status ms = step_markers(s);
       if (ms) return ms;
     }
     if (record) {
@@ -1165,13 +1222,13 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
         }
       }
       if (ctx->nc > 0) {
-        HIPCHECK(ctx, ahead_join());
+        HIPCHECK(ctx, join_markers());
         if (first)
           timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_markers_step(L, B, hrow); });
         else
           timed(IBM_PROF_MARKERS, 0, [&] { ibmk::run_spread(L, B); });
-        if (use_side && pass == passes - 1 && s + 1 < n_steps) {
-          ibm_status ms = rebuild_ahead(ctx->step + 1);
+        if (pass == passes - 1) {
+          ibm_status ms = queue_after(s);
           if (ms) return ms;
         }
       } else if (hrow && first) {
@@ -1236,7 +1293,7 @@ ibm_status ibm_step(ibm_ctx *ctx, int32_t n_steps, uint32_t flags, double *hist,
     }
   }
   if (done > 0) ibmk::run_mass(L, B);
-  HIPCHECK(ctx, ahead_join());  // a step that failed may leave the next one's markers queued
+  HIPCHECK(ctx, join_all());  // a step that failed may leave later steps' markers queued
   HIPCHECK(ctx, hipStreamSynchronize(st));
   int f[8];
   {

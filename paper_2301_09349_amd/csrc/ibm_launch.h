@@ -6,6 +6,28 @@
 
 namespace ibmk {
 
+// The buffers a marker set-up writes: the markers in use at one time and the
+// set-up's own work arrays. A context holds two such sets (one in Bufs, the other in
+// Bufs::alt), so that a moving body's set-up for a later step can run while a step
+// reads the markers of its own.
+struct MarkerSet {
+  double *cXc, *cUdc;
+  int64_t *ckey;
+  double *cd2;
+  int *ckeep;
+  int *mcount, *ids;
+  double *X, *Ud, *Tw, *dA, *eps;
+  int *sidx;
+  double *sw1;
+  int64_t *pcell;
+  double *pw;
+  uint64_t *keys, *keys_in;
+  int *seg, *ell_col;
+  double *ell_val;
+  int *ell_cnt;
+  double *ev[4];
+};
+
 // Device buffers carved from the caller's workspace.
 struct Bufs {
   // conserved state, two copies (ping-pong): rho, mom[3], E, F[3]
@@ -87,7 +109,13 @@ struct Bufs {
   // density-based step: primitives rho, u[3], theta of the state (dprim0) and
   // u**[3], theta** of the intermediate state (dprim1), state type [N] each
   void *dprim0[5], *dprim1[5];
+  // the second marker set (the first is in the fields above)
+  MarkerSet alt;
 };
+
+// The marker set held in the fields of B, and B with the fields set to m.
+MarkerSet marker_set_of(const Bufs &B);
+void put_marker_set(Bufs &B, const MarkerSet &m);
 
 // Kernel view of the diffusion systems' buffers.
 struct DiffSys {

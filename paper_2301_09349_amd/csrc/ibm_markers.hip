@@ -1433,6 +1433,60 @@ static void launch_eps_solve(const Launch &L, const Bufs &B, int nc, const doubl
   }
 }
 
+MarkerSet marker_set_of(const Bufs &B) {
+  MarkerSet m;
+  m.cXc = B.cXc;
+  m.cUdc = B.cUdc;
+  m.ckey = B.ckey;
+  m.cd2 = B.cd2;
+  m.ckeep = B.ckeep;
+  m.mcount = B.mcount;
+  m.ids = B.ids;
+  m.X = B.X;
+  m.Ud = B.Ud;
+  m.Tw = B.Tw;
+  m.dA = B.dA;
+  m.eps = B.eps;
+  m.sidx = B.sidx;
+  m.sw1 = B.sw1;
+  m.pcell = B.pcell;
+  m.pw = B.pw;
+  m.keys = B.keys;
+  m.keys_in = B.keys_in;
+  m.seg = B.seg;
+  m.ell_col = B.ell_col;
+  m.ell_val = B.ell_val;
+  m.ell_cnt = B.ell_cnt;
+  for (int v = 0; v < 4; ++v) m.ev[v] = B.ev[v];
+  return m;
+}
+
+void put_marker_set(Bufs &B, const MarkerSet &m) {
+  B.cXc = m.cXc;
+  B.cUdc = m.cUdc;
+  B.ckey = m.ckey;
+  B.cd2 = m.cd2;
+  B.ckeep = m.ckeep;
+  B.mcount = m.mcount;
+  B.ids = m.ids;
+  B.X = m.X;
+  B.Ud = m.Ud;
+  B.Tw = m.Tw;
+  B.dA = m.dA;
+  B.eps = m.eps;
+  B.sidx = m.sidx;
+  B.sw1 = m.sw1;
+  B.pcell = m.pcell;
+  B.pw = m.pw;
+  B.keys = m.keys;
+  B.keys_in = m.keys_in;
+  B.seg = m.seg;
+  B.ell_col = m.ell_col;
+  B.ell_val = m.ell_val;
+  B.ell_cnt = m.ell_cnt;
+  for (int v = 0; v < 4; ++v) B.ev[v] = m.ev[v];
+}
+
 void run_rebuild_markers(const Launch &L, const Bufs &B, int nc, double off, double vel, int axis,
                          int dedupe, bool save_eps) {
   if (!small_body(L, nc)) {

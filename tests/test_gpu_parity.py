@@ -234,10 +234,11 @@ def test_moving_body_parity(cuda, name, over):
                                   {"scheme": inputs.SCHEME_PRESSURE, "n_outer": 2},
                                   {"scheme": inputs.SCHEME_DENSITY}])
 def test_moving_markers_ahead_and_inline_agree(cuda, monkeypatch, kind):
-    # the next step's markers set up on the context's second stream during the
-    # pressure solve, against the same set-up at each step's start on the context's
-    # stream (IBM_REBUILD=inline): bitwise the same steps, also over two calls, and the
-    # same markers in use and wall fluxes after them
+    # later steps' markers set up ahead on the context's side streams into its two
+    # marker sets, against the same set-up at each step's start on the context's
+    # stream (IBM_REBUILD=inline): bitwise the same steps over calls of 5, 1, 2 and 3
+    # steps (the sets alternate within a call and start afresh in each), and the same
+    # markers in use and wall fluxes after every call
     c = inputs.scaled("osc2", (96, 96), ns=80, **kind)
     runs = {}
     for mode in ("ahead", "inline"):
@@ -246,17 +247,18 @@ def test_moving_markers_ahead_and_inline_agree(cuda, monkeypatch, kind):
         else:
             monkeypatch.delenv("IBM_REBUILD", raising=False)
         g = make_gpu(c)
-        h1, _ = g.step(5)
-        h2, _ = g.step(3)
-        ids, eps = g.markers_in_use()
-        f, h, _ = g.wall_fluxes()
-        runs[mode] = [to_np(x).copy() for x in (h1, h2, ids, eps, f, h)]
+        runs[mode] = []
+        for n in (5, 1, 2, 3):
+            h, _ = g.step(n)
+            ids, eps = g.markers_in_use()
+            f, q, _ = g.wall_fluxes()
+            runs[mode] += [to_np(x).copy() for x in (h, ids, eps, f, q)]
         runs[mode] += [to_np(x).copy() for x in g.get_state()[:3]]
     for a, b in zip(runs["ahead"], runs["inline"]):
         assert np.array_equal(a, b)
     o = make_oracle(c)
-    o.step(8)
-    assert rel_l2(runs["ahead"][3], o.eps()) < 1e-9
+    o.step(11)
+    assert rel_l2(runs["ahead"][-6], o.eps()) < 1e-9
 
 
 @pytest.mark.parametrize("shape,bc", [

@@ -2137,6 +2137,44 @@ struct DTile {
   }
 };
 
+// The points of a DTile<DIM, 2> that the inviscid faces read -- the tile and its
+// two-deep halo, but only where at most one coordinate lies outside the tile (the
+// faces reconstruct along their normal) -- stored in three slabs: A the tile's rows
+// with their x halo ((TX + 4) x TY x TZ), B the y halo of the tile's columns
+// (TX x 4 x TZ), C the z halo (TX x TY x 4, 3D). 768 points in 3D instead of the
+// box's 1152, so that three blocks fit the LDS of a CU.
+template <int DIM>
+struct DCross {
+  using T = DTile<DIM, 2>;
+  static constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ;
+  static constexpr int AX = TX + 4;
+  static constexpr int NA = AX * TY * TZ, NB = TX * 4 * TZ, NC = DIM == 3 ? TX * TY * 4 : 0;
+  static constexpr int NP = NA + NB + NC;
+  // the halo layer (-2, -1, n, n + 1 -> 0..3) of a coordinate outside [0, n)
+  __device__ static int layer(int v, int n) { return v < 0 ? v + 2 : v - n + 2; }
+  __device__ static int a(int i, int j, int k) { return (k * TY + j) * AX + (i + 2); }
+  __device__ static int b(int i, int j, int k) { return NA + (k * 4 + layer(j, TY)) * TX + i; }
+  __device__ static int c(int i, int j, int k) { return NA + NB + (layer(k, TZ) * TY + j) * TX + i; }
+  // local point of slot p (the inverse of a, b and c)
+  __device__ static void point(int p, int &i, int &j, int &k) {
+    if (p < NA) {
+      i = p % AX - 2;
+      j = (p / AX) % TY;
+      k = p / (AX * TY);
+    } else if (p < NA + NB) {
+      const int q = p - NA, l = (q / TX) % 4;
+      i = q % TX;
+      j = l < 2 ? l - 2 : TY + l - 2;
+      k = q / (TX * 4);
+    } else {
+      const int q = p - NA - NB, l = q / (TX * TY);
+      i = q % TX;
+      j = (q / TX) % TY;
+      k = l < 2 ? l - 2 : TZ + l - 2;
+    }
+  }
+};
+
 // Inviscid part: rho^{n+1} = rho^n - dt D(F_rho), (rho u)** = (rho u)^n - dt D(F_m),
 // (rho e_t)** = (rho e_t)^n - dt D(F_e) from the central-upwind fluxes of the
 // state at step n; u** = (rho u)**/rho^{n+1} and theta** = ((rho e_t)**/rho^{n+1}
@@ -2147,21 +2185,18 @@ __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> s
                                                            S *m1, S *m2, DensPrim<S> p1,
                                                            const int *flags) {
   using T = DTile<DIM, 2>;
+  using X = DCross<DIM>;
   constexpr int NV = DIM + 2;  // rho, u[DIM], theta
-  __shared__ S lv[NV * T::NP];
+  __shared__ S lv[NV * X::NP];
   __shared__ S lf[NV * T::NFD];
   if (dens_skip(flags)) return;
   int x0, y0, z0;
   T::origin(g, blockIdx.x, x0, y0, z0);
-  // phase 1: primitives of the tile and its halo (up to two layers outside the box).
-  // The faces reconstruct along their normal only, so the halo's edges and corners
-  // (points outside the tile in two or more directions) are never read: not loaded.
-  for (int p = threadIdx.x; p < T::NP; p += kThreads) {
-    const int li = p % T::SX - 2, lj = (p / T::SX) % T::SY - 2;
-    const int lk = DIM == 3 ? p / (T::SX * T::SY) - 2 : 0;
-    const int outside = (li < 0 || li >= T::TX) + (lj < 0 || lj >= T::TY) +
-                        (DIM == 3 && (lk < 0 || lk >= T::TZ));
-    if (outside >= 2) continue;
+  // phase 1: primitives of the points the faces read (up to two layers outside the
+  // box)
+  for (int p = threadIdx.x; p < X::NP; p += kThreads) {
+    int li, lj, lk;
+    X::point(p, li, lj, lk);
     const int gi = x0 + li, gj = y0 + lj, gk = z0 + lk;
     bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
     if (DIM == 3) ok = ok && gk >= -2 && gk <= g.n[2] + 1;
@@ -2170,8 +2205,8 @@ __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> s
     load_rut<DIM>(g, p0, gi, gj, gk, r, u, th);
     lv[p] = r;
 #pragma unroll
-    for (int q = 0; q < DIM; ++q) lv[(1 + q) * T::NP + p] = u[q];
-    lv[(1 + DIM) * T::NP + p] = th;
+    for (int q = 0; q < DIM; ++q) lv[(1 + q) * X::NP + p] = u[q];
+    lv[(1 + DIM) * X::NP + p] = th;
   }
   __syncthreads();
   const int ci = threadIdx.x % T::TX, cj = (threadIdx.x / T::TX) % T::TY;
@@ -2188,7 +2223,6 @@ __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> s
     const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2);
     for (int f = threadIdx.x; f < FX * FY * FZ; f += kThreads) {
       const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
-      const int fl[3] = {fi, fj, fk};
       const int gf[3] = {x0 + fi, y0 + fj, z0 + fk};
       bool ok = true;
 #pragma unroll
@@ -2197,13 +2231,22 @@ __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> s
       S r[4], u[4][3], th[4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        int c3[3] = {fl[0], fl[1], fl[2]};
-        c3[d] += m - 2;
-        const int lp = T::pt(c3[0], c3[1], c3[2]);
+        // the point m - 2 cells from the face's high cell along d: in slab A, or in
+        // the halo slab of direction d
+        int lp;
+        if (d == 0) {
+          lp = X::a(fi + m - 2, fj, fk);
+        } else if (d == 1) {
+          const int j = fj + m - 2;
+          lp = (j >= 0 && j < T::TY) ? X::a(fi, j, fk) : X::b(fi, j, fk);
+        } else {
+          const int k = fk + m - 2;
+          lp = (k >= 0 && k < T::TZ) ? X::a(fi, fj, k) : X::c(fi, fj, k);
+        }
         r[m] = lv[lp];
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) u[m][q] = lv[(1 + q) * T::NP + lp];
-        th[m] = lv[(1 + DIM) * T::NP + lp];
+        for (int q = 0; q < DIM; ++q) u[m][q] = lv[(1 + q) * X::NP + lp];
+        th[m] = lv[(1 + DIM) * X::NP + lp];
       }
       S fr, fm[3], fe;
       knp_flux<DIM, S>(g, d, r, u, th, fr, fm, fe);
@@ -2212,7 +2255,8 @@ __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> s
       for (int q = 0; q < DIM; ++q) lf[(1 + q) * T::NFD + f] = fm[q];
       lf[(1 + DIM) * T::NFD + f] = fe;
       // the face belongs to this tile unless it is the next tile's first face
-      if (fl[d] < (d == 0 ? T::TX : d == 1 ? T::TY : T::TZ) || gf[d] == g.n[d])
+      if ((d == 0 ? fi : d == 1 ? fj : fk) < (d == 0 ? T::TX : d == 1 ? T::TY : T::TZ) ||
+          gf[d] == g.n[d])
         nxt.F[d][fidx(g, d, gf[0], gf[1], gf[2])] = fr;
     }
     __syncthreads();

@@ -2108,12 +2108,12 @@ __device__ __forceinline__ bool dens_skip(const int *flags) {
   return skip != 0;
 }
 
-// Tiles of the density-based kernels: one cell per thread (256 cells: 32 x 8 in
-// 2D, 8 x 8 x 4 in 3D) and a halo of H cells on every side, corners included, in
-// LDS; each face of the tile is formed once.
-template <int DIM, int H>
+// Tiles of the density-based kernels: one cell per thread (32 x 8 in 2D, 8 x 8 x TZ3
+// in 3D) and a halo of H cells on every side, corners included, in LDS; each face of
+// the tile is formed once.
+template <int DIM, int H, int TZ3 = 4>
 struct DTile {
-  static constexpr int TX = DIM == 2 ? 32 : 8, TY = 8, TZ = DIM == 2 ? 1 : 4;
+  static constexpr int TX = DIM == 2 ? 32 : 8, TY = 8, TZ = DIM == 2 ? 1 : TZ3;
   static constexpr int HZ = DIM == 2 ? 0 : H;
   static constexpr int SX = TX + 2 * H, SY = TY + 2 * H, SZ = TZ + 2 * HZ;
   static constexpr int NP = SX * SY * SZ;
@@ -2141,12 +2141,18 @@ struct DTile {
 // two-deep halo, but only where at most one coordinate lies outside the tile (the
 // faces reconstruct along their normal) -- stored in three slabs: A the tile's rows
 // with their x halo ((TX + 4) x TY x TZ), B the y halo of the tile's columns
-// (TX x 4 x TZ), C the z halo (TX x TY x 4, 3D). 768 points in 3D instead of the
-// box's 1152, so that three blocks fit the LDS of a CU.
+// (TX x 4 x TZ), C the z halo (TX x TY x 4, 3D): 1280 points for an 8 x 8 x 8 tile
+// instead of the box's 1728.
+// the inviscid kernel's 3D tiles are 8 x 8 x 8 (512 threads): fewer halo points per
+// cell than 8 x 8 x 4, and two blocks of eight waves per CU in FP64 (LDS 74 KB)
+#ifndef IBM_DENS_TZ
+#define IBM_DENS_TZ 8
+#endif
 template <int DIM>
 struct DCross {
-  using T = DTile<DIM, 2>;
+  using T = DTile<DIM, 2, IBM_DENS_TZ>;
   static constexpr int TX = T::TX, TY = T::TY, TZ = T::TZ;
+  static constexpr int NT = TX * TY * TZ;  // threads: one per cell
   static constexpr int AX = TX + 4;
   static constexpr int NA = AX * TY * TZ, NB = TX * 4 * TZ, NC = DIM == 3 ? TX * TY * 4 : 0;
   static constexpr int NP = NA + NB + NC;
@@ -2180,21 +2186,22 @@ struct DCross {
 // state at step n; u** = (rho u)**/rho^{n+1} and theta** = ((rho e_t)**/rho^{n+1}
 // - |u**|^2/2)/c_v into p1; the mass flux into the next state's face arrays.
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> st, StateV<S> nxt,
+__global__ __launch_bounds__(DCross<DIM>::NT) void k_dens_inviscid(GridK g, StateV<S> st, StateV<S> nxt,
                                                            DensPrim<S> p0, S *rho1, S *m0,
                                                            S *m1, S *m2, DensPrim<S> p1,
                                                            const int *flags) {
-  using T = DTile<DIM, 2>;
   using X = DCross<DIM>;
+  using T = typename X::T;
   constexpr int NV = DIM + 2;  // rho, u[DIM], theta
-  __shared__ S lv[NV * X::NP];
-  __shared__ S lf[NV * T::NFD];
+  extern __shared__ __align__(16) unsigned char smem[];
+  S *lv = reinterpret_cast<S *>(smem);  // [NV][NP]
+  S *lf = lv + NV * X::NP;              // [NV][NFD]
   if (dens_skip(flags)) return;
   int x0, y0, z0;
   T::origin(g, blockIdx.x, x0, y0, z0);
   // phase 1: primitives of the points the faces read (up to two layers outside the
   // box)
-  for (int p = threadIdx.x; p < X::NP; p += kThreads) {
+  for (int p = threadIdx.x; p < X::NP; p += X::NT) {
     int li, lj, lk;
     X::point(p, li, lj, lk);
     const int gi = x0 + li, gj = y0 + lj, gk = z0 + lk;
@@ -2221,7 +2228,7 @@ __global__ __launch_bounds__(kThreads) void k_dens_inviscid(GridK g, StateV<S> s
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2);
-    for (int f = threadIdx.x; f < FX * FY * FZ; f += kThreads) {
+    for (int f = threadIdx.x; f < FX * FY * FZ; f += X::NT) {
       const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
       const int gf[3] = {x0 + fi, y0 + fj, z0 + fk};
       bool ok = true;
@@ -3606,8 +3613,17 @@ void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
     const unsigned nb = (unsigned)((L.g.N + kThreads - 1) / kThreads);
     hipLaunchKernelGGL((k_dens_prim<DIM, S>), dim3(nb), dim3(kThreads), 0, L.st, L.g, st, p0,
                        (const int *)B.flags);
-    const unsigned nt2 = (unsigned)DTile<DIM, 2>::tiles(L.g), nt1 = (unsigned)DTile<DIM, 1>::tiles(L.g);
-    hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nt2), dim3(kThreads), 0, L.st, L.g, st, nx,
+    using X = DCross<DIM>;
+    const unsigned nt2 = (unsigned)X::T::tiles(L.g), nt1 = (unsigned)DTile<DIM, 1>::tiles(L.g);
+    const size_t shm = sizeof(S) * (size_t)(DIM + 2) * (X::NP + X::T::NFD);
+    if (shm > 65536) {
+      static bool enabled = false;  // once per instance
+      if (!enabled)
+        (void)hipFuncSetAttribute((const void *)k_dens_inviscid<DIM, S>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      enabled = true;
+    }
+    hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nt2), dim3(X::NT), shm, L.st, L.g, st, nx,
                        p0, (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], p1,
                        (const int *)B.flags);
     hipLaunchKernelGGL((k_dens_viscous<DIM, S>), dim3(nt1), dim3(kThreads), 0, L.st, L.g,

@@ -384,7 +384,6 @@ size_t plan(const ibm_grid_desc &d, const GridK &g, int max_markers, int tape_st
     B.dsc = imp ? C.take<ibmk::DiffScal>(1) : nullptr;
     const bool dens = d.scheme == IBM_SCHEME_DENSITY;
     for (int v = 0; v < 5; ++v) {
-      B.dprim0[v] = (dens && (v == 0 || v == 4 || v <= dim)) ? field(N) : nullptr;
       B.dprim1[v] = (dens && (v < dim || v == 3)) ? field(N) : nullptr;
     }
   }

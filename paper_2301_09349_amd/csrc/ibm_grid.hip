@@ -2006,43 +2006,12 @@ __global__ void k_dsys_finish(GridK g, DiffSys D, const S *rho_s, S *ms0, S *ms1
 }
 
 // ------------------------------------------ App. B (density-based variant)
-// Primitive arrays of the density-based step: rho, u[3], theta of the state at
-// step n (p0), and u**, theta** of the intermediate state (p1); formed once per
-// cell so that the face stencils only load them.
+// u**, theta** of the density-based step's intermediate state, formed once per cell
+// so that the viscous stencils only load them.
 template <typename S>
 struct DensPrim {
-  S *v[5];  // p0: rho, u0, u1, u2, theta; p1: u0, u1, u2, theta (the last unused)
+  S *v[5];  // u0, u1, u2, theta (the last unused)
 };
-
-template <int DIM, typename S>
-__global__ void k_dens_prim(GridK g, StateV<S> st, DensPrim<S> p0, const int *flags) {
-  if (flags[FLAG_NONFINITE] || flags[FLAG_SUPPORT] || flags[FLAG_EPS] || flags[FLAG_GRAM]) return;
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.N) return;
-  const S r = st.rho[c];
-  const S inv = S(1) / r;
-  p0.v[0][c] = r;
-#pragma unroll
-  for (int q = 0; q < DIM; ++q) p0.v[1 + q][c] = st.mom[q][c] * inv;
-  p0.v[4][c] = st.E[c] * inv * S(g.inv_cv);
-}
-
-// Density, velocity and temperature at a (possibly ghost) cell, from p0.
-template <int DIM, typename S>
-__device__ __forceinline__ void load_rut(const GridK &g, const DensPrim<S> &p0, int i, int j,
-                                         int k, S &r, S *u, S &th) {
-  Resolved rs = resolve<DIM>(g, i, j, k);
-  r = p0.v[0][rs.c];
-#pragma unroll
-  for (int q = 0; q < DIM; ++q) u[q] = p0.v[1 + q][rs.c];
-  th = p0.v[4][rs.c];
-  if (any_side<DIM, S>(rs)) {
-    r = ghosted<DIM>(g, rs, V_RHO, r);
-#pragma unroll
-    for (int q = 0; q < DIM; ++q) u[q] = ghosted<DIM>(g, rs, V_U0 + q, u[q]);
-    th = ghosted<DIM>(g, rs, V_TH, th);
-  }
-}
 
 // Central-upwind flux (Kurganov, Noelle, Petrova; the scheme of rhoCentralFoam)
 // of rho, rho u and rho e_t through a face of direction d, from rho, u, theta at
@@ -2187,7 +2156,7 @@ struct DCross {
 // - |u**|^2/2)/c_v into p1; the mass flux into the next state's face arrays.
 template <int DIM, typename S>
 __global__ __launch_bounds__(DCross<DIM>::NT) void k_dens_inviscid(GridK g, StateV<S> st, StateV<S> nxt,
-                                                           DensPrim<S> p0, S *rho1, S *m0,
+                                                           S *rho1, S *m0,
                                                            S *m1, S *m2, DensPrim<S> p1,
                                                            const int *flags) {
   using X = DCross<DIM>;
@@ -2200,7 +2169,7 @@ __global__ __launch_bounds__(DCross<DIM>::NT) void k_dens_inviscid(GridK g, Stat
   int x0, y0, z0;
   T::origin(g, blockIdx.x, x0, y0, z0);
   // phase 1: primitives of the points the faces read (up to two layers outside the
-  // box)
+  // box), from the state
   for (int p = threadIdx.x; p < X::NP; p += X::NT) {
     int li, lj, lk;
     X::point(p, li, lj, lk);
@@ -2208,8 +2177,8 @@ __global__ __launch_bounds__(DCross<DIM>::NT) void k_dens_inviscid(GridK g, Stat
     bool ok = gi >= -2 && gi <= g.n[0] + 1 && gj >= -2 && gj <= g.n[1] + 1;
     if (DIM == 3) ok = ok && gk >= -2 && gk <= g.n[2] + 1;
     if (!ok) continue;
-    S r, u[3], th;
-    load_rut<DIM>(g, p0, gi, gj, gk, r, u, th);
+    S r, u[3], th, pp;
+    load_prim<DIM>(g, st, gi, gj, gk, r, u, th, pp);
     lv[p] = r;
 #pragma unroll
     for (int q = 0; q < DIM; ++q) lv[(1 + q) * X::NP + p] = u[q];
@@ -3609,10 +3578,7 @@ static DensPrim<S> dens_prim(void *const *a) {
 void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
   IBM_DISPATCH(L, {
     const StateV<S> st = state_of<S>(B, cur), nx = state_of<S>(B, cur ^ 1);
-    const DensPrim<S> p0 = dens_prim<S>(B.dprim0), p1 = dens_prim<S>(B.dprim1);
-    const unsigned nb = (unsigned)((L.g.N + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL((k_dens_prim<DIM, S>), dim3(nb), dim3(kThreads), 0, L.st, L.g, st, p0,
-                       (const int *)B.flags);
+    const DensPrim<S> p1 = dens_prim<S>(B.dprim1);
     using X = DCross<DIM>;
     const unsigned nt2 = (unsigned)X::T::tiles(L.g), nt1 = (unsigned)DTile<DIM, 1>::tiles(L.g);
     const size_t shm = sizeof(S) * (size_t)(DIM + 2) * (X::NP + X::T::NFD);
@@ -3624,7 +3590,7 @@ void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
       enabled = true;
     }
     hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nt2), dim3(X::NT), shm, L.st, L.g, st, nx,
-                       p0, (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], p1,
+                       (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], p1,
                        (const int *)B.flags);
     hipLaunchKernelGGL((k_dens_viscous<DIM, S>), dim3(nt1), dim3(kThreads), 0, L.st, L.g,
                        (const S *)B.rho_s, (const S *)B.mhat[0], (const S *)B.mhat[1],

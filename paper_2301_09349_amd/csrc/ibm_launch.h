@@ -106,9 +106,9 @@ struct Bufs {
   double *dr[2][kDiffVars], *dw[2][kDiffVars], *ds[2][kDiffVars], *dp[kDiffVars];
   double *dpart;
   DiffScal *dsc;
-  // density-based step: primitives rho, u[3], theta of the state (dprim0) and
-  // u**[3], theta** of the intermediate state (dprim1), state type [N] each
-  void *dprim0[5], *dprim1[5];
+  // density-based step: u**[3], theta** of the intermediate state, state type [N]
+  // each
+  void *dprim1[5];
   // the second marker set (the first is in the fields above)
   MarkerSet alt;
 };
@@ -200,8 +200,7 @@ void run_diff_start(const Launch &L, const Bufs &B, int cur, int ring, int order
 void run_diff_iteration(const Launch &L, const Bufs &B, int ring, int it);
 void run_diff_finish(const Launch &L, const Bufs &B, int ring);
 void run_mass(const Launch &L, const Bufs &B);
-// density-based step (App. B): the primitives of state `cur`, the central-upwind
-// inviscid part (rho^{n+1} into rho_s, (rho u)** into mhat, u** and theta** into
+// density-based step (App. B): the central-upwind inviscid part of state `cur` (rho^{n+1} into rho_s, (rho u)** into mhat, u** and theta** into
 // dprim1, the mass flux into the other slot's faces), then the explicit viscous
 // part into mom_s, E_s; after the marker sources, the finish writes the other
 // state slot

@@ -2289,19 +2289,26 @@ __device__ __forceinline__ void load_star(const GridK &g, const DensPrim<S> &p1,
 // average of the two centred cell gradients, mu_f the face average; heat flux
 // lambda_f d theta / d n; Phi = tau:grad u at the cell from centred gradients.
 // Into ms, E_s (the body's sources are then added by the marker kernels).
+// 3D tiles of the viscous kernel: 8 x 8 x 8 (512 threads; fewer halo points per cell)
+#ifndef IBM_DENSV_TZ
+#define IBM_DENSV_TZ 8
+#endif
+template <int DIM>
+using DVTile = DTile<DIM, 1, IBM_DENSV_TZ>;
 template <int DIM, typename S>
-__global__ __launch_bounds__(kThreads) void k_dens_viscous(GridK g, const S *rho1, const S *m0,
+__global__ __launch_bounds__(DVTile<DIM>::TX * DVTile<DIM>::TY * DVTile<DIM>::TZ) void k_dens_viscous(GridK g, const S *rho1, const S *m0,
                                                           const S *m1, const S *m2,
                                                           DensPrim<S> p1, S *ms0, S *ms1,
                                                           S *ms2, S *E_s, const int *flags) {
-  using T = DTile<DIM, 1>;
+  using T = DVTile<DIM>;
+  constexpr int NT = T::TX * T::TY * T::TZ;
   constexpr int NV = DIM + 2;  // u[DIM], theta, mu
   __shared__ S lv[NV * T::NP];
   __shared__ S lf[(DIM + 1) * T::NFD];
   if (dens_skip(flags)) return;
   int x0, y0, z0;
   T::origin(g, blockIdx.x, x0, y0, z0);
-  for (int p = threadIdx.x; p < T::NP; p += kThreads) {
+  for (int p = threadIdx.x; p < T::NP; p += NT) {
     const int li = p % T::SX - 1, lj = (p / T::SX) % T::SY - 1;
     const int lk = DIM == 3 ? p / (T::SX * T::SY) - 1 : 0;
     const int gi = x0 + li, gj = y0 + lj, gk = z0 + lk;
@@ -2325,7 +2332,7 @@ __global__ __launch_bounds__(kThreads) void k_dens_viscous(GridK g, const S *rho
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
     const int FX = T::TX + (d == 0), FY = T::TY + (d == 1), FZ = T::TZ + (d == 2);
-    for (int f = threadIdx.x; f < FX * FY * FZ; f += kThreads) {
+    for (int f = threadIdx.x; f < FX * FY * FZ; f += NT) {
       const int fi = f % FX, fj = (f / FX) % FY, fk = f / (FX * FY);
       const int gf[3] = {x0 + fi, y0 + fj, z0 + fk};
       bool ok = true;
@@ -3580,7 +3587,7 @@ void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
     const StateV<S> st = state_of<S>(B, cur), nx = state_of<S>(B, cur ^ 1);
     const DensPrim<S> p1 = dens_prim<S>(B.dprim1);
     using X = DCross<DIM>;
-    const unsigned nt2 = (unsigned)X::T::tiles(L.g), nt1 = (unsigned)DTile<DIM, 1>::tiles(L.g);
+    const unsigned nt2 = (unsigned)X::T::tiles(L.g), nt1 = (unsigned)DVTile<DIM>::tiles(L.g);
     const size_t shm = sizeof(S) * (size_t)(DIM + 2) * (X::NP + X::T::NFD);
     if (shm > 65536) {
       static bool enabled = false;  // once per instance
@@ -3592,7 +3599,8 @@ void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
     hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nt2), dim3(X::NT), shm, L.st, L.g, st, nx,
                        (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], p1,
                        (const int *)B.flags);
-    hipLaunchKernelGGL((k_dens_viscous<DIM, S>), dim3(nt1), dim3(kThreads), 0, L.st, L.g,
+    constexpr int nv = DVTile<DIM>::TX * DVTile<DIM>::TY * DVTile<DIM>::TZ;
+    hipLaunchKernelGGL((k_dens_viscous<DIM, S>), dim3(nt1), dim3(nv), 0, L.st, L.g,
                        (const S *)B.rho_s, (const S *)B.mhat[0], (const S *)B.mhat[1],
                        (const S *)B.mhat[2], p1, (S *)B.mom_s[0], (S *)B.mom_s[1],
                        (S *)B.mom_s[2], (S *)B.E_s, (const int *)B.flags);

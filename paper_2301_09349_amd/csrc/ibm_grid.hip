@@ -2022,7 +2022,7 @@ struct DensPrim {
 // normal velocities; alpha = a+/(a+ - a-), omega = -a+ a-/(a+ - a-);
 // flux = alpha f(L) + (1 - alpha) f(R) - omega (W_R - W_L), with the pressure
 // alpha pL + (1 - alpha) pR in the normal momentum flux.
-template <int DIM, typename S>
+template <int DIM, typename S, bool FAST = false>
 __device__ __forceinline__ void knp_flux(const GridK &g, int d, const S *r, const S (*u)[3],
                                          const S *th, S &fr, S *fm, S &fe) {
   S rL, rR, thL, thR, uL[3], uR[3];
@@ -2032,14 +2032,14 @@ __device__ __forceinline__ void knp_flux(const GridK &g, int d, const S *r, cons
 #pragma unroll
     for (int q = 0; q < DIM; ++q) uL[q] = uR[q] = S(0.5) * (u[1][q] + u[2][q]);
   } else {
-    rL = vanleer(r[1], r[2], r[0]);
-    rR = vanleer(r[2], r[1], r[3]);
-    thL = vanleer(th[1], th[2], th[0]);
-    thR = vanleer(th[2], th[1], th[3]);
+    rL = vanleer<S, FAST>(r[1], r[2], r[0]);
+    rR = vanleer<S, FAST>(r[2], r[1], r[3]);
+    thL = vanleer<S, FAST>(th[1], th[2], th[0]);
+    thR = vanleer<S, FAST>(th[2], th[1], th[3]);
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
-      uL[q] = vanleer(u[1][q], u[2][q], u[0][q]);
-      uR[q] = vanleer(u[2][q], u[1][q], u[3][q]);
+      uL[q] = vanleer<S, FAST>(u[1][q], u[2][q], u[0][q]);
+      uR[q] = vanleer<S, FAST>(u[2][q], u[1][q], u[3][q]);
     }
   }
   S kL = S(0), kR = S(0);
@@ -2050,7 +2050,7 @@ __device__ __forceinline__ void knp_flux(const GridK &g, int d, const S *r, cons
   }
   const S Rg = S(g.R), gam = S(g.gm1 + 1.0), cv = S(g.cv);
   const S pL = rL * Rg * thL, pR = rR * Rg * thR;
-  const S cL = sqrt(gam * Rg * thL), cR = sqrt(gam * Rg * thR);
+  const S cL = qsqrt<FAST>(gam * Rg * thL), cR = qsqrt<FAST>(gam * Rg * thR);
   const S vL = uL[d], vR = uR[d];
   S ap = vL + cL, am = vL - cL;
   if (vR + cR > ap) ap = vR + cR;
@@ -2058,7 +2058,7 @@ __device__ __forceinline__ void knp_flux(const GridK &g, int d, const S *r, cons
   if (vR - cR < am) am = vR - cR;
   if (am > S(0)) am = S(0);
   const S span = ap - am;
-  const S al = ap / span, om = -(ap * am) / span, bl = S(1) - al;
+  const S al = qdiv<FAST>(ap, span), om = -qdiv<FAST>(ap * am, span), bl = S(1) - al;
   const S eL = rL * (cv * thL + S(0.5) * kL), eR = rR * (cv * thR + S(0.5) * kR);
   fr = al * vL * rL + bl * vR * rR - om * (rR - rL);
 #pragma unroll
@@ -2225,7 +2225,7 @@ __global__ __launch_bounds__(DCross<DIM>::NT) void k_dens_inviscid(GridK g, Stat
         th[m] = lv[(1 + DIM) * X::NP + lp];
       }
       S fr, fm[3], fe;
-      knp_flux<DIM, S>(g, d, r, u, th, fr, fm, fe);
+      knp_flux<DIM, S, DIM == 3>(g, d, r, u, th, fr, fm, fe);
       lf[f] = fr;
 #pragma unroll
       for (int q = 0; q < DIM; ++q) lf[(1 + q) * T::NFD + f] = fm[q];

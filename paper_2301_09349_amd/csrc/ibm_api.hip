@@ -714,6 +714,7 @@ ibm_status create_ctx(const ibm_grid_desc *desc, void *dev_workspace, size_t byt
                              : std::strcmp(cgs, "linear") == 0 ? 1
                              : std::strcmp(cgs, "quadratic") == 0 ? 2 : 3;
     if (ctx->L.pred_lds && need > 65536) ibmk::enable_predictor_lds(desc->dim, desc->precision);
+    if (desc->scheme == IBM_SCHEME_DENSITY) ibmk::enable_density_lds(desc->dim, desc->precision);
     // a moving body's markers set up ahead on side streams; IBM_REBUILD=inline
     // keeps them on the context's stream (a context without its own allocations
     // always does)

@@ -3582,20 +3582,38 @@ static DensPrim<S> dens_prim(void *const *a) {
   return p;
 }
 
+// dynamic LDS of the inviscid kernel: the slabs' primitives and one direction's face
+// fluxes
+template <int DIM, typename S>
+static size_t dens_lds_bytes() {
+  using X = DCross<DIM>;
+  return sizeof(S) * (size_t)(DIM + 2) * (X::NP + X::T::NFD);
+}
+template <int DIM, typename S>
+static void enable_dens_lds() {
+  const size_t b = dens_lds_bytes<DIM, S>();
+  if (b > 65536)
+    (void)hipFuncSetAttribute((const void *)k_dens_inviscid<DIM, S>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+}
+void enable_density_lds(int dim, int prec) {
+  if (dim == 2 && prec == 0)
+    enable_dens_lds<2, double>();
+  else if (dim == 2)
+    enable_dens_lds<2, float>();
+  else if (prec == 0)
+    enable_dens_lds<3, double>();
+  else
+    enable_dens_lds<3, float>();
+}
+
 void run_density_predictor(const Launch &L, const Bufs &B, int cur) {
   IBM_DISPATCH(L, {
     const StateV<S> st = state_of<S>(B, cur), nx = state_of<S>(B, cur ^ 1);
     const DensPrim<S> p1 = dens_prim<S>(B.dprim1);
     using X = DCross<DIM>;
     const unsigned nt2 = (unsigned)X::T::tiles(L.g), nt1 = (unsigned)DVTile<DIM>::tiles(L.g);
-    const size_t shm = sizeof(S) * (size_t)(DIM + 2) * (X::NP + X::T::NFD);
-    if (shm > 65536) {
-      static bool enabled = false;  // once per instance
-      if (!enabled)
-        (void)hipFuncSetAttribute((const void *)k_dens_inviscid<DIM, S>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-      enabled = true;
-    }
+    const size_t shm = dens_lds_bytes<DIM, S>();
     hipLaunchKernelGGL((k_dens_inviscid<DIM, S>), dim3(nt2), dim3(X::NT), shm, L.st, L.g, st, nx,
                        (S *)B.rho_s, (S *)B.mhat[0], (S *)B.mhat[1], (S *)B.mhat[2], p1,
                        (const int *)B.flags);

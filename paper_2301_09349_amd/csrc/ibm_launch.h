@@ -205,6 +205,8 @@ void run_mass(const Launch &L, const Bufs &B);
 // part into mom_s, E_s; after the marker sources, the finish writes the other
 // state slot
 void run_density_predictor(const Launch &L, const Bufs &B, int cur);
+// lets the inviscid kernel take its LDS beyond 64 KB (once per process and form)
+void enable_density_lds(int dim, int prec);
 void run_density_finish(const Launch &L, const Bufs &B, int cur, int tag);
 int64_t cell_blocks(const GridK &g);
 

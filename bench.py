@@ -99,7 +99,7 @@ KERNEL_CLASS = [("k_predictor", "predictor"), ("k_setup", "setup"), ("k_cg_start
                 ("k_correct", "correct"), ("k_interp_force", "markers"), ("k_spread", "markers"),
                 ("k_totals", "markers"), ("k_markers_fused", "markers"),
                 ("k_dsys", "diffusion"), ("k_diff_coef", "diffusion"),
-                ("k_dens_prim", "predictor"), ("k_dens_inviscid", "predictor"),
+                ("k_dens_inviscid", "predictor"),
                 ("k_dens_viscous", "predictor"),
                 ("k_dens_finish", "correct"),
                 ("k_rebuild_small", "rebuild"), ("k_eps_cg_wave", "rebuild")]
@@ -496,8 +496,8 @@ def run_moving(steps: int, warmup: int):
     (200 candidate markers, y = 0.2 D sin(2 pi 0.2 t), Re 100, Ma 0.2, Tw/Tinf 1.2).
     Per kernel class, "markers" is the marker work on the step's own stream
     (interpolation, forcing, totals, spreading, and the set-up of the first step of a
-    call) and "rebuild" the next step's marker set-up on the library's second stream,
-    which overlaps the rest of the step."""
+    call) and "rebuild" a later step's marker set-up on one of the library's side
+    streams, which overlaps the steps."""
     from paper_2301_09349_amd import inputs
 
     # f_0 from the pressure-based step: on the density-based one the fixed cylinder's

@@ -1181,6 +1181,14 @@ constexpr int kColPitch = kColTX + 2;
 constexpr int kColSlots = (kColTY + 2) * kColPitch;
 constexpr int kColHalo = 2 * kColTX + 2 * kColTY;
 static_assert(kColHalo <= kColThreads, "halo slots exceed the block's threads");
+// The CG iteration's tiles are twice as tall (64 x 16, 1024 threads): less of the
+// y halo of r, w, s is read again per cell (304 against 313 us per iteration on
+// 256^3); the other column kernels keep 64 x 8, where the taller tile was slower.
+#ifndef IBM_CG_ITER_TY
+#define IBM_CG_ITER_TY 16
+#endif
+constexpr int kCgTY = IBM_CG_ITER_TY;
+static_assert(2 * kColTX + 2 * kCgTY <= kColTX * kCgTY, "halo slots exceed the block's threads");
 
 // Index v along direction d resolved to a cell of the box and the sign of the
 // homogeneous ghost rule: wrap (periodic), else the mirror cell with sigma -1 beyond
@@ -1250,8 +1258,8 @@ __device__ __forceinline__ double col_rprime(double alpha, double beta, double r
   return MODE == COL_START ? r : MODE == COL_FIRST ? r - alpha * w : r - alpha * (w + beta * s);
 }
 
-template <int MODE, typename S>
-__global__ __launch_bounds__(kColThreads) void k_cg_col(
+template <int MODE, typename S, int TY = kCgTY>
+__global__ __launch_bounds__(kColTX * TY) void k_cg_col(
     GridK g, int it, int tiles_x, int tiles_y, int zc, int64_t items, const S *__restrict__ psi,
     const double *__restrict__ r, const double *__restrict__ w, const double *__restrict__ sold,
     double *__restrict__ rn, double *__restrict__ wn, double *__restrict__ snew,
@@ -1260,7 +1268,8 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col(
   constexpr bool START = MODE == COL_START, FIRST = MODE == COL_FIRST;
   __shared__ double lds[48];
   __shared__ int done0;
-  __shared__ double plane_lds[2][kColSlots];
+  constexpr int kSlots = (TY + 2) * kColPitch, kHalo = 2 * kColTX + 2 * TY;
+  __shared__ double plane_lds[2][kSlots];
   double alpha = 0.0, beta = 0.0;
   if (!START && !cg_head(it, partials, cs, flags, progress, lds, done0, alpha, beta)) return;
   const int lx = threadIdx.x % kColTX, ly = threadIdx.x / kColTX;
@@ -1277,17 +1286,17 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col(
     const int64_t rest = item / tiles_x;
     const int ty = (int)(rest % tiles_y);
     const int ch = (int)(rest / tiles_y);
-    const int i = tx * kColTX + lx, j = ty * kColTY + ly;
+    const int i = tx * kColTX + lx, j = ty * TY + ly;
     const int k0 = ch * zc, k1 = min(k0 + zc, n2);
     const bool inside = i < n0 && j < n1;
     double sx, sy;
     const int64_t col = col_resolve(g, 0, i, sx) + (int64_t)n0 * col_resolve(g, 1, j, sy);
     const double sxy = sx * sy;
-    // halo slot of this thread: rows y = -1 and kColTY, then columns x = -1 and kColTX
+    // halo slot of this thread: rows y = -1 and TY, then columns x = -1 and kColTX
     int hslot = -1;
     int64_t hcol = 0;
     double hsig = 1.0;
-    if (threadIdx.x < kColHalo) {
+    if (threadIdx.x < kHalo) {
       const int t = threadIdx.x;
       int hx, hy;
       if (t < kColTX) {
@@ -1295,17 +1304,17 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col(
         hy = -1;
       } else if (t < 2 * kColTX) {
         hx = t - kColTX;
-        hy = kColTY;
-      } else if (t < 2 * kColTX + kColTY) {
+        hy = TY;
+      } else if (t < 2 * kColTX + TY) {
         hx = -1;
         hy = t - 2 * kColTX;
       } else {
         hx = kColTX;
-        hy = t - 2 * kColTX - kColTY;
+        hy = t - 2 * kColTX - TY;
       }
       double s1, s2;
       hcol = col_resolve(g, 0, tx * kColTX + hx, s1) +
-             (int64_t)n0 * col_resolve(g, 1, ty * kColTY + hy, s2);
+             (int64_t)n0 * col_resolve(g, 1, ty * TY + hy, s2);
       hsig = s1 * s2;
       hslot = (hy + 1) * kColPitch + (hx + 1);
     }
@@ -3320,9 +3329,10 @@ void run_predictor(const Launch &L, const Bufs &B, int base, int cur, int order,
 // Work items of the column kernels: x-y tiles times chunks of z planes, about one
 // item per block. The kernels run g.nblocks blocks, as every kernel whose per-block
 // partial sums the CG's head adds up (the head sums gridDim.x of them).
-void col_plan(const GridK &g, int &tiles_x, int &tiles_y, int &zc, int64_t &items, int &blocks) {
+void col_plan(const GridK &g, int &tiles_x, int &tiles_y, int &zc, int64_t &items, int &blocks,
+              int tile_y) {
   tiles_x = (g.n[0] + kColTX - 1) / kColTX;
-  tiles_y = (g.n[1] + kColTY - 1) / kColTY;
+  tiles_y = (g.n[1] + tile_y - 1) / tile_y;
   blocks = (int)g.nblocks;
   const int64_t cols = (int64_t)tiles_x * tiles_y;
   const int64_t want = std::max<int64_t>(1, blocks / cols);
@@ -3335,7 +3345,7 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
   if (L.prec == 1 && L.refine32 && L.g.dim == 3 && L.cg_col) {
     int tx, ty, zc, nbk;
     int64_t items;
-    col_plan(L.g, tx, ty, zc, items, nbk);
+    col_plan(L.g, tx, ty, zc, items, nbk, kColTY);
     hipLaunchKernelGGL((k_setup_col<float, true>), dim3((unsigned)nbk), dim3(kColThreads), 0,
                        L.st, L.g, tx, ty, zc, items, (const float *)B.rho[cur],
                        (const float *)B.mhat[0], (const float *)B.mhat[1],
@@ -3362,7 +3372,7 @@ void run_setup(const Launch &L, const Bufs &B, int cur, int tag) {
   if (L.g.dim == 3 && L.cg_col) {
     int tx, ty, zc, nbk;
     int64_t items;
-    col_plan(L.g, tx, ty, zc, items, nbk);
+    col_plan(L.g, tx, ty, zc, items, nbk, kColTY);
     auto go = [&](auto sdum) {
       using S = decltype(sdum);
       hipLaunchKernelGGL((k_setup_col<S>), dim3((unsigned)nbk), dim3(kColThreads), 0, L.st, L.g,
@@ -3394,10 +3404,10 @@ void run_cg64_start(const Launch &L, const Bufs &B) {
   if (L.g.dim == 3 && L.cg_col) {
     int tx, ty, zc, nbk;
     int64_t items;
-    col_plan(L.g, tx, ty, zc, items, nbk);
+    col_plan(L.g, tx, ty, zc, items, nbk, kCgTY);
     auto go = [&](auto sdum) {
       using S = decltype(sdum);
-      hipLaunchKernelGGL((k_cg_col<COL_START, S>), dim3((unsigned)nbk), dim3(kColThreads), 0,
+      hipLaunchKernelGGL((k_cg_col<COL_START, S>), dim3((unsigned)nbk), dim3(kColTX * kCgTY), 0,
                          L.st, L.g, 0, tx, ty, zc, items, (const S *)B.psi,
                          (const double *)B.rv[0], (const double *)nullptr,
                          (const double *)nullptr, (double *)nullptr, B.wv[0], (double *)nullptr,
@@ -3421,7 +3431,7 @@ static void run_mcg_iter(const Launch &L, const Bufs &B, int it) {
   if (DIM == 3 && L.cg_col) {
     int tx, ty, zc, nbk;
     int64_t items;
-    col_plan(L.g, tx, ty, zc, items, nbk);
+    col_plan(L.g, tx, ty, zc, items, nbk, kColTY);
     hipLaunchKernelGGL(k_mcg_col, dim3((unsigned)nbk), dim3(kColThreads), 0, L.st, L.g, it, tx,
                        ty, zc, items, (const float *)B.psi, (const double *)B.b, B.x, B.x2,
                        (const float *)B.rv32[a], (const float *)B.wv32[a],
@@ -3452,12 +3462,12 @@ void run_cg64_iteration(const Launch &L, const Bufs &B, int it) {
   if (L.g.dim == 3 && L.cg_col) {
     int tx, ty, zc, nbk;
     int64_t items;
-    col_plan(L.g, tx, ty, zc, items, nbk);
+    col_plan(L.g, tx, ty, zc, items, nbk, kCgTY);
     const int a = it & 1, bb = a ^ 1;
     auto go = [&](auto mode, auto sdum) {
       using S = decltype(sdum);
       constexpr int M = decltype(mode)::value;
-      hipLaunchKernelGGL((k_cg_col<M, S>), dim3((unsigned)nbk), dim3(kColThreads), 0, L.st, L.g,
+      hipLaunchKernelGGL((k_cg_col<M, S>), dim3((unsigned)nbk), dim3(kColTX * kCgTY), 0, L.st, L.g,
                          it, tx, ty, zc, items, (const S *)B.psi, (const double *)B.rv[a],
                          (const double *)B.wv[a], (const double *)B.sv[a], B.rv[bb], B.wv[bb],
                          B.sv[bb], B.pv, B.x, B.partials, B.cg, (const int *)B.flags, B.progress);
@@ -3488,7 +3498,7 @@ void run_correct(const Launch &L, const Bufs &B, int cur, int tag) {
   if (L.g.dim == 3 && L.cg_col) {
     int tx, ty, zc, nbk;
     int64_t items;
-    col_plan(L.g, tx, ty, zc, items, nbk);
+    col_plan(L.g, tx, ty, zc, items, nbk, kColTY);
     auto go = [&](auto sdum) {
       using S = decltype(sdum);
       hipLaunchKernelGGL((k_correct_col<S>), dim3((unsigned)nbk), dim3(kColThreads), 0, L.st,

@@ -1236,9 +1236,10 @@ __device__ __forceinline__ void col_halo_slot(const GridK &g, int tx, int ty, in
   hslot = (hy + 1) * kColPitch + (hx + 1);
 }
 
-// FP32 form's solve by refinement (see k_mcg_iter): an inner solve stops at 1e-4 of
-// its start residual (or kInnerMax iterations); the stages of its kernels.
-constexpr double kInnerTol2 = 1e-8;
+// FP32 form's solve by refinement (see k_mcg_iter): an inner solve stops at 1e-5 of
+// its start residual (or kInnerMax iterations); the stages of its kernels. (At 1e-4
+// the 256^3 sphere took 9.9 inner launches per step, at 1e-5 9.0, at 1e-6 9.0.)
+constexpr double kInnerTol2 = 1e-10;
 constexpr int kInnerMax = 60;
 enum { MS_INNER = 0, MS_START = 1, MS_FIRST = 2 };
 
@@ -2464,7 +2465,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_dens_finish(GridK g, const S 
 
 // ------------------------------------- FP32 form: pressure by iterative refinement
 // x and the outer residual r = b - A x are FP64; each inner solve A d = r runs the
-// single-reduction CG on FP32 vectors with FP64 dot products to a relative 1e-4 (or
+// single-reduction CG on FP32 vectors with FP64 dot products to a relative 1e-5 (or
 // kInnerMax iterations), then x += d and the FP64 residual is formed again. The
 // solve ends when the FP64 residual meets |r| <= rtol |b|. One kernel per
 // iteration: an inner CG iteration, or a refinement that also starts the next
